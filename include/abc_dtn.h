@@ -1,0 +1,161 @@
+/*
+ * abc_dtn.h -- C ABI of the gfx950 time stepper for the semi-discrete 3D
+ * Schroedinger equation closed by discrete Dirichlet-to-Neumann absorbing
+ * boundary conditions (Wu & Li, arXiv:1908.02456).
+ *
+ * What is computed
+ * ----------------
+ * The box holds nx*ny*nz grid points x_j = (j - (n-1)/2) h per axis.  Inside
+ * it the Hamiltonian is H = -(1/2) Delta_h + V (hbar = m = 1, Sec. 2), with
+ * Delta_h the axis-by-axis central difference of half-width R (R = 1 is the
+ * 3D seven-point Laplacian; R = 3 is the paper's "seven points in each
+ * direction").  The exterior (V = 0) acts on the box only through the
+ * boundary layer Gamma (points within R of a face), Sec. 2.  The supported
+ * dynamics are (Sec. 3):
+ *   ABC_ZEROTH:  d/dt psi = -i (H psi + E^T M E psi),  M = K(s0)
+ *   ABC_FIRST:   d/dt psi = -i H psi - i E^T f,  d/dt f = B f + A E psi,
+ *                A = -i H_{Gamma,II} H_{II,Gamma},  B = s1 I - A K(s1)^{-1}
+ *                (the first-order stability theorem), or with a finite s2 the
+ *                two-point interpolation R11(s1) = K(s1), R11(s2) = K(s2)
+ *   ABC_DIRICHLET / ABC_PERIODIC: no condition (zero outside / wrap-around),
+ * where K(s) is the discrete DtN map (Sec. 2, evaluated by the App. A
+ * boundary-element formula).  Time stepping is the fourth-order Taylor
+ * propagator of Sec. 4, sum_{k<=4} (dt L)^k / k!, applied to the generator L
+ * of the (augmented) linear dynamics; with a mean field (Sec. 4.3, simplified
+ * to U = t0 rho + t3 rho^2, rho = sum over the batch of |psi_j|^2) U is
+ * rebuilt from the state at the start of every step.
+ *
+ * Two forms of the boundary operators:
+ *   ABC_FORM_BOX    the paper's dense n_Gamma x n_Gamma matrices (exact;
+ *                   memory n_Gamma^2 * 16 B, so only for small boxes).
+ *   ABC_FORM_FACES  each face sees the half-space beyond it; its operator is
+ *                   the Toeplitz section, over the face's R-layer slab, of the
+ *                   half-space DtN kernel, truncated to |p|_inf <= window and
+ *                   (fejer = 1) tapered by the separable triangular window,
+ *                   which keeps both stability theorems' sign conditions.
+ *                   window >= max(n)-1 with fejer = 0 is the exact section.
+ *
+ * Memory, layout and ownership
+ * ----------------------------
+ * All state buffers are device memory owned by the caller:
+ *   psi  complex, [z][y][x][orb] (orbital fastest; x fastest when batch = 1),
+ *        interleaved (re, im); complex128 for ABC_C128, complex64 for ABC_C64.
+ *   V    real external potential [z][y][x], float64 (ABC_C128) or float32
+ *        (ABC_C64); may be NULL for V = 0.
+ *   aux  complex128 always (the auxiliary recurrences stay in FP64),
+ *        abc_aux_elems() elements, zero at t = 0 (the exterior starts empty,
+ *        Sec. 2).  Face form: [face][layer][t_slow][t_fast][orb] with faces in
+ *        the order x-,x+,y-,y+,z-,z+; layer 0 is the outermost box layer;
+ *        (t_slow, t_fast) = (z, y) for x-faces, (z, x) for y-faces, (y, x)
+ *        for z-faces.  Box form: [gamma][orb], Gamma in C order of (z, y, x).
+ * The context owns only setup products (operators) and scratch.
+ *
+ * Errors and threading
+ * --------------------
+ * Every call returns an abc_status; no exception crosses the ABI.  The text
+ * of the last error of the calling thread is returned by abc_last_error().
+ * All device work of abc_step/abc_diagnostics is queued on the given stream
+ * (a hipStream_t passed as void*; NULL = the default stream) and nothing
+ * synchronises with the host.  One context must not be used by two streams
+ * at once (it owns the scratch buffers).
+ */
+#ifndef ABC_DTN_H
+#define ABC_DTN_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct abc_ctx abc_ctx;
+
+typedef enum {
+  ABC_OK = 0,
+  ABC_EINVAL = -1,     /* invalid parameters or buffer sizes               */
+  ABC_ENOMEM = -2,     /* device or host allocation failed                 */
+  ABC_EDEVICE = -3,    /* a HIP runtime or library call failed             */
+  ABC_EUNSTABLE = -4,  /* stability self-check at setup failed             */
+  ABC_ENOTSUP = -5     /* combination not implemented                      */
+} abc_status;
+
+enum { ABC_DIRICHLET = 0, ABC_PERIODIC = 1, ABC_ZEROTH = 2, ABC_FIRST = 3 };
+enum { ABC_FORM_BOX = 0, ABC_FORM_FACES = 1 };
+enum { ABC_C128 = 0, ABC_C64 = 1 };
+enum { ABC_MF_NONE = 0, ABC_MF_T0T3 = 1 };
+/* execution path of abc_step */
+enum { ABC_PATH_AUTO = 0, ABC_PATH_STAGED = 1, ABC_PATH_FUSED = 2 };
+
+typedef struct {
+  int nx, ny, nz;     /* box points per axis (>= 2R + 1)                     */
+  double h, dt;       /* grid spacing, time step                            */
+  int radius;         /* R in {1, 2, 3}                                     */
+  int order;          /* ABC_DIRICHLET | ABC_PERIODIC | ABC_ZEROTH | ABC_FIRST */
+  int form;           /* ABC_FORM_BOX | ABC_FORM_FACES                      */
+  double s0;          /* zeroth-order interpolation point (> 0)             */
+  double s1, s2;      /* first-order points; s2 <= 0 selects the theorem's
+                         (s1, infinity) pair; s2 > 0 two-point (box form)   */
+  int window;         /* face form: kernel half-width w (|p|_inf <= w)       */
+  int fejer;          /* face form: 1 = triangular window, 0 = truncation    */
+  int dtype;          /* ABC_C128 | ABC_C64                                 */
+  int batch;          /* wavefunctions sharing grid, V and boundary (>= 1)  */
+  int meanfield;      /* ABC_MF_NONE | ABC_MF_T0T3                          */
+  double t0, t3;      /* mean-field coefficients                            */
+  int path;           /* ABC_PATH_*                                        */
+  int reserved[7];    /* must be zero                                       */
+} abc_params;
+
+/* Fill p with defaults (R = 1, first order, face form, w = 0, fejer = 1,
+ * s0 = s1 = 1, s2 = 0, C128, batch 1, no mean field, automatic path). */
+void abc_params_default(abc_params* p);
+
+/* Build the operators for p on the current HIP device (host FP64 setup;
+ * may take seconds for the box form) and allocate the context's scratch.
+ * Box form: K(s) by App. A, dense solves on the device.  Face form:
+ * half-line DtN symbols per transverse mode, kernel coefficients.
+ * Returns ABC_EUNSTABLE when a sign condition of the stability theorems
+ * fails on the symbol, or when dt times the spectral-radius bound of the
+ * kinetic and boundary operators exceeds the Taylor-4 stability limit
+ * 2 sqrt(2).  On success *out owns device memory until abc_destroy. */
+abc_status abc_setup(const abc_params* p, abc_ctx** out);
+
+/* Advance (psi, aux) by n_steps Taylor-4 steps in place.  psi, V, aux as
+ * described above (aux may be NULL unless order == ABC_FIRST).  No
+ * allocation, no host synchronisation. */
+abc_status abc_step(abc_ctx* ctx, void* psi, void* aux, const void* V,
+                    int n_steps, void* stream);
+
+/* FP64 diagnostics of a state, written to device memory out (3*batch + 1
+ * doubles): [0, batch) norm h^3 sum |psi_j|^2; [batch, 2 batch) Lyapunov
+ * functional h^3 (psi_j^* psi_j + f_j^* Q f_j) (Sec. 3, zeroth- and
+ * first-order stability proofs; Q = (H_{Gamma,II} H_{II,Gamma})^{-1});
+ * [2 batch, 3 batch) h^3 Re <psi_j, H_{I,I} psi_j>; [3 batch] mean-field
+ * interaction energy h^3 sum (t0 rho^2/2 + t3 rho^3/3) (0 without it).
+ * Deterministic (fixed-order two-pass reduction). */
+abc_status abc_diagnostics(abc_ctx* ctx, const void* psi, const void* aux,
+                           const void* V, double* out, void* stream);
+
+/* Number of complex128 elements of the auxiliary buffer (0 unless first order). */
+size_t abc_aux_elems(const abc_ctx* ctx);
+
+/* Copy a setup product to host memory (for inspection and tests).
+ * which = 0: face kernel, R*R*(2w+1)^2 complex128 as [l][l'][p1+w][p2+w];
+ * which = 1: box-form matrix, M (zeroth) or [B | A] (first), row-major.
+ * which = 2: face-form normal-line blocks, a (R*R) then q (R*R) complex128.
+ * n = capacity in complex128 elements; returns EINVAL if too small. */
+abc_status abc_export(const abc_ctx* ctx, int which, void* host_out, size_t n);
+
+/* Bytes of device memory held by the context. */
+size_t abc_device_bytes(const abc_ctx* ctx);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* abc_last_error(void);
+
+/* Release everything the context owns (NULL is ignored). */
+void abc_destroy(abc_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ABC_DTN_H */

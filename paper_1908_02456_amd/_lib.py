@@ -1,0 +1,80 @@
+"""ctypes declarations of the C ABI in include/abc_dtn.h (argument marshalling
+only; every computation happens in the HIP library)."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libabc_dtn.so")
+
+ABC_OK, ABC_EINVAL, ABC_ENOMEM, ABC_EDEVICE, ABC_EUNSTABLE, ABC_ENOTSUP = 0, -1, -2, -3, -4, -5
+STATUS_NAMES = {0: "ABC_OK", -1: "ABC_EINVAL", -2: "ABC_ENOMEM", -3: "ABC_EDEVICE",
+                -4: "ABC_EUNSTABLE", -5: "ABC_ENOTSUP"}
+ORDERS = {"dirichlet": 0, "periodic": 1, "zeroth": 2, "first": 3}
+FORMS = {"box": 0, "faces": 1}
+DTYPES = {"c128": 0, "c64": 1}
+PATHS = {"auto": 0, "staged": 1, "fused": 2}
+
+EXPORTED = ["abc_params_default", "abc_setup", "abc_step", "abc_diagnostics", "abc_aux_elems",
+            "abc_export", "abc_device_bytes", "abc_last_error", "abc_destroy"]
+
+
+class AbcParams(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
+        ("h", ctypes.c_double), ("dt", ctypes.c_double),
+        ("radius", ctypes.c_int), ("order", ctypes.c_int), ("form", ctypes.c_int),
+        ("s0", ctypes.c_double), ("s1", ctypes.c_double), ("s2", ctypes.c_double),
+        ("window", ctypes.c_int), ("fejer", ctypes.c_int), ("dtype", ctypes.c_int),
+        ("batch", ctypes.c_int), ("meanfield", ctypes.c_int),
+        ("t0", ctypes.c_double), ("t3", ctypes.c_double),
+        ("path", ctypes.c_int), ("reserved", ctypes.c_int * 7),
+    ]
+
+
+class AbcError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s: %s" % (STATUS_NAMES.get(status, status), msg))
+        self.status = status
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load the library once; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError("libabc_dtn.so is not built (run __graft_entry__.build())")
+    lib = ctypes.CDLL(path)
+    P = ctypes.POINTER(AbcParams)
+    vp = ctypes.c_void_p
+    lib.abc_params_default.argtypes = [P]
+    lib.abc_params_default.restype = None
+    lib.abc_setup.argtypes = [P, ctypes.POINTER(vp)]
+    lib.abc_setup.restype = ctypes.c_int
+    lib.abc_step.argtypes = [vp, vp, vp, vp, ctypes.c_int, vp]
+    lib.abc_step.restype = ctypes.c_int
+    lib.abc_diagnostics.argtypes = [vp, vp, vp, vp, vp, vp]
+    lib.abc_diagnostics.restype = ctypes.c_int
+    lib.abc_aux_elems.argtypes = [vp]
+    lib.abc_aux_elems.restype = ctypes.c_size_t
+    lib.abc_export.argtypes = [vp, ctypes.c_int, vp, ctypes.c_size_t]
+    lib.abc_export.restype = ctypes.c_int
+    lib.abc_device_bytes.argtypes = [vp]
+    lib.abc_device_bytes.restype = ctypes.c_size_t
+    lib.abc_last_error.argtypes = []
+    lib.abc_last_error.restype = ctypes.c_char_p
+    lib.abc_destroy.argtypes = [vp]
+    lib.abc_destroy.restype = None
+    _lib = lib
+    return lib
+
+
+def check(status: int) -> None:
+    if status != ABC_OK:
+        msg = load().abc_last_error().decode(errors="replace")
+        raise AbcError(status, msg)

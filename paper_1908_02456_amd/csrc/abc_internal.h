@@ -1,0 +1,96 @@
+// Internal declarations shared by the host setup, the C ABI and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <complex>
+#include <string>
+#include <vector>
+
+#include "../../include/abc_dtn.h"
+
+namespace abc {
+
+using cd = std::complex<double>;
+
+constexpr int kMaxR = 3;
+
+// Geometry of the box and of its six face slabs.  Face f = 2*axis + side,
+// axis 0 = x, 1 = y, 2 = z; side 0 = low, 1 = high.  Transverse coordinates
+// (t_slow, t_fast) are (z, y) for x-faces, (z, x) for y-faces, (y, x) for
+// z-faces; layer 0 is the outermost box layer.
+struct Geometry {
+  int nx, ny, nz, R, batch;
+  long long npts;            // nx*ny*nz
+  long long face_off[7];     // element offsets of each face slab (units of complex * batch)
+  int face_n1[6], face_n2[6];
+};
+
+Geometry make_geometry(int nx, int ny, int nz, int R, int batch);
+
+// Host setup products ------------------------------------------------------
+
+// Central second-derivative weights c_0..c_R.
+void fd_weights(int R, double* c);
+
+struct FaceOps {
+  int R = 1, w = 0;
+  std::vector<cd> kernel;    // [l][l'][p1+w][p2+w]
+  cd a[kMaxR * kMaxR];       // normal-line block of A (first order)
+  cd q[kMaxR * kMaxR];       // Lyapunov weight (H_gs H_gs^T)^{-1}
+  double kernel_abs_sum = 0; // max over l of sum_{l',p} |k| (spectral bound)
+  double symbol_norm = 0;    // sup over modes of the Frobenius norm of the
+                             // (Lyapunov-weighted) symbol
+  double coupling_norm = 0;  // Frobenius norm of the face coupling block
+};
+
+// Half-line DtN symbol per transverse mode by cyclic reduction of the
+// semi-infinite block-tridiagonal exterior operator (R x R result).
+void halfline_symbol(int R, double h, cd shift, cd* out);
+
+// Face operators; returns ABC_OK or ABC_EUNSTABLE (sign condition violated).
+abc_status build_face_ops(const abc_params& p, FaceOps& ops, std::string& err);
+
+// Box form: dense operators assembled on the host and finished on the
+// device.  mat_dev receives M (n x n) or [B | A] (n x 2n), row-major.
+abc_status build_box_ops(const abc_params& p, double2** mat_dev, double2** q_dev, int* n_gamma,
+                         std::vector<int>& gamma_lin, double* spectral_bound, std::string& err);
+
+}  // namespace abc
+
+// Kernel launchers (kernels.hip) -------------------------------------------
+
+struct abc_launch {
+  abc::Geometry g;
+  double h, dt;
+  double c[abc::kMaxR + 1];
+  int order, form, periodic, dtype, w;
+  int meanfield;
+  double t0, t3;
+  // face operators
+  const double2* face_ker;
+  double2 a_loc[abc::kMaxR * abc::kMaxR];
+  double2 q_loc[abc::kMaxR * abc::kMaxR];
+  // box form
+  const double2* box_mat;
+  const double2* box_q;       // Lyapunov weight (H_gs H_gs^T)^{-1}, n x n
+  const int* gamma_lin;       // gamma index -> linear point index
+  const int* point_gamma;     // linear point index -> gamma index or -1
+  int n_gamma;
+};
+
+struct abc_scratch {
+  void* y[2];          // stage vectors (psi dtype)
+  void* acc;           // Taylor accumulator (psi dtype)
+  double2* g[2];       // aux stage vectors
+  double2* facc;       // aux accumulator
+  double2* src;        // zeroth-order source on the faces / Gamma
+  void* veff;          // V + mean field (psi real dtype)
+  double* red;         // reduction partials
+  int red_blocks;
+};
+
+hipError_t launch_step_staged(const abc_launch& L, const abc_scratch& S, void* psi, double2* aux,
+                              const void* V, int n_steps, hipStream_t st);
+hipError_t launch_diagnostics(const abc_launch& L, const abc_scratch& S, const void* psi,
+                              const double2* aux, const void* V, double* out, hipStream_t st);

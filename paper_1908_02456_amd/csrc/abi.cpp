@@ -1,0 +1,303 @@
+// C ABI of libabc_dtn: parameter checks, operator setup and upload, scratch
+// ownership and dispatch of the device paths.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "abc_internal.h"
+#include "fused.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+abc_status fail(abc_status s, const std::string& msg) {
+  g_last_error = msg;
+  return s;
+}
+
+}  // namespace
+
+struct abc_ctx {
+  abc_params p{};
+  abc_launch L{};
+  abc_scratch S{};
+  abc::FaceOps face;
+  std::vector<void*> allocations;
+  size_t bytes = 0;
+  size_t aux_elems = 0;
+  int n_gamma = 0;
+  int use_fused = 0;
+  double2* box_mat = nullptr;
+  double2* box_q = nullptr;
+};
+
+namespace {
+
+abc_status dev_alloc(abc_ctx* c, void** ptr, size_t bytes) {
+  if (bytes == 0) {
+    *ptr = nullptr;
+    return ABC_OK;
+  }
+  hipError_t e = hipMalloc(ptr, bytes);
+  if (e != hipSuccess) return fail(ABC_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+  c->allocations.push_back(*ptr);
+  c->bytes += bytes;
+  return ABC_OK;
+}
+
+abc_status check_params(const abc_params& p) {
+  if (p.nx < 1 || p.ny < 1 || p.nz < 1) return fail(ABC_EINVAL, "box sizes must be positive");
+  if (p.radius < 1 || p.radius > abc::kMaxR) return fail(ABC_EINVAL, "radius must be 1, 2 or 3");
+  if (p.nx < 2 * p.radius + 1 || p.ny < 2 * p.radius + 1 || p.nz < 2 * p.radius + 1)
+    return fail(ABC_EINVAL, "every axis needs at least 2R+1 points");
+  if (!(p.h > 0) || !(p.dt > 0) || !std::isfinite(p.h) || !std::isfinite(p.dt))
+    return fail(ABC_EINVAL, "h and dt must be positive and finite");
+  if (p.order < ABC_DIRICHLET || p.order > ABC_FIRST) return fail(ABC_EINVAL, "unknown order");
+  if (p.form != ABC_FORM_BOX && p.form != ABC_FORM_FACES) return fail(ABC_EINVAL, "unknown form");
+  if (p.dtype != ABC_C128 && p.dtype != ABC_C64) return fail(ABC_EINVAL, "unknown dtype");
+  if (p.batch < 1) return fail(ABC_EINVAL, "batch must be >= 1");
+  if (p.meanfield != ABC_MF_NONE && p.meanfield != ABC_MF_T0T3) return fail(ABC_EINVAL, "unknown mean field");
+  if (p.path < ABC_PATH_AUTO || p.path > ABC_PATH_FUSED) return fail(ABC_EINVAL, "unknown path");
+  if (p.window < 0) return fail(ABC_EINVAL, "window must be >= 0");
+  if (p.order == ABC_PERIODIC && p.nx < 2 * p.radius + 1) return fail(ABC_EINVAL, "periodic box too small");
+  if (p.order == ABC_ZEROTH && !(p.s0 > 0)) return fail(ABC_EUNSTABLE, "s0 must be positive (zeroth-order theorem)");
+  if (p.order == ABC_FIRST && !(p.s1 > 0)) return fail(ABC_EUNSTABLE, "s1 must be positive (first-order theorem)");
+  if (p.order == ABC_FIRST && p.form == ABC_FORM_FACES && p.s2 > 0)
+    return fail(ABC_ENOTSUP, "the face form implements the theorem's (s1, infinity) pair only");
+  for (int i = 0; i < 7; ++i)
+    if (p.reserved[i] != 0) return fail(ABC_EINVAL, "reserved fields must be zero");
+  return ABC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void abc_params_default(abc_params* p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof(*p));
+  p->nx = p->ny = p->nz = 32;
+  p->h = 0.2;
+  p->dt = 0.002;
+  p->radius = 1;
+  p->order = ABC_FIRST;
+  p->form = ABC_FORM_FACES;
+  p->s0 = 1.0;
+  p->s1 = 1.0;
+  p->s2 = 0.0;
+  p->window = 0;
+  p->fejer = 1;
+  p->dtype = ABC_C128;
+  p->batch = 1;
+  p->meanfield = ABC_MF_NONE;
+  p->path = ABC_PATH_AUTO;
+}
+
+const char* abc_last_error(void) { return g_last_error.c_str(); }
+
+void abc_destroy(abc_ctx* c) {
+  if (!c) return;
+  for (void* ptr : c->allocations) (void)hipFree(ptr);
+  delete c;
+}
+
+abc_status abc_setup(const abc_params* pp, abc_ctx** out) {
+  g_last_error.clear();
+  if (!pp || !out) return fail(ABC_EINVAL, "null argument");
+  *out = nullptr;
+  abc_status st = check_params(*pp);
+  if (st != ABC_OK) return st;
+  const abc_params& p = *pp;
+  abc_ctx* c = new abc_ctx();
+  c->p = p;
+  abc_launch& L = c->L;
+  L.g = abc::make_geometry(p.nx, p.ny, p.nz, p.radius, p.batch);
+  L.h = p.h;
+  L.dt = p.dt;
+  abc::fd_weights(p.radius, L.c);
+  L.order = p.order;
+  L.form = p.form;
+  L.periodic = p.order == ABC_PERIODIC;
+  L.dtype = p.dtype;
+  L.w = p.window;
+  L.meanfield = p.meanfield;
+  L.t0 = p.t0;
+  L.t3 = p.t3;
+  const bool bc = p.order == ABC_ZEROTH || p.order == ABC_FIRST;
+
+  // spectral bound of the kinetic part: 3 max_theta sigma_1(theta)
+  double smax = 0;
+  for (int j = 0; j <= 256; ++j) {
+    double th = M_PI * j / 256, acc = -L.c[0];
+    for (int k = 1; k <= p.radius; ++k) acc -= 2 * L.c[k] * std::cos(k * th);
+    smax = std::max(smax, acc / (2 * p.h * p.h));
+  }
+  double rho = 3 * smax;
+
+  std::string err;
+  if (bc && p.form == ABC_FORM_FACES) {
+    st = abc::build_face_ops(p, c->face, err);
+    if (st != ABC_OK) { abc_destroy(c); return fail(st, err); }
+    const int R = p.radius;
+    for (int i = 0; i < R * R; ++i) {
+      L.a_loc[i] = make_double2(c->face.a[i].real(), c->face.a[i].imag());
+      L.q_loc[i] = make_double2(c->face.q[i].real(), c->face.q[i].imag());
+    }
+    void* kd = nullptr;
+    const size_t kb = c->face.kernel.size() * sizeof(double2);
+    if ((st = dev_alloc(c, &kd, kb)) != ABC_OK) { abc_destroy(c); return st; }
+    if (hipMemcpy(kd, c->face.kernel.data(), kb, hipMemcpyHostToDevice) != hipSuccess) {
+      abc_destroy(c);
+      return fail(ABC_EDEVICE, "hipMemcpy of face kernel failed");
+    }
+    L.face_ker = static_cast<const double2*>(kd);
+    // Lyapunov-weighted block bound: zeroth order adds up to three faces'
+    // operators to H; first order couples psi and f through blocks of norm
+    // |H_{Gamma,Sigma}| (three faces at a corner) and B acts on f
+    if (p.order == ABC_ZEROTH)
+      rho += 3 * c->face.symbol_norm;
+    else
+      rho = std::max(rho, c->face.symbol_norm) + std::sqrt(3.0) * c->face.coupling_norm;
+  }
+  if (bc && p.form == ABC_FORM_BOX) {
+    std::vector<int> glin;
+    double bound = 0;
+    st = abc::build_box_ops(p, &c->box_mat, &c->box_q, &c->n_gamma, glin, &bound, err);
+    if (st != ABC_OK) { abc_destroy(c); return fail(st, err); }
+    if (c->box_mat) { c->allocations.push_back(c->box_mat); c->bytes += (size_t)c->n_gamma * c->n_gamma * 16 * (p.order == ABC_FIRST ? 2 : 1); }
+    if (c->box_q) { c->allocations.push_back(c->box_q); c->bytes += (size_t)c->n_gamma * c->n_gamma * 16; }
+    L.box_mat = c->box_mat;
+    L.box_q = c->box_q;
+    L.n_gamma = c->n_gamma;
+    std::vector<int> pg(L.g.npts, -1);
+    for (int i = 0; i < c->n_gamma; ++i) pg[glin[i]] = i;
+    void *gl = nullptr, *pgd = nullptr;
+    if ((st = dev_alloc(c, &gl, glin.size() * sizeof(int))) != ABC_OK ||
+        (st = dev_alloc(c, &pgd, pg.size() * sizeof(int))) != ABC_OK) {
+      abc_destroy(c);
+      return st;
+    }
+    if (hipMemcpy(gl, glin.data(), glin.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(pgd, pg.data(), pg.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess) {
+      abc_destroy(c);
+      return fail(ABC_EDEVICE, "hipMemcpy of Gamma maps failed");
+    }
+    L.gamma_lin = static_cast<const int*>(gl);
+    L.point_gamma = static_cast<const int*>(pgd);
+    rho = p.order == ABC_ZEROTH ? rho + bound : std::max(rho, bound) + std::sqrt(3.0) * 2.0 * std::abs(L.c[1]) / (2 * p.h * p.h);
+  }
+  // fourth-order Taylor polynomial: |T4(i y)| <= 1 requires |y| <= 2 sqrt(2)
+  if (p.dt * rho > 2.0 * std::sqrt(2.0)) {
+    abc_destroy(c);
+    return fail(ABC_EUNSTABLE, "dt times the spectral bound exceeds the Taylor-4 stability limit 2 sqrt(2)");
+  }
+
+  // scratch
+  const size_t csz = p.dtype == ABC_C64 ? 8 : 16;
+  const size_t rsz = p.dtype == ABC_C64 ? 4 : 8;
+  const size_t nel = (size_t)L.g.npts * p.batch;
+  abc_scratch& S = c->S;
+  size_t naux = 0;
+  if (bc) naux = p.form == ABC_FORM_BOX ? (size_t)c->n_gamma * p.batch : (size_t)L.g.face_off[6];
+  c->aux_elems = p.order == ABC_FIRST ? naux : 0;
+  S.red_blocks = 256 + 64;
+  void* tmp = nullptr;
+  if ((st = dev_alloc(c, &S.y[0], nel * csz)) != ABC_OK || (st = dev_alloc(c, &S.y[1], nel * csz)) != ABC_OK ||
+      (st = dev_alloc(c, &S.acc, nel * csz)) != ABC_OK) {
+    abc_destroy(c);
+    return st;
+  }
+  if (bc) {
+    if ((st = dev_alloc(c, &tmp, naux * 16)) != ABC_OK) { abc_destroy(c); return st; }
+    S.g[0] = static_cast<double2*>(tmp);
+    if ((st = dev_alloc(c, &tmp, naux * 16)) != ABC_OK) { abc_destroy(c); return st; }
+    S.g[1] = static_cast<double2*>(tmp);
+    if ((st = dev_alloc(c, &tmp, naux * 16)) != ABC_OK) { abc_destroy(c); return st; }
+    S.facc = static_cast<double2*>(tmp);
+    if ((st = dev_alloc(c, &tmp, naux * 16)) != ABC_OK) { abc_destroy(c); return st; }
+    S.src = static_cast<double2*>(tmp);
+  }
+  if (p.meanfield) {
+    if ((st = dev_alloc(c, &S.veff, (size_t)L.g.npts * rsz)) != ABC_OK) { abc_destroy(c); return st; }
+  }
+  if ((st = dev_alloc(c, &tmp, (size_t)p.batch * S.red_blocks * 4 * sizeof(double))) != ABC_OK) {
+    abc_destroy(c);
+    return st;
+  }
+  S.red = static_cast<double*>(tmp);
+
+  c->use_fused = 0;
+  if (p.path != ABC_PATH_STAGED) {
+    std::string why;
+    const bool ok = fused_supported(p, &why);
+    if (p.path == ABC_PATH_FUSED && !ok) {
+      abc_destroy(c);
+      return fail(ABC_ENOTSUP, "fused path: " + why);
+    }
+    c->use_fused = ok ? 1 : 0;
+    if (c->use_fused) {
+      st = fused_prepare(c->p, c->L, &c->allocations, &c->bytes, err);
+      if (st != ABC_OK) { abc_destroy(c); return fail(st, err); }
+    }
+  }
+  *out = c;
+  return ABC_OK;
+}
+
+size_t abc_aux_elems(const abc_ctx* c) { return c ? c->aux_elems : 0; }
+
+size_t abc_device_bytes(const abc_ctx* c) { return c ? c->bytes : 0; }
+
+abc_status abc_step(abc_ctx* c, void* psi, void* aux, const void* V, int n_steps, void* stream) {
+  if (!c || !psi) return fail(ABC_EINVAL, "null context or psi");
+  if (n_steps < 0) return fail(ABC_EINVAL, "n_steps must be >= 0");
+  if (c->p.order == ABC_FIRST && !aux) return fail(ABC_EINVAL, "first order needs the aux buffer");
+  if (n_steps == 0) return ABC_OK;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipError_t e;
+  if (c->use_fused)
+    e = launch_step_fused(c->L, c->S, psi, static_cast<double2*>(aux), V, n_steps, st);
+  else
+    e = launch_step_staged(c->L, c->S, psi, static_cast<double2*>(aux), V, n_steps, st);
+  if (e != hipSuccess) return fail(ABC_EDEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
+  return ABC_OK;
+}
+
+abc_status abc_diagnostics(abc_ctx* c, const void* psi, const void* aux, const void* V, double* out, void* stream) {
+  if (!c || !psi || !out) return fail(ABC_EINVAL, "null argument");
+  hipError_t e = launch_diagnostics(c->L, c->S, psi, static_cast<const double2*>(aux), V, out,
+                                    static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return fail(ABC_EDEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
+  return ABC_OK;
+}
+
+abc_status abc_export(const abc_ctx* c, int which, void* host_out, size_t n) {
+  if (!c || !host_out) return fail(ABC_EINVAL, "null argument");
+  if (which == 0) {
+    if (c->face.kernel.size() > n) return fail(ABC_EINVAL, "buffer too small");
+    std::memcpy(host_out, c->face.kernel.data(), c->face.kernel.size() * sizeof(abc::cd));
+    return ABC_OK;
+  }
+  if (which == 1) {
+    if (!c->box_mat) return fail(ABC_EINVAL, "no box-form matrix");
+    const size_t cnt = (size_t)c->n_gamma * c->n_gamma * (c->p.order == ABC_FIRST ? 2 : 1);
+    if (cnt > n) return fail(ABC_EINVAL, "buffer too small");
+    if (hipMemcpy(host_out, c->box_mat, cnt * 16, hipMemcpyDeviceToHost) != hipSuccess)
+      return fail(ABC_EDEVICE, "hipMemcpy failed");
+    return ABC_OK;
+  }
+  if (which == 2) {
+    const int R = c->p.radius;
+    if ((size_t)2 * R * R > n) return fail(ABC_EINVAL, "buffer too small");
+    abc::cd* o = static_cast<abc::cd*>(host_out);
+    for (int i = 0; i < R * R; ++i) { o[i] = c->face.a[i]; o[R * R + i] = c->face.q[i]; }
+    return ABC_OK;
+  }
+  return fail(ABC_EINVAL, "unknown export");
+}
+
+}  // extern "C"

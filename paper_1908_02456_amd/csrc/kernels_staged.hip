@@ -1,0 +1,609 @@
+// Stage-by-stage kernels for the Taylor-4 step with the DtN boundary
+// conditions.  One launch per stage for the box sweep plus one per stage for
+// the boundary operator; this path handles every order, form, kernel width
+// and precision and is the reference the fused kernel is checked against.
+//
+// A stage computes z_k = (dt/k) L z_{k-1} for the generator
+//   L(psi, f) = (-i H psi - i E^T f,  B f + A E psi)        (first order)
+//   L psi     = -i (H psi + E^T M E psi)                   (zeroth order)
+// (Sec. 3 dynamics) and accumulates z_0 + ... + z_4 (Sec. 4 Taylor step).
+#include <hip/hip_runtime.h>
+
+#include "abc_internal.h"
+
+using abc::Geometry;
+
+namespace {
+
+template <typename T> struct cpx;
+template <> struct cpx<double> { using t = double2; };
+template <> struct cpx<float> { using t = float2; };
+
+constexpr int kBlock = 256;
+
+struct StencilCoef {
+  double diag;               // -(3 c_0) / (2 h^2)
+  double off[abc::kMaxR + 1];  // -c_k / (2 h^2), k >= 1
+};
+
+__device__ __forceinline__ long long lin(const Geometry& g, int x, int y, int z) {
+  return ((long long)z * g.ny + y) * g.nx + x;
+}
+
+// linear index of face element (f, layer, t1, t2) in the box
+__device__ __forceinline__ long long face_point(const Geometry& g, int f, int l, int t1, int t2) {
+  switch (f) {
+    case 0: return lin(g, l, t2, t1);
+    case 1: return lin(g, g.nx - 1 - l, t2, t1);
+    case 2: return lin(g, t2, l, t1);
+    case 3: return lin(g, t2, g.ny - 1 - l, t1);
+    case 4: return lin(g, t2, t1, l);
+    default: return lin(g, t2, t1, g.nz - 1 - l);
+  }
+}
+
+// sum over the faces containing point (x, y, z) of the face buffer value
+__device__ __forceinline__ double2 face_gather(const Geometry& g, const double2* __restrict__ fb,
+                                               int x, int y, int z, int b) {
+  double2 s = make_double2(0.0, 0.0);
+  const int R = g.R, B = g.batch;
+  auto add = [&](int f, int l, int t1, int t2) {
+    const double2 v = fb[g.face_off[f] + (((long long)l * g.face_n1[f] + t1) * g.face_n2[f] + t2) * B + b];
+    s.x += v.x;
+    s.y += v.y;
+  };
+  if (x < R) add(0, x, z, y);
+  if (x >= g.nx - R) add(1, g.nx - 1 - x, z, y);
+  if (y < R) add(2, y, z, x);
+  if (y >= g.ny - R) add(3, g.ny - 1 - y, z, x);
+  if (z < R) add(4, z, y, x);
+  if (z >= g.nz - R) add(5, g.nz - 1 - z, y, x);
+  return s;
+}
+
+// ---------------------------------------------------------------------------
+// mean field: veff = V + t0 rho + t3 rho^2, rho = sum_b |psi_b|^2
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(kBlock) meanfield_kernel(const typename cpx<T>::t* __restrict__ psi,
+                                                           const T* __restrict__ V, T* __restrict__ veff,
+                                                           long long npts, int batch, T t0, T t3) {
+  long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= npts) return;
+  T rho = 0;
+  for (int b = 0; b < batch; ++b) {
+    auto v = psi[p * batch + b];
+    rho += v.x * v.x + v.y * v.y;
+  }
+  T base = V ? V[p] : T(0);
+  veff[p] = base + t0 * rho + t3 * rho * rho;
+}
+
+// ---------------------------------------------------------------------------
+// box sweep of one stage
+// mode 0: acc = y_in + y_new, y_out = y_new      (stage 1, y_in = psi)
+// mode 1: acc += y_new,       y_out = y_new      (stages 2, 3)
+// mode 2: psi = acc + y_new                      (stage 4)
+// ---------------------------------------------------------------------------
+template <typename T, int R, bool PER>
+__global__ void __launch_bounds__(kBlock) stage_kernel(
+    const typename cpx<T>::t* __restrict__ yin, typename cpx<T>::t* __restrict__ yout,
+    typename cpx<T>::t* __restrict__ acc, typename cpx<T>::t* __restrict__ psi_out,
+    const T* __restrict__ V, const double2* __restrict__ fsrc, const double2* __restrict__ bsrc,
+    const int* __restrict__ point_gamma, Geometry g, StencilCoef sc, double coef, int mode) {
+  using C = typename cpx<T>::t;
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int B = g.batch;
+  if (e >= g.npts * B) return;
+  const long long p = e / B;
+  const int b = (int)(e - p * B);
+  const int x = (int)(p % g.nx);
+  const int y = (int)((p / g.nx) % g.ny);
+  const int z = (int)(p / ((long long)g.nx * g.ny));
+  const C c0 = yin[e];
+  T hr = T(sc.diag) * c0.x, hi = T(sc.diag) * c0.y;
+  const long long sx = B, sy = (long long)g.nx * B, sz = (long long)g.nx * g.ny * B;
+#pragma unroll
+  for (int k = 1; k <= R; ++k) {
+    const T w = T(sc.off[k]);
+    T ar = 0, ai = 0;
+    if (PER) {
+      const int xp = (x + k) % g.nx, xm = (x - k + g.nx) % g.nx;
+      const int yp = (y + k) % g.ny, ym = (y - k + g.ny) % g.ny;
+      const int zp = (z + k) % g.nz, zm = (z - k + g.nz) % g.nz;
+      const C v0 = yin[(lin(g, xp, y, z)) * B + b], v1 = yin[(lin(g, xm, y, z)) * B + b];
+      const C v2 = yin[(lin(g, x, yp, z)) * B + b], v3 = yin[(lin(g, x, ym, z)) * B + b];
+      const C v4 = yin[(lin(g, x, y, zp)) * B + b], v5 = yin[(lin(g, x, y, zm)) * B + b];
+      ar = v0.x + v1.x + v2.x + v3.x + v4.x + v5.x;
+      ai = v0.y + v1.y + v2.y + v3.y + v4.y + v5.y;
+    } else {
+      if (x + k < g.nx) { C v = yin[e + k * sx]; ar += v.x; ai += v.y; }
+      if (x - k >= 0) { C v = yin[e - k * sx]; ar += v.x; ai += v.y; }
+      if (y + k < g.ny) { C v = yin[e + k * sy]; ar += v.x; ai += v.y; }
+      if (y - k >= 0) { C v = yin[e - k * sy]; ar += v.x; ai += v.y; }
+      if (z + k < g.nz) { C v = yin[e + k * sz]; ar += v.x; ai += v.y; }
+      if (z - k >= 0) { C v = yin[e - k * sz]; ar += v.x; ai += v.y; }
+    }
+    hr += w * ar;
+    hi += w * ai;
+  }
+  if (V) {
+    const T v = V[p];
+    hr += v * c0.x;
+    hi += v * c0.y;
+  }
+  // boundary term (FP64 source, added in the stencil precision)
+  if (fsrc) {
+    if (x < R || x >= g.nx - R || y < R || y >= g.ny - R || z < R || z >= g.nz - R) {
+      const double2 s = face_gather(g, fsrc, x, y, z, b);
+      hr += T(s.x);
+      hi += T(s.y);
+    }
+  } else if (bsrc) {
+    const int gi = point_gamma[p];
+    if (gi >= 0) {
+      const double2 s = bsrc[(long long)gi * B + b];
+      hr += T(s.x);
+      hi += T(s.y);
+    }
+  }
+  // y_new = coef * (-i) (H y + src)
+  const T cf = T(coef);
+  C yn;
+  yn.x = cf * hi;
+  yn.y = -cf * hr;
+  if (mode == 0) {
+    C a;
+    a.x = c0.x + yn.x;
+    a.y = c0.y + yn.y;
+    acc[e] = a;
+    yout[e] = yn;
+  } else if (mode == 1) {
+    C a = acc[e];
+    a.x += yn.x;
+    a.y += yn.y;
+    acc[e] = a;
+    yout[e] = yn;
+  } else {
+    C a = acc[e];
+    a.x += yn.x;
+    a.y += yn.y;
+    psi_out[e] = a;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// face-form boundary operator, one thread per face element (f, l, t1, t2, b)
+// first order: g_out = coef (B g_in + A E y);  mode as above for (facc, aux)
+// zeroth order: src = M E y
+// ---------------------------------------------------------------------------
+struct LocalBlock {
+  double2 m[abc::kMaxR * abc::kMaxR];
+};
+
+template <typename T, int R>
+__global__ void __launch_bounds__(kBlock) face_kernel(
+    const double2* __restrict__ gin, double2* __restrict__ gout, double2* __restrict__ facc,
+    double2* __restrict__ aux_out, const typename cpx<T>::t* __restrict__ yin,
+    const double2* __restrict__ ker, LocalBlock a, Geometry g, int w, double coef, int mode,
+    int first) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int B = g.batch;
+  if (e >= g.face_off[6]) return;
+  int f = 0;
+  while (e >= g.face_off[f + 1]) ++f;
+  const long long r = e - g.face_off[f];
+  const int n1 = g.face_n1[f], n2 = g.face_n2[f];
+  const int b = (int)(r % B);
+  const long long q = r / B;
+  const int t2 = (int)(q % n2);
+  const int t1 = (int)((q / n2) % n1);
+  const int l = (int)(q / ((long long)n1 * n2));
+  const int K = 2 * w + 1;
+  double sr = 0, si = 0;
+  const int j1lo = max(0, t1 - w), j1hi = min(n1 - 1, t1 + w);
+  const int j2lo = max(0, t2 - w), j2hi = min(n2 - 1, t2 + w);
+  for (int lp = 0; lp < R; ++lp) {
+    const double2* kl = ker + ((long long)(l * R + lp)) * K * K;
+    for (int j1 = j1lo; j1 <= j1hi; ++j1) {
+      const double2* krow = kl + (long long)(t1 - j1 + w) * K;
+      for (int j2 = j2lo; j2 <= j2hi; ++j2) {
+        const double2 kv = krow[t2 - j2 + w];
+        double2 v;
+        if (first) {
+          v = gin[g.face_off[f] + (((long long)lp * n1 + j1) * n2 + j2) * B + b];
+        } else {
+          const auto yv = yin[face_point(g, f, lp, j1, j2) * B + b];
+          v = make_double2((double)yv.x, (double)yv.y);
+        }
+        sr += kv.x * v.x - kv.y * v.y;
+        si += kv.x * v.y + kv.y * v.x;
+      }
+    }
+  }
+  if (!first) {
+    gout[e] = make_double2(sr, si);
+    return;
+  }
+  for (int lp = 0; lp < R; ++lp) {
+    const double2 av = a.m[l * R + lp];
+    const auto yv = yin[face_point(g, f, lp, t1, t2) * B + b];
+    const double yr = (double)yv.x, yi = (double)yv.y;
+    sr += av.x * yr - av.y * yi;
+    si += av.x * yi + av.y * yr;
+  }
+  const double2 gn = make_double2(coef * sr, coef * si);
+  if (mode == 0) {
+    const double2 g0 = gin[e];
+    facc[e] = make_double2(g0.x + gn.x, g0.y + gn.y);
+    gout[e] = gn;
+  } else if (mode == 1) {
+    double2 s = facc[e];
+    s.x += gn.x;
+    s.y += gn.y;
+    facc[e] = s;
+    gout[e] = gn;
+  } else {
+    const double2 s = facc[e];
+    aux_out[e] = make_double2(s.x + gn.x, s.y + gn.y);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// box form: dense operator on Gamma.  One workgroup per row block; the row
+// of the n x ncol matrix times [x1; x2] where x1 = aux stage (first order) or
+// absent, x2 = E y.  out = coef * (row . x)  (first) or row . x (zeroth).
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(kBlock) box_gemv_kernel(
+    const double2* __restrict__ mat, int n, int ncol, const double2* __restrict__ gin,
+    const typename cpx<T>::t* __restrict__ yin, const int* __restrict__ gamma_lin,
+    double2* __restrict__ gout, double2* __restrict__ facc, double2* __restrict__ aux_out,
+    int batch, double coef, int mode, int first) {
+  __shared__ double2 red[kBlock];
+  const int row = blockIdx.x;
+  const int b = blockIdx.y;
+  double sr = 0, si = 0;
+  const double2* mrow = mat + (long long)row * ncol;
+  for (int j = threadIdx.x; j < ncol; j += blockDim.x) {
+    const double2 m = mrow[j];
+    double2 v;
+    if (first && j < n) {
+      v = gin[(long long)j * batch + b];
+    } else {
+      const int jj = first ? j - n : j;
+      const auto yv = yin[(long long)gamma_lin[jj] * batch + b];
+      v = make_double2((double)yv.x, (double)yv.y);
+    }
+    sr += m.x * v.x - m.y * v.y;
+    si += m.x * v.y + m.y * v.x;
+  }
+  red[threadIdx.x] = make_double2(sr, si);
+  __syncthreads();
+  for (int s = kBlock / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+      red[threadIdx.x].x += red[threadIdx.x + s].x;
+      red[threadIdx.x].y += red[threadIdx.x + s].y;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
+  const long long e = (long long)row * batch + b;
+  if (!first) {
+    gout[e] = red[0];
+    return;
+  }
+  const double2 gn = make_double2(coef * red[0].x, coef * red[0].y);
+  if (mode == 0) {
+    const double2 g0 = gin[e];
+    facc[e] = make_double2(g0.x + gn.x, g0.y + gn.y);
+    gout[e] = gn;
+  } else if (mode == 1) {
+    double2 s = facc[e];
+    s.x += gn.x;
+    s.y += gn.y;
+    facc[e] = s;
+    gout[e] = gn;
+  } else {
+    const double2 s = facc[e];
+    aux_out[e] = make_double2(s.x + gn.x, s.y + gn.y);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// diagnostics: per-(orbital, block) partial sums, then a fixed-order finish
+// ---------------------------------------------------------------------------
+constexpr int kRedBlocks = 256;  // point blocks per orbital
+constexpr int kAuxBlocks = 64;   // aux blocks per orbital
+
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int s = kBlock / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+    __syncthreads();
+  }
+  const double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+template <typename T, int R, bool PER>
+__global__ void __launch_bounds__(kBlock) diag_points_kernel(
+    const typename cpx<T>::t* __restrict__ psi, const T* __restrict__ V, Geometry g, StencilCoef sc,
+    int meanfield, double t0, double t3, double* __restrict__ part) {
+  __shared__ double sh[kBlock];
+  using C = typename cpx<T>::t;
+  const int b = blockIdx.y, B = g.batch;
+  double nrm = 0, en = 0, eint = 0;
+  for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < g.npts;
+       p += (long long)gridDim.x * blockDim.x) {
+    const int x = (int)(p % g.nx);
+    const int y = (int)((p / g.nx) % g.ny);
+    const int z = (int)(p / ((long long)g.nx * g.ny));
+    const C c0 = psi[p * B + b];
+    const double cr = c0.x, ci = c0.y;
+    double hr = sc.diag * cr, hi = sc.diag * ci;
+    for (int k = 1; k <= R; ++k) {
+      double ar = 0, ai = 0;
+      int nb[6][3] = {{x + k, y, z}, {x - k, y, z}, {x, y + k, z}, {x, y - k, z}, {x, y, z + k}, {x, y, z - k}};
+      for (int m = 0; m < 6; ++m) {
+        int xx = nb[m][0], yy = nb[m][1], zz = nb[m][2];
+        if (PER) {
+          xx = (xx + g.nx) % g.nx; yy = (yy + g.ny) % g.ny; zz = (zz + g.nz) % g.nz;
+        } else if (xx < 0 || xx >= g.nx || yy < 0 || yy >= g.ny || zz < 0 || zz >= g.nz) {
+          continue;
+        }
+        const C v = psi[lin(g, xx, yy, zz) * B + b];
+        ar += v.x;
+        ai += v.y;
+      }
+      hr += sc.off[k] * ar;
+      hi += sc.off[k] * ai;
+    }
+    if (V) {
+      hr += (double)V[p] * cr;
+      hi += (double)V[p] * ci;
+    }
+    nrm += cr * cr + ci * ci;
+    en += cr * hr + ci * hi;
+    if (meanfield && b == 0) {
+      double rho = 0;
+      for (int bb = 0; bb < B; ++bb) {
+        const C v = psi[p * B + bb];
+        rho += (double)v.x * v.x + (double)v.y * v.y;
+      }
+      eint += t0 * rho * rho / 2 + t3 * rho * rho * rho / 3;
+    }
+  }
+  nrm = block_sum(nrm, sh);
+  en = block_sum(en, sh);
+  eint = block_sum(eint, sh);
+  if (threadIdx.x == 0) {
+    double* o = part + ((long long)b * (kRedBlocks + kAuxBlocks) + blockIdx.x) * 4;
+    o[0] = nrm;
+    o[1] = en;
+    o[2] = eint;
+    o[3] = 0;
+  }
+}
+
+template <int R>
+__global__ void __launch_bounds__(kBlock) diag_aux_kernel(const double2* __restrict__ aux, Geometry g,
+                                                           LocalBlock q, long long nface_lines,
+                                                           double* __restrict__ part) {
+  // sum over face lines (f, t1, t2) of f^* q f per orbital
+  __shared__ double sh[kBlock];
+  const int b = blockIdx.y, B = g.batch;
+  double s = 0;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < nface_lines;
+       e += (long long)gridDim.x * blockDim.x) {
+    // locate face f and transverse index
+    long long acc = 0;
+    int f = 0;
+    for (; f < 6; ++f) {
+      const long long m = (long long)g.face_n1[f] * g.face_n2[f];
+      if (e < acc + m) break;
+      acc += m;
+    }
+    const long long t = e - acc;
+    const long long plane = (long long)g.face_n1[f] * g.face_n2[f];
+    double2 v[R];
+    for (int l = 0; l < R; ++l) v[l] = aux[g.face_off[f] + ((long long)l * plane + t) * B + b];
+    for (int l = 0; l < R; ++l)
+      for (int lp = 0; lp < R; ++lp) {
+        const double2 qq = q.m[l * R + lp];
+        // conj(v_l) * qq * v_lp, real part
+        const double xr = qq.x * v[lp].x - qq.y * v[lp].y;
+        const double xi = qq.x * v[lp].y + qq.y * v[lp].x;
+        s += v[l].x * xr + v[l].y * xi;
+      }
+  }
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) {
+    double* o = part + ((long long)b * (kRedBlocks + kAuxBlocks) + kRedBlocks + blockIdx.x) * 4;
+    o[0] = s;
+    o[1] = 0;
+    o[2] = 0;
+    o[3] = 0;
+  }
+}
+
+__global__ void diag_box_aux_kernel(const double2* __restrict__ aux, const double2* __restrict__ qmat, int n,
+                                    int batch, double* __restrict__ part) {
+  // f^* Q f with dense Q (box form); rows strided over the aux blocks
+  __shared__ double sh[kBlock];
+  const int b = blockIdx.y;
+  double s = 0;
+  for (int i = blockIdx.x; i < n; i += gridDim.x) {
+    double xr = 0, xi = 0;
+    for (int j = threadIdx.x; j < n; j += blockDim.x) {
+      const double2 qq = qmat[(long long)i * n + j];
+      const double2 v = aux[(long long)j * batch + b];
+      xr += qq.x * v.x - qq.y * v.y;
+      xi += qq.x * v.y + qq.y * v.x;
+    }
+    xr = block_sum(xr, sh);
+    xi = block_sum(xi, sh);
+    const double2 vi = aux[(long long)i * batch + b];
+    s += vi.x * xr + vi.y * xi;
+  }
+  if (threadIdx.x == 0) {
+    double* o = part + ((long long)b * (kRedBlocks + kAuxBlocks) + kRedBlocks + blockIdx.x) * 4;
+    o[0] = s;
+    o[1] = 0;
+    o[2] = 0;
+    o[3] = 0;
+  }
+}
+
+__global__ void diag_finish_kernel(const double* __restrict__ part, int batch, double h3, int has_aux,
+                                   double* __restrict__ out) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= batch) return;
+  const double* pb = part + (long long)b * (kRedBlocks + kAuxBlocks) * 4;
+  double nrm = 0, en = 0, eint = 0, qa = 0;
+  for (int i = 0; i < kRedBlocks; ++i) {
+    nrm += pb[i * 4 + 0];
+    en += pb[i * 4 + 1];
+    eint += pb[i * 4 + 2];
+  }
+  if (has_aux)
+    for (int i = 0; i < kAuxBlocks; ++i) qa += pb[(kRedBlocks + i) * 4];
+  out[b] = h3 * nrm;
+  out[batch + b] = h3 * (nrm + qa);
+  out[2 * batch + b] = h3 * en;
+  if (b == 0) out[3 * batch] = h3 * eint;
+}
+
+StencilCoef make_coef(const abc_launch& L) {
+  StencilCoef sc{};
+  const double s = 1.0 / (2.0 * L.h * L.h);
+  sc.diag = -3.0 * L.c[0] * s;
+  for (int k = 1; k <= L.g.R; ++k) sc.off[k] = -L.c[k] * s;
+  return sc;
+}
+
+LocalBlock make_local(const double2* m) {
+  LocalBlock a{};
+  for (int i = 0; i < abc::kMaxR * abc::kMaxR; ++i) a.m[i] = m[i];
+  return a;
+}
+
+inline unsigned nblocks(long long n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+template <typename T, int R, bool PER>
+hipError_t step_staged_t(const abc_launch& L, const abc_scratch& S, void* psi_v, double2* aux,
+                         const void* V_v, int n_steps, hipStream_t st) {
+  using C = typename cpx<T>::t;
+  const Geometry& g = L.g;
+  C* psi = static_cast<C*>(psi_v);
+  const T* V = static_cast<const T*>(V_v);
+  C* y[2] = {static_cast<C*>(S.y[0]), static_cast<C*>(S.y[1])};
+  C* acc = static_cast<C*>(S.acc);
+  const StencilCoef sc = make_coef(L);
+  const LocalBlock a = make_local(L.a_loc);
+  const long long nel = g.npts * g.batch;
+  const long long nface = g.face_off[6];
+  const bool first = L.order == ABC_FIRST, zeroth = L.order == ABC_ZEROTH;
+  const bool box = L.form == ABC_FORM_BOX;
+  for (int s = 0; s < n_steps; ++s) {
+    const T* Vuse = V;
+    if (L.meanfield) {
+      meanfield_kernel<T><<<nblocks(g.npts), kBlock, 0, st>>>(psi, V, static_cast<T*>(S.veff), g.npts, g.batch,
+                                                            T(L.t0), T(L.t3));
+      Vuse = static_cast<const T*>(S.veff);
+    }
+    const C* ycur = psi;
+    const double2* gcur = aux;  // g_0 = f
+    for (int k = 1; k <= 4; ++k) {
+      const double coef = L.dt / k;
+      const int mode = k == 1 ? 0 : (k == 4 ? 2 : 1);
+      const double2* fsrc = nullptr;
+      const double2* bsrc = nullptr;
+      if (first || zeroth) {
+        double2* gnext = (k == 4) ? nullptr : S.g[(k - 1) & 1];
+        if (box) {
+          const int ncol = first ? 2 * L.n_gamma : L.n_gamma;
+          dim3 grid(L.n_gamma, g.batch);
+          box_gemv_kernel<T><<<grid, kBlock, 0, st>>>(L.box_mat, L.n_gamma, ncol, gcur, ycur, L.gamma_lin,
+                                                      first ? gnext : S.src, S.facc, aux, g.batch, coef, mode,
+                                                      first ? 1 : 0);
+        } else {
+          face_kernel<T, R><<<nblocks(nface), kBlock, 0, st>>>(gcur, first ? gnext : S.src, S.facc, aux, ycur,
+                                                               L.face_ker, a, g, L.w, coef, mode, first ? 1 : 0);
+        }
+        const double2* s_for_stage = first ? gcur : S.src;
+        if (box) bsrc = s_for_stage; else fsrc = s_for_stage;
+        if (first) gcur = gnext;
+      }
+      C* yout = (k == 4) ? nullptr : y[(k - 1) & 1];
+      stage_kernel<T, R, PER><<<nblocks(nel), kBlock, 0, st>>>(ycur, yout, acc, psi, Vuse, fsrc, bsrc,
+                                                               L.point_gamma, g, sc, coef, mode);
+      ycur = yout;
+    }
+  }
+  return hipGetLastError();
+}
+
+template <typename T, int R, bool PER>
+hipError_t diag_t(const abc_launch& L, const abc_scratch& S, const void* psi, const double2* aux, const void* V,
+                  double* out, hipStream_t st) {
+  using C = typename cpx<T>::t;
+  const Geometry& g = L.g;
+  const StencilCoef sc = make_coef(L);
+  dim3 grid(kRedBlocks, g.batch);
+  diag_points_kernel<T, R, PER><<<grid, kBlock, 0, st>>>(static_cast<const C*>(psi), static_cast<const T*>(V), g, sc,
+                                                         L.meanfield, L.t0, L.t3, S.red);
+  const int has_aux = (L.order == ABC_FIRST && aux) ? 1 : 0;
+  if (has_aux) {
+    dim3 ga(kAuxBlocks, g.batch);
+    if (L.form == ABC_FORM_BOX) {
+      diag_box_aux_kernel<<<ga, kBlock, 0, st>>>(aux, L.box_q, L.n_gamma, g.batch, S.red);
+    } else {
+      long long lines = 0;
+      for (int f = 0; f < 6; ++f) lines += (long long)g.face_n1[f] * g.face_n2[f];
+      diag_aux_kernel<R><<<ga, kBlock, 0, st>>>(aux, g, make_local(L.q_loc), lines, S.red);
+    }
+  }
+  diag_finish_kernel<<<(g.batch + 63) / 64, 64, 0, st>>>(S.red, g.batch, L.h * L.h * L.h, has_aux, out);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t dispatch_step(const abc_launch& L, const abc_scratch& S, void* psi, double2* aux, const void* V,
+                         int n, hipStream_t st) {
+  const bool per = L.periodic != 0;
+  switch (L.g.R) {
+    case 1: return per ? step_staged_t<T, 1, true>(L, S, psi, aux, V, n, st) : step_staged_t<T, 1, false>(L, S, psi, aux, V, n, st);
+    case 2: return per ? step_staged_t<T, 2, true>(L, S, psi, aux, V, n, st) : step_staged_t<T, 2, false>(L, S, psi, aux, V, n, st);
+    case 3: return per ? step_staged_t<T, 3, true>(L, S, psi, aux, V, n, st) : step_staged_t<T, 3, false>(L, S, psi, aux, V, n, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <typename T>
+hipError_t dispatch_diag(const abc_launch& L, const abc_scratch& S, const void* psi, const double2* aux,
+                         const void* V, double* out, hipStream_t st) {
+  const bool per = L.periodic != 0;
+  switch (L.g.R) {
+    case 1: return per ? diag_t<T, 1, true>(L, S, psi, aux, V, out, st) : diag_t<T, 1, false>(L, S, psi, aux, V, out, st);
+    case 2: return per ? diag_t<T, 2, true>(L, S, psi, aux, V, out, st) : diag_t<T, 2, false>(L, S, psi, aux, V, out, st);
+    case 3: return per ? diag_t<T, 3, true>(L, S, psi, aux, V, out, st) : diag_t<T, 3, false>(L, S, psi, aux, V, out, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+hipError_t launch_step_staged(const abc_launch& L, const abc_scratch& S, void* psi, double2* aux, const void* V,
+                              int n_steps, hipStream_t st) {
+  if (L.dtype == ABC_C64) return dispatch_step<float>(L, S, psi, aux, V, n_steps, st);
+  return dispatch_step<double>(L, S, psi, aux, V, n_steps, st);
+}
+
+hipError_t launch_diagnostics(const abc_launch& L, const abc_scratch& S, const void* psi, const double2* aux,
+                              const void* V, double* out, hipStream_t st) {
+  if (L.dtype == ABC_C64) return dispatch_diag<float>(L, S, psi, aux, V, out, st);
+  return dispatch_diag<double>(L, S, psi, aux, V, out, st);
+}

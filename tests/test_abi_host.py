@@ -1,0 +1,86 @@
+"""Host-side checks of the C ABI: the library loads, exports every symbol the
+header declares, and the ctypes structure matches the C layout.  No GPU."""
+import ctypes
+import os
+import re
+import subprocess
+import tempfile
+
+import pytest
+
+from paper_1908_02456_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "abc_dtn.h")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"\b(abc_[a-z_]+)\s*\(", text)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.skip("library not built")
+    return _lib.load()
+
+
+def test_header_declares_what_binding_uses():
+    assert set(_declared_functions()) == set(_lib.EXPORTED)
+
+
+def test_library_exports_every_declared_symbol(lib):
+    out = subprocess.run(["nm", "-D", "--defined-only", _lib.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(re.findall(r" T (\w+)", out))
+    missing = [n for n in _declared_functions() if n not in exported]
+    assert not missing, missing
+
+
+def test_params_struct_layout_matches_c():
+    src = r'''
+#include <stdio.h>
+#include <stddef.h>
+#include "abc_dtn.h"
+int main(void) {
+  printf("%zu", sizeof(abc_params));
+#define F(x) printf(" %zu", offsetof(abc_params, x));
+  F(nx) F(ny) F(nz) F(h) F(dt) F(radius) F(order) F(form) F(s0) F(s1) F(s2) F(window) F(fejer)
+  F(dtype) F(batch) F(meanfield) F(t0) F(t3) F(path) F(reserved)
+  printf("\n");
+  return 0;
+}
+'''
+    with tempfile.TemporaryDirectory() as d:
+        c = os.path.join(d, "t.c")
+        exe = os.path.join(d, "t")
+        open(c, "w").write(src)
+        subprocess.run(["gcc", "-I" + os.path.dirname(HEADER), c, "-o", exe], check=True)
+        vals = [int(v) for v in subprocess.run([exe], capture_output=True, text=True).stdout.split()]
+    P = _lib.AbcParams
+    names = ["nx", "ny", "nz", "h", "dt", "radius", "order", "form", "s0", "s1", "s2", "window", "fejer",
+             "dtype", "batch", "meanfield", "t0", "t3", "path", "reserved"]
+    assert vals[0] == ctypes.sizeof(P)
+    assert vals[1:] == [getattr(P, n).offset for n in names]
+
+
+def test_defaults_and_error_text(lib):
+    p = _lib.AbcParams()
+    lib.abc_params_default(ctypes.byref(p))
+    assert (p.radius, p.order, p.form, p.dtype, p.batch, p.fejer) == (1, 3, 1, 0, 1, 1)
+    # invalid parameters are rejected before any device call
+    p.radius = 7
+    ctx = ctypes.c_void_p()
+    st = lib.abc_setup(ctypes.byref(p), ctypes.byref(ctx))
+    assert st == _lib.ABC_EINVAL
+    assert b"radius" in lib.abc_last_error()
+    assert not ctx.value
+    lib.abc_params_default(ctypes.byref(p))
+    p.s1 = -1.0
+    assert lib.abc_setup(ctypes.byref(p), ctypes.byref(ctx)) == _lib.ABC_EUNSTABLE
+    lib.abc_params_default(ctypes.byref(p))
+    p.reserved[2] = 1
+    assert lib.abc_setup(ctypes.byref(p), ctypes.byref(ctx)) == _lib.ABC_EINVAL
+    lib.abc_destroy(None)

@@ -1,0 +1,148 @@
+"""HIP path vs the FP64 oracle, element by element, on the same seeded inputs.
+
+FP64 path: max |psi_gpu - psi_oracle| <= 1e-12 max |psi_oracle| (and the same
+for the auxiliary variable).  FP32 stencil path (complex64 state, FP64
+auxiliary recurrences): 1e-5.  Every case prints its name before it touches
+the GPU.
+"""
+import math
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import dtn, integrate
+from paper_1908_02456_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+TOL32 = 1e-5
+
+
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1908_02456_amd.solver import Solver
+    return Solver
+
+
+def _run_pair(name, shape, h, dt, R, order, steps, *, form="faces", s0=1.0, s1=1.0, s2=math.inf, window=0,
+              fejer=True, batch=None, meanfield=None, dtype="c128", seed=0, psi0=None, V=None, path="auto"):
+    print("case:", name, shape, "R", R, order, form, "w", window, "batch", batch, dtype, flush=True)
+    Solver = _gpu()
+    if psi0 is None:
+        full = shape if batch is None else shape + (batch,)
+        psi0 = W.random_complex(full, seed=seed)
+    if V is None:
+        V = W.random_potential(shape, seed=seed + 100, scale=2.0)
+    st = integrate.make_setup(shape, h, dt, R, order, form=form, s0=s0, s1=s1, s2=s2, window=window,
+                              use_window=fejer, t0=None if meanfield is None else meanfield[0],
+                              t3=0.0 if meanfield is None else meanfield[1])
+    ref_psi, ref_aux, _ = integrate.run(st, psi0, V, steps)
+    solver = Solver(shape, h, dt, radius=R, order=order, form=form, s0=s0, s1=s1,
+                    s2=(0.0 if math.isinf(s2) else s2), window=window, fejer=fejer, dtype=dtype,
+                    batch=1 if batch is None else batch, meanfield=meanfield, path=path)
+    cdt = torch.complex128 if dtype == "c128" else torch.complex64
+    rdt = torch.float64 if dtype == "c128" else torch.float32
+    psi = torch.from_numpy(psi0).to(cdt).cuda().contiguous()
+    Vt = torch.from_numpy(V).to(rdt).cuda().contiguous()
+    aux = solver.new_aux()
+    solver.step(psi, aux, Vt, steps)
+    torch.cuda.synchronize()
+    got = psi.cpu().numpy().astype(np.complex128)
+    scale = np.abs(ref_psi).max()
+    err = np.abs(got - ref_psi).max() / scale
+    out = {"err": err, "solver": solver, "psi": psi, "aux": aux, "V": Vt, "ref_psi": ref_psi,
+           "ref_aux": ref_aux, "st": st}
+    if order == "first":
+        ref_flat = integrate.pack_aux(st, ref_aux)
+        got_aux = aux.cpu().numpy()[:ref_flat.size]
+        out["aux_err"] = np.abs(got_aux - ref_flat).max() / max(np.abs(ref_flat).max(), 1e-300)
+    return out
+
+
+@pytest.mark.parametrize("R", [1, 2, 3])
+@pytest.mark.parametrize("order", ["dirichlet", "periodic"])
+def test_no_condition_parity(R, order):
+    r = _run_pair("plain", (13, 11, 17), 0.3, 0.01, R, order, 4)
+    assert r["err"] < TOL64, r["err"]
+
+
+@pytest.mark.parametrize("R,window,fejer", [(1, 0, True), (1, 2, True), (2, 1, True), (3, 0, True),
+                                            (1, 3, False)])
+def test_zeroth_faces_parity(R, window, fejer):
+    r = _run_pair("zeroth-faces", (12, 10, 14), 0.25, 0.004, R, "zeroth", 5, s0=2.0, window=window, fejer=fejer)
+    assert r["err"] < TOL64, r["err"]
+
+
+@pytest.mark.parametrize("R,window,fejer", [(1, 0, True), (1, 3, True), (2, 2, True), (3, 1, True),
+                                            (1, 9, False)])
+def test_first_faces_parity(R, window, fejer):
+    r = _run_pair("first-faces", (11, 10, 13), 0.25, 0.004, R, "first", 6, s1=1.5, window=window, fejer=fejer)
+    assert r["err"] < TOL64, r["err"]
+    assert r["aux_err"] < TOL64, r["aux_err"]
+
+
+def test_first_faces_full_section_parity():
+    # window = n - 1 without taper: the exact Toeplitz section of each face
+    r = _run_pair("first-faces-full", (10, 10, 10), 0.25, 0.004, 1, "first", 4, s1=1.0, window=9, fejer=False)
+    assert r["err"] < TOL64 and r["aux_err"] < TOL64, (r["err"], r["aux_err"])
+
+
+@pytest.mark.parametrize("R,order,s2", [(1, "zeroth", math.inf), (1, "first", math.inf), (1, "first", 2.0),
+                                        (2, "zeroth", math.inf), (2, "first", math.inf)])
+def test_box_form_parity(R, order, s2):
+    n = 6 if R == 1 else 7
+    r = _run_pair("box", (n, n, n), 0.3, 0.004, R, order, 5, form="box", s0=1.0, s1=1.0, s2=s2)
+    assert r["err"] < TOL64, r["err"]
+    if order == "first":
+        assert r["aux_err"] < TOL64, r["aux_err"]
+
+
+def test_batch_meanfield_parity():
+    r = _run_pair("batch-meanfield", (9, 10, 11), 0.3, 0.004, 1, "first", 5, s1=1.0, window=2, batch=3,
+                  meanfield=(-1.0, 0.5))
+    assert r["err"] < TOL64 and r["aux_err"] < TOL64, (r["err"], r["aux_err"])
+
+
+@pytest.mark.parametrize("order,window", [("first", 0), ("first", 2), ("zeroth", 1), ("dirichlet", 0)])
+def test_fp32_path_parity(order, window):
+    r = _run_pair("c64", (12, 11, 10), 0.25, 0.004, 1, order, 8, s0=1.0, s1=1.0, window=window, dtype="c64")
+    assert r["err"] < TOL32, r["err"]
+
+
+def test_face_kernel_export_matches_oracle():
+    Solver = _gpu()
+    h, R, w, s1 = 0.2, 2, 4, 1.3
+    s = Solver((9, 9, 9), h, 0.002, radius=R, order="first", s1=s1, window=w, fejer=True)
+    got = s.face_kernel()
+    ref = dtn.face_first(h, R, s1, w).kernel
+    assert np.abs(got - ref).max() < 1e-12 * np.abs(ref).max()
+
+
+def test_diagnostics_match_oracle():
+    r = _run_pair("diag", (10, 9, 11), 0.25, 0.004, 1, "first", 3, s1=1.0, window=1)
+    assert r["err"] < TOL64
+    d = r["solver"].diagnostics(r["psi"], r["aux"], r["V"]).cpu().numpy()
+    st = r["st"]
+    ref = integrate.diagnostics(st, r["ref_psi"], r["ref_aux"], np.asarray(r["V"].cpu().numpy()))
+    assert abs(d[0] - ref["norm"]) < 1e-12 * ref["norm"]
+    assert abs(d[1] - ref["lyapunov"]) < 1e-12 * ref["lyapunov"]
+    assert abs(d[2] - ref["energy"]) < 1e-11 * abs(ref["energy"])
+
+
+def test_zero_steps_and_minimum_box():
+    r = _run_pair("min-box", (3, 3, 3), 0.3, 0.004, 1, "first", 0, window=1)
+    assert r["err"] == 0
+    r = _run_pair("min-box", (3, 3, 3), 0.3, 0.004, 1, "first", 3, window=1)
+    assert r["err"] < TOL64
+
+
+def test_setup_rejects_unstable_dt():
+    Solver = _gpu()
+    from paper_1908_02456_amd._lib import AbcError, ABC_EUNSTABLE
+    with pytest.raises(AbcError) as e:
+        Solver((8, 8, 8), 0.1, 0.1, order="first")
+    assert e.value.status == ABC_EUNSTABLE
