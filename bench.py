@@ -1,0 +1,186 @@
+"""Throughput of the DtN-ABC time stepper on one MI355X.
+
+A step is one fourth-order Taylor step of the whole hot path (interior
+stencil + potential, boundary operators, auxiliary boundary variables, all
+four stages) over the full grid.  Default workload: one orbital on a 128^3
+grid, h = 0.2, dt = 0.002, static Gaussian well V = -5 exp(-|x|^2/2), packet
+with k = (3, 1, 0) from a seeded centre, first-order face-form condition,
+complex128.  Inputs are resident in HBM before the timed region starts.
+
+Prints one JSON line.  Besides throughput it reports the roofline of the
+dominant kernel (HIP events over the timed region), the FP64 oracle timed on
+the host on a bounded sample, and the physics error of the absorbing run
+against a run on a box twice as large per axis with zero boundary values
+(same h, dt, integrator; reflections from its walls cannot return in time).
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--dtype c128|c64]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def physics_error(Solver, torch, wl, dtype, window, path, steps_total):
+    """Relative L2 error at T of the absorbing run vs the doubled Dirichlet box,
+    both started from the same box-only data (zero outside the small box)."""
+    n = wl.n
+    big = 2 * n
+    off = (big - n) // 2
+    cdt = torch.complex128 if dtype == "c128" else torch.complex64
+    rdt = torch.float64 if dtype == "c128" else torch.float32
+    from paper_1908_02456_amd import workloads as W
+    # zero-extended initial data; the well is evaluated on the big grid
+    psi_b = torch.zeros((big, big, big), dtype=cdt, device="cuda")
+    psi_b[off:off + n, off:off + n, off:off + n] = torch.from_numpy(wl.psi0).to(cdt)
+    Vb = torch.from_numpy(W.gaussian_well((big,) * 3, wl.h, 5.0)).to(rdt).cuda()
+    sb = Solver((big,) * 3, wl.h, wl.dt, order="dirichlet", dtype=dtype, path=path)
+    sb.step(psi_b, None, Vb, steps_total)
+    ref = psi_b[off:off + n, off:off + n, off:off + n].to(torch.complex128)
+    s = Solver((n,) * 3, wl.h, wl.dt, order="first", s1=wl.s1, window=window, dtype=dtype, path=path)
+    psi = torch.from_numpy(wl.psi0).to(cdt).cuda()
+    aux = s.new_aux()
+    V = torch.from_numpy(wl.V).to(rdt).cuda()
+    s.step(psi, aux, V, steps_total)
+    # the same box with zero boundary values (what the condition replaces)
+    sd = Solver((n,) * 3, wl.h, wl.dt, order="dirichlet", dtype=dtype, path=path)
+    psid = torch.from_numpy(wl.psi0).to(cdt).cuda()
+    sd.step(psid, None, V, steps_total)
+    torch.cuda.synchronize()
+    nr = torch.linalg.vector_norm(ref).item()
+    e_abc = torch.linalg.vector_norm(psi.to(torch.complex128) - ref).item() / nr
+    e_dir = torch.linalg.vector_norm(psid.to(torch.complex128) - ref).item() / nr
+    h3 = wl.h ** 3
+    return {"err_vs_large_box": e_abc, "err_dirichlet_same_box": e_dir, "large_box_n": big,
+            "T": steps_total * wl.dt, "norm_abc": h3 * float(torch.sum(torch.abs(psi.to(torch.complex128)) ** 2)),
+            "norm_large_box_in_box": h3 * nr * nr, "norm_initial": h3 * float(np.sum(np.abs(wl.psi0) ** 2))}
+
+
+def cpu_baseline(wl, window, budget_s=15.0):
+    """FP64 oracle (NumPy, single-threaded elementwise) on the same workload,
+    for as many whole steps as fit in about budget_s seconds."""
+    try:
+        from threadpoolctl import threadpool_limits
+    except Exception:  # pragma: no cover
+        threadpool_limits = None
+    from oracle import integrate
+    st = integrate.make_setup((wl.n,) * 3, wl.h, wl.dt, wl.radius, "first", s1=wl.s1, window=window)
+    psi, aux = wl.psi0.copy(), integrate.zero_aux(st)
+    ctx = threadpool_limits(1) if threadpool_limits else None
+    if ctx:
+        ctx.__enter__()
+    try:
+        t0 = time.perf_counter()
+        steps = 0
+        while True:
+            psi, aux = integrate.taylor4_step(st, psi, aux, wl.V)
+            steps += 1
+            el = time.perf_counter() - t0
+            if el > budget_s or steps >= 50:
+                break
+    finally:
+        if ctx:
+            ctx.__exit__(None, None, None)
+    return {"value": wl.n ** 3 * steps / el, "unit": "grid-point-updates/s", "cores": 1, "kind": "oracle",
+            "sample": "%d Taylor steps of the same %d^3 first-order face-form workload (FP64 NumPy, %.1f s)"
+                      % (steps, wl.n, el)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=400)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--dtype", default="c128", choices=["c128", "c64"])
+    ap.add_argument("--n", type=int, default=128)
+    ap.add_argument("--window", type=int, default=0)
+    ap.add_argument("--path", default="auto", choices=["auto", "staged", "fused"])
+    ap.add_argument("--no-physics", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (see DESIGN.md for how the "
+              "stepper would shard); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1908_02456_amd import workloads as W
+    from paper_1908_02456_amd.solver import Solver
+
+    wl = W.well_packet(n=args.n, window=args.window)
+    cdt = torch.complex128 if args.dtype == "c128" else torch.complex64
+    rdt = torch.float64 if args.dtype == "c128" else torch.float32
+    log("setup: %d^3 first-order faces w=%d %s path=%s" % (wl.n, args.window, args.dtype, args.path))
+    s = Solver((wl.n,) * 3, wl.h, wl.dt, order="first", s1=wl.s1, window=args.window, dtype=args.dtype,
+               path=args.path)
+    psi = torch.from_numpy(wl.psi0).to(cdt).cuda().contiguous()
+    V = torch.from_numpy(wl.V).to(rdt).cuda().contiguous()
+    aux = s.new_aux()
+    stream = torch.cuda.current_stream()
+    s.step(psi, aux, V, args.warmup)
+    torch.cuda.synchronize()
+    log("warmup done (%d steps)" % args.warmup)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    s.step(psi, aux, V, args.steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    ms_step = ms / args.steps
+    npts = wl.n ** 3
+    value = npts * args.steps / (ms / 1e3)
+    log("timed %d steps: %.3f ms/step, %.3e GPUPS" % (args.steps, ms_step, value))
+
+    # algorithmic bytes per grid-point update: psi read + write, V read,
+    # plus the FP64 auxiliary slab (read + write) spread over the volume
+    csz = 16 if args.dtype == "c128" else 8
+    rsz = 8 if args.dtype == "c128" else 4
+    aux_bytes = 6 * wl.radius * wl.n * wl.n * 32
+    step_bytes = npts * (2 * csz + rsz) + aux_bytes
+    fused = s.use_fused if hasattr(s, "use_fused") else None
+    launches_per_step = 1
+    kernel = "fused Taylor-4 step" if fused else "whole staged step (4 stencil + 4 boundary launches)"
+    achieved = step_bytes / (ms_step / 1e3) / 1e9 / launches_per_step
+    roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": kernel,
+            "alg_bytes_per_launch": step_bytes}
+
+    out = {"metric": "grid-point-updates/s incl. ABC (% HBM roofline); err vs FP64 large-box oracle",
+           "value": value, "unit": "grid-point-updates/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64" if args.dtype == "c128" else "f32 stencil / f64 aux",
+           "data": "synthetic",
+           "config": {"workload": "single orbital %d^3, h=%.2g, dt=%.3g, first-order face-form DtN ABC "
+                                  "(s1=%.3g, w=%d), Gaussian well + k=(3,1,0) packet, %s"
+                                  % (wl.n, wl.h, wl.dt, wl.s1, args.window, args.dtype),
+                      "grid": [wl.n] * 3, "radius": wl.radius, "path": args.path},
+           "roofline": roof}
+    if not args.no_physics:
+        log("physics run: %d steps vs %d^3 zero-boundary box" % (wl.steps, 2 * wl.n))
+        out["physics"] = physics_error(Solver, torch, wl, args.dtype, args.window, args.path, wl.steps)
+    if not args.no_cpu:
+        log("cpu baseline (oracle) ...")
+        out["cpu_baseline"] = cpu_baseline(wl, args.window)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -145,6 +145,9 @@ size_t abc_aux_elems(const abc_ctx* ctx);
  * n = capacity in complex128 elements; returns EINVAL if too small. */
 abc_status abc_export(const abc_ctx* ctx, int which, void* host_out, size_t n);
 
+/* Execution path chosen at setup: ABC_PATH_STAGED or ABC_PATH_FUSED. */
+int abc_path(const abc_ctx* ctx);
+
 /* Bytes of device memory held by the context. */
 size_t abc_device_bytes(const abc_ctx* ctx);
 

@@ -17,7 +17,7 @@ DTYPES = {"c128": 0, "c64": 1}
 PATHS = {"auto": 0, "staged": 1, "fused": 2}
 
 EXPORTED = ["abc_params_default", "abc_setup", "abc_step", "abc_diagnostics", "abc_aux_elems",
-            "abc_export", "abc_device_bytes", "abc_last_error", "abc_destroy"]
+            "abc_export", "abc_path", "abc_device_bytes", "abc_last_error", "abc_destroy"]
 
 
 class AbcParams(ctypes.Structure):
@@ -64,6 +64,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.abc_aux_elems.restype = ctypes.c_size_t
     lib.abc_export.argtypes = [vp, ctypes.c_int, vp, ctypes.c_size_t]
     lib.abc_export.restype = ctypes.c_int
+    lib.abc_path.argtypes = [vp]
+    lib.abc_path.restype = ctypes.c_int
     lib.abc_device_bytes.argtypes = [vp]
     lib.abc_device_bytes.restype = ctypes.c_size_t
     lib.abc_last_error.argtypes = []

@@ -155,6 +155,7 @@ abc_status abc_setup(const abc_params* pp, abc_ctx** out) {
       return fail(ABC_EDEVICE, "hipMemcpy of face kernel failed");
     }
     L.face_ker = static_cast<const double2*>(kd);
+    L.fused_m0 = L.fused_b0 = make_double2(c->face.kernel[0].real(), c->face.kernel[0].imag());
     // Lyapunov-weighted block bound: zeroth order adds up to three faces'
     // operators to H; first order couples psi and f through blocks of norm
     // |H_{Gamma,Sigma}| (three faces at a corner) and B acts on f
@@ -251,6 +252,8 @@ abc_status abc_setup(const abc_params* pp, abc_ctx** out) {
 size_t abc_aux_elems(const abc_ctx* c) { return c ? c->aux_elems : 0; }
 
 size_t abc_device_bytes(const abc_ctx* c) { return c ? c->bytes : 0; }
+
+int abc_path(const abc_ctx* c) { return (c && c->use_fused) ? ABC_PATH_FUSED : ABC_PATH_STAGED; }
 
 abc_status abc_step(abc_ctx* c, void* psi, void* aux, const void* V, int n_steps, void* stream) {
   if (!c || !psi) return fail(ABC_EINVAL, "null context or psi");

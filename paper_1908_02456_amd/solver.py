@@ -65,6 +65,7 @@ class Solver:
         self._ctx = ctx
         self._lib = lib
         self.aux_elems = int(lib.abc_aux_elems(ctx))
+        self.use_fused = int(lib.abc_path(ctx)) == _lib.PATHS["fused"]
 
     # ------------------------------------------------------------------
     def close(self):

@@ -66,21 +66,23 @@ def _run_pair(name, shape, h, dt, R, order, steps, *, form="faces", s0=1.0, s1=1
 @pytest.mark.parametrize("R", [1, 2, 3])
 @pytest.mark.parametrize("order", ["dirichlet", "periodic"])
 def test_no_condition_parity(R, order):
-    r = _run_pair("plain", (13, 11, 17), 0.3, 0.01, R, order, 4)
+    r = _run_pair("plain", (13, 11, 17), 0.3, 0.01, R, order, 4, path="staged")
     assert r["err"] < TOL64, r["err"]
 
 
 @pytest.mark.parametrize("R,window,fejer", [(1, 0, True), (1, 2, True), (2, 1, True), (3, 0, True),
                                             (1, 3, False)])
 def test_zeroth_faces_parity(R, window, fejer):
-    r = _run_pair("zeroth-faces", (12, 10, 14), 0.25, 0.004, R, "zeroth", 5, s0=2.0, window=window, fejer=fejer)
+    r = _run_pair("zeroth-faces", (12, 10, 14), 0.25, 0.004, R, "zeroth", 5, s0=2.0, window=window, fejer=fejer,
+                  path="staged")
     assert r["err"] < TOL64, r["err"]
 
 
 @pytest.mark.parametrize("R,window,fejer", [(1, 0, True), (1, 3, True), (2, 2, True), (3, 1, True),
                                             (1, 9, False)])
 def test_first_faces_parity(R, window, fejer):
-    r = _run_pair("first-faces", (11, 10, 13), 0.25, 0.004, R, "first", 6, s1=1.5, window=window, fejer=fejer)
+    r = _run_pair("first-faces", (11, 10, 13), 0.25, 0.004, R, "first", 6, s1=1.5, window=window, fejer=fejer,
+                  path="staged")
     assert r["err"] < TOL64, r["err"]
     assert r["aux_err"] < TOL64, r["aux_err"]
 
@@ -138,6 +140,54 @@ def test_zero_steps_and_minimum_box():
     assert r["err"] == 0
     r = _run_pair("min-box", (3, 3, 3), 0.3, 0.004, 1, "first", 3, window=1)
     assert r["err"] < TOL64
+
+
+@pytest.mark.parametrize("order", ["dirichlet", "zeroth", "first"])
+@pytest.mark.parametrize("shape", [(21, 19, 37), (9, 17, 128), (16, 16, 16)])
+@pytest.mark.parametrize("steps", [5, 6])
+def test_fused_path_parity(order, shape, steps):
+    # several 8x8 (y, z) tiles with ragged tails; odd and even step counts
+    r = _run_pair("fused", shape, 0.25, 0.004, 1, order, steps, s0=1.5, s1=1.5, window=0, path="fused")
+    assert r["solver"].use_fused
+    assert r["err"] < TOL64, r["err"]
+    if order == "first":
+        assert r["aux_err"] < TOL64, r["aux_err"]
+
+
+@pytest.mark.parametrize("order", ["dirichlet", "first"])
+def test_fused_path_parity_fp32(order):
+    r = _run_pair("fused-c64", (19, 21, 45), 0.25, 0.004, 1, order, 7, s1=1.0, window=0, dtype="c64",
+                  path="fused")
+    assert r["solver"].use_fused
+    assert r["err"] < TOL32, r["err"]
+
+
+def test_full_size_headline_parity():
+    # the 128^3 single-orbital first-order workload in the launch
+    # configuration the benchmark times, two steps, every grid point compared
+    wl = W.well_packet(n=128)
+    r = _run_pair("headline-128", (128, 128, 128), wl.h, wl.dt, 1, "first", 2, s1=wl.s1, window=0,
+                  psi0=wl.psi0, V=wl.V, path="auto")
+    assert r["solver"].use_fused
+    assert r["err"] < TOL64, r["err"]
+    assert r["aux_err"] < TOL64, r["aux_err"]
+
+
+def test_staged_and_fused_agree():
+    Solver = _gpu()
+    shape = (24, 20, 40)
+    psi0 = W.random_complex(shape, seed=11)
+    V = W.random_potential(shape, seed=12)
+    outs = []
+    for path in ("staged", "fused"):
+        s = Solver(shape, 0.25, 0.004, order="first", s1=2.0, window=0, path=path)
+        psi = torch.from_numpy(psi0).cuda()
+        aux = s.new_aux()
+        s.step(psi, aux, torch.from_numpy(V).cuda(), 9)
+        outs.append((psi.cpu().numpy(), aux.cpu().numpy()))
+    scale = np.abs(outs[0][0]).max()
+    assert np.abs(outs[0][0] - outs[1][0]).max() < 1e-12 * scale
+    assert np.abs(outs[0][1] - outs[1][1]).max() < 1e-12 * np.abs(outs[0][1]).max()
 
 
 def test_setup_rejects_unstable_dt():
