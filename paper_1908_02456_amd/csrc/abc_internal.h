@@ -72,6 +72,7 @@ struct abc_launch {
   double2 a_loc[abc::kMaxR * abc::kMaxR];
   double2 q_loc[abc::kMaxR * abc::kMaxR];
   double2 fused_m0, fused_b0;  // window-0 face operator value (host copy)
+  int fused_stages;            // 4: one launch per step; 2: two launches
   // box form
   const double2* box_mat;
   const double2* box_q;       // Lyapunov weight (H_gs H_gs^T)^{-1}, n x n

@@ -1,41 +1,50 @@
-// Fused Taylor-4 step: all four stages of z_k = (dt/k) L z_{k-1} and the
-// accumulation psi' = z_0 + ... + z_4 (Sec. 4 Taylor propagator) in one
-// sweep, with the boundary terms of the face-form conditions (Sec. 3) when
-// the face operators are local (window 0).
+// Fused Taylor-4 step kernels (Sec. 4 Taylor propagator applied to the
+// dynamics of Sec. 3), for R = 1, local (window 0) face operators and boxes
+// of at most 128 columns.
 //
-// Layout of the sweep (R = 1):
-//   * a workgroup owns an output tile of all x (<= 128), 8 rows in y and 8
-//     planes in z; it loads 4-deep halos in y and z (one per stage);
-//   * one wavefront per y row (16 rows = 8 output + 2 x 4 halo), each lane
-//     holding two consecutive x columns, so x needs no halo;
-//   * the workgroup marches z: when plane zi is loaded, stage k works on
-//     plane zi - k.  Each stage keeps the plane below and the centre plane of
-//     its input in registers (the plane above is the previous stage's fresh
-//     output) and publishes its centre plane in LDS for the x/y neighbours;
-//   * the first-order auxiliary recurrence g_k = (dt/k)(b g_{k-1} + a y_{k-1})
-//     is carried per face point along the same pipeline (z faces in
-//     registers, x and y faces in LDS slots);
-//   * tiles are mapped so that consecutive tiles share an XCD (and its L2),
-//     which keeps the halo re-reads on chip.
-// psi and the auxiliary slab are read from one buffer and written to another
-// (neighbouring tiles read halos that this tile overwrites).
+// The step U = sum_{k<=4} (dt L)^k / k! is evaluated in Horner form, the same
+// polynomial with a different rounding order:
+//   u3 = z0 + (dt/4) L z0,  u2 = z0 + (dt/3) L u3,  u1 = z0 + (dt/2) L u2,
+//   z' = z0 + dt L u1,       z0 = (psi, f).
+//
+// Sweep layout shared by both kernels:
+//   * a workgroup owns an output tile of all x, TY rows in y and TZ planes in
+//     z, and loads one halo row/plane per fused stage on each side;
+//   * one wavefront per y row, two consecutive x columns per lane, so x needs
+//     no halo; rows are published in LDS as [column parity][1 + lane] with a
+//     zero guard cell at each end (conflict-free, branch-free x neighbours);
+//   * the workgroup marches z: when plane zi is loaded, stage k works on plane
+//     zi - k with its input's below/centre planes in registers, the plane above
+//     being the previous stage's fresh output; the initial state needed by the
+//     Horner stages rides along in a register delay line;
+//   * tiles are numbered so that consecutive tiles share an XCD and its L2.
+// fused_step_kernel runs all four stages (one launch per step);
+// fused2_kernel runs half of them (two launches per step, two-deep halos,
+// half the register state).  First-order boundary terms are added to each
+// half by fo_boundary_kernel.  The state is read from one buffer and written
+// to another, since neighbouring tiles read halos that a tile overwrites.
 #include <hip/hip_runtime.h>
+
+#include <cstdlib>
+#include <type_traits>
+#include <utility>
 
 #include "fused.h"
 
 namespace {
 
-constexpr int kTY = 8;
-constexpr int kTZ = 8;
-constexpr int kHalo = 4;
-constexpr int kRows = kTY + 2 * kHalo;  // 16 wavefronts
+constexpr int kHalo = 4;  // four-stage kernel: one plane/row per stage
 constexpr int kCols = 128;
-constexpr int kThreads = 64 * kRows;
-constexpr int kIters = kTZ + 2 * kHalo;
 
 template <typename T> struct cpx;
 template <> struct cpx<double> { using t = double2; };
 template <> struct cpx<float> { using t = float2; };
+
+// Four-stage output tile per precision (256 tiles at 128^3 in both cases).
+// FP32: 8 x 8, 16 waves; FP64: 4 x 16, 12 waves (register budget).
+template <typename T> struct Tile;
+template <> struct Tile<float> { static constexpr int TY = 8, TZ = 8; };
+template <> struct Tile<double> { static constexpr int TY = 4, TZ = 16; };
 
 struct FusedArgs {
   int nx, ny, nz;
@@ -55,105 +64,113 @@ __device__ __forceinline__ C czero() {
   return z;
 }
 
+// Workgroup barrier ordering LDS only.  __syncthreads() also waits for every
+// outstanding global load (vmcnt(0)), which would drain the next plane's
+// prefetch at each barrier; here only LDS traffic (lgkmcnt) is waited for.
+// The empty asm statements keep the compiler from moving memory accesses
+// across the barrier; loads still in flight are waited for where their
+// registers are first used.
+__device__ __forceinline__ void sync_lds() {
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_waitcnt(0xC07F);  // gfx9 encoding: vmcnt 63, expcnt 7, lgkmcnt 0
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+}
+
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
-// ORDER: 0 = no condition (zero outside), 2 = zeroth order, 3 = first order.
-//
-// The four stages are evaluated in Horner form, which is the same
-// polynomial sum_{k<=4} (dt L)^k / k! with a different rounding order:
-//   u3 = z0 + (dt/4) L z0,  u2 = z0 + (dt/3) L u3,  u1 = z0 + (dt/2) L u2,
-//   z' = z0 + dt L u1,       z0 = (psi, f).
-// Nothing has to be accumulated across planes: stage k only needs the
-// initial state at its own plane (registers for stages 1-2, a cached
-// re-read for stages 3-4).
+// ORDER: 0 = no boundary term (zero outside the box), 2 = zeroth order.
 template <typename T, int ORDER>
-__global__ void __launch_bounds__(kThreads) fused_step_kernel(
+__global__ void __launch_bounds__(64 * (Tile<T>::TY + 2 * kHalo)) fused_step_kernel(
     const typename cpx<T>::t* __restrict__ pin, typename cpx<T>::t* __restrict__ pout, const T* __restrict__ V,
-    const double2* __restrict__ fin, double2* __restrict__ fout, FusedArgs a) {
+    FusedArgs a) {
   using C = typename cpx<T>::t;
-  __shared__ C plane[4][kRows][kCols];
-  constexpr int GX = ORDER == 3 ? kRows : 1;
-  constexpr int GY = ORDER == 3 ? kCols : 1;
-  __shared__ double2 gx[2][3][2][GX];  // x-face aux stages [side][stage-1][parity][row]
-  __shared__ double2 gy[2][3][2][GY];  // y-face aux stages [side][stage-1][parity][x]
+  constexpr int TY = Tile<T>::TY, TZ = Tile<T>::TZ;
+  constexpr int ROWS = TY + 2 * kHalo;
+  constexpr int NT = 64 * ROWS;
+  constexpr int ITERS = TZ + 2 * kHalo;
+  __shared__ C plane[4][ROWS][2][66];
 
   const int lane = threadIdx.x & 63;
   const int r = threadIdx.x >> 6;
   int tile = blockIdx.x;
   if (a.tiles_per_xcd) tile = (blockIdx.x & 7) * a.tiles_per_xcd + (blockIdx.x >> 3);
   const int ty = tile % a.nty, tz = tile / a.nty;
-  const int y0 = ty * kTY, z0 = tz * kTZ;
-  const int y = y0 - kHalo + r;
-  const bool row_in = y >= 0 && y < a.ny;
+  const int y0 = ty * TY, z0 = tz * TZ;
   const int nx = a.nx, ny = a.ny, nz = a.nz;
   const int sz = nx * ny;
+  const int y = y0 - kHalo + r;
+  const bool row_in = y >= 0 && y < ny;
   const int ybase = y * nx;
-  const bool own_row = r >= kHalo && r < kHalo + kTY && row_in;
+  const bool own_row = r >= kHalo && r < kHalo + TY && row_in;
 
-  for (int i = threadIdx.x; i < 4 * kRows * kCols; i += kThreads) (&plane[0][0][0])[i] = czero<C>();
+  for (int i = threadIdx.x; i < 4 * ROWS * 2 * 66; i += NT) (&plane[0][0][0][0])[i] = czero<C>();
   __syncthreads();
 
-  // Yc[j] / Yb[j]: stage-j output at the centre / below plane of stage j+1
-  C Yc[4][2], Yb[4][2];
+  C Yc[4][2], Yb[4][2];  // stage-j output at the centre / below plane of stage j+1
+  T Vd[4][2];            // V at planes zi-1 .. zi-4
+  C Pz[2][2];            // psi at planes zi-3, zi-4
+  C pf[2];               // psi and V at plane zi+1, fetched an iteration ahead
+  T pv[2];
 #pragma unroll
-  for (int j = 0; j < 4; ++j)
+  for (int c = 0; c < 2; ++c) {
 #pragma unroll
-    for (int c = 0; c < 2; ++c) Yc[j][c] = Yb[j][c] = czero<C>();
-  double2 gz[2] = {make_double2(0, 0), make_double2(0, 0)};
-
+    for (int j = 0; j < 4; ++j) {
+      Yc[j][c] = Yb[j][c] = czero<C>();
+      Vd[j][c] = T(0);
+    }
+    Pz[0][c] = Pz[1][c] = czero<C>();
+  }
   const T diag = T(a.diag), off = T(a.off);
 
-  for (int it = 0; it < kIters; ++it) {
-    const int zi = z0 - kHalo + it;
-    C nw[5][2];
-    const bool load_ok = row_in && zi >= 0 && zi < nz;
+  auto fetch = [&](int zz) {
+    const bool ok = row_in && zz >= 0 && zz < nz;
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
       const int x = 2 * lane + c;
-      nw[0][c] = (load_ok && x < nx) ? pin[zi * sz + ybase + x] : czero<C>();
+      const int idx = ok ? zz * sz + ybase + min(x, nx - 1) : 0;  // always a valid address
+      const C pv_ = pin[idx];
+      const T vv = a.has_V ? V[idx] : T(0);
+      pf[c] = (ok && x < nx) ? pv_ : czero<C>();
+      pv[c] = (ok && x < nx) ? vv : T(0);
     }
+  };
+  fetch(z0 - kHalo);
+
+  for (int it = 0; it < ITERS; ++it) {
+    const int zi = z0 - kHalo + it;
+    C prev[2];    // previous stage's output at the plane above (stage 0: psi(zi))
+    T vcur[2];
+    C psi_m2[2];  // psi at plane zi - 2
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      prev[c] = pf[c];
+      vcur[c] = pv[c];
+      psi_m2[c] = Yb[0][c];
+    }
+    if (it + 1 < ITERS) fetch(zi + 1);
 #pragma unroll
     for (int k = 1; k <= 4; ++k) {
       const int zk = zi - k;
-      const bool active = r >= k && r < kRows - k && it >= 2 * k && row_in && zk >= 0 && zk < nz;
-      if (!active) {
-        nw[k][0] = nw[k][1] = czero<C>();
-        continue;
-      }
       const T cf = T(a.coef[5 - k]);
+      const bool active = r >= k && r < ROWS - k && it >= 2 * k && row_in && zk >= 0 && zk < nz;
+      C out[2];
 #pragma unroll
       for (int c = 0; c < 2; ++c) {
         const int x = 2 * lane + c;
-        if (x >= nx) {
-          nw[k][c] = czero<C>();
-          continue;
-        }
-        const C cen = Yc[k - 1][c], bel = Yb[k - 1][c], abv = nw[k - 1][c];
-        const C ym = plane[k - 1][r - 1][x];
-        const C yp = plane[k - 1][r + 1][x];
-        C xm, xp;
-        if (c == 0) {
-          xm = x > 0 ? plane[k - 1][r][x - 1] : czero<C>();
-          xp = Yc[k - 1][1];
-        } else {
-          xm = Yc[k - 1][0];
-          xp = (x + 1 < kCols) ? plane[k - 1][r][x + 1] : czero<C>();
-        }
-        // initial state at this plane: centre of stage 1, below of stage 1,
-        // re-read for stages 3 and 4
-        C z0v;
-        if (k == 1) z0v = Yc[0][c];
-        else if (k == 2) z0v = Yb[0][c];
-        else z0v = pin[zk * sz + ybase + x];
-        T hr = diag * cen.x + off * (bel.x + abv.x + ym.x + yp.x + xm.x + xp.x);
-        T hi = diag * cen.y + off * (bel.y + abv.y + ym.y + yp.y + xm.y + xp.y);
-        if (a.has_V) {
-          const T v = V[zk * sz + ybase + x];
-          hr += v * cen.x;
-          hi += v * cen.y;
-        }
+        out[c] = czero<C>();
+        if (!active) continue;
+        const C cen = Yc[k - 1][c], bel = Yb[k - 1][c], abv = prev[c];
+        const C ym = plane[k - 1][r - 1][c][lane + 1];
+        const C yp = plane[k - 1][r + 1][c][lane + 1];
+        const C xm = c == 0 ? plane[k - 1][r][1][lane] : Yc[k - 1][0];
+        const C xp = c == 0 ? Yc[k - 1][1] : plane[k - 1][r][0][lane + 2];
+        const C z0v = k == 1 ? Yc[0][c] : (k == 2 ? psi_m2[c] : Pz[k - 3][c]);
+        const T v = Vd[k - 1][c];
+        T hr = diag * cen.x + off * (bel.x + abv.x + ym.x + yp.x + xm.x + xp.x) + v * cen.x;
+        T hi = diag * cen.y + off * (bel.y + abv.y + ym.y + yp.y + xm.y + xp.y) + v * cen.y;
         if (ORDER == 2) {
           const int nf = (x == 0) + (x == nx - 1) + (y == 0) + (y == ny - 1) + (zk == 0) + (zk == nz - 1);
           if (nf) {
@@ -162,51 +179,16 @@ __global__ void __launch_bounds__(kThreads) fused_step_kernel(
             hi += T(nf * s.y);
           }
         }
-        if (ORDER == 3) {
-          // aux stage v_k = f + c_k (b v_{k-1} + a u_{k-1}) per face point;
-          // the psi stage sees the sum of v_{k-1} over the faces at the point
-          const bool own = own_row && zk >= z0 && zk < z0 + kTZ && k == 4;
-          const double2 yc = make_double2((double)cen.x, (double)cen.y);
-          const double cfd = a.coef[5 - k];
-          double sr = 0, si = 0;
-          auto aux_stage = [&](int idx, double2 vp) {
-            const double2 f0 = fin[idx];
-            const double2 t1 = cmul(a.b0, vp), t2 = cmul(a.a0, yc);
-            sr += vp.x;
-            si += vp.y;
-            return make_double2(f0.x + cfd * (t1.x + t2.x), f0.y + cfd * (t1.y + t2.y));
-          };
-          if (x == 0 || x == nx - 1) {  // x faces: (t_slow, t_fast) = (z, y)
-            const int side = x == 0 ? 0 : 1;
-            const int idx = a.face_off[side] + zk * ny + y;
-            const double2 vp = k == 1 ? fin[idx] : gx[side][k - 2][(it - 1) & 1][r];
-            const double2 vk = aux_stage(idx, vp);
-            if (k <= 3) gx[side][k - 1][it & 1][r] = vk;
-            if (own) fout[idx] = vk;
-          }
-          if (y == 0 || y == ny - 1) {  // y faces: (z, x)
-            const int side = y == 0 ? 0 : 1;
-            const int idx = a.face_off[2 + side] + zk * nx + x;
-            const double2 vp = k == 1 ? fin[idx] : gy[side][k - 2][(it - 1) & 1][x];
-            const double2 vk = aux_stage(idx, vp);
-            if (k <= 3) gy[side][k - 1][it & 1][x] = vk;
-            if (own) fout[idx] = vk;
-          }
-          if (zk == 0 || zk == nz - 1) {  // z faces: (y, x); one stage per iteration
-            const int side = zk == 0 ? 0 : 1;
-            const int idx = a.face_off[4 + side] + ybase + x;
-            const double2 vp = k == 1 ? fin[idx] : gz[c];
-            const double2 vk = aux_stage(idx, vp);
-            gz[c] = vk;
-            if (own) fout[idx] = vk;
-          }
-          hr += T(sr);
-          hi += T(si);
-        }
-        C o;
-        o.x = z0v.x + cf * hi;
-        o.y = z0v.y - cf * hr;
-        nw[k][c] = o;
+        // columns past the box edge stay zero (they are x neighbours)
+        out[c].x = x < nx ? z0v.x + cf * hi : T(0);
+        out[c].y = x < nx ? z0v.y - cf * hr : T(0);
+      }
+      // stage k is the last reader of its input window: slide it now
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        Yb[k - 1][c] = Yc[k - 1][c];
+        Yc[k - 1][c] = prev[c];
+        prev[c] = out[c];
       }
     }
     // stage 4 output is the new state at plane zi - 4
@@ -215,31 +197,287 @@ __global__ void __launch_bounds__(kThreads) fused_step_kernel(
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
       const int x = 2 * lane + c;
-      if (own_out && x < nx) pout[z4 * sz + ybase + x] = nw[4][c];
+      if (own_out && x < nx) pout[z4 * sz + ybase + x] = prev[c];
+      Pz[1][c] = Pz[0][c];
+      Pz[0][c] = psi_m2[c];
+      Vd[3][c] = Vd[2][c];
+      Vd[2][c] = Vd[1][c];
+      Vd[1][c] = Vd[0][c];
+      Vd[0][c] = vcur[c];
     }
+    sync_lds();
 #pragma unroll
     for (int j = 0; j < 4; ++j)
 #pragma unroll
-      for (int c = 0; c < 2; ++c) {
-        Yb[j][c] = Yc[j][c];
-        Yc[j][c] = nw[j][c];
-      }
-    __syncthreads();
-#pragma unroll
-    for (int j = 0; j < 4; ++j)
-#pragma unroll
-      for (int c = 0; c < 2; ++c) plane[j][r][2 * lane + c] = Yc[j][c];
-    __syncthreads();
+      for (int c = 0; c < 2; ++c) plane[j][r][c][lane + 1] = Yc[j][c];
+    sync_lds();
   }
 }
 
-FusedArgs make_args(const abc_launch& L) {
+// Half of the Horner step per launch:
+//   half A:  u3 = psi + (dt/4) L psi,  u2 = psi + (dt/3) L u3   -> u2
+//   half B:  u1 = psi + (dt/2) L u2,   psi' = psi + dt L u1      -> psi'
+// w is the field the first stage differentiates (psi in A, u2 in B), base the
+// Horner base psi (the same buffer in A).  Tiles 8 x 8, 12 waves.
+constexpr int kTY2 = 8, kTZ2 = 8, kHalo2 = 2;
+
+template <typename T, int ORDER, bool SAME_BASE>
+__global__ void __launch_bounds__(64 * (kTY2 + 2 * kHalo2)) fused2_kernel(
+    const typename cpx<T>::t* __restrict__ w_in, const typename cpx<T>::t* __restrict__ base_in,
+    typename cpx<T>::t* __restrict__ out, const T* __restrict__ V, FusedArgs a, double cA, double cB) {
+  using C = typename cpx<T>::t;
+  constexpr int TY = kTY2, TZ = kTZ2, H = kHalo2;
+  constexpr int ROWS = TY + 2 * H;
+  constexpr int NT = 64 * ROWS;
+  constexpr int ITERS = TZ + 2 * H;
+  __shared__ C plane[2][ROWS][2][66];
+
+  const int lane = threadIdx.x & 63;
+  const int r = threadIdx.x >> 6;
+  int tile = blockIdx.x;
+  if (a.tiles_per_xcd) tile = (blockIdx.x & 7) * a.tiles_per_xcd + (blockIdx.x >> 3);
+  const int ty = tile % a.nty, tz = tile / a.nty;
+  const int y0 = ty * TY, z0 = tz * TZ;
+  const int nx = a.nx, ny = a.ny, nz = a.nz;
+  const int sz = nx * ny;
+  const int y = y0 - H + r;
+  const bool row_in = y >= 0 && y < ny;
+  const int ybase = y * nx;
+  const bool own_row = r >= H && r < H + TY && row_in;
+
+  for (int i = threadIdx.x; i < 2 * ROWS * 2 * 66; i += NT) (&plane[0][0][0][0])[i] = czero<C>();
+  __syncthreads();
+
+  C Yc[2][2], Yb[2][2];  // stage inputs: centre / below (j = 0: w, j = 1: stage-1 output)
+  C Bd[2][2];            // base at planes zi-1, zi-2 (separate base only)
+  T Vd[2][2];            // V at planes zi-1, zi-2
+  C pf[2], pb[2];        // fields at plane zi+1, fetched an iteration ahead
+  T pv[2];
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      Yc[j][c] = Yb[j][c] = Bd[j][c] = czero<C>();
+      Vd[j][c] = T(0);
+    }
+    pb[c] = czero<C>();
+  }
+  const T diag = T(a.diag), off = T(a.off);
+
+  auto fetch = [&](int zz) {
+    const bool ok = row_in && zz >= 0 && zz < nz;
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      const int x = 2 * lane + c;
+      const bool in = ok && x < nx;
+      const int idx = ok ? zz * sz + ybase + min(x, nx - 1) : 0;  // always a valid address
+      const C wv = w_in[idx];
+      pf[c] = in ? wv : czero<C>();
+      if (!SAME_BASE) {
+        const C bv = base_in[idx];
+        pb[c] = in ? bv : czero<C>();
+      }
+      const T vv = a.has_V ? V[idx] : T(0);
+      pv[c] = in ? vv : T(0);
+    }
+  };
+  fetch(z0 - H);
+
+  for (int it = 0; it < ITERS; ++it) {
+    const int zi = z0 - H + it;
+    C prev[2];
+    T vcur[2];
+    C bcur[2], wm2[2];  // base at plane zi; w at plane zi - 2 (before the slide)
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      prev[c] = pf[c];
+      vcur[c] = pv[c];
+      bcur[c] = SAME_BASE ? pf[c] : pb[c];
+      wm2[c] = Yb[0][c];
+    }
+    if (it + 1 < ITERS) fetch(zi + 1);
+#pragma unroll
+    for (int k = 1; k <= 2; ++k) {
+      const int zk = zi - k;
+      const T cf = T(k == 1 ? cA : cB);
+      const bool active = r >= k && r < ROWS - k && it >= 2 * k && row_in && zk >= 0 && zk < nz;
+      C o[2];
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        const int x = 2 * lane + c;
+        o[c] = czero<C>();
+        if (!active) continue;
+        const C cen = Yc[k - 1][c], bel = Yb[k - 1][c], abv = prev[c];
+        const C ym = plane[k - 1][r - 1][c][lane + 1];
+        const C yp = plane[k - 1][r + 1][c][lane + 1];
+        const C xm = c == 0 ? plane[k - 1][r][1][lane] : Yc[k - 1][0];
+        const C xp = c == 0 ? Yc[k - 1][1] : plane[k - 1][r][0][lane + 2];
+        C b0;
+        if (SAME_BASE) b0 = k == 1 ? Yc[0][c] : wm2[c];
+        else b0 = Bd[k - 1][c];
+        const T v = Vd[k - 1][c];
+        T hr = diag * cen.x + off * (bel.x + abv.x + ym.x + yp.x + xm.x + xp.x) + v * cen.x;
+        T hi = diag * cen.y + off * (bel.y + abv.y + ym.y + yp.y + xm.y + xp.y) + v * cen.y;
+        if (ORDER == 2) {
+          const int nf = (x == 0) + (x == nx - 1) + (y == 0) + (y == ny - 1) + (zk == 0) + (zk == nz - 1);
+          if (nf) {
+            const double2 sv = cmul(a.m0, make_double2((double)cen.x, (double)cen.y));
+            hr += T(nf * sv.x);
+            hi += T(nf * sv.y);
+          }
+        }
+        o[c].x = x < nx ? b0.x + cf * hi : T(0);
+        o[c].y = x < nx ? b0.y - cf * hr : T(0);
+      }
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        Yb[k - 1][c] = Yc[k - 1][c];
+        Yc[k - 1][c] = prev[c];
+        prev[c] = o[c];
+      }
+    }
+    const int z2 = zi - 2;
+    const bool own_out = own_row && it >= 2 * H && z2 < nz;
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      const int x = 2 * lane + c;
+      if (own_out && x < nx) out[z2 * sz + ybase + x] = prev[c];
+      Vd[1][c] = Vd[0][c];
+      Vd[0][c] = vcur[c];
+      if (!SAME_BASE) {
+        Bd[1][c] = Bd[0][c];
+        Bd[0][c] = bcur[c];
+      }
+    }
+    sync_lds();
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int c = 0; c < 2; ++c) plane[j][r][c][lane + 1] = Yc[j][c];
+    sync_lds();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// First-order boundary terms of a two-stage half, added after the half ran
+// without them (the Dirichlet box, i.e. H = -(1/2) Delta_h + V with zero
+// outside).  The half is linear, and with local (window 0) face operators the
+// sources it sees are known up front:
+//   stage 1 adds -i cA sum_f av_f at face points, so the stage-1 output is
+//     s1 = s1_plain + D,  D = -i cA sum_f av_f   (zero off the faces);
+//   the auxiliary stage is v_f = fb_f + cA (b av_f + a w)  (w: stage-1 input);
+//   stage 2 adds -i cB (sum_f v_f) at face points and sees D through H, so
+//     out = out_plain - i cB (H D + sum_f v_f)   on points within one layer of
+//   a face; and the auxiliary output is fb_f + cB (b v_f + a s1) at faces.
+// One workgroup per (z, y) row: full rows on the two outer planes/rows of
+// each side, the four outer columns elsewhere.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(64) fo_boundary_kernel(
+    const typename cpx<T>::t* __restrict__ w, const typename cpx<T>::t* __restrict__ base,
+    typename cpx<T>::t* __restrict__ out, const T* __restrict__ V, const double2* __restrict__ av,
+    const double2* __restrict__ fb, double2* __restrict__ aux_out, FusedArgs a, double cA, double cB) {
+  const int nx = a.nx, ny = a.ny, nz = a.nz;
+  const int z = blockIdx.x / ny, y = blockIdx.x - (blockIdx.x / ny) * ny;
+  const bool full = z <= 1 || z >= nz - 2 || y <= 1 || y >= ny - 2;
+  const int count = full ? nx : 4;
+  const int sz = nx * ny;
+  auto face_idx = [&](int f, int xx, int yy, int zz) {
+    switch (f) {
+      case 0: return a.face_off[0] + zz * ny + yy;
+      case 1: return a.face_off[1] + zz * ny + yy;
+      case 2: return a.face_off[2] + zz * nx + xx;
+      case 3: return a.face_off[3] + zz * nx + xx;
+      case 4: return a.face_off[4] + yy * nx + xx;
+      default: return a.face_off[5] + yy * nx + xx;
+    }
+  };
+  auto on_face = [&](int f, int xx, int yy, int zz) {
+    switch (f) {
+      case 0: return xx == 0;
+      case 1: return xx == nx - 1;
+      case 2: return yy == 0;
+      case 3: return yy == ny - 1;
+      case 4: return zz == 0;
+      default: return zz == nz - 1;
+    }
+  };
+  // D at a box point: -i cA sum over its faces of av
+  auto Dat = [&](int xx, int yy, int zz) {
+    double sr = 0, si = 0;
+    for (int f = 0; f < 6; ++f)
+      if (on_face(f, xx, yy, zz)) {
+        const double2 v = av[face_idx(f, xx, yy, zz)];
+        sr += v.x;
+        si += v.y;
+      }
+    return make_double2(cA * si, -cA * sr);
+  };
+  auto load = [&](const typename cpx<T>::t* p, int xx, int yy, int zz) {
+    const auto v = p[zz * sz + yy * nx + xx];
+    return make_double2((double)v.x, (double)v.y);
+  };
+  for (int t = threadIdx.x; t < count; t += blockDim.x) {
+    const int x = full ? t : (t < 2 ? t : nx - 4 + t);
+    const int p = z * sz + y * nx + x;
+    const double vq = a.has_V ? (double)V[p] : 0.0;
+    // H D at q
+    const double2 dq = Dat(x, y, z);
+    double hr = (a.diag + vq) * dq.x, hi = (a.diag + vq) * dq.y;
+    const int nb[6][3] = {{x - 1, y, z}, {x + 1, y, z}, {x, y - 1, z}, {x, y + 1, z}, {x, y, z - 1}, {x, y, z + 1}};
+    double2 wn_sum = make_double2(0, 0);
+    for (int m = 0; m < 6; ++m) {
+      const int xx = nb[m][0], yy = nb[m][1], zz = nb[m][2];
+      if (xx < 0 || xx >= nx || yy < 0 || yy >= ny || zz < 0 || zz >= nz) continue;
+      const double2 dn = Dat(xx, yy, zz);
+      hr += a.off * dn.x;
+      hi += a.off * dn.y;
+      const double2 wv = load(w, xx, yy, zz);
+      wn_sum.x += wv.x;
+      wn_sum.y += wv.y;
+    }
+    const double2 wq = load(w, x, y, z);
+    // face terms at q
+    double2 vs = make_double2(0, 0);
+    const bool face_q = x == 0 || x == nx - 1 || y == 0 || y == ny - 1 || z == 0 || z == nz - 1;
+    double2 s1 = make_double2(0, 0);
+    if (face_q) {
+      // stage-1 output at q: base + cA (-i)(H w) + D
+      const double hwr = (a.diag + vq) * wq.x + a.off * wn_sum.x;
+      const double hwi = (a.diag + vq) * wq.y + a.off * wn_sum.y;
+      const double2 bq = load(base, x, y, z);
+      s1 = make_double2(bq.x + cA * hwi + dq.x, bq.y - cA * hwr + dq.y);
+    }
+    const double2 aw = cmul(a.a0, wq), as1 = cmul(a.a0, s1);
+    for (int f = 0; f < 6; ++f) {
+      if (!on_face(f, x, y, z)) continue;
+      const int fi = face_idx(f, x, y, z);
+      const double2 f0 = fb[fi], v0 = av[fi];
+      const double2 bv = cmul(a.b0, v0);
+      const double2 vf = make_double2(f0.x + cA * (bv.x + aw.x), f0.y + cA * (bv.y + aw.y));
+      vs.x += vf.x;
+      vs.y += vf.y;
+      const double2 bvf = cmul(a.b0, vf);
+      aux_out[fi] = make_double2(f0.x + cB * (bvf.x + as1.x), f0.y + cB * (bvf.y + as1.y));
+    }
+    hr += vs.x;
+    hi += vs.y;
+    auto o = out[p];
+    o.x += T(cB * hi);
+    o.y -= T(cB * hr);
+    out[p] = o;
+  }
+}
+
+template <typename T>
+FusedArgs make_args(const abc_launch& L, bool two) {
   FusedArgs a{};
   a.nx = L.g.nx;
   a.ny = L.g.ny;
   a.nz = L.g.nz;
-  a.nty = (a.ny + kTY - 1) / kTY;
-  const int ntz = (a.nz + kTZ - 1) / kTZ;
+  const int TY = two ? kTY2 : Tile<T>::TY, TZ = two ? kTZ2 : Tile<T>::TZ;
+  a.nty = (a.ny + TY - 1) / TY;
+  const int ntz = (a.nz + TZ - 1) / TZ;
   a.ntiles = a.nty * ntz;
   a.tiles_per_xcd = (a.ntiles % 8 == 0) ? a.ntiles / 8 : 0;
   const double s = 1.0 / (2.0 * L.h * L.h);
@@ -264,18 +502,26 @@ bool fused_supported(const abc_params& p, std::string* why) {
   if ((p.order == ABC_ZEROTH || p.order == ABC_FIRST) && (p.form != ABC_FORM_FACES || p.window != 0))
     return no("local (window 0) face operators only");
   if (p.nx > kCols) return no("nx <= 128");
-  if (p.nz < 5 || p.ny < 3) return no("ny >= 3 and nz >= 5");
+  if (p.nz < 5 || p.ny < 4 || p.nx < 4) return no("nx, ny >= 4 and nz >= 5");
   if ((long long)p.nx * p.ny * p.nz >= (1LL << 31)) return no("grid below 2^31 points");
   return true;
 }
 
 abc_status fused_prepare(const abc_params& p, abc_launch& L, std::vector<void*>* allocs, size_t* bytes,
                          std::string& err) {
-  (void)p;
   (void)allocs;
   (void)bytes;
   (void)err;
-  (void)L;
+  // Stages per launch: the FP64 four-stage pipeline is register bound, so FP64
+  // runs two launches of two stages; first order always does (its boundary
+  // terms are added per half).  ABC_FUSED_STAGES (2 or 4) overrides the
+  // default for Dirichlet and zeroth order (tuning).
+  L.fused_stages = p.dtype == ABC_C128 ? 2 : 4;
+  if (const char* e = std::getenv("ABC_FUSED_STAGES")) {
+    const int v = std::atoi(e);
+    if (v == 2 || v == 4) L.fused_stages = v;
+  }
+  if (p.order == ABC_FIRST) L.fused_stages = 2;
   return ABC_OK;
 }
 
@@ -285,15 +531,18 @@ template <typename T>
 hipError_t step_t(const abc_launch& L, const abc_scratch& S, void* psi_v, double2* aux, const void* V_v, int n,
                   hipStream_t st) {
   using C = typename cpx<T>::t;
-  FusedArgs a = make_args(L);
+  const bool two = L.fused_stages == 2;
+  FusedArgs a = make_args<T>(L, two);
   a.m0 = L.fused_m0;
   a.b0 = L.fused_b0;
   a.a0 = L.a_loc[0];
   a.has_V = V_v != nullptr;
   C* user = static_cast<C*>(psi_v);
   C* scr = static_cast<C*>(S.y[0]);
+  C* mid = static_cast<C*>(S.y[1]);
   double2* fuser = aux;
   double2* fscr = S.facc;
+  double2* vmid = S.g[0];
   const bool first = L.order == ABC_FIRST;
   const size_t pbytes = (size_t)L.g.npts * sizeof(C);
   const size_t fbytes = (size_t)L.g.face_off[6] * sizeof(double2);
@@ -315,17 +564,26 @@ hipError_t step_t(const abc_launch& L, const abc_scratch& S, void* psi_v, double
     fdst = fuser;
   }
   const T* V = static_cast<const T*>(V_v);
+  const int nthreads = 64 * (Tile<T>::TY + 2 * kHalo);
+  const int nthreads2 = 64 * (kTY2 + 2 * kHalo2);
+  const unsigned rows = (unsigned)(L.g.ny * L.g.nz);
+  const double dt = L.dt;
   for (int s = 0; s < n; ++s) {
-    switch (L.order) {
-      case ABC_ZEROTH:
-        fused_step_kernel<T, 2><<<a.ntiles, kThreads, 0, st>>>(src, dst, V, nullptr, nullptr, a);
-        break;
-      case ABC_FIRST:
-        fused_step_kernel<T, 3><<<a.ntiles, kThreads, 0, st>>>(src, dst, V, fsrc, fdst, a);
-        break;
-      default:
-        fused_step_kernel<T, 0><<<a.ntiles, kThreads, 0, st>>>(src, dst, V, nullptr, nullptr, a);
-        break;
+    if (two) {
+      if (L.order == ABC_ZEROTH) {
+        fused2_kernel<T, 2, true><<<a.ntiles, nthreads2, 0, st>>>(src, src, mid, V, a, dt / 4, dt / 3);
+        fused2_kernel<T, 2, false><<<a.ntiles, nthreads2, 0, st>>>(mid, src, dst, V, a, dt / 2, dt);
+      } else {
+        fused2_kernel<T, 0, true><<<a.ntiles, nthreads2, 0, st>>>(src, src, mid, V, a, dt / 4, dt / 3);
+        if (first) fo_boundary_kernel<T><<<rows, 64, 0, st>>>(src, src, mid, V, fsrc, fsrc, vmid, a, dt / 4, dt / 3);
+        fused2_kernel<T, 0, false><<<a.ntiles, nthreads2, 0, st>>>(mid, src, dst, V, a, dt / 2, dt);
+        if (first) fo_boundary_kernel<T><<<rows, 64, 0, st>>>(mid, src, dst, V, vmid, fsrc, fdst, a, dt / 2, dt);
+      }
+    } else {
+      if (L.order == ABC_ZEROTH)
+        fused_step_kernel<T, 2><<<a.ntiles, nthreads, 0, st>>>(src, dst, V, a);
+      else
+        fused_step_kernel<T, 0><<<a.ntiles, nthreads, 0, st>>>(src, dst, V, a);
     }
     std::swap(src, dst);
     std::swap(fsrc, fdst);
