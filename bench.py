@@ -72,6 +72,57 @@ def physics_error(Solver, torch, wl, dtype, window, path, steps_total):
             "norm_large_box_in_box": h3 * nr * nr, "norm_initial": h3 * float(np.sum(np.abs(wl.psi0) ** 2))}
 
 
+def shell_counts(n, R):
+    """Points within one layer of a face (depth <= 1) and face-slab entries of a cube of side n."""
+    inner = max(n - 4, 0) ** 3
+    return n ** 3 - inner, 6 * R * n * n
+
+
+def alg_bytes(label, n, R, csz, rsz):
+    """Algorithmic bytes of one launch of the step at n^3 (what the launch must
+    read and write once: state csz, potential rsz, FP64 face aux 16 B)."""
+    npts = n ** 3
+    shell, faces = shell_counts(n, R)
+    if label in ("fused_step", "fused2_half_a"):
+        return npts * (2 * csz + rsz)               # read psi, V; write result
+    if label == "fused2_half_b":
+        return npts * (3 * csz + rsz)               # read u2, psi, V; write psi'
+    if label == "fo_boundary_a":                    # out r/w + w on the shell; V, aux in/out on faces
+        return shell * 3 * csz + faces * (rsz + 32)
+    if label == "fo_boundary_b":                    # as A plus base and the separate aux base
+        return shell * 3 * csz + faces * (rsz + csz + 48)
+    if label.startswith("stage_"):                  # y in, acc, psi/base, V, y out
+        return npts * (4 * csz + rsz)
+    if label.startswith("boundary_"):
+        return faces * (16 * 3 + csz)
+    return None
+
+
+def measured_traffic(label, args):
+    """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
+    summary, if it was taken on this launch, workload and the current kernel
+    source; None otherwise."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic_%s_%d_%s.txt" % (label, args.n, args.dtype))
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line:
+                k, v = line.split(":", 1)
+                fields[k.strip()] = v.strip()
+    src = os.path.join(ROOT, "paper_1908_02456_amd", "csrc", fields.get("source", "fused.hip"))
+    with open(src, "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()
+    if fields.get("source_sha256") != sha:
+        return None
+    try:
+        return float(fields["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def cpu_baseline(wl, window, budget_s=15.0):
     """FP64 oracle (NumPy, single-threaded elementwise) on the same workload,
     for as many whole steps as fit in about budget_s seconds."""
@@ -113,6 +164,8 @@ def main():
     ap.add_argument("--path", default="auto", choices=["auto", "staged", "fused"])
     ap.add_argument("--no-physics", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-gib", type=float, default=0.0,
+                    help="also run one plain device copy of this size (calibrates rocprofv3 byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (see DESIGN.md for how the "
@@ -149,19 +202,29 @@ def main():
     value = npts * args.steps / (ms / 1e3)
     log("timed %d steps: %.3f ms/step, %.3e GPUPS" % (args.steps, ms_step, value))
 
-    # algorithmic bytes per grid-point update: psi read + write, V read,
-    # plus the FP64 auxiliary slab (read + write) spread over the volume
+    # per-launch durations (HIP events around every launch, same stream), then
+    # the roofline of the dominant launch from its algorithmic bytes
+    per_launch = s.step_timed(psi, aux, V, args.steps, stream=stream)
+    torch.cuda.synchronize()
     csz = 16 if args.dtype == "c128" else 8
     rsz = 8 if args.dtype == "c128" else 4
-    aux_bytes = 6 * wl.radius * wl.n * wl.n * 32
-    step_bytes = npts * (2 * csz + rsz) + aux_bytes
-    fused = s.use_fused if hasattr(s, "use_fused") else None
-    launches_per_step = 1
-    kernel = "fused Taylor-4 step" if fused else "whole staged step (4 stencil + 4 boundary launches)"
-    achieved = step_bytes / (ms_step / 1e3) / 1e9 / launches_per_step
+    table = []
+    for label, lms in per_launch:
+        b = alg_bytes(label, wl.n, wl.radius, csz, rsz)
+        table.append({"launch": label, "ms": lms, "alg_bytes": b,
+                      "GB/s": (b / (lms / 1e3) / 1e9) if (b and lms > 0) else None})
+    dom = max(table, key=lambda r: r["ms"])
+    log("launches per step: " + ", ".join("%s %.2f us" % (r["launch"], r["ms"] * 1e3) for r in table))
+    achieved = dom["GB/s"]
     roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": kernel,
-            "alg_bytes_per_launch": step_bytes}
+            "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
+            "traffic": measured_traffic(dom["launch"], args), "kernel": dom["launch"],
+            "alg_bytes_per_launch": dom["alg_bytes"], "avg_launch_ms": dom["ms"],
+            "launches": table}
+    # the method's own bytes per update (state in/out, V, FP64 face aux in/out)
+    step_bytes = npts * (2 * csz + rsz) + 6 * wl.radius * wl.n * wl.n * 32
+    roof["step_alg_bytes"] = step_bytes
+    roof["step_frac"] = step_bytes / (ms_step / 1e3) / 1e9 / HBM_PEAK_GBS
 
     out = {"metric": "grid-point-updates/s incl. ABC (% HBM roofline); err vs FP64 large-box oracle",
            "value": value, "unit": "grid-point-updates/s", "n_gpus": 1, "steps": args.steps,
@@ -173,6 +236,15 @@ def main():
                                   % (wl.n, wl.h, wl.dt, wl.s1, args.window, args.dtype),
                       "grid": [wl.n] * 3, "radius": wl.radius, "path": args.path},
            "roofline": roof}
+    if args.copy_gib > 0:
+        nb = int(args.copy_gib * (1 << 30)) // 16 * 16
+        src_t = torch.ones(nb // 8, dtype=torch.float64, device="cuda")
+        dst_t = torch.empty_like(src_t)
+        torch.cuda.synchronize()
+        dst_t.copy_(src_t)
+        torch.cuda.synchronize()
+        out["copy_calibration_bytes"] = 2 * nb
+        del src_t, dst_t
     if not args.no_physics:
         log("physics run: %d steps vs %d^3 zero-boundary box" % (wl.steps, 2 * wl.n))
         out["physics"] = physics_error(Solver, torch, wl, args.dtype, args.window, args.path, wl.steps)

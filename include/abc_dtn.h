@@ -125,6 +125,24 @@ abc_status abc_setup(const abc_params* p, abc_ctx** out);
 abc_status abc_step(abc_ctx* ctx, void* psi, void* aux, const void* V,
                     int n_steps, void* stream);
 
+/* Measurement run: advances the state by n_steps (>= 1) exactly as abc_step
+ * does, but issues every kernel launch through hipExtLaunchKernel with a
+ * start/stop HIP event pair that brackets that kernel's execution, then
+ * waits for the stream.  *launches receives the number k of kernel launches
+ * per step; ms[j], for j < min(cap, k), the mean over the steps of the
+ * duration in milliseconds of the j-th launch of a step.  abc_launch_label
+ * names the launches.  Synchronises with the host; creates and destroys
+ * 2 k n_steps events.  ABC_EINVAL on null arguments or n_steps < 1,
+ * ABC_EDEVICE if a launch or an event call fails. */
+abc_status abc_step_timed(abc_ctx* ctx, void* psi, void* aux, const void* V,
+                          int n_steps, void* stream, double* ms, int cap,
+                          int* launches);
+
+/* Name of the j-th kernel launch of a step as timed by the last
+ * abc_step_timed on ctx (owned by ctx, valid until the next such call or
+ * abc_destroy); NULL if j is out of range or no timed call was made. */
+const char* abc_launch_label(const abc_ctx* ctx, int j);
+
 /* FP64 diagnostics of a state, written to device memory out (3*batch + 1
  * doubles): [0, batch) norm h^3 sum |psi_j|^2; [batch, 2 batch) Lyapunov
  * functional h^3 (psi_j^* psi_j + f_j^* Q f_j) (Sec. 3, zeroth- and

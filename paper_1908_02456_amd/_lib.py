@@ -17,7 +17,8 @@ DTYPES = {"c128": 0, "c64": 1}
 PATHS = {"auto": 0, "staged": 1, "fused": 2}
 
 EXPORTED = ["abc_params_default", "abc_setup", "abc_step", "abc_diagnostics", "abc_aux_elems",
-            "abc_export", "abc_path", "abc_device_bytes", "abc_last_error", "abc_destroy"]
+            "abc_export", "abc_path", "abc_device_bytes", "abc_last_error", "abc_destroy",
+            "abc_step_timed", "abc_launch_label"]
 
 
 class AbcParams(ctypes.Structure):
@@ -58,6 +59,11 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.abc_setup.restype = ctypes.c_int
     lib.abc_step.argtypes = [vp, vp, vp, vp, ctypes.c_int, vp]
     lib.abc_step.restype = ctypes.c_int
+    lib.abc_step_timed.argtypes = [vp, vp, vp, vp, ctypes.c_int, vp, vp, ctypes.c_int,
+                                   ctypes.POINTER(ctypes.c_int)]
+    lib.abc_step_timed.restype = ctypes.c_int
+    lib.abc_launch_label.argtypes = [vp, ctypes.c_int]
+    lib.abc_launch_label.restype = ctypes.c_char_p
     lib.abc_diagnostics.argtypes = [vp, vp, vp, vp, vp, vp]
     lib.abc_diagnostics.restype = ctypes.c_int
     lib.abc_aux_elems.argtypes = [vp]

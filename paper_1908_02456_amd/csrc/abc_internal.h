@@ -1,6 +1,7 @@
 // Internal declarations shared by the host setup, the C ABI and the kernels.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <complex>
@@ -92,7 +93,53 @@ struct abc_scratch {
   int red_blocks;
 };
 
+// Per-launch timing for measurement runs: every kernel launch of a step is
+// issued through hipExtLaunchKernel with a fresh start/stop event pair, so
+// the pair brackets exactly that kernel's execution.  The first step's labels
+// name the launches of a step.
+struct abc_timer {
+  struct span { hipEvent_t start, stop; };
+  std::vector<span> ev;
+  std::vector<std::string> labels;
+  int steps_done = 0;
+  hipError_t err = hipSuccess;
+  bool pair(const char* label, hipEvent_t* start, hipEvent_t* stop) {
+    hipError_t r = hipEventCreate(start);
+    if (r == hipSuccess) {
+      r = hipEventCreate(stop);
+      if (r != hipSuccess) hipEventDestroy(*start);
+    }
+    if (r != hipSuccess) {
+      if (err == hipSuccess) err = r;
+      return false;
+    }
+    ev.push_back({*start, *stop});
+    if (steps_done == 0) labels.emplace_back(label);
+    return true;
+  }
+  void end_step() { ++steps_done; }
+  ~abc_timer() {
+    for (span& s : ev) {
+      hipEventDestroy(s.start);
+      hipEventDestroy(s.stop);
+    }
+  }
+};
+
+// Launches kernel k; with a timer, through hipExtLaunchKernel with a start and
+// stop event recorded around it.
+template <typename... P, typename... A>
+void abc_launch_kernel(abc_timer* tm, const char* label, void (*k)(P...), dim3 grid, dim3 block, hipStream_t st,
+                       A... args) {
+  if (!tm) {
+    k<<<grid, block, 0, st>>>(args...);
+    return;
+  }
+  hipEvent_t e0, e1;
+  if (tm->pair(label, &e0, &e1)) hipExtLaunchKernelGGL(k, grid, block, 0, st, e0, e1, 0, args...);
+}
+
 hipError_t launch_step_staged(const abc_launch& L, const abc_scratch& S, void* psi, double2* aux,
-                              const void* V, int n_steps, hipStream_t st);
+                              const void* V, int n_steps, hipStream_t st, abc_timer* tm = nullptr);
 hipError_t launch_diagnostics(const abc_launch& L, const abc_scratch& S, const void* psi,
                               const double2* aux, const void* V, double* out, hipStream_t st);

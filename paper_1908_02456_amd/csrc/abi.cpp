@@ -33,6 +33,7 @@ struct abc_ctx {
   int use_fused = 0;
   double2* box_mat = nullptr;
   double2* box_q = nullptr;
+  std::vector<std::string> launch_labels;  // launches of a step, from the last abc_step_timed
 };
 
 namespace {
@@ -268,6 +269,43 @@ abc_status abc_step(abc_ctx* c, void* psi, void* aux, const void* V, int n_steps
     e = launch_step_staged(c->L, c->S, psi, static_cast<double2*>(aux), V, n_steps, st);
   if (e != hipSuccess) return fail(ABC_EDEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
   return ABC_OK;
+}
+
+abc_status abc_step_timed(abc_ctx* c, void* psi, void* aux, const void* V, int n_steps, void* stream, double* ms,
+                          int cap, int* launches) {
+  if (!c || !psi || !launches || (cap > 0 && !ms)) return fail(ABC_EINVAL, "null argument");
+  if (n_steps < 1) return fail(ABC_EINVAL, "n_steps must be >= 1");
+  if (c->p.order == ABC_FIRST && !aux) return fail(ABC_EINVAL, "first order needs the aux buffer");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  abc_timer tm;
+  hipError_t e;
+  if (c->use_fused)
+    e = launch_step_fused(c->L, c->S, psi, static_cast<double2*>(aux), V, n_steps, st, &tm);
+  else
+    e = launch_step_staged(c->L, c->S, psi, static_cast<double2*>(aux), V, n_steps, st, &tm);
+  if (e == hipSuccess) e = tm.err;
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  const int k = (int)tm.labels.size();
+  const bool whole = e == hipSuccess && tm.ev.size() == (size_t)n_steps * k;
+  if (whole) {
+    for (int j = 0; j < cap && j < k; ++j) ms[j] = 0;
+    for (size_t i = 0; i < tm.ev.size() && e == hipSuccess; ++i) {
+      float t = 0;
+      e = hipEventElapsedTime(&t, tm.ev[i].start, tm.ev[i].stop);
+      const int j = (int)(i % k);
+      if (j < cap) ms[j] += (double)t / n_steps;
+    }
+  }
+  if (e != hipSuccess) return fail(ABC_EDEVICE, std::string("timed step: ") + hipGetErrorString(e));
+  if (!whole) return fail(ABC_EDEVICE, "timed step: event count mismatch");
+  c->launch_labels = tm.labels;
+  *launches = k;
+  return ABC_OK;
+}
+
+const char* abc_launch_label(const abc_ctx* c, int j) {
+  if (!c || j < 0 || j >= (int)c->launch_labels.size()) return nullptr;
+  return c->launch_labels[j].c_str();
 }
 
 abc_status abc_diagnostics(abc_ctx* c, const void* psi, const void* aux, const void* V, double* out, void* stream) {

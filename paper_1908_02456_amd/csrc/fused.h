@@ -15,4 +15,4 @@ abc_status fused_prepare(const abc_params& p, abc_launch& L, std::vector<void*>*
                          std::string& err);
 
 hipError_t launch_step_fused(const abc_launch& L, const abc_scratch& S, void* psi, double2* aux, const void* V,
-                             int n_steps, hipStream_t st);
+                             int n_steps, hipStream_t st, abc_timer* tm = nullptr);

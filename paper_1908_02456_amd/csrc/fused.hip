@@ -369,104 +369,117 @@ __global__ void __launch_bounds__(64 * (kTY2 + 2 * kHalo2)) fused2_kernel(
 //   stage 2 adds -i cB (sum_f v_f) at face points and sees D through H, so
 //     out = out_plain - i cB (H D + sum_f v_f)   on points within one layer of
 //   a face; and the auxiliary output is fb_f + cB (b v_f + a s1) at faces.
-// One workgroup per (z, y) row: full rows on the two outer planes/rows of
-// each side, the four outer columns elsewhere.
+// One thread per shell point (depth <= 1), enumerated so that consecutive
+// threads take consecutive x where they can: the two outer planes on each z
+// side, then the two outer rows on each y side, then the four outer columns.
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ int shell_points(int nx, int ny, int nz) {
+  return 4 * nx * ny + 4 * nx * (nz - 4) + 4 * (ny - 4) * (nz - 4);
+}
+
 template <typename T>
-__global__ void __launch_bounds__(64) fo_boundary_kernel(
+__global__ void __launch_bounds__(256) fo_boundary_kernel(
     const typename cpx<T>::t* __restrict__ w, const typename cpx<T>::t* __restrict__ base,
     typename cpx<T>::t* __restrict__ out, const T* __restrict__ V, const double2* __restrict__ av,
     const double2* __restrict__ fb, double2* __restrict__ aux_out, FusedArgs a, double cA, double cB) {
   const int nx = a.nx, ny = a.ny, nz = a.nz;
-  const int z = blockIdx.x / ny, y = blockIdx.x - (blockIdx.x / ny) * ny;
-  const bool full = z <= 1 || z >= nz - 2 || y <= 1 || y >= ny - 2;
-  const int count = full ? nx : 4;
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= shell_points(nx, ny, nz)) return;
+  int x, y, z;
+  const int nA = 4 * nx * ny, nB = 4 * nx * (nz - 4);
+  if (t < nA) {
+    const int k = t / (nx * ny), rem = t - k * nx * ny;
+    z = k < 2 ? k : nz - 4 + k;
+    y = rem / nx;
+    x = rem - y * nx;
+  } else if (t < nA + nB) {
+    t -= nA;
+    const int row = t / nx, k = row & 3;
+    x = t - row * nx;
+    z = 2 + (row >> 2);
+    y = k < 2 ? k : ny - 4 + k;
+  } else {
+    t -= nA + nB;
+    const int k = t & 3, rest = t >> 2;
+    x = k < 2 ? k : nx - 4 + k;
+    z = 2 + rest / (ny - 4);
+    y = 2 + rest - (z - 2) * (ny - 4);
+  }
   const int sz = nx * ny;
+  // faces through a point: bit f set for face f (2*axis + side)
+  auto mask = [&](int xx, int yy, int zz) {
+    return (xx == 0) | (xx == nx - 1) << 1 | (yy == 0) << 2 | (yy == ny - 1) << 3 | (zz == 0) << 4 |
+           (zz == nz - 1) << 5;
+  };
   auto face_idx = [&](int f, int xx, int yy, int zz) {
-    switch (f) {
-      case 0: return a.face_off[0] + zz * ny + yy;
-      case 1: return a.face_off[1] + zz * ny + yy;
-      case 2: return a.face_off[2] + zz * nx + xx;
-      case 3: return a.face_off[3] + zz * nx + xx;
-      case 4: return a.face_off[4] + yy * nx + xx;
-      default: return a.face_off[5] + yy * nx + xx;
-    }
+    const int ax = f >> 1;
+    const int t2 = ax == 0 ? zz * ny + yy : (ax == 1 ? zz * nx + xx : yy * nx + xx);
+    return a.face_off[f] + t2;
   };
-  auto on_face = [&](int f, int xx, int yy, int zz) {
-    switch (f) {
-      case 0: return xx == 0;
-      case 1: return xx == nx - 1;
-      case 2: return yy == 0;
-      case 3: return yy == ny - 1;
-      case 4: return zz == 0;
-      default: return zz == nz - 1;
-    }
-  };
-  // D at a box point: -i cA sum over its faces of av
-  auto Dat = [&](int xx, int yy, int zz) {
-    double sr = 0, si = 0;
+  // sum over the faces of a point of av (D = -i cA times it)
+  auto av_sum = [&](int m, int xx, int yy, int zz) {
+    double2 s = make_double2(0, 0);
     for (int f = 0; f < 6; ++f)
-      if (on_face(f, xx, yy, zz)) {
+      if (m >> f & 1) {
         const double2 v = av[face_idx(f, xx, yy, zz)];
-        sr += v.x;
-        si += v.y;
+        s.x += v.x;
+        s.y += v.y;
       }
-    return make_double2(cA * si, -cA * sr);
+    return s;
   };
-  auto load = [&](const typename cpx<T>::t* p, int xx, int yy, int zz) {
-    const auto v = p[zz * sz + yy * nx + xx];
+  auto load = [&](const typename cpx<T>::t* ptr, int idx) {
+    const auto v = ptr[idx];
     return make_double2((double)v.x, (double)v.y);
   };
-  for (int t = threadIdx.x; t < count; t += blockDim.x) {
-    const int x = full ? t : (t < 2 ? t : nx - 4 + t);
-    const int p = z * sz + y * nx + x;
-    const double vq = a.has_V ? (double)V[p] : 0.0;
-    // H D at q
-    const double2 dq = Dat(x, y, z);
-    double hr = (a.diag + vq) * dq.x, hi = (a.diag + vq) * dq.y;
-    const int nb[6][3] = {{x - 1, y, z}, {x + 1, y, z}, {x, y - 1, z}, {x, y + 1, z}, {x, y, z - 1}, {x, y, z + 1}};
-    double2 wn_sum = make_double2(0, 0);
-    for (int m = 0; m < 6; ++m) {
-      const int xx = nb[m][0], yy = nb[m][1], zz = nb[m][2];
-      if (xx < 0 || xx >= nx || yy < 0 || yy >= ny || zz < 0 || zz >= nz) continue;
-      const double2 dn = Dat(xx, yy, zz);
-      hr += a.off * dn.x;
-      hi += a.off * dn.y;
-      const double2 wv = load(w, xx, yy, zz);
-      wn_sum.x += wv.x;
-      wn_sum.y += wv.y;
+  const int p = z * sz + y * nx + x;
+  const int mq = mask(x, y, z);
+  const double vq = a.has_V ? (double)V[p] : 0.0;
+  // H applied to sum_f av_f, then scaled by -i cA below
+  const double2 sq = mq ? av_sum(mq, x, y, z) : make_double2(0, 0);
+  double2 hs = make_double2((a.diag + vq) * sq.x, (a.diag + vq) * sq.y);
+  double2 wn = make_double2(0, 0);  // sum of w over the in-box neighbours
+  const int nb[6][3] = {{x - 1, y, z}, {x + 1, y, z}, {x, y - 1, z}, {x, y + 1, z}, {x, y, z - 1}, {x, y, z + 1}};
+  for (int m = 0; m < 6; ++m) {
+    const int xx = nb[m][0], yy = nb[m][1], zz = nb[m][2];
+    if (xx < 0 || xx >= nx || yy < 0 || yy >= ny || zz < 0 || zz >= nz) continue;
+    const int mn = mask(xx, yy, zz);
+    if (mn) {
+      const double2 sn = av_sum(mn, xx, yy, zz);
+      hs.x += a.off * sn.x;
+      hs.y += a.off * sn.y;
     }
-    const double2 wq = load(w, x, y, z);
-    // face terms at q
-    double2 vs = make_double2(0, 0);
-    const bool face_q = x == 0 || x == nx - 1 || y == 0 || y == ny - 1 || z == 0 || z == nz - 1;
-    double2 s1 = make_double2(0, 0);
-    if (face_q) {
-      // stage-1 output at q: base + cA (-i)(H w) + D
-      const double hwr = (a.diag + vq) * wq.x + a.off * wn_sum.x;
-      const double hwi = (a.diag + vq) * wq.y + a.off * wn_sum.y;
-      const double2 bq = load(base, x, y, z);
-      s1 = make_double2(bq.x + cA * hwi + dq.x, bq.y - cA * hwr + dq.y);
+    if (mq) {
+      const double2 wv = load(w, zz * sz + yy * nx + xx);
+      wn.x += wv.x;
+      wn.y += wv.y;
     }
+  }
+  // H D = -i cA hs
+  double hr = cA * hs.y, hi = -cA * hs.x;
+  if (mq) {
+    const double2 wq = load(w, p);
+    // stage-1 output at q: base - i cA (H w + sum_f av_f)
+    const double hwr = (a.diag + vq) * wq.x + a.off * wn.x + sq.x;
+    const double hwi = (a.diag + vq) * wq.y + a.off * wn.y + sq.y;
+    const double2 bq = load(base, p);
+    const double2 s1 = make_double2(bq.x + cA * hwi, bq.y - cA * hwr);
     const double2 aw = cmul(a.a0, wq), as1 = cmul(a.a0, s1);
     for (int f = 0; f < 6; ++f) {
-      if (!on_face(f, x, y, z)) continue;
+      if (!(mq >> f & 1)) continue;
       const int fi = face_idx(f, x, y, z);
       const double2 f0 = fb[fi], v0 = av[fi];
       const double2 bv = cmul(a.b0, v0);
       const double2 vf = make_double2(f0.x + cA * (bv.x + aw.x), f0.y + cA * (bv.y + aw.y));
-      vs.x += vf.x;
-      vs.y += vf.y;
+      hr += vf.x;
+      hi += vf.y;
       const double2 bvf = cmul(a.b0, vf);
       aux_out[fi] = make_double2(f0.x + cB * (bvf.x + as1.x), f0.y + cB * (bvf.y + as1.y));
     }
-    hr += vs.x;
-    hi += vs.y;
-    auto o = out[p];
-    o.x += T(cB * hi);
-    o.y -= T(cB * hr);
-    out[p] = o;
   }
+  auto o = out[p];
+  o.x += T(cB * hi);
+  o.y -= T(cB * hr);
+  out[p] = o;
 }
 
 template <typename T>
@@ -529,7 +542,7 @@ namespace {
 
 template <typename T>
 hipError_t step_t(const abc_launch& L, const abc_scratch& S, void* psi_v, double2* aux, const void* V_v, int n,
-                  hipStream_t st) {
+                  hipStream_t st, abc_timer* tm) {
   using C = typename cpx<T>::t;
   const bool two = L.fused_stages == 2;
   FusedArgs a = make_args<T>(L, two);
@@ -566,25 +579,36 @@ hipError_t step_t(const abc_launch& L, const abc_scratch& S, void* psi_v, double
   const T* V = static_cast<const T*>(V_v);
   const int nthreads = 64 * (Tile<T>::TY + 2 * kHalo);
   const int nthreads2 = 64 * (kTY2 + 2 * kHalo2);
-  const unsigned rows = (unsigned)(L.g.ny * L.g.nz);
+  const long long nshell = 4LL * L.g.nx * L.g.ny + 4LL * L.g.nx * (L.g.nz - 4) + 4LL * (L.g.ny - 4) * (L.g.nz - 4);
+  const unsigned bgrid = (unsigned)((nshell + 255) / 256);
   const double dt = L.dt;
+  const dim3 g1(a.ntiles), b4(nthreads), b2(nthreads2), gb(bgrid), bb(256);
   for (int s = 0; s < n; ++s) {
     if (two) {
       if (L.order == ABC_ZEROTH) {
-        fused2_kernel<T, 2, true><<<a.ntiles, nthreads2, 0, st>>>(src, src, mid, V, a, dt / 4, dt / 3);
-        fused2_kernel<T, 2, false><<<a.ntiles, nthreads2, 0, st>>>(mid, src, dst, V, a, dt / 2, dt);
+        abc_launch_kernel(tm, "fused2_half_a", fused2_kernel<T, 2, true>, g1, b2, st, (const C*)src, (const C*)src,
+                          mid, V, a, dt / 4, dt / 3);
+        abc_launch_kernel(tm, "fused2_half_b", fused2_kernel<T, 2, false>, g1, b2, st, (const C*)mid,
+                          (const C*)src, dst, V, a, dt / 2, dt);
       } else {
-        fused2_kernel<T, 0, true><<<a.ntiles, nthreads2, 0, st>>>(src, src, mid, V, a, dt / 4, dt / 3);
-        if (first) fo_boundary_kernel<T><<<rows, 64, 0, st>>>(src, src, mid, V, fsrc, fsrc, vmid, a, dt / 4, dt / 3);
-        fused2_kernel<T, 0, false><<<a.ntiles, nthreads2, 0, st>>>(mid, src, dst, V, a, dt / 2, dt);
-        if (first) fo_boundary_kernel<T><<<rows, 64, 0, st>>>(mid, src, dst, V, vmid, fsrc, fdst, a, dt / 2, dt);
+        abc_launch_kernel(tm, "fused2_half_a", fused2_kernel<T, 0, true>, g1, b2, st, (const C*)src, (const C*)src,
+                          mid, V, a, dt / 4, dt / 3);
+        if (first)
+          abc_launch_kernel(tm, "fo_boundary_a", fo_boundary_kernel<T>, gb, bb, st, (const C*)src, (const C*)src,
+                            mid, V, (const double2*)fsrc, (const double2*)fsrc, vmid, a, dt / 4, dt / 3);
+        abc_launch_kernel(tm, "fused2_half_b", fused2_kernel<T, 0, false>, g1, b2, st, (const C*)mid,
+                          (const C*)src, dst, V, a, dt / 2, dt);
+        if (first)
+          abc_launch_kernel(tm, "fo_boundary_b", fo_boundary_kernel<T>, gb, bb, st, (const C*)mid, (const C*)src,
+                            dst, V, (const double2*)vmid, (const double2*)fsrc, fdst, a, dt / 2, dt);
       }
     } else {
       if (L.order == ABC_ZEROTH)
-        fused_step_kernel<T, 2><<<a.ntiles, nthreads, 0, st>>>(src, dst, V, a);
+        abc_launch_kernel(tm, "fused_step", fused_step_kernel<T, 2>, g1, b4, st, (const C*)src, dst, V, a);
       else
-        fused_step_kernel<T, 0><<<a.ntiles, nthreads, 0, st>>>(src, dst, V, a);
+        abc_launch_kernel(tm, "fused_step", fused_step_kernel<T, 0>, g1, b4, st, (const C*)src, dst, V, a);
     }
+    if (tm) tm->end_step();
     std::swap(src, dst);
     std::swap(fsrc, fdst);
   }
@@ -594,7 +618,7 @@ hipError_t step_t(const abc_launch& L, const abc_scratch& S, void* psi_v, double
 }  // namespace
 
 hipError_t launch_step_fused(const abc_launch& L, const abc_scratch& S, void* psi, double2* aux, const void* V,
-                             int n_steps, hipStream_t st) {
-  if (L.dtype == ABC_C64) return step_t<float>(L, S, psi, aux, V, n_steps, st);
-  return step_t<double>(L, S, psi, aux, V, n_steps, st);
+                             int n_steps, hipStream_t st, abc_timer* tm) {
+  if (L.dtype == ABC_C64) return step_t<float>(L, S, psi, aux, V, n_steps, st, tm);
+  return step_t<double>(L, S, psi, aux, V, n_steps, st, tm);
 }

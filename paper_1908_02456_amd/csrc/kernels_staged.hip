@@ -494,7 +494,9 @@ inline unsigned nblocks(long long n) { return (unsigned)((n + kBlock - 1) / kBlo
 
 template <typename T, int R, bool PER>
 hipError_t step_staged_t(const abc_launch& L, const abc_scratch& S, void* psi_v, double2* aux,
-                         const void* V_v, int n_steps, hipStream_t st) {
+                         const void* V_v, int n_steps, hipStream_t st, abc_timer* tm) {
+  static const char* kStageLabel[5] = {"", "stage_1", "stage_2", "stage_3", "stage_4"};
+  static const char* kBoundLabel[5] = {"", "boundary_1", "boundary_2", "boundary_3", "boundary_4"};
   using C = typename cpx<T>::t;
   const Geometry& g = L.g;
   C* psi = static_cast<C*>(psi_v);
@@ -510,8 +512,8 @@ hipError_t step_staged_t(const abc_launch& L, const abc_scratch& S, void* psi_v,
   for (int s = 0; s < n_steps; ++s) {
     const T* Vuse = V;
     if (L.meanfield) {
-      meanfield_kernel<T><<<nblocks(g.npts), kBlock, 0, st>>>(psi, V, static_cast<T*>(S.veff), g.npts, g.batch,
-                                                            T(L.t0), T(L.t3));
+      abc_launch_kernel(tm, "meanfield", meanfield_kernel<T>, dim3(nblocks(g.npts)), dim3(kBlock), st,
+                        (const C*)psi, V, static_cast<T*>(S.veff), g.npts, g.batch, T(L.t0), T(L.t3));
       Vuse = static_cast<const T*>(S.veff);
     }
     const C* ycur = psi;
@@ -526,22 +528,24 @@ hipError_t step_staged_t(const abc_launch& L, const abc_scratch& S, void* psi_v,
         if (box) {
           const int ncol = first ? 2 * L.n_gamma : L.n_gamma;
           dim3 grid(L.n_gamma, g.batch);
-          box_gemv_kernel<T><<<grid, kBlock, 0, st>>>(L.box_mat, L.n_gamma, ncol, gcur, ycur, L.gamma_lin,
-                                                      first ? gnext : S.src, S.facc, aux, g.batch, coef, mode,
-                                                      first ? 1 : 0);
+          abc_launch_kernel(tm, kBoundLabel[k], box_gemv_kernel<T>, grid, dim3(kBlock), st, L.box_mat, L.n_gamma,
+                            ncol, gcur, ycur, L.gamma_lin, first ? gnext : S.src, S.facc, aux, g.batch, coef, mode,
+                            first ? 1 : 0);
         } else {
-          face_kernel<T, R><<<nblocks(nface), kBlock, 0, st>>>(gcur, first ? gnext : S.src, S.facc, aux, ycur,
-                                                               L.face_ker, a, g, L.w, coef, mode, first ? 1 : 0);
+          abc_launch_kernel(tm, kBoundLabel[k], face_kernel<T, R>, dim3(nblocks(nface)), dim3(kBlock), st, gcur,
+                            first ? gnext : S.src, S.facc, aux, ycur, L.face_ker, a, g, L.w, coef, mode,
+                            first ? 1 : 0);
         }
         const double2* s_for_stage = first ? gcur : S.src;
         if (box) bsrc = s_for_stage; else fsrc = s_for_stage;
         if (first) gcur = gnext;
       }
       C* yout = (k == 4) ? nullptr : y[(k - 1) & 1];
-      stage_kernel<T, R, PER><<<nblocks(nel), kBlock, 0, st>>>(ycur, yout, acc, psi, Vuse, fsrc, bsrc,
-                                                               L.point_gamma, g, sc, coef, mode);
+      abc_launch_kernel(tm, kStageLabel[k], stage_kernel<T, R, PER>, dim3(nblocks(nel)), dim3(kBlock), st, ycur,
+                        yout, acc, psi, Vuse, fsrc, bsrc, L.point_gamma, g, sc, coef, mode);
       ycur = yout;
     }
+    if (tm) tm->end_step();
   }
   return hipGetLastError();
 }
@@ -572,12 +576,12 @@ hipError_t diag_t(const abc_launch& L, const abc_scratch& S, const void* psi, co
 
 template <typename T>
 hipError_t dispatch_step(const abc_launch& L, const abc_scratch& S, void* psi, double2* aux, const void* V,
-                         int n, hipStream_t st) {
+                         int n, hipStream_t st, abc_timer* tm) {
   const bool per = L.periodic != 0;
   switch (L.g.R) {
-    case 1: return per ? step_staged_t<T, 1, true>(L, S, psi, aux, V, n, st) : step_staged_t<T, 1, false>(L, S, psi, aux, V, n, st);
-    case 2: return per ? step_staged_t<T, 2, true>(L, S, psi, aux, V, n, st) : step_staged_t<T, 2, false>(L, S, psi, aux, V, n, st);
-    case 3: return per ? step_staged_t<T, 3, true>(L, S, psi, aux, V, n, st) : step_staged_t<T, 3, false>(L, S, psi, aux, V, n, st);
+    case 1: return per ? step_staged_t<T, 1, true>(L, S, psi, aux, V, n, st, tm) : step_staged_t<T, 1, false>(L, S, psi, aux, V, n, st, tm);
+    case 2: return per ? step_staged_t<T, 2, true>(L, S, psi, aux, V, n, st, tm) : step_staged_t<T, 2, false>(L, S, psi, aux, V, n, st, tm);
+    case 3: return per ? step_staged_t<T, 3, true>(L, S, psi, aux, V, n, st, tm) : step_staged_t<T, 3, false>(L, S, psi, aux, V, n, st, tm);
   }
   return hipErrorInvalidValue;
 }
@@ -597,9 +601,9 @@ hipError_t dispatch_diag(const abc_launch& L, const abc_scratch& S, const void* 
 }  // namespace
 
 hipError_t launch_step_staged(const abc_launch& L, const abc_scratch& S, void* psi, double2* aux, const void* V,
-                              int n_steps, hipStream_t st) {
-  if (L.dtype == ABC_C64) return dispatch_step<float>(L, S, psi, aux, V, n_steps, st);
-  return dispatch_step<double>(L, S, psi, aux, V, n_steps, st);
+                              int n_steps, hipStream_t st, abc_timer* tm) {
+  if (L.dtype == ABC_C64) return dispatch_step<float>(L, S, psi, aux, V, n_steps, st, tm);
+  return dispatch_step<double>(L, S, psi, aux, V, n_steps, st, tm);
 }
 
 hipError_t launch_diagnostics(const abc_launch& L, const abc_scratch& S, const void* psi, const double2* aux,

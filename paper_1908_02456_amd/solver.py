@@ -116,6 +116,18 @@ class Solver:
         _lib.check(self._lib.abc_step(self._ctx, psi.data_ptr(), ap, vp, int(n_steps), _stream_handle(stream)))
         return psi
 
+    def step_timed(self, psi, aux=None, V=None, n_steps: int = 1, stream=None, cap: int = 64):
+        """Advance like step() and return [(launch label, mean ms per step)] for
+        the kernel launches of one step (HIP events around each launch)."""
+        self._check_psi(psi)
+        vp = self._check_V(V)
+        ap = self._check_aux(aux)
+        ms = (ctypes.c_double * cap)()
+        k = ctypes.c_int(0)
+        _lib.check(self._lib.abc_step_timed(self._ctx, psi.data_ptr(), ap, vp, int(n_steps), _stream_handle(stream),
+                                            ctypes.cast(ms, ctypes.c_void_p), cap, ctypes.byref(k)))
+        return [(self._lib.abc_launch_label(self._ctx, j).decode(), ms[j]) for j in range(min(k.value, cap))]
+
     def diagnostics(self, psi, aux=None, V=None, out: Optional[torch.Tensor] = None, stream=None):
         """Tensor of 3*batch+1 float64: norm, Lyapunov W, energy per orbital, interaction energy."""
         self._check_psi(psi)

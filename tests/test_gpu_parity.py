@@ -196,3 +196,27 @@ def test_setup_rejects_unstable_dt():
     with pytest.raises(AbcError) as e:
         Solver((8, 8, 8), 0.1, 0.1, order="first")
     assert e.value.status == ABC_EUNSTABLE
+
+
+@pytest.mark.parametrize("path,order", [("fused", "first"), ("staged", "first"), ("fused", "dirichlet")])
+def test_step_timed_matches_step(path, order):
+    # the measurement entry runs the same kernels with the same launch shapes
+    print("case: step_timed", path, order, flush=True)
+    Solver = _gpu()
+    shape = (20, 18, 24)
+    psi0 = W.random_complex(shape, seed=21)
+    V = torch.from_numpy(W.random_potential(shape, seed=22)).cuda()
+    outs = []
+    for timed in (False, True):
+        s = Solver(shape, 0.25, 0.004, order=order, s1=1.5, window=0, path=path)
+        psi = torch.from_numpy(psi0).cuda()
+        aux = s.new_aux()
+        if timed:
+            launches = s.step_timed(psi, aux, V, 5)
+            assert launches and all(ms > 0 for _, ms in launches)
+        else:
+            s.step(psi, aux, V, 5)
+        torch.cuda.synchronize()
+        outs.append((psi.cpu().numpy(), aux.cpu().numpy()))
+    assert np.array_equal(outs[0][0], outs[1][0])
+    assert np.array_equal(outs[0][1], outs[1][1])
