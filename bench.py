@@ -78,19 +78,17 @@ def shell_counts(n, R):
     return n ** 3 - inner, 6 * R * n * n
 
 
-def alg_bytes(label, n, R, csz, rsz):
+def alg_bytes(label, n, R, csz, rsz, first=True):
     """Algorithmic bytes of one launch of the step at n^3 (what the launch must
     read and write once: state csz, potential rsz, FP64 face aux 16 B)."""
     npts = n ** 3
-    shell, faces = shell_counts(n, R)
-    if label in ("fused_step", "fused2_half_a"):
-        return npts * (2 * csz + rsz)               # read psi, V; write result
-    if label == "fused2_half_b":
-        return npts * (3 * csz + rsz)               # read u2, psi, V; write psi'
-    if label == "fo_boundary_a":                    # out r/w + w on the shell; V, aux in/out on faces
-        return shell * 3 * csz + faces * (rsz + 32)
-    if label == "fo_boundary_b":                    # as A plus base and the separate aux base
-        return shell * 3 * csz + faces * (rsz + csz + 48)
+    _, faces = shell_counts(n, R)
+    if label == "fused_step":
+        return npts * (2 * csz + rsz)               # read psi, V; write psi'
+    if label == "fused2_half_a":                    # read psi, V, f; write u2 and its aux
+        return npts * (2 * csz + rsz) + (faces * 32 if first else 0)
+    if label == "fused2_half_b":                    # read u2, psi, V, both aux; write psi', f'
+        return npts * (3 * csz + rsz) + (faces * 48 if first else 0)
     if label.startswith("stage_"):                  # y in, acc, psi/base, V, y out
         return npts * (4 * csz + rsz)
     if label.startswith("boundary_"):

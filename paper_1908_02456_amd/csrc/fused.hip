@@ -20,9 +20,12 @@
 //   * tiles are numbered so that consecutive tiles share an XCD and its L2.
 // fused_step_kernel runs all four stages (one launch per step);
 // fused2_kernel runs half of them (two launches per step, two-deep halos,
-// half the register state).  First-order boundary terms are added to each
-// half by fo_boundary_kernel.  The state is read from one buffer and written
-// to another, since neighbouring tiles read halos that a tile overwrites.
+// half the register state) and also carries the first-order condition: the
+// face sources and the auxiliary stages are evaluated at face points only
+// (whole rows on y and z faces, the two edge lanes on x faces), from the
+// auxiliary arrays in global memory and the field values already in
+// registers.  The state is read from one buffer and written to another,
+// since neighbouring tiles read halos that a tile overwrites.
 #include <hip/hip_runtime.h>
 
 #include <cstdlib>
@@ -224,7 +227,8 @@ constexpr int kTY2 = 8, kTZ2 = 8, kHalo2 = 2;
 template <typename T, int ORDER, bool SAME_BASE>
 __global__ void __launch_bounds__(64 * (kTY2 + 2 * kHalo2)) fused2_kernel(
     const typename cpx<T>::t* __restrict__ w_in, const typename cpx<T>::t* __restrict__ base_in,
-    typename cpx<T>::t* __restrict__ out, const T* __restrict__ V, FusedArgs a, double cA, double cB) {
+    typename cpx<T>::t* __restrict__ out, const T* __restrict__ V, FusedArgs a, double cA, double cB,
+    const double2* __restrict__ av, const double2* __restrict__ fb, double2* __restrict__ aux_out) {
   using C = typename cpx<T>::t;
   constexpr int TY = kTY2, TZ = kTZ2, H = kHalo2;
   constexpr int ROWS = TY + 2 * H;
@@ -246,7 +250,6 @@ __global__ void __launch_bounds__(64 * (kTY2 + 2 * kHalo2)) fused2_kernel(
   const bool own_row = r >= H && r < H + TY && row_in;
 
   for (int i = threadIdx.x; i < 2 * ROWS * 2 * 66; i += NT) (&plane[0][0][0][0])[i] = czero<C>();
-  __syncthreads();
 
   C Yc[2][2], Yb[2][2];  // stage inputs: centre / below (j = 0: w, j = 1: stage-1 output)
   C Bd[2][2];            // base at planes zi-1, zi-2 (separate base only)
@@ -282,6 +285,71 @@ __global__ void __launch_bounds__(64 * (kTY2 + 2 * kHalo2)) fused2_kernel(
     }
   };
   fetch(z0 - H);
+
+  // First order: the tile's face data (auxiliary input av and base fb) staged
+  // in LDS once, for planes z0-1 .. z0+TZ and rows 1 .. ROWS-2 of the tile:
+  // both x faces, and the tile's y-face row and z-face plane if it has them
+  // (at most one of each when ny, nz >= TY + 2).  Every thread issues all of
+  // its loads before storing any, so the staging costs one memory round trip,
+  // overlapped with the first plane fetch.
+  constexpr int FP = TZ + 2, FR = ROWS - 2;
+  constexpr int NX = ORDER == 3 ? 2 * 2 * FP * FR : 1;
+  constexpr int NY = ORDER == 3 ? 2 * FP * kCols : 1;
+  constexpr int NZ = ORDER == 3 ? 2 * FR * kCols : 1;
+  __shared__ double2 fxs[NX];  // [arr][side][plane][row]
+  __shared__ double2 fys[NY];  // [arr][plane][x]
+  __shared__ double2 fzs[NZ];  // [arr][row][x]
+  int yface = -1, zface = -1;  // face index (2/3, 4/5) of the staged row / plane
+  if (ORDER == 3) {
+    const int ylo = y0 - H + 1, zlo = z0 - 1;
+    if (ylo <= 0) yface = 2;
+    else if (ylo <= ny - 1 && ny - 1 < ylo + FR) yface = 3;
+    if (zlo <= 0) zface = 4;
+    else if (zlo <= nz - 1 && nz - 1 < zlo + FP) zface = 5;
+    constexpr int KX = (NX + NT - 1) / NT, KY = (NY + NT - 1) / NT, KZ = (NZ + NT - 1) / NT;
+    const int ny_el = 2 * FP * nx, nz_el = 2 * FR * nx;
+    double2 rx[KX], ry[KY], rz[KZ];
+#pragma unroll
+    for (int j = 0; j < KX; ++j) {
+      const int i = threadIdx.x + j * NT;
+      const int rr = i % FR, pl = (i / FR) % FP, side = (i / (FR * FP)) & 1, arr = i / (2 * FR * FP);
+      const int yy = ylo + rr, zz = zlo + pl;
+      rx[j] = make_double2(0, 0);
+      if (i < NX && yy >= 0 && yy < ny && zz >= 0 && zz < nz) rx[j] = (arr ? fb : av)[a.face_off[side] + zz * ny + yy];
+    }
+#pragma unroll
+    for (int j = 0; j < KY; ++j) {
+      const int i = threadIdx.x + j * NT;
+      const int xx = i % nx, pl = (i / nx) % FP, arr = i / (nx * FP);
+      const int zz = zlo + pl;
+      ry[j] = make_double2(0, 0);
+      if (yface >= 0 && i < ny_el && zz >= 0 && zz < nz) ry[j] = (arr ? fb : av)[a.face_off[yface] + zz * nx + xx];
+    }
+#pragma unroll
+    for (int j = 0; j < KZ; ++j) {
+      const int i = threadIdx.x + j * NT;
+      const int xx = i % nx, rr = (i / nx) % FR, arr = i / (nx * FR);
+      const int yy = ylo + rr;
+      rz[j] = make_double2(0, 0);
+      if (zface >= 0 && i < nz_el && yy >= 0 && yy < ny) rz[j] = (arr ? fb : av)[a.face_off[zface] + yy * nx + xx];
+    }
+#pragma unroll
+    for (int j = 0; j < KX; ++j) {
+      const int i = threadIdx.x + j * NT;
+      if (i < NX) fxs[i] = rx[j];
+    }
+#pragma unroll
+    for (int j = 0; j < KY; ++j) {
+      const int i = threadIdx.x + j * NT;
+      if (i < ny_el) fys[(i / (nx * FP) * FP + (i / nx) % FP) * kCols + i % nx] = ry[j];
+    }
+#pragma unroll
+    for (int j = 0; j < KZ; ++j) {
+      const int i = threadIdx.x + j * NT;
+      if (i < nz_el) fzs[(i / (nx * FR) * FR + (i / nx) % FR) * kCols + i % nx] = rz[j];
+    }
+  }
+  __syncthreads();
 
   for (int it = 0; it < ITERS; ++it) {
     const int zi = z0 - H + it;
@@ -326,6 +394,52 @@ __global__ void __launch_bounds__(64 * (kTY2 + 2 * kHalo2)) fused2_kernel(
             hi += T(nf * sv.y);
           }
         }
+        if (ORDER == 3) {
+          // first order: the psi stage sees -i sum_f g_f at face points, with
+          // g = the auxiliary input (stage 1) or the auxiliary stage
+          // v_f = fb_f + cA (b av_f + a w) (stage 2), which also produces the
+          // auxiliary output fb_f + cB (b v_f + a s1) at owned points
+          const bool fx = x == 0 || x == nx - 1, fy = y == 0 || y == ny - 1, fz = zk == 0 || zk == nz - 1;
+          if ((fx || fy || fz) && x < nx) {
+            const int pl = zk - (z0 - 1), rr = r - 1;
+            double sr = 0, si = 0;
+            double2 aw = make_double2(0, 0), as1 = make_double2(0, 0);
+            if (k == 2) {
+              aw = cmul(a.a0, make_double2((double)wm2[c].x, (double)wm2[c].y));
+              as1 = cmul(a.a0, make_double2((double)cen.x, (double)cen.y));
+            }
+            const bool own = k == 2 && own_row && it >= 2 * H;
+            // one face through the point: its auxiliary input g and base f0
+            auto face = [&](const double2* lds_g, const double2* lds_f, int gi) {
+              const double2 g = *lds_g;
+              if (k == 1) {
+                sr += g.x;
+                si += g.y;
+                return;
+              }
+              const double2 f0 = *lds_f;
+              const double2 bg = cmul(a.b0, g);
+              const double2 v = make_double2(f0.x + cA * (bg.x + aw.x), f0.y + cA * (bg.y + aw.y));
+              sr += v.x;
+              si += v.y;
+              if (own) {
+                const double2 bv = cmul(a.b0, v);
+                aux_out[gi] = make_double2(f0.x + cB * (bv.x + as1.x), f0.y + cB * (bv.y + as1.y));
+              }
+            };
+            if (fx) {
+              const int side = x == 0 ? 0 : 1;
+              face(&fxs[((0 * 2 + side) * FP + pl) * FR + rr], &fxs[((1 * 2 + side) * FP + pl) * FR + rr],
+                   a.face_off[side] + zk * ny + y);
+            }
+            if (fy)
+              face(&fys[(0 * FP + pl) * kCols + x], &fys[(1 * FP + pl) * kCols + x], a.face_off[yface] + zk * nx + x);
+            if (fz)
+              face(&fzs[(0 * FR + rr) * kCols + x], &fzs[(1 * FR + rr) * kCols + x], a.face_off[zface] + y * nx + x);
+            hr += T(sr);
+            hi += T(si);
+          }
+        }
         o[c].x = x < nx ? b0.x + cf * hi : T(0);
         o[c].y = x < nx ? b0.y - cf * hr : T(0);
       }
@@ -356,130 +470,6 @@ __global__ void __launch_bounds__(64 * (kTY2 + 2 * kHalo2)) fused2_kernel(
       for (int c = 0; c < 2; ++c) plane[j][r][c][lane + 1] = Yc[j][c];
     sync_lds();
   }
-}
-
-// ---------------------------------------------------------------------------
-// First-order boundary terms of a two-stage half, added after the half ran
-// without them (the Dirichlet box, i.e. H = -(1/2) Delta_h + V with zero
-// outside).  The half is linear, and with local (window 0) face operators the
-// sources it sees are known up front:
-//   stage 1 adds -i cA sum_f av_f at face points, so the stage-1 output is
-//     s1 = s1_plain + D,  D = -i cA sum_f av_f   (zero off the faces);
-//   the auxiliary stage is v_f = fb_f + cA (b av_f + a w)  (w: stage-1 input);
-//   stage 2 adds -i cB (sum_f v_f) at face points and sees D through H, so
-//     out = out_plain - i cB (H D + sum_f v_f)   on points within one layer of
-//   a face; and the auxiliary output is fb_f + cB (b v_f + a s1) at faces.
-// One thread per shell point (depth <= 1), enumerated so that consecutive
-// threads take consecutive x where they can: the two outer planes on each z
-// side, then the two outer rows on each y side, then the four outer columns.
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ int shell_points(int nx, int ny, int nz) {
-  return 4 * nx * ny + 4 * nx * (nz - 4) + 4 * (ny - 4) * (nz - 4);
-}
-
-template <typename T>
-__global__ void __launch_bounds__(256) fo_boundary_kernel(
-    const typename cpx<T>::t* __restrict__ w, const typename cpx<T>::t* __restrict__ base,
-    typename cpx<T>::t* __restrict__ out, const T* __restrict__ V, const double2* __restrict__ av,
-    const double2* __restrict__ fb, double2* __restrict__ aux_out, FusedArgs a, double cA, double cB) {
-  const int nx = a.nx, ny = a.ny, nz = a.nz;
-  int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= shell_points(nx, ny, nz)) return;
-  int x, y, z;
-  const int nA = 4 * nx * ny, nB = 4 * nx * (nz - 4);
-  if (t < nA) {
-    const int k = t / (nx * ny), rem = t - k * nx * ny;
-    z = k < 2 ? k : nz - 4 + k;
-    y = rem / nx;
-    x = rem - y * nx;
-  } else if (t < nA + nB) {
-    t -= nA;
-    const int row = t / nx, k = row & 3;
-    x = t - row * nx;
-    z = 2 + (row >> 2);
-    y = k < 2 ? k : ny - 4 + k;
-  } else {
-    t -= nA + nB;
-    const int k = t & 3, rest = t >> 2;
-    x = k < 2 ? k : nx - 4 + k;
-    z = 2 + rest / (ny - 4);
-    y = 2 + rest - (z - 2) * (ny - 4);
-  }
-  const int sz = nx * ny;
-  // faces through a point: bit f set for face f (2*axis + side)
-  auto mask = [&](int xx, int yy, int zz) {
-    return (xx == 0) | (xx == nx - 1) << 1 | (yy == 0) << 2 | (yy == ny - 1) << 3 | (zz == 0) << 4 |
-           (zz == nz - 1) << 5;
-  };
-  auto face_idx = [&](int f, int xx, int yy, int zz) {
-    const int ax = f >> 1;
-    const int t2 = ax == 0 ? zz * ny + yy : (ax == 1 ? zz * nx + xx : yy * nx + xx);
-    return a.face_off[f] + t2;
-  };
-  // sum over the faces of a point of av (D = -i cA times it)
-  auto av_sum = [&](int m, int xx, int yy, int zz) {
-    double2 s = make_double2(0, 0);
-    for (int f = 0; f < 6; ++f)
-      if (m >> f & 1) {
-        const double2 v = av[face_idx(f, xx, yy, zz)];
-        s.x += v.x;
-        s.y += v.y;
-      }
-    return s;
-  };
-  auto load = [&](const typename cpx<T>::t* ptr, int idx) {
-    const auto v = ptr[idx];
-    return make_double2((double)v.x, (double)v.y);
-  };
-  const int p = z * sz + y * nx + x;
-  const int mq = mask(x, y, z);
-  const double vq = a.has_V ? (double)V[p] : 0.0;
-  // H applied to sum_f av_f, then scaled by -i cA below
-  const double2 sq = mq ? av_sum(mq, x, y, z) : make_double2(0, 0);
-  double2 hs = make_double2((a.diag + vq) * sq.x, (a.diag + vq) * sq.y);
-  double2 wn = make_double2(0, 0);  // sum of w over the in-box neighbours
-  const int nb[6][3] = {{x - 1, y, z}, {x + 1, y, z}, {x, y - 1, z}, {x, y + 1, z}, {x, y, z - 1}, {x, y, z + 1}};
-  for (int m = 0; m < 6; ++m) {
-    const int xx = nb[m][0], yy = nb[m][1], zz = nb[m][2];
-    if (xx < 0 || xx >= nx || yy < 0 || yy >= ny || zz < 0 || zz >= nz) continue;
-    const int mn = mask(xx, yy, zz);
-    if (mn) {
-      const double2 sn = av_sum(mn, xx, yy, zz);
-      hs.x += a.off * sn.x;
-      hs.y += a.off * sn.y;
-    }
-    if (mq) {
-      const double2 wv = load(w, zz * sz + yy * nx + xx);
-      wn.x += wv.x;
-      wn.y += wv.y;
-    }
-  }
-  // H D = -i cA hs
-  double hr = cA * hs.y, hi = -cA * hs.x;
-  if (mq) {
-    const double2 wq = load(w, p);
-    // stage-1 output at q: base - i cA (H w + sum_f av_f)
-    const double hwr = (a.diag + vq) * wq.x + a.off * wn.x + sq.x;
-    const double hwi = (a.diag + vq) * wq.y + a.off * wn.y + sq.y;
-    const double2 bq = load(base, p);
-    const double2 s1 = make_double2(bq.x + cA * hwi, bq.y - cA * hwr);
-    const double2 aw = cmul(a.a0, wq), as1 = cmul(a.a0, s1);
-    for (int f = 0; f < 6; ++f) {
-      if (!(mq >> f & 1)) continue;
-      const int fi = face_idx(f, x, y, z);
-      const double2 f0 = fb[fi], v0 = av[fi];
-      const double2 bv = cmul(a.b0, v0);
-      const double2 vf = make_double2(f0.x + cA * (bv.x + aw.x), f0.y + cA * (bv.y + aw.y));
-      hr += vf.x;
-      hi += vf.y;
-      const double2 bvf = cmul(a.b0, vf);
-      aux_out[fi] = make_double2(f0.x + cB * (bvf.x + as1.x), f0.y + cB * (bvf.y + as1.y));
-    }
-  }
-  auto o = out[p];
-  o.x += T(cB * hi);
-  o.y -= T(cB * hr);
-  out[p] = o;
 }
 
 template <typename T>
@@ -516,6 +506,8 @@ bool fused_supported(const abc_params& p, std::string* why) {
     return no("local (window 0) face operators only");
   if (p.nx > kCols) return no("nx <= 128");
   if (p.nz < 5 || p.ny < 4 || p.nx < 4) return no("nx, ny >= 4 and nz >= 5");
+  if (p.order == ABC_FIRST && (p.ny < kTY2 + 2 || p.nz < kTZ2 + 2))
+    return no("first order: ny, nz >= 10 (one y-face row and one z-face plane per tile)");
   if ((long long)p.nx * p.ny * p.nz >= (1LL << 31)) return no("grid below 2^31 points");
   return true;
 }
@@ -579,28 +571,25 @@ hipError_t step_t(const abc_launch& L, const abc_scratch& S, void* psi_v, double
   const T* V = static_cast<const T*>(V_v);
   const int nthreads = 64 * (Tile<T>::TY + 2 * kHalo);
   const int nthreads2 = 64 * (kTY2 + 2 * kHalo2);
-  const long long nshell = 4LL * L.g.nx * L.g.ny + 4LL * L.g.nx * (L.g.nz - 4) + 4LL * (L.g.ny - 4) * (L.g.nz - 4);
-  const unsigned bgrid = (unsigned)((nshell + 255) / 256);
   const double dt = L.dt;
-  const dim3 g1(a.ntiles), b4(nthreads), b2(nthreads2), gb(bgrid), bb(256);
+  const dim3 g1(a.ntiles), b4(nthreads), b2(nthreads2);
   for (int s = 0; s < n; ++s) {
     if (two) {
       if (L.order == ABC_ZEROTH) {
         abc_launch_kernel(tm, "fused2_half_a", fused2_kernel<T, 2, true>, g1, b2, st, (const C*)src, (const C*)src,
-                          mid, V, a, dt / 4, dt / 3);
+                          mid, V, a, dt / 4, dt / 3, nullptr, nullptr, nullptr);
         abc_launch_kernel(tm, "fused2_half_b", fused2_kernel<T, 2, false>, g1, b2, st, (const C*)mid,
-                          (const C*)src, dst, V, a, dt / 2, dt);
+                          (const C*)src, dst, V, a, dt / 2, dt, nullptr, nullptr, nullptr);
+      } else if (first) {
+        abc_launch_kernel(tm, "fused2_half_a", fused2_kernel<T, 3, true>, g1, b2, st, (const C*)src, (const C*)src,
+                          mid, V, a, dt / 4, dt / 3, (const double2*)fsrc, (const double2*)fsrc, vmid);
+        abc_launch_kernel(tm, "fused2_half_b", fused2_kernel<T, 3, false>, g1, b2, st, (const C*)mid,
+                          (const C*)src, dst, V, a, dt / 2, dt, (const double2*)vmid, (const double2*)fsrc, fdst);
       } else {
         abc_launch_kernel(tm, "fused2_half_a", fused2_kernel<T, 0, true>, g1, b2, st, (const C*)src, (const C*)src,
-                          mid, V, a, dt / 4, dt / 3);
-        if (first)
-          abc_launch_kernel(tm, "fo_boundary_a", fo_boundary_kernel<T>, gb, bb, st, (const C*)src, (const C*)src,
-                            mid, V, (const double2*)fsrc, (const double2*)fsrc, vmid, a, dt / 4, dt / 3);
+                          mid, V, a, dt / 4, dt / 3, nullptr, nullptr, nullptr);
         abc_launch_kernel(tm, "fused2_half_b", fused2_kernel<T, 0, false>, g1, b2, st, (const C*)mid,
-                          (const C*)src, dst, V, a, dt / 2, dt);
-        if (first)
-          abc_launch_kernel(tm, "fo_boundary_b", fo_boundary_kernel<T>, gb, bb, st, (const C*)mid, (const C*)src,
-                            dst, V, (const double2*)vmid, (const double2*)fsrc, fdst, a, dt / 2, dt);
+                          (const C*)src, dst, V, a, dt / 2, dt, nullptr, nullptr, nullptr);
       }
     } else {
       if (L.order == ABC_ZEROTH)

@@ -143,10 +143,11 @@ def test_zero_steps_and_minimum_box():
 
 
 @pytest.mark.parametrize("order", ["dirichlet", "zeroth", "first"])
-@pytest.mark.parametrize("shape", [(21, 19, 37), (9, 17, 128), (16, 16, 16)])
+@pytest.mark.parametrize("shape", [(21, 19, 37), (10, 17, 128), (16, 16, 16)])
 @pytest.mark.parametrize("steps", [5, 6])
 def test_fused_path_parity(order, shape, steps):
-    # several 8x8 (y, z) tiles with ragged tails; odd and even step counts
+    # several 8x8 (y, z) tiles with ragged tails (10 = one plane/row past a
+    # tile and a face row/plane in the halo); odd and even step counts
     r = _run_pair("fused", shape, 0.25, 0.004, 1, order, steps, s0=1.5, s1=1.5, window=0, path="fused")
     assert r["solver"].use_fused
     assert r["err"] < TOL64, r["err"]
@@ -220,3 +221,18 @@ def test_step_timed_matches_step(path, order):
         outs.append((psi.cpu().numpy(), aux.cpu().numpy()))
     assert np.array_equal(outs[0][0], outs[1][0])
     assert np.array_equal(outs[0][1], outs[1][1])
+
+
+def test_fused_first_order_small_box_falls_back():
+    # the fused first-order kernel stages one y-face row and one z-face plane
+    # per tile, so boxes with ny or nz below 10 run on the staged path
+    print("case: fused fallback", flush=True)
+    Solver = _gpu()
+    from paper_1908_02456_amd._lib import AbcError, ABC_ENOTSUP
+    with pytest.raises(AbcError) as e:
+        Solver((9, 17, 20), 0.25, 0.004, order="first", window=0, path="fused")
+    assert e.value.status == ABC_ENOTSUP
+    s = Solver((9, 17, 20), 0.25, 0.004, order="first", window=0, path="auto")
+    assert not s.use_fused
+    r = _run_pair("fused-fallback", (9, 17, 20), 0.25, 0.004, 1, "first", 4, s1=1.5, window=0, path="auto")
+    assert r["err"] < TOL64 and r["aux_err"] < TOL64
