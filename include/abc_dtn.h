@@ -143,6 +143,28 @@ abc_status abc_step_timed(abc_ctx* ctx, void* psi, void* aux, const void* V,
  * abc_destroy); NULL if j is out of range or no timed call was made. */
 const char* abc_launch_label(const abc_ctx* ctx, int j);
 
+/* Objectives of abc_adjoint. */
+enum { ABC_OBJ_PROB = 0, ABC_OBJ_ENERGY = 1 };
+
+/* Discrete adjoint (reverse mode) of n_steps Taylor steps of the stepping map
+ * of Sec. 4 on the dynamics of Sec. 3, started from (psi0, f = 0).
+ * objective ABC_OBJ_PROB: J = h^3 sum |psi_N|^2 (probability left in the
+ * box); ABC_OBJ_ENERGY: J = h^3 Re <psi_N, H_{I,I} psi_N> (no boundary term).
+ * Writes J to the host double *J_out, dJ/dRe psi0 + i dJ/dIm psi0 to
+ * grad_psi0 (device, complex128, psi's layout, caller-owned) and dJ/dV to
+ * grad_V (device, float64 [z][y][x], caller-owned).  psi0 and V are device
+ * buffers of the context's box (V may be NULL for V = 0).  Checkpoints every
+ * ckpt_stride steps (<= 0: ceil(sqrt(n_steps))); device memory for
+ * (n/stride + stride + 10) states is allocated and freed by the call, which
+ * synchronises the stream.  Supported: complex128, one orbital, no mean
+ * field; Dirichlet and periodic boxes; face-form zeroth order (any R) and
+ * first order (R = 1).  Others: ABC_ENOTSUP.  ABC_ENOMEM if the buffers do
+ * not fit, ABC_EDEVICE on HIP failures. */
+abc_status abc_adjoint(abc_ctx* ctx, const void* psi0, const void* V,
+                       int n_steps, int ckpt_stride, int objective,
+                       void* grad_psi0, double* grad_V, double* J_out,
+                       void* stream);
+
 /* FP64 diagnostics of a state, written to device memory out (3*batch + 1
  * doubles): [0, batch) norm h^3 sum |psi_j|^2; [batch, 2 batch) Lyapunov
  * functional h^3 (psi_j^* psi_j + f_j^* Q f_j) (Sec. 3, zeroth- and

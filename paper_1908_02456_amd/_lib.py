@@ -15,10 +15,11 @@ ORDERS = {"dirichlet": 0, "periodic": 1, "zeroth": 2, "first": 3}
 FORMS = {"box": 0, "faces": 1}
 DTYPES = {"c128": 0, "c64": 1}
 PATHS = {"auto": 0, "staged": 1, "fused": 2}
+OBJECTIVES = {"prob": 0, "energy": 1}
 
 EXPORTED = ["abc_params_default", "abc_setup", "abc_step", "abc_diagnostics", "abc_aux_elems",
             "abc_export", "abc_path", "abc_device_bytes", "abc_last_error", "abc_destroy",
-            "abc_step_timed", "abc_launch_label"]
+            "abc_step_timed", "abc_launch_label", "abc_adjoint"]
 
 
 class AbcParams(ctypes.Structure):
@@ -64,6 +65,9 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.abc_step_timed.restype = ctypes.c_int
     lib.abc_launch_label.argtypes = [vp, ctypes.c_int]
     lib.abc_launch_label.restype = ctypes.c_char_p
+    lib.abc_adjoint.argtypes = [vp, vp, vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, vp,
+                                ctypes.POINTER(ctypes.c_double), vp]
+    lib.abc_adjoint.restype = ctypes.c_int
     lib.abc_diagnostics.argtypes = [vp, vp, vp, vp, vp, vp]
     lib.abc_diagnostics.restype = ctypes.c_int
     lib.abc_aux_elems.argtypes = [vp]

@@ -139,7 +139,23 @@ void abc_launch_kernel(abc_timer* tm, const char* label, void (*k)(P...), dim3 g
   if (tm->pair(label, &e0, &e1)) hipExtLaunchKernelGGL(k, grid, block, 0, st, e0, e1, 0, args...);
 }
 
+// keep (optional): three psi-sized buffers that receive the stage vectors
+// z_1, z_2, z_3 of the (last) step instead of the scratch ping-pong.
 hipError_t launch_step_staged(const abc_launch& L, const abc_scratch& S, void* psi, double2* aux,
-                              const void* V, int n_steps, hipStream_t st, abc_timer* tm = nullptr);
+                              const void* V, int n_steps, hipStream_t st, abc_timer* tm = nullptr,
+                              void* const* keep = nullptr);
+// Discrete adjoint (adjoint.hip).  La is L with the adjoint operators
+// (dt -> -dt, conjugate-transposed boundary operators, rescaled aux).
+struct abc_adjoint_args {
+  const void* psi0;
+  const void* V;
+  int n_steps, stride, objective;
+  void* grad_psi0;
+  double* grad_V;
+  double* J_host;
+};
+abc_status run_adjoint(const abc_launch& L, const abc_launch& La, const abc_scratch& S, const abc_adjoint_args& a,
+                       hipStream_t st, std::string& err);
+
 hipError_t launch_diagnostics(const abc_launch& L, const abc_scratch& S, const void* psi,
                               const double2* aux, const void* V, double* out, hipStream_t st);

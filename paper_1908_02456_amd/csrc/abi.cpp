@@ -34,6 +34,8 @@ struct abc_ctx {
   double2* box_mat = nullptr;
   double2* box_q = nullptr;
   std::vector<std::string> launch_labels;  // launches of a step, from the last abc_step_timed
+  abc_launch La{};                         // adjoint operator set (built on first abc_adjoint)
+  bool adjoint_ready = false;
 };
 
 namespace {
@@ -306,6 +308,62 @@ abc_status abc_step_timed(abc_ctx* c, void* psi, void* aux, const void* V, int n
 const char* abc_launch_label(const abc_ctx* c, int j) {
   if (!c || j < 0 || j >= (int)c->launch_labels.size()) return nullptr;
   return c->launch_labels[j].c_str();
+}
+
+namespace {
+
+// Adjoint operator set: -dt, and for the face form the kernel of the
+// conjugate-transposed section, k'_{l,l'}(p) = conj(k_{l',l}(-p)); first order
+// (R = 1) with the aux rescaled by -i conj(a): a -> -conj(a), B -> -B^H.
+abc_status build_adjoint(abc_ctx* c) {
+  abc_launch& La = c->La;
+  La = c->L;
+  La.dt = -c->L.dt;
+  if (c->p.order == ABC_ZEROTH || c->p.order == ABC_FIRST) {
+    const int R = c->p.radius, K = 2 * c->p.window + 1;
+    const double sgn = c->p.order == ABC_FIRST ? -1.0 : 1.0;
+    std::vector<double2> kh(c->face.kernel.size());
+    for (int l = 0; l < R; ++l)
+      for (int lp = 0; lp < R; ++lp)
+        for (int i = 0; i < K; ++i)
+          for (int j = 0; j < K; ++j) {
+            const abc::cd v = std::conj(c->face.kernel[((lp * R + l) * K + (K - 1 - i)) * K + (K - 1 - j)]);
+            kh[((l * R + lp) * K + i) * K + j] = make_double2(sgn * v.real(), sgn * v.imag());
+          }
+    void* kd = nullptr;
+    abc_status st = dev_alloc(c, &kd, kh.size() * sizeof(double2));
+    if (st != ABC_OK) return st;
+    if (hipMemcpy(kd, kh.data(), kh.size() * sizeof(double2), hipMemcpyHostToDevice) != hipSuccess)
+      return fail(ABC_EDEVICE, "hipMemcpy of adjoint kernel failed");
+    La.face_ker = static_cast<const double2*>(kd);
+    if (c->p.order == ABC_FIRST) La.a_loc[0] = make_double2(-c->L.a_loc[0].x, c->L.a_loc[0].y);
+  }
+  c->adjoint_ready = true;
+  return ABC_OK;
+}
+
+}  // namespace
+
+abc_status abc_adjoint(abc_ctx* c, const void* psi0, const void* V, int n_steps, int ckpt_stride, int objective,
+                       void* grad_psi0, double* grad_V, double* J_out, void* stream) {
+  if (!c || !psi0 || !grad_psi0 || !grad_V || !J_out) return fail(ABC_EINVAL, "null argument");
+  if (n_steps < 0) return fail(ABC_EINVAL, "n_steps must be >= 0");
+  if (objective != ABC_OBJ_PROB && objective != ABC_OBJ_ENERGY) return fail(ABC_EINVAL, "unknown objective");
+  const abc_params& p = c->p;
+  if (p.dtype != ABC_C128) return fail(ABC_ENOTSUP, "adjoint: complex128 only");
+  if (p.batch != 1 || p.meanfield != ABC_MF_NONE) return fail(ABC_ENOTSUP, "adjoint: one orbital, no mean field");
+  if ((p.order == ABC_ZEROTH || p.order == ABC_FIRST) && p.form != ABC_FORM_FACES)
+    return fail(ABC_ENOTSUP, "adjoint: face form only");
+  if (p.order == ABC_FIRST && p.radius != 1) return fail(ABC_ENOTSUP, "adjoint: first order needs R = 1");
+  if (!c->adjoint_ready) {
+    abc_status st = build_adjoint(c);
+    if (st != ABC_OK) return st;
+  }
+  abc_adjoint_args a{psi0, V, n_steps, ckpt_stride, objective, grad_psi0, grad_V, J_out};
+  std::string err;
+  abc_status st = run_adjoint(c->L, c->La, c->S, a, static_cast<hipStream_t>(stream), err);
+  if (st != ABC_OK) return fail(st, err);
+  return ABC_OK;
 }
 
 abc_status abc_diagnostics(abc_ctx* c, const void* psi, const void* aux, const void* V, double* out, void* stream) {

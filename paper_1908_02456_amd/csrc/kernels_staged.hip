@@ -494,7 +494,7 @@ inline unsigned nblocks(long long n) { return (unsigned)((n + kBlock - 1) / kBlo
 
 template <typename T, int R, bool PER>
 hipError_t step_staged_t(const abc_launch& L, const abc_scratch& S, void* psi_v, double2* aux,
-                         const void* V_v, int n_steps, hipStream_t st, abc_timer* tm) {
+                         const void* V_v, int n_steps, hipStream_t st, abc_timer* tm, void* const* keep) {
   static const char* kStageLabel[5] = {"", "stage_1", "stage_2", "stage_3", "stage_4"};
   static const char* kBoundLabel[5] = {"", "boundary_1", "boundary_2", "boundary_3", "boundary_4"};
   using C = typename cpx<T>::t;
@@ -540,7 +540,7 @@ hipError_t step_staged_t(const abc_launch& L, const abc_scratch& S, void* psi_v,
         if (box) bsrc = s_for_stage; else fsrc = s_for_stage;
         if (first) gcur = gnext;
       }
-      C* yout = (k == 4) ? nullptr : y[(k - 1) & 1];
+      C* yout = (k == 4) ? nullptr : (keep ? static_cast<C*>(keep[k - 1]) : y[(k - 1) & 1]);
       abc_launch_kernel(tm, kStageLabel[k], stage_kernel<T, R, PER>, dim3(nblocks(nel)), dim3(kBlock), st, ycur,
                         yout, acc, psi, Vuse, fsrc, bsrc, L.point_gamma, g, sc, coef, mode);
       ycur = yout;
@@ -576,12 +576,12 @@ hipError_t diag_t(const abc_launch& L, const abc_scratch& S, const void* psi, co
 
 template <typename T>
 hipError_t dispatch_step(const abc_launch& L, const abc_scratch& S, void* psi, double2* aux, const void* V,
-                         int n, hipStream_t st, abc_timer* tm) {
+                         int n, hipStream_t st, abc_timer* tm, void* const* keep) {
   const bool per = L.periodic != 0;
   switch (L.g.R) {
-    case 1: return per ? step_staged_t<T, 1, true>(L, S, psi, aux, V, n, st, tm) : step_staged_t<T, 1, false>(L, S, psi, aux, V, n, st, tm);
-    case 2: return per ? step_staged_t<T, 2, true>(L, S, psi, aux, V, n, st, tm) : step_staged_t<T, 2, false>(L, S, psi, aux, V, n, st, tm);
-    case 3: return per ? step_staged_t<T, 3, true>(L, S, psi, aux, V, n, st, tm) : step_staged_t<T, 3, false>(L, S, psi, aux, V, n, st, tm);
+    case 1: return per ? step_staged_t<T, 1, true>(L, S, psi, aux, V, n, st, tm, keep) : step_staged_t<T, 1, false>(L, S, psi, aux, V, n, st, tm, keep);
+    case 2: return per ? step_staged_t<T, 2, true>(L, S, psi, aux, V, n, st, tm, keep) : step_staged_t<T, 2, false>(L, S, psi, aux, V, n, st, tm, keep);
+    case 3: return per ? step_staged_t<T, 3, true>(L, S, psi, aux, V, n, st, tm, keep) : step_staged_t<T, 3, false>(L, S, psi, aux, V, n, st, tm, keep);
   }
   return hipErrorInvalidValue;
 }
@@ -601,9 +601,9 @@ hipError_t dispatch_diag(const abc_launch& L, const abc_scratch& S, const void* 
 }  // namespace
 
 hipError_t launch_step_staged(const abc_launch& L, const abc_scratch& S, void* psi, double2* aux, const void* V,
-                              int n_steps, hipStream_t st, abc_timer* tm) {
-  if (L.dtype == ABC_C64) return dispatch_step<float>(L, S, psi, aux, V, n_steps, st, tm);
-  return dispatch_step<double>(L, S, psi, aux, V, n_steps, st, tm);
+                              int n_steps, hipStream_t st, abc_timer* tm, void* const* keep) {
+  if (L.dtype == ABC_C64) return dispatch_step<float>(L, S, psi, aux, V, n_steps, st, tm, keep);
+  return dispatch_step<double>(L, S, psi, aux, V, n_steps, st, tm, keep);
 }
 
 hipError_t launch_diagnostics(const abc_launch& L, const abc_scratch& S, const void* psi, const double2* aux,

@@ -128,6 +128,23 @@ class Solver:
                                             ctypes.cast(ms, ctypes.c_void_p), cap, ctypes.byref(k)))
         return [(self._lib.abc_launch_label(self._ctx, j).decode(), ms[j]) for j in range(min(k.value, cap))]
 
+    def adjoint(self, psi0, V=None, n_steps: int = 1, objective: str = "prob", ckpt_stride: int = 0,
+                stream=None):
+        """Reverse-mode gradient of J(psi_N) after n_steps from (psi0, f = 0).
+
+        Returns (J, grad_psi0, grad_V) with grad_psi0 = dJ/dRe psi0 + i dJ/dIm psi0
+        (complex128, psi0's shape) and grad_V = dJ/dV (float64, the box shape).
+        objective: "prob" (h^3 sum |psi_N|^2) or "energy" (h^3 Re <psi_N, H psi_N>)."""
+        self._check_psi(psi0)
+        vp = self._check_V(V)
+        gpsi = torch.empty_like(psi0)
+        gV = torch.empty(self.shape, dtype=torch.float64, device=psi0.device)
+        J = ctypes.c_double(0.0)
+        _lib.check(self._lib.abc_adjoint(self._ctx, psi0.data_ptr(), vp, int(n_steps), int(ckpt_stride),
+                                         _lib.OBJECTIVES[objective], gpsi.data_ptr(), gV.data_ptr(),
+                                         ctypes.byref(J), _stream_handle(stream)))
+        return J.value, gpsi, gV
+
     def diagnostics(self, psi, aux=None, V=None, out: Optional[torch.Tensor] = None, stream=None):
         """Tensor of 3*batch+1 float64: norm, Lyapunov W, energy per orbital, interaction energy."""
         self._check_psi(psi)

@@ -170,3 +170,13 @@ def well_packet(n=128, h=0.2, steps=2000, dt=0.002, seed=2, radius=1, s1=1.0,
     V = gaussian_well(shape, h, 5.0)
     return Workload("well_packet_%d" % n, n, h, dt, steps, "first", "faces", radius=radius,
                     s1=s1, window=window, psi0=psi0, V=V)
+
+
+def adjoint_packet(n=96, h=0.2, steps=500, dt=0.002, s1=1.0, window=0):
+    """Adjoint workload parameters: well amplitude 5 at the origin, packet
+    centred at x = 4 with k = (3, 0, 0) heading for the +x face; first order.
+    Returns a dict of the scalar parameters (the fields are built from them,
+    so that gradients can flow back to them)."""
+    return {"n": n, "h": h, "steps": steps, "dt": dt, "s1": s1, "window": window,
+            "amplitude": 5.0, "well_center": (0.0, 0.0, 0.0), "packet_center": (4.0, 0.0, 0.0),
+            "k": (3.0, 0.0, 0.0)}
