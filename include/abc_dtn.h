@@ -165,6 +165,44 @@ abc_status abc_adjoint(abc_ctx* ctx, const void* psi0, const void* V,
                        void* grad_psi0, double* grad_V, double* J_out,
                        void* stream);
 
+/* Tile-depth tuner for the fused path: times a few steps with each tile depth
+ * (4, 8 or 16 z-planes per tile, as the box and order allow) on the given
+ * buffers and keeps the fastest for later abc_step calls; *tz_out (may be
+ * NULL) receives it (0 on the staged path, which has nothing to tune).  The
+ * state is restored afterwards; the call allocates temporary copies of psi
+ * and aux and synchronises the stream. */
+abc_status abc_tune(abc_ctx* ctx, void* psi, void* aux, const void* V,
+                    void* stream, int* tz_out);
+
+/* Batches of independent boxes (uneven sizes, mixed orders and precisions).
+ * abc_setup_batch sets up n instances from ps[0..n-1] (each as abc_setup).
+ * Instances that run on the fused path are grouped by (order, precision);
+ * every group is stepped by one descriptor-driven launch per half step over
+ * the concatenated tiles of all its boxes, with one tile depth per group
+ * (abc_tune_batch picks it by timing).  Other instances are stepped one by
+ * one with abc_step.  abc_step_batch advances instance i's psi[i] (and
+ * aux[i], first order; V[i] may be NULL, V itself may be NULL for V = 0) by
+ * n_steps on the stream; with ABC_BATCH_GRAPH in flags the whole call is
+ * captured once into a HIP graph per (buffers, n_steps, stream), which later
+ * calls with the same arguments replay (the stream must not be the default
+ * stream).  Descriptor uploads are staged in pinned host memory; a call may
+ * wait for the previous call's upload to complete.  Errors as abc_setup /
+ * abc_step; setup errors name the instance. */
+typedef struct abc_batch abc_batch;
+enum { ABC_BATCH_GRAPH = 1 };
+abc_status abc_setup_batch(const abc_params* ps, int n, abc_batch** out);
+abc_status abc_step_batch(abc_batch* b, void* const* psi, void* const* aux,
+                          const void* const* V, int n_steps, int flags,
+                          void* stream);
+abc_status abc_tune_batch(abc_batch* b, void* const* psi, void* const* aux,
+                          const void* const* V, void* stream);
+/* aux elements of instance i (as abc_aux_elems), 0 if out of range */
+size_t abc_batch_aux_elems(const abc_batch* b, int i);
+/* number of descriptor-driven launch groups, and the tile depth of one */
+int abc_batch_launch_groups(const abc_batch* b);
+int abc_batch_tile_depth(const abc_batch* b, int group);
+void abc_destroy_batch(abc_batch* b);
+
 /* FP64 diagnostics of a state, written to device memory out (3*batch + 1
  * doubles): [0, batch) norm h^3 sum |psi_j|^2; [batch, 2 batch) Lyapunov
  * functional h^3 (psi_j^* psi_j + f_j^* Q f_j) (Sec. 3, zeroth- and

@@ -11,6 +11,7 @@ LIB_PATH = os.path.join(HERE, "libabc_dtn.so")
 ABC_OK, ABC_EINVAL, ABC_ENOMEM, ABC_EDEVICE, ABC_EUNSTABLE, ABC_ENOTSUP = 0, -1, -2, -3, -4, -5
 STATUS_NAMES = {0: "ABC_OK", -1: "ABC_EINVAL", -2: "ABC_ENOMEM", -3: "ABC_EDEVICE",
                 -4: "ABC_EUNSTABLE", -5: "ABC_ENOTSUP"}
+ABC_BATCH_GRAPH = 1
 ORDERS = {"dirichlet": 0, "periodic": 1, "zeroth": 2, "first": 3}
 FORMS = {"box": 0, "faces": 1}
 DTYPES = {"c128": 0, "c64": 1}
@@ -19,7 +20,9 @@ OBJECTIVES = {"prob": 0, "energy": 1}
 
 EXPORTED = ["abc_params_default", "abc_setup", "abc_step", "abc_diagnostics", "abc_aux_elems",
             "abc_export", "abc_path", "abc_device_bytes", "abc_last_error", "abc_destroy",
-            "abc_step_timed", "abc_launch_label", "abc_adjoint"]
+            "abc_step_timed", "abc_launch_label", "abc_adjoint", "abc_tune", "abc_setup_batch",
+            "abc_step_batch", "abc_tune_batch", "abc_batch_aux_elems", "abc_batch_launch_groups",
+            "abc_batch_tile_depth", "abc_destroy_batch"]
 
 
 class AbcParams(ctypes.Structure):
@@ -68,6 +71,22 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.abc_adjoint.argtypes = [vp, vp, vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, vp,
                                 ctypes.POINTER(ctypes.c_double), vp]
     lib.abc_adjoint.restype = ctypes.c_int
+    lib.abc_tune.argtypes = [vp, vp, vp, vp, vp, ctypes.POINTER(ctypes.c_int)]
+    lib.abc_tune.restype = ctypes.c_int
+    lib.abc_setup_batch.argtypes = [P, ctypes.c_int, ctypes.POINTER(vp)]
+    lib.abc_setup_batch.restype = ctypes.c_int
+    lib.abc_step_batch.argtypes = [vp, vp, vp, vp, ctypes.c_int, ctypes.c_int, vp]
+    lib.abc_step_batch.restype = ctypes.c_int
+    lib.abc_tune_batch.argtypes = [vp, vp, vp, vp, vp]
+    lib.abc_tune_batch.restype = ctypes.c_int
+    lib.abc_batch_aux_elems.argtypes = [vp, ctypes.c_int]
+    lib.abc_batch_aux_elems.restype = ctypes.c_size_t
+    lib.abc_batch_launch_groups.argtypes = [vp]
+    lib.abc_batch_launch_groups.restype = ctypes.c_int
+    lib.abc_batch_tile_depth.argtypes = [vp, ctypes.c_int]
+    lib.abc_batch_tile_depth.restype = ctypes.c_int
+    lib.abc_destroy_batch.argtypes = [vp]
+    lib.abc_destroy_batch.restype = None
     lib.abc_diagnostics.argtypes = [vp, vp, vp, vp, vp, vp]
     lib.abc_diagnostics.restype = ctypes.c_int
     lib.abc_aux_elems.argtypes = [vp]

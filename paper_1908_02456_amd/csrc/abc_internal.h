@@ -74,6 +74,7 @@ struct abc_launch {
   double2 q_loc[abc::kMaxR * abc::kMaxR];
   double2 fused_m0, fused_b0;  // window-0 face operator value (host copy)
   int fused_stages;            // 4: one launch per step; 2: two launches
+  int fused_tz;                // planes per tile of the two-stage kernel (4, 8, 16)
   // box form
   const double2* box_mat;
   const double2* box_q;       // Lyapunov weight (H_gs H_gs^T)^{-1}, n x n

@@ -400,3 +400,340 @@ abc_status abc_export(const abc_ctx* c, int which, void* host_out, size_t n) {
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Tile-depth tuner and batches of uneven boxes
+// ---------------------------------------------------------------------------
+
+namespace {
+
+// mean milliseconds per step of `run(n)` over a few steps, after a warm-up
+template <typename F>
+abc_status time_steps(F run, hipStream_t st, float* ms_out) {
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return fail(ABC_EDEVICE, "hipEventCreate failed");
+  if (hipEventCreate(&e1) != hipSuccess) {
+    hipEventDestroy(e0);
+    return fail(ABC_EDEVICE, "hipEventCreate failed");
+  }
+  hipError_t e = run(2);
+  if (e == hipSuccess) e = hipEventRecord(e0, st);
+  if (e == hipSuccess) e = run(6);
+  if (e == hipSuccess) e = hipEventRecord(e1, st);
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
+  float ms = 0;
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (e != hipSuccess) return fail(ABC_EDEVICE, std::string("tuner timing: ") + hipGetErrorString(e));
+  *ms_out = ms / 6;
+  return ABC_OK;
+}
+
+// saved copies of states advanced by the tuner, restored afterwards
+struct Saved {
+  std::vector<std::pair<void*, void*>> items;  // (user, copy)
+  std::vector<size_t> bytes;
+  ~Saved() {
+    for (auto& it : items) (void)hipFree(it.second);
+  }
+  abc_status save(void* p, size_t n, hipStream_t st) {
+    if (!p || !n) return ABC_OK;
+    void* c = nullptr;
+    if (hipMalloc(&c, n) != hipSuccess) return fail(ABC_ENOMEM, "tuner: hipMalloc of a state copy failed");
+    items.push_back({p, c});
+    bytes.push_back(n);
+    if (hipMemcpyAsync(c, p, n, hipMemcpyDeviceToDevice, st) != hipSuccess)
+      return fail(ABC_EDEVICE, "tuner: state copy failed");
+    return ABC_OK;
+  }
+  abc_status restore(hipStream_t st) {
+    for (size_t i = 0; i < items.size(); ++i)
+      if (hipMemcpyAsync(items[i].first, items[i].second, bytes[i], hipMemcpyDeviceToDevice, st) != hipSuccess)
+        return fail(ABC_EDEVICE, "tuner: state restore failed");
+    if (hipStreamSynchronize(st) != hipSuccess) return fail(ABC_EDEVICE, "tuner: synchronise failed");
+    return ABC_OK;
+  }
+};
+
+size_t psi_bytes(const abc_ctx* c) {
+  return (size_t)c->L.g.npts * c->p.batch * (c->p.dtype == ABC_C64 ? 8 : 16);
+}
+
+}  // namespace
+
+abc_status abc_tune(abc_ctx* c, void* psi, void* aux, const void* V, void* stream, int* tz_out) {
+  if (!c || !psi) return fail(ABC_EINVAL, "null argument");
+  if (c->p.order == ABC_FIRST && !aux) return fail(ABC_EINVAL, "first order needs the aux buffer");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (!c->use_fused || c->L.fused_stages != 2) {
+    if (tz_out) *tz_out = c->use_fused ? c->L.fused_tz : 0;
+    return ABC_OK;
+  }
+  Saved sv;
+  abc_status s = sv.save(psi, psi_bytes(c), st);
+  if (s == ABC_OK) s = sv.save(aux, c->aux_elems * sizeof(double2), st);
+  if (s != ABC_OK) return s;
+  int best = c->L.fused_tz;
+  float best_ms = 1e30f;
+  for (int tz : {4, 8, 16}) {
+    if (!fused_tz_valid(c->L, tz)) continue;
+    c->L.fused_tz = tz;
+    float ms = 0;
+    s = time_steps([&](int n) { return launch_step_fused(c->L, c->S, psi, static_cast<double2*>(aux), V, n, st); },
+                   st, &ms);
+    if (s != ABC_OK) return s;
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = tz;
+    }
+  }
+  c->L.fused_tz = best;
+  if (tz_out) *tz_out = best;
+  return sv.restore(st);
+}
+
+struct abc_batch {
+  std::vector<abc_ctx*> inst;
+  struct Group {
+    int order = 0, dtype = 0, tz = 8;
+    std::vector<int> idx;
+    void* host = nullptr;  // pinned descriptor staging
+    void* dev = nullptr;   // descriptors of eager calls
+    void* gdev = nullptr;  // descriptors baked into the cached graph
+    hipEvent_t copied = nullptr;
+    bool pending = false;
+  };
+  std::vector<Group> groups;
+  std::vector<int> fallback;  // instances stepped through abc_step one by one
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::vector<const void*> key;
+  int key_n = -1;
+  hipStream_t key_stream = nullptr;
+};
+
+void abc_destroy_batch(abc_batch* b) {
+  if (!b) return;
+  if (b->exec) hipGraphExecDestroy(b->exec);
+  if (b->graph) hipGraphDestroy(b->graph);
+  for (auto& g : b->groups) {
+    if (g.copied) hipEventDestroy(g.copied);
+    if (g.host) hipHostFree(g.host);
+    if (g.dev) hipFree(g.dev);
+    if (g.gdev) hipFree(g.gdev);
+  }
+  for (abc_ctx* c : b->inst) abc_destroy(c);
+  delete b;
+}
+
+abc_status abc_setup_batch(const abc_params* ps, int n, abc_batch** out) {
+  g_last_error.clear();
+  if (!ps || !out || n < 1) return fail(ABC_EINVAL, "null argument or empty batch");
+  *out = nullptr;
+  abc_batch* b = new abc_batch();
+  for (int i = 0; i < n; ++i) {
+    abc_ctx* c = nullptr;
+    abc_status st = abc_setup(&ps[i], &c);
+    if (st != ABC_OK) {
+      const std::string msg = "instance " + std::to_string(i) + ": " + g_last_error;
+      abc_destroy_batch(b);
+      return fail(st, msg);
+    }
+    b->inst.push_back(c);
+    if (!(c->use_fused && c->L.fused_stages == 2)) {
+      b->fallback.push_back(i);
+      continue;
+    }
+    abc_batch::Group* g = nullptr;
+    for (auto& gg : b->groups)
+      if (gg.order == c->p.order && gg.dtype == c->p.dtype) g = &gg;
+    if (!g) {
+      b->groups.emplace_back();
+      g = &b->groups.back();
+      g->order = c->p.order;
+      g->dtype = c->p.dtype;
+    }
+    g->idx.push_back(i);
+  }
+  for (auto& g : b->groups) {
+    for (int i : g.idx) g.tz = std::min(g.tz, fused_max_tz(g.order, b->inst[i]->p.nz));
+    for (int i : g.idx) b->inst[i]->L.fused_tz = g.tz;
+    const size_t bytes = fused_batch_desc_bytes((int)g.idx.size());
+    if (hipHostMalloc(&g.host, bytes) != hipSuccess || hipMalloc(&g.dev, bytes) != hipSuccess ||
+        hipMalloc(&g.gdev, bytes) != hipSuccess || hipEventCreate(&g.copied) != hipSuccess) {
+      abc_destroy_batch(b);
+      return fail(ABC_ENOMEM, "batch descriptor buffers");
+    }
+  }
+  *out = b;
+  return ABC_OK;
+}
+
+size_t abc_batch_aux_elems(const abc_batch* b, int i) {
+  if (!b || i < 0 || i >= (int)b->inst.size()) return 0;
+  return b->inst[i]->aux_elems;
+}
+
+int abc_batch_launch_groups(const abc_batch* b) { return b ? (int)b->groups.size() : 0; }
+
+int abc_batch_tile_depth(const abc_batch* b, int group) {
+  if (!b || group < 0 || group >= (int)b->groups.size()) return 0;
+  return b->groups[group].tz;
+}
+
+namespace {
+
+std::vector<FusedMember> members(abc_batch* b, const abc_batch::Group& g, void* const* psi, void* const* aux,
+                                 const void* const* V) {
+  std::vector<FusedMember> m;
+  for (int i : g.idx)
+    m.push_back({&b->inst[i]->L, &b->inst[i]->S, psi[i], aux ? static_cast<double2*>(aux[i]) : nullptr,
+                 V ? V[i] : nullptr});
+  return m;
+}
+
+abc_status check_batch_args(abc_batch* b, void* const* psi, void* const* aux) {
+  if (!b || !psi) return fail(ABC_EINVAL, "null argument");
+  for (size_t i = 0; i < b->inst.size(); ++i) {
+    if (!psi[i]) return fail(ABC_EINVAL, "null psi for instance " + std::to_string(i));
+    if (b->inst[i]->p.order == ABC_FIRST && (!aux || !aux[i]))
+      return fail(ABC_EINVAL, "first-order instance " + std::to_string(i) + " needs its aux buffer");
+  }
+  return ABC_OK;
+}
+
+// enqueue every launch of an n-step batch call; descriptors are already in
+// `use_graph ? gdev : dev`
+abc_status enqueue_batch(abc_batch* b, void* const* psi, void* const* aux, const void* const* V, int n,
+                         hipStream_t st, bool use_graph, const std::vector<int>& totals) {
+  for (size_t k = 0; k < b->groups.size(); ++k) {
+    auto& g = b->groups[k];
+    hipError_t e = launch_batch_fused(members(b, g, psi, aux, V), g.tz, use_graph ? g.gdev : g.dev, totals[k], n, st,
+                                      nullptr);
+    if (e != hipSuccess) return fail(ABC_EDEVICE, std::string("batch launch: ") + hipGetErrorString(e));
+  }
+  for (int i : b->fallback) {
+    abc_status s = abc_step(b->inst[i], psi[i], aux ? aux[i] : nullptr, V ? V[i] : nullptr, n, st);
+    if (s != ABC_OK) return s;
+  }
+  return ABC_OK;
+}
+
+}  // namespace
+
+abc_status abc_step_batch(abc_batch* b, void* const* psi, void* const* aux, const void* const* V, int n_steps,
+                          int flags, void* stream) {
+  abc_status s = check_batch_args(b, psi, aux);
+  if (s != ABC_OK) return s;
+  if (n_steps < 0) return fail(ABC_EINVAL, "n_steps must be >= 0");
+  if (n_steps == 0) return ABC_OK;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const bool graph = (flags & ABC_BATCH_GRAPH) != 0;
+  if (graph && !st) return fail(ABC_EINVAL, "graph capture needs a non-default stream");
+  std::vector<int> totals(b->groups.size());
+  if (!graph) {
+    for (size_t k = 0; k < b->groups.size(); ++k) {
+      auto& g = b->groups[k];
+      // the staging buffer is reused once its previous copy has completed
+      if (g.pending && hipEventSynchronize(g.copied) != hipSuccess) return fail(ABC_EDEVICE, "event wait failed");
+      totals[k] = fused_batch_build(members(b, g, psi, aux, V), g.host, n_steps);
+      if (hipMemcpyAsync(g.dev, g.host, fused_batch_desc_bytes((int)g.idx.size()), hipMemcpyHostToDevice, st) !=
+              hipSuccess ||
+          hipEventRecord(g.copied, st) != hipSuccess)
+        return fail(ABC_EDEVICE, "descriptor upload failed");
+      g.pending = true;
+    }
+    return enqueue_batch(b, psi, aux, V, n_steps, st, false, totals);
+  }
+  // graph mode: one captured graph per (buffers, n_steps, stream), replayed
+  std::vector<const void*> key;
+  for (size_t i = 0; i < b->inst.size(); ++i) {
+    key.push_back(psi[i]);
+    key.push_back(aux ? aux[i] : nullptr);
+    key.push_back(V ? V[i] : nullptr);
+  }
+  if (!(b->exec && key == b->key && n_steps == b->key_n && st == b->key_stream)) {
+    if (b->exec) hipGraphExecDestroy(b->exec);
+    if (b->graph) hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+    for (size_t k = 0; k < b->groups.size(); ++k) {
+      auto& g = b->groups[k];
+      if (g.pending && hipEventSynchronize(g.copied) != hipSuccess) return fail(ABC_EDEVICE, "event wait failed");
+      g.pending = false;
+      totals[k] = fused_batch_build(members(b, g, psi, aux, V), g.host, n_steps);
+      if (hipMemcpy(g.gdev, g.host, fused_batch_desc_bytes((int)g.idx.size()), hipMemcpyHostToDevice) != hipSuccess)
+        return fail(ABC_EDEVICE, "descriptor upload failed");
+    }
+    if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess)
+      return fail(ABC_EDEVICE, "hipStreamBeginCapture failed");
+    s = enqueue_batch(b, psi, aux, V, n_steps, st, true, totals);
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(st, &graph);
+    if (s != ABC_OK) {
+      if (graph) hipGraphDestroy(graph);
+      return s;
+    }
+    if (e != hipSuccess || !graph) return fail(ABC_EDEVICE, "hipStreamEndCapture failed");
+    if (hipGraphInstantiate(&b->exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+      hipGraphDestroy(graph);
+      return fail(ABC_EDEVICE, "hipGraphInstantiate failed");
+    }
+    b->graph = graph;
+    b->key = key;
+    b->key_n = n_steps;
+    b->key_stream = st;
+  }
+  if (hipGraphLaunch(b->exec, st) != hipSuccess) return fail(ABC_EDEVICE, "hipGraphLaunch failed");
+  return ABC_OK;
+}
+
+abc_status abc_tune_batch(abc_batch* b, void* const* psi, void* const* aux, const void* const* V, void* stream) {
+  abc_status s = check_batch_args(b, psi, aux);
+  if (s != ABC_OK) return s;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  Saved sv;
+  for (size_t i = 0; i < b->inst.size(); ++i) {
+    s = sv.save(psi[i], psi_bytes(b->inst[i]), st);
+    if (s == ABC_OK && aux) s = sv.save(aux[i], b->inst[i]->aux_elems * sizeof(double2), st);
+    if (s != ABC_OK) return s;
+  }
+  for (auto& g : b->groups) {
+    int max_tz = 16;
+    for (int i : g.idx) max_tz = std::min(max_tz, fused_max_tz(g.order, b->inst[i]->p.nz));
+    const auto m = members(b, g, psi, aux, V);
+    int best = g.tz;
+    float best_ms = 1e30f;
+    for (int tz : {4, 8, 16}) {
+      if (tz > max_tz) continue;
+      for (int i : g.idx) b->inst[i]->L.fused_tz = tz;
+      float ms = 0;
+      s = time_steps(
+          [&](int n) {
+            if (g.pending && hipEventSynchronize(g.copied) != hipSuccess) return hipErrorUnknown;
+            const int total = fused_batch_build(m, g.host, n);
+            hipError_t e = hipMemcpyAsync(g.dev, g.host, fused_batch_desc_bytes((int)g.idx.size()),
+                                          hipMemcpyHostToDevice, st);
+            if (e == hipSuccess) e = hipEventRecord(g.copied, st);
+            g.pending = true;
+            if (e == hipSuccess) e = launch_batch_fused(m, tz, g.dev, total, n, st, nullptr);
+            return e;
+          },
+          st, &ms);
+      if (s != ABC_OK) return s;
+      if (ms < best_ms) {
+        best_ms = ms;
+        best = tz;
+      }
+    }
+    g.tz = best;
+    for (int i : g.idx) b->inst[i]->L.fused_tz = best;
+  }
+  // a cached graph was captured with the old depths
+  if (b->exec) hipGraphExecDestroy(b->exec);
+  if (b->graph) hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
+  return sv.restore(st);
+}

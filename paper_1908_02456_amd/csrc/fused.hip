@@ -51,6 +51,7 @@ template <> struct Tile<double> { static constexpr int TY = 4, TZ = 16; };
 
 struct FusedArgs {
   int nx, ny, nz;
+  int ntx, xw;  // x chunks and output columns per chunk (two-stage kernel)
   int nty, ntiles, tiles_per_xcd;
   double diag, off;
   double coef[5];
@@ -221,16 +222,36 @@ __global__ void __launch_bounds__(64 * (Tile<T>::TY + 2 * kHalo)) fused_step_ker
 //   half A:  u3 = psi + (dt/4) L psi,  u2 = psi + (dt/3) L u3   -> u2
 //   half B:  u1 = psi + (dt/2) L u2,   psi' = psi + dt L u1      -> psi'
 // w is the field the first stage differentiates (psi in A, u2 in B), base the
-// Horner base psi (the same buffer in A).  Tiles 8 x 8, 12 waves.
-constexpr int kTY2 = 8, kTZ2 = 8, kHalo2 = 2;
+// Horner base psi (the same buffer in A).  Tiles are TY = 8 rows by TZ
+// planes (TZ in {4, 8, 16}, chosen by the tuner) by one x chunk: the whole
+// row when nx <= 128, else chunks of at most 124 output columns loaded with
+// a two-column halo on each side (the chunk edges see zero neighbours, which
+// only corrupts the halo columns, never an output).  12 waves.
+constexpr int kTY2 = 8, kHalo2 = 2, kChunk = kCols - 2 * kHalo2;
 
-template <typename T, int ORDER, bool SAME_BASE>
-__global__ void __launch_bounds__(64 * (kTY2 + 2 * kHalo2)) fused2_kernel(
-    const typename cpx<T>::t* __restrict__ w_in, const typename cpx<T>::t* __restrict__ base_in,
-    typename cpx<T>::t* __restrict__ out, const T* __restrict__ V, FusedArgs a, double cA, double cB,
-    const double2* __restrict__ av, const double2* __restrict__ fb, double2* __restrict__ aux_out) {
+// one box of a (possibly batched) two-stage launch
+struct Box2 {
+  FusedArgs a;
+  const void* w;
+  const void* base;
+  void* out;
+  const void* V;
+  const double2* av;
+  const double2* fb;
+  double2* aux_out;
+  int tile_begin;  // first global tile of this box in the launch
+  int pad;
+};
+
+template <typename T, int ORDER, bool SAME_BASE, int TZ>
+__device__ __forceinline__ void fused2_body(const typename cpx<T>::t* __restrict__ w_in,
+                                            const typename cpx<T>::t* __restrict__ base_in,
+                                            typename cpx<T>::t* __restrict__ out, const T* __restrict__ V,
+                                            const FusedArgs& a, double cA, double cB,
+                                            const double2* __restrict__ av, const double2* __restrict__ fb,
+                                            double2* __restrict__ aux_out, int tile) {
   using C = typename cpx<T>::t;
-  constexpr int TY = kTY2, TZ = kTZ2, H = kHalo2;
+  constexpr int TY = kTY2, H = kHalo2;
   constexpr int ROWS = TY + 2 * H;
   constexpr int NT = 64 * ROWS;
   constexpr int ITERS = TZ + 2 * H;
@@ -238,9 +259,8 @@ __global__ void __launch_bounds__(64 * (kTY2 + 2 * kHalo2)) fused2_kernel(
 
   const int lane = threadIdx.x & 63;
   const int r = threadIdx.x >> 6;
-  int tile = blockIdx.x;
-  if (a.tiles_per_xcd) tile = (blockIdx.x & 7) * a.tiles_per_xcd + (blockIdx.x >> 3);
-  const int ty = tile % a.nty, tz = tile / a.nty;
+  const int tx = tile % a.ntx, rest = tile / a.ntx;
+  const int ty = rest % a.nty, tz = rest / a.nty;
   const int y0 = ty * TY, z0 = tz * TZ;
   const int nx = a.nx, ny = a.ny, nz = a.nz;
   const int sz = nx * ny;
@@ -248,6 +268,9 @@ __global__ void __launch_bounds__(64 * (kTY2 + 2 * kHalo2)) fused2_kernel(
   const bool row_in = y >= 0 && y < ny;
   const int ybase = y * nx;
   const bool own_row = r >= H && r < H + TY && row_in;
+  // columns: x = xb + 2 lane + c; owned outputs in [xo, xe)
+  const int xo = tx * a.xw, xe = min(xo + a.xw, nx);
+  const int xb = a.ntx == 1 ? 0 : xo - H;
 
   for (int i = threadIdx.x; i < 2 * ROWS * 2 * 66; i += NT) (&plane[0][0][0][0])[i] = czero<C>();
 
@@ -271,9 +294,9 @@ __global__ void __launch_bounds__(64 * (kTY2 + 2 * kHalo2)) fused2_kernel(
     const bool ok = row_in && zz >= 0 && zz < nz;
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
-      const int x = 2 * lane + c;
-      const bool in = ok && x < nx;
-      const int idx = ok ? zz * sz + ybase + min(x, nx - 1) : 0;  // always a valid address
+      const int x = xb + 2 * lane + c;
+      const bool in = ok && x >= 0 && x < nx;
+      const int idx = ok ? zz * sz + ybase + min(max(x, 0), nx - 1) : 0;  // always a valid address
       const C wv = w_in[idx];
       pf[c] = in ? wv : czero<C>();
       if (!SAME_BASE) {
@@ -289,16 +312,17 @@ __global__ void __launch_bounds__(64 * (kTY2 + 2 * kHalo2)) fused2_kernel(
   // First order: the tile's face data (auxiliary input av and base fb) staged
   // in LDS once, for planes z0-1 .. z0+TZ and rows 1 .. ROWS-2 of the tile:
   // both x faces, and the tile's y-face row and z-face plane if it has them
-  // (at most one of each when ny, nz >= TY + 2).  Every thread issues all of
-  // its loads before storing any, so the staging costs one memory round trip,
-  // overlapped with the first plane fetch.
+  // (at most one of each when ny >= TY + 2 and nz >= TZ + 2), indexed by the
+  // chunk's local column.  Every thread issues all of its loads before
+  // storing any, so the staging costs one memory round trip, overlapped with
+  // the first plane fetch.
   constexpr int FP = TZ + 2, FR = ROWS - 2;
   constexpr int NX = ORDER == 3 ? 2 * 2 * FP * FR : 1;
   constexpr int NY = ORDER == 3 ? 2 * FP * kCols : 1;
   constexpr int NZ = ORDER == 3 ? 2 * FR * kCols : 1;
   __shared__ double2 fxs[NX];  // [arr][side][plane][row]
-  __shared__ double2 fys[NY];  // [arr][plane][x]
-  __shared__ double2 fzs[NZ];  // [arr][row][x]
+  __shared__ double2 fys[NY];  // [arr][plane][local column]
+  __shared__ double2 fzs[NZ];  // [arr][row][local column]
   int yface = -1, zface = -1;  // face index (2/3, 4/5) of the staged row / plane
   if (ORDER == 3) {
     const int ylo = y0 - H + 1, zlo = z0 - 1;
@@ -307,7 +331,6 @@ __global__ void __launch_bounds__(64 * (kTY2 + 2 * kHalo2)) fused2_kernel(
     if (zlo <= 0) zface = 4;
     else if (zlo <= nz - 1 && nz - 1 < zlo + FP) zface = 5;
     constexpr int KX = (NX + NT - 1) / NT, KY = (NY + NT - 1) / NT, KZ = (NZ + NT - 1) / NT;
-    const int ny_el = 2 * FP * nx, nz_el = 2 * FR * nx;
     double2 rx[KX], ry[KY], rz[KZ];
 #pragma unroll
     for (int j = 0; j < KX; ++j) {
@@ -320,18 +343,20 @@ __global__ void __launch_bounds__(64 * (kTY2 + 2 * kHalo2)) fused2_kernel(
 #pragma unroll
     for (int j = 0; j < KY; ++j) {
       const int i = threadIdx.x + j * NT;
-      const int xx = i % nx, pl = (i / nx) % FP, arr = i / (nx * FP);
-      const int zz = zlo + pl;
+      const int lx = i % kCols, pl = (i / kCols) % FP;
+      const int xx = xb + lx, zz = zlo + pl;
       ry[j] = make_double2(0, 0);
-      if (yface >= 0 && i < ny_el && zz >= 0 && zz < nz) ry[j] = (arr ? fb : av)[a.face_off[yface] + zz * nx + xx];
+      if (yface >= 0 && i < NY && xx >= 0 && xx < nx && zz >= 0 && zz < nz)
+        ry[j] = (i >= FP * kCols ? fb : av)[a.face_off[yface] + zz * nx + xx];
     }
 #pragma unroll
     for (int j = 0; j < KZ; ++j) {
       const int i = threadIdx.x + j * NT;
-      const int xx = i % nx, rr = (i / nx) % FR, arr = i / (nx * FR);
-      const int yy = ylo + rr;
+      const int lx = i % kCols, rr = (i / kCols) % FR;
+      const int xx = xb + lx, yy = ylo + rr;
       rz[j] = make_double2(0, 0);
-      if (zface >= 0 && i < nz_el && yy >= 0 && yy < ny) rz[j] = (arr ? fb : av)[a.face_off[zface] + yy * nx + xx];
+      if (zface >= 0 && i < NZ && xx >= 0 && xx < nx && yy >= 0 && yy < ny)
+        rz[j] = (i >= FR * kCols ? fb : av)[a.face_off[zface] + yy * nx + xx];
     }
 #pragma unroll
     for (int j = 0; j < KX; ++j) {
@@ -341,12 +366,12 @@ __global__ void __launch_bounds__(64 * (kTY2 + 2 * kHalo2)) fused2_kernel(
 #pragma unroll
     for (int j = 0; j < KY; ++j) {
       const int i = threadIdx.x + j * NT;
-      if (i < ny_el) fys[(i / (nx * FP) * FP + (i / nx) % FP) * kCols + i % nx] = ry[j];
+      if (i < NY) fys[i] = ry[j];
     }
 #pragma unroll
     for (int j = 0; j < KZ; ++j) {
       const int i = threadIdx.x + j * NT;
-      if (i < nz_el) fzs[(i / (nx * FR) * FR + (i / nx) % FR) * kCols + i % nx] = rz[j];
+      if (i < NZ) fzs[i] = rz[j];
     }
   }
   __syncthreads();
@@ -372,7 +397,8 @@ __global__ void __launch_bounds__(64 * (kTY2 + 2 * kHalo2)) fused2_kernel(
       C o[2];
 #pragma unroll
       for (int c = 0; c < 2; ++c) {
-        const int x = 2 * lane + c;
+        const int lx = 2 * lane + c, x = xb + lx;
+        const bool in = x >= 0 && x < nx;
         o[c] = czero<C>();
         if (!active) continue;
         const C cen = Yc[k - 1][c], bel = Yb[k - 1][c], abv = prev[c];
@@ -400,7 +426,7 @@ __global__ void __launch_bounds__(64 * (kTY2 + 2 * kHalo2)) fused2_kernel(
           // v_f = fb_f + cA (b av_f + a w) (stage 2), which also produces the
           // auxiliary output fb_f + cB (b v_f + a s1) at owned points
           const bool fx = x == 0 || x == nx - 1, fy = y == 0 || y == ny - 1, fz = zk == 0 || zk == nz - 1;
-          if ((fx || fy || fz) && x < nx) {
+          if ((fx || fy || fz) && in) {
             const int pl = zk - (z0 - 1), rr = r - 1;
             double sr = 0, si = 0;
             double2 aw = make_double2(0, 0), as1 = make_double2(0, 0);
@@ -408,7 +434,7 @@ __global__ void __launch_bounds__(64 * (kTY2 + 2 * kHalo2)) fused2_kernel(
               aw = cmul(a.a0, make_double2((double)wm2[c].x, (double)wm2[c].y));
               as1 = cmul(a.a0, make_double2((double)cen.x, (double)cen.y));
             }
-            const bool own = k == 2 && own_row && it >= 2 * H;
+            const bool own = k == 2 && own_row && it >= 2 * H && x >= xo && x < xe;
             // one face through the point: its auxiliary input g and base f0
             auto face = [&](const double2* lds_g, const double2* lds_f, int gi) {
               const double2 g = *lds_g;
@@ -433,15 +459,18 @@ __global__ void __launch_bounds__(64 * (kTY2 + 2 * kHalo2)) fused2_kernel(
                    a.face_off[side] + zk * ny + y);
             }
             if (fy)
-              face(&fys[(0 * FP + pl) * kCols + x], &fys[(1 * FP + pl) * kCols + x], a.face_off[yface] + zk * nx + x);
+              face(&fys[(0 * FP + pl) * kCols + lx], &fys[(1 * FP + pl) * kCols + lx],
+                   a.face_off[yface] + zk * nx + x);
             if (fz)
-              face(&fzs[(0 * FR + rr) * kCols + x], &fzs[(1 * FR + rr) * kCols + x], a.face_off[zface] + y * nx + x);
+              face(&fzs[(0 * FR + rr) * kCols + lx], &fzs[(1 * FR + rr) * kCols + lx],
+                   a.face_off[zface] + y * nx + x);
             hr += T(sr);
             hi += T(si);
           }
         }
-        o[c].x = x < nx ? b0.x + cf * hi : T(0);
-        o[c].y = x < nx ? b0.y - cf * hr : T(0);
+        // columns outside the box stay zero (they are x neighbours)
+        o[c].x = in ? b0.x + cf * hi : T(0);
+        o[c].y = in ? b0.y - cf * hr : T(0);
       }
 #pragma unroll
       for (int c = 0; c < 2; ++c) {
@@ -454,8 +483,8 @@ __global__ void __launch_bounds__(64 * (kTY2 + 2 * kHalo2)) fused2_kernel(
     const bool own_out = own_row && it >= 2 * H && z2 < nz;
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
-      const int x = 2 * lane + c;
-      if (own_out && x < nx) out[z2 * sz + ybase + x] = prev[c];
+      const int x = xb + 2 * lane + c;
+      if (own_out && x >= xo && x < xe) out[z2 * sz + ybase + x] = prev[c];
       Vd[1][c] = Vd[0][c];
       Vd[0][c] = vcur[c];
       if (!SAME_BASE) {
@@ -472,26 +501,99 @@ __global__ void __launch_bounds__(64 * (kTY2 + 2 * kHalo2)) fused2_kernel(
   }
 }
 
+// one box, arguments in the kernel argument segment
+template <typename T, int ORDER, bool SAME_BASE, int TZ>
+__global__ void __launch_bounds__(64 * (kTY2 + 2 * kHalo2)) fused2_kernel(
+    const typename cpx<T>::t* __restrict__ w_in, const typename cpx<T>::t* __restrict__ base_in,
+    typename cpx<T>::t* __restrict__ out, const T* __restrict__ V, FusedArgs a, double cA, double cB,
+    const double2* __restrict__ av, const double2* __restrict__ fb, double2* __restrict__ aux_out) {
+  int tile = blockIdx.x;
+  if (a.tiles_per_xcd) tile = (blockIdx.x & 7) * a.tiles_per_xcd + (blockIdx.x >> 3);
+  fused2_body<T, ORDER, SAME_BASE, TZ>(w_in, base_in, out, V, a, cA, cB, av, fb, aux_out, tile);
+}
+
+// many boxes in one launch: the grid is the concatenation of the boxes' tiles
+// (padded to a multiple of 8 for the XCD-aware order); each workgroup finds
+// its box by binary search over the boxes' first tiles
+template <typename T, int ORDER, bool SAME_BASE, int TZ>
+__global__ void __launch_bounds__(64 * (kTY2 + 2 * kHalo2)) fused2_batch_kernel(
+    const Box2* __restrict__ boxes, int nbox, int total_tiles, int half) {
+  using C = typename cpx<T>::t;
+  const int per_xcd = gridDim.x >> 3;
+  const int t = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+  if (t >= total_tiles) return;
+  int lo = 0, hi = nbox - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (boxes[mid].tile_begin <= t) lo = mid;
+    else hi = mid - 1;
+  }
+  const Box2& b = boxes[lo];
+  // Horner coefficients of the box's own time step: (dt/4, dt/3) or (dt/2, dt)
+  const double cA = half ? b.a.coef[2] : b.a.coef[4], cB = half ? b.a.coef[1] : b.a.coef[3];
+  fused2_body<T, ORDER, SAME_BASE, TZ>(static_cast<const C*>(b.w), static_cast<const C*>(b.base),
+                                       static_cast<C*>(b.out), static_cast<const T*>(b.V), b.a, cA, cB, b.av, b.fb,
+                                       b.aux_out, t - b.tile_begin);
+}
+
 template <typename T>
 FusedArgs make_args(const abc_launch& L, bool two) {
   FusedArgs a{};
   a.nx = L.g.nx;
   a.ny = L.g.ny;
   a.nz = L.g.nz;
-  const int TY = two ? kTY2 : Tile<T>::TY, TZ = two ? kTZ2 : Tile<T>::TZ;
+  const int TY = two ? kTY2 : Tile<T>::TY, TZ = two ? L.fused_tz : Tile<T>::TZ;
+  a.ntx = (two && a.nx > kCols) ? (a.nx + kChunk - 1) / kChunk : 1;
+  a.xw = (a.nx + a.ntx - 1) / a.ntx;
   a.nty = (a.ny + TY - 1) / TY;
   const int ntz = (a.nz + TZ - 1) / TZ;
-  a.ntiles = a.nty * ntz;
+  a.ntiles = a.ntx * a.nty * ntz;
   a.tiles_per_xcd = (a.ntiles % 8 == 0) ? a.ntiles / 8 : 0;
   const double s = 1.0 / (2.0 * L.h * L.h);
   a.diag = -3.0 * L.c[0] * s;
   a.off = -L.c[1] * s;
   for (int k = 1; k <= 4; ++k) a.coef[k] = L.dt / k;
   for (int f = 0; f < 7; ++f) a.face_off[f] = (int)L.g.face_off[f];
+  a.m0 = L.fused_m0;
+  a.b0 = L.fused_b0;
+  a.a0 = L.a_loc[0];
   return a;
 }
 
+// launch one two-stage kernel instance for a runtime tile depth
+template <typename T, int ORDER, bool SB, typename... A>
+void launch2(abc_timer* tm, const char* label, int tz, dim3 g, dim3 b, hipStream_t st, A... args) {
+  if constexpr (ORDER == 3) {
+    if (tz == 4) return abc_launch_kernel(tm, label, fused2_kernel<T, ORDER, SB, 4>, g, b, st, args...);
+    return abc_launch_kernel(tm, label, fused2_kernel<T, ORDER, SB, 8>, g, b, st, args...);
+  } else {
+    if (tz == 4) return abc_launch_kernel(tm, label, fused2_kernel<T, ORDER, SB, 4>, g, b, st, args...);
+    if (tz == 16) return abc_launch_kernel(tm, label, fused2_kernel<T, ORDER, SB, 16>, g, b, st, args...);
+    return abc_launch_kernel(tm, label, fused2_kernel<T, ORDER, SB, 8>, g, b, st, args...);
+  }
+}
+
+template <typename T, int ORDER, bool SB>
+void launch2_batch(abc_timer* tm, const char* label, int tz, dim3 g, hipStream_t st, const Box2* boxes, int nbox,
+                   int total, int half) {
+  const dim3 b(64 * (kTY2 + 2 * kHalo2));
+  if constexpr (ORDER == 3) {
+    if (tz == 4) return abc_launch_kernel(tm, label, fused2_batch_kernel<T, ORDER, SB, 4>, g, b, st, boxes, nbox, total, half);
+    return abc_launch_kernel(tm, label, fused2_batch_kernel<T, ORDER, SB, 8>, g, b, st, boxes, nbox, total, half);
+  } else {
+    if (tz == 4) return abc_launch_kernel(tm, label, fused2_batch_kernel<T, ORDER, SB, 4>, g, b, st, boxes, nbox, total, half);
+    if (tz == 16) return abc_launch_kernel(tm, label, fused2_batch_kernel<T, ORDER, SB, 16>, g, b, st, boxes, nbox, total, half);
+    return abc_launch_kernel(tm, label, fused2_batch_kernel<T, ORDER, SB, 8>, g, b, st, boxes, nbox, total, half);
+  }
+}
+
 }  // namespace
+
+int fused_max_tz(int order, int nz) {
+  // first order: one z-face plane per tile needs nz >= TZ + 2
+  if (order == ABC_FIRST) return nz >= 10 ? 8 : 4;
+  return 16;
+}
 
 bool fused_supported(const abc_params& p, std::string* why) {
   auto no = [&](const char* m) {
@@ -504,10 +606,9 @@ bool fused_supported(const abc_params& p, std::string* why) {
   if (p.order == ABC_PERIODIC) return no("periodic boxes use the staged path");
   if ((p.order == ABC_ZEROTH || p.order == ABC_FIRST) && (p.form != ABC_FORM_FACES || p.window != 0))
     return no("local (window 0) face operators only");
-  if (p.nx > kCols) return no("nx <= 128");
   if (p.nz < 5 || p.ny < 4 || p.nx < 4) return no("nx, ny >= 4 and nz >= 5");
-  if (p.order == ABC_FIRST && (p.ny < kTY2 + 2 || p.nz < kTZ2 + 2))
-    return no("first order: ny, nz >= 10 (one y-face row and one z-face plane per tile)");
+  if (p.order == ABC_FIRST && (p.ny < kTY2 + 2 || p.nz < 6))
+    return no("first order: ny >= 10 and nz >= 6 (one y-face row and one z-face plane per tile)");
   if ((long long)p.nx * p.ny * p.nz >= (1LL << 31)) return no("grid below 2^31 points");
   return true;
 }
@@ -518,16 +619,22 @@ abc_status fused_prepare(const abc_params& p, abc_launch& L, std::vector<void*>*
   (void)bytes;
   (void)err;
   // Stages per launch: the FP64 four-stage pipeline is register bound, so FP64
-  // runs two launches of two stages; first order always does (its boundary
-  // terms are added per half).  ABC_FUSED_STAGES (2 or 4) overrides the
-  // default for Dirichlet and zeroth order (tuning).
+  // runs two launches of two stages; first order and boxes wider than 128
+  // columns always do.  ABC_FUSED_STAGES (2 or 4) overrides the default for
+  // Dirichlet and zeroth order; the tile depth (4, 8 or 16 planes) starts at
+  // 8 and is set by the tuner.
   L.fused_stages = p.dtype == ABC_C128 ? 2 : 4;
   if (const char* e = std::getenv("ABC_FUSED_STAGES")) {
     const int v = std::atoi(e);
     if (v == 2 || v == 4) L.fused_stages = v;
   }
-  if (p.order == ABC_FIRST) L.fused_stages = 2;
+  if (p.order == ABC_FIRST || p.nx > kCols) L.fused_stages = 2;
+  L.fused_tz = std::min(8, fused_max_tz(p.order, p.nz));
   return ABC_OK;
+}
+
+bool fused_tz_valid(const abc_launch& L, int tz) {
+  return (tz == 4 || tz == 8 || tz == 16) && tz <= fused_max_tz(L.order, L.g.nz);
 }
 
 namespace {
@@ -538,9 +645,6 @@ hipError_t step_t(const abc_launch& L, const abc_scratch& S, void* psi_v, double
   using C = typename cpx<T>::t;
   const bool two = L.fused_stages == 2;
   FusedArgs a = make_args<T>(L, two);
-  a.m0 = L.fused_m0;
-  a.b0 = L.fused_b0;
-  a.a0 = L.a_loc[0];
   a.has_V = V_v != nullptr;
   C* user = static_cast<C*>(psi_v);
   C* scr = static_cast<C*>(S.y[0]);
@@ -572,24 +676,27 @@ hipError_t step_t(const abc_launch& L, const abc_scratch& S, void* psi_v, double
   const int nthreads = 64 * (Tile<T>::TY + 2 * kHalo);
   const int nthreads2 = 64 * (kTY2 + 2 * kHalo2);
   const double dt = L.dt;
+  const int tz = L.fused_tz;
   const dim3 g1(a.ntiles), b4(nthreads), b2(nthreads2);
+  const double2* none = nullptr;
+  double2* none_w = nullptr;
   for (int s = 0; s < n; ++s) {
     if (two) {
       if (L.order == ABC_ZEROTH) {
-        abc_launch_kernel(tm, "fused2_half_a", fused2_kernel<T, 2, true>, g1, b2, st, (const C*)src, (const C*)src,
-                          mid, V, a, dt / 4, dt / 3, nullptr, nullptr, nullptr);
-        abc_launch_kernel(tm, "fused2_half_b", fused2_kernel<T, 2, false>, g1, b2, st, (const C*)mid,
-                          (const C*)src, dst, V, a, dt / 2, dt, nullptr, nullptr, nullptr);
+        launch2<T, 2, true>(tm, "fused2_half_a", tz, g1, b2, st, (const C*)src, (const C*)src, mid, V, a, dt / 4,
+                            dt / 3, none, none, none_w);
+        launch2<T, 2, false>(tm, "fused2_half_b", tz, g1, b2, st, (const C*)mid, (const C*)src, dst, V, a, dt / 2,
+                             dt, none, none, none_w);
       } else if (first) {
-        abc_launch_kernel(tm, "fused2_half_a", fused2_kernel<T, 3, true>, g1, b2, st, (const C*)src, (const C*)src,
-                          mid, V, a, dt / 4, dt / 3, (const double2*)fsrc, (const double2*)fsrc, vmid);
-        abc_launch_kernel(tm, "fused2_half_b", fused2_kernel<T, 3, false>, g1, b2, st, (const C*)mid,
-                          (const C*)src, dst, V, a, dt / 2, dt, (const double2*)vmid, (const double2*)fsrc, fdst);
+        launch2<T, 3, true>(tm, "fused2_half_a", tz, g1, b2, st, (const C*)src, (const C*)src, mid, V, a, dt / 4,
+                            dt / 3, (const double2*)fsrc, (const double2*)fsrc, vmid);
+        launch2<T, 3, false>(tm, "fused2_half_b", tz, g1, b2, st, (const C*)mid, (const C*)src, dst, V, a, dt / 2,
+                             dt, (const double2*)vmid, (const double2*)fsrc, fdst);
       } else {
-        abc_launch_kernel(tm, "fused2_half_a", fused2_kernel<T, 0, true>, g1, b2, st, (const C*)src, (const C*)src,
-                          mid, V, a, dt / 4, dt / 3, nullptr, nullptr, nullptr);
-        abc_launch_kernel(tm, "fused2_half_b", fused2_kernel<T, 0, false>, g1, b2, st, (const C*)mid,
-                          (const C*)src, dst, V, a, dt / 2, dt, nullptr, nullptr, nullptr);
+        launch2<T, 0, true>(tm, "fused2_half_a", tz, g1, b2, st, (const C*)src, (const C*)src, mid, V, a, dt / 4,
+                            dt / 3, none, none, none_w);
+        launch2<T, 0, false>(tm, "fused2_half_b", tz, g1, b2, st, (const C*)mid, (const C*)src, dst, V, a, dt / 2,
+                             dt, none, none, none_w);
       }
     } else {
       if (L.order == ABC_ZEROTH)
@@ -610,4 +717,104 @@ hipError_t launch_step_fused(const abc_launch& L, const abc_scratch& S, void* ps
                              int n_steps, hipStream_t st, abc_timer* tm) {
   if (L.dtype == ABC_C64) return step_t<float>(L, S, psi, aux, V, n_steps, st, tm);
   return step_t<double>(L, S, psi, aux, V, n_steps, st, tm);
+}
+
+// ---------------------------------------------------------------------------
+// Batched boxes: one descriptor-driven launch per half-step for every group of
+// boxes that share (order, precision, tile depth).
+// ---------------------------------------------------------------------------
+
+size_t fused_batch_desc_bytes(int nbox) { return (size_t)4 * nbox * sizeof(Box2); }
+
+int fused_batch_build(const std::vector<FusedMember>& m, void* host, int n) {
+  const int nb = (int)m.size();
+  Box2* hb = static_cast<Box2*>(host);
+  int total = 0;
+  // descriptor sets [parity][half]; each box keeps its own ping-pong, arranged
+  // like the single-box path so that the last step writes the caller's buffers
+  for (int i = 0; i < nb; ++i) {
+    const abc_launch& L = *m[i].L;
+    const abc_scratch& S = *m[i].S;
+    FusedArgs a = L.dtype == ABC_C64 ? make_args<float>(L, true) : make_args<double>(L, true);
+    a.has_V = m[i].V != nullptr;
+    char* user = static_cast<char*>(m[i].psi);
+    char* scr = static_cast<char*>(S.y[0]);
+    char* mid = static_cast<char*>(S.y[1]);
+    double2* fuser = m[i].aux;
+    double2* fscr = S.facc;
+    double2* vmid = S.g[0];
+    const bool first = L.order == ABC_FIRST;
+    char* src0 = (n & 1) ? scr : user;
+    char* dst0 = (n & 1) ? user : scr;
+    double2* fsrc0 = (n & 1) ? fscr : fuser;
+    double2* fdst0 = (n & 1) ? fuser : fscr;
+    for (int q = 0; q < 2; ++q) {
+      char* src = q == 0 ? src0 : dst0;
+      char* dst = q == 0 ? dst0 : src0;
+      double2* fsrc = q == 0 ? fsrc0 : fdst0;
+      double2* fdst = q == 0 ? fdst0 : fsrc0;
+      Box2& A = hb[(q * 2 + 0) * nb + i];
+      Box2& B = hb[(q * 2 + 1) * nb + i];
+      A.a = a;
+      A.w = src;
+      A.base = src;
+      A.out = mid;
+      A.V = m[i].V;
+      A.av = first ? fsrc : nullptr;
+      A.fb = first ? fsrc : nullptr;
+      A.aux_out = first ? vmid : nullptr;
+      A.tile_begin = total;
+      A.pad = 0;
+      B = A;
+      B.w = mid;
+      B.av = first ? vmid : nullptr;
+      B.out = dst;
+      B.aux_out = first ? fdst : nullptr;
+    }
+    total += a.ntiles;
+  }
+  return total;
+}
+
+hipError_t launch_batch_fused(const std::vector<FusedMember>& m, int tz, const void* dev, int total, int n,
+                              hipStream_t st, abc_timer* tm) {
+  const int nb = (int)m.size();
+  if (nb == 0 || n <= 0) return hipSuccess;
+  const abc_launch& L0 = *m[0].L;
+  if (n & 1)
+    for (int i = 0; i < nb; ++i) {
+      const abc_launch& L = *m[i].L;
+      const size_t csz = L.dtype == ABC_C64 ? 8 : 16;
+      hipError_t e = hipMemcpyAsync(m[i].S->y[0], m[i].psi, (size_t)L.g.npts * csz, hipMemcpyDeviceToDevice, st);
+      if (e == hipSuccess && L.order == ABC_FIRST)
+        e = hipMemcpyAsync(m[i].S->facc, m[i].aux, (size_t)L.g.face_off[6] * sizeof(double2),
+                           hipMemcpyDeviceToDevice, st);
+      if (e != hipSuccess) return e;
+    }
+  const Box2* db = static_cast<const Box2*>(dev);
+  const dim3 g((unsigned)((total + 7) / 8 * 8));
+  const int order = L0.order;
+  const bool c64 = L0.dtype == ABC_C64;
+  for (int s = 0; s < n; ++s) {
+    const int q = s & 1;
+    const Box2* dA = db + (q * 2 + 0) * nb;
+    const Box2* dB = db + (q * 2 + 1) * nb;
+#define ABC_BATCH_PAIR(T, ORD)                                                        \
+  do {                                                                                \
+    launch2_batch<T, ORD, true>(tm, "fused2_batch_a", tz, g, st, dA, nb, total, 0);   \
+    launch2_batch<T, ORD, false>(tm, "fused2_batch_b", tz, g, st, dB, nb, total, 1);  \
+  } while (0)
+    if (c64) {
+      if (order == ABC_FIRST) ABC_BATCH_PAIR(float, 3);
+      else if (order == ABC_ZEROTH) ABC_BATCH_PAIR(float, 2);
+      else ABC_BATCH_PAIR(float, 0);
+    } else {
+      if (order == ABC_FIRST) ABC_BATCH_PAIR(double, 3);
+      else if (order == ABC_ZEROTH) ABC_BATCH_PAIR(double, 2);
+      else ABC_BATCH_PAIR(double, 0);
+    }
+#undef ABC_BATCH_PAIR
+    if (tm) tm->end_step();
+  }
+  return hipGetLastError();
 }

@@ -22,6 +22,31 @@ def _stream_handle(stream) -> Optional[int]:
     return stream.cuda_stream
 
 
+def make_params(shape, h, dt, *, radius=1, order="first", form="faces", s0=1.0, s1=1.0, s2=0.0, window=0,
+                fejer=True, dtype="c128", batch=1, meanfield=None, path="auto") -> _lib.AbcParams:
+    """abc_params for a box of shape (nz, ny, nx) (see include/abc_dtn.h)."""
+    lib = _lib.load()
+    p = _lib.AbcParams()
+    lib.abc_params_default(ctypes.byref(p))
+    nz, ny, nx = (int(v) for v in shape)
+    p.nx, p.ny, p.nz = nx, ny, nz
+    p.h, p.dt = float(h), float(dt)
+    p.radius = int(radius)
+    p.order = _lib.ORDERS[order]
+    p.form = _lib.FORMS[form]
+    p.s0, p.s1 = float(s0), float(s1)
+    p.s2 = 0.0 if (s2 is None or (isinstance(s2, float) and math.isinf(s2))) else float(s2)
+    p.window = int(window)
+    p.fejer = 1 if fejer else 0
+    p.dtype = _lib.DTYPES[dtype]
+    p.batch = int(batch)
+    if meanfield is not None:
+        p.meanfield = 1
+        p.t0, p.t3 = float(meanfield[0]), float(meanfield[1])
+    p.path = _lib.PATHS[path]
+    return p
+
+
 class Solver:
     """One context of the C ABI (operators + scratch) for a fixed box.
 
@@ -34,24 +59,9 @@ class Solver:
                  s2: float = 0.0, window: int = 0, fejer: bool = True, dtype: str = "c128",
                  batch: int = 1, meanfield=None, path: str = "auto", device=None):
         lib = _lib.load()
-        p = _lib.AbcParams()
-        lib.abc_params_default(ctypes.byref(p))
+        p = make_params(shape, h, dt, radius=radius, order=order, form=form, s0=s0, s1=s1, s2=s2,
+                        window=window, fejer=fejer, dtype=dtype, batch=batch, meanfield=meanfield, path=path)
         nz, ny, nx = (int(v) for v in shape)
-        p.nx, p.ny, p.nz = nx, ny, nz
-        p.h, p.dt = float(h), float(dt)
-        p.radius = int(radius)
-        p.order = _lib.ORDERS[order]
-        p.form = _lib.FORMS[form]
-        p.s0, p.s1 = float(s0), float(s1)
-        p.s2 = 0.0 if (s2 is None or (isinstance(s2, float) and math.isinf(s2))) else float(s2)
-        p.window = int(window)
-        p.fejer = 1 if fejer else 0
-        p.dtype = _lib.DTYPES[dtype]
-        p.batch = int(batch)
-        if meanfield is not None:
-            p.meanfield = 1
-            p.t0, p.t3 = float(meanfield[0]), float(meanfield[1])
-        p.path = _lib.PATHS[path]
         self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
         self.params = p
         self.shape = (nz, ny, nx)
@@ -145,6 +155,15 @@ class Solver:
                                          ctypes.byref(J), _stream_handle(stream)))
         return J.value, gpsi, gV
 
+    def tune(self, psi, aux=None, V=None, stream=None) -> int:
+        """Pick the fused path's tile depth by timing (state restored); returns it."""
+        self._check_psi(psi)
+        vp = self._check_V(V)
+        ap = self._check_aux(aux)
+        tz = ctypes.c_int(0)
+        _lib.check(self._lib.abc_tune(self._ctx, psi.data_ptr(), ap, vp, _stream_handle(stream), ctypes.byref(tz)))
+        return tz.value
+
     def diagnostics(self, psi, aux=None, V=None, out: Optional[torch.Tensor] = None, stream=None):
         """Tensor of 3*batch+1 float64: norm, Lyapunov W, energy per orbital, interaction energy."""
         self._check_psi(psi)
@@ -168,3 +187,77 @@ class Solver:
 
     def device_bytes(self) -> int:
         return int(self._lib.abc_device_bytes(self._ctx))
+
+
+class Batch:
+    """Independent boxes stepped together (abc_setup_batch / abc_step_batch).
+
+    configs: list of dicts with the Solver keyword arguments plus "shape", "h", "dt".
+    """
+
+    def __init__(self, configs, device=None):
+        lib = _lib.load()
+        n = len(configs)
+        arr = (_lib.AbcParams * n)()
+        self.configs = []
+        for i, cfg in enumerate(configs):
+            cfg = dict(cfg)
+            shape, h, dt = cfg.pop("shape"), cfg.pop("h"), cfg.pop("dt")
+            arr[i] = make_params(shape, h, dt, **cfg)
+            self.configs.append(dict(shape=tuple(int(v) for v in shape), dtype=cfg.get("dtype", "c128"),
+                                     order=cfg.get("order", "first")))
+        self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+        b = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _lib.check(lib.abc_setup_batch(arr, n, ctypes.byref(b)))
+        self._b = b
+        self._lib = lib
+        self.n = n
+        self.aux_elems = [int(lib.abc_batch_aux_elems(b, i)) for i in range(n)]
+
+    def close(self):
+        if getattr(self, "_b", None) is not None and self._b.value:
+            self._lib.abc_destroy_batch(self._b)
+            self._b = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def new_aux(self, i):
+        return torch.zeros(max(self.aux_elems[i], 1), dtype=torch.complex128, device=self.device)
+
+    def groups(self):
+        g = int(self._lib.abc_batch_launch_groups(self._b))
+        return [int(self._lib.abc_batch_tile_depth(self._b, k)) for k in range(g)]
+
+    def _ptrs(self, psis, auxs, Vs):
+        if len(psis) != self.n:
+            raise ValueError("expected %d psi tensors" % self.n)
+        for i, (p, cfg) in enumerate(zip(psis, self.configs)):
+            cdt = torch.complex128 if cfg["dtype"] == "c128" else torch.complex64
+            if p.dtype != cdt or tuple(p.shape) != cfg["shape"] or not p.is_contiguous() or p.device.type != "cuda":
+                raise ValueError("psi %d must be a contiguous %s tensor of shape %s" % (i, cdt, cfg["shape"]))
+        P = (ctypes.c_void_p * self.n)(*[p.data_ptr() for p in psis])
+        A = None
+        if auxs is not None:
+            for i, a in enumerate(auxs):
+                if a is not None and (a.dtype != torch.complex128 or a.numel() < self.aux_elems[i]):
+                    raise ValueError("aux %d must hold %d complex128 elements" % (i, self.aux_elems[i]))
+            A = (ctypes.c_void_p * self.n)(*[0 if a is None else a.data_ptr() for a in auxs])
+        Vp = None
+        if Vs is not None:
+            Vp = (ctypes.c_void_p * self.n)(*[0 if v is None else v.data_ptr() for v in Vs])
+        return P, A, Vp
+
+    def step(self, psis, auxs=None, Vs=None, n_steps=1, graph=False, stream=None):
+        P, A, Vp = self._ptrs(psis, auxs, Vs)
+        flags = _lib.ABC_BATCH_GRAPH if graph else 0
+        _lib.check(self._lib.abc_step_batch(self._b, P, A, Vp, int(n_steps), flags, _stream_handle(stream)))
+
+    def tune(self, psis, auxs=None, Vs=None, stream=None):
+        P, A, Vp = self._ptrs(psis, auxs, Vs)
+        _lib.check(self._lib.abc_tune_batch(self._b, P, A, Vp, _stream_handle(stream)))
+        return self.groups()

@@ -180,3 +180,26 @@ def adjoint_packet(n=96, h=0.2, steps=500, dt=0.002, s1=1.0, window=0):
     return {"n": n, "h": h, "steps": steps, "dt": dt, "s1": s1, "window": window,
             "amplitude": 5.0, "well_center": (0.0, 0.0, 0.0), "packet_center": (4.0, 0.0, 0.0),
             "k": (3.0, 0.0, 0.0)}
+
+
+def uneven_batch(count=64, seed=4, sizes=(48, 64, 96, 128, 160), h=0.2, dt=0.002, steps=500):
+    """Independent single-orbital instances: cubic box N drawn uniformly from
+    ``sizes``, well amplitude ~ U[1, 5] centred ~ U[-1, 1]^3, packet centred
+    ~ U[-1, 1]^3 with k ~ U[-3, 3]^3, order zeroth or first with probability
+    1/2 each (local face operators, s = 1).  Returns a list of dicts with the
+    box, the parameters and the fields."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(count):
+        n = int(rng.choice(sizes))
+        amp = float(rng.uniform(1.0, 5.0))
+        wc = tuple(float(v) for v in rng.uniform(-1.0, 1.0, size=3))
+        pc = tuple(float(v) for v in rng.uniform(-1.0, 1.0, size=3))
+        k = tuple(float(v) for v in rng.uniform(-3.0, 3.0, size=3))
+        order = "first" if rng.random() < 0.5 else "zeroth"
+        shape = (n, n, n)
+        out.append({"shape": shape, "h": h, "dt": dt, "steps": steps, "order": order, "s0": 1.0, "s1": 1.0,
+                    "window": 0, "amplitude": amp, "well_center": wc, "packet_center": pc, "k": k,
+                    "V": gaussian_well(shape, h, amp, center=wc),
+                    "psi0": gaussian_packet(shape, h, center=pc, k=k)})
+    return out

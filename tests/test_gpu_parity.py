@@ -143,7 +143,7 @@ def test_zero_steps_and_minimum_box():
 
 
 @pytest.mark.parametrize("order", ["dirichlet", "zeroth", "first"])
-@pytest.mark.parametrize("shape", [(21, 19, 37), (10, 17, 128), (16, 16, 16)])
+@pytest.mark.parametrize("shape", [(21, 19, 37), (10, 17, 128), (16, 16, 16), (11, 12, 131), (6, 10, 250)])
 @pytest.mark.parametrize("steps", [5, 6])
 def test_fused_path_parity(order, shape, steps):
     # several 8x8 (y, z) tiles with ragged tails (10 = one plane/row past a
@@ -225,14 +225,14 @@ def test_step_timed_matches_step(path, order):
 
 def test_fused_first_order_small_box_falls_back():
     # the fused first-order kernel stages one y-face row and one z-face plane
-    # per tile, so boxes with ny or nz below 10 run on the staged path
+    # per tile, so boxes with ny below 10 (or nz below 6) run on the staged path
     print("case: fused fallback", flush=True)
     Solver = _gpu()
     from paper_1908_02456_amd._lib import AbcError, ABC_ENOTSUP
     with pytest.raises(AbcError) as e:
-        Solver((9, 17, 20), 0.25, 0.004, order="first", window=0, path="fused")
+        Solver((9, 8, 20), 0.25, 0.004, order="first", window=0, path="fused")
     assert e.value.status == ABC_ENOTSUP
-    s = Solver((9, 17, 20), 0.25, 0.004, order="first", window=0, path="auto")
+    s = Solver((9, 8, 20), 0.25, 0.004, order="first", window=0, path="auto")
     assert not s.use_fused
-    r = _run_pair("fused-fallback", (9, 17, 20), 0.25, 0.004, 1, "first", 4, s1=1.5, window=0, path="auto")
+    r = _run_pair("fused-fallback", (9, 8, 20), 0.25, 0.004, 1, "first", 4, s1=1.5, window=0, path="auto")
     assert r["err"] < TOL64 and r["aux_err"] < TOL64
