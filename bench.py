@@ -121,6 +121,99 @@ def measured_traffic(label, args):
         return None
 
 
+def _time(torch, fn, stream=None):
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1)
+
+
+def bench_c64(Solver, torch, wl, steps, psi_ref):
+    """The same workload with the complex64 stencil (FP64 aux), and its
+    deviation from the complex128 run after the same steps."""
+    s = Solver((wl.n,) * 3, wl.h, wl.dt, order="first", s1=wl.s1, window=wl.window, dtype="c64")
+    psi = torch.from_numpy(wl.psi0).to(torch.complex64).cuda()
+    V = torch.from_numpy(wl.V).to(torch.float32).cuda()
+    aux = s.new_aux()
+    s.step(psi, aux, V, 20)
+    ms = _time(torch, lambda: s.step(psi, aux, V, steps))
+    psi = torch.from_numpy(wl.psi0).to(torch.complex64).cuda()
+    aux = s.new_aux()
+    s.step(psi, aux, V, 20 + steps)
+    d = (psi.to(torch.complex128) - psi_ref).abs().max().item() / psi_ref.abs().max().item()
+    return {"ms_per_step": ms / steps, "value": wl.n ** 3 * steps / (ms / 1e3), "unit": "grid-point-updates/s",
+            "rel_dev_from_c128_after_steps": d, "steps": 20 + steps}
+
+
+def bench_batch(Batch, Solver, torch, W, steps=20):
+    """64 uneven instances (N in {48..160}, mixed zeroth/first, complex128):
+    tuned descriptor-driven launches, eager and graph-captured, against the
+    same instances stepped one after another."""
+    insts = W.uneven_batch()
+    cfgs = [dict(shape=d["shape"], h=d["h"], dt=d["dt"], order=d["order"], s0=d["s0"], s1=d["s1"], window=0)
+            for d in insts]
+    b = Batch(cfgs)
+    psis = [torch.from_numpy(d["psi0"]).cuda() for d in insts]
+    Vs = [torch.from_numpy(d["V"]).cuda() for d in insts]
+    auxs = [b.new_aux(i) for i in range(len(insts))]
+    depths = b.tune(psis, auxs, Vs)
+    stream = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    pts = sum(int(np.prod(d["shape"])) for d in insts)
+    with torch.cuda.stream(stream):
+        b.step(psis, auxs, Vs, 2, stream=stream)
+        ms_eager = _time(torch, lambda: b.step(psis, auxs, Vs, steps, stream=stream), stream)
+        b.step(psis, auxs, Vs, steps, graph=True, stream=stream)
+        ms_graph = _time(torch, lambda: b.step(psis, auxs, Vs, steps, graph=True, stream=stream), stream)
+    singles = [Solver(d["shape"], d["h"], d["dt"], order=d["order"], s0=1.0, s1=1.0, window=0) for d in insts]
+    saux = [s.new_aux() for s in singles]
+
+    def seq():
+        for s, p, a, v in zip(singles, psis, saux, Vs):
+            s.step(p, a, v, steps)
+    seq()
+    ms_seq = _time(torch, seq)
+    return {"instances": len(insts), "grid_points": pts, "steps": steps, "tile_depths": depths,
+            "value_graph": pts * steps / (ms_graph / 1e3), "value_eager": pts * steps / (ms_eager / 1e3),
+            "value_sequential_single": pts * steps / (ms_seq / 1e3), "unit": "grid-point-updates/s",
+            "speedup_vs_sequential": ms_seq / ms_graph}
+
+
+def bench_adjoint(Solver, torch, W):
+    """Adjoint workload (96^3, 500 steps, first order, FP64): reverse-mode
+    gradient with sqrt(n) checkpoints, against the plain forward run."""
+    prm = W.adjoint_packet()
+    n = prm["n"]
+    s = Solver((n,) * 3, prm["h"], prm["dt"], order="first", s1=prm["s1"], window=prm["window"])
+    psi0 = torch.from_numpy(W.gaussian_packet((n,) * 3, prm["h"], center=prm["packet_center"], k=prm["k"])).cuda()
+    V = torch.from_numpy(W.gaussian_well((n,) * 3, prm["h"], prm["amplitude"])).cuda()
+    out = {}
+    ms_adj = _time(torch, lambda: out.setdefault("r", s.adjoint(psi0, V, prm["steps"], "prob")))
+    psi = psi0.clone()
+    aux = s.new_aux()
+    ms_fwd = _time(torch, lambda: s.step(psi, aux, V, prm["steps"]))
+    return {"grid": n, "steps": prm["steps"], "J": out["r"][0], "ms_adjoint": ms_adj, "ms_forward": ms_fwd,
+            "adjoint_over_forward": ms_adj / ms_fwd, "forward_path": "fused" if s.use_fused else "staged"}
+
+
+def bench_tdhf(Solver, torch, W, steps=10):
+    """32 oscillator orbitals on 96^3 with the mean field U = -rho + 0.5 rho^2,
+    first-order condition, complex64 stencil / FP64 aux (staged path)."""
+    n, nb, h = 96, 32, 0.2
+    orb = W.oscillator_orbitals((n,) * 3, h, nb, seed=3)
+    s = Solver((n,) * 3, h, 0.002, order="first", s1=1.0, window=0, dtype="c64", batch=nb, meanfield=(-1.0, 0.5))
+    psi = torch.from_numpy(orb).to(torch.complex64).cuda().contiguous()
+    aux = s.new_aux()
+    s.step(psi, aux, None, 2)
+    ms = _time(torch, lambda: s.step(psi, aux, None, steps))
+    return {"grid": n, "orbitals": nb, "steps": steps, "ms_per_step": ms / steps,
+            "value": n ** 3 * nb * steps / (ms / 1e3), "unit": "orbital-point-updates/s", "path": "staged"}
+
+
 def cpu_baseline(wl, window, budget_s=15.0):
     """FP64 oracle (NumPy, single-threaded elementwise) on the same workload,
     for as many whole steps as fit in about budget_s seconds."""
@@ -162,6 +255,7 @@ def main():
     ap.add_argument("--path", default="auto", choices=["auto", "staged", "fused"])
     ap.add_argument("--no-physics", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-extra", action="store_true", help="skip the batch / adjoint / c64 / TDHF figures")
     ap.add_argument("--copy-gib", type=float, default=0.0,
                     help="also run one plain device copy of this size (calibrates rocprofv3 byte counters)")
     args = ap.parse_args()
@@ -243,6 +337,22 @@ def main():
         torch.cuda.synchronize()
         out["copy_calibration_bytes"] = 2 * nb
         del src_t, dst_t
+    if not args.no_extra:
+        from paper_1908_02456_amd.solver import Batch
+        extra = {}
+        psi_ref = torch.from_numpy(wl.psi0).cuda()
+        s.step(psi_ref, s.new_aux(), torch.from_numpy(wl.V).cuda(), 220) if args.dtype == "c128" else None
+        for name, fn in (("c64", lambda: bench_c64(Solver, torch, wl, 200, psi_ref)),
+                         ("batch", lambda: bench_batch(Batch, Solver, torch, W)),
+                         ("adjoint", lambda: bench_adjoint(Solver, torch, W)),
+                         ("tdhf", lambda: bench_tdhf(Solver, torch, W))):
+            log("extra: %s" % name)
+            try:
+                extra[name] = fn()
+            except Exception as exc:  # reported, not fatal for the headline line
+                extra[name] = {"error": repr(exc)}
+            torch.cuda.empty_cache()
+        out["extra"] = extra
     if not args.no_physics:
         log("physics run: %d steps vs %d^3 zero-boundary box" % (wl.steps, 2 * wl.n))
         out["physics"] = physics_error(Solver, torch, wl, args.dtype, args.window, args.path, wl.steps)
