@@ -1,26 +1,25 @@
 // Fused Taylor-4 step kernels (Sec. 4 Taylor propagator applied to the
-// dynamics of Sec. 3), for R = 1, local (window 0) face operators and boxes
-// of at most 128 columns.
+// dynamics of Sec. 3), for R = 1 and local (window 0) face operators.
 //
 // The step U = sum_{k<=4} (dt L)^k / k! is evaluated in Horner form, the same
 // polynomial with a different rounding order:
 //   u3 = z0 + (dt/4) L z0,  u2 = z0 + (dt/3) L u3,  u1 = z0 + (dt/2) L u2,
 //   z' = z0 + dt L u1,       z0 = (psi, f).
 //
-// Sweep layout shared by both kernels:
-//   * a workgroup owns an output tile of all x, TY rows in y and TZ planes in
-//     z, and loads one halo row/plane per fused stage on each side;
-//   * one wavefront per y row, two consecutive x columns per lane, so x needs
-//     no halo; rows are published in LDS as [column parity][1 + lane] with a
-//     zero guard cell at each end (conflict-free, branch-free x neighbours);
+// Sweep layout:
+//   * a workgroup owns an output tile of one x chunk (the whole row up to 128
+//     columns), TY rows in y and TZ planes in z, and loads one halo row/plane
+//     per fused stage on each side;
+//   * one wavefront per y row, two consecutive x columns per lane; rows are
+//     published in LDS as [column parity][1 + lane] with a zero guard cell at
+//     each end (conflict-free, branch-free x neighbours);
 //   * the workgroup marches z: when plane zi is loaded, stage k works on plane
 //     zi - k with its input's below/centre planes in registers, the plane above
 //     being the previous stage's fresh output; the initial state needed by the
 //     Horner stages rides along in a register delay line;
 //   * tiles are numbered so that consecutive tiles share an XCD and its L2.
-// fused_step_kernel runs all four stages (one launch per step);
-// fused2_kernel runs half of them (two launches per step, two-deep halos,
-// half the register state) and also carries the first-order condition: the
+// fused2_kernel runs two of the four stages per launch (two launches per step,
+// two-deep halos) and also carries the zeroth- and first-order conditions: the
 // face sources and the auxiliary stages are evaluated at face points only
 // (whole rows on y and z faces, the two edge lanes on x faces), from the
 // auxiliary arrays in global memory and the field values already in
@@ -36,18 +35,11 @@
 
 namespace {
 
-constexpr int kHalo = 4;  // four-stage kernel: one plane/row per stage
 constexpr int kCols = 128;
 
 template <typename T> struct cpx;
 template <> struct cpx<double> { using t = double2; };
 template <> struct cpx<float> { using t = float2; };
-
-// Four-stage output tile per precision (256 tiles at 128^3 in both cases).
-// FP32: 8 x 8, 16 waves; FP64: 4 x 16, 12 waves (register budget).
-template <typename T> struct Tile;
-template <> struct Tile<float> { static constexpr int TY = 8, TZ = 8; };
-template <> struct Tile<double> { static constexpr int TY = 4, TZ = 16; };
 
 struct FusedArgs {
   int nx, ny, nz;
@@ -85,137 +77,26 @@ __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
-// ORDER: 0 = no boundary term (zero outside the box), 2 = zeroth order.
-template <typename T, int ORDER>
-__global__ void __launch_bounds__(64 * (Tile<T>::TY + 2 * kHalo)) fused_step_kernel(
-    const typename cpx<T>::t* __restrict__ pin, typename cpx<T>::t* __restrict__ pout, const T* __restrict__ V,
-    FusedArgs a) {
-  using C = typename cpx<T>::t;
-  constexpr int TY = Tile<T>::TY, TZ = Tile<T>::TZ;
-  constexpr int ROWS = TY + 2 * kHalo;
-  constexpr int NT = 64 * ROWS;
-  constexpr int ITERS = TZ + 2 * kHalo;
-  __shared__ C plane[4][ROWS][2][66];
+// Raw buffer loads: an offset at or beyond the buffer's size returns zero,
+// which is how halo cells outside the box read as zero without a select on
+// the loaded value (a select would force the wait right after the load).
+// Buffers are limited to below 4 GiB (checked on the host).
+constexpr unsigned kOob = 0xFFFFFFF0u;
 
-  const int lane = threadIdx.x & 63;
-  const int r = threadIdx.x >> 6;
-  int tile = blockIdx.x;
-  if (a.tiles_per_xcd) tile = (blockIdx.x & 7) * a.tiles_per_xcd + (blockIdx.x >> 3);
-  const int ty = tile % a.nty, tz = tile / a.nty;
-  const int y0 = ty * TY, z0 = tz * TZ;
-  const int nx = a.nx, ny = a.ny, nz = a.nz;
-  const int sz = nx * ny;
-  const int y = y0 - kHalo + r;
-  const bool row_in = y >= 0 && y < ny;
-  const int ybase = y * nx;
-  const bool own_row = r >= kHalo && r < kHalo + TY && row_in;
-
-  for (int i = threadIdx.x; i < 4 * ROWS * 2 * 66; i += NT) (&plane[0][0][0][0])[i] = czero<C>();
-  __syncthreads();
-
-  C Yc[4][2], Yb[4][2];  // stage-j output at the centre / below plane of stage j+1
-  T Vd[4][2];            // V at planes zi-1 .. zi-4
-  C Pz[2][2];            // psi at planes zi-3, zi-4
-  C pf[2];               // psi and V at plane zi+1, fetched an iteration ahead
-  T pv[2];
-#pragma unroll
-  for (int c = 0; c < 2; ++c) {
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      Yc[j][c] = Yb[j][c] = czero<C>();
-      Vd[j][c] = T(0);
-    }
-    Pz[0][c] = Pz[1][c] = czero<C>();
-  }
-  const T diag = T(a.diag), off = T(a.off);
-
-  auto fetch = [&](int zz) {
-    const bool ok = row_in && zz >= 0 && zz < nz;
-#pragma unroll
-    for (int c = 0; c < 2; ++c) {
-      const int x = 2 * lane + c;
-      const int idx = ok ? zz * sz + ybase + min(x, nx - 1) : 0;  // always a valid address
-      const C pv_ = pin[idx];
-      const T vv = a.has_V ? V[idx] : T(0);
-      pf[c] = (ok && x < nx) ? pv_ : czero<C>();
-      pv[c] = (ok && x < nx) ? vv : T(0);
-    }
-  };
-  fetch(z0 - kHalo);
-
-  for (int it = 0; it < ITERS; ++it) {
-    const int zi = z0 - kHalo + it;
-    C prev[2];    // previous stage's output at the plane above (stage 0: psi(zi))
-    T vcur[2];
-    C psi_m2[2];  // psi at plane zi - 2
-#pragma unroll
-    for (int c = 0; c < 2; ++c) {
-      prev[c] = pf[c];
-      vcur[c] = pv[c];
-      psi_m2[c] = Yb[0][c];
-    }
-    if (it + 1 < ITERS) fetch(zi + 1);
-#pragma unroll
-    for (int k = 1; k <= 4; ++k) {
-      const int zk = zi - k;
-      const T cf = T(a.coef[5 - k]);
-      const bool active = r >= k && r < ROWS - k && it >= 2 * k && row_in && zk >= 0 && zk < nz;
-      C out[2];
-#pragma unroll
-      for (int c = 0; c < 2; ++c) {
-        const int x = 2 * lane + c;
-        out[c] = czero<C>();
-        if (!active) continue;
-        const C cen = Yc[k - 1][c], bel = Yb[k - 1][c], abv = prev[c];
-        const C ym = plane[k - 1][r - 1][c][lane + 1];
-        const C yp = plane[k - 1][r + 1][c][lane + 1];
-        const C xm = c == 0 ? plane[k - 1][r][1][lane] : Yc[k - 1][0];
-        const C xp = c == 0 ? Yc[k - 1][1] : plane[k - 1][r][0][lane + 2];
-        const C z0v = k == 1 ? Yc[0][c] : (k == 2 ? psi_m2[c] : Pz[k - 3][c]);
-        const T v = Vd[k - 1][c];
-        T hr = diag * cen.x + off * (bel.x + abv.x + ym.x + yp.x + xm.x + xp.x) + v * cen.x;
-        T hi = diag * cen.y + off * (bel.y + abv.y + ym.y + yp.y + xm.y + xp.y) + v * cen.y;
-        if (ORDER == 2) {
-          const int nf = (x == 0) + (x == nx - 1) + (y == 0) + (y == ny - 1) + (zk == 0) + (zk == nz - 1);
-          if (nf) {
-            const double2 s = cmul(a.m0, make_double2((double)cen.x, (double)cen.y));
-            hr += T(nf * s.x);
-            hi += T(nf * s.y);
-          }
-        }
-        // columns past the box edge stay zero (they are x neighbours)
-        out[c].x = x < nx ? z0v.x + cf * hi : T(0);
-        out[c].y = x < nx ? z0v.y - cf * hr : T(0);
-      }
-      // stage k is the last reader of its input window: slide it now
-#pragma unroll
-      for (int c = 0; c < 2; ++c) {
-        Yb[k - 1][c] = Yc[k - 1][c];
-        Yc[k - 1][c] = prev[c];
-        prev[c] = out[c];
-      }
-    }
-    // stage 4 output is the new state at plane zi - 4
-    const int z4 = zi - 4;
-    const bool own_out = own_row && it >= 2 * kHalo && z4 < nz;
-#pragma unroll
-    for (int c = 0; c < 2; ++c) {
-      const int x = 2 * lane + c;
-      if (own_out && x < nx) pout[z4 * sz + ybase + x] = prev[c];
-      Pz[1][c] = Pz[0][c];
-      Pz[0][c] = psi_m2[c];
-      Vd[3][c] = Vd[2][c];
-      Vd[2][c] = Vd[1][c];
-      Vd[1][c] = Vd[0][c];
-      Vd[0][c] = vcur[c];
-    }
-    sync_lds();
-#pragma unroll
-    for (int j = 0; j < 4; ++j)
-#pragma unroll
-      for (int c = 0; c < 2; ++c) plane[j][r][c][lane + 1] = Yc[j][c];
-    sync_lds();
-  }
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p, unsigned bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
+}
+__device__ __forceinline__ void bload(__amdgpu_buffer_rsrc_t r, unsigned off, double2& v) {
+  v = __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+}
+__device__ __forceinline__ void bload(__amdgpu_buffer_rsrc_t r, unsigned off, float2& v) {
+  v = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+__device__ __forceinline__ void bload(__amdgpu_buffer_rsrc_t r, unsigned off, double& v) {
+  v = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+__device__ __forceinline__ void bload(__amdgpu_buffer_rsrc_t r, unsigned off, float& v) {
+  v = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
 }
 
 // Half of the Horner step per launch:
@@ -243,7 +124,7 @@ struct Box2 {
   int pad;
 };
 
-template <typename T, int ORDER, bool SAME_BASE, int TZ>
+template <typename T, int ORDER, bool SAME_BASE, int TZ, int PF>
 __device__ __forceinline__ void fused2_body(const typename cpx<T>::t* __restrict__ w_in,
                                             const typename cpx<T>::t* __restrict__ base_in,
                                             typename cpx<T>::t* __restrict__ out, const T* __restrict__ V,
@@ -277,8 +158,8 @@ __device__ __forceinline__ void fused2_body(const typename cpx<T>::t* __restrict
   C Yc[2][2], Yb[2][2];  // stage inputs: centre / below (j = 0: w, j = 1: stage-1 output)
   C Bd[2][2];            // base at planes zi-1, zi-2 (separate base only)
   T Vd[2][2];            // V at planes zi-1, zi-2
-  C pf[2], pb[2];        // fields at plane zi+1, fetched an iteration ahead
-  T pv[2];
+  C pf[PF][2], pb[PF][2];  // fields of the next PF planes (ring indexed by plane)
+  T pv[PF][2];
 #pragma unroll
   for (int c = 0; c < 2; ++c) {
 #pragma unroll
@@ -286,28 +167,29 @@ __device__ __forceinline__ void fused2_body(const typename cpx<T>::t* __restrict
       Yc[j][c] = Yb[j][c] = Bd[j][c] = czero<C>();
       Vd[j][c] = T(0);
     }
-    pb[c] = czero<C>();
+#pragma unroll
+    for (int q = 0; q < PF; ++q) pb[q][c] = czero<C>();
   }
   const T diag = T(a.diag), off = T(a.off);
+  const unsigned cbytes = (unsigned)(nz * sz) * (unsigned)sizeof(C);
+  const __amdgpu_buffer_rsrc_t rw = make_rsrc(w_in, cbytes), rbase = make_rsrc(base_in, cbytes);
+  const __amdgpu_buffer_rsrc_t rv = make_rsrc(V, a.has_V ? (unsigned)(nz * sz) * (unsigned)sizeof(T) : 0u);
 
-  auto fetch = [&](int zz) {
+  // plane zz into ring slot q; cells outside the box read as zero
+  auto fetch = [&](int zz, int q) {
     const bool ok = row_in && zz >= 0 && zz < nz;
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
       const int x = xb + 2 * lane + c;
       const bool in = ok && x >= 0 && x < nx;
-      const int idx = ok ? zz * sz + ybase + min(max(x, 0), nx - 1) : 0;  // always a valid address
-      const C wv = w_in[idx];
-      pf[c] = in ? wv : czero<C>();
-      if (!SAME_BASE) {
-        const C bv = base_in[idx];
-        pb[c] = in ? bv : czero<C>();
-      }
-      const T vv = a.has_V ? V[idx] : T(0);
-      pv[c] = in ? vv : T(0);
+      const unsigned idx = in ? (unsigned)(zz * sz + ybase + x) : 0u;
+      bload(rw, in ? idx * (unsigned)sizeof(C) : kOob, pf[q][c]);
+      if (!SAME_BASE) bload(rbase, in ? idx * (unsigned)sizeof(C) : kOob, pb[q][c]);
+      bload(rv, in ? idx * (unsigned)sizeof(T) : kOob, pv[q][c]);
     }
   };
-  fetch(z0 - H);
+#pragma unroll
+  for (int q = 0; q < PF; ++q) fetch(z0 - H + q, q);
 
   // First order: the tile's face data (auxiliary input av and base fb) staged
   // in LDS once, for planes z0-1 .. z0+TZ and rows 1 .. ROWS-2 of the tile:
@@ -324,12 +206,18 @@ __device__ __forceinline__ void fused2_body(const typename cpx<T>::t* __restrict
   __shared__ double2 fys[NY];  // [arr][plane][local column]
   __shared__ double2 fzs[NZ];  // [arr][row][local column]
   int yface = -1, zface = -1;  // face index (2/3, 4/5) of the staged row / plane
+  // face slab offsets as scalars (a per-lane index into the argument array
+  // would make the compiler loop over the distinct indices)
+  const int off_x0 = a.face_off[0], off_x1 = a.face_off[1];
+  int off_y = 0, off_z = 0;
   if (ORDER == 3) {
     const int ylo = y0 - H + 1, zlo = z0 - 1;
     if (ylo <= 0) yface = 2;
     else if (ylo <= ny - 1 && ny - 1 < ylo + FR) yface = 3;
     if (zlo <= 0) zface = 4;
     else if (zlo <= nz - 1 && nz - 1 < zlo + FP) zface = 5;
+    off_y = yface == 3 ? a.face_off[3] : a.face_off[2];
+    off_z = zface == 5 ? a.face_off[5] : a.face_off[4];
     constexpr int KX = (NX + NT - 1) / NT, KY = (NY + NT - 1) / NT, KZ = (NZ + NT - 1) / NT;
     double2 rx[KX], ry[KY], rz[KZ];
 #pragma unroll
@@ -338,7 +226,7 @@ __device__ __forceinline__ void fused2_body(const typename cpx<T>::t* __restrict
       const int rr = i % FR, pl = (i / FR) % FP, side = (i / (FR * FP)) & 1, arr = i / (2 * FR * FP);
       const int yy = ylo + rr, zz = zlo + pl;
       rx[j] = make_double2(0, 0);
-      if (i < NX && yy >= 0 && yy < ny && zz >= 0 && zz < nz) rx[j] = (arr ? fb : av)[a.face_off[side] + zz * ny + yy];
+      if (i < NX && yy >= 0 && yy < ny && zz >= 0 && zz < nz) rx[j] = (arr ? fb : av)[(side ? off_x1 : off_x0) + zz * ny + yy];
     }
 #pragma unroll
     for (int j = 0; j < KY; ++j) {
@@ -347,7 +235,7 @@ __device__ __forceinline__ void fused2_body(const typename cpx<T>::t* __restrict
       const int xx = xb + lx, zz = zlo + pl;
       ry[j] = make_double2(0, 0);
       if (yface >= 0 && i < NY && xx >= 0 && xx < nx && zz >= 0 && zz < nz)
-        ry[j] = (i >= FP * kCols ? fb : av)[a.face_off[yface] + zz * nx + xx];
+        ry[j] = (i >= FP * kCols ? fb : av)[off_y + zz * nx + xx];
     }
 #pragma unroll
     for (int j = 0; j < KZ; ++j) {
@@ -356,7 +244,7 @@ __device__ __forceinline__ void fused2_body(const typename cpx<T>::t* __restrict
       const int xx = xb + lx, yy = ylo + rr;
       rz[j] = make_double2(0, 0);
       if (zface >= 0 && i < NZ && xx >= 0 && xx < nx && yy >= 0 && yy < ny)
-        rz[j] = (i >= FR * kCols ? fb : av)[a.face_off[zface] + yy * nx + xx];
+        rz[j] = (i >= FR * kCols ? fb : av)[off_z + yy * nx + xx];
     }
 #pragma unroll
     for (int j = 0; j < KX; ++j) {
@@ -376,19 +264,21 @@ __device__ __forceinline__ void fused2_body(const typename cpx<T>::t* __restrict
   }
   __syncthreads();
 
+#pragma unroll
   for (int it = 0; it < ITERS; ++it) {
     const int zi = z0 - H + it;
     C prev[2];
     T vcur[2];
     C bcur[2], wm2[2];  // base at plane zi; w at plane zi - 2 (before the slide)
+    const int q = it % PF;  // ring slot of plane zi (the loop is unrolled)
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
-      prev[c] = pf[c];
-      vcur[c] = pv[c];
-      bcur[c] = SAME_BASE ? pf[c] : pb[c];
+      prev[c] = pf[q][c];
+      vcur[c] = pv[q][c];
+      bcur[c] = SAME_BASE ? pf[q][c] : pb[q][c];
       wm2[c] = Yb[0][c];
     }
-    if (it + 1 < ITERS) fetch(zi + 1);
+    if (it + PF < ITERS) fetch(zi + PF, q);
 #pragma unroll
     for (int k = 1; k <= 2; ++k) {
       const int zk = zi - k;
@@ -420,57 +310,87 @@ __device__ __forceinline__ void fused2_body(const typename cpx<T>::t* __restrict
             hi += T(nf * sv.y);
           }
         }
-        if (ORDER == 3) {
-          // first order: the psi stage sees -i sum_f g_f at face points, with
-          // g = the auxiliary input (stage 1) or the auxiliary stage
-          // v_f = fb_f + cA (b av_f + a w) (stage 2), which also produces the
-          // auxiliary output fb_f + cB (b v_f + a s1) at owned points
-          const bool fx = x == 0 || x == nx - 1, fy = y == 0 || y == ny - 1, fz = zk == 0 || zk == nz - 1;
-          if ((fx || fy || fz) && in) {
-            const int pl = zk - (z0 - 1), rr = r - 1;
-            double sr = 0, si = 0;
-            double2 aw = make_double2(0, 0), as1 = make_double2(0, 0);
-            if (k == 2) {
-              aw = cmul(a.a0, make_double2((double)wm2[c].x, (double)wm2[c].y));
-              as1 = cmul(a.a0, make_double2((double)cen.x, (double)cen.y));
-            }
-            const bool own = k == 2 && own_row && it >= 2 * H && x >= xo && x < xe;
-            // one face through the point: its auxiliary input g and base f0
-            auto face = [&](const double2* lds_g, const double2* lds_f, int gi) {
-              const double2 g = *lds_g;
-              if (k == 1) {
-                sr += g.x;
-                si += g.y;
-                return;
-              }
-              const double2 f0 = *lds_f;
-              const double2 bg = cmul(a.b0, g);
-              const double2 v = make_double2(f0.x + cA * (bg.x + aw.x), f0.y + cA * (bg.y + aw.y));
-              sr += v.x;
-              si += v.y;
-              if (own) {
-                const double2 bv = cmul(a.b0, v);
-                aux_out[gi] = make_double2(f0.x + cB * (bv.x + as1.x), f0.y + cB * (bv.y + as1.y));
-              }
-            };
-            if (fx) {
-              const int side = x == 0 ? 0 : 1;
-              face(&fxs[((0 * 2 + side) * FP + pl) * FR + rr], &fxs[((1 * 2 + side) * FP + pl) * FR + rr],
-                   a.face_off[side] + zk * ny + y);
-            }
-            if (fy)
-              face(&fys[(0 * FP + pl) * kCols + lx], &fys[(1 * FP + pl) * kCols + lx],
-                   a.face_off[yface] + zk * nx + x);
-            if (fz)
-              face(&fzs[(0 * FR + rr) * kCols + lx], &fzs[(1 * FR + rr) * kCols + lx],
-                   a.face_off[zface] + y * nx + x);
-            hr += T(sr);
-            hi += T(si);
-          }
-        }
         // columns outside the box stay zero (they are x neighbours)
         o[c].x = in ? b0.x + cf * hi : T(0);
         o[c].y = in ? b0.y - cf * hr : T(0);
+      }
+      if (ORDER == 3 && active) {
+        // First order: the psi stage also sees -i sum_f g_f at face points,
+        // with g = the auxiliary input (stage 1) or the auxiliary stage
+        // v_f = fb_f + cA (b av_f + a w) (stage 2), which also produces the
+        // auxiliary output fb_f + cB (b v_f + a s1) at owned points.  The
+        // correction -i cf (sum g) is added to the plain stage output.  On a
+        // y- or z-face row (wave-uniform) both columns of every lane are face
+        // points; elsewhere a lane has at most one x-face column, so the wave
+        // pays for a single divergent pass.
+        const bool fyz = y == 0 || y == ny - 1 || zk == 0 || zk == nz - 1;
+        const int pl = zk - (z0 - 1), rr = r - 1;
+        const bool own_pt = k == 2 && own_row && it >= 2 * H;
+        const double cf2 = k == 1 ? cA : cB;
+        // correction (re, im) at local column lx with stage input cenc and w
+        auto corr = [&](int lx, const C& cenc, const C& wc) {
+          const int x = xb + lx;
+          const bool fx = x == 0 || x == nx - 1, fy = y == 0 || y == ny - 1, fz = zk == 0 || zk == nz - 1;
+          double sr = 0, si = 0;
+          double2 aw = make_double2(0, 0), as1 = make_double2(0, 0);
+          if (k == 2) {
+            aw = cmul(a.a0, make_double2((double)wc.x, (double)wc.y));
+            as1 = cmul(a.a0, make_double2((double)cenc.x, (double)cenc.y));
+          }
+          const bool own = own_pt && x >= xo && x < xe;
+          // one face through the point: its auxiliary input g and base f0
+          auto face = [&](const double2* lds_g, const double2* lds_f, int gi) {
+            const double2 g = *lds_g;
+            if (k == 1) {
+              sr += g.x;
+              si += g.y;
+              return;
+            }
+            const double2 f0 = *lds_f;
+            const double2 bg = cmul(a.b0, g);
+            const double2 v = make_double2(f0.x + cA * (bg.x + aw.x), f0.y + cA * (bg.y + aw.y));
+            sr += v.x;
+            si += v.y;
+            if (own) {
+              const double2 bv = cmul(a.b0, v);
+              aux_out[gi] = make_double2(f0.x + cB * (bv.x + as1.x), f0.y + cB * (bv.y + as1.y));
+            }
+          };
+          if (fx) {
+            const int side = x == 0 ? 0 : 1;
+            face(&fxs[((0 * 2 + side) * FP + pl) * FR + rr], &fxs[((1 * 2 + side) * FP + pl) * FR + rr],
+                 (side ? off_x1 : off_x0) + zk * ny + y);
+          }
+          if (fy)
+            face(&fys[(0 * FP + pl) * kCols + lx], &fys[(1 * FP + pl) * kCols + lx], off_y + zk * nx + x);
+          if (fz)
+            face(&fzs[(0 * FR + rr) * kCols + lx], &fzs[(1 * FR + rr) * kCols + lx], off_z + y * nx + x);
+          return make_double2(cf2 * si, -cf2 * sr);
+        };
+        if (fyz) {
+#pragma unroll
+          for (int c = 0; c < 2; ++c) {
+            const int x = xb + 2 * lane + c;
+            if (x >= 0 && x < nx) {
+              const double2 d = corr(2 * lane + c, Yc[k - 1][c], wm2[c]);
+              o[c].x += T(d.x);
+              o[c].y += T(d.y);
+            }
+          }
+        } else {
+          const int x0 = xb + 2 * lane;
+          const int cx = (x0 == 0 || x0 == nx - 1) ? 0 : ((x0 + 1 == nx - 1) ? 1 : -1);
+          if (cx >= 0) {
+            const C cenc = cx ? Yc[k - 1][1] : Yc[k - 1][0];
+            const C wc = cx ? wm2[1] : wm2[0];
+            const double2 d = corr(2 * lane + cx, cenc, wc);
+            const T dx = T(d.x), dy = T(d.y);
+            o[0].x += cx ? T(0) : dx;
+            o[0].y += cx ? T(0) : dy;
+            o[1].x += cx ? dx : T(0);
+            o[1].y += cx ? dy : T(0);
+          }
+        }
       }
 #pragma unroll
       for (int c = 0; c < 2; ++c) {
@@ -502,20 +422,20 @@ __device__ __forceinline__ void fused2_body(const typename cpx<T>::t* __restrict
 }
 
 // one box, arguments in the kernel argument segment
-template <typename T, int ORDER, bool SAME_BASE, int TZ>
+template <typename T, int ORDER, bool SAME_BASE, int TZ, int PF = 1>
 __global__ void __launch_bounds__(64 * (kTY2 + 2 * kHalo2)) fused2_kernel(
     const typename cpx<T>::t* __restrict__ w_in, const typename cpx<T>::t* __restrict__ base_in,
     typename cpx<T>::t* __restrict__ out, const T* __restrict__ V, FusedArgs a, double cA, double cB,
     const double2* __restrict__ av, const double2* __restrict__ fb, double2* __restrict__ aux_out) {
   int tile = blockIdx.x;
   if (a.tiles_per_xcd) tile = (blockIdx.x & 7) * a.tiles_per_xcd + (blockIdx.x >> 3);
-  fused2_body<T, ORDER, SAME_BASE, TZ>(w_in, base_in, out, V, a, cA, cB, av, fb, aux_out, tile);
+  fused2_body<T, ORDER, SAME_BASE, TZ, PF>(w_in, base_in, out, V, a, cA, cB, av, fb, aux_out, tile);
 }
 
 // many boxes in one launch: the grid is the concatenation of the boxes' tiles
 // (padded to a multiple of 8 for the XCD-aware order); each workgroup finds
 // its box by binary search over the boxes' first tiles
-template <typename T, int ORDER, bool SAME_BASE, int TZ>
+template <typename T, int ORDER, bool SAME_BASE, int TZ, int PF = 1>
 __global__ void __launch_bounds__(64 * (kTY2 + 2 * kHalo2)) fused2_batch_kernel(
     const Box2* __restrict__ boxes, int nbox, int total_tiles, int half) {
   using C = typename cpx<T>::t;
@@ -531,19 +451,19 @@ __global__ void __launch_bounds__(64 * (kTY2 + 2 * kHalo2)) fused2_batch_kernel(
   const Box2& b = boxes[lo];
   // Horner coefficients of the box's own time step: (dt/4, dt/3) or (dt/2, dt)
   const double cA = half ? b.a.coef[2] : b.a.coef[4], cB = half ? b.a.coef[1] : b.a.coef[3];
-  fused2_body<T, ORDER, SAME_BASE, TZ>(static_cast<const C*>(b.w), static_cast<const C*>(b.base),
+  fused2_body<T, ORDER, SAME_BASE, TZ, PF>(static_cast<const C*>(b.w), static_cast<const C*>(b.base),
                                        static_cast<C*>(b.out), static_cast<const T*>(b.V), b.a, cA, cB, b.av, b.fb,
                                        b.aux_out, t - b.tile_begin);
 }
 
 template <typename T>
-FusedArgs make_args(const abc_launch& L, bool two) {
+FusedArgs make_args(const abc_launch& L) {
   FusedArgs a{};
   a.nx = L.g.nx;
   a.ny = L.g.ny;
   a.nz = L.g.nz;
-  const int TY = two ? kTY2 : Tile<T>::TY, TZ = two ? L.fused_tz : Tile<T>::TZ;
-  a.ntx = (two && a.nx > kCols) ? (a.nx + kChunk - 1) / kChunk : 1;
+  const int TY = kTY2, TZ = L.fused_tz;
+  a.ntx = a.nx > kCols ? (a.nx + kChunk - 1) / kChunk : 1;
   a.xw = (a.nx + a.ntx - 1) / a.ntx;
   a.nty = (a.ny + TY - 1) / TY;
   const int ntz = (a.nz + TZ - 1) / TZ;
@@ -563,6 +483,7 @@ FusedArgs make_args(const abc_launch& L, bool two) {
 // launch one two-stage kernel instance for a runtime tile depth
 template <typename T, int ORDER, bool SB, typename... A>
 void launch2(abc_timer* tm, const char* label, int tz, dim3 g, dim3 b, hipStream_t st, A... args) {
+
   if constexpr (ORDER == 3) {
     if (tz == 4) return abc_launch_kernel(tm, label, fused2_kernel<T, ORDER, SB, 4>, g, b, st, args...);
     return abc_launch_kernel(tm, label, fused2_kernel<T, ORDER, SB, 8>, g, b, st, args...);
@@ -610,6 +531,9 @@ bool fused_supported(const abc_params& p, std::string* why) {
   if (p.order == ABC_FIRST && (p.ny < kTY2 + 2 || p.nz < 6))
     return no("first order: ny >= 10 and nz >= 6 (one y-face row and one z-face plane per tile)");
   if ((long long)p.nx * p.ny * p.nz >= (1LL << 31)) return no("grid below 2^31 points");
+  // raw buffer loads address each array with 32-bit byte offsets
+  if ((long long)p.nx * p.ny * p.nz * (p.dtype == ABC_C64 ? 8 : 16) >= (1LL << 32) - 16)
+    return no("state array below 4 GiB");
   return true;
 }
 
@@ -618,17 +542,10 @@ abc_status fused_prepare(const abc_params& p, abc_launch& L, std::vector<void*>*
   (void)allocs;
   (void)bytes;
   (void)err;
-  // Stages per launch: the FP64 four-stage pipeline is register bound, so FP64
-  // runs two launches of two stages; first order and boxes wider than 128
-  // columns always do.  ABC_FUSED_STAGES (2 or 4) overrides the default for
-  // Dirichlet and zeroth order; the tile depth (4, 8 or 16 planes) starts at
-  // 8 and is set by the tuner.
-  L.fused_stages = p.dtype == ABC_C128 ? 2 : 4;
-  if (const char* e = std::getenv("ABC_FUSED_STAGES")) {
-    const int v = std::atoi(e);
-    if (v == 2 || v == 4) L.fused_stages = v;
-  }
-  if (p.order == ABC_FIRST || p.nx > kCols) L.fused_stages = 2;
+  // two launches of two Horner stages per step (a four-stage pipeline is
+  // register bound in FP64 and measured slower in both precisions); the tile
+  // depth (4, 8 or 16 planes) starts at 8 and is set by the tuner
+  L.fused_stages = 2;
   L.fused_tz = std::min(8, fused_max_tz(p.order, p.nz));
   return ABC_OK;
 }
@@ -643,8 +560,7 @@ template <typename T>
 hipError_t step_t(const abc_launch& L, const abc_scratch& S, void* psi_v, double2* aux, const void* V_v, int n,
                   hipStream_t st, abc_timer* tm) {
   using C = typename cpx<T>::t;
-  const bool two = L.fused_stages == 2;
-  FusedArgs a = make_args<T>(L, two);
+  FusedArgs a = make_args<T>(L);
   a.has_V = V_v != nullptr;
   C* user = static_cast<C*>(psi_v);
   C* scr = static_cast<C*>(S.y[0]);
@@ -673,15 +589,14 @@ hipError_t step_t(const abc_launch& L, const abc_scratch& S, void* psi_v, double
     fdst = fuser;
   }
   const T* V = static_cast<const T*>(V_v);
-  const int nthreads = 64 * (Tile<T>::TY + 2 * kHalo);
   const int nthreads2 = 64 * (kTY2 + 2 * kHalo2);
   const double dt = L.dt;
   const int tz = L.fused_tz;
-  const dim3 g1(a.ntiles), b4(nthreads), b2(nthreads2);
+  const dim3 g1(a.ntiles), b2(nthreads2);
   const double2* none = nullptr;
   double2* none_w = nullptr;
   for (int s = 0; s < n; ++s) {
-    if (two) {
+    {
       if (L.order == ABC_ZEROTH) {
         launch2<T, 2, true>(tm, "fused2_half_a", tz, g1, b2, st, (const C*)src, (const C*)src, mid, V, a, dt / 4,
                             dt / 3, none, none, none_w);
@@ -698,11 +613,6 @@ hipError_t step_t(const abc_launch& L, const abc_scratch& S, void* psi_v, double
         launch2<T, 0, false>(tm, "fused2_half_b", tz, g1, b2, st, (const C*)mid, (const C*)src, dst, V, a, dt / 2,
                              dt, none, none, none_w);
       }
-    } else {
-      if (L.order == ABC_ZEROTH)
-        abc_launch_kernel(tm, "fused_step", fused_step_kernel<T, 2>, g1, b4, st, (const C*)src, dst, V, a);
-      else
-        abc_launch_kernel(tm, "fused_step", fused_step_kernel<T, 0>, g1, b4, st, (const C*)src, dst, V, a);
     }
     if (tm) tm->end_step();
     std::swap(src, dst);
@@ -735,7 +645,7 @@ int fused_batch_build(const std::vector<FusedMember>& m, void* host, int n) {
   for (int i = 0; i < nb; ++i) {
     const abc_launch& L = *m[i].L;
     const abc_scratch& S = *m[i].S;
-    FusedArgs a = L.dtype == ABC_C64 ? make_args<float>(L, true) : make_args<double>(L, true);
+    FusedArgs a = L.dtype == ABC_C64 ? make_args<float>(L) : make_args<double>(L);
     a.has_V = m[i].V != nullptr;
     char* user = static_cast<char*>(m[i].psi);
     char* scr = static_cast<char*>(S.y[0]);
