@@ -191,26 +191,37 @@ __device__ __forceinline__ void fused2_body(const typename cpx<T>::t* __restrict
 #pragma unroll
   for (int q = 0; q < PF; ++q) fetch(z0 - H + q, q);
 
-  // First order: the tile's face data (auxiliary input av and base fb) staged
-  // in LDS once, for planes z0-1 .. z0+TZ and rows 1 .. ROWS-2 of the tile:
-  // both x faces, and the tile's y-face row and z-face plane if it has them
-  // (at most one of each when ny >= TY + 2 and nz >= TZ + 2), indexed by the
-  // chunk's local column.  Every thread issues all of its loads before
-  // storing any, so the staging costs one memory round trip, overlapped with
-  // the first plane fetch.
+  // First order: the tile's face data staged in LDS once, before the sweep.
+  //  * x faces (both sides): the auxiliary input g = av over the stage-1
+  //    planes z0-1 .. z0+TZ and rows 1 .. ROWS-2, and the base f0 = fb over
+  //    the own planes and rows (the halo wave forms v and the outputs).
+  //  * the tile's y-face row and z-face plane, if it has them (at most one of
+  //    each when ny >= TY + 2 and nz >= TZ + 2): g over the stage-1
+  //    planes/rows, and over the own planes/rows the stage-2 source
+  //    v = f0 + cA (b g + a w) and the output base Q = f0 + cB b v, computed
+  //    here from w in global memory, so that the sweep only adds g or v and
+  //    writes Q + cB a s1.
+  // Every thread issues all of its loads before using any, so the staging
+  // costs one memory round trip, overlapped with the first plane fetch.
   constexpr int FP = TZ + 2, FR = ROWS - 2;
-  constexpr int NX = ORDER == 3 ? 2 * 2 * FP * FR : 1;
-  constexpr int NY = ORDER == 3 ? 2 * FP * kCols : 1;
-  constexpr int NZ = ORDER == 3 ? 2 * FR * kCols : 1;
-  __shared__ double2 fxs[NX];  // [arr][side][plane][row]
-  __shared__ double2 fys[NY];  // [arr][plane][local column]
-  __shared__ double2 fzs[NZ];  // [arr][row][local column]
+  constexpr bool FO = ORDER == 3;
+  constexpr int NXG = FO ? 2 * FP * FR : 1, NXF = FO ? 2 * TZ * TY : 1;
+  constexpr int NYG = FO ? FP * kCols : 1, NYV = FO ? TZ * kCols : 1;
+  constexpr int NZG = FO ? FR * kCols : 1, NZV = FO ? TY * kCols : 1;
+  __shared__ double2 fxg[NXG];  // [side][plane][row]
+  __shared__ double2 fxf[NXF];  // [side][own plane][own row]
+  __shared__ double2 fyg[NYG];  // [plane][local column]
+  __shared__ double2 fyv[NYV], fyq[NYV];  // [own plane][local column]
+  __shared__ double2 fzg[NZG];  // [row][local column]
+  __shared__ double2 fzv[NZV], fzq[NZV];  // [own row][local column]
+  // x-face auxiliary stages v of the next two planes, [plane & 1][own row][side]
+  __shared__ double2 vx[FO ? 2 * TY * 2 : 1];
   int yface = -1, zface = -1;  // face index (2/3, 4/5) of the staged row / plane
   // face slab offsets as scalars (a per-lane index into the argument array
   // would make the compiler loop over the distinct indices)
   const int off_x0 = a.face_off[0], off_x1 = a.face_off[1];
   int off_y = 0, off_z = 0;
-  if (ORDER == 3) {
+  if (FO) {
     const int ylo = y0 - H + 1, zlo = z0 - 1;
     if (ylo <= 0) yface = 2;
     else if (ylo <= ny - 1 && ny - 1 < ylo + FR) yface = 3;
@@ -218,48 +229,103 @@ __device__ __forceinline__ void fused2_body(const typename cpx<T>::t* __restrict
     else if (zlo <= nz - 1 && nz - 1 < zlo + FP) zface = 5;
     off_y = yface == 3 ? a.face_off[3] : a.face_off[2];
     off_z = zface == 5 ? a.face_off[5] : a.face_off[4];
-    constexpr int KX = (NX + NT - 1) / NT, KY = (NY + NT - 1) / NT, KZ = (NZ + NT - 1) / NT;
-    double2 rx[KX], ry[KY], rz[KZ];
+    const int yrow = yface == 3 ? ny - 1 : 0, zpl = zface == 5 ? nz - 1 : 0;
+    constexpr int NXA = NXG + NXF;
+    constexpr int KX = (NXA + NT - 1) / NT, KYG = (NYG + NT - 1) / NT, KYV = (NYV + NT - 1) / NT;
+    constexpr int KZG = (NZG + NT - 1) / NT, KZV = (NZV + NT - 1) / NT;
+    double2 rx[KX], ryg[KYG], rzg[KZG];
+    double2 ryv[KYV][2], rzv[KZV][2];  // (g, f0) of the own planes / rows
+    C ryw[KYV], rzw[KZV];               // w there
 #pragma unroll
     for (int j = 0; j < KX; ++j) {
       const int i = threadIdx.x + j * NT;
-      const int rr = i % FR, pl = (i / FR) % FP, side = (i / (FR * FP)) & 1, arr = i / (2 * FR * FP);
-      const int yy = ylo + rr, zz = zlo + pl;
       rx[j] = make_double2(0, 0);
-      if (i < NX && yy >= 0 && yy < ny && zz >= 0 && zz < nz) rx[j] = (arr ? fb : av)[(side ? off_x1 : off_x0) + zz * ny + yy];
+      if (i < NXG) {
+        const int rr = i % FR, pl = (i / FR) % FP, side = i / (FR * FP);
+        const int yy = ylo + rr, zz = zlo + pl;
+        if (yy >= 0 && yy < ny && zz >= 0 && zz < nz) rx[j] = av[(side ? off_x1 : off_x0) + zz * ny + yy];
+      } else if (i < NXA) {
+        const int e = i - NXG;
+        const int jj = e % TY, pl = (e / TY) % TZ, side = e / (TY * TZ);
+        const int yy = y0 + jj, zz = z0 + pl;
+        if (yy < ny && zz < nz) rx[j] = fb[(side ? off_x1 : off_x0) + zz * ny + yy];
+      }
     }
 #pragma unroll
-    for (int j = 0; j < KY; ++j) {
+    for (int j = 0; j < KYG; ++j) {
       const int i = threadIdx.x + j * NT;
-      const int lx = i % kCols, pl = (i / kCols) % FP;
+      const int lx = i % kCols, pl = i / kCols;
       const int xx = xb + lx, zz = zlo + pl;
-      ry[j] = make_double2(0, 0);
-      if (yface >= 0 && i < NY && xx >= 0 && xx < nx && zz >= 0 && zz < nz)
-        ry[j] = (i >= FP * kCols ? fb : av)[off_y + zz * nx + xx];
+      ryg[j] = make_double2(0, 0);
+      if (yface >= 0 && i < NYG && xx >= 0 && xx < nx && zz >= 0 && zz < nz) ryg[j] = av[off_y + zz * nx + xx];
     }
 #pragma unroll
-    for (int j = 0; j < KZ; ++j) {
+    for (int j = 0; j < KYV; ++j) {
       const int i = threadIdx.x + j * NT;
-      const int lx = i % kCols, rr = (i / kCols) % FR;
-      const int xx = xb + lx, yy = ylo + rr;
-      rz[j] = make_double2(0, 0);
-      if (zface >= 0 && i < NZ && xx >= 0 && xx < nx && yy >= 0 && yy < ny)
-        rz[j] = (i >= FR * kCols ? fb : av)[off_z + yy * nx + xx];
+      const int lx = i % kCols, pl = i / kCols;
+      const int xx = xb + lx, zz = z0 + pl;
+      ryv[j][0] = ryv[j][1] = make_double2(0, 0);
+      ryw[j] = czero<C>();
+      if (yface >= 0 && i < NYV && xx >= 0 && xx < nx && zz < nz) {
+        ryv[j][0] = av[off_y + zz * nx + xx];
+        ryv[j][1] = fb[off_y + zz * nx + xx];
+        ryw[j] = w_in[zz * sz + yrow * nx + xx];
+      }
     }
+#pragma unroll
+    for (int j = 0; j < KZG; ++j) {
+      const int i = threadIdx.x + j * NT;
+      const int lx = i % kCols, rr = i / kCols;
+      const int xx = xb + lx, yy = ylo + rr;
+      rzg[j] = make_double2(0, 0);
+      if (zface >= 0 && i < NZG && xx >= 0 && xx < nx && yy >= 0 && yy < ny) rzg[j] = av[off_z + yy * nx + xx];
+    }
+#pragma unroll
+    for (int j = 0; j < KZV; ++j) {
+      const int i = threadIdx.x + j * NT;
+      const int lx = i % kCols, jj = i / kCols;
+      const int xx = xb + lx, yy = y0 + jj;
+      rzv[j][0] = rzv[j][1] = make_double2(0, 0);
+      rzw[j] = czero<C>();
+      if (zface >= 0 && i < NZV && xx >= 0 && xx < nx && yy < ny) {
+        rzv[j][0] = av[off_z + yy * nx + xx];
+        rzv[j][1] = fb[off_z + yy * nx + xx];
+        rzw[j] = w_in[zpl * sz + yy * nx + xx];
+      }
+    }
+    // v = f0 + cA (b g + a w), Q = f0 + cB b v
+    auto vq = [&](const double2& g, const double2& f0, const C& wv, double2* v_out, double2* q_out) {
+      const double2 bg = cmul(a.b0, g), aw = cmul(a.a0, make_double2((double)wv.x, (double)wv.y));
+      const double2 v = make_double2(f0.x + cA * (bg.x + aw.x), f0.y + cA * (bg.y + aw.y));
+      const double2 bv = cmul(a.b0, v);
+      *v_out = v;
+      *q_out = make_double2(f0.x + cB * bv.x, f0.y + cB * bv.y);
+    };
 #pragma unroll
     for (int j = 0; j < KX; ++j) {
       const int i = threadIdx.x + j * NT;
-      if (i < NX) fxs[i] = rx[j];
+      if (i < NXG) fxg[i] = rx[j];
+      else if (i < NXA) fxf[i - NXG] = rx[j];
     }
 #pragma unroll
-    for (int j = 0; j < KY; ++j) {
+    for (int j = 0; j < KYG; ++j) {
       const int i = threadIdx.x + j * NT;
-      if (i < NY) fys[i] = ry[j];
+      if (i < NYG) fyg[i] = ryg[j];
     }
 #pragma unroll
-    for (int j = 0; j < KZ; ++j) {
+    for (int j = 0; j < KYV; ++j) {
       const int i = threadIdx.x + j * NT;
-      if (i < NZ) fzs[i] = rz[j];
+      if (i < NYV) vq(ryv[j][0], ryv[j][1], ryw[j], &fyv[i], &fyq[i]);
+    }
+#pragma unroll
+    for (int j = 0; j < KZG; ++j) {
+      const int i = threadIdx.x + j * NT;
+      if (i < NZG) fzg[i] = rzg[j];
+    }
+#pragma unroll
+    for (int j = 0; j < KZV; ++j) {
+      const int i = threadIdx.x + j * NT;
+      if (i < NZV) vq(rzv[j][0], rzv[j][1], rzw[j], &fzv[i], &fzq[i]);
     }
   }
   __syncthreads();
@@ -267,6 +333,38 @@ __device__ __forceinline__ void fused2_body(const typename cpx<T>::t* __restrict
 #pragma unroll
   for (int it = 0; it < ITERS; ++it) {
     const int zi = z0 - H + it;
+    if (ORDER == 3 && r == 0 && lane < 2 * TY) {
+      // First-order x faces, done by the top halo wave (idle in both stages),
+      // one lane per (own row, side).  It reads the rows published at the end
+      // of the previous iteration: plane[0] holds w at plane zi-1 and
+      // plane[1] the stage-1 output s1 at plane zi-2.
+      //  * v_f = fb_f + cA (b av_f + a w) at plane zi-1, for the next
+      //    iteration's stage 2 (LDS ring);
+      //  * the auxiliary output fb_f + cB (b v_f + a s1) at plane zi-2.
+      const int j = lane >> 1, side = lane & 1;
+      const int rj = H + j, yj = y0 + j;
+      const int xf = side ? nx - 1 : 0, lxf = xf - xb;
+      if (lxf >= 0 && lxf < kCols && yj < ny) {
+        const int ci = lxf & 1, li = (lxf >> 1) + 1, rr = rj - 1;
+        const int p1 = zi - 1, p2 = zi - 2;
+        if (p1 >= z0 && p1 < z0 + TZ && p1 < nz) {
+          const int pl = p1 - (z0 - 1);
+          const double2 g = fxg[(side * FP + pl) * FR + rr];
+          const double2 f0 = fxf[(side * TZ + (p1 - z0)) * TY + j];
+          const C wv = plane[0][rj][ci][li];
+          const double2 bg = cmul(a.b0, g), aw = cmul(a.a0, make_double2((double)wv.x, (double)wv.y));
+          vx[((p1 & 1) * TY + j) * 2 + side] = make_double2(f0.x + cA * (bg.x + aw.x), f0.y + cA * (bg.y + aw.y));
+        }
+        if (p2 >= z0 && p2 < z0 + TZ && p2 < nz && xf >= xo && xf < xe) {
+          const double2 f0 = fxf[(side * TZ + (p2 - z0)) * TY + j];
+          const double2 v = vx[((p2 & 1) * TY + j) * 2 + side];
+          const C s1 = plane[1][rj][ci][li];
+          const double2 bv = cmul(a.b0, v), as1 = cmul(a.a0, make_double2((double)s1.x, (double)s1.y));
+          aux_out[(side ? off_x1 : off_x0) + p2 * ny + yj] =
+              make_double2(f0.x + cB * (bv.x + as1.x), f0.y + cB * (bv.y + as1.y));
+        }
+      }
+    }
     C prev[2];
     T vcur[2];
     C bcur[2], wm2[2];  // base at plane zi; w at plane zi - 2 (before the slide)
@@ -317,78 +415,60 @@ __device__ __forceinline__ void fused2_body(const typename cpx<T>::t* __restrict
       if (ORDER == 3 && active) {
         // First order: the psi stage also sees -i sum_f g_f at face points,
         // with g = the auxiliary input (stage 1) or the auxiliary stage
-        // v_f = fb_f + cA (b av_f + a w) (stage 2), which also produces the
-        // auxiliary output fb_f + cB (b v_f + a s1) at owned points.  The
-        // correction -i cf (sum g) is added to the plain stage output.  On a
-        // y- or z-face row (wave-uniform) both columns of every lane are face
-        // points; elsewhere a lane has at most one x-face column, so the wave
-        // pays for a single divergent pass.
-        const bool fyz = y == 0 || y == ny - 1 || zk == 0 || zk == nz - 1;
+        // v_f = fb_f + cA (b av_f + a w) (stage 2), added to the plain stage
+        // output as -i cf g.
         const int pl = zk - (z0 - 1), rr = r - 1;
-        const bool own_pt = k == 2 && own_row && it >= 2 * H;
         const double cf2 = k == 1 ? cA : cB;
-        // correction (re, im) at local column lx with stage input cenc and w
-        auto corr = [&](int lx, const C& cenc, const C& wc) {
-          const int x = xb + lx;
-          const bool fx = x == 0 || x == nx - 1, fy = y == 0 || y == ny - 1, fz = zk == 0 || zk == nz - 1;
-          double sr = 0, si = 0;
-          double2 aw = make_double2(0, 0), as1 = make_double2(0, 0);
-          if (k == 2) {
-            aw = cmul(a.a0, make_double2((double)wc.x, (double)wc.y));
-            as1 = cmul(a.a0, make_double2((double)cenc.x, (double)cenc.y));
-          }
-          const bool own = own_pt && x >= xo && x < xe;
-          // one face through the point: its auxiliary input g and base f0
-          auto face = [&](const double2* lds_g, const double2* lds_f, int gi) {
-            const double2 g = *lds_g;
-            if (k == 1) {
-              sr += g.x;
-              si += g.y;
-              return;
-            }
-            const double2 f0 = *lds_f;
-            const double2 bg = cmul(a.b0, g);
-            const double2 v = make_double2(f0.x + cA * (bg.x + aw.x), f0.y + cA * (bg.y + aw.y));
-            sr += v.x;
-            si += v.y;
-            if (own) {
-              const double2 bv = cmul(a.b0, v);
-              aux_out[gi] = make_double2(f0.x + cB * (bv.x + as1.x), f0.y + cB * (bv.y + as1.y));
-            }
-          };
-          if (fx) {
-            const int side = x == 0 ? 0 : 1;
-            face(&fxs[((0 * 2 + side) * FP + pl) * FR + rr], &fxs[((1 * 2 + side) * FP + pl) * FR + rr],
-                 (side ? off_x1 : off_x0) + zk * ny + y);
-          }
-          if (fy)
-            face(&fys[(0 * FP + pl) * kCols + lx], &fys[(1 * FP + pl) * kCols + lx], off_y + zk * nx + x);
-          if (fz)
-            face(&fzs[(0 * FR + rr) * kCols + lx], &fzs[(1 * FR + rr) * kCols + lx], off_z + y * nx + x);
-          return make_double2(cf2 * si, -cf2 * sr);
-        };
-        if (fyz) {
-#pragma unroll
-          for (int c = 0; c < 2; ++c) {
-            const int x = xb + 2 * lane + c;
-            if (x >= 0 && x < nx) {
-              const double2 d = corr(2 * lane + c, Yc[k - 1][c], wm2[c]);
-              o[c].x += T(d.x);
-              o[c].y += T(d.y);
-            }
-          }
-        } else {
+        // x faces: at most one column per lane, its source ready in LDS
+        // (stage 1: av; stage 2: v from the halo wave's ring)
+        {
           const int x0 = xb + 2 * lane;
           const int cx = (x0 == 0 || x0 == nx - 1) ? 0 : ((x0 + 1 == nx - 1) ? 1 : -1);
           if (cx >= 0) {
-            const C cenc = cx ? Yc[k - 1][1] : Yc[k - 1][0];
-            const C wc = cx ? wm2[1] : wm2[0];
-            const double2 d = corr(2 * lane + cx, cenc, wc);
-            const T dx = T(d.x), dy = T(d.y);
+            const int side = x0 + cx == 0 ? 0 : 1;
+            const double2 g = k == 1 ? fxg[(side * FP + pl) * FR + rr] : vx[((zk & 1) * TY + (r - H)) * 2 + side];
+            const T dx = T(cf2 * g.y), dy = T(-cf2 * g.x);
             o[0].x += cx ? T(0) : dx;
             o[0].y += cx ? T(0) : dy;
             o[1].x += cx ? dx : T(0);
             o[1].y += cx ? dy : T(0);
+          }
+        }
+        // y and z faces: whole rows (wave-uniform), both columns of each lane,
+        // sources precomputed at staging; stage 2 also writes the auxiliary
+        // outputs Q + cB a s1 at owned points
+        const bool fy = y == 0 || y == ny - 1, fz = zk == 0 || zk == nz - 1;
+        if (fy || fz) {
+          const bool own_pt = k == 2 && own_row && it >= 2 * H;
+          const double2 ba = make_double2(cB * a.a0.x, cB * a.a0.y);
+#pragma unroll
+          for (int c = 0; c < 2; ++c) {
+            const int lx = 2 * lane + c, x = xb + lx;
+            if (x < 0 || x >= nx) continue;
+            const bool own = own_pt && x >= xo && x < xe;
+            double sr = 0, si = 0;
+            double2 as1 = make_double2(0, 0);
+            if (k == 2 && own) as1 = cmul(ba, make_double2((double)Yc[1][c].x, (double)Yc[1][c].y));
+            if (fy) {
+              const double2 g = k == 1 ? fyg[pl * kCols + lx] : fyv[(zk - z0) * kCols + lx];
+              sr += g.x;
+              si += g.y;
+              if (own) {
+                const double2 q = fyq[(zk - z0) * kCols + lx];
+                aux_out[off_y + zk * nx + x] = make_double2(q.x + as1.x, q.y + as1.y);
+              }
+            }
+            if (fz) {
+              const double2 g = k == 1 ? fzg[rr * kCols + lx] : fzv[(r - H) * kCols + lx];
+              sr += g.x;
+              si += g.y;
+              if (own) {
+                const double2 q = fzq[(r - H) * kCols + lx];
+                aux_out[off_z + y * nx + x] = make_double2(q.x + as1.x, q.y + as1.y);
+              }
+            }
+            o[c].x += T(cf2 * si);
+            o[c].y += T(-cf2 * sr);
           }
         }
       }
