@@ -214,6 +214,38 @@ def bench_tdhf(Solver, torch, W, steps=10):
             "value": n ** 3 * nb * steps / (ms / 1e3), "unit": "orbital-point-updates/s", "path": "staged"}
 
 
+def bench_r3(Solver, torch, wl, steps=20):
+    """The same 128^3 first-order workload with the seven-points-per-axis
+    stencil (R = 3), which runs on the general staged path."""
+    s = Solver((wl.n,) * 3, wl.h, wl.dt, radius=3, order="first", s1=wl.s1, window=wl.window)
+    psi = torch.from_numpy(wl.psi0).cuda()
+    V = torch.from_numpy(wl.V).cuda()
+    aux = s.new_aux()
+    s.step(psi, aux, V, 2)
+    ms = _time(torch, lambda: s.step(psi, aux, V, steps))
+    return {"radius": 3, "ms_per_step": ms / steps, "value": wl.n ** 3 * steps / (ms / 1e3),
+            "unit": "grid-point-updates/s", "path": "fused" if s.use_fused else "staged"}
+
+
+def bench_box_batch(Solver, torch, W, nb=32, steps=20):
+    """Paper-literal dense box form (32^3, R = 1, zeroth order, free packet)
+    over an orbital batch: one complex GEMM per stage for all orbitals,
+    against the single-orbital GEMV path run once per orbital."""
+    wl = W.free_packet_small()
+    n = wl.n
+    psi1 = torch.from_numpy(wl.psi0).cuda()
+    s1 = Solver((n,) * 3, wl.h, wl.dt, order="zeroth", form="box", s0=wl.s0)
+    s1.step(psi1, None, None, 2)
+    ms1 = _time(torch, lambda: s1.step(psi1, None, None, steps))
+    sb = Solver((n,) * 3, wl.h, wl.dt, order="zeroth", form="box", s0=wl.s0, batch=nb)
+    psib = psi1.unsqueeze(-1).repeat(1, 1, 1, nb).contiguous()
+    sb.step(psib, None, None, 2)
+    msb = _time(torch, lambda: sb.step(psib, None, None, steps))
+    return {"grid": n, "orbitals": nb, "value_gemm_batch": n ** 3 * nb * steps / (msb / 1e3),
+            "value_single_orbital": n ** 3 * steps / (ms1 / 1e3), "unit": "orbital-point-updates/s",
+            "speedup_vs_per_orbital": (ms1 * nb) / msb}
+
+
 def cpu_baseline(wl, window, budget_s=15.0):
     """FP64 oracle (NumPy, single-threaded elementwise) on the same workload,
     for as many whole steps as fit in about budget_s seconds."""
@@ -345,7 +377,9 @@ def main():
         for name, fn in (("c64", lambda: bench_c64(Solver, torch, wl, 200, psi_ref)),
                          ("batch", lambda: bench_batch(Batch, Solver, torch, W)),
                          ("adjoint", lambda: bench_adjoint(Solver, torch, W)),
-                         ("tdhf", lambda: bench_tdhf(Solver, torch, W))):
+                         ("tdhf", lambda: bench_tdhf(Solver, torch, W)),
+                         ("r3", lambda: bench_r3(Solver, torch, wl)),
+                         ("box_batch", lambda: bench_box_batch(Solver, torch, W))):
             log("extra: %s" % name)
             try:
                 extra[name] = fn()

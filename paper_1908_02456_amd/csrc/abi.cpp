@@ -7,6 +7,8 @@
 #include <string>
 #include <vector>
 
+#include <rocblas/rocblas.h>
+
 #include "abc_internal.h"
 #include "fused.h"
 
@@ -34,6 +36,7 @@ struct abc_ctx {
   double2* box_mat = nullptr;
   double2* box_q = nullptr;
   std::vector<std::string> launch_labels;  // launches of a step, from the last abc_step_timed
+  rocblas_handle blas = nullptr;           // box form over an orbital batch
   abc_launch La{};                         // adjoint operator set (built on first abc_adjoint)
   bool adjoint_ready = false;
 };
@@ -104,6 +107,7 @@ const char* abc_last_error(void) { return g_last_error.c_str(); }
 
 void abc_destroy(abc_ctx* c) {
   if (!c) return;
+  if (c->blas) rocblas_destroy_handle(c->blas);
   for (void* ptr : c->allocations) (void)hipFree(ptr);
   delete c;
 }
@@ -224,6 +228,28 @@ abc_status abc_setup(const abc_params* pp, abc_ctx** out) {
     S.facc = static_cast<double2*>(tmp);
     if ((st = dev_alloc(c, &tmp, naux * 16)) != ABC_OK) { abc_destroy(c); return st; }
     S.src = static_cast<double2*>(tmp);
+    if (p.form == ABC_FORM_BOX && p.batch > 1) {
+      // the operator over the orbital batch is one complex GEMM per stage;
+      // a first call here lets rocBLAS finish its lazy setup (no allocation
+      // in abc_step afterwards)
+      if ((st = dev_alloc(c, &tmp, naux * 16)) != ABC_OK) { abc_destroy(c); return st; }
+      S.bwork[0] = static_cast<double2*>(tmp);
+      if ((st = dev_alloc(c, &tmp, naux * 16)) != ABC_OK) { abc_destroy(c); return st; }
+      S.bwork[1] = static_cast<double2*>(tmp);
+      const int n = c->n_gamma, nb = p.batch, ld = p.order == ABC_FIRST ? 2 * n : n;
+      const rocblas_double_complex one = {1.0, 0.0}, zero = {0.0, 0.0};
+      if (rocblas_create_handle(&c->blas) != rocblas_status_success ||
+          hipMemset(S.bwork[0], 0, naux * 16) != hipSuccess ||
+          rocblas_zgemm(c->blas, rocblas_operation_none, rocblas_operation_none, nb, n, n, &one,
+                        reinterpret_cast<const rocblas_double_complex*>(S.bwork[0]), nb,
+                        reinterpret_cast<const rocblas_double_complex*>(L.box_mat), ld, &zero,
+                        reinterpret_cast<rocblas_double_complex*>(S.bwork[1]), nb) != rocblas_status_success ||
+          hipDeviceSynchronize() != hipSuccess) {
+        abc_destroy(c);
+        return fail(ABC_EDEVICE, "rocBLAS setup for the batched box form failed");
+      }
+      L.blas = c->blas;
+    }
   }
   if (p.meanfield) {
     if ((st = dev_alloc(c, &S.veff, (size_t)L.g.npts * rsz)) != ABC_OK) { abc_destroy(c); return st; }

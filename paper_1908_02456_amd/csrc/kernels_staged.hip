@@ -9,6 +9,8 @@
 // (Sec. 3 dynamics) and accumulates z_0 + ... + z_4 (Sec. 4 Taylor step).
 #include <hip/hip_runtime.h>
 
+#include <rocblas/rocblas.h>
+
 #include "abc_internal.h"
 
 using abc::Geometry;
@@ -490,6 +492,48 @@ LocalBlock make_local(const double2* m) {
   return a;
 }
 
+// ---------------------------------------------------------------------------
+// box form over an orbital batch: the operator is applied to all orbitals at
+// once as a dense complex GEMM (rocBLAS zgemm, matrix cores) instead of one
+// matrix pass per orbital.  gather: E y -> [gamma][orbital]; epilogue: the
+// first-order aux stage update of box_gemv_kernel on the GEMM result.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(kBlock) box_gather_kernel(const typename cpx<T>::t* __restrict__ yin,
+                                                            const int* __restrict__ gamma_lin, int n, int batch,
+                                                            double2* __restrict__ out) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long long)n * batch) return;
+  const long long gi = e / batch;
+  const int b = (int)(e - gi * batch);
+  const auto v = yin[(long long)gamma_lin[gi] * batch + b];
+  out[e] = make_double2((double)v.x, (double)v.y);
+}
+
+__global__ void __launch_bounds__(kBlock) box_epilogue_kernel(const double2* __restrict__ t,
+                                                              const double2* __restrict__ gin,
+                                                              double2* __restrict__ gout, double2* __restrict__ facc,
+                                                              double2* __restrict__ aux_out, long long count,
+                                                              double coef, int mode) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= count) return;
+  const double2 gn = make_double2(coef * t[e].x, coef * t[e].y);
+  if (mode == 0) {
+    const double2 g0 = gin[e];
+    facc[e] = make_double2(g0.x + gn.x, g0.y + gn.y);
+    gout[e] = gn;
+  } else if (mode == 1) {
+    double2 s2 = facc[e];
+    s2.x += gn.x;
+    s2.y += gn.y;
+    facc[e] = s2;
+    gout[e] = gn;
+  } else {
+    const double2 s2 = facc[e];
+    aux_out[e] = make_double2(s2.x + gn.x, s2.y + gn.y);
+  }
+}
+
 inline unsigned nblocks(long long n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
 template <typename T, int R, bool PER>
@@ -525,7 +569,33 @@ hipError_t step_staged_t(const abc_launch& L, const abc_scratch& S, void* psi_v,
       const double2* bsrc = nullptr;
       if (first || zeroth) {
         double2* gnext = (k == 4) ? nullptr : S.g[(k - 1) & 1];
-        if (box) {
+        if (box && L.blas && g.batch > 1) {
+          // Y^T = X^T M^T in rocBLAS's column-major view of the row-major
+          // operator [B | A] (n x 2n) or M (n x n): T = B g + A E y, or M E y
+          const int n = L.n_gamma, nb = g.batch, ld = first ? 2 * n : n;
+          const long long cnt = (long long)n * nb;
+          abc_launch_kernel(tm, kBoundLabel[k], box_gather_kernel<T>, dim3(nblocks(cnt)), dim3(kBlock), st,
+                            (const C*)ycur, L.gamma_lin, n, nb, S.bwork[0]);
+          double2* tout = first ? S.bwork[1] : S.src;
+          if (tm) tm->mark_host(st, "box_gemm");
+          const rocblas_double_complex one = {1.0, 0.0}, zero = {0.0, 0.0};
+          rocblas_handle hb = static_cast<rocblas_handle>(L.blas);
+          rocblas_status rs = rocblas_set_stream(hb, st);
+          if (rs == rocblas_status_success && first)
+            rs = rocblas_zgemm(hb, rocblas_operation_none, rocblas_operation_none, nb, n, n, &one,
+                               reinterpret_cast<const rocblas_double_complex*>(gcur), nb,
+                               reinterpret_cast<const rocblas_double_complex*>(L.box_mat), ld, &zero,
+                               reinterpret_cast<rocblas_double_complex*>(tout), nb);
+          if (rs == rocblas_status_success)
+            rs = rocblas_zgemm(hb, rocblas_operation_none, rocblas_operation_none, nb, n, n, &one,
+                               reinterpret_cast<const rocblas_double_complex*>(S.bwork[0]), nb,
+                               reinterpret_cast<const rocblas_double_complex*>(L.box_mat + (first ? n : 0)), ld,
+                               first ? &one : &zero, reinterpret_cast<rocblas_double_complex*>(tout), nb);
+          if (rs != rocblas_status_success) return hipErrorLaunchFailure;
+          if (first)
+            abc_launch_kernel(tm, "box_epilogue", box_epilogue_kernel, dim3(nblocks(cnt)), dim3(kBlock), st,
+                              (const double2*)tout, gcur, gnext, S.facc, aux, cnt, coef, mode);
+        } else if (box) {
           const int ncol = first ? 2 * L.n_gamma : L.n_gamma;
           dim3 grid(L.n_gamma, g.batch);
           abc_launch_kernel(tm, kBoundLabel[k], box_gemv_kernel<T>, grid, dim3(kBlock), st, L.box_mat, L.n_gamma,

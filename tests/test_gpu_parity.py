@@ -236,3 +236,15 @@ def test_fused_first_order_small_box_falls_back():
     assert not s.use_fused
     r = _run_pair("fused-fallback", (9, 8, 20), 0.25, 0.004, 1, "first", 4, s1=1.5, window=0, path="auto")
     assert r["err"] < TOL64 and r["aux_err"] < TOL64
+
+
+@pytest.mark.parametrize("R,order,s2", [(1, "zeroth", math.inf), (1, "first", math.inf), (2, "first", math.inf),
+                                        (1, "first", 2.0)])
+def test_box_form_orbital_batch_parity(R, order, s2):
+    # box form over an orbital batch: the operator is applied as one complex
+    # GEMM per stage (rocBLAS) instead of one matrix pass per orbital
+    n = 6 if R == 1 else 7
+    r = _run_pair("box-batch", (n, n, n), 0.3, 0.004, R, order, 5, form="box", s0=1.0, s1=1.0, s2=s2, batch=5)
+    assert r["err"] < TOL64, r["err"]
+    if order == "first":
+        assert r["aux_err"] < TOL64, r["aux_err"]
