@@ -154,9 +154,10 @@ enum { ABC_OBJ_PROB = 0, ABC_OBJ_ENERGY = 1 };
  * grad_psi0 (device, complex128, psi's layout, caller-owned) and dJ/dV to
  * grad_V (device, float64 [z][y][x], caller-owned).  psi0 and V are device
  * buffers of the context's box (V may be NULL for V = 0).  Checkpoints every
- * ckpt_stride steps (<= 0: ceil(sqrt(n_steps))); device memory for
- * (n/stride + stride + 10) states is allocated and freed by the call, which
- * synchronises the stream.  Supported: complex128, one orbital, no mean
+ * ckpt_stride steps (<= 0: ceil(sqrt(n_steps))) during a forward sweep on
+ * the context's path; each segment is recomputed once, keeping its states
+ * and stage vectors.  Device memory for about n/stride + 4 stride + 8 states
+ * is allocated and freed by the call, which synchronises the stream.  Supported: complex128, one orbital, no mean
  * field; Dirichlet and periodic boxes; face-form zeroth order (any R) and
  * first order (R = 1).  Others: ABC_ENOTSUP.  ABC_ENOMEM if the buffers do
  * not fit, ABC_EDEVICE on HIP failures. */

@@ -159,6 +159,7 @@ struct abc_adjoint_args {
   void* grad_psi0;
   double* grad_V;
   double* J_host;
+  int use_fused;  // forward sweep on the fused path
 };
 abc_status run_adjoint(const abc_launch& L, const abc_launch& La, const abc_scratch& S, const abc_adjoint_args& a,
                        hipStream_t st, std::string& err);

@@ -385,7 +385,7 @@ abc_status abc_adjoint(abc_ctx* c, const void* psi0, const void* V, int n_steps,
     abc_status st = build_adjoint(c);
     if (st != ABC_OK) return st;
   }
-  abc_adjoint_args a{psi0, V, n_steps, ckpt_stride, objective, grad_psi0, grad_V, J_out};
+  abc_adjoint_args a{psi0, V, n_steps, ckpt_stride, objective, grad_psi0, grad_V, J_out, c->use_fused};
   std::string err;
   abc_status st = run_adjoint(c->L, c->La, c->S, a, static_cast<hipStream_t>(stream), err);
   if (st != ABC_OK) return fail(st, err);

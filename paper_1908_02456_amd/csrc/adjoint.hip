@@ -15,8 +15,10 @@
 // polynomial gives
 //   dJ/dV_p += dt sum_{j+m<=3} j! m! / (j+m+1)! Im(conj(y_j[p]) z_m[p]).
 //
-// Checkpoints every `stride` steps (default ceil(sqrt(n))); each segment is
-// recomputed forward once into a segment store, then walked backwards.
+// Checkpoints every `stride` steps (default ceil(sqrt(n))), taken during a
+// forward sweep on the fastest available path; each segment is recomputed
+// once on the staged kernels, keeping every step's state and forward stage
+// vectors, then walked backwards with one adjoint step per step.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -25,6 +27,7 @@
 #include <vector>
 
 #include "abc_internal.h"
+#include "fused.h"
 
 using abc::Geometry;
 
@@ -192,7 +195,10 @@ abc_status run_adjoint(const abc_launch& L, const abc_launch& La, const abc_scra
   const size_t pb = np * sizeof(double2), fb = std::max<size_t>(nf, 1) * sizeof(double2);
   const size_t round = 256;
   const int nb = (int)((np + kBlock - 1) / kBlock);
-  const size_t total = (10 + (size_t)nck + nseg) * (pb + round) + (3 + (size_t)nck + nseg) * (fb + round) +
+  // psi-sized: X, lam, y0, 3 adjoint stage vectors, checkpoints, segment
+  // states and 3 forward stage vectors per segment step
+  const size_t npsi = 6 + (size_t)nck + nseg + 3 * (size_t)nseg;
+  const size_t total = npsi * (pb + round) + (2 + (size_t)nck + nseg) * (fb + round) +
                        ((size_t)nb + 1) * sizeof(double) + 2 * round;
   Arena ar;
   hipError_t e = hipMalloc(&ar.base, total);
@@ -203,15 +209,14 @@ abc_status run_adjoint(const abc_launch& L, const abc_launch& La, const abc_scra
   ar.cap = total;
   double2* X = ar.take<double2>(pb);
   double2* lam = ar.take<double2>(pb);
-  double2* z0 = ar.take<double2>(pb);
   double2* y0 = ar.take<double2>(pb);
-  void* kz[3];
   void* ky[3];
-  for (int i = 0; i < 3; ++i) kz[i] = ar.take<double2>(pb);
   for (int i = 0; i < 3; ++i) ky[i] = ar.take<double2>(pb);
   std::vector<double2*> ckp(nck), seg(nseg);
   for (auto& q : ckp) q = ar.take<double2>(pb);
   for (auto& q : seg) q = ar.take<double2>(pb);
+  std::vector<void*> kz(3 * (size_t)nseg);
+  for (auto& q : kz) q = ar.take<double2>(pb);
   double2* fX = ar.take<double2>(fb);
   double2* mu = ar.take<double2>(fb);
   std::vector<double2*> ckf(nck), segf(nseg);
@@ -238,7 +243,7 @@ abc_status run_adjoint(const abc_launch& L, const abc_launch& La, const abc_scra
     ABC_TRY(hipMemcpyAsync(ckp[c], X, pb, hipMemcpyDeviceToDevice, st));
     if (nf) ABC_TRY(hipMemcpyAsync(ckf[c], fX, nf * sizeof(double2), hipMemcpyDeviceToDevice, st));
     const int k = std::min(stride, N - c * stride);
-    ABC_TRY(launch_step_staged(L, S, X, aux, V, k, st));
+    ABC_TRY(a.use_fused ? launch_step_fused(L, S, X, aux, V, k, st) : launch_step_staged(L, S, X, aux, V, k, st));
   }
   // objective at psi_N; the adjoint aux starts at zero
   ABC_TRY(objective(L, X, V, a.objective, lam, a.grad_V, partial, Jd, st));
@@ -248,23 +253,24 @@ abc_status run_adjoint(const abc_launch& L, const abc_launch& La, const abc_scra
   // backward over segments
   for (int c = nck - 1; c >= 0; --c) {
     const int s0 = c * stride, len = std::min(stride, N - s0);
+    // recompute the segment, keeping each step's state and stage vectors
     ABC_TRY(hipMemcpyAsync(seg[0], ckp[c], pb, hipMemcpyDeviceToDevice, st));
     if (nf) ABC_TRY(hipMemcpyAsync(segf[0], ckf[c], nf * sizeof(double2), hipMemcpyDeviceToDevice, st));
-    for (int i = 1; i < len; ++i) {
-      ABC_TRY(hipMemcpyAsync(seg[i], seg[i - 1], pb, hipMemcpyDeviceToDevice, st));
-      if (nf) ABC_TRY(hipMemcpyAsync(segf[i], segf[i - 1], nf * sizeof(double2), hipMemcpyDeviceToDevice, st));
-      ABC_TRY(launch_step_staged(L, S, seg[i], nf ? segf[i] : nullptr, V, 1, st));
+    for (int i = 0; i < len; ++i) {
+      double2* next = i + 1 < len ? seg[i + 1] : X;
+      double2* nextf = i + 1 < len ? segf[i + 1] : fX;
+      ABC_TRY(hipMemcpyAsync(next, seg[i], pb, hipMemcpyDeviceToDevice, st));
+      if (nf) ABC_TRY(hipMemcpyAsync(nextf, segf[i], nf * sizeof(double2), hipMemcpyDeviceToDevice, st));
+      ABC_TRY(launch_step_staged(L, S, next, nf ? nextf : nullptr, V, 1, st, nullptr, &kz[3 * (size_t)i]));
     }
     for (int i = len - 1; i >= 0; --i) {
-      // forward stage vectors of step s0 + i (the segment state is consumed)
-      ABC_TRY(hipMemcpyAsync(z0, seg[i], pb, hipMemcpyDeviceToDevice, st));
-      ABC_TRY(launch_step_staged(L, S, seg[i], nf ? segf[i] : nullptr, V, 1, st, nullptr, kz));
       // adjoint step, keeping its stage vectors
       ABC_TRY(hipMemcpyAsync(y0, lam, pb, hipMemcpyDeviceToDevice, st));
       ABC_TRY(launch_step_staged(La, S, lam, nf ? mu : nullptr, V, 1, st, nullptr, ky));
       vgrad_kernel<<<gb, kBlock, 0, st>>>(a.grad_V, y0, static_cast<double2*>(ky[0]), static_cast<double2*>(ky[1]),
-                                          static_cast<double2*>(ky[2]), z0, static_cast<double2*>(kz[0]),
-                                          static_cast<double2*>(kz[1]), static_cast<double2*>(kz[2]), npl, L.dt);
+                                          static_cast<double2*>(ky[2]), seg[i], static_cast<double2*>(kz[3 * i]),
+                                          static_cast<double2*>(kz[3 * i + 1]), static_cast<double2*>(kz[3 * i + 2]),
+                                          npl, L.dt);
       ABC_TRY(hipGetLastError());
     }
   }

@@ -136,7 +136,10 @@ __device__ __forceinline__ void fused2_body(const typename cpx<T>::t* __restrict
   constexpr int ROWS = TY + 2 * H;
   constexpr int NT = 64 * ROWS;
   constexpr int ITERS = TZ + 2 * H;
-  __shared__ C plane[2][ROWS][2][66];
+  // rows published for the y/x neighbours; double-buffered (one barrier per
+  // plane) where LDS allows, i.e. without the first-order face staging
+  constexpr int DBN = ORDER == 3 ? 1 : 2;
+  __shared__ C planes[DBN][2][ROWS][2][66];
 
   const int lane = threadIdx.x & 63;
   const int r = threadIdx.x >> 6;
@@ -153,7 +156,7 @@ __device__ __forceinline__ void fused2_body(const typename cpx<T>::t* __restrict
   const int xo = tx * a.xw, xe = min(xo + a.xw, nx);
   const int xb = a.ntx == 1 ? 0 : xo - H;
 
-  for (int i = threadIdx.x; i < 2 * ROWS * 2 * 66; i += NT) (&plane[0][0][0][0])[i] = czero<C>();
+  for (int i = threadIdx.x; i < DBN * 2 * ROWS * 2 * 66; i += NT) (&planes[0][0][0][0][0])[i] = czero<C>();
 
   C Yc[2][2], Yb[2][2];  // stage inputs: centre / below (j = 0: w, j = 1: stage-1 output)
   C Bd[2][2];            // base at planes zi-1, zi-2 (separate base only)
@@ -333,6 +336,7 @@ __device__ __forceinline__ void fused2_body(const typename cpx<T>::t* __restrict
 #pragma unroll
   for (int it = 0; it < ITERS; ++it) {
     const int zi = z0 - H + it;
+    auto& plane = planes[DBN == 2 ? (it & 1) : 0];  // rows published by the previous iteration
     if (ORDER == 3 && r == 0 && lane < 2 * TY) {
       // First-order x faces, done by the top halo wave (idle in both stages),
       // one lane per (own row, side).  It reads the rows published at the end
@@ -492,11 +496,14 @@ __device__ __forceinline__ void fused2_body(const typename cpx<T>::t* __restrict
         Bd[0][c] = bcur[c];
       }
     }
-    sync_lds();
+    // publish this plane's stage inputs; with a single buffer every wave
+    // must first be done reading the previous ones
+    auto& pnext = planes[DBN == 2 ? ((it + 1) & 1) : 0];
+    if (DBN == 1) sync_lds();
 #pragma unroll
     for (int j = 0; j < 2; ++j)
 #pragma unroll
-      for (int c = 0; c < 2; ++c) plane[j][r][c][lane + 1] = Yc[j][c];
+      for (int c = 0; c < 2; ++c) pnext[j][r][c][lane + 1] = Yc[j][c];
     sync_lds();
   }
 }

@@ -61,10 +61,13 @@ def test_adjoint_zero_steps_and_strides_agree():
     s = Solver(shape, 0.25, 0.004, order="first", s1=1.0, window=0)
     J0, g0, gV0 = s.adjoint(psi0, V, 0, "prob")
     assert torch.allclose(g0, 2 * 0.25 ** 3 * psi0, rtol=0, atol=0) and float(gV0.abs().max()) == 0.0
+    # checkpoints come from the forward sweep (fused path) and segment states
+    # from the staged recompute, so strides agree to rounding, not bit for bit
     outs = [s.adjoint(psi0, V, 13, "prob", st) for st in (1, 4, 0, 13, 50)]
     for J, g, gV in outs[1:]:
         assert J == outs[0][0]
-        assert torch.equal(g, outs[0][1]) and torch.equal(gV, outs[0][2])
+        assert float((g - outs[0][1]).abs().max()) < 1e-12 * float(outs[0][1].abs().max())
+        assert float((gV - outs[0][2]).abs().max()) < 1e-12 * float(outs[0][2].abs().max())
 
 
 def test_adjoint_rejects_unsupported():
