@@ -202,7 +202,8 @@ def bench_adjoint(Solver, torch, W):
 
 def bench_tdhf(Solver, torch, W, steps=10):
     """32 oscillator orbitals on 96^3 with the mean field U = -rho + 0.5 rho^2,
-    first-order condition, complex64 stencil / FP64 aux (staged path)."""
+    first-order condition, complex64 stencil / FP64 aux (orbitals as boxes of
+    one fused launch, the mean field rebuilt every step)."""
     n, nb, h = 96, 32, 0.2
     orb = W.oscillator_orbitals((n,) * 3, h, nb, seed=3)
     s = Solver((n,) * 3, h, 0.002, order="first", s1=1.0, window=0, dtype="c64", batch=nb, meanfield=(-1.0, 0.5))
@@ -211,7 +212,8 @@ def bench_tdhf(Solver, torch, W, steps=10):
     s.step(psi, aux, None, 2)
     ms = _time(torch, lambda: s.step(psi, aux, None, steps))
     return {"grid": n, "orbitals": nb, "steps": steps, "ms_per_step": ms / steps,
-            "value": n ** 3 * nb * steps / (ms / 1e3), "unit": "orbital-point-updates/s", "path": "staged"}
+            "value": n ** 3 * nb * steps / (ms / 1e3), "unit": "orbital-point-updates/s",
+            "path": "fused orbital batch" if s.use_fused else "staged"}
 
 
 def bench_r3(Solver, torch, wl, steps=20):

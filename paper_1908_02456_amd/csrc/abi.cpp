@@ -37,6 +37,7 @@ struct abc_ctx {
   double2* box_q = nullptr;
   std::vector<std::string> launch_labels;  // launches of a step, from the last abc_step_timed
   rocblas_handle blas = nullptr;           // box form over an orbital batch
+  OrbitalBatch* orb = nullptr;             // fused path over an orbital batch / mean field
   abc_launch La{};                         // adjoint operator set (built on first abc_adjoint)
   bool adjoint_ready = false;
 };
@@ -108,6 +109,11 @@ const char* abc_last_error(void) { return g_last_error.c_str(); }
 void abc_destroy(abc_ctx* c) {
   if (!c) return;
   if (c->blas) rocblas_destroy_handle(c->blas);
+  if (c->orb) {
+    if (c->orb->copied) hipEventDestroy(c->orb->copied);
+    if (c->orb->desc_host) hipHostFree(c->orb->desc_host);
+    delete c->orb;
+  }
   for (void* ptr : c->allocations) (void)hipFree(ptr);
   delete c;
 }
@@ -273,6 +279,31 @@ abc_status abc_setup(const abc_params* pp, abc_ctx** out) {
       st = fused_prepare(c->p, c->L, &c->allocations, &c->bytes, err);
       if (st != ABC_OK) { abc_destroy(c); return fail(st, err); }
     }
+    if (c->use_fused && (p.batch > 1 || p.meanfield != ABC_MF_NONE)) {
+      // orbitals stepped as boxes of one descriptor-driven launch
+      c->orb = new OrbitalBatch();
+      OrbitalBatch& ob = *c->orb;
+      ob.L1 = L;
+      ob.L1.g = abc::make_geometry(p.nx, p.ny, p.nz, p.radius, 1);
+      ob.B = p.batch;
+      ob.tz = L.fused_tz;
+      ob.S.assign(p.batch, abc_scratch{});
+      const bool first = p.order == ABC_FIRST;
+      const size_t np = (size_t)L.g.npts, nf = (size_t)ob.L1.g.face_off[6];
+      for (int i = 0; i < 3 && st == ABC_OK; ++i) {
+        st = dev_alloc(c, &ob.soa[i], (size_t)p.batch * np * csz);
+        if (st == ABC_OK && first) {
+          st = dev_alloc(c, &tmp, (size_t)p.batch * nf * 16);
+          ob.soa_f[i] = static_cast<double2*>(tmp);
+        }
+      }
+      if (st == ABC_OK && p.meanfield) st = dev_alloc(c, &ob.veff, np * rsz);
+      if (st == ABC_OK) st = dev_alloc(c, &ob.desc_dev, fused_batch_desc_bytes(p.batch));
+      if (st == ABC_OK && (hipHostMalloc(&ob.desc_host, fused_batch_desc_bytes(p.batch)) != hipSuccess ||
+                           hipEventCreate(&ob.copied) != hipSuccess))
+        st = fail(ABC_ENOMEM, "orbital batch descriptors");
+      if (st != ABC_OK) { abc_destroy(c); return st; }
+    }
   }
   *out = c;
   return ABC_OK;
@@ -291,7 +322,9 @@ abc_status abc_step(abc_ctx* c, void* psi, void* aux, const void* V, int n_steps
   if (n_steps == 0) return ABC_OK;
   hipStream_t st = static_cast<hipStream_t>(stream);
   hipError_t e;
-  if (c->use_fused)
+  if (c->orb)
+    e = launch_step_orbitals(*c->orb, psi, static_cast<double2*>(aux), V, n_steps, st, nullptr);
+  else if (c->use_fused)
     e = launch_step_fused(c->L, c->S, psi, static_cast<double2*>(aux), V, n_steps, st);
   else
     e = launch_step_staged(c->L, c->S, psi, static_cast<double2*>(aux), V, n_steps, st);
@@ -307,7 +340,9 @@ abc_status abc_step_timed(abc_ctx* c, void* psi, void* aux, const void* V, int n
   hipStream_t st = static_cast<hipStream_t>(stream);
   abc_timer tm;
   hipError_t e;
-  if (c->use_fused)
+  if (c->orb)
+    e = launch_step_orbitals(*c->orb, psi, static_cast<double2*>(aux), V, n_steps, st, &tm);
+  else if (c->use_fused)
     e = launch_step_fused(c->L, c->S, psi, static_cast<double2*>(aux), V, n_steps, st, &tm);
   else
     e = launch_step_staged(c->L, c->S, psi, static_cast<double2*>(aux), V, n_steps, st, &tm);
@@ -492,7 +527,7 @@ abc_status abc_tune(abc_ctx* c, void* psi, void* aux, const void* V, void* strea
   if (!c || !psi) return fail(ABC_EINVAL, "null argument");
   if (c->p.order == ABC_FIRST && !aux) return fail(ABC_EINVAL, "first order needs the aux buffer");
   hipStream_t st = static_cast<hipStream_t>(stream);
-  if (!c->use_fused || c->L.fused_stages != 2) {
+  if (!c->use_fused || c->orb || c->L.fused_stages != 2) {
     if (tz_out) *tz_out = c->use_fused ? c->L.fused_tz : 0;
     return ABC_OK;
   }
@@ -567,7 +602,7 @@ abc_status abc_setup_batch(const abc_params* ps, int n, abc_batch** out) {
       return fail(st, msg);
     }
     b->inst.push_back(c);
-    if (!(c->use_fused && c->L.fused_stages == 2)) {
+    if (!(c->use_fused && !c->orb && c->L.fused_stages == 2)) {
       b->fallback.push_back(i);
       continue;
     }

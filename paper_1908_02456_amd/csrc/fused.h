@@ -38,3 +38,25 @@ size_t fused_batch_desc_bytes(int nbox);
 int fused_batch_build(const std::vector<FusedMember>& m, void* host, int n);
 hipError_t launch_batch_fused(const std::vector<FusedMember>& m, int tz, const void* dev, int total, int n,
                               hipStream_t st, abc_timer* tm);
+
+// Orbital batches (and the mean field) on the fused path: the orbitals are
+// transposed once per call from [point][orbital] to one array per orbital,
+// stepped as boxes of a descriptor-driven launch sharing one potential (the
+// mean field rebuilt from the current state before every step), and
+// transposed back.  All buffers below are owned by the context.
+struct OrbitalBatch {
+  abc_launch L1;                   // the launch of one orbital (batch 1 geometry)
+  int B = 0;                       // orbitals
+  int tz = 8;
+  void* soa[3] = {nullptr, nullptr, nullptr};  // psi arrays [B][npts]: state A, state B, u2
+  double2* soa_f[3] = {nullptr, nullptr, nullptr};  // aux arrays [B][nface]: A, B, aux of u2
+  void* veff = nullptr;            // V + mean field (psi's real type), or null
+  void* desc_host = nullptr;       // pinned staging of the descriptors
+  void* desc_dev = nullptr;
+  hipEvent_t copied = nullptr;
+  bool pending = false;
+  std::vector<abc_scratch> S;      // per-orbital scratch views into soa / soa_f
+};
+size_t orbital_batch_bytes(const abc_launch& L1, int B, bool first, bool meanfield);
+hipError_t launch_step_orbitals(OrbitalBatch& ob, void* psi, double2* aux, const void* V, int n_steps,
+                                hipStream_t st, abc_timer* tm);

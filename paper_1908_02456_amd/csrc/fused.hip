@@ -609,8 +609,7 @@ bool fused_supported(const abc_params& p, std::string* why) {
     return false;
   };
   if (p.radius != 1) return no("radius 1 only");
-  if (p.batch != 1) return no("batch 1 only");
-  if (p.meanfield != ABC_MF_NONE) return no("no mean field");
+  if (p.batch > 64) return no("at most 64 orbitals");
   if (p.order == ABC_PERIODIC) return no("periodic boxes use the staged path");
   if ((p.order == ABC_ZEROTH || p.order == ABC_FIRST) && (p.form != ABC_FORM_FACES || p.window != 0))
     return no("local (window 0) face operators only");
@@ -814,4 +813,159 @@ hipError_t launch_batch_fused(const std::vector<FusedMember>& m, int tz, const v
     if (tm) tm->end_step();
   }
   return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Orbital batches on the fused path
+// ---------------------------------------------------------------------------
+namespace {
+
+// [n][B] <-> [B][n] through an LDS tile of 64 rows x B (B <= 64)
+template <typename E>
+__global__ void __launch_bounds__(256) aos_soa_kernel(const E* __restrict__ in, E* __restrict__ out, long long n,
+                                                      int B, int to_soa) {
+  extern __shared__ unsigned char smem[];
+  E* tile = reinterpret_cast<E*>(smem);  // [B][65]
+  const long long i0 = (long long)blockIdx.x * 64;
+  const int cnt = (int)min((long long)64, n - i0);
+  if (to_soa) {
+    for (int t = threadIdx.x; t < cnt * B; t += blockDim.x) {
+      const int i = t / B, b = t - i * B;
+      tile[b * 65 + i] = in[(i0 + i) * B + b];
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < 64 * B; t += blockDim.x) {
+      const int b = t >> 6, i = t & 63;
+      if (i < cnt) out[(long long)b * n + i0 + i] = tile[b * 65 + i];
+    }
+  } else {
+    for (int t = threadIdx.x; t < 64 * B; t += blockDim.x) {
+      const int b = t >> 6, i = t & 63;
+      if (i < cnt) tile[b * 65 + i] = in[(long long)b * n + i0 + i];
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < cnt * B; t += blockDim.x) {
+      const int i = t / B, b = t - i * B;
+      out[(i0 + i) * B + b] = tile[b * 65 + i];
+    }
+  }
+}
+
+template <typename E>
+hipError_t transpose(const void* in, void* out, long long n, int B, bool to_soa, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  const unsigned blocks = (unsigned)((n + 63) / 64);
+  aos_soa_kernel<E><<<blocks, 256, (size_t)B * 65 * sizeof(E), st>>>(static_cast<const E*>(in), static_cast<E*>(out),
+                                                                      n, B, to_soa ? 1 : 0);
+  return hipGetLastError();
+}
+
+// V + t0 rho + t3 rho^2 with rho = sum_b |psi_b|^2 (Sec. 4.3 mean field,
+// simplified functional), from the orbital arrays of the current state
+template <typename T>
+__global__ void __launch_bounds__(256) meanfield_soa_kernel(const typename cpx<T>::t* __restrict__ cur,
+                                                            const T* __restrict__ V, T* __restrict__ veff,
+                                                            long long n, int B, T t0, T t3) {
+  const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  T rho = 0;
+  for (int b = 0; b < B; ++b) {
+    const auto v = cur[(long long)b * n + p];
+    rho += v.x * v.x + v.y * v.y;
+  }
+  const T base = V ? V[p] : T(0);
+  veff[p] = base + t0 * rho + t3 * rho * rho;
+}
+
+// one step of parity q over every box of a batch (descriptors already on the
+// device, ping-pong arranged by fused_batch_build)
+hipError_t launch_batch_step(const abc_launch& L0, int nb, int tz, const void* dev, int total, int q,
+                             hipStream_t st, abc_timer* tm) {
+  const Box2* db = static_cast<const Box2*>(dev);
+  const dim3 g((unsigned)((total + 7) / 8 * 8));
+  const Box2* dA = db + (q * 2 + 0) * nb;
+  const Box2* dB = db + (q * 2 + 1) * nb;
+  const int order = L0.order;
+#define ABC_BATCH_PAIR(T, ORD)                                                        \
+  do {                                                                                \
+    launch2_batch<T, ORD, true>(tm, "fused2_batch_a", tz, g, st, dA, nb, total, 0);   \
+    launch2_batch<T, ORD, false>(tm, "fused2_batch_b", tz, g, st, dB, nb, total, 1);  \
+  } while (0)
+  if (L0.dtype == ABC_C64) {
+    if (order == ABC_FIRST) ABC_BATCH_PAIR(float, 3);
+    else if (order == ABC_ZEROTH) ABC_BATCH_PAIR(float, 2);
+    else ABC_BATCH_PAIR(float, 0);
+  } else {
+    if (order == ABC_FIRST) ABC_BATCH_PAIR(double, 3);
+    else if (order == ABC_ZEROTH) ABC_BATCH_PAIR(double, 2);
+    else ABC_BATCH_PAIR(double, 0);
+  }
+#undef ABC_BATCH_PAIR
+  return hipGetLastError();
+}
+
+}  // namespace
+
+size_t orbital_batch_bytes(const abc_launch& L1, int B, bool first, bool meanfield) {
+  const size_t csz = L1.dtype == ABC_C64 ? 8 : 16, rsz = L1.dtype == ABC_C64 ? 4 : 8;
+  return 3 * (size_t)B * L1.g.npts * csz + (first ? 3 * (size_t)B * L1.g.face_off[6] * 16 : 0) +
+         (meanfield ? (size_t)L1.g.npts * rsz : 0) + fused_batch_desc_bytes(B);
+}
+
+hipError_t launch_step_orbitals(OrbitalBatch& ob, void* psi, double2* aux, const void* V, int n, hipStream_t st,
+                                abc_timer* tm) {
+  if (n <= 0) return hipSuccess;
+  const abc_launch& L1 = ob.L1;
+  const int B = ob.B;
+  const long long np = L1.g.npts, nf = L1.g.face_off[6];
+  const bool c64 = L1.dtype == ABC_C64;
+  const bool first = L1.order == ABC_FIRST;
+  const size_t csz = c64 ? 8 : 16;
+  // the initial state goes where fused_batch_build expects it (array B for
+  // an odd count), so that the result ends in array A
+  const int in = (n & 1) ? 1 : 0;
+  hipError_t e = c64 ? transpose<float2>(psi, ob.soa[in], np, B, true, st)
+                     : transpose<double2>(psi, ob.soa[in], np, B, true, st);
+  if (e == hipSuccess && first) e = transpose<double2>(aux, ob.soa_f[in], nf, B, true, st);
+  if (e != hipSuccess) return e;
+  std::vector<FusedMember> m(B);
+  for (int b = 0; b < B; ++b) {
+    abc_scratch& S = ob.S[b];
+    S.y[0] = static_cast<char*>(ob.soa[1]) + (size_t)b * np * csz;
+    S.y[1] = static_cast<char*>(ob.soa[2]) + (size_t)b * np * csz;
+    if (first) {
+      S.facc = ob.soa_f[1] + (size_t)b * nf;
+      S.g[0] = ob.soa_f[2] + (size_t)b * nf;
+    }
+    m[b] = {&L1, &S, static_cast<char*>(ob.soa[0]) + (size_t)b * np * csz, first ? ob.soa_f[0] + (size_t)b * nf : nullptr,
+            ob.veff ? ob.veff : V};
+  }
+  if (ob.pending && hipEventSynchronize(ob.copied) != hipSuccess) return hipErrorUnknown;
+  const int total = fused_batch_build(m, ob.desc_host, n);
+  e = hipMemcpyAsync(ob.desc_dev, ob.desc_host, fused_batch_desc_bytes(B), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipEventRecord(ob.copied, st);
+  if (e != hipSuccess) return e;
+  ob.pending = true;
+  for (int s = 0; s < n; ++s) {
+    const int q = s & 1;
+    if (ob.veff) {
+      // the current state: array `in` for even s, the other one for odd s
+      const void* cur = ob.soa[q == 0 ? in : 1 - in];
+      const unsigned blocks = (unsigned)((np + 255) / 256);
+      if (c64)
+        abc_launch_kernel(tm, "meanfield", meanfield_soa_kernel<float>, dim3(blocks), dim3(256), st,
+                          static_cast<const float2*>(cur), static_cast<const float*>(V), static_cast<float*>(ob.veff),
+                          np, B, float(L1.t0), float(L1.t3));
+      else
+        abc_launch_kernel(tm, "meanfield", meanfield_soa_kernel<double>, dim3(blocks), dim3(256), st,
+                          static_cast<const double2*>(cur), static_cast<const double*>(V),
+                          static_cast<double*>(ob.veff), np, B, L1.t0, L1.t3);
+    }
+    e = launch_batch_step(L1, B, ob.tz, ob.desc_dev, total, q, st, tm);
+    if (e != hipSuccess) return e;
+    if (tm) tm->end_step();
+  }
+  e = c64 ? transpose<float2>(ob.soa[0], psi, np, B, false, st) : transpose<double2>(ob.soa[0], psi, np, B, false, st);
+  if (e == hipSuccess && first) e = transpose<double2>(ob.soa_f[0], aux, nf, B, false, st);
+  return e;
 }

@@ -248,3 +248,40 @@ def test_box_form_orbital_batch_parity(R, order, s2):
     assert r["err"] < TOL64, r["err"]
     if order == "first":
         assert r["aux_err"] < TOL64, r["aux_err"]
+
+
+@pytest.mark.parametrize("batch,meanfield,dtype,order", [(3, None, "c128", "first"), (5, (-1.0, 0.5), "c128", "first"),
+                                                         (1, (-1.0, 0.5), "c128", "first"),
+                                                         (4, (-1.0, 0.5), "c128", "zeroth"),
+                                                         (6, (-1.0, 0.5), "c64", "first"),
+                                                         (2, None, "c128", "dirichlet")])
+@pytest.mark.parametrize("steps", [4, 5])
+def test_orbital_batch_fused_parity(batch, meanfield, dtype, order, steps):
+    # orbitals transposed to one array each and stepped as boxes of one
+    # descriptor-driven launch, the mean field rebuilt before every step
+    r = _run_pair("orbital-batch", (12, 11, 13), 0.25, 0.004, 1, order, steps, s0=1.5, s1=1.5, window=0,
+                  batch=batch, meanfield=meanfield, dtype=dtype, path="fused")
+    assert r["solver"].use_fused
+    tol = TOL32 if dtype == "c64" else TOL64
+    assert r["err"] < tol, r["err"]
+    if order == "first":
+        assert r["aux_err"] < (1e-5 if dtype == "c64" else TOL64), r["aux_err"]
+
+
+def test_orbital_batch_fused_and_staged_agree():
+    # 32 orbitals with the mean field, both paths on the same inputs
+    print("case: orbital batch 32", flush=True)
+    Solver = _gpu()
+    shape, nb = (16, 14, 20), 32
+    psi0 = W.random_complex(shape + (nb,), seed=61) * 0.3
+    V = torch.from_numpy(W.random_potential(shape, seed=62)).cuda()
+    outs = []
+    for path in ("staged", "fused"):
+        s = Solver(shape, 0.25, 0.004, order="first", s1=1.0, window=0, batch=nb, meanfield=(-1.0, 0.5), path=path)
+        psi = torch.from_numpy(psi0).cuda()
+        aux = s.new_aux()
+        s.step(psi, aux, V, 7)
+        torch.cuda.synchronize()
+        outs.append((psi.cpu().numpy(), aux.cpu().numpy()))
+    assert np.abs(outs[0][0] - outs[1][0]).max() < 1e-12 * np.abs(outs[0][0]).max()
+    assert np.abs(outs[0][1] - outs[1][1]).max() < 1e-12 * np.abs(outs[0][1]).max()
