@@ -84,3 +84,71 @@ def test_defaults_and_error_text(lib):
     p.reserved[2] = 1
     assert lib.abc_setup(ctypes.byref(p), ctypes.byref(ctx)) == _lib.ABC_EINVAL
     lib.abc_destroy(None)
+
+
+BAD_PARAMS = [
+    (dict(nx=0), _lib.ABC_EINVAL, b"positive"),
+    (dict(radius=0), _lib.ABC_EINVAL, b"radius"),
+    (dict(radius=3, nx=6), _lib.ABC_EINVAL, b"2R+1"),
+    (dict(h=0.0), _lib.ABC_EINVAL, b"h and dt"),
+    (dict(dt=float("nan")), _lib.ABC_EINVAL, b"h and dt"),
+    (dict(order=9), _lib.ABC_EINVAL, b"order"),
+    (dict(form=5), _lib.ABC_EINVAL, b"form"),
+    (dict(dtype=3), _lib.ABC_EINVAL, b"dtype"),
+    (dict(batch=0), _lib.ABC_EINVAL, b"batch"),
+    (dict(meanfield=4), _lib.ABC_EINVAL, b"mean field"),
+    (dict(path=7), _lib.ABC_EINVAL, b"path"),
+    (dict(window=-1), _lib.ABC_EINVAL, b"window"),
+    (dict(order=2, s0=0.0), _lib.ABC_EUNSTABLE, b"s0"),
+    (dict(order=3, s1=-1.0), _lib.ABC_EUNSTABLE, b"s1"),
+    (dict(order=3, form=1, s2=2.0), _lib.ABC_ENOTSUP, b"face form"),
+]
+
+
+@pytest.mark.parametrize("changes,status,text", BAD_PARAMS)
+def test_setup_rejects_invalid_parameters(lib, changes, status, text):
+    # every rule of the parameter check fires before any device call
+    p = _lib.AbcParams()
+    lib.abc_params_default(ctypes.byref(p))
+    p.nx = p.ny = p.nz = 8
+    p.h, p.dt = 0.25, 0.004
+    for k, v in changes.items():
+        setattr(p, k, v)
+    ctx = ctypes.c_void_p()
+    assert lib.abc_setup(ctypes.byref(p), ctypes.byref(ctx)) == status
+    assert text in lib.abc_last_error()
+    assert not ctx.value
+
+
+def test_reserved_fields_must_be_zero(lib):
+    p = _lib.AbcParams()
+    lib.abc_params_default(ctypes.byref(p))
+    p.nx = p.ny = p.nz = 8
+    p.h, p.dt = 0.25, 0.004
+    p.reserved[3] = 1
+    ctx = ctypes.c_void_p()
+    assert lib.abc_setup(ctypes.byref(p), ctypes.byref(ctx)) == _lib.ABC_EINVAL
+    assert b"reserved" in lib.abc_last_error()
+
+
+def test_null_arguments_are_rejected_without_a_device(lib):
+    vp = ctypes.c_void_p
+    assert lib.abc_setup(None, None) == _lib.ABC_EINVAL
+    assert lib.abc_step(None, None, None, None, 1, None) == _lib.ABC_EINVAL
+    k = ctypes.c_int(0)
+    assert lib.abc_step_timed(None, None, None, None, 1, None, None, 0, ctypes.byref(k)) == _lib.ABC_EINVAL
+    J = ctypes.c_double(0)
+    assert lib.abc_adjoint(None, None, None, 1, 0, 0, None, None, ctypes.byref(J), None) == _lib.ABC_EINVAL
+    assert lib.abc_diagnostics(None, None, None, None, None, None) == _lib.ABC_EINVAL
+    assert lib.abc_export(None, 0, None, 0) == _lib.ABC_EINVAL
+    assert lib.abc_tune(None, None, None, None, None, None) == _lib.ABC_EINVAL
+    b = vp()
+    assert lib.abc_setup_batch(None, 0, ctypes.byref(b)) == _lib.ABC_EINVAL
+    assert lib.abc_step_batch(None, None, None, None, 1, 0, None) == _lib.ABC_EINVAL
+    assert lib.abc_tune_batch(None, None, None, None, None) == _lib.ABC_EINVAL
+    assert lib.abc_aux_elems(None) == 0 and lib.abc_device_bytes(None) == 0
+    assert lib.abc_batch_aux_elems(None, 0) == 0 and lib.abc_batch_launch_groups(None) == 0
+    assert lib.abc_batch_tile_depth(None, 0) == 0
+    assert lib.abc_launch_label(None, 0) is None
+    lib.abc_destroy(None)
+    lib.abc_destroy_batch(None)
