@@ -120,6 +120,12 @@ class BoxOperators:
     A: Optional[np.ndarray] = None      # first order
     B: Optional[np.ndarray] = None
     Q: Optional[np.ndarray] = None      # Lyapunov weight (Theorem-based first order)
+    # second order (Sec. 3.3): R22(s) = (s^2 I - s B1 - B0)^{-1} (s A1 + A0), C = B1 A1 + A0
+    B1: Optional[np.ndarray] = None
+    B0: Optional[np.ndarray] = None
+    A1: Optional[np.ndarray] = None
+    A0: Optional[np.ndarray] = None
+    C: Optional[np.ndarray] = None
 
 
 def box_coupling_product(shape, h, R) -> np.ndarray:
@@ -154,6 +160,40 @@ def box_first(shape, h, R, s1, s2=math.inf, L=None) -> BoxOperators:
     B = np.linalg.solve((K2 - K1).T, (s2 * K2 - s1 * K1).T).T
     A = (s1 * np.eye(n) - B) @ K1
     return BoxOperators("first", gamma, A=A, B=B, Q=None)
+
+
+def interp_second(Ks, s_pts):
+    """Coefficients of the second-order rational approximation (Sec. 3.3),
+    R22(s) = (s^2 I - s B1 - B0)^{-1} (s A1 + A0), from R22(s_j) = K(s_j) at
+    four points: (s_j^2 I - s_j B1 - B0) K_j = s_j A1 + A0, i.e.
+    [B1 B0 A1 A0] [s_j K_j; K_j; s_j I; I] = s_j^2 K_j for j = 1..4, solved as
+    one linear system.  Works on dense matrices and on stacks of per-mode
+    blocks (leading axes)."""
+    if len(Ks) != 4 or len(s_pts) != 4:
+        raise ValueError("four interpolation points")
+    n = Ks[0].shape[-1]
+    I = np.broadcast_to(np.eye(n, dtype=np.complex128), Ks[0].shape)
+    cols = [np.concatenate([s * K, K, s * I, I], axis=-2) for K, s in zip(Ks, s_pts)]
+    M = np.concatenate(cols, axis=-1)                                  # (..., 4n, 4n)
+    rhs = np.concatenate([s * s * K for K, s in zip(Ks, s_pts)], axis=-1)  # (..., n, 4n)
+    X = np.swapaxes(np.linalg.solve(np.swapaxes(M, -1, -2), np.swapaxes(rhs, -1, -2)), -1, -2)
+    return tuple(X[..., :, k * n:(k + 1) * n] for k in range(4))
+
+
+def r22(B1, B0, A1, A0, s):
+    """The second-order rational function at s (dense)."""
+    n = B1.shape[-1]
+    return np.linalg.solve(s * s * np.eye(n) - s * B1 - B0, s * A1 + A0)
+
+
+def box_second(shape, h, R, s_pts, L=None) -> BoxOperators:
+    """Second-order coefficients of the dense box form by four-point
+    interpolation of the DtN map (Sec. 3.3; the paper gives no stability
+    theorem for this order)."""
+    gamma = gamma_points(shape, R)
+    Ks = [dtn_box(shape, h, R, s, L) for s in s_pts]
+    B1, B0, A1, A0 = interp_second(Ks, s_pts)
+    return BoxOperators("second", gamma, B1=B1, B0=B0, A1=A1, A0=A0, C=B1 @ A1 + A0)
 
 
 # ---------------------------------------------------------------------------
@@ -239,6 +279,8 @@ class FaceOperators:
     a: Optional[np.ndarray] = None
     q: Optional[np.ndarray] = None
     symbol: Optional[np.ndarray] = None
+    # second order: kernels of B1, B0, A1 and C = B1 A1 + A0 (per-mode products)
+    kernels2: Optional[dict] = None
 
 
 def face_symbol_k(s: float, h: float, R: int, P: int) -> np.ndarray:
@@ -273,6 +315,25 @@ def face_first(h, R, s1, w, P=None, window=True) -> FaceOperators:
     if window:
         ker = ker * fejer_window(w)[None, None]
     return FaceOperators("first", R, w, ker, a=a, q=np.linalg.inv(HH), symbol=bsym)
+
+
+def face_second(h, R, s_pts, w, P=None, window=True) -> FaceOperators:
+    """Second-order face operators: the four-point interpolation of Sec. 3.3
+    applied mode by mode to the half-line symbol k^(theta; s), giving symbols
+    b1, b0, a1, a0 and c = b1 a1 + a0, whose windowed sections are the
+    kernels."""
+    if P is None:
+        P = max(default_symbol_points(s, h, w) for s in s_pts)
+    Ks = [face_symbol_k(s, h, R, P) for s in s_pts]
+    b1, b0, a1, a0 = interp_second(Ks, s_pts)
+    syms = {"b1": b1, "b0": b0, "a1": a1, "c": b1 @ a1 + a0}
+    kers = {}
+    for name, sym in syms.items():
+        ker = face_kernel_from_symbol(sym, w)
+        if window:
+            ker = ker * fejer_window(w)[None, None]
+        kers[name] = ker
+    return FaceOperators("second", R, w, kers["b1"], kernels2=kers, symbol=syms)
 
 
 def face_apply_kernel(ker: np.ndarray, slab: np.ndarray) -> np.ndarray:

@@ -48,8 +48,14 @@ class Setup:
 
 
 def make_setup(shape, h, dt, R, order, form="faces", s0=1.0, s1=1.0, s2=math.inf,
-               window=0, use_window=True, P=None, t0=None, t3=0.0) -> Setup:
+               window=0, use_window=True, P=None, t0=None, t3=0.0, s_second=(1.0, 2.0, 3.0, 10.0)) -> Setup:
     st = Setup(tuple(shape), h, dt, R, order, form, t0=t0, t3=t3)
+    if order == "second":
+        if form == "box":
+            st.box = dtn.box_second(shape, h, R, s_second)
+        else:
+            st.faces = dtn.face_second(h, R, s_second, window, P=P, window=use_window)
+        return st
     if order == "zeroth":
         if form == "box":
             st.box = dtn.box_zeroth(shape, h, R, s0)
@@ -79,6 +85,9 @@ def face_shapes(shape, R):
 
 def zero_aux(st: Setup, batch: Optional[int] = None):
     extra = () if batch is None else (batch,)
+    if st.order == "second":
+        one = Setup(st.shape, st.h, st.dt, st.R, "first", st.form, box=st.box, faces=st.faces)
+        return (zero_aux(one, batch), zero_aux(one, batch))
     if st.order != "first":
         return None
     if st.form == "box":
@@ -91,12 +100,19 @@ def pack_aux(st: Setup, aux) -> np.ndarray:
     [face][layer][t_slow][t_fast][orb], faces in the order x-, x+, y-, y+, z-, z+."""
     if aux is None:
         return np.zeros(0, dtype=np.complex128)
+    if isinstance(aux, tuple):  # second order: the f part, then the g part
+        one = Setup(st.shape, st.h, st.dt, st.R, "first", st.form, box=st.box, faces=st.faces)
+        return np.concatenate([pack_aux(one, aux[0]), pack_aux(one, aux[1])])
     if st.form == "box":
         return aux.reshape(-1)
     return np.concatenate([a.reshape(-1) for a in aux])
 
 
 def unpack_aux(st: Setup, flat: np.ndarray, batch: Optional[int] = None):
+    if st.order == "second":
+        one = Setup(st.shape, st.h, st.dt, st.R, "first", st.form, box=st.box, faces=st.faces)
+        half = flat.size // 2
+        return (unpack_aux(one, flat[:half], batch), unpack_aux(one, flat[half:], batch))
     if st.order != "first":
         return None
     extra = () if batch is None else (batch,)
@@ -114,6 +130,8 @@ def _axpy_aux(a, x, y):
     """a * x + y for aux containers."""
     if x is None:
         return None
+    if isinstance(x, tuple):
+        return tuple(_axpy_aux(a, xi, yi) for xi, yi in zip(x, y))
     if isinstance(x, list):
         return [a * xi + yi for xi, yi in zip(x, y)]
     return a * x + y
@@ -122,6 +140,8 @@ def _axpy_aux(a, x, y):
 def _scale_aux(a, x):
     if x is None:
         return None
+    if isinstance(x, tuple):
+        return tuple(_scale_aux(a, xi) for xi in x)
     if isinstance(x, list):
         return [a * xi for xi in x]
     return a * x
@@ -130,6 +150,8 @@ def _scale_aux(a, x):
 def _copy_aux(x):
     if x is None:
         return None
+    if isinstance(x, tuple):
+        return tuple(_copy_aux(xi) for xi in x)
     if isinstance(x, list):
         return [xi.copy() for xi in x]
     return x.copy()
@@ -181,6 +203,26 @@ def generator(st: Setup, y: np.ndarray, g, V: np.ndarray):
                 slab = dtn.face_extract(y, f, st.R)
                 dg.append(dtn.face_apply_kernel(st.faces.kernel, g[f])
                           + dtn.face_apply_local(st.faces.a, slab))
+    elif st.order == "second":
+        # Sec. 3.3 dynamics written first-order in (psi, f, g) with
+        # g = df/dt - A1 E psi (zero at t = 0 for zero exterior data):
+        #   d psi/dt = -i H psi - i E^T f,  df/dt = g + A1 E psi,
+        #   dg/dt = B1 g + B0 f + (B1 A1 + A0) E psi
+        f, gg = g
+        if st.form == "box":
+            _scatter_gamma(st, dy, -1j * f)
+            Ey = _gather_gamma(st, y)
+            dg = (gg + st.box.A1 @ Ey, st.box.B1 @ gg + st.box.B0 @ f + st.box.C @ Ey)
+        else:
+            k = st.faces.kernels2
+            dfs, dgs = [], []
+            for fi in range(6):
+                dtn.face_scatter_add(dy, -1j * f[fi], fi, st.R)
+                slab = dtn.face_extract(y, fi, st.R)
+                dfs.append(gg[fi] + dtn.face_apply_kernel(k["a1"], slab))
+                dgs.append(dtn.face_apply_kernel(k["b1"], gg[fi]) + dtn.face_apply_kernel(k["b0"], f[fi])
+                           + dtn.face_apply_kernel(k["c"], slab))
+            dg = (dfs, dgs)
     return dy, dg
 
 
@@ -228,8 +270,9 @@ def norm(st: Setup, psi: np.ndarray) -> np.ndarray:
 
 
 def aux_energy(st: Setup, aux) -> np.ndarray:
-    """f^* Q f (per orbital), Q = (H_{Gamma,II} H_{II,Gamma})^{-1}."""
-    if aux is None:
+    """f^* Q f (per orbital), Q = (H_{Gamma,II} H_{II,Gamma})^{-1}.  The
+    second order has no Lyapunov functional in the paper: 0."""
+    if aux is None or st.order == "second":
         return 0.0
     if st.form == "box":
         Qf = st.box.Q @ aux
