@@ -248,6 +248,74 @@ def bench_box_batch(Solver, torch, W, nb=32, steps=20):
             "speedup_vs_per_orbital": (ms1 * nb) / msb}
 
 
+def bench_orders_box(Solver, torch, W, n=16, big=40, h=0.25, dt=0.005, steps=200):
+    """The dense box form with each order on a free packet (k = 2 along x)
+    leaving an n^3 box: relative L2 error at T against a big^3 zero-boundary
+    box (data zero-extended) and the time per step of each order."""
+    psi0 = W.gaussian_packet((n,) * 3, h, k=(2.0, 0.0, 0.0))
+    off = (big - n) // 2
+    pb = torch.zeros((big,) * 3, dtype=torch.complex128, device="cuda")
+    pb[off:off + n, off:off + n, off:off + n] = torch.from_numpy(psi0).cuda()
+    Solver((big,) * 3, h, dt, order="dirichlet").step(pb, None, None, steps)
+    ref = pb[off:off + n, off:off + n, off:off + n].clone()
+    nr = torch.linalg.vector_norm(ref).item()
+    out = {"grid": n, "reference_grid": big, "h": h, "dt": dt, "steps": steps, "T": steps * dt}
+    for name, kw in (("dirichlet", dict(order="dirichlet")), ("zeroth", dict(order="zeroth", s0=1.0)),
+                     ("first", dict(order="first", s1=1.0)), ("first_two_point", dict(order="first", s1=1.0, s2=4.0)),
+                     ("second", dict(order="second", s_points=(1.0, 2.0, 3.0, 10.0)))):
+        t0 = time.perf_counter()
+        s = Solver((n,) * 3, h, dt, form="box", **kw)
+        setup_s = time.perf_counter() - t0
+        psi = torch.from_numpy(psi0).cuda()
+        aux = s.new_aux()
+        s.step(psi, aux, None, steps)
+        torch.cuda.synchronize()
+        e = torch.linalg.vector_norm(psi - ref).item() / nr
+        p2 = torch.from_numpy(psi0).cuda()
+        a2 = s.new_aux()
+        s.step(p2, a2, None, 2)
+        ms = _time(torch, lambda: s.step(p2, a2, None, 20)) / 20
+        out[name] = {"err_vs_large_box": e, "ms_per_step": ms, "setup_s": setup_s}
+    return out
+
+
+def bench_box64(Solver, torch, W, n=64, big=128, h=0.25, dt=0.005, steps=500):
+    """Face form against the paper's dense box form on a 64^3 box
+    (n_Gamma = 23816; the box operators are built on the device): a free
+    packet exp(-|x - (4, 0, 0)|^2/2) e^{2ix} leaving the box, relative L2
+    error at T against a 128^3 zero-boundary box (data zero-extended), with
+    setup time and time per step."""
+    psi0 = W.gaussian_packet((n,) * 3, h, center=(4.0, 0.0, 0.0), k=(2.0, 0.0, 0.0))
+    off = (big - n) // 2
+    pb = torch.zeros((big,) * 3, dtype=torch.complex128, device="cuda")
+    pb[off:off + n, off:off + n, off:off + n] = torch.from_numpy(psi0).cuda()
+    Solver((big,) * 3, h, dt, order="dirichlet").step(pb, None, None, steps)
+    ref = pb[off:off + n, off:off + n, off:off + n].clone()
+    del pb
+    nr = torch.linalg.vector_norm(ref).item()
+    out = {"grid": n, "reference_grid": big, "h": h, "dt": dt, "steps": steps, "T": steps * dt}
+    for name, kw in (("dirichlet", dict(order="dirichlet")),
+                     ("faces_first_w0", dict(order="first", s1=1.0, window=0)),
+                     ("faces_first_w8", dict(order="first", s1=1.0, window=8)),
+                     ("box_zeroth", dict(order="zeroth", s0=1.0, form="box")),
+                     ("box_first", dict(order="first", s1=1.0, form="box"))):
+        log("  box64: %s" % name)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s = Solver((n,) * 3, h, dt, **kw)
+        torch.cuda.synchronize()
+        setup_s = time.perf_counter() - t0
+        psi = torch.from_numpy(psi0).cuda()
+        aux = s.new_aux()
+        ms = _time(torch, lambda: s.step(psi, aux, None, steps)) / steps
+        e = torch.linalg.vector_norm(psi - ref).item() / nr
+        out[name] = {"err_vs_large_box": e, "ms_per_step": ms, "setup_s": setup_s,
+                     "device_bytes": s.device_bytes()}
+        del s, psi, aux
+        torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(wl, window, budget_s=15.0):
     """FP64 oracle (NumPy, single-threaded elementwise) on the same workload,
     for as many whole steps as fit in about budget_s seconds."""
@@ -381,7 +449,9 @@ def main():
                          ("adjoint", lambda: bench_adjoint(Solver, torch, W)),
                          ("tdhf", lambda: bench_tdhf(Solver, torch, W)),
                          ("r3", lambda: bench_r3(Solver, torch, wl)),
-                         ("box_batch", lambda: bench_box_batch(Solver, torch, W))):
+                         ("box_batch", lambda: bench_box_batch(Solver, torch, W)),
+                         ("orders_box", lambda: bench_orders_box(Solver, torch, W)),
+                         ("box64", lambda: bench_box64(Solver, torch, W))):
             log("extra: %s" % name)
             try:
                 extra[name] = fn()

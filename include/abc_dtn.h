@@ -17,6 +17,14 @@
  *                A = -i H_{Gamma,II} H_{II,Gamma},  B = s1 I - A K(s1)^{-1}
  *                (the first-order stability theorem), or with a finite s2 the
  *                two-point interpolation R11(s1) = K(s1), R11(s2) = K(s2)
+ *   ABC_SECOND:  the second-order approximation of Sec. 3.3,
+ *                K(s) ~ (s^2 I - s B1 - B0)^{-1} (s A1 + A0), interpolating
+ *                K at the four points s1, s2, s3, s4; its dynamics
+ *                d2f/dt2 = B1 df/dt + B0 f + A1 E dpsi/dt + A0 E psi run as
+ *                the first-order system in (psi, f, g), g = df/dt - A1 E psi:
+ *                d/dt psi = -i H psi - i E^T f,  d/dt f = g + A1 E psi,
+ *                d/dt g = B1 g + B0 f + (B1 A1 + A0) E psi  (box form only;
+ *                the paper gives no stability theorem for this order)
  *   ABC_DIRICHLET / ABC_PERIODIC: no condition (zero outside / wrap-around),
  * where K(s) is the discrete DtN map (Sec. 2, evaluated by the App. A
  * boundary-element formula).  Time stepping is the fourth-order Taylor
@@ -47,7 +55,8 @@
  *        Sec. 2).  Face form: [face][layer][t_slow][t_fast][orb] with faces in
  *        the order x-,x+,y-,y+,z-,z+; layer 0 is the outermost box layer;
  *        (t_slow, t_fast) = (z, y) for x-faces, (z, x) for y-faces, (y, x)
- *        for z-faces.  Box form: [gamma][orb], Gamma in C order of (z, y, x).
+ *        for z-faces.  Box form: [gamma][orb], Gamma in C order of (z, y, x);
+ *        second order holds f then g, each [gamma][orb].
  * The context owns only setup products (operators) and scratch.
  *
  * Errors and threading
@@ -79,7 +88,7 @@ typedef enum {
   ABC_ENOTSUP = -5     /* combination not implemented                      */
 } abc_status;
 
-enum { ABC_DIRICHLET = 0, ABC_PERIODIC = 1, ABC_ZEROTH = 2, ABC_FIRST = 3 };
+enum { ABC_DIRICHLET = 0, ABC_PERIODIC = 1, ABC_ZEROTH = 2, ABC_FIRST = 3, ABC_SECOND = 4 };
 enum { ABC_FORM_BOX = 0, ABC_FORM_FACES = 1 };
 enum { ABC_C128 = 0, ABC_C64 = 1 };
 enum { ABC_MF_NONE = 0, ABC_MF_T0T3 = 1 };
@@ -90,11 +99,13 @@ typedef struct {
   int nx, ny, nz;     /* box points per axis (>= 2R + 1)                     */
   double h, dt;       /* grid spacing, time step                            */
   int radius;         /* R in {1, 2, 3}                                     */
-  int order;          /* ABC_DIRICHLET | ABC_PERIODIC | ABC_ZEROTH | ABC_FIRST */
+  int order;          /* ABC_DIRICHLET | ABC_PERIODIC | ABC_ZEROTH | ABC_FIRST
+                         | ABC_SECOND                                        */
   int form;           /* ABC_FORM_BOX | ABC_FORM_FACES                      */
   double s0;          /* zeroth-order interpolation point (> 0)             */
   double s1, s2;      /* first-order points; s2 <= 0 selects the theorem's
-                         (s1, infinity) pair; s2 > 0 two-point (box form)   */
+                         (s1, infinity) pair; s2 > 0 two-point (box form).
+                         Second order: the first two of its four points     */
   int window;         /* face form: kernel half-width w (|p|_inf <= w)       */
   int fejer;          /* face form: 1 = triangular window, 0 = truncation    */
   int dtype;          /* ABC_C128 | ABC_C64                                 */
@@ -102,25 +113,33 @@ typedef struct {
   int meanfield;      /* ABC_MF_NONE | ABC_MF_T0T3                          */
   double t0, t3;      /* mean-field coefficients                            */
   int path;           /* ABC_PATH_*                                        */
-  int reserved[7];    /* must be zero                                       */
+  int reserved[3];    /* must be zero                                       */
+  double s3, s4;      /* second order: the last two interpolation points;
+                         s1..s4 positive and distinct                       */
 } abc_params;
 
 /* Fill p with defaults (R = 1, first order, face form, w = 0, fejer = 1,
- * s0 = s1 = 1, s2 = 0, C128, batch 1, no mean field, automatic path). */
+ * s0 = s1 = 1, s2 = 0, s3 = 3, s4 = 10, C128, batch 1, no mean field,
+ * automatic path). */
 void abc_params_default(abc_params* p);
 
 /* Build the operators for p on the current HIP device (host FP64 setup;
  * may take seconds for the box form) and allocate the context's scratch.
  * Box form: K(s) by App. A, dense solves on the device.  Face form:
  * half-line DtN symbols per transverse mode, kernel coefficients.
+ * Second order: box form only (ABC_ENOTSUP for the face form), the four
+ * points positive and pairwise distinct (ABC_EINVAL otherwise); its
+ * coefficients come from one 4 n_Gamma square solve (Sec. 3.3).
  * Returns ABC_EUNSTABLE when a sign condition of the stability theorems
  * fails on the symbol, or when dt times the spectral-radius bound of the
  * kinetic and boundary operators exceeds the Taylor-4 stability limit
- * 2 sqrt(2).  On success *out owns device memory until abc_destroy. */
+ * 2 sqrt(2) (for the second order the boundary part of that bound is a
+ * power-iteration estimate of the spectral radius of the (f, g) block).
+ * On success *out owns device memory until abc_destroy. */
 abc_status abc_setup(const abc_params* p, abc_ctx** out);
 
 /* Advance (psi, aux) by n_steps Taylor-4 steps in place.  psi, V, aux as
- * described above (aux may be NULL unless order == ABC_FIRST).  No
+ * described above (aux may be NULL unless order is ABC_FIRST or ABC_SECOND).  No
  * allocation, no host synchronisation. */
 abc_status abc_step(abc_ctx* ctx, void* psi, void* aux, const void* V,
                     int n_steps, void* stream);
@@ -159,7 +178,7 @@ enum { ABC_OBJ_PROB = 0, ABC_OBJ_ENERGY = 1 };
  * and stage vectors.  Device memory for about n/stride + 4 stride + 8 states
  * is allocated and freed by the call, which synchronises the stream.  Supported: complex128, one orbital, no mean
  * field; Dirichlet and periodic boxes; face-form zeroth order (any R) and
- * first order (R = 1).  Others: ABC_ENOTSUP.  ABC_ENOMEM if the buffers do
+ * first order (R = 1).  Others (the box form, the second order): ABC_ENOTSUP.  ABC_ENOMEM if the buffers do
  * not fit, ABC_EDEVICE on HIP failures. */
 abc_status abc_adjoint(abc_ctx* ctx, const void* psi0, const void* V,
                        int n_steps, int ckpt_stride, int objective,
@@ -182,7 +201,7 @@ abc_status abc_tune(abc_ctx* ctx, void* psi, void* aux, const void* V,
  * the concatenated tiles of all its boxes, with one tile depth per group
  * (abc_tune_batch picks it by timing).  Other instances are stepped one by
  * one with abc_step.  abc_step_batch advances instance i's psi[i] (and
- * aux[i], first order; V[i] may be NULL, V itself may be NULL for V = 0) by
+ * aux[i], first and second order; V[i] may be NULL, V itself may be NULL for V = 0) by
  * n_steps on the stream; with ABC_BATCH_GRAPH in flags the whole call is
  * captured once into a HIP graph per (buffers, n_steps, stream), which later
  * calls with the same arguments replay (the stream must not be the default
@@ -207,19 +226,24 @@ void abc_destroy_batch(abc_batch* b);
 /* FP64 diagnostics of a state, written to device memory out (3*batch + 1
  * doubles): [0, batch) norm h^3 sum |psi_j|^2; [batch, 2 batch) Lyapunov
  * functional h^3 (psi_j^* psi_j + f_j^* Q f_j) (Sec. 3, zeroth- and
- * first-order stability proofs; Q = (H_{Gamma,II} H_{II,Gamma})^{-1});
+ * first-order stability proofs; Q = (H_{Gamma,II} H_{II,Gamma})^{-1};
+ * equal to the norm for the other orders, the second included, for which
+ * the paper states no such functional);
  * [2 batch, 3 batch) h^3 Re <psi_j, H_{I,I} psi_j>; [3 batch] mean-field
  * interaction energy h^3 sum (t0 rho^2/2 + t3 rho^3/3) (0 without it).
  * Deterministic (fixed-order two-pass reduction). */
 abc_status abc_diagnostics(abc_ctx* ctx, const void* psi, const void* aux,
                            const void* V, double* out, void* stream);
 
-/* Number of complex128 elements of the auxiliary buffer (0 unless first order). */
+/* Number of complex128 elements of the auxiliary buffer (0 unless first or
+ * second order; second order: 2 n_Gamma batch). */
 size_t abc_aux_elems(const abc_ctx* ctx);
 
 /* Copy a setup product to host memory (for inspection and tests).
  * which = 0: face kernel, R*R*(2w+1)^2 complex128 as [l][l'][p1+w][p2+w];
- * which = 1: box-form matrix, M (zeroth) or [B | A] (first), row-major.
+ * which = 1: box-form matrix, row-major: M (zeroth, n x n), [B | A] (first,
+ *            n x 2n) or [[0, I, A1], [B0, B1, B1 A1 + A0]] (second,
+ *            2n x 3n, acting on [f; g; E psi]), n = n_Gamma.
  * which = 2: face-form normal-line blocks, a (R*R) then q (R*R) complex128.
  * n = capacity in complex128 elements; returns EINVAL if too small. */
 abc_status abc_export(const abc_ctx* ctx, int which, void* host_out, size_t n);

@@ -12,7 +12,7 @@ ABC_OK, ABC_EINVAL, ABC_ENOMEM, ABC_EDEVICE, ABC_EUNSTABLE, ABC_ENOTSUP = 0, -1,
 STATUS_NAMES = {0: "ABC_OK", -1: "ABC_EINVAL", -2: "ABC_ENOMEM", -3: "ABC_EDEVICE",
                 -4: "ABC_EUNSTABLE", -5: "ABC_ENOTSUP"}
 ABC_BATCH_GRAPH = 1
-ORDERS = {"dirichlet": 0, "periodic": 1, "zeroth": 2, "first": 3}
+ORDERS = {"dirichlet": 0, "periodic": 1, "zeroth": 2, "first": 3, "second": 4}
 FORMS = {"box": 0, "faces": 1}
 DTYPES = {"c128": 0, "c64": 1}
 PATHS = {"auto": 0, "staged": 1, "fused": 2}
@@ -34,7 +34,8 @@ class AbcParams(ctypes.Structure):
         ("window", ctypes.c_int), ("fejer", ctypes.c_int), ("dtype", ctypes.c_int),
         ("batch", ctypes.c_int), ("meanfield", ctypes.c_int),
         ("t0", ctypes.c_double), ("t3", ctypes.c_double),
-        ("path", ctypes.c_int), ("reserved", ctypes.c_int * 7),
+        ("path", ctypes.c_int), ("reserved", ctypes.c_int * 3),
+        ("s3", ctypes.c_double), ("s4", ctypes.c_double),
     ]
 
 

@@ -29,6 +29,16 @@ struct Geometry {
 
 Geometry make_geometry(int nx, int ny, int nz, int R, int batch);
 
+// Box-form operator shapes for n = n_Gamma.  Boundary variables per orbital:
+// none (zeroth), f (first) or f, g (second, Sec. 3.3).  The row-major
+// operator is M (n x n), [B | A] (n x 2n) or [[0, I, A1], [B0, B1, C]]
+// (2n x 3n): rows = the boundary variables' derivatives (or M E psi),
+// columns = [boundary variables; E psi].
+inline int box_aux_rows(int order, int n) { return order == ABC_SECOND ? 2 * n : (order == ABC_FIRST ? n : 0); }
+inline int box_rows(int order, int n) { return order == ABC_ZEROTH ? n : box_aux_rows(order, n); }
+inline int box_cols(int order, int n) { return box_aux_rows(order, n) + n; }
+inline size_t box_mat_elems(int order, int n) { return (size_t)box_rows(order, n) * box_cols(order, n); }
+
 // Host setup products ------------------------------------------------------
 
 // Central second-derivative weights c_0..c_R.
@@ -52,8 +62,9 @@ void halfline_symbol(int R, double h, cd shift, cd* out);
 // Face operators; returns ABC_OK or ABC_EUNSTABLE (sign condition violated).
 abc_status build_face_ops(const abc_params& p, FaceOps& ops, std::string& err);
 
-// Box form: dense operators assembled on the host and finished on the
-// device.  mat_dev receives M (n x n) or [B | A] (n x 2n), row-major.
+// Box form: dense operators built on the device.  mat_dev receives the
+// row-major operator (box_rows x box_cols), q_dev the first order's
+// Lyapunov weight (n x n) or NULL.
 abc_status build_box_ops(const abc_params& p, double2** mat_dev, double2** q_dev, int* n_gamma,
                          std::vector<int>& gamma_lin, double* spectral_bound, std::string& err);
 

@@ -63,7 +63,7 @@ abc_status check_params(const abc_params& p) {
     return fail(ABC_EINVAL, "every axis needs at least 2R+1 points");
   if (!(p.h > 0) || !(p.dt > 0) || !std::isfinite(p.h) || !std::isfinite(p.dt))
     return fail(ABC_EINVAL, "h and dt must be positive and finite");
-  if (p.order < ABC_DIRICHLET || p.order > ABC_FIRST) return fail(ABC_EINVAL, "unknown order");
+  if (p.order < ABC_DIRICHLET || p.order > ABC_SECOND) return fail(ABC_EINVAL, "unknown order");
   if (p.form != ABC_FORM_BOX && p.form != ABC_FORM_FACES) return fail(ABC_EINVAL, "unknown form");
   if (p.dtype != ABC_C128 && p.dtype != ABC_C64) return fail(ABC_EINVAL, "unknown dtype");
   if (p.batch < 1) return fail(ABC_EINVAL, "batch must be >= 1");
@@ -75,7 +75,19 @@ abc_status check_params(const abc_params& p) {
   if (p.order == ABC_FIRST && !(p.s1 > 0)) return fail(ABC_EUNSTABLE, "s1 must be positive (first-order theorem)");
   if (p.order == ABC_FIRST && p.form == ABC_FORM_FACES && p.s2 > 0)
     return fail(ABC_ENOTSUP, "the face form implements the theorem's (s1, infinity) pair only");
-  for (int i = 0; i < 7; ++i)
+  if (p.order == ABC_SECOND) {
+    // four-point interpolation (Sec. 3.3): the system is singular unless the
+    // points are distinct
+    const double sp[4] = {p.s1, p.s2, p.s3, p.s4};
+    for (int i = 0; i < 4; ++i) {
+      if (!(sp[i] > 0) || !std::isfinite(sp[i])) return fail(ABC_EINVAL, "second order: s1..s4 must be positive");
+      for (int j = 0; j < i; ++j)
+        if (sp[i] == sp[j]) return fail(ABC_EINVAL, "second order: s1..s4 must be distinct");
+    }
+    if (p.form != ABC_FORM_BOX)
+      return fail(ABC_ENOTSUP, "second order: box form only (the face sections lose stability)");
+  }
+  for (int i = 0; i < 3; ++i)
     if (p.reserved[i] != 0) return fail(ABC_EINVAL, "reserved fields must be zero");
   return ABC_OK;
 }
@@ -96,6 +108,8 @@ void abc_params_default(abc_params* p) {
   p->s0 = 1.0;
   p->s1 = 1.0;
   p->s2 = 0.0;
+  p->s3 = 3.0;
+  p->s4 = 10.0;
   p->window = 0;
   p->fejer = 1;
   p->dtype = ABC_C128;
@@ -140,7 +154,7 @@ abc_status abc_setup(const abc_params* pp, abc_ctx** out) {
   L.meanfield = p.meanfield;
   L.t0 = p.t0;
   L.t3 = p.t3;
-  const bool bc = p.order == ABC_ZEROTH || p.order == ABC_FIRST;
+  const bool bc = p.order == ABC_ZEROTH || p.order == ABC_FIRST || p.order == ABC_SECOND;
 
   // spectral bound of the kinetic part: 3 max_theta sigma_1(theta)
   double smax = 0;
@@ -182,7 +196,7 @@ abc_status abc_setup(const abc_params* pp, abc_ctx** out) {
     double bound = 0;
     st = abc::build_box_ops(p, &c->box_mat, &c->box_q, &c->n_gamma, glin, &bound, err);
     if (st != ABC_OK) { abc_destroy(c); return fail(st, err); }
-    if (c->box_mat) { c->allocations.push_back(c->box_mat); c->bytes += (size_t)c->n_gamma * c->n_gamma * 16 * (p.order == ABC_FIRST ? 2 : 1); }
+    if (c->box_mat) { c->allocations.push_back(c->box_mat); c->bytes += abc::box_mat_elems(p.order, c->n_gamma) * 16; }
     if (c->box_q) { c->allocations.push_back(c->box_q); c->bytes += (size_t)c->n_gamma * c->n_gamma * 16; }
     L.box_mat = c->box_mat;
     L.box_q = c->box_q;
@@ -202,6 +216,9 @@ abc_status abc_setup(const abc_params* pp, abc_ctx** out) {
     }
     L.gamma_lin = static_cast<const int*>(gl);
     L.point_gamma = static_cast<const int*>(pgd);
+    // zeroth: M adds to H; first and second: the boundary block (B, or the
+    // (f, g) block [[0, I], [B0, B1]]) beside H, coupled through blocks of
+    // the size of H_{Gamma,Sigma}
     rho = p.order == ABC_ZEROTH ? rho + bound : std::max(rho, bound) + std::sqrt(3.0) * 2.0 * std::abs(L.c[1]) / (2 * p.h * p.h);
   }
   // fourth-order Taylor polynomial: |T4(i y)| <= 1 requires |y| <= 2 sqrt(2)
@@ -217,7 +234,8 @@ abc_status abc_setup(const abc_params* pp, abc_ctx** out) {
   abc_scratch& S = c->S;
   size_t naux = 0;
   if (bc) naux = p.form == ABC_FORM_BOX ? (size_t)c->n_gamma * p.batch : (size_t)L.g.face_off[6];
-  c->aux_elems = p.order == ABC_FIRST ? naux : 0;
+  if (p.order == ABC_SECOND) naux *= 2;  // f and g
+  c->aux_elems = p.order == ABC_FIRST || p.order == ABC_SECOND ? naux : 0;
   S.red_blocks = 256 + 64;
   void* tmp = nullptr;
   if ((st = dev_alloc(c, &S.y[0], nel * csz)) != ABC_OK || (st = dev_alloc(c, &S.y[1], nel * csz)) != ABC_OK ||
@@ -242,7 +260,8 @@ abc_status abc_setup(const abc_params* pp, abc_ctx** out) {
       S.bwork[0] = static_cast<double2*>(tmp);
       if ((st = dev_alloc(c, &tmp, naux * 16)) != ABC_OK) { abc_destroy(c); return st; }
       S.bwork[1] = static_cast<double2*>(tmp);
-      const int n = c->n_gamma, nb = p.batch, ld = p.order == ABC_FIRST ? 2 * n : n;
+      const int n = c->n_gamma, nb = p.batch;
+      const int ld = abc::box_cols(p.order, n);
       const rocblas_double_complex one = {1.0, 0.0}, zero = {0.0, 0.0};
       if (rocblas_create_handle(&c->blas) != rocblas_status_success ||
           hipMemset(S.bwork[0], 0, naux * 16) != hipSuccess ||
@@ -318,7 +337,7 @@ int abc_path(const abc_ctx* c) { return (c && c->use_fused) ? ABC_PATH_FUSED : A
 abc_status abc_step(abc_ctx* c, void* psi, void* aux, const void* V, int n_steps, void* stream) {
   if (!c || !psi) return fail(ABC_EINVAL, "null context or psi");
   if (n_steps < 0) return fail(ABC_EINVAL, "n_steps must be >= 0");
-  if (c->p.order == ABC_FIRST && !aux) return fail(ABC_EINVAL, "first order needs the aux buffer");
+  if (c->aux_elems && !aux) return fail(ABC_EINVAL, "first and second order need the aux buffer");
   if (n_steps == 0) return ABC_OK;
   hipStream_t st = static_cast<hipStream_t>(stream);
   hipError_t e;
@@ -336,7 +355,7 @@ abc_status abc_step_timed(abc_ctx* c, void* psi, void* aux, const void* V, int n
                           int cap, int* launches) {
   if (!c || !psi || !launches || (cap > 0 && !ms)) return fail(ABC_EINVAL, "null argument");
   if (n_steps < 1) return fail(ABC_EINVAL, "n_steps must be >= 1");
-  if (c->p.order == ABC_FIRST && !aux) return fail(ABC_EINVAL, "first order needs the aux buffer");
+  if (c->aux_elems && !aux) return fail(ABC_EINVAL, "first and second order need the aux buffer");
   hipStream_t st = static_cast<hipStream_t>(stream);
   abc_timer tm;
   hipError_t e;
@@ -413,6 +432,7 @@ abc_status abc_adjoint(abc_ctx* c, const void* psi0, const void* V, int n_steps,
   const abc_params& p = c->p;
   if (p.dtype != ABC_C128) return fail(ABC_ENOTSUP, "adjoint: complex128 only");
   if (p.batch != 1 || p.meanfield != ABC_MF_NONE) return fail(ABC_ENOTSUP, "adjoint: one orbital, no mean field");
+  if (p.order == ABC_SECOND) return fail(ABC_ENOTSUP, "adjoint: not for the second order");
   if ((p.order == ABC_ZEROTH || p.order == ABC_FIRST) && p.form != ABC_FORM_FACES)
     return fail(ABC_ENOTSUP, "adjoint: face form only");
   if (p.order == ABC_FIRST && p.radius != 1) return fail(ABC_ENOTSUP, "adjoint: first order needs R = 1");
@@ -444,7 +464,7 @@ abc_status abc_export(const abc_ctx* c, int which, void* host_out, size_t n) {
   }
   if (which == 1) {
     if (!c->box_mat) return fail(ABC_EINVAL, "no box-form matrix");
-    const size_t cnt = (size_t)c->n_gamma * c->n_gamma * (c->p.order == ABC_FIRST ? 2 : 1);
+    const size_t cnt = abc::box_mat_elems(c->p.order, c->n_gamma);
     if (cnt > n) return fail(ABC_EINVAL, "buffer too small");
     if (hipMemcpy(host_out, c->box_mat, cnt * 16, hipMemcpyDeviceToHost) != hipSuccess)
       return fail(ABC_EDEVICE, "hipMemcpy failed");
@@ -525,7 +545,7 @@ size_t psi_bytes(const abc_ctx* c) {
 
 abc_status abc_tune(abc_ctx* c, void* psi, void* aux, const void* V, void* stream, int* tz_out) {
   if (!c || !psi) return fail(ABC_EINVAL, "null argument");
-  if (c->p.order == ABC_FIRST && !aux) return fail(ABC_EINVAL, "first order needs the aux buffer");
+  if (c->aux_elems && !aux) return fail(ABC_EINVAL, "first and second order need the aux buffer");
   hipStream_t st = static_cast<hipStream_t>(stream);
   if (!c->use_fused || c->orb || c->L.fused_stages != 2) {
     if (tz_out) *tz_out = c->use_fused ? c->L.fused_tz : 0;
@@ -658,8 +678,8 @@ abc_status check_batch_args(abc_batch* b, void* const* psi, void* const* aux) {
   if (!b || !psi) return fail(ABC_EINVAL, "null argument");
   for (size_t i = 0; i < b->inst.size(); ++i) {
     if (!psi[i]) return fail(ABC_EINVAL, "null psi for instance " + std::to_string(i));
-    if (b->inst[i]->p.order == ABC_FIRST && (!aux || !aux[i]))
-      return fail(ABC_EINVAL, "first-order instance " + std::to_string(i) + " needs its aux buffer");
+    if (b->inst[i]->aux_elems && (!aux || !aux[i]))
+      return fail(ABC_EINVAL, "instance " + std::to_string(i) + " needs its aux buffer");
   }
   return ABC_OK;
 }

@@ -611,6 +611,7 @@ bool fused_supported(const abc_params& p, std::string* why) {
   if (p.radius != 1) return no("radius 1 only");
   if (p.batch > 64) return no("at most 64 orbitals");
   if (p.order == ABC_PERIODIC) return no("periodic boxes use the staged path");
+  if (p.order == ABC_SECOND) return no("the second order (box form) uses the staged path");
   if ((p.order == ABC_ZEROTH || p.order == ABC_FIRST) && (p.form != ABC_FORM_FACES || p.window != 0))
     return no("local (window 0) face operators only");
   if (p.nz < 5 || p.ny < 4 || p.nx < 4) return no("nx, ny >= 4 and nz >= 5");

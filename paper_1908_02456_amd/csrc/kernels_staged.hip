@@ -6,7 +6,11 @@
 // A stage computes z_k = (dt/k) L z_{k-1} for the generator
 //   L(psi, f) = (-i H psi - i E^T f,  B f + A E psi)        (first order)
 //   L psi     = -i (H psi + E^T M E psi)                   (zeroth order)
+//   L(psi, f, g) = (-i H psi - i E^T f,  g + A1 E psi,
+//                   B1 g + B0 f + (B1 A1 + A0) E psi)      (second order)
 // (Sec. 3 dynamics) and accumulates z_0 + ... + z_4 (Sec. 4 Taylor step).
+// The second order exists in the box form only; its boundary variables
+// [f; g] are one vector of 2 n_Gamma rows for the box operator.
 #include <hip/hip_runtime.h>
 
 #include <rocblas/rocblas.h>
@@ -252,29 +256,32 @@ __global__ void __launch_bounds__(kBlock) face_kernel(
 }
 
 // ---------------------------------------------------------------------------
-// box form: dense operator on Gamma.  One workgroup per row block; the row
-// of the n x ncol matrix times [x1; x2] where x1 = aux stage (first order) or
-// absent, x2 = E y.  out = coef * (row . x)  (first) or row . x (zeroth).
+// box form: dense operator on Gamma.  One workgroup per row; the row of the
+// rows x ncol matrix times [x1; x2] where x1 = the naux boundary variables of
+// the stage (first and second order) or absent (naux = 0, zeroth), x2 = E y.
+// out = coef * (row . x) with the stage update (naux > 0), or row . x.
+// Rows below `ident` (second order: the n rows of df/dt) hold [0, I] on the
+// boundary columns; they read only their E y columns and add g directly.
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ void __launch_bounds__(kBlock) box_gemv_kernel(
-    const double2* __restrict__ mat, int n, int ncol, const double2* __restrict__ gin,
+    const double2* __restrict__ mat, int naux, int ncol, int ident, const double2* __restrict__ gin,
     const typename cpx<T>::t* __restrict__ yin, const int* __restrict__ gamma_lin,
     double2* __restrict__ gout, double2* __restrict__ facc, double2* __restrict__ aux_out,
-    int batch, double coef, int mode, int first) {
+    int batch, double coef, int mode) {
   __shared__ double2 red[kBlock];
   const int row = blockIdx.x;
   const int b = blockIdx.y;
   double sr = 0, si = 0;
   const double2* mrow = mat + (long long)row * ncol;
-  for (int j = threadIdx.x; j < ncol; j += blockDim.x) {
+  const int j0 = row < ident ? naux : 0;
+  for (int j = j0 + threadIdx.x; j < ncol; j += blockDim.x) {
     const double2 m = mrow[j];
     double2 v;
-    if (first && j < n) {
+    if (j < naux) {
       v = gin[(long long)j * batch + b];
     } else {
-      const int jj = first ? j - n : j;
-      const auto yv = yin[(long long)gamma_lin[jj] * batch + b];
+      const auto yv = yin[(long long)gamma_lin[j - naux] * batch + b];
       v = make_double2((double)yv.x, (double)yv.y);
     }
     sr += m.x * v.x - m.y * v.y;
@@ -291,9 +298,14 @@ __global__ void __launch_bounds__(kBlock) box_gemv_kernel(
   }
   if (threadIdx.x != 0) return;
   const long long e = (long long)row * batch + b;
-  if (!first) {
+  if (naux == 0) {
     gout[e] = red[0];
     return;
+  }
+  if (row < ident) {
+    const double2 gv = gin[(long long)(row + ident) * batch + b];
+    red[0].x += gv.x;
+    red[0].y += gv.y;
   }
   const double2 gn = make_double2(coef * red[0].x, coef * red[0].y);
   if (mode == 0) {
@@ -496,7 +508,7 @@ LocalBlock make_local(const double2* m) {
 // box form over an orbital batch: the operator is applied to all orbitals at
 // once as a dense complex GEMM (rocBLAS zgemm, matrix cores) instead of one
 // matrix pass per orbital.  gather: E y -> [gamma][orbital]; epilogue: the
-// first-order aux stage update of box_gemv_kernel on the GEMM result.
+// aux stage update of box_gemv_kernel on the GEMM result.
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ void __launch_bounds__(kBlock) box_gather_kernel(const typename cpx<T>::t* __restrict__ yin,
@@ -551,7 +563,9 @@ hipError_t step_staged_t(const abc_launch& L, const abc_scratch& S, void* psi_v,
   const LocalBlock a = make_local(L.a_loc);
   const long long nel = g.npts * g.batch;
   const long long nface = g.face_off[6];
-  const bool first = L.order == ABC_FIRST, zeroth = L.order == ABC_ZEROTH;
+  const bool zeroth = L.order == ABC_ZEROTH;
+  // boundary variables with their own recurrence: f (first), f and g (second)
+  const bool rec = L.order == ABC_FIRST || L.order == ABC_SECOND;
   const bool box = L.form == ABC_FORM_BOX;
   for (int s = 0; s < n_steps; ++s) {
     const T* Vuse = V;
@@ -567,48 +581,52 @@ hipError_t step_staged_t(const abc_launch& L, const abc_scratch& S, void* psi_v,
       const int mode = k == 1 ? 0 : (k == 4 ? 2 : 1);
       const double2* fsrc = nullptr;
       const double2* bsrc = nullptr;
-      if (first || zeroth) {
+      if (rec || zeroth) {
         double2* gnext = (k == 4) ? nullptr : S.g[(k - 1) & 1];
         if (box && L.blas && g.batch > 1) {
           // Y^T = X^T M^T in rocBLAS's column-major view of the row-major
-          // operator [B | A] (n x 2n) or M (n x n): T = B g + A E y, or M E y
-          const int n = L.n_gamma, nb = g.batch, ld = first ? 2 * n : n;
-          const long long cnt = (long long)n * nb;
-          abc_launch_kernel(tm, kBoundLabel[k], box_gather_kernel<T>, dim3(nblocks(cnt)), dim3(kBlock), st,
+          // operator (rows x (na + n)): T = [B | A] [g; E y] (first),
+          // the 2n rows of the second order, or M E y (zeroth)
+          const int n = L.n_gamma, nb = g.batch;
+          const int na = abc::box_aux_rows(L.order, n), rows = abc::box_rows(L.order, n);
+          const int ld = abc::box_cols(L.order, n);
+          const long long cnt = (long long)rows * nb, ng = (long long)n * nb;
+          abc_launch_kernel(tm, kBoundLabel[k], box_gather_kernel<T>, dim3(nblocks(ng)), dim3(kBlock), st,
                             (const C*)ycur, L.gamma_lin, n, nb, S.bwork[0]);
-          double2* tout = first ? S.bwork[1] : S.src;
+          double2* tout = rec ? S.bwork[1] : S.src;
           if (tm) tm->mark_host(st, "box_gemm");
           const rocblas_double_complex one = {1.0, 0.0}, zero = {0.0, 0.0};
           rocblas_handle hb = static_cast<rocblas_handle>(L.blas);
           rocblas_status rs = rocblas_set_stream(hb, st);
-          if (rs == rocblas_status_success && first)
-            rs = rocblas_zgemm(hb, rocblas_operation_none, rocblas_operation_none, nb, n, n, &one,
+          if (rs == rocblas_status_success && rec)
+            rs = rocblas_zgemm(hb, rocblas_operation_none, rocblas_operation_none, nb, rows, na, &one,
                                reinterpret_cast<const rocblas_double_complex*>(gcur), nb,
                                reinterpret_cast<const rocblas_double_complex*>(L.box_mat), ld, &zero,
                                reinterpret_cast<rocblas_double_complex*>(tout), nb);
           if (rs == rocblas_status_success)
-            rs = rocblas_zgemm(hb, rocblas_operation_none, rocblas_operation_none, nb, n, n, &one,
+            rs = rocblas_zgemm(hb, rocblas_operation_none, rocblas_operation_none, nb, rows, n, &one,
                                reinterpret_cast<const rocblas_double_complex*>(S.bwork[0]), nb,
-                               reinterpret_cast<const rocblas_double_complex*>(L.box_mat + (first ? n : 0)), ld,
-                               first ? &one : &zero, reinterpret_cast<rocblas_double_complex*>(tout), nb);
+                               reinterpret_cast<const rocblas_double_complex*>(L.box_mat + na), ld,
+                               rec ? &one : &zero, reinterpret_cast<rocblas_double_complex*>(tout), nb);
           if (rs != rocblas_status_success) return hipErrorLaunchFailure;
-          if (first)
+          if (rec)
             abc_launch_kernel(tm, "box_epilogue", box_epilogue_kernel, dim3(nblocks(cnt)), dim3(kBlock), st,
                               (const double2*)tout, gcur, gnext, S.facc, aux, cnt, coef, mode);
         } else if (box) {
-          const int ncol = first ? 2 * L.n_gamma : L.n_gamma;
-          dim3 grid(L.n_gamma, g.batch);
-          abc_launch_kernel(tm, kBoundLabel[k], box_gemv_kernel<T>, grid, dim3(kBlock), st, L.box_mat, L.n_gamma,
-                            ncol, gcur, ycur, L.gamma_lin, first ? gnext : S.src, S.facc, aux, g.batch, coef, mode,
-                            first ? 1 : 0);
+          const int n = L.n_gamma;
+          dim3 grid(abc::box_rows(L.order, n), g.batch);
+          abc_launch_kernel(tm, kBoundLabel[k], box_gemv_kernel<T>, grid, dim3(kBlock), st, L.box_mat,
+                            abc::box_aux_rows(L.order, n), abc::box_cols(L.order, n),
+                            L.order == ABC_SECOND ? n : 0, gcur, ycur, L.gamma_lin,
+                            rec ? gnext : S.src, S.facc, aux, g.batch, coef, mode);
         } else {
           abc_launch_kernel(tm, kBoundLabel[k], face_kernel<T, R>, dim3(nblocks(nface)), dim3(kBlock), st, gcur,
-                            first ? gnext : S.src, S.facc, aux, ycur, L.face_ker, a, g, L.w, coef, mode,
-                            first ? 1 : 0);
+                            rec ? gnext : S.src, S.facc, aux, ycur, L.face_ker, a, g, L.w, coef, mode,
+                            rec ? 1 : 0);
         }
-        const double2* s_for_stage = first ? gcur : S.src;
+        const double2* s_for_stage = rec ? gcur : S.src;
         if (box) bsrc = s_for_stage; else fsrc = s_for_stage;
-        if (first) gcur = gnext;
+        if (rec) gcur = gnext;
       }
       C* yout = (k == 4) ? nullptr : (keep ? static_cast<C*>(keep[k - 1]) : y[(k - 1) & 1]);
       abc_launch_kernel(tm, kStageLabel[k], stage_kernel<T, R, PER>, dim3(nblocks(nel)), dim3(kBlock), st, ycur,

@@ -22,9 +22,15 @@ def _stream_handle(stream) -> Optional[int]:
     return stream.cuda_stream
 
 
+SECOND_ORDER_POINTS = (1.0, 2.0, 3.0, 10.0)
+
+
 def make_params(shape, h, dt, *, radius=1, order="first", form="faces", s0=1.0, s1=1.0, s2=0.0, window=0,
-                fejer=True, dtype="c128", batch=1, meanfield=None, path="auto") -> _lib.AbcParams:
-    """abc_params for a box of shape (nz, ny, nx) (see include/abc_dtn.h)."""
+                fejer=True, dtype="c128", batch=1, meanfield=None, path="auto",
+                s_points=None) -> _lib.AbcParams:
+    """abc_params for a box of shape (nz, ny, nx) (see include/abc_dtn.h).
+    s_points: the four interpolation points of the second order (default
+    SECOND_ORDER_POINTS); s1, s2 are the first order's."""
     lib = _lib.load()
     p = _lib.AbcParams()
     lib.abc_params_default(ctypes.byref(p))
@@ -36,6 +42,11 @@ def make_params(shape, h, dt, *, radius=1, order="first", form="faces", s0=1.0, 
     p.form = _lib.FORMS[form]
     p.s0, p.s1 = float(s0), float(s1)
     p.s2 = 0.0 if (s2 is None or (isinstance(s2, float) and math.isinf(s2))) else float(s2)
+    if order == "second":
+        pts = SECOND_ORDER_POINTS if s_points is None else tuple(float(v) for v in s_points)
+        if len(pts) != 4:
+            raise ValueError("the second order takes four interpolation points")
+        p.s1, p.s2, p.s3, p.s4 = pts
     p.window = int(window)
     p.fejer = 1 if fejer else 0
     p.dtype = _lib.DTYPES[dtype]
@@ -50,17 +61,19 @@ def make_params(shape, h, dt, *, radius=1, order="first", form="faces", s0=1.0, 
 class Solver:
     """One context of the C ABI (operators + scratch) for a fixed box.
 
-    shape: (nz, ny, nx).  order: "dirichlet" | "periodic" | "zeroth" | "first".
+    shape: (nz, ny, nx).  order: "dirichlet" | "periodic" | "zeroth" | "first"
+    | "second" (box form; s_points = its four interpolation points).
     form: "faces" | "box".  dtype: "c128" | "c64".  meanfield: (t0, t3) or None.
     """
 
     def __init__(self, shape: Sequence[int], h: float, dt: float, *, radius: int = 1,
                  order: str = "first", form: str = "faces", s0: float = 1.0, s1: float = 1.0,
                  s2: float = 0.0, window: int = 0, fejer: bool = True, dtype: str = "c128",
-                 batch: int = 1, meanfield=None, path: str = "auto", device=None):
+                 batch: int = 1, meanfield=None, path: str = "auto", device=None, s_points=None):
         lib = _lib.load()
         p = make_params(shape, h, dt, radius=radius, order=order, form=form, s0=s0, s1=s1, s2=s2,
-                        window=window, fejer=fejer, dtype=dtype, batch=batch, meanfield=meanfield, path=path)
+                        window=window, fejer=fejer, dtype=dtype, batch=batch, meanfield=meanfield, path=path,
+                        s_points=s_points)
         nz, ny, nx = (int(v) for v in shape)
         self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
         self.params = p
@@ -112,7 +125,7 @@ class Solver:
         return V.data_ptr()
 
     def _check_aux(self, aux):
-        if self.order != "first":
+        if self.aux_elems == 0:
             return None if aux is None else aux.data_ptr()
         if aux is None or aux.dtype != torch.complex128 or aux.numel() < self.aux_elems or not aux.is_contiguous():
             raise ValueError("aux must be a contiguous complex128 tensor of %d elements" % self.aux_elems)
@@ -168,7 +181,7 @@ class Solver:
         """Tensor of 3*batch+1 float64: norm, Lyapunov W, energy per orbital, interaction energy."""
         self._check_psi(psi)
         vp = self._check_V(V)
-        ap = self._check_aux(aux) if self.order == "first" else None
+        ap = self._check_aux(aux) if self.aux_elems else None
         if out is None:
             out = torch.empty(3 * self.batch + 1, dtype=torch.float64, device=self.device)
         _lib.check(self._lib.abc_diagnostics(self._ctx, psi.data_ptr(), ap, vp, out.data_ptr(),

@@ -48,7 +48,7 @@ int main(void) {
   printf("%zu", sizeof(abc_params));
 #define F(x) printf(" %zu", offsetof(abc_params, x));
   F(nx) F(ny) F(nz) F(h) F(dt) F(radius) F(order) F(form) F(s0) F(s1) F(s2) F(window) F(fejer)
-  F(dtype) F(batch) F(meanfield) F(t0) F(t3) F(path) F(reserved)
+  F(dtype) F(batch) F(meanfield) F(t0) F(t3) F(path) F(reserved) F(s3) F(s4)
   printf("\n");
   return 0;
 }
@@ -61,7 +61,7 @@ int main(void) {
         vals = [int(v) for v in subprocess.run([exe], capture_output=True, text=True).stdout.split()]
     P = _lib.AbcParams
     names = ["nx", "ny", "nz", "h", "dt", "radius", "order", "form", "s0", "s1", "s2", "window", "fejer",
-             "dtype", "batch", "meanfield", "t0", "t3", "path", "reserved"]
+             "dtype", "batch", "meanfield", "t0", "t3", "path", "reserved", "s3", "s4"]
     assert vals[0] == ctypes.sizeof(P)
     assert vals[1:] == [getattr(P, n).offset for n in names]
 
@@ -70,6 +70,7 @@ def test_defaults_and_error_text(lib):
     p = _lib.AbcParams()
     lib.abc_params_default(ctypes.byref(p))
     assert (p.radius, p.order, p.form, p.dtype, p.batch, p.fejer) == (1, 3, 1, 0, 1, 1)
+    assert (p.s0, p.s1, p.s2, p.s3, p.s4) == (1.0, 1.0, 0.0, 3.0, 10.0)
     # invalid parameters are rejected before any device call
     p.radius = 7
     ctx = ctypes.c_void_p()
@@ -81,7 +82,7 @@ def test_defaults_and_error_text(lib):
     p.s1 = -1.0
     assert lib.abc_setup(ctypes.byref(p), ctypes.byref(ctx)) == _lib.ABC_EUNSTABLE
     lib.abc_params_default(ctypes.byref(p))
-    p.reserved[2] = 1
+    p.reserved[0] = 1
     assert lib.abc_setup(ctypes.byref(p), ctypes.byref(ctx)) == _lib.ABC_EINVAL
     lib.abc_destroy(None)
 
@@ -102,6 +103,11 @@ BAD_PARAMS = [
     (dict(order=2, s0=0.0), _lib.ABC_EUNSTABLE, b"s0"),
     (dict(order=3, s1=-1.0), _lib.ABC_EUNSTABLE, b"s1"),
     (dict(order=3, form=1, s2=2.0), _lib.ABC_ENOTSUP, b"face form"),
+    (dict(order=5), _lib.ABC_EINVAL, b"order"),
+    (dict(order=4, form=0, s2=2.0, s3=2.0), _lib.ABC_EINVAL, b"distinct"),
+    (dict(order=4, form=0, s2=0.0), _lib.ABC_EINVAL, b"positive"),
+    (dict(order=4, form=0, s2=2.0, s4=float("inf")), _lib.ABC_EINVAL, b"positive"),
+    (dict(order=4, form=1, s2=2.0), _lib.ABC_ENOTSUP, b"box form only"),
 ]
 
 
@@ -125,7 +131,7 @@ def test_reserved_fields_must_be_zero(lib):
     lib.abc_params_default(ctypes.byref(p))
     p.nx = p.ny = p.nz = 8
     p.h, p.dt = 0.25, 0.004
-    p.reserved[3] = 1
+    p.reserved[2] = 1
     ctx = ctypes.c_void_p()
     assert lib.abc_setup(ctypes.byref(p), ctypes.byref(ctx)) == _lib.ABC_EINVAL
     assert b"reserved" in lib.abc_last_error()
