@@ -37,9 +37,9 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def physics_error(Solver, torch, wl, dtype, window, path, steps_total):
-    """Relative L2 error at T of the absorbing run vs the doubled Dirichlet box,
-    both started from the same box-only data (zero outside the small box)."""
+def large_box_reference(Solver, torch, wl, dtype, path, steps_total):
+    """The doubled zero-boundary box run from the zero-extended data, cut back
+    to the small box (complex128)."""
     n = wl.n
     big = 2 * n
     off = (big - n) // 2
@@ -52,7 +52,17 @@ def physics_error(Solver, torch, wl, dtype, window, path, steps_total):
     Vb = torch.from_numpy(W.gaussian_well((big,) * 3, wl.h, 5.0)).to(rdt).cuda()
     sb = Solver((big,) * 3, wl.h, wl.dt, order="dirichlet", dtype=dtype, path=path)
     sb.step(psi_b, None, Vb, steps_total)
-    ref = psi_b[off:off + n, off:off + n, off:off + n].to(torch.complex128)
+    return psi_b[off:off + n, off:off + n, off:off + n].to(torch.complex128).clone()
+
+
+def physics_error(Solver, torch, wl, dtype, window, path, steps_total):
+    """Relative L2 error at T of the absorbing run vs the doubled Dirichlet box,
+    both started from the same box-only data (zero outside the small box)."""
+    n = wl.n
+    big = 2 * n
+    cdt = torch.complex128 if dtype == "c128" else torch.complex64
+    rdt = torch.float64 if dtype == "c128" else torch.float32
+    ref = large_box_reference(Solver, torch, wl, dtype, path, steps_total)
     s = Solver((n,) * 3, wl.h, wl.dt, order="first", s1=wl.s1, window=window, dtype=dtype, path=path)
     psi = torch.from_numpy(wl.psi0).to(cdt).cuda()
     aux = s.new_aux()
@@ -316,6 +326,38 @@ def bench_box64(Solver, torch, W, n=64, big=128, h=0.25, dt=0.005, steps=500):
     return out
 
 
+def bench_h2_point(Solver, torch, wl, modes=64, nodes=4096):
+    """The H2-optimal first-order point (Sec. 5 proposal) of the face form at
+    the headline h for windows 0 and 8: time per objective evaluation on the
+    device, the minimiser, and the physics error of the headline run (2000
+    steps, 128^3) at that point against s1 = 1.  (The oracle's time for the
+    same objective is part of the CPU baseline.)"""
+    from paper_1908_02456_amd import solver as api
+    pts = np.exp(np.linspace(math.log(0.1), math.log(1000.0), 8))
+    api.h2_objective(wl.h, pts[:1], modes=modes, nodes=nodes)
+    t0 = time.perf_counter()
+    api.h2_objective(wl.h, pts, modes=modes, nodes=nodes)
+    gpu_s = (time.perf_counter() - t0) / len(pts)
+    out = {"modes": modes, "nodes": nodes, "gpu_s_per_point": gpu_s,
+           "gpu_integrand_evals_per_s": modes * modes * nodes / gpu_s}
+    ref = large_box_reference(Solver, torch, wl, "c128", "auto", wl.steps)
+    nr = torch.linalg.vector_norm(ref).item()
+    V = torch.from_numpy(wl.V).cuda()
+    for w in (0, 8):
+        s_best, j_best = api.optimal_point(wl.h, window=w, modes=modes, nodes=nodes)
+        row = {"s1_opt": s_best, "J_opt": j_best,
+               "J_at_1": float(api.h2_objective(wl.h, 1.0, window=w, modes=modes, nodes=nodes)[0])}
+        for tag, s1 in (("s1_1", 1.0), ("s1_opt", s_best)):
+            s = Solver((wl.n,) * 3, wl.h, wl.dt, order="first", s1=s1, window=w)
+            psi = torch.from_numpy(wl.psi0).cuda()
+            aux = s.new_aux()
+            s.step(psi, aux, V, wl.steps)
+            torch.cuda.synchronize()
+            row["err_" + tag] = torch.linalg.vector_norm(psi - ref).item() / nr
+        out["w%d" % w] = row
+    return out
+
+
 def cpu_baseline(wl, window, budget_s=15.0):
     """FP64 oracle (NumPy, single-threaded elementwise) on the same workload,
     for as many whole steps as fit in about budget_s seconds."""
@@ -338,12 +380,19 @@ def cpu_baseline(wl, window, budget_s=15.0):
             el = time.perf_counter() - t0
             if el > budget_s or steps >= 50:
                 break
+        # the oracle's H2 objective of the first-order point (one candidate)
+        from oracle import h2
+        t0 = time.perf_counter()
+        h2.h2_objective(wl.h, 1.0, 0, P=32, N=1024)
+        h2_s = time.perf_counter() - t0
     finally:
         if ctx:
             ctx.__exit__(None, None, None)
     return {"value": wl.n ** 3 * steps / el, "unit": "grid-point-updates/s", "cores": 1, "kind": "oracle",
             "sample": "%d Taylor steps of the same %d^3 first-order face-form workload (FP64 NumPy, %.1f s)"
-                      % (steps, wl.n, el)}
+                      % (steps, wl.n, el),
+            "h2_objective": {"s_per_point": h2_s, "integrand_evals_per_s": 32 * 32 * 1024 / h2_s,
+                             "sample": "one candidate, 32 x 32 modes x 1024 nodes"}}
 
 
 def main():
@@ -451,7 +500,8 @@ def main():
                          ("r3", lambda: bench_r3(Solver, torch, wl)),
                          ("box_batch", lambda: bench_box_batch(Solver, torch, W)),
                          ("orders_box", lambda: bench_orders_box(Solver, torch, W)),
-                         ("box64", lambda: bench_box64(Solver, torch, W))):
+                         ("box64", lambda: bench_box64(Solver, torch, W)),
+                         ("h2_point", lambda: bench_h2_point(Solver, torch, wl))):
             log("extra: %s" % name)
             try:
                 extra[name] = fn()

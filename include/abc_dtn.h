@@ -223,6 +223,24 @@ int abc_batch_launch_groups(const abc_batch* b);
 int abc_batch_tile_depth(const abc_batch* b, int group);
 void abc_destroy_batch(abc_batch* b);
 
+/* H2 objective of the first-order interpolation point (Sec. 5 proposes the
+ * minimiser of ||K(s) - R11(s)||_H2 as the best point).  For the face form
+ * with R = 1 it is evaluated per half-space and per transverse Fourier mode:
+ *   J(s1) = P^-2 sum_theta (1/2pi) int |k^(theta; i w) - a/(i w - b_w(theta))|^2 dw
+ * with k^ the half-line DtN symbol on the imaginary axis (limit from
+ * Re s > 0), a = -i H_gs H_gs^T and b_w the symbol of the kernel of B that
+ * abc_setup builds at s1 with p's window and fejer settings (Theorem 3.2
+ * per mode).  theta runs over the modes x modes grid 2 pi j / modes; the
+ * frequency integral uses `nodes` midpoints of w = W0 (tan(phi) - 1),
+ * W0 = 3/h^2.  p: a first-order face-form parameter set with radius 1
+ * (its s1 is ignored); s1[0..count-1]: candidate points (host, > 0); out:
+ * host array of count doubles.  Device memory is allocated and freed by the
+ * call, which synchronises the stream.  ABC_EINVAL for bad sizes or points,
+ * ABC_ENOTSUP for other orders, forms or radii, ABC_EUNSTABLE if the face
+ * setup rejects a candidate. */
+abc_status abc_h2_objective(const abc_params* p, const double* s1, int count,
+                            int modes, int nodes, double* out, void* stream);
+
 /* FP64 diagnostics of a state, written to device memory out (3*batch + 1
  * doubles): [0, batch) norm h^3 sum |psi_j|^2; [batch, 2 batch) Lyapunov
  * functional h^3 (psi_j^* psi_j + f_j^* Q f_j) (Sec. 3, zeroth- and

@@ -22,7 +22,7 @@ EXPORTED = ["abc_params_default", "abc_setup", "abc_step", "abc_diagnostics", "a
             "abc_export", "abc_path", "abc_device_bytes", "abc_last_error", "abc_destroy",
             "abc_step_timed", "abc_launch_label", "abc_adjoint", "abc_tune", "abc_setup_batch",
             "abc_step_batch", "abc_tune_batch", "abc_batch_aux_elems", "abc_batch_launch_groups",
-            "abc_batch_tile_depth", "abc_destroy_batch"]
+            "abc_batch_tile_depth", "abc_destroy_batch", "abc_h2_objective"]
 
 
 class AbcParams(ctypes.Structure):
@@ -88,6 +88,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.abc_batch_tile_depth.restype = ctypes.c_int
     lib.abc_destroy_batch.argtypes = [vp]
     lib.abc_destroy_batch.restype = None
+    lib.abc_h2_objective.argtypes = [P, vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, vp]
+    lib.abc_h2_objective.restype = ctypes.c_int
     lib.abc_diagnostics.argtypes = [vp, vp, vp, vp, vp, vp]
     lib.abc_diagnostics.restype = ctypes.c_int
     lib.abc_aux_elems.argtypes = [vp]

@@ -172,6 +172,11 @@ struct abc_adjoint_args {
   double* J_host;
   int use_fused;  // forward sweep on the fused path
 };
+// H2 objective of candidate first-order points (face form, R = 1): out[c]
+// for s1[c]; synchronises the stream (h2.hip)
+abc_status run_h2_objective(const abc_params& p, const double* s1, int count, int modes, int nodes, double* out,
+                            hipStream_t st, std::string& err);
+
 abc_status run_adjoint(const abc_launch& L, const abc_launch& La, const abc_scratch& S, const abc_adjoint_args& a,
                        hipStream_t st, std::string& err);
 

@@ -447,6 +447,24 @@ abc_status abc_adjoint(abc_ctx* c, const void* psi0, const void* V, int n_steps,
   return ABC_OK;
 }
 
+abc_status abc_h2_objective(const abc_params* p, const double* s1, int count, int modes, int nodes, double* out,
+                            void* stream) {
+  g_last_error.clear();
+  if (!p || !s1 || !out) return fail(ABC_EINVAL, "null argument");
+  if (count < 1 || modes < 4 || modes > 4096 || nodes < 16 || nodes > (1 << 24))
+    return fail(ABC_EINVAL, "H2 objective: count >= 1, 4 <= modes <= 4096, 16 <= nodes <= 2^24");
+  abc_status st = check_params(*p);
+  if (st != ABC_OK) return st;
+  if (p->order != ABC_FIRST || p->form != ABC_FORM_FACES || p->radius != 1)
+    return fail(ABC_ENOTSUP, "H2 objective: first-order face form with R = 1 only");
+  for (int c = 0; c < count; ++c)
+    if (!(s1[c] > 0) || !std::isfinite(s1[c])) return fail(ABC_EINVAL, "H2 objective: points must be positive");
+  std::string err;
+  st = run_h2_objective(*p, s1, count, modes, nodes, out, static_cast<hipStream_t>(stream), err);
+  if (st != ABC_OK) return fail(st, err);
+  return ABC_OK;
+}
+
 abc_status abc_diagnostics(abc_ctx* c, const void* psi, const void* aux, const void* V, double* out, void* stream) {
   if (!c || !psi || !out) return fail(ABC_EINVAL, "null argument");
   hipError_t e = launch_diagnostics(c->L, c->S, psi, static_cast<const double2*>(aux), V, out,

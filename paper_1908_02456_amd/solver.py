@@ -202,6 +202,46 @@ class Solver:
         return int(self._lib.abc_device_bytes(self._ctx))
 
 
+def h2_objective(h: float, s1, *, window: int = 0, fejer: bool = True, modes: int = 64, nodes: int = 4096,
+                 stream=None) -> np.ndarray:
+    """H2 objective J(s1) of the first-order face-form condition (R = 1) for
+    each candidate point, evaluated on the device (abc_h2_objective)."""
+    lib = _lib.load()
+    pts = np.ascontiguousarray(np.atleast_1d(np.asarray(s1, dtype=np.float64)))
+    p = make_params((8, 8, 8), h, 1e-3, order="first", form="faces", window=window, fejer=fejer)
+    out = np.zeros(pts.size, dtype=np.float64)
+    _lib.check(lib.abc_h2_objective(ctypes.byref(p), pts.ctypes.data, int(pts.size), int(modes), int(nodes),
+                                    out.ctypes.data, _stream_handle(stream)))
+    return out
+
+
+def optimal_point(h: float, *, window: int = 0, fejer: bool = True, modes: int = 64, nodes: int = 4096,
+                  lo: float = 1e-2, hi: float = 1e4, grid: int = 25, iters: int = 30):
+    """The H2-optimal first-order point: the smallest J on a log-spaced grid
+    over [lo, hi], refined by golden-section search in log s1 between the
+    grid neighbours of that point.  Returns (s1, J(s1))."""
+    xs = np.exp(np.linspace(math.log(lo), math.log(hi), grid))
+    js = h2_objective(h, xs, window=window, fejer=fejer, modes=modes, nodes=nodes)
+    k = int(np.argmin(js))
+    a = math.log(xs[max(k - 1, 0)])
+    b = math.log(xs[min(k + 1, grid - 1)])
+    f = lambda t: float(h2_objective(h, math.exp(t), window=window, fejer=fejer, modes=modes, nodes=nodes)[0])
+    g = (math.sqrt(5.0) - 1.0) / 2.0
+    c, d = b - g * (b - a), a + g * (b - a)
+    fc, fd = f(c), f(d)
+    for _ in range(iters):
+        if fc < fd:
+            b, d, fd = d, c, fc
+            c = b - g * (b - a)
+            fc = f(c)
+        else:
+            a, c, fc = c, d, fd
+            d = a + g * (b - a)
+            fd = f(d)
+    best = min([(fc, c), (fd, d), (float(js[k]), math.log(xs[k]))])
+    return math.exp(best[1]), best[0]
+
+
 class Batch:
     """Independent boxes stepped together (abc_setup_batch / abc_step_batch).
 

@@ -17,7 +17,7 @@ HEADER = os.path.join(ROOT, "include", "abc_dtn.h")
 def _declared_functions():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    names = re.findall(r"\b(abc_[a-z_]+)\s*\(", text)
+    names = re.findall(r"\b(abc_[a-z0-9_]+)\s*\(", text)
     return sorted(set(names))
 
 
@@ -135,6 +135,26 @@ def test_reserved_fields_must_be_zero(lib):
     ctx = ctypes.c_void_p()
     assert lib.abc_setup(ctypes.byref(p), ctypes.byref(ctx)) == _lib.ABC_EINVAL
     assert b"reserved" in lib.abc_last_error()
+
+
+def test_h2_objective_rejects_invalid_arguments_without_a_device(lib):
+    p = _lib.AbcParams()
+    lib.abc_params_default(ctypes.byref(p))
+    p.nx = p.ny = p.nz = 8
+    pts = (ctypes.c_double * 2)(1.0, 2.0)
+    out = (ctypes.c_double * 2)()
+    assert lib.abc_h2_objective(None, pts, 2, 16, 64, out, None) == _lib.ABC_EINVAL
+    assert lib.abc_h2_objective(ctypes.byref(p), pts, 0, 16, 64, out, None) == _lib.ABC_EINVAL
+    assert lib.abc_h2_objective(ctypes.byref(p), pts, 2, 2, 64, out, None) == _lib.ABC_EINVAL
+    assert lib.abc_h2_objective(ctypes.byref(p), pts, 2, 16, 8, out, None) == _lib.ABC_EINVAL
+    bad = (ctypes.c_double * 2)(1.0, -2.0)
+    assert lib.abc_h2_objective(ctypes.byref(p), bad, 2, 16, 64, out, None) == _lib.ABC_EINVAL
+    assert b"positive" in lib.abc_last_error()
+    p.order = 2
+    assert lib.abc_h2_objective(ctypes.byref(p), pts, 2, 16, 64, out, None) == _lib.ABC_ENOTSUP
+    p.order, p.radius = 3, 2
+    assert lib.abc_h2_objective(ctypes.byref(p), pts, 2, 16, 64, out, None) == _lib.ABC_ENOTSUP
+    assert b"R = 1" in lib.abc_last_error()
 
 
 def test_null_arguments_are_rejected_without_a_device(lib):

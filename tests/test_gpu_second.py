@@ -171,7 +171,7 @@ def test_second_order_zero_steps_leaves_state():
 
 def test_second_order_absorbs_better_than_first_order():
     # free packet leaving a 12^3 box, all on the device: error against a 28^3
-    # zero-boundary box (same h, dt; data zero-extended) orders as Sec. 5 reports
+    # zero-boundary box (same h, dt; data zero-extended) orders as Sec. 4.2 reports
     Solver = _gpu()
     n, big, h, dt, steps = 12, 28, 0.25, 0.005, 160
     print("case: second-absorption", n, big, flush=True)
