@@ -91,7 +91,7 @@ typedef enum {
 enum { ABC_DIRICHLET = 0, ABC_PERIODIC = 1, ABC_ZEROTH = 2, ABC_FIRST = 3, ABC_SECOND = 4 };
 enum { ABC_FORM_BOX = 0, ABC_FORM_FACES = 1 };
 enum { ABC_C128 = 0, ABC_C64 = 1 };
-enum { ABC_MF_NONE = 0, ABC_MF_T0T3 = 1 };
+enum { ABC_MF_NONE = 0, ABC_MF_T0T3 = 1, ABC_MF_SKYRME = 2 };
 /* execution path of abc_step */
 enum { ABC_PATH_AUTO = 0, ABC_PATH_STAGED = 1, ABC_PATH_FUSED = 2 };
 
@@ -116,11 +116,21 @@ typedef struct {
   int reserved[3];    /* must be zero                                       */
   double s3, s4;      /* second order: the last two interpolation points;
                          s1..s4 positive and distinct                       */
+  /* ABC_MF_SKYRME (Sec. 4.3): U = t0 rho + t3 rho^2 + W_Y + W_C with
+     (Delta_h - 1/a^2) W_Y = -4 pi v0 a rho and Delta_h W_C = -2 pi e2 rho on
+     the box (Delta_h the wavefunctions' Laplacian, zero outside), solved by
+     preconditioned conjugate gradients at the start of every step          */
+  double v0, a_yukawa;  /* Yukawa strength and range (a > 0 unless v0 = 0) */
+  double e2;            /* Coulomb e^2 (0: no Coulomb term)                 */
+  double pcg_tol;       /* relative residual of the solves (> 0)            */
+  int pcg_maxit;        /* iteration cap per solve (>= 1)                   */
+  int reserved2[3];     /* must be zero                                     */
 } abc_params;
 
 /* Fill p with defaults (R = 1, first order, face form, w = 0, fejer = 1,
  * s0 = s1 = 1, s2 = 0, s3 = 3, s4 = 10, C128, batch 1, no mean field,
- * automatic path). */
+ * automatic path; v0 = e2 = 0, a_yukawa = 1, pcg_tol = 1e-12,
+ * pcg_maxit = 1000). */
 void abc_params_default(abc_params* p);
 
 /* Build the operators for p on the current HIP device (host FP64 setup;
@@ -139,8 +149,10 @@ void abc_params_default(abc_params* p);
 abc_status abc_setup(const abc_params* p, abc_ctx** out);
 
 /* Advance (psi, aux) by n_steps Taylor-4 steps in place.  psi, V, aux as
- * described above (aux may be NULL unless order is ABC_FIRST or ABC_SECOND).  No
- * allocation, no host synchronisation. */
+ * described above (aux may be NULL unless order is ABC_FIRST or ABC_SECOND).
+ * No allocation, no host synchronisation, except with ABC_MF_SKYRME, whose
+ * potential solves read their convergence flag on the host every 8
+ * iterations. */
 abc_status abc_step(abc_ctx* ctx, void* psi, void* aux, const void* V,
                     int n_steps, void* stream);
 
@@ -241,6 +253,21 @@ void abc_destroy_batch(abc_batch* b);
 abc_status abc_h2_objective(const abc_params* p, const double* s1, int count,
                             int modes, int nodes, double* out, void* stream);
 
+/* Effective potential V + U of the state psi for an ABC_MF_SKYRME context:
+ * t0 rho + t3 rho^2 plus the Yukawa and Coulomb fields of rho = sum over
+ * orbitals of |psi_j|^2, solved as in abc_step (the solves start from the
+ * context's previous potentials).  psi, V (may be NULL) and out ([z][y][x],
+ * the state's real type) are device buffers.  The call synchronises the
+ * stream (the solves read their convergence flag on the host).
+ * ABC_ENOTSUP for other mean fields. */
+abc_status abc_effective_potential(abc_ctx* ctx, const void* psi, const void* V,
+                                   void* out, void* stream);
+
+/* Conjugate-gradient work of the ABC_MF_SKYRME solves so far: out[0] =
+ * number of mean-field evaluations, out[1] = Yukawa iterations, out[2] =
+ * Coulomb iterations (all zero for other mean fields). */
+abc_status abc_potential_iterations(const abc_ctx* ctx, long long* out);
+
 /* FP64 diagnostics of a state, written to device memory out (3*batch + 1
  * doubles): [0, batch) norm h^3 sum |psi_j|^2; [batch, 2 batch) Lyapunov
  * functional h^3 (psi_j^* psi_j + f_j^* Q f_j) (Sec. 3, zeroth- and
@@ -248,7 +275,8 @@ abc_status abc_h2_objective(const abc_params* p, const double* s1, int count,
  * equal to the norm for the other orders, the second included, for which
  * the paper states no such functional);
  * [2 batch, 3 batch) h^3 Re <psi_j, H_{I,I} psi_j>; [3 batch] mean-field
- * interaction energy h^3 sum (t0 rho^2/2 + t3 rho^3/3) (0 without it).
+ * interaction energy h^3 sum (t0 rho^2/2 + t3 rho^3/3) (0 without it; the
+ * Yukawa and Coulomb terms of ABC_MF_SKYRME are not included).
  * Deterministic (fixed-order two-pass reduction). */
 abc_status abc_diagnostics(abc_ctx* ctx, const void* psi, const void* aux,
                            const void* V, double* out, void* stream);

@@ -18,7 +18,8 @@ applied to the generator L of the (augmented) linear dynamics, evaluated as
 z_0 = state, z_k = (dt / k) L z_{k-1}, new state = z_0 + ... + z_4.
 
 Mean field (Sec. 4.3 with the simplified functional U = t0 rho + t3 rho^2,
-rho = sum_j |phi_j|^2): rebuilt from the state at the start of each step and
+rho = sum_j |phi_j|^2, optionally plus the Yukawa and Coulomb fields of rho
+from :mod:`poisson`): rebuilt from the state at the start of each step and
 held fixed across the four stages.
 """
 from __future__ import annotations
@@ -29,7 +30,7 @@ from typing import List, Optional, Sequence
 
 import numpy as np
 
-from . import dtn
+from . import dtn, poisson
 from .stencil import apply_H, laplacian
 
 
@@ -45,11 +46,15 @@ class Setup:
     faces: Optional[dtn.FaceOperators] = None
     t0: Optional[float] = None   # mean field U = t0 rho + t3 rho^2 when set
     t3: float = 0.0
+    v0: float = 0.0              # Yukawa strength and range (with t0 set)
+    a_y: float = 1.0
+    e2: float = 0.0              # Coulomb e^2 (with t0 set)
 
 
 def make_setup(shape, h, dt, R, order, form="faces", s0=1.0, s1=1.0, s2=math.inf,
-               window=0, use_window=True, P=None, t0=None, t3=0.0, s_second=(1.0, 2.0, 3.0, 10.0)) -> Setup:
-    st = Setup(tuple(shape), h, dt, R, order, form, t0=t0, t3=t3)
+               window=0, use_window=True, P=None, t0=None, t3=0.0, s_second=(1.0, 2.0, 3.0, 10.0),
+               v0=0.0, a_y=1.0, e2=0.0) -> Setup:
+    st = Setup(tuple(shape), h, dt, R, order, form, t0=t0, t3=t3, v0=v0, a_y=a_y, e2=e2)
     if order == "second":
         if form == "box":
             st.box = dtn.box_second(shape, h, R, s_second)
@@ -162,11 +167,17 @@ def _copy_aux(x):
 # ---------------------------------------------------------------------------
 
 def meanfield(st: Setup, psi: np.ndarray) -> np.ndarray:
-    """U = t0 rho + t3 rho^2 with rho = sum over orbitals of |phi_j|^2."""
+    """U = t0 rho + t3 rho^2 (+ W_Y + W_C) with rho = sum over orbitals of
+    |phi_j|^2."""
     rho = np.abs(psi) ** 2
     if psi.ndim == 4:
         rho = rho.sum(axis=3)
-    return st.t0 * rho + st.t3 * rho * rho
+    U = st.t0 * rho + st.t3 * rho * rho
+    if st.v0 != 0.0:
+        U = U + poisson.yukawa(rho, st.h, st.R, st.v0, st.a_y)
+    if st.e2 != 0.0:
+        U = U + poisson.coulomb(rho, st.h, st.R, st.e2)
+    return U
 
 
 def _gather_gamma(st, y):

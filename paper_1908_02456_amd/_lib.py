@@ -22,7 +22,8 @@ EXPORTED = ["abc_params_default", "abc_setup", "abc_step", "abc_diagnostics", "a
             "abc_export", "abc_path", "abc_device_bytes", "abc_last_error", "abc_destroy",
             "abc_step_timed", "abc_launch_label", "abc_adjoint", "abc_tune", "abc_setup_batch",
             "abc_step_batch", "abc_tune_batch", "abc_batch_aux_elems", "abc_batch_launch_groups",
-            "abc_batch_tile_depth", "abc_destroy_batch", "abc_h2_objective"]
+            "abc_batch_tile_depth", "abc_destroy_batch", "abc_h2_objective",
+            "abc_effective_potential", "abc_potential_iterations"]
 
 
 class AbcParams(ctypes.Structure):
@@ -36,6 +37,8 @@ class AbcParams(ctypes.Structure):
         ("t0", ctypes.c_double), ("t3", ctypes.c_double),
         ("path", ctypes.c_int), ("reserved", ctypes.c_int * 3),
         ("s3", ctypes.c_double), ("s4", ctypes.c_double),
+        ("v0", ctypes.c_double), ("a_yukawa", ctypes.c_double), ("e2", ctypes.c_double),
+        ("pcg_tol", ctypes.c_double), ("pcg_maxit", ctypes.c_int), ("reserved2", ctypes.c_int * 3),
     ]
 
 
@@ -90,6 +93,10 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.abc_destroy_batch.restype = None
     lib.abc_h2_objective.argtypes = [P, vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, vp]
     lib.abc_h2_objective.restype = ctypes.c_int
+    lib.abc_effective_potential.argtypes = [vp, vp, vp, vp, vp]
+    lib.abc_effective_potential.restype = ctypes.c_int
+    lib.abc_potential_iterations.argtypes = [vp, ctypes.POINTER(ctypes.c_longlong)]
+    lib.abc_potential_iterations.restype = ctypes.c_int
     lib.abc_diagnostics.argtypes = [vp, vp, vp, vp, vp, vp]
     lib.abc_diagnostics.restype = ctypes.c_int
     lib.abc_aux_elems.argtypes = [vp]

@@ -17,7 +17,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libabc_dtn.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["abi.cpp", "setup.cpp", "setup_box.cpp", "kernels_staged.hip", "fused.hip", "adjoint.hip", "h2.hip"]
+SOURCES = ["abi.cpp", "setup.cpp", "setup_box.cpp", "kernels_staged.hip", "fused.hip", "adjoint.hip", "h2.hip", "poisson.hip"]
 
 # no packed-FP32 instructions in device code; host pass ignores the feature
 DEVICE_FLAGS = ["--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]

@@ -72,6 +72,20 @@ abc_status build_box_ops(const abc_params& p, double2** mat_dev, double2** q_dev
 
 // Kernel launchers (kernels.hip) -------------------------------------------
 
+// Long-range mean-field potentials (poisson.hip): conjugate-gradient state
+// and work buffers over the box, all FP64 device memory except `host`
+struct PotentialSolver {
+  int nx = 0, ny = 0, nz = 0, R = 1;
+  double h = 0, c[abc::kMaxR + 1] = {0, 0, 0, 0};
+  double v0 = 0, a = 1, e2 = 0, tol = 1e-12;
+  int maxit = 1000, nblk = 0;
+  double *rho = nullptr, *wy = nullptr, *wc = nullptr;  // density, Yukawa and Coulomb fields (persist)
+  double *r = nullptr, *p = nullptr, *q = nullptr;      // CG vectors
+  double *part = nullptr, *scal = nullptr;              // 3 nblk partial sums, scalar slots
+  double* host = nullptr;                               // pinned: convergence flag, iteration count
+  long long iters_y = 0, iters_c = 0, solves = 0;
+};
+
 struct abc_launch {
   abc::Geometry g;
   double h, dt;
@@ -79,6 +93,7 @@ struct abc_launch {
   int order, form, periodic, dtype, w;
   int meanfield;
   double t0, t3;
+  PotentialSolver* pot;        // ABC_MF_SKYRME solves (or null)
   // face operators
   const double2* face_ker;
   double2 a_loc[abc::kMaxR * abc::kMaxR];
@@ -172,6 +187,11 @@ struct abc_adjoint_args {
   double* J_host;
   int use_fused;  // forward sweep on the fused path
 };
+// V + t0 rho + t3 rho^2 + W_Y + W_C for psi ([point][orbital], or orbital
+// arrays when soa) into veff; synchronises the stream during the solves
+hipError_t skyrme_veff(PotentialSolver& ps, const void* psi, bool soa, int B, bool c64, const void* V, void* veff,
+                       double t0, double t3, hipStream_t st, abc_timer* tm);
+
 // H2 objective of candidate first-order points (face form, R = 1): out[c]
 // for s1[c]; synchronises the stream (h2.hip)
 abc_status run_h2_objective(const abc_params& p, const double* s1, int count, int modes, int nodes, double* out,

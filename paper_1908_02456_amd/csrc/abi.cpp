@@ -40,6 +40,7 @@ struct abc_ctx {
   OrbitalBatch* orb = nullptr;             // fused path over an orbital batch / mean field
   abc_launch La{};                         // adjoint operator set (built on first abc_adjoint)
   bool adjoint_ready = false;
+  PotentialSolver pot;                     // ABC_MF_SKYRME solves
 };
 
 namespace {
@@ -67,7 +68,17 @@ abc_status check_params(const abc_params& p) {
   if (p.form != ABC_FORM_BOX && p.form != ABC_FORM_FACES) return fail(ABC_EINVAL, "unknown form");
   if (p.dtype != ABC_C128 && p.dtype != ABC_C64) return fail(ABC_EINVAL, "unknown dtype");
   if (p.batch < 1) return fail(ABC_EINVAL, "batch must be >= 1");
-  if (p.meanfield != ABC_MF_NONE && p.meanfield != ABC_MF_T0T3) return fail(ABC_EINVAL, "unknown mean field");
+  if (p.meanfield < ABC_MF_NONE || p.meanfield > ABC_MF_SKYRME) return fail(ABC_EINVAL, "unknown mean field");
+  if (p.meanfield == ABC_MF_SKYRME) {
+    if (!std::isfinite(p.t0) || !std::isfinite(p.t3) || !std::isfinite(p.v0) || !std::isfinite(p.e2))
+      return fail(ABC_EINVAL, "mean field: t0, t3, v0 and e2 must be finite");
+    if (p.v0 != 0.0 && !(p.a_yukawa > 0 && std::isfinite(p.a_yukawa)))
+      return fail(ABC_EINVAL, "mean field: the Yukawa range must be positive");
+    if (!(p.pcg_tol > 0 && std::isfinite(p.pcg_tol)) || p.pcg_maxit < 1)
+      return fail(ABC_EINVAL, "mean field: pcg_tol > 0 and pcg_maxit >= 1");
+  }
+  for (int i = 0; i < 3; ++i)
+    if (p.reserved2[i] != 0) return fail(ABC_EINVAL, "reserved fields must be zero");
   if (p.path < ABC_PATH_AUTO || p.path > ABC_PATH_FUSED) return fail(ABC_EINVAL, "unknown path");
   if (p.window < 0) return fail(ABC_EINVAL, "window must be >= 0");
   if (p.order == ABC_PERIODIC && p.nx < 2 * p.radius + 1) return fail(ABC_EINVAL, "periodic box too small");
@@ -110,6 +121,9 @@ void abc_params_default(abc_params* p) {
   p->s2 = 0.0;
   p->s3 = 3.0;
   p->s4 = 10.0;
+  p->a_yukawa = 1.0;
+  p->pcg_tol = 1e-12;
+  p->pcg_maxit = 1000;
   p->window = 0;
   p->fejer = 1;
   p->dtype = ABC_C128;
@@ -123,6 +137,7 @@ const char* abc_last_error(void) { return g_last_error.c_str(); }
 void abc_destroy(abc_ctx* c) {
   if (!c) return;
   if (c->blas) rocblas_destroy_handle(c->blas);
+  if (c->pot.host) (void)hipHostFree(c->pot.host);
   if (c->orb) {
     if (c->orb->copied) hipEventDestroy(c->orb->copied);
     if (c->orb->desc_host) hipHostFree(c->orb->desc_host);
@@ -285,6 +300,41 @@ abc_status abc_setup(const abc_params* pp, abc_ctx** out) {
   }
   S.red = static_cast<double*>(tmp);
 
+  if (p.meanfield == ABC_MF_SKYRME) {
+    PotentialSolver& ps = c->pot;
+    ps.nx = p.nx;
+    ps.ny = p.ny;
+    ps.nz = p.nz;
+    ps.R = p.radius;
+    ps.h = p.h;
+    for (int k = 0; k <= abc::kMaxR; ++k) ps.c[k] = L.c[k];
+    ps.v0 = p.v0;
+    ps.a = p.a_yukawa;
+    ps.e2 = p.e2;
+    ps.tol = p.pcg_tol;
+    ps.maxit = p.pcg_maxit;
+    const size_t np = (size_t)L.g.npts;
+    ps.nblk = (int)std::min<size_t>(1024, (np + 255) / 256);
+    double** vec[6] = {&ps.rho, &ps.wy, &ps.wc, &ps.r, &ps.p, &ps.q};
+    for (int i = 0; i < 6 && st == ABC_OK; ++i) {
+      st = dev_alloc(c, &tmp, np * sizeof(double));
+      *vec[i] = static_cast<double*>(tmp);
+    }
+    if (st == ABC_OK) st = dev_alloc(c, &tmp, 3 * (size_t)ps.nblk * sizeof(double));
+    ps.part = static_cast<double*>(tmp);
+    if (st == ABC_OK) st = dev_alloc(c, &tmp, 8 * sizeof(double));
+    ps.scal = static_cast<double*>(tmp);
+    if (st == ABC_OK && hipHostMalloc(&tmp, 2 * sizeof(double)) != hipSuccess) st = fail(ABC_ENOMEM, "pinned memory");
+    if (st == ABC_OK) ps.host = static_cast<double*>(tmp);
+    // the potentials start at zero (the first solve starts from zero)
+    if (st == ABC_OK && (hipMemset(ps.wy, 0, np * sizeof(double)) != hipSuccess ||
+                         hipMemset(ps.wc, 0, np * sizeof(double)) != hipSuccess ||
+                         hipDeviceSynchronize() != hipSuccess))
+      st = fail(ABC_EDEVICE, "hipMemset failed");
+    if (st != ABC_OK) { abc_destroy(c); return st; }
+    L.pot = &ps;
+  }
+
   c->use_fused = 0;
   if (p.path != ABC_PATH_STAGED) {
     std::string why;
@@ -444,6 +494,23 @@ abc_status abc_adjoint(abc_ctx* c, const void* psi0, const void* V, int n_steps,
   std::string err;
   abc_status st = run_adjoint(c->L, c->La, c->S, a, static_cast<hipStream_t>(stream), err);
   if (st != ABC_OK) return fail(st, err);
+  return ABC_OK;
+}
+
+abc_status abc_effective_potential(abc_ctx* c, const void* psi, const void* V, void* out, void* stream) {
+  if (!c || !psi || !out) return fail(ABC_EINVAL, "null argument");
+  if (c->p.meanfield != ABC_MF_SKYRME) return fail(ABC_ENOTSUP, "effective potential: ABC_MF_SKYRME contexts only");
+  const hipError_t e = skyrme_veff(c->pot, psi, false, c->p.batch, c->p.dtype == ABC_C64, V, out, c->p.t0, c->p.t3,
+                                   static_cast<hipStream_t>(stream), nullptr);
+  if (e != hipSuccess) return fail(ABC_EDEVICE, std::string("effective potential: ") + hipGetErrorString(e));
+  return ABC_OK;
+}
+
+abc_status abc_potential_iterations(const abc_ctx* c, long long* out) {
+  if (!c || !out) return fail(ABC_EINVAL, "null argument");
+  out[0] = c->pot.solves;
+  out[1] = c->pot.iters_y;
+  out[2] = c->pot.iters_c;
   return ABC_OK;
 }
 
@@ -633,6 +700,10 @@ abc_status abc_setup_batch(const abc_params* ps, int n, abc_batch** out) {
   abc_batch* b = new abc_batch();
   for (int i = 0; i < n; ++i) {
     abc_ctx* c = nullptr;
+    if (ps[i].meanfield == ABC_MF_SKYRME) {
+      abc_destroy_batch(b);
+      return fail(ABC_ENOTSUP, "instance " + std::to_string(i) + ": the Skyrme mean field is not batched");
+    }
     abc_status st = abc_setup(&ps[i], &c);
     if (st != ABC_OK) {
       const std::string msg = "instance " + std::to_string(i) + ": " + g_last_error;

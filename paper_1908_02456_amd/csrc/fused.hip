@@ -953,7 +953,9 @@ hipError_t launch_step_orbitals(OrbitalBatch& ob, void* psi, double2* aux, const
       // the current state: array `in` for even s, the other one for odd s
       const void* cur = ob.soa[q == 0 ? in : 1 - in];
       const unsigned blocks = (unsigned)((np + 255) / 256);
-      if (c64)
+      if (L1.meanfield == ABC_MF_SKYRME)
+        e = skyrme_veff(*L1.pot, cur, true, B, c64, V, ob.veff, L1.t0, L1.t3, st, tm);
+      else if (c64)
         abc_launch_kernel(tm, "meanfield", meanfield_soa_kernel<float>, dim3(blocks), dim3(256), st,
                           static_cast<const float2*>(cur), static_cast<const float*>(V), static_cast<float*>(ob.veff),
                           np, B, float(L1.t0), float(L1.t3));
@@ -961,6 +963,7 @@ hipError_t launch_step_orbitals(OrbitalBatch& ob, void* psi, double2* aux, const
         abc_launch_kernel(tm, "meanfield", meanfield_soa_kernel<double>, dim3(blocks), dim3(256), st,
                           static_cast<const double2*>(cur), static_cast<const double*>(V),
                           static_cast<double*>(ob.veff), np, B, L1.t0, L1.t3);
+      if (e != hipSuccess) return e;
     }
     e = launch_batch_step(L1, B, ob.tz, ob.desc_dev, total, q, st, tm);
     if (e != hipSuccess) return e;

@@ -569,7 +569,11 @@ hipError_t step_staged_t(const abc_launch& L, const abc_scratch& S, void* psi_v,
   const bool box = L.form == ABC_FORM_BOX;
   for (int s = 0; s < n_steps; ++s) {
     const T* Vuse = V;
-    if (L.meanfield) {
+    if (L.meanfield == ABC_MF_SKYRME) {
+      const hipError_t e = skyrme_veff(*L.pot, psi, false, g.batch, sizeof(T) == 4, V, S.veff, L.t0, L.t3, st, tm);
+      if (e != hipSuccess) return e;
+      Vuse = static_cast<const T*>(S.veff);
+    } else if (L.meanfield) {
       abc_launch_kernel(tm, "meanfield", meanfield_kernel<T>, dim3(nblocks(g.npts)), dim3(kBlock), st,
                         (const C*)psi, V, static_cast<T*>(S.veff), g.npts, g.batch, T(L.t0), T(L.t3));
       Vuse = static_cast<const T*>(S.veff);

@@ -51,7 +51,17 @@ def make_params(shape, h, dt, *, radius=1, order="first", form="faces", s0=1.0, 
     p.fejer = 1 if fejer else 0
     p.dtype = _lib.DTYPES[dtype]
     p.batch = int(batch)
-    if meanfield is not None:
+    if isinstance(meanfield, dict):
+        # Sec. 4.3 with the long-range terms: t0, t3, v0, a (Yukawa), e2
+        # (Coulomb), tol and maxit of the conjugate-gradient solves
+        mf = dict(meanfield)
+        p.meanfield = 2
+        p.t0, p.t3 = float(mf.pop("t0", 0.0)), float(mf.pop("t3", 0.0))
+        p.v0, p.a_yukawa, p.e2 = float(mf.pop("v0", 0.0)), float(mf.pop("a", 1.0)), float(mf.pop("e2", 0.0))
+        p.pcg_tol, p.pcg_maxit = float(mf.pop("tol", 1e-12)), int(mf.pop("maxit", 1000))
+        if mf:
+            raise ValueError("unknown mean-field keys %s" % sorted(mf))
+    elif meanfield is not None:
         p.meanfield = 1
         p.t0, p.t3 = float(meanfield[0]), float(meanfield[1])
     p.path = _lib.PATHS[path]
@@ -63,7 +73,9 @@ class Solver:
 
     shape: (nz, ny, nx).  order: "dirichlet" | "periodic" | "zeroth" | "first"
     | "second" (box form; s_points = its four interpolation points).
-    form: "faces" | "box".  dtype: "c128" | "c64".  meanfield: (t0, t3) or None.
+    form: "faces" | "box".  dtype: "c128" | "c64".  meanfield: (t0, t3), a dict with
+    t0, t3, v0, a, e2, tol, maxit (the Skyrme mean field with Yukawa and Coulomb
+    terms), or None.
     """
 
     def __init__(self, shape: Sequence[int], h: float, dt: float, *, radius: int = 1,
@@ -187,6 +199,22 @@ class Solver:
         _lib.check(self._lib.abc_diagnostics(self._ctx, psi.data_ptr(), ap, vp, out.data_ptr(),
                                              _stream_handle(stream)))
         return out
+
+    def effective_potential(self, psi, V=None, out: Optional[torch.Tensor] = None, stream=None):
+        """V + t0 rho + t3 rho^2 + W_Y + W_C of psi (Skyrme mean field only)."""
+        self._check_psi(psi)
+        vp = self._check_V(V)
+        if out is None:
+            out = torch.empty(self.shape, dtype=self.rdtype, device=self.device)
+        _lib.check(self._lib.abc_effective_potential(self._ctx, psi.data_ptr(), vp, out.data_ptr(),
+                                                     _stream_handle(stream)))
+        return out
+
+    def potential_iterations(self):
+        """(mean-field evaluations, Yukawa CG iterations, Coulomb CG iterations)."""
+        buf = (ctypes.c_longlong * 3)()
+        _lib.check(self._lib.abc_potential_iterations(self._ctx, buf))
+        return tuple(int(v) for v in buf)
 
     def export(self, which: int, count: int) -> np.ndarray:
         buf = np.zeros(count, dtype=np.complex128)

@@ -48,7 +48,8 @@ int main(void) {
   printf("%zu", sizeof(abc_params));
 #define F(x) printf(" %zu", offsetof(abc_params, x));
   F(nx) F(ny) F(nz) F(h) F(dt) F(radius) F(order) F(form) F(s0) F(s1) F(s2) F(window) F(fejer)
-  F(dtype) F(batch) F(meanfield) F(t0) F(t3) F(path) F(reserved) F(s3) F(s4)
+  F(dtype) F(batch) F(meanfield) F(t0) F(t3) F(path) F(reserved) F(s3) F(s4) F(v0) F(a_yukawa) F(e2)
+  F(pcg_tol) F(pcg_maxit) F(reserved2)
   printf("\n");
   return 0;
 }
@@ -61,7 +62,8 @@ int main(void) {
         vals = [int(v) for v in subprocess.run([exe], capture_output=True, text=True).stdout.split()]
     P = _lib.AbcParams
     names = ["nx", "ny", "nz", "h", "dt", "radius", "order", "form", "s0", "s1", "s2", "window", "fejer",
-             "dtype", "batch", "meanfield", "t0", "t3", "path", "reserved", "s3", "s4"]
+             "dtype", "batch", "meanfield", "t0", "t3", "path", "reserved", "s3", "s4", "v0", "a_yukawa", "e2",
+             "pcg_tol", "pcg_maxit", "reserved2"]
     assert vals[0] == ctypes.sizeof(P)
     assert vals[1:] == [getattr(P, n).offset for n in names]
 
@@ -71,6 +73,7 @@ def test_defaults_and_error_text(lib):
     lib.abc_params_default(ctypes.byref(p))
     assert (p.radius, p.order, p.form, p.dtype, p.batch, p.fejer) == (1, 3, 1, 0, 1, 1)
     assert (p.s0, p.s1, p.s2, p.s3, p.s4) == (1.0, 1.0, 0.0, 3.0, 10.0)
+    assert (p.v0, p.a_yukawa, p.e2, p.pcg_tol, p.pcg_maxit) == (0.0, 1.0, 0.0, 1e-12, 1000)
     # invalid parameters are rejected before any device call
     p.radius = 7
     ctx = ctypes.c_void_p()
@@ -108,6 +111,11 @@ BAD_PARAMS = [
     (dict(order=4, form=0, s2=0.0), _lib.ABC_EINVAL, b"positive"),
     (dict(order=4, form=0, s2=2.0, s4=float("inf")), _lib.ABC_EINVAL, b"positive"),
     (dict(order=4, form=1, s2=2.0), _lib.ABC_ENOTSUP, b"box form only"),
+    (dict(meanfield=3), _lib.ABC_EINVAL, b"mean field"),
+    (dict(meanfield=2, v0=1.0, a_yukawa=0.0), _lib.ABC_EINVAL, b"Yukawa range"),
+    (dict(meanfield=2, pcg_tol=0.0), _lib.ABC_EINVAL, b"pcg_tol"),
+    (dict(meanfield=2, pcg_maxit=0), _lib.ABC_EINVAL, b"pcg_maxit"),
+    (dict(meanfield=2, e2=float("nan")), _lib.ABC_EINVAL, b"finite"),
 ]
 
 
@@ -135,6 +143,10 @@ def test_reserved_fields_must_be_zero(lib):
     ctx = ctypes.c_void_p()
     assert lib.abc_setup(ctypes.byref(p), ctypes.byref(ctx)) == _lib.ABC_EINVAL
     assert b"reserved" in lib.abc_last_error()
+    p.reserved[2] = 0
+    p.reserved2[1] = 1
+    assert lib.abc_setup(ctypes.byref(p), ctypes.byref(ctx)) == _lib.ABC_EINVAL
+    assert b"reserved" in lib.abc_last_error()
 
 
 def test_h2_objective_rejects_invalid_arguments_without_a_device(lib):
@@ -159,6 +171,8 @@ def test_h2_objective_rejects_invalid_arguments_without_a_device(lib):
 
 def test_null_arguments_are_rejected_without_a_device(lib):
     vp = ctypes.c_void_p
+    assert lib.abc_effective_potential(None, None, None, None, None) == _lib.ABC_EINVAL
+    assert lib.abc_potential_iterations(None, None) == _lib.ABC_EINVAL
     assert lib.abc_setup(None, None) == _lib.ABC_EINVAL
     assert lib.abc_step(None, None, None, None, 1, None) == _lib.ABC_EINVAL
     k = ctypes.c_int(0)
