@@ -83,6 +83,11 @@ struct PotentialSolver {
   double *r = nullptr, *p = nullptr, *q = nullptr;      // CG vectors
   double *part = nullptr, *scal = nullptr;              // 3 nblk partial sums, scalar slots
   double* host = nullptr;                               // pinned: convergence flag, iteration count
+  // sine-transform preconditioner: DST-I matrices and R = 1 eigenvalues per
+  // axis, its work vectors, the preconditioned residual and a rocBLAS handle
+  double *sx = nullptr, *sy = nullptr, *sz = nullptr, *ex = nullptr, *ey = nullptr, *ez = nullptr;
+  double *t1 = nullptr, *t2 = nullptr, *z = nullptr;
+  void* blas = nullptr;
   long long iters_y = 0, iters_c = 0, solves = 0;
 };
 
@@ -189,6 +194,7 @@ struct abc_adjoint_args {
 };
 // V + t0 rho + t3 rho^2 + W_Y + W_C for psi ([point][orbital], or orbital
 // arrays when soa) into veff; synchronises the stream during the solves
+hipError_t potential_warmup(PotentialSolver& ps);
 hipError_t skyrme_veff(PotentialSolver& ps, const void* psi, bool soa, int B, bool c64, const void* V, void* veff,
                        double t0, double t3, hipStream_t st, abc_timer* tm);
 

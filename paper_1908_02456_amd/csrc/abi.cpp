@@ -138,6 +138,7 @@ void abc_destroy(abc_ctx* c) {
   if (!c) return;
   if (c->blas) rocblas_destroy_handle(c->blas);
   if (c->pot.host) (void)hipHostFree(c->pot.host);
+  if (c->pot.blas) rocblas_destroy_handle(static_cast<rocblas_handle>(c->pot.blas));
   if (c->orb) {
     if (c->orb->copied) hipEventDestroy(c->orb->copied);
     if (c->orb->desc_host) hipHostFree(c->orb->desc_host);
@@ -315,11 +316,36 @@ abc_status abc_setup(const abc_params* pp, abc_ctx** out) {
     ps.maxit = p.pcg_maxit;
     const size_t np = (size_t)L.g.npts;
     ps.nblk = (int)std::min<size_t>(1024, (np + 255) / 256);
-    double** vec[6] = {&ps.rho, &ps.wy, &ps.wc, &ps.r, &ps.p, &ps.q};
-    for (int i = 0; i < 6 && st == ABC_OK; ++i) {
+    double** vec[9] = {&ps.rho, &ps.wy, &ps.wc, &ps.r, &ps.p, &ps.q, &ps.t1, &ps.t2, &ps.z};
+    for (int i = 0; i < 9 && st == ABC_OK; ++i) {
       st = dev_alloc(c, &tmp, np * sizeof(double));
       *vec[i] = static_cast<double*>(tmp);
     }
+    // sine transforms and R = 1 eigenvalues per axis (preconditioner)
+    const int dims[3] = {p.nx, p.ny, p.nz};
+    double** mats[3] = {&ps.sx, &ps.sy, &ps.sz};
+    double** eigs[3] = {&ps.ex, &ps.ey, &ps.ez};
+    for (int a = 0; a < 3 && st == ABC_OK; ++a) {
+      const int n = dims[a];
+      std::vector<double> S((size_t)n * n), ev(n);
+      for (int j = 0; j < n; ++j) {
+        ev[j] = (2.0 - 2.0 * std::cos(M_PI * (j + 1) / (n + 1))) / (p.h * p.h);
+        for (int k = 0; k < n; ++k) S[(size_t)j * n + k] = std::sin(M_PI * (double)(j + 1) * (k + 1) / (n + 1));
+      }
+      st = dev_alloc(c, &tmp, S.size() * sizeof(double));
+      *mats[a] = static_cast<double*>(tmp);
+      if (st == ABC_OK) st = dev_alloc(c, &tmp, ev.size() * sizeof(double));
+      if (st == ABC_OK) *eigs[a] = static_cast<double*>(tmp);
+      if (st == ABC_OK && (hipMemcpy(*mats[a], S.data(), S.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
+                           hipMemcpy(*eigs[a], ev.data(), ev.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess))
+        st = fail(ABC_EDEVICE, "hipMemcpy failed");
+    }
+    if (st == ABC_OK) {
+      rocblas_handle hb = nullptr;
+      if (rocblas_create_handle(&hb) != rocblas_status_success) st = fail(ABC_EDEVICE, "rocblas_create_handle failed");
+      else ps.blas = hb;
+    }
+    if (st == ABC_OK && potential_warmup(ps) != hipSuccess) st = fail(ABC_EDEVICE, "potential solver set-up failed");
     if (st == ABC_OK) st = dev_alloc(c, &tmp, 3 * (size_t)ps.nblk * sizeof(double));
     ps.part = static_cast<double*>(tmp);
     if (st == ABC_OK) st = dev_alloc(c, &tmp, 8 * sizeof(double));

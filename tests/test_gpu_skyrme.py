@@ -47,7 +47,10 @@ def test_effective_potential_matches_oracle(shape, R, batch):
     got = s.effective_potential(torch.from_numpy(psi0).cuda(), torch.from_numpy(V).cuda()).cpu().numpy()
     assert np.abs(got - ref).max() < 1e-11 * np.abs(ref).max()
     n_eval, iy, ic = s.potential_iterations()
-    assert n_eval == 1 and iy > 5 and ic > 5
+    assert n_eval == 1 and iy >= 1 and ic >= 1
+    if R == 1:
+        # the sine-transform preconditioner is the exact inverse for R = 1
+        assert iy <= 3 and ic <= 3, (iy, ic)
     # the same state again: the solves start from their own solution
     s.effective_potential(torch.from_numpy(psi0).cuda(), torch.from_numpy(V).cuda())
     n2, iy2, ic2 = s.potential_iterations()
