@@ -337,21 +337,22 @@ __device__ __forceinline__ void fused2_body(const typename cpx<T>::t* __restrict
   for (int it = 0; it < ITERS; ++it) {
     const int zi = z0 - H + it;
     auto& plane = planes[DBN == 2 ? (it & 1) : 0];  // rows published by the previous iteration
-    if (ORDER == 3 && r == 0 && lane < 2 * TY) {
-      // First-order x faces, done by the top halo wave (idle in both stages),
-      // one lane per (own row, side).  It reads the rows published at the end
-      // of the previous iteration: plane[0] holds w at plane zi-1 and
-      // plane[1] the stage-1 output s1 at plane zi-2.
-      //  * v_f = fb_f + cA (b av_f + a w) at plane zi-1, for the next
-      //    iteration's stage 2 (LDS ring);
-      //  * the auxiliary output fb_f + cB (b v_f + a s1) at plane zi-2.
+    if (ORDER == 3 && (r == 0 || r == ROWS - 1) && lane < 2 * TY) {
+      // First-order x faces, done by the two halo waves at the tile's edges
+      // (idle in both stages), one lane per (own row, side).  They read the
+      // rows published at the end of the previous iteration: plane[0] holds w
+      // at plane zi-1 and plane[1] the stage-1 output s1 at plane zi-2.
+      //  * top wave: v_f = fb_f + cA (b av_f + a w) at plane zi-1, for the
+      //    next iteration's stage 2 (LDS ring);
+      //  * bottom wave: the auxiliary output fb_f + cB (b v_f + a s1) at
+      //    plane zi-2 (v_f from the ring, written an iteration earlier).
       const int j = lane >> 1, side = lane & 1;
       const int rj = H + j, yj = y0 + j;
       const int xf = side ? nx - 1 : 0, lxf = xf - xb;
       if (lxf >= 0 && lxf < kCols && yj < ny) {
         const int ci = lxf & 1, li = (lxf >> 1) + 1, rr = rj - 1;
         const int p1 = zi - 1, p2 = zi - 2;
-        if (p1 >= z0 && p1 < z0 + TZ && p1 < nz) {
+        if (r == 0 && p1 >= z0 && p1 < z0 + TZ && p1 < nz) {
           const int pl = p1 - (z0 - 1);
           const double2 g = fxg[(side * FP + pl) * FR + rr];
           const double2 f0 = fxf[(side * TZ + (p1 - z0)) * TY + j];
@@ -359,7 +360,7 @@ __device__ __forceinline__ void fused2_body(const typename cpx<T>::t* __restrict
           const double2 bg = cmul(a.b0, g), aw = cmul(a.a0, make_double2((double)wv.x, (double)wv.y));
           vx[((p1 & 1) * TY + j) * 2 + side] = make_double2(f0.x + cA * (bg.x + aw.x), f0.y + cA * (bg.y + aw.y));
         }
-        if (p2 >= z0 && p2 < z0 + TZ && p2 < nz && xf >= xo && xf < xe) {
+        if (r == ROWS - 1 && p2 >= z0 && p2 < z0 + TZ && p2 < nz && xf >= xo && xf < xe) {
           const double2 f0 = fxf[(side * TZ + (p2 - z0)) * TY + j];
           const double2 v = vx[((p2 & 1) * TY + j) * 2 + side];
           const C s1 = plane[1][rj][ci][li];
@@ -381,6 +382,25 @@ __device__ __forceinline__ void fused2_body(const typename cpx<T>::t* __restrict
       wm2[c] = Yb[0][c];
     }
     if (it + PF < ITERS) fetch(zi + PF, q);
+    // First order: the x-face sources of this iteration's two stages, read
+    // from LDS by the lanes holding a face column ahead of the stencil work,
+    // so that their latency overlaps it.  Indices are clamped in range; they
+    // do not bind in the active stages that use the values.  Stage 1: av at
+    // plane zi-1; stage 2: v at plane zi-2 from the halo wave's ring.
+    double2 gx[2] = {make_double2(0, 0), make_double2(0, 0)};
+    int cxf = -1;
+    if (ORDER == 3) {
+      const int x0 = xb + 2 * lane;
+      cxf = (x0 == 0 || x0 == nx - 1) ? 0 : ((x0 + 1 == nx - 1) ? 1 : -1);
+      if (cxf >= 0) {
+        const int side = x0 + cxf == 0 ? 0 : 1;
+        const int rrc = min(max(r - 1, 0), FR - 1);
+        const int plc = min(max(zi - z0, 0), FP - 1);
+        const int jc = min(max(r - H, 0), TY - 1);
+        gx[0] = fxg[(side * FP + plc) * FR + rrc];
+        gx[1] = vx[(((zi - 2) & 1) * TY + jc) * 2 + side];
+      }
+    }
 #pragma unroll
     for (int k = 1; k <= 2; ++k) {
       const int zk = zi - k;
@@ -423,20 +443,14 @@ __device__ __forceinline__ void fused2_body(const typename cpx<T>::t* __restrict
         // output as -i cf g.
         const int pl = zk - (z0 - 1), rr = r - 1;
         const double cf2 = k == 1 ? cA : cB;
-        // x faces: at most one column per lane, its source ready in LDS
-        // (stage 1: av; stage 2: v from the halo wave's ring)
-        {
-          const int x0 = xb + 2 * lane;
-          const int cx = (x0 == 0 || x0 == nx - 1) ? 0 : ((x0 + 1 == nx - 1) ? 1 : -1);
-          if (cx >= 0) {
-            const int side = x0 + cx == 0 ? 0 : 1;
-            const double2 g = k == 1 ? fxg[(side * FP + pl) * FR + rr] : vx[((zk & 1) * TY + (r - H)) * 2 + side];
-            const T dx = T(cf2 * g.y), dy = T(-cf2 * g.x);
-            o[0].x += cx ? T(0) : dx;
-            o[0].y += cx ? T(0) : dy;
-            o[1].x += cx ? dx : T(0);
-            o[1].y += cx ? dy : T(0);
-          }
+        // x faces: at most one column per lane, its source read above
+        if (cxf >= 0) {
+          const double2 g = gx[k - 1];
+          const T dx = T(cf2 * g.y), dy = T(-cf2 * g.x);
+          o[0].x += cxf ? T(0) : dx;
+          o[0].y += cxf ? T(0) : dy;
+          o[1].x += cxf ? dx : T(0);
+          o[1].y += cxf ? dy : T(0);
         }
         // y and z faces: whole rows (wave-uniform), both columns of each lane,
         // sources precomputed at staging; stage 2 also writes the auxiliary
