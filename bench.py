@@ -380,6 +380,33 @@ def bench_h2_point(Solver, torch, wl, modes=64, nodes=4096):
     return out
 
 
+def bench_face_windows(Solver, torch, wl, steps_timed=20):
+    """The headline workload with wider face operators: w = 0 (fused path),
+    w = 8 with the Fejer window (staged, direct convolution) and the exact
+    section w = n - 1 (staged, zero-padded 2D FFTs): time per step and the
+    relative error against the large zero-boundary box after 2000 steps."""
+    ref = large_box_reference(Solver, torch, wl, "c128", "auto", wl.steps)
+    nr = torch.linalg.vector_norm(ref).item()
+    V = torch.from_numpy(wl.V).cuda()
+    out = {}
+    for name, w, fejer in (("w0", 0, True), ("w8_fejer", 8, True), ("exact_fft", wl.n - 1, False)):
+        log("  face windows: %s" % name)
+        s = Solver((wl.n,) * 3, wl.h, wl.dt, order="first", s1=wl.s1, window=w, fejer=fejer)
+        psi = torch.from_numpy(wl.psi0).cuda()
+        aux = s.new_aux()
+        s.step(psi, aux, V, 2)
+        ms = _time(torch, lambda: s.step(psi, aux, V, steps_timed)) / steps_timed
+        psi = torch.from_numpy(wl.psi0).cuda()
+        aux = s.new_aux()
+        s.step(psi, aux, V, wl.steps)
+        torch.cuda.synchronize()
+        out[name] = {"window": w, "fejer": fejer, "ms_per_step": ms, "path": "fused" if s.use_fused else "staged",
+                     "err_vs_large_box": torch.linalg.vector_norm(psi - ref).item() / nr}
+        del s, psi, aux
+        torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(wl, window, budget_s=15.0):
     """FP64 oracle (NumPy, single-threaded elementwise) on the same workload,
     for as many whole steps as fit in about budget_s seconds."""
@@ -524,7 +551,8 @@ def main():
                          ("box_batch", lambda: bench_box_batch(Solver, torch, W)),
                          ("orders_box", lambda: bench_orders_box(Solver, torch, W)),
                          ("box64", lambda: bench_box64(Solver, torch, W)),
-                         ("h2_point", lambda: bench_h2_point(Solver, torch, wl))):
+                         ("h2_point", lambda: bench_h2_point(Solver, torch, wl)),
+                         ("face_windows", lambda: bench_face_windows(Solver, torch, wl))):
             log("extra: %s" % name)
             try:
                 extra[name] = fn()

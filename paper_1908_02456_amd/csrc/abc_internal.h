@@ -91,6 +91,18 @@ struct PotentialSolver {
   long long iters_y = 0, iters_c = 0, solves = 0;
 };
 
+// Exact face sections (fejer = 0, window >= max(n) - 1) applied by FFT:
+// every face layer zero-padded to P1 x P2 (powers of two >= 2 n - 1), the
+// kernel's spectra precomputed per face pair (x, y, z faces share sizes and
+// kernel), circular convolution in the transform domain (kernels_staged.hip)
+struct FaceFFT {
+  int P1[3], P2[3], S[3];      // per face pair: padded sizes, slabs (2 faces x R layers x batch)
+  long long woff[4];           // each pair's slabs in W and Z (complex elements)
+  long long soff[4];           // each pair's R x R kernel spectra in spec
+  long long twoff[3][4];       // twiddles per pair: forward / inverse along t2, forward / inverse along t1
+  double2 *W, *Z, *spec, *tw;
+};
+
 struct abc_launch {
   abc::Geometry g;
   double h, dt;
@@ -101,6 +113,7 @@ struct abc_launch {
   PotentialSolver* pot;        // ABC_MF_SKYRME solves (or null)
   // face operators
   const double2* face_ker;
+  const FaceFFT* face_fft;     // exact sections by FFT (staged path), or null
   double2 a_loc[abc::kMaxR * abc::kMaxR];
   double2 q_loc[abc::kMaxR * abc::kMaxR];
   double2 fused_m0, fused_b0;  // window-0 face operator value (host copy)
@@ -192,6 +205,11 @@ struct abc_adjoint_args {
   double* J_host;
   int use_fused;  // forward sweep on the fused path
 };
+// Build the FFT plan of the exact face sections (device buffers appended to
+// allocs); the kernel is ops.kernel, of width w >= max(n) - 1
+abc_status face_fft_setup(const abc::Geometry& g, int R, int w, const std::vector<abc::cd>& kernel, FaceFFT& ff,
+                          std::vector<void*>* allocs, size_t* bytes, std::string& err);
+
 // V + t0 rho + t3 rho^2 + W_Y + W_C for psi ([point][orbital], or orbital
 // arrays when soa) into veff; synchronises the stream during the solves
 hipError_t potential_warmup(PotentialSolver& ps);

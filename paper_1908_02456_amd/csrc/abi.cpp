@@ -41,6 +41,7 @@ struct abc_ctx {
   abc_launch La{};                         // adjoint operator set (built on first abc_adjoint)
   bool adjoint_ready = false;
   PotentialSolver pot;                     // ABC_MF_SKYRME solves
+  FaceFFT fft{};                           // exact face sections by FFT
 };
 
 namespace {
@@ -199,6 +200,13 @@ abc_status abc_setup(const abc_params* pp, abc_ctx** out) {
     }
     L.face_ker = static_cast<const double2*>(kd);
     L.fused_m0 = L.fused_b0 = make_double2(c->face.kernel[0].real(), c->face.kernel[0].imag());
+    // exact sections (no taper, window covering every face): apply them by
+    // zero-padded 2D FFTs instead of the direct convolution
+    if (p.fejer == 0 && p.window >= std::max({p.nx, p.ny, p.nz}) - 1) {
+      st = face_fft_setup(L.g, p.radius, p.window, c->face.kernel, c->fft, &c->allocations, &c->bytes, err);
+      if (st != ABC_OK) { abc_destroy(c); return fail(st, err); }
+      L.face_fft = &c->fft;
+    }
     // Lyapunov-weighted block bound: zeroth order adds up to three faces'
     // operators to H; first order couples psi and f through blocks of norm
     // |H_{Gamma,Sigma}| (three faces at a corner) and B acts on f
@@ -475,6 +483,7 @@ abc_status build_adjoint(abc_ctx* c) {
   abc_launch& La = c->La;
   La = c->L;
   La.dt = -c->L.dt;
+  La.face_fft = nullptr;  // the adjoint kernel is applied directly
   if (c->p.order == ABC_ZEROTH || c->p.order == ABC_FIRST) {
     const int R = c->p.radius, K = 2 * c->p.window + 1;
     const double sgn = c->p.order == ABC_FIRST ? -1.0 : 1.0;

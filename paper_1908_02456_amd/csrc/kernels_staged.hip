@@ -15,6 +15,9 @@
 
 #include <rocblas/rocblas.h>
 
+#include <algorithm>
+#include <cmath>
+
 #include "abc_internal.h"
 
 using abc::Geometry;
@@ -253,6 +256,202 @@ __global__ void __launch_bounds__(kBlock) face_kernel(
     const double2 s = facc[e];
     aux_out[e] = make_double2(s.x + gn.x, s.y + gn.y);
   }
+}
+
+// ---------------------------------------------------------------------------
+// exact face sections by FFT.  Per face pair q (faces 2q, 2q + 1) the slabs
+// s = (side R + l) B + b of P1 x P2 points ([t1][t2]) hold the zero-padded
+// face layers; the circular convolution with the padded kernel equals the
+// Toeplitz section on the n1 x n2 face because P >= 2 n - 1.
+// ---------------------------------------------------------------------------
+
+// x (the aux stage, or E y for the zeroth order) into the padded slabs of pair q
+template <typename T>
+__global__ void __launch_bounds__(kBlock) fft_pack_kernel(const double2* __restrict__ gin,
+                                                          const typename cpx<T>::t* __restrict__ yin, int first,
+                                                          Geometry g, FaceFFT ff, int q) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int P1 = ff.P1[q], P2 = ff.P2[q], R = g.R, B = g.batch;
+  const long long per = (long long)P1 * P2;
+  if (e >= (long long)ff.S[q] * per) return;
+  const int sl = (int)(e / per);
+  const int m = (int)(e - (long long)sl * per);
+  const int i1 = m / P2, i2 = m % P2;
+  const int b = sl % B, l = (sl / B) % R, side = sl / (B * R);
+  const int f = 2 * q + side;
+  const int n1 = g.face_n1[f], n2 = g.face_n2[f];
+  double2 v = make_double2(0.0, 0.0);
+  if (i1 < n1 && i2 < n2) {
+    if (first) {
+      v = gin[g.face_off[f] + (((long long)l * n1 + i1) * n2 + i2) * B + b];
+    } else {
+      const auto yv = yin[face_point(g, f, l, i1, i2) * B + b];
+      v = make_double2((double)yv.x, (double)yv.y);
+    }
+  }
+  ff.W[ff.woff[q] + e] = v;
+}
+
+// radix-2 transforms of TW lines of length L = 2^logL per workgroup in LDS
+// ([t][k]); line t of group gi starts at (gi / per) A + (gi % per) TW C +
+// t tstride and steps kstride; tw[k] = exp(+-2 pi i k / L), k < L/2
+__global__ void __launch_bounds__(kBlock) fft_lines_kernel(double2* __restrict__ a, const double2* __restrict__ tw,
+                                                           int L, int logL, int TW, int per, long long A, long long C,
+                                                           long long tstride, long long kstride) {
+  extern __shared__ double2 buf[];
+  const int gi = blockIdx.x;
+  const long long base = (long long)(gi / per) * A + (long long)(gi % per) * TW * C;
+  const int tot = TW * L;
+  const bool kfast = kstride == 1;
+  for (int e = threadIdx.x; e < tot; e += blockDim.x) {
+    const int t = kfast ? e / L : e % TW;
+    const int k = kfast ? e % L : e / TW;
+    const unsigned rk = __brev((unsigned)k) >> (32 - logL);
+    buf[t * L + rk] = a[base + t * tstride + k * kstride];
+  }
+  __syncthreads();
+  for (int len = 2, sh = 1; len <= L; len <<= 1, ++sh) {
+    const int half = len >> 1, step = L >> sh;
+    for (int bf = threadIdx.x; bf < tot / 2; bf += blockDim.x) {
+      const int t = bf / (L / 2), r = bf % (L / 2);
+      const int grp = r / half, pos = r % half;
+      const int i0 = t * L + grp * len + pos, i1 = i0 + half;
+      const double2 w = tw[pos * step];
+      const double2 u = buf[i0], v0 = buf[i1];
+      const double2 v = make_double2(v0.x * w.x - v0.y * w.y, v0.x * w.y + v0.y * w.x);
+      buf[i0] = make_double2(u.x + v.x, u.y + v.y);
+      buf[i1] = make_double2(u.x - v.x, u.y - v.y);
+    }
+    __syncthreads();
+  }
+  for (int e = threadIdx.x; e < tot; e += blockDim.x) {
+    const int t = kfast ? e / L : e % TW;
+    const int k = kfast ? e % L : e / TW;
+    a[base + t * tstride + k * kstride] = buf[t * L + k];
+  }
+}
+
+// Z(l) = sum_l' spec(l, l') W(l') / (P1 P2) per point of the spectra, pair q
+__global__ void __launch_bounds__(kBlock) fft_mul_kernel(FaceFFT ff, int q, int R, int B) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long per = (long long)ff.P1[q] * ff.P2[q];
+  if (e >= (long long)ff.S[q] * per) return;
+  const int sl = (int)(e / per);
+  const long long m = e - (long long)sl * per;
+  const int b = sl % B, l = (sl / B) % R, side = sl / (B * R);
+  const double inv = 1.0 / (double)per;
+  double zr = 0, zi = 0;
+  for (int lp = 0; lp < R; ++lp) {
+    const double2 k = ff.spec[ff.soff[q] + (long long)(l * R + lp) * per + m];
+    const double2 x = ff.W[ff.woff[q] + ((long long)((side * R + lp) * B + b)) * per + m];
+    zr += k.x * x.x - k.y * x.y;
+    zi += k.x * x.y + k.y * x.x;
+  }
+  ff.Z[ff.woff[q] + e] = make_double2(zr * inv, zi * inv);
+}
+
+// the face_kernel epilogue on the convolution read from Z
+template <typename T, int R>
+__global__ void __launch_bounds__(kBlock) fft_finish_kernel(
+    const double2* __restrict__ gin, double2* __restrict__ gout, double2* __restrict__ facc,
+    double2* __restrict__ aux_out, const typename cpx<T>::t* __restrict__ yin, LocalBlock a, Geometry g, FaceFFT ff,
+    double coef, int mode, int first) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int B = g.batch;
+  if (e >= g.face_off[6]) return;
+  int f = 0;
+  while (e >= g.face_off[f + 1]) ++f;
+  const long long r = e - g.face_off[f];
+  const int n1 = g.face_n1[f], n2 = g.face_n2[f];
+  const int b = (int)(r % B);
+  const long long qq = r / B;
+  const int t2 = (int)(qq % n2);
+  const int t1 = (int)((qq / n2) % n1);
+  const int l = (int)(qq / ((long long)n1 * n2));
+  const int q = f >> 1, side = f & 1;
+  const long long per = (long long)ff.P1[q] * ff.P2[q];
+  const double2 cv = ff.Z[ff.woff[q] + ((long long)((side * R + l) * B + b)) * per + (long long)t1 * ff.P2[q] + t2];
+  double sr = cv.x, si = cv.y;
+  if (!first) {
+    gout[e] = make_double2(sr, si);
+    return;
+  }
+  for (int lp = 0; lp < R; ++lp) {
+    const double2 av = a.m[l * R + lp];
+    const auto yv = yin[face_point(g, f, lp, t1, t2) * B + b];
+    const double yr = (double)yv.x, yi = (double)yv.y;
+    sr += av.x * yr - av.y * yi;
+    si += av.x * yi + av.y * yr;
+  }
+  const double2 gn = make_double2(coef * sr, coef * si);
+  if (mode == 0) {
+    const double2 g0 = gin[e];
+    facc[e] = make_double2(g0.x + gn.x, g0.y + gn.y);
+    gout[e] = gn;
+  } else if (mode == 1) {
+    double2 s2 = facc[e];
+    s2.x += gn.x;
+    s2.y += gn.y;
+    facc[e] = s2;
+    gout[e] = gn;
+  } else {
+    const double2 s2 = facc[e];
+    aux_out[e] = make_double2(s2.x + gn.x, s2.y + gn.y);
+  }
+}
+
+inline int ilog2(int v) {
+  int k = 0;
+  while ((1 << k) < v) ++k;
+  return k;
+}
+
+// 2D transform of S slabs of P1 x P2 points at base, with the twiddle
+// tables tw2 (length P2 lines) and tw1 (length P1 lines); at most 64 KB of
+// LDS per workgroup (P <= 4096)
+hipError_t fft2_slabs(double2* base, int P1, int P2, int S, const double2* tw2, const double2* tw1, hipStream_t st) {
+  {
+    const int L = P2, TW = std::min(P1, std::max(1, 4096 / L));
+    fft_lines_kernel<<<S * P1 / TW, kBlock, (size_t)TW * L * sizeof(double2), st>>>(
+        base, tw2, L, ilog2(L), TW, 1, (long long)TW * L, 0, L, 1);
+  }
+  {
+    const int L = P1, TW = std::min(P2, std::max(1, 4096 / L));
+    const int per = P2 / TW;
+    fft_lines_kernel<<<S * per, kBlock, (size_t)TW * L * sizeof(double2), st>>>(
+        base, tw1, L, ilog2(L), TW, per, (long long)P1 * P2, 1, 1, P2);
+  }
+  return hipGetLastError();
+}
+
+// 2D transform of every slab of pair q in a (forward: fwd = 1)
+hipError_t fft2_pair(const FaceFFT& ff, double2* a, int q, bool fwd, hipStream_t st) {
+  return fft2_slabs(a + ff.woff[q], ff.P1[q], ff.P2[q], ff.S[q], ff.tw + ff.twoff[q][fwd ? 0 : 1],
+                    ff.tw + ff.twoff[q][fwd ? 2 : 3], st);
+}
+
+// the face operator of one stage by FFT: gout (first order: coef (B g + A E
+// y) with the Taylor modes of face_kernel; zeroth: M E y)
+template <typename T, int R>
+hipError_t face_fft_apply(const abc_launch& L, const double2* gin, double2* gout, double2* facc, double2* aux_out,
+                          const typename cpx<T>::t* yin, const LocalBlock& a, double coef, int mode, int first,
+                          hipStream_t st, abc_timer* tm, const char* label) {
+  const FaceFFT& ff = *L.face_fft;
+  const Geometry& g = L.g;
+  for (int q = 0; q < 3; ++q) {
+    const long long cnt = (long long)ff.S[q] * ff.P1[q] * ff.P2[q];
+    const unsigned nb = (unsigned)((cnt + kBlock - 1) / kBlock);
+    fft_pack_kernel<T><<<nb, kBlock, 0, st>>>(gin, yin, first, g, ff, q);
+    hipError_t e = fft2_pair(ff, ff.W, q, true, st);
+    if (e != hipSuccess) return e;
+    fft_mul_kernel<<<nb, kBlock, 0, st>>>(ff, q, g.R, g.batch);
+    e = fft2_pair(ff, ff.Z, q, false, st);
+    if (e != hipSuccess) return e;
+  }
+  const long long nface = g.face_off[6];
+  abc_launch_kernel(tm, label, fft_finish_kernel<T, R>, dim3((unsigned)((nface + kBlock - 1) / kBlock)), dim3(kBlock),
+                    st, gin, gout, facc, aux_out, yin, a, g, ff, coef, mode, first);
+  return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
@@ -623,6 +822,10 @@ hipError_t step_staged_t(const abc_launch& L, const abc_scratch& S, void* psi_v,
                             abc::box_aux_rows(L.order, n), abc::box_cols(L.order, n),
                             L.order == ABC_SECOND ? n : 0, gcur, ycur, L.gamma_lin,
                             rec ? gnext : S.src, S.facc, aux, g.batch, coef, mode);
+        } else if (L.face_fft) {
+          const hipError_t e = face_fft_apply<T, R>(L, gcur, rec ? gnext : S.src, S.facc, aux, ycur, a, coef, mode,
+                                                    rec ? 1 : 0, st, tm, kBoundLabel[k]);
+          if (e != hipSuccess) return e;
         } else {
           abc_launch_kernel(tm, kBoundLabel[k], face_kernel<T, R>, dim3(nblocks(nface)), dim3(kBlock), st, gcur,
                             rec ? gnext : S.src, S.facc, aux, ycur, L.face_ker, a, g, L.w, coef, mode,
@@ -702,4 +905,80 @@ hipError_t launch_diagnostics(const abc_launch& L, const abc_scratch& S, const v
                               const void* V, double* out, hipStream_t st) {
   if (L.dtype == ABC_C64) return dispatch_diag<float>(L, S, psi, aux, V, out, st);
   return dispatch_diag<double>(L, S, psi, aux, V, out, st);
+}
+
+// FFT plan of the exact face sections: padded sizes per face pair, work
+// slabs, twiddle tables, and the kernel spectra (the padded R x R kernel
+// layers transformed on the device)
+abc_status face_fft_setup(const Geometry& g, int R, int w, const std::vector<abc::cd>& kernel, FaceFFT& ff,
+                          std::vector<void*>* allocs, size_t* bytes, std::string& err) {
+  const int K = 2 * w + 1, B = g.batch;
+  long long woff = 0, soff = 0;
+  std::vector<double2> tw;
+  for (int q = 0; q < 3; ++q) {
+    const int n1 = g.face_n1[2 * q], n2 = g.face_n2[2 * q];
+    if (w < n1 - 1 || w < n2 - 1) { err = "the FFT face path needs the exact section (window >= n - 1)"; return ABC_EINVAL; }
+    int P1 = 2, P2 = 2;
+    while (P1 < 2 * n1 - 1) P1 *= 2;
+    while (P2 < 2 * n2 - 1) P2 *= 2;
+    if (P1 > 4096 || P2 > 4096) { err = "face too large for the FFT face path"; return ABC_ENOTSUP; }
+    ff.P1[q] = P1;
+    ff.P2[q] = P2;
+    ff.S[q] = 2 * R * B;
+    ff.woff[q] = woff;
+    woff += (long long)ff.S[q] * P1 * P2;
+    ff.soff[q] = soff;
+    soff += (long long)R * R * P1 * P2;
+    const int Ls[4] = {P2, P2, P1, P1};
+    const double sg[4] = {-1.0, 1.0, -1.0, 1.0};
+    for (int j = 0; j < 4; ++j) {
+      ff.twoff[q][j] = (long long)tw.size();
+      for (int k = 0; k < Ls[j] / 2; ++k)
+        tw.push_back(make_double2(std::cos(2 * M_PI * k / Ls[j]), sg[j] * std::sin(2 * M_PI * k / Ls[j])));
+    }
+  }
+  ff.woff[3] = woff;
+  ff.soff[3] = soff;
+  std::vector<double2> spec((size_t)soff, make_double2(0.0, 0.0));
+  for (int q = 0; q < 3; ++q) {
+    const int n1 = g.face_n1[2 * q], n2 = g.face_n2[2 * q], P1 = ff.P1[q], P2 = ff.P2[q];
+    for (int l = 0; l < R; ++l)
+      for (int lp = 0; lp < R; ++lp) {
+        double2* dst = spec.data() + ff.soff[q] + (long long)(l * R + lp) * P1 * P2;
+        for (int p1 = -(n1 - 1); p1 <= n1 - 1; ++p1)
+          for (int p2 = -(n2 - 1); p2 <= n2 - 1; ++p2) {
+            const abc::cd v = kernel[((size_t)(l * R + lp) * K + (p1 + w)) * K + (p2 + w)];
+            dst[(size_t)((p1 + P1) % P1) * P2 + (p2 + P2) % P2] = make_double2(v.real(), v.imag());
+          }
+      }
+  }
+  void *pw = nullptr, *pz = nullptr, *ps = nullptr, *pt = nullptr;
+  const size_t wb = (size_t)woff * sizeof(double2), sb = (size_t)soff * sizeof(double2), tb = tw.size() * sizeof(double2);
+  auto dalloc = [&](void** ptr, size_t nbytes) {
+    if (hipMalloc(ptr, nbytes) != hipSuccess) return false;
+    allocs->push_back(*ptr);
+    *bytes += nbytes;
+    return true;
+  };
+  if (!dalloc(&pw, wb) || !dalloc(&pz, wb) || !dalloc(&ps, sb) || !dalloc(&pt, tb)) {
+    err = "device allocation for the FFT face path failed";
+    return ABC_ENOMEM;
+  }
+  ff.W = static_cast<double2*>(pw);
+  ff.Z = static_cast<double2*>(pz);
+  ff.spec = static_cast<double2*>(ps);
+  ff.tw = static_cast<double2*>(pt);
+  if (hipMemcpy(ff.spec, spec.data(), sb, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(ff.tw, tw.data(), tb, hipMemcpyHostToDevice) != hipSuccess) {
+    err = "hipMemcpy failed";
+    return ABC_EDEVICE;
+  }
+  for (int q = 0; q < 3; ++q)
+    if (fft2_slabs(ff.spec + ff.soff[q], ff.P1[q], ff.P2[q], R * R, ff.tw + ff.twoff[q][0], ff.tw + ff.twoff[q][2],
+                   nullptr) != hipSuccess) {
+      err = "kernel spectra transform failed";
+      return ABC_EDEVICE;
+    }
+  if (hipDeviceSynchronize() != hipSuccess) { err = "kernel spectra transform failed"; return ABC_EDEVICE; }
+  return ABC_OK;
 }
