@@ -248,7 +248,8 @@ abc_status abc_setup(const abc_params* pp, abc_ctx** out) {
   // fourth-order Taylor polynomial: |T4(i y)| <= 1 requires |y| <= 2 sqrt(2)
   if (p.dt * rho > 2.0 * std::sqrt(2.0)) {
     abc_destroy(c);
-    return fail(ABC_EUNSTABLE, "dt times the spectral bound exceeds the Taylor-4 stability limit 2 sqrt(2)");
+    return fail(ABC_EUNSTABLE, "dt times the spectral bound exceeds the Taylor-4 stability limit 2 sqrt(2) (dt * bound = " +
+                                   std::to_string(p.dt * rho) + ")");
   }
 
   // scratch
@@ -289,7 +290,7 @@ abc_status abc_setup(const abc_params* pp, abc_ctx** out) {
       const rocblas_double_complex one = {1.0, 0.0}, zero = {0.0, 0.0};
       if (rocblas_create_handle(&c->blas) != rocblas_status_success ||
           hipMemset(S.bwork[0], 0, naux * 16) != hipSuccess ||
-          rocblas_zgemm(c->blas, rocblas_operation_none, rocblas_operation_none, nb, n, n, &one,
+          rocblas_zgemm_64(c->blas, rocblas_operation_none, rocblas_operation_none, nb, n, n, &one,
                         reinterpret_cast<const rocblas_double_complex*>(S.bwork[0]), nb,
                         reinterpret_cast<const rocblas_double_complex*>(L.box_mat), ld, &zero,
                         reinterpret_cast<rocblas_double_complex*>(S.bwork[1]), nb) != rocblas_status_success ||

@@ -802,12 +802,12 @@ hipError_t step_staged_t(const abc_launch& L, const abc_scratch& S, void* psi_v,
           rocblas_handle hb = static_cast<rocblas_handle>(L.blas);
           rocblas_status rs = rocblas_set_stream(hb, st);
           if (rs == rocblas_status_success && rec)
-            rs = rocblas_zgemm(hb, rocblas_operation_none, rocblas_operation_none, nb, rows, na, &one,
+            rs = rocblas_zgemm_64(hb, rocblas_operation_none, rocblas_operation_none, nb, rows, na, &one,
                                reinterpret_cast<const rocblas_double_complex*>(gcur), nb,
                                reinterpret_cast<const rocblas_double_complex*>(L.box_mat), ld, &zero,
                                reinterpret_cast<rocblas_double_complex*>(tout), nb);
           if (rs == rocblas_status_success)
-            rs = rocblas_zgemm(hb, rocblas_operation_none, rocblas_operation_none, nb, rows, n, &one,
+            rs = rocblas_zgemm_64(hb, rocblas_operation_none, rocblas_operation_none, nb, rows, n, &one,
                                reinterpret_cast<const rocblas_double_complex*>(S.bwork[0]), nb,
                                reinterpret_cast<const rocblas_double_complex*>(L.box_mat + na), ld,
                                rec ? &one : &zero, reinterpret_cast<rocblas_double_complex*>(tout), nb);

@@ -329,16 +329,17 @@ struct GammaDev {
 // solve A X = B in place of B (A: m x m column-major, destroyed; B: m x nrhs)
 abc_status lu_solve(rocblas_handle hnd, DevBufs& db, int m, int nrhs, double2* A, double2* B, std::string& err,
                     const char* what) {
-  rocblas_int* ipiv = nullptr;
-  rocblas_int* info = nullptr;
+  // 64-bit index interface: m * m may exceed 2^31 (the second order's 4n system)
+  int64_t* ipiv = nullptr;
+  int64_t* info = nullptr;
   if (!db.alloc(&ipiv, (size_t)m) || !db.alloc(&info, 1)) { err = "hipMalloc failed"; return ABC_ENOMEM; }
-  if (rocsolver_zgetrf(hnd, m, m, reinterpret_cast<zc*>(A), m, ipiv, info) != rocblas_status_success ||
-      rocsolver_zgetrs(hnd, rocblas_operation_none, m, nrhs, reinterpret_cast<zc*>(A), m, ipiv,
-                       reinterpret_cast<zc*>(B), m) != rocblas_status_success) {
+  if (rocsolver_zgetrf_64(hnd, m, m, reinterpret_cast<zc*>(A), m, ipiv, info) != rocblas_status_success ||
+      rocsolver_zgetrs_64(hnd, rocblas_operation_none, m, nrhs, reinterpret_cast<zc*>(A), m, ipiv,
+                          reinterpret_cast<zc*>(B), m) != rocblas_status_success) {
     err = "rocSOLVER failed";
     return ABC_EDEVICE;
   }
-  rocblas_int hinfo = 0;
+  int64_t hinfo = 0;
   if (hipMemcpy(&hinfo, info, sizeof(hinfo), hipMemcpyDeviceToHost) != hipSuccess) {
     err = "hipMemcpy failed";
     return ABC_EDEVICE;
@@ -462,31 +463,44 @@ abc_status power_bound(rocblas_handle hnd, DevBufs& db, const double2* mat, int 
   if (st != ABC_OK) return st;
   if (!db.alloc(&u, (size_t)m)) { err = "hipMalloc failed"; return ABC_ENOMEM; }
   const zc one(1.0, 0.0), zero(0.0, 0.0);
-  double est = 0, nv = 0;
-  if (rocblas_dznrm2(hnd, m, reinterpret_cast<zc*>(v), 1, &nv) != rocblas_status_success) {
+  // the growth per iteration is averaged geometrically over the second half
+  // of the iterations: for a dominant complex pair the one-step ratio
+  // oscillates around the spectral radius, its geometric mean does not
+  constexpr int kIters = 120;
+  double est = 0, nv = 0, logsum = 0;
+  int nlog = 0;
+  if (rocblas_dznrm2_64(hnd, m, reinterpret_cast<zc*>(v), 1, &nv) != rocblas_status_success) {
     err = "rocBLAS failed";
     return ABC_EDEVICE;
   }
-  for (int it = 0; it < 60; ++it) {
+  for (int it = 0; it < kIters; ++it) {
     // the row-major block is the transpose of a column-major view with lda = ld
     double nu = 0;
-    if (rocblas_zgemv(hnd, rocblas_operation_transpose, m, m, &one, reinterpret_cast<const zc*>(mat), ld,
-                      reinterpret_cast<const zc*>(v), 1, &zero, reinterpret_cast<zc*>(u), 1) !=
+    if (rocblas_zgemv_64(hnd, rocblas_operation_transpose, m, m, &one, reinterpret_cast<const zc*>(mat), ld,
+                         reinterpret_cast<const zc*>(v), 1, &zero, reinterpret_cast<zc*>(u), 1) !=
             rocblas_status_success ||
-        rocblas_dznrm2(hnd, m, reinterpret_cast<zc*>(u), 1, &nu) != rocblas_status_success) {
+        rocblas_dznrm2_64(hnd, m, reinterpret_cast<zc*>(u), 1, &nu) != rocblas_status_success) {
       err = "rocBLAS failed";
       return ABC_EDEVICE;
     }
-    est = nu / nv;
-    if (!(nu > 0)) break;
+    if (!(nu > 0)) {
+      est = 0;
+      nlog = 0;
+      break;
+    }
+    if (it >= kIters / 2) {
+      logsum += std::log(nu / nv);
+      ++nlog;
+    }
     const double sc = 1.0 / nu;
-    if (rocblas_zdscal(hnd, m, &sc, reinterpret_cast<zc*>(u), 1) != rocblas_status_success) {
+    if (rocblas_zdscal_64(hnd, m, &sc, reinterpret_cast<zc*>(u), 1) != rocblas_status_success) {
       err = "rocBLAS failed";
       return ABC_EDEVICE;
     }
     std::swap(u, v);
     nv = 1.0;
   }
+  if (nlog > 0) est = std::exp(logsum / nlog);
   *bound = 1.25 * est;
   return ABC_OK;
 }
@@ -505,9 +519,7 @@ abc_status build_box_ops(const abc_params& p, double2** mat_dev, double2** q_dev
   const double need = p.order == ABC_SECOND ? 36 * nn : (p.order == ABC_FIRST ? 7 * nn : 3 * nn);
   size_t free_b = 0, total_b = 0;
   if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) { err = "hipMemGetInfo failed"; return ABC_EDEVICE; }
-  // library calls take 32-bit sizes: keep every dense matrix below 2^31 entries
-  const double biggest = p.order == ABC_SECOND ? 16.0 * n * n : (double)box_mat_elems(p.order, n);
-  if (need > 0.9 * (double)free_b || biggest >= 2147483647.0) {
+  if (need > 0.9 * (double)free_b) {
     err = "box form too large for this box and device (about " + std::to_string((long long)(need / 1e9)) +
           " GB of setup buffers); use the face form";
     return ABC_ENOMEM;
@@ -590,7 +602,7 @@ abc_status build_box_ops(const abc_params& p, double2** mat_dev, double2** q_dev
       }
       if (st == ABC_OK) {
         const zc alpha(-1.0, 0.0), beta(p.s1, 0.0);
-        if (rocblas_zgemm(hnd, rocblas_operation_transpose, rocblas_operation_none, n, n, n, &alpha,
+        if (rocblas_zgemm_64(hnd, rocblas_operation_transpose, rocblas_operation_none, n, n, n, &alpha,
                           reinterpret_cast<const zc*>(K2), n, reinterpret_cast<const zc*>(K1), n, &beta,
                           reinterpret_cast<zc*>(Acm), n) != rocblas_status_success) {
           err = "device GEMM for A failed";
@@ -653,9 +665,9 @@ abc_status build_box_ops(const abc_params& p, double2** mat_dev, double2** q_dev
     if (st == ABC_OK) {
       const zc one(1.0, 0.0);
       // W (column-major, = Y_3 = A0^T) += Y_2 Y_0 = A1^T B1^T
-      if (rocblas_zgemm(hnd, rocblas_operation_none, rocblas_operation_none, n, n, n, &one,
-                        reinterpret_cast<const zc*>(XT + 2LL * n), (int)m, reinterpret_cast<const zc*>(XT), (int)m,
-                        &one, reinterpret_cast<zc*>(W), n) != rocblas_status_success) {
+      if (rocblas_zgemm_64(hnd, rocblas_operation_none, rocblas_operation_none, n, n, n, &one,
+                           reinterpret_cast<const zc*>(XT + 2LL * n), m, reinterpret_cast<const zc*>(XT), m, &one,
+                           reinterpret_cast<zc*>(W), n) != rocblas_status_success) {
         err = "device GEMM for B1 A1 + A0 failed";
         st = ABC_EDEVICE;
       }
