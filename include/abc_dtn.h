@@ -85,7 +85,8 @@ typedef enum {
   ABC_ENOMEM = -2,     /* device or host allocation failed                 */
   ABC_EDEVICE = -3,    /* a HIP runtime or library call failed             */
   ABC_EUNSTABLE = -4,  /* stability self-check at setup failed             */
-  ABC_ENOTSUP = -5     /* combination not implemented                      */
+  ABC_ENOTSUP = -5,    /* combination not implemented                      */
+  ABC_EIO = -6         /* a checkpoint file could not be read or written   */
 } abc_status;
 
 enum { ABC_DIRICHLET = 0, ABC_PERIODIC = 1, ABC_ZEROTH = 2, ABC_FIRST = 3, ABC_SECOND = 4 };
@@ -302,6 +303,22 @@ size_t abc_device_bytes(const abc_ctx* ctx);
 
 /* Message of the last failed call on this thread ("" if none). */
 const char* abc_last_error(void);
+
+/* Checkpoint and resume.  abc_state_save writes the state (psi, and aux
+ * unless the context has none) of ctx's box to the file `path`: a 128-byte
+ * header (magic "ABCSTATE", format version, nx, ny, nz, radius, order, form,
+ * dtype, batch, window, fejer, h, dt, s0, s1, s2, the caller's step
+ * counter, the byte counts of psi and aux, in native byte order), then psi
+ * and aux as stored on the device.  psi and
+ * aux are device buffers; the call waits for the stream, copies through host
+ * memory and allocates a host buffer of their size.  abc_state_load reads
+ * such a file into psi and aux for a context with the same box and
+ * parameters (ABC_EINVAL otherwise, naming the first mismatch) and returns
+ * the stored step counter in *step (may be NULL).  ABC_EIO if the file cannot
+ * be opened, read or written. */
+abc_status abc_state_save(abc_ctx* ctx, const void* psi, const void* aux, long long step, const char* path,
+                          void* stream);
+abc_status abc_state_load(abc_ctx* ctx, void* psi, void* aux, long long* step, const char* path, void* stream);
 
 /* Release everything the context owns (NULL is ignored). */
 void abc_destroy(abc_ctx* ctx);

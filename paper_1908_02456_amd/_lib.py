@@ -8,9 +8,9 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libabc_dtn.so")
 
-ABC_OK, ABC_EINVAL, ABC_ENOMEM, ABC_EDEVICE, ABC_EUNSTABLE, ABC_ENOTSUP = 0, -1, -2, -3, -4, -5
+ABC_OK, ABC_EINVAL, ABC_ENOMEM, ABC_EDEVICE, ABC_EUNSTABLE, ABC_ENOTSUP, ABC_EIO = 0, -1, -2, -3, -4, -5, -6
 STATUS_NAMES = {0: "ABC_OK", -1: "ABC_EINVAL", -2: "ABC_ENOMEM", -3: "ABC_EDEVICE",
-                -4: "ABC_EUNSTABLE", -5: "ABC_ENOTSUP"}
+                -4: "ABC_EUNSTABLE", -5: "ABC_ENOTSUP", -6: "ABC_EIO"}
 ABC_BATCH_GRAPH = 1
 ORDERS = {"dirichlet": 0, "periodic": 1, "zeroth": 2, "first": 3, "second": 4}
 FORMS = {"box": 0, "faces": 1}
@@ -23,7 +23,7 @@ EXPORTED = ["abc_params_default", "abc_setup", "abc_step", "abc_diagnostics", "a
             "abc_step_timed", "abc_launch_label", "abc_adjoint", "abc_tune", "abc_setup_batch",
             "abc_step_batch", "abc_tune_batch", "abc_batch_aux_elems", "abc_batch_launch_groups",
             "abc_batch_tile_depth", "abc_destroy_batch", "abc_h2_objective",
-            "abc_effective_potential", "abc_potential_iterations"]
+            "abc_effective_potential", "abc_potential_iterations", "abc_state_save", "abc_state_load"]
 
 
 class AbcParams(ctypes.Structure):
@@ -97,6 +97,10 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.abc_effective_potential.restype = ctypes.c_int
     lib.abc_potential_iterations.argtypes = [vp, ctypes.POINTER(ctypes.c_longlong)]
     lib.abc_potential_iterations.restype = ctypes.c_int
+    lib.abc_state_save.argtypes = [vp, vp, vp, ctypes.c_longlong, ctypes.c_char_p, vp]
+    lib.abc_state_save.restype = ctypes.c_int
+    lib.abc_state_load.argtypes = [vp, vp, vp, ctypes.POINTER(ctypes.c_longlong), ctypes.c_char_p, vp]
+    lib.abc_state_load.restype = ctypes.c_int
     lib.abc_diagnostics.argtypes = [vp, vp, vp, vp, vp, vp]
     lib.abc_diagnostics.restype = ctypes.c_int
     lib.abc_aux_elems.argtypes = [vp]

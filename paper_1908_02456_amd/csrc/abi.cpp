@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdint>
+#include <cstdio>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -539,6 +541,94 @@ abc_status abc_effective_potential(abc_ctx* c, const void* psi, const void* V, v
   const hipError_t e = skyrme_veff(c->pot, psi, false, c->p.batch, c->p.dtype == ABC_C64, V, out, c->p.t0, c->p.t3,
                                    static_cast<hipStream_t>(stream), nullptr);
   if (e != hipSuccess) return fail(ABC_EDEVICE, std::string("effective potential: ") + hipGetErrorString(e));
+  return ABC_OK;
+}
+
+namespace {
+
+// checkpoint header: 128 bytes, native (little-endian) layout
+struct StateHeader {
+  char magic[8];
+  int32_t version;
+  int32_t nx, ny, nz, radius, order, form, dtype, batch, window, fejer, reserved0;
+  double h, dt, s0, s1, s2;
+  int64_t step;
+  int64_t psi_bytes, aux_bytes;
+  char pad[8];
+};
+static_assert(sizeof(StateHeader) == 128, "checkpoint header size");
+
+StateHeader make_header(const abc_params& p, long long step, int64_t psi_bytes, int64_t aux_bytes) {
+  StateHeader hd{};
+  std::memcpy(hd.magic, "ABCSTATE", 8);
+  hd.version = 1;
+  hd.nx = p.nx; hd.ny = p.ny; hd.nz = p.nz; hd.radius = p.radius; hd.order = p.order; hd.form = p.form;
+  hd.dtype = p.dtype; hd.batch = p.batch; hd.window = p.window; hd.fejer = p.fejer;
+  hd.h = p.h; hd.dt = p.dt; hd.s0 = p.s0; hd.s1 = p.s1; hd.s2 = p.s2;
+  hd.step = step;
+  hd.psi_bytes = psi_bytes;
+  hd.aux_bytes = aux_bytes;
+  return hd;
+}
+
+int64_t psi_bytes_of(const abc_ctx* c) {
+  return (int64_t)c->p.nx * c->p.ny * c->p.nz * c->p.batch * (c->p.dtype == ABC_C64 ? 8 : 16);
+}
+
+}  // namespace
+
+abc_status abc_state_save(abc_ctx* c, const void* psi, const void* aux, long long step, const char* path,
+                          void* stream) {
+  if (!c || !psi || !path) return fail(ABC_EINVAL, "null argument");
+  if (c->aux_elems && !aux) return fail(ABC_EINVAL, "this context's state includes the aux buffer");
+  const int64_t pb = psi_bytes_of(c), ab = (int64_t)c->aux_elems * 16;
+  std::vector<char> buf((size_t)(pb + ab));
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (hipStreamSynchronize(st) != hipSuccess || hipMemcpy(buf.data(), psi, pb, hipMemcpyDeviceToHost) != hipSuccess ||
+      (ab && hipMemcpy(buf.data() + pb, aux, ab, hipMemcpyDeviceToHost) != hipSuccess))
+    return fail(ABC_EDEVICE, "checkpoint: device copy failed");
+  const StateHeader hd = make_header(c->p, step, pb, ab);
+  FILE* fp = std::fopen(path, "wb");
+  if (!fp) return fail(ABC_EIO, std::string("checkpoint: cannot open ") + path);
+  const bool ok = std::fwrite(&hd, sizeof(hd), 1, fp) == 1 && std::fwrite(buf.data(), 1, buf.size(), fp) == buf.size();
+  if (std::fclose(fp) != 0 || !ok) return fail(ABC_EIO, std::string("checkpoint: cannot write ") + path);
+  return ABC_OK;
+}
+
+abc_status abc_state_load(abc_ctx* c, void* psi, void* aux, long long* step, const char* path, void* stream) {
+  if (!c || !psi || !path) return fail(ABC_EINVAL, "null argument");
+  if (c->aux_elems && !aux) return fail(ABC_EINVAL, "this context's state includes the aux buffer");
+  FILE* fp = std::fopen(path, "rb");
+  if (!fp) return fail(ABC_EIO, std::string("checkpoint: cannot open ") + path);
+  StateHeader hd{};
+  if (std::fread(&hd, sizeof(hd), 1, fp) != 1) {
+    std::fclose(fp);
+    return fail(ABC_EIO, "checkpoint: short header");
+  }
+  const StateHeader want = make_header(c->p, 0, psi_bytes_of(c), (int64_t)c->aux_elems * 16);
+  const char* bad = nullptr;
+  if (std::memcmp(hd.magic, want.magic, 8) != 0 || hd.version != want.version) bad = "not a checkpoint of this format";
+  else if (hd.nx != want.nx || hd.ny != want.ny || hd.nz != want.nz) bad = "box size";
+  else if (hd.radius != want.radius || hd.order != want.order || hd.form != want.form) bad = "radius, order or form";
+  else if (hd.dtype != want.dtype || hd.batch != want.batch) bad = "dtype or batch";
+  else if (hd.window != want.window || hd.fejer != want.fejer) bad = "face window";
+  else if (hd.h != want.h || hd.dt != want.dt) bad = "h or dt";
+  else if (hd.s0 != want.s0 || hd.s1 != want.s1 || hd.s2 != want.s2) bad = "interpolation points";
+  else if (hd.psi_bytes != want.psi_bytes || hd.aux_bytes != want.aux_bytes) bad = "state sizes";
+  if (bad) {
+    std::fclose(fp);
+    return fail(ABC_EINVAL, std::string("checkpoint does not match the context: ") + bad);
+  }
+  std::vector<char> buf((size_t)(hd.psi_bytes + hd.aux_bytes));
+  const bool ok = std::fread(buf.data(), 1, buf.size(), fp) == buf.size();
+  std::fclose(fp);
+  if (!ok) return fail(ABC_EIO, "checkpoint: short data");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (hipStreamSynchronize(st) != hipSuccess ||
+      hipMemcpy(psi, buf.data(), hd.psi_bytes, hipMemcpyHostToDevice) != hipSuccess ||
+      (hd.aux_bytes && hipMemcpy(aux, buf.data() + hd.psi_bytes, hd.aux_bytes, hipMemcpyHostToDevice) != hipSuccess))
+    return fail(ABC_EDEVICE, "checkpoint: device copy failed");
+  if (step) *step = hd.step;
   return ABC_OK;
 }
 

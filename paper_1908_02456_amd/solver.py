@@ -216,6 +216,22 @@ class Solver:
         _lib.check(self._lib.abc_potential_iterations(self._ctx, buf))
         return tuple(int(v) for v in buf)
 
+    def save_state(self, path: str, psi, aux=None, step: int = 0, stream=None):
+        """Checkpoint (psi, aux) and a step counter to a file (abc_state_save)."""
+        self._check_psi(psi)
+        ap = self._check_aux(aux) if self.aux_elems else None
+        _lib.check(self._lib.abc_state_save(self._ctx, psi.data_ptr(), ap, int(step), str(path).encode(),
+                                            _stream_handle(stream)))
+
+    def load_state(self, path: str, psi, aux=None, stream=None) -> int:
+        """Restore (psi, aux) from a checkpoint of a matching context; returns its step."""
+        self._check_psi(psi)
+        ap = self._check_aux(aux) if self.aux_elems else None
+        step = ctypes.c_longlong(0)
+        _lib.check(self._lib.abc_state_load(self._ctx, psi.data_ptr(), ap, ctypes.byref(step), str(path).encode(),
+                                            _stream_handle(stream)))
+        return int(step.value)
+
     def export(self, which: int, count: int) -> np.ndarray:
         buf = np.zeros(count, dtype=np.complex128)
         _lib.check(self._lib.abc_export(self._ctx, which, buf.ctypes.data, count))

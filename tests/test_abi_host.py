@@ -172,6 +172,8 @@ def test_h2_objective_rejects_invalid_arguments_without_a_device(lib):
 def test_null_arguments_are_rejected_without_a_device(lib):
     vp = ctypes.c_void_p
     assert lib.abc_effective_potential(None, None, None, None, None) == _lib.ABC_EINVAL
+    assert lib.abc_state_save(None, None, None, 0, b"/tmp/x", None) == _lib.ABC_EINVAL
+    assert lib.abc_state_load(None, None, None, None, b"/tmp/x", None) == _lib.ABC_EINVAL
     assert lib.abc_potential_iterations(None, None) == _lib.ABC_EINVAL
     assert lib.abc_setup(None, None) == _lib.ABC_EINVAL
     assert lib.abc_step(None, None, None, None, 1, None) == _lib.ABC_EINVAL
