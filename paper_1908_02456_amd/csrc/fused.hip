@@ -136,9 +136,22 @@ __device__ __forceinline__ void fused2_body(const typename cpx<T>::t* __restrict
   constexpr int ROWS = TY + 2 * H;
   constexpr int NT = 64 * ROWS;
   constexpr int ITERS = TZ + 2 * H;
-  // rows published for the y/x neighbours; double-buffered (one barrier per
-  // plane) where LDS allows, i.e. without the first-order face staging
-  constexpr int DBN = ORDER == 3 ? 1 : 2;
+  // First order: the z-face plane's data in registers (ZREG) or staged in
+  // LDS.  Registers cost 8 per lane when the base is the stage-1 source (half
+  // A) and 16 with a separate base, which in FP64 spills; so half A keeps
+  // them in registers and half B in LDS.
+  constexpr bool ZREG = SAME_BASE;
+  constexpr bool FO = ORDER == 3;
+  constexpr int FP = TZ + 2, FR = ROWS - 2;
+  constexpr int NXG = FO ? 2 * FP * FR : 1, NXF = FO ? 2 * TZ * TY : 1;
+  constexpr int NYG = FO ? FP * kCols : 1, NYV = FO ? TZ * kCols : 1;
+  constexpr int NZG = FO && !ZREG ? FR * kCols : 1, NZV = FO && !ZREG ? TY * kCols : 1;
+  constexpr int NVX = FO ? 2 * TY * 2 : 1;
+  // rows published for the y/x neighbours, double-buffered (one barrier per
+  // plane) when both buffers fit in the 160 KiB of LDS beside the face data
+  constexpr int kPlaneBytes = 2 * ROWS * 2 * 66 * (int)sizeof(C);
+  constexpr int kFaceBytes = 16 * (NXG + NXF + NYG + 2 * NYV + NZG + 2 * NZV + NVX);
+  constexpr int DBN = 2 * kPlaneBytes + kFaceBytes <= 160 * 1024 ? 2 : 1;
   __shared__ C planes[DBN][2][ROWS][2][66];
 
   const int lane = threadIdx.x & 63;
@@ -204,21 +217,22 @@ __device__ __forceinline__ void fused2_body(const typename cpx<T>::t* __restrict
   //    v = f0 + cA (b g + a w) and the output base Q = f0 + cB b v, computed
   //    here from w in global memory, so that the sweep only adds g or v and
   //    writes Q + cB a s1.
+  // With ZREG the z-face plane stays in registers instead: each row wave
+  // holds g of its own row there and forms v and Q in the sweep, which
+  // leaves LDS for double-buffered planes.
   // Every thread issues all of its loads before using any, so the staging
   // costs one memory round trip, overlapped with the first plane fetch.
-  constexpr int FP = TZ + 2, FR = ROWS - 2;
-  constexpr bool FO = ORDER == 3;
-  constexpr int NXG = FO ? 2 * FP * FR : 1, NXF = FO ? 2 * TZ * TY : 1;
-  constexpr int NYG = FO ? FP * kCols : 1, NYV = FO ? TZ * kCols : 1;
-  constexpr int NZG = FO ? FR * kCols : 1, NZV = FO ? TY * kCols : 1;
   __shared__ double2 fxg[NXG];  // [side][plane][row]
   __shared__ double2 fxf[NXF];  // [side][own plane][own row]
   __shared__ double2 fyg[NYG];  // [plane][local column]
   __shared__ double2 fyv[NYV], fyq[NYV];  // [own plane][local column]
   __shared__ double2 fzg[NZG];  // [row][local column]
   __shared__ double2 fzv[NZV], fzq[NZV];  // [own row][local column]
+  // z face: g and f0 of this wave's row at the face plane, per column
+  double2 gz[2] = {make_double2(0, 0), make_double2(0, 0)};
+  double2 f0z[2] = {make_double2(0, 0), make_double2(0, 0)};
   // x-face auxiliary stages v of the next two planes, [plane & 1][own row][side]
-  __shared__ double2 vx[FO ? 2 * TY * 2 : 1];
+  __shared__ double2 vx[NVX];
   int yface = -1, zface = -1;  // face index (2/3, 4/5) of the staged row / plane
   // face slab offsets as scalars (a per-lane index into the argument array
   // would make the compiler loop over the distinct indices)
@@ -239,6 +253,18 @@ __device__ __forceinline__ void fused2_body(const typename cpx<T>::t* __restrict
     double2 rx[KX], ryg[KYG], rzg[KZG];
     double2 ryv[KYV][2], rzv[KZV][2];  // (g, f0) of the own planes / rows
     C ryw[KYV], rzw[KZV];               // w there
+    // z face in registers: g on the stage-1 rows (1 .. ROWS-2), f0 on the
+    // own rows; with a shared base f0 is g itself
+    if (ZREG && zface >= 0 && row_in && r >= 1 && r < ROWS - 1) {
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        const int xx = xb + 2 * lane + c;
+        if (xx >= 0 && xx < nx) {
+          gz[c] = av[off_z + ybase + xx];
+          if (!SAME_BASE && own_row) f0z[c] = fb[off_z + ybase + xx];
+        }
+      }
+    }
 #pragma unroll
     for (int j = 0; j < KX; ++j) {
       const int i = threadIdx.x + j * NT;
@@ -281,7 +307,8 @@ __device__ __forceinline__ void fused2_body(const typename cpx<T>::t* __restrict
       const int lx = i % kCols, rr = i / kCols;
       const int xx = xb + lx, yy = ylo + rr;
       rzg[j] = make_double2(0, 0);
-      if (zface >= 0 && i < NZG && xx >= 0 && xx < nx && yy >= 0 && yy < ny) rzg[j] = av[off_z + yy * nx + xx];
+      if (!ZREG && zface >= 0 && i < NZG && xx >= 0 && xx < nx && yy >= 0 && yy < ny)
+        rzg[j] = av[off_z + yy * nx + xx];
     }
 #pragma unroll
     for (int j = 0; j < KZV; ++j) {
@@ -290,7 +317,7 @@ __device__ __forceinline__ void fused2_body(const typename cpx<T>::t* __restrict
       const int xx = xb + lx, yy = y0 + jj;
       rzv[j][0] = rzv[j][1] = make_double2(0, 0);
       rzw[j] = czero<C>();
-      if (zface >= 0 && i < NZV && xx >= 0 && xx < nx && yy < ny) {
+      if (!ZREG && zface >= 0 && i < NZV && xx >= 0 && xx < nx && yy < ny) {
         rzv[j][0] = av[off_z + yy * nx + xx];
         rzv[j][1] = fb[off_z + yy * nx + xx];
         rzw[j] = w_in[zpl * sz + yy * nx + xx];
@@ -320,15 +347,17 @@ __device__ __forceinline__ void fused2_body(const typename cpx<T>::t* __restrict
       const int i = threadIdx.x + j * NT;
       if (i < NYV) vq(ryv[j][0], ryv[j][1], ryw[j], &fyv[i], &fyq[i]);
     }
+    if constexpr (!ZREG) {
 #pragma unroll
-    for (int j = 0; j < KZG; ++j) {
-      const int i = threadIdx.x + j * NT;
-      if (i < NZG) fzg[i] = rzg[j];
-    }
+      for (int j = 0; j < KZG; ++j) {
+        const int i = threadIdx.x + j * NT;
+        if (i < NZG) fzg[i] = rzg[j];
+      }
 #pragma unroll
-    for (int j = 0; j < KZV; ++j) {
-      const int i = threadIdx.x + j * NT;
-      if (i < NZV) vq(rzv[j][0], rzv[j][1], rzw[j], &fzv[i], &fzq[i]);
+      for (int j = 0; j < KZV; ++j) {
+        const int i = threadIdx.x + j * NT;
+        if (i < NZV) vq(rzv[j][0], rzv[j][1], rzw[j], &fzv[i], &fzq[i]);
+      }
     }
   }
   __syncthreads();
@@ -476,13 +505,31 @@ __device__ __forceinline__ void fused2_body(const typename cpx<T>::t* __restrict
                 aux_out[off_y + zk * nx + x] = make_double2(q.x + as1.x, q.y + as1.y);
               }
             }
-            if (fz) {
+            if (fz && !ZREG) {
               const double2 g = k == 1 ? fzg[rr * kCols + lx] : fzv[(r - H) * kCols + lx];
               sr += g.x;
               si += g.y;
               if (own) {
                 const double2 q = fzq[(r - H) * kCols + lx];
                 aux_out[off_z + y * nx + x] = make_double2(q.x + as1.x, q.y + as1.y);
+              }
+            }
+            if (fz && ZREG) {
+              if (k == 1) {
+                sr += gz[c].x;
+                si += gz[c].y;
+              } else {
+                // v = f0 + cA (b g + a w) with w at this plane, Q = f0 + cB b v
+                const double2 f0 = SAME_BASE ? gz[c] : f0z[c];
+                const double2 bg = cmul(a.b0, gz[c]);
+                const double2 aw = cmul(a.a0, make_double2((double)wm2[c].x, (double)wm2[c].y));
+                const double2 v = make_double2(f0.x + cA * (bg.x + aw.x), f0.y + cA * (bg.y + aw.y));
+                sr += v.x;
+                si += v.y;
+                if (own) {
+                  const double2 bv = cmul(a.b0, v);
+                  aux_out[off_z + y * nx + x] = make_double2(f0.x + cB * bv.x + as1.x, f0.y + cB * bv.y + as1.y);
+                }
               }
             }
             o[c].x += T(cf2 * si);
