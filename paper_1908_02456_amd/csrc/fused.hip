@@ -136,26 +136,25 @@ __device__ __forceinline__ void fused2_body(const typename cpx<T>::t* __restrict
   constexpr int ROWS = TY + 2 * H;
   constexpr int NT = 64 * ROWS;
   constexpr int ITERS = TZ + 2 * H;
-  // First order: the z-face plane's data in registers (ZREG) or staged in
-  // LDS.  Registers cost 8 per lane when the base is the stage-1 source (half
-  // A) and 16 with a separate base, which in FP64 spills; so half A keeps
-  // them in registers and half B in LDS.
-  constexpr bool ZREG = SAME_BASE;
   constexpr bool FO = ORDER == 3;
   constexpr int FP = TZ + 2, FR = ROWS - 2;
+  // first-order face data in LDS (sizes in double2; 1 = unused)
   constexpr int NXG = FO ? 2 * FP * FR : 1, NXF = FO ? 2 * TZ * TY : 1;
-  constexpr int NYG = FO ? FP * kCols : 1, NYV = FO ? TZ * kCols : 1;
-  constexpr int NZG = FO && !ZREG ? FR * kCols : 1, NZV = FO && !ZREG ? TY * kCols : 1;
-  constexpr int NVX = FO ? 2 * TY * 2 : 1;
-  // rows published for the y/x neighbours, double-buffered (one barrier per
-  // plane) when both buffers fit in the 160 KiB of LDS beside the face data
-  constexpr int kPlaneBytes = 2 * ROWS * 2 * 66 * (int)sizeof(C);
-  constexpr int kFaceBytes = 16 * (NXG + NXF + NYG + 2 * NYV + NZG + 2 * NZV + NVX);
+  constexpr int NYG = FO ? FP * kCols : 1, NYF = FO && !SAME_BASE ? TZ * kCols : 1;
+  constexpr int NZF = FO && !SAME_BASE ? TY * kCols : 1;
+  constexpr int NVX = FO ? 2 * TY * 2 : 1, NVY = FO ? 2 * kCols : 1;
+  // Rows published for the y/x neighbours: the stage-1 inputs w of every row
+  // and the stage-1 outputs s1 of rows 1 .. ROWS-2 (the only rows stage 2
+  // reads).  Double-buffered (one barrier per plane) when both buffers fit in
+  // the 160 KiB of LDS beside the face data.
+  constexpr int kPlaneBytes = (2 * ROWS - 2) * 2 * 66 * (int)sizeof(C);
+  constexpr int kFaceBytes = 16 * (NXG + NXF + NYG + NYF + NZF + NVX + NVY);
   constexpr int DBN = 2 * kPlaneBytes + kFaceBytes <= 160 * 1024 ? 2 : 1;
-  __shared__ C planes[DBN][2][ROWS][2][66];
+  __shared__ C plw[DBN][ROWS][2][66];
+  __shared__ C pls[DBN][ROWS - 2][2][66];
 
   const int lane = threadIdx.x & 63;
-  const int r = threadIdx.x >> 6;
+  const int r = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform row
   const int tx = tile % a.ntx, rest = tile / a.ntx;
   const int ty = rest % a.nty, tz = rest / a.nty;
   const int y0 = ty * TY, z0 = tz * TZ;
@@ -169,7 +168,8 @@ __device__ __forceinline__ void fused2_body(const typename cpx<T>::t* __restrict
   const int xo = tx * a.xw, xe = min(xo + a.xw, nx);
   const int xb = a.ntx == 1 ? 0 : xo - H;
 
-  for (int i = threadIdx.x; i < DBN * 2 * ROWS * 2 * 66; i += NT) (&planes[0][0][0][0][0])[i] = czero<C>();
+  for (int i = threadIdx.x; i < DBN * ROWS * 2 * 66; i += NT) (&plw[0][0][0][0])[i] = czero<C>();
+  for (int i = threadIdx.x; i < DBN * (ROWS - 2) * 2 * 66; i += NT) (&pls[0][0][0][0])[i] = czero<C>();
 
   C Yc[2][2], Yb[2][2];  // stage inputs: centre / below (j = 0: w, j = 1: stage-1 output)
   C Bd[2][2];            // base at planes zi-1, zi-2 (separate base only)
@@ -207,33 +207,35 @@ __device__ __forceinline__ void fused2_body(const typename cpx<T>::t* __restrict
 #pragma unroll
   for (int q = 0; q < PF; ++q) fetch(z0 - H + q, q);
 
-  // First order: the tile's face data staged in LDS once, before the sweep.
-  //  * x faces (both sides): the auxiliary input g = av over the stage-1
-  //    planes z0-1 .. z0+TZ and rows 1 .. ROWS-2, and the base f0 = fb over
-  //    the own planes and rows (the halo wave forms v and the outputs).
-  //  * the tile's y-face row and z-face plane, if it has them (at most one of
-  //    each when ny >= TY + 2 and nz >= TZ + 2): g over the stage-1
-  //    planes/rows, and over the own planes/rows the stage-2 source
-  //    v = f0 + cA (b g + a w) and the output base Q = f0 + cB b v, computed
-  //    here from w in global memory, so that the sweep only adds g or v and
-  //    writes Q + cB a s1.
-  // With ZREG the z-face plane stays in registers instead: each row wave
-  // holds g of its own row there and forms v and Q in the sweep, which
-  // leaves LDS for double-buffered planes.
-  // Every thread issues all of its loads before using any, so the staging
-  // costs one memory round trip, overlapped with the first plane fetch.
+  // First order: the tile's face data, read once before the sweep.
+  //  * x faces (both sides), in LDS: the auxiliary input g = av over the
+  //    stage-1 planes z0-1 .. z0+TZ and rows 1 .. ROWS-2, and the base
+  //    f0 = fb over the own planes and rows (the halo waves form v and the
+  //    outputs).
+  //  * the tile's z-face plane, if it has one (at most one when
+  //    nz >= TZ + 2): each row wave holds g of its own row there in
+  //    registers; f0 over the own rows is staged in LDS when the base is a
+  //    separate buffer (half B) and is g itself otherwise.
+  //  * the tile's y-face row, if it has one (at most one when
+  //    ny >= TY + 2), in LDS: g over the stage-1 planes and, with a separate
+  //    base, f0 over the own planes.  The halo waves form its stage-2 source
+  //    and auxiliary outputs during the sweep, as for the x faces.
+  // The stage-2 source is v = f0 + cA (b g + a w) and the auxiliary output
+  // f0 + cB (b v + a s1).  Every thread issues all of its loads before using
+  // any, so the staging costs one memory round trip, overlapped with the
+  // first plane fetch.
   __shared__ double2 fxg[NXG];  // [side][plane][row]
   __shared__ double2 fxf[NXF];  // [side][own plane][own row]
   __shared__ double2 fyg[NYG];  // [plane][local column]
-  __shared__ double2 fyv[NYV], fyq[NYV];  // [own plane][local column]
-  __shared__ double2 fzg[NZG];  // [row][local column]
-  __shared__ double2 fzv[NZV], fzq[NZV];  // [own row][local column]
-  // z face: g and f0 of this wave's row at the face plane, per column
+  __shared__ double2 fyf[NYF];  // [own plane][local column]
+  __shared__ double2 fzf[NZF];  // [own row][local column]
+  // z face: g of this wave's row at the face plane, per column
   double2 gz[2] = {make_double2(0, 0), make_double2(0, 0)};
-  double2 f0z[2] = {make_double2(0, 0), make_double2(0, 0)};
-  // x-face auxiliary stages v of the next two planes, [plane & 1][own row][side]
+  // auxiliary stages v of the next two planes: x faces [plane & 1][own row]
+  // [side], y-face row [plane & 1][local column]
   __shared__ double2 vx[NVX];
-  int yface = -1, zface = -1;  // face index (2/3, 4/5) of the staged row / plane
+  __shared__ double2 vy[NVY];
+  int yface = -1, zface = -1;  // face index (2/3, 4/5) of the tile's y row / z plane
   // face slab offsets as scalars (a per-lane index into the argument array
   // would make the compiler loop over the distinct indices)
   const int off_x0 = a.face_off[0], off_x1 = a.face_off[1];
@@ -246,23 +248,15 @@ __device__ __forceinline__ void fused2_body(const typename cpx<T>::t* __restrict
     else if (zlo <= nz - 1 && nz - 1 < zlo + FP) zface = 5;
     off_y = yface == 3 ? a.face_off[3] : a.face_off[2];
     off_z = zface == 5 ? a.face_off[5] : a.face_off[4];
-    const int yrow = yface == 3 ? ny - 1 : 0, zpl = zface == 5 ? nz - 1 : 0;
     constexpr int NXA = NXG + NXF;
-    constexpr int KX = (NXA + NT - 1) / NT, KYG = (NYG + NT - 1) / NT, KYV = (NYV + NT - 1) / NT;
-    constexpr int KZG = (NZG + NT - 1) / NT, KZV = (NZV + NT - 1) / NT;
-    double2 rx[KX], ryg[KYG], rzg[KZG];
-    double2 ryv[KYV][2], rzv[KZV][2];  // (g, f0) of the own planes / rows
-    C ryw[KYV], rzw[KZV];               // w there
-    // z face in registers: g on the stage-1 rows (1 .. ROWS-2), f0 on the
-    // own rows; with a shared base f0 is g itself
-    if (ZREG && zface >= 0 && row_in && r >= 1 && r < ROWS - 1) {
+    constexpr int KX = (NXA + NT - 1) / NT, KYG = (NYG + NT - 1) / NT, KYF = (NYF + NT - 1) / NT;
+    constexpr int KZF = (NZF + NT - 1) / NT;
+    double2 rx[KX], ryg[KYG], ryf[KYF], rzf[KZF];
+    if (zface >= 0 && row_in && r >= 1 && r < ROWS - 1) {
 #pragma unroll
       for (int c = 0; c < 2; ++c) {
         const int xx = xb + 2 * lane + c;
-        if (xx >= 0 && xx < nx) {
-          gz[c] = av[off_z + ybase + xx];
-          if (!SAME_BASE && own_row) f0z[c] = fb[off_z + ybase + xx];
-        }
+        if (xx >= 0 && xx < nx) gz[c] = av[off_z + ybase + xx];
       }
     }
 #pragma unroll
@@ -289,48 +283,21 @@ __device__ __forceinline__ void fused2_body(const typename cpx<T>::t* __restrict
       if (yface >= 0 && i < NYG && xx >= 0 && xx < nx && zz >= 0 && zz < nz) ryg[j] = av[off_y + zz * nx + xx];
     }
 #pragma unroll
-    for (int j = 0; j < KYV; ++j) {
+    for (int j = 0; j < KYF; ++j) {
       const int i = threadIdx.x + j * NT;
       const int lx = i % kCols, pl = i / kCols;
       const int xx = xb + lx, zz = z0 + pl;
-      ryv[j][0] = ryv[j][1] = make_double2(0, 0);
-      ryw[j] = czero<C>();
-      if (yface >= 0 && i < NYV && xx >= 0 && xx < nx && zz < nz) {
-        ryv[j][0] = av[off_y + zz * nx + xx];
-        ryv[j][1] = fb[off_y + zz * nx + xx];
-        ryw[j] = w_in[zz * sz + yrow * nx + xx];
-      }
+      ryf[j] = make_double2(0, 0);
+      if (!SAME_BASE && yface >= 0 && i < NYF && xx >= 0 && xx < nx && zz < nz) ryf[j] = fb[off_y + zz * nx + xx];
     }
 #pragma unroll
-    for (int j = 0; j < KZG; ++j) {
-      const int i = threadIdx.x + j * NT;
-      const int lx = i % kCols, rr = i / kCols;
-      const int xx = xb + lx, yy = ylo + rr;
-      rzg[j] = make_double2(0, 0);
-      if (!ZREG && zface >= 0 && i < NZG && xx >= 0 && xx < nx && yy >= 0 && yy < ny)
-        rzg[j] = av[off_z + yy * nx + xx];
-    }
-#pragma unroll
-    for (int j = 0; j < KZV; ++j) {
+    for (int j = 0; j < KZF; ++j) {
       const int i = threadIdx.x + j * NT;
       const int lx = i % kCols, jj = i / kCols;
       const int xx = xb + lx, yy = y0 + jj;
-      rzv[j][0] = rzv[j][1] = make_double2(0, 0);
-      rzw[j] = czero<C>();
-      if (!ZREG && zface >= 0 && i < NZV && xx >= 0 && xx < nx && yy < ny) {
-        rzv[j][0] = av[off_z + yy * nx + xx];
-        rzv[j][1] = fb[off_z + yy * nx + xx];
-        rzw[j] = w_in[zpl * sz + yy * nx + xx];
-      }
+      rzf[j] = make_double2(0, 0);
+      if (!SAME_BASE && zface >= 0 && i < NZF && xx >= 0 && xx < nx && yy < ny) rzf[j] = fb[off_z + yy * nx + xx];
     }
-    // v = f0 + cA (b g + a w), Q = f0 + cB b v
-    auto vq = [&](const double2& g, const double2& f0, const C& wv, double2* v_out, double2* q_out) {
-      const double2 bg = cmul(a.b0, g), aw = cmul(a.a0, make_double2((double)wv.x, (double)wv.y));
-      const double2 v = make_double2(f0.x + cA * (bg.x + aw.x), f0.y + cA * (bg.y + aw.y));
-      const double2 bv = cmul(a.b0, v);
-      *v_out = v;
-      *q_out = make_double2(f0.x + cB * bv.x, f0.y + cB * bv.y);
-    };
 #pragma unroll
     for (int j = 0; j < KX; ++j) {
       const int i = threadIdx.x + j * NT;
@@ -342,35 +309,56 @@ __device__ __forceinline__ void fused2_body(const typename cpx<T>::t* __restrict
       const int i = threadIdx.x + j * NT;
       if (i < NYG) fyg[i] = ryg[j];
     }
+    if constexpr (!SAME_BASE) {
 #pragma unroll
-    for (int j = 0; j < KYV; ++j) {
-      const int i = threadIdx.x + j * NT;
-      if (i < NYV) vq(ryv[j][0], ryv[j][1], ryw[j], &fyv[i], &fyq[i]);
-    }
-    if constexpr (!ZREG) {
-#pragma unroll
-      for (int j = 0; j < KZG; ++j) {
+      for (int j = 0; j < KYF; ++j) {
         const int i = threadIdx.x + j * NT;
-        if (i < NZG) fzg[i] = rzg[j];
+        if (i < NYF) fyf[i] = ryf[j];
       }
 #pragma unroll
-      for (int j = 0; j < KZV; ++j) {
+      for (int j = 0; j < KZF; ++j) {
         const int i = threadIdx.x + j * NT;
-        if (i < NZV) vq(rzv[j][0], rzv[j][1], rzw[j], &fzv[i], &fzq[i]);
+        if (i < NZF) fzf[i] = rzf[j];
       }
     }
   }
   __syncthreads();
 
+  // the y-face row when it is one of the tile's own rows (stage 2 and the
+  // auxiliary outputs run there), as a tile row index; -1 otherwise
+  int ryown = -1;
+  if (FO && yface >= 0) {
+    const int yf = yface == 3 ? ny - 1 : 0;
+    if (yf >= y0 && yf < y0 + TY) ryown = yf - (y0 - H);
+  }
+
 #pragma unroll
   for (int it = 0; it < ITERS; ++it) {
     const int zi = z0 - H + it;
-    auto& plane = planes[DBN == 2 ? (it & 1) : 0];  // rows published by the previous iteration
+    // rows published by the previous iteration, and the buffers of the next
+    auto& pw = plw[DBN == 2 ? (it & 1) : 0];
+    auto& ps = pls[DBN == 2 ? (it & 1) : 0];
+    auto& pwn = plw[DBN == 2 ? ((it + 1) & 1) : 0];
+    auto& psn = pls[DBN == 2 ? ((it + 1) & 1) : 0];
+    C prev[2];
+    T vcur[2];
+    C bcur[2], wm2[2];  // base at plane zi; w at plane zi - 2 (before the slide)
+    const int q = it % PF;  // ring slot of plane zi (the loop is unrolled)
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      prev[c] = pf[q][c];
+      vcur[c] = pv[q][c];
+      bcur[c] = SAME_BASE ? pf[q][c] : pb[q][c];
+      wm2[c] = Yb[0][c];
+    }
+    if (it + PF < ITERS) fetch(zi + PF, q);
+    // The halo waves' face work below runs after their prefetch is issued,
+    // so that its latency overlaps the work.
     if (ORDER == 3 && (r == 0 || r == ROWS - 1) && lane < 2 * TY) {
       // First-order x faces, done by the two halo waves at the tile's edges
       // (idle in both stages), one lane per (own row, side).  They read the
-      // rows published at the end of the previous iteration: plane[0] holds w
-      // at plane zi-1 and plane[1] the stage-1 output s1 at plane zi-2.
+      // rows published at the end of the previous iteration: pw holds w at
+      // plane zi-1 and ps the stage-1 output s1 at plane zi-2.
       //  * top wave: v_f = fb_f + cA (b av_f + a w) at plane zi-1, for the
       //    next iteration's stage 2 (LDS ring);
       //  * bottom wave: the auxiliary output fb_f + cB (b v_f + a s1) at
@@ -385,32 +373,47 @@ __device__ __forceinline__ void fused2_body(const typename cpx<T>::t* __restrict
           const int pl = p1 - (z0 - 1);
           const double2 g = fxg[(side * FP + pl) * FR + rr];
           const double2 f0 = fxf[(side * TZ + (p1 - z0)) * TY + j];
-          const C wv = plane[0][rj][ci][li];
+          const C wv = pw[rj][ci][li];
           const double2 bg = cmul(a.b0, g), aw = cmul(a.a0, make_double2((double)wv.x, (double)wv.y));
-          vx[((p1 & 1) * TY + j) * 2 + side] = make_double2(f0.x + cA * (bg.x + aw.x), f0.y + cA * (bg.y + aw.y));
+          const double2 v = make_double2(f0.x + cA * (bg.x + aw.x), f0.y + cA * (bg.y + aw.y));
+          vx[((p1 & 1) * TY + j) * 2 + side] = v;
         }
         if (r == ROWS - 1 && p2 >= z0 && p2 < z0 + TZ && p2 < nz && xf >= xo && xf < xe) {
           const double2 f0 = fxf[(side * TZ + (p2 - z0)) * TY + j];
           const double2 v = vx[((p2 & 1) * TY + j) * 2 + side];
-          const C s1 = plane[1][rj][ci][li];
+          const C s1 = ps[rj - 1][ci][li];
           const double2 bv = cmul(a.b0, v), as1 = cmul(a.a0, make_double2((double)s1.x, (double)s1.y));
           aux_out[(side ? off_x1 : off_x0) + p2 * ny + yj] =
               make_double2(f0.x + cB * (bv.x + as1.x), f0.y + cB * (bv.y + as1.y));
         }
       }
     }
-    C prev[2];
-    T vcur[2];
-    C bcur[2], wm2[2];  // base at plane zi; w at plane zi - 2 (before the slide)
-    const int q = it % PF;  // ring slot of plane zi (the loop is unrolled)
+    if (ORDER == 3 && ryown >= 0 && (r == 0 || r == ROWS - 1)) {
+      // The y-face row, by the same two halo waves over its whole width: the
+      // top wave forms v = f0 + cA (b g + a w) at plane zi-1 into the ring;
+      // the bottom wave writes the auxiliary output f0 + cB (b v + a s1) at
+      // plane zi-2.
+      const int p = r == 0 ? zi - 1 : zi - 2;
+      if (p >= z0 && p < z0 + TZ && p < nz) {
 #pragma unroll
-    for (int c = 0; c < 2; ++c) {
-      prev[c] = pf[q][c];
-      vcur[c] = pv[q][c];
-      bcur[c] = SAME_BASE ? pf[q][c] : pb[q][c];
-      wm2[c] = Yb[0][c];
+        for (int c = 0; c < 2; ++c) {
+          const int lx = 2 * lane + c, x = xb + lx;
+          if (x < 0 || x >= nx) continue;
+          const double2 g = fyg[(p - z0 + 1) * kCols + lx];
+          const double2 f0 = SAME_BASE ? g : fyf[(p - z0) * kCols + lx];
+          if (r == 0) {
+            const C wv = pw[ryown][c][lane + 1];
+            const double2 bg = cmul(a.b0, g), aw = cmul(a.a0, make_double2((double)wv.x, (double)wv.y));
+            vy[(p & 1) * kCols + lx] = make_double2(f0.x + cA * (bg.x + aw.x), f0.y + cA * (bg.y + aw.y));
+          } else if (x >= xo && x < xe) {
+            const double2 v = vy[(p & 1) * kCols + lx];
+            const C s1 = ps[ryown - 1][c][lane + 1];
+            const double2 bv = cmul(a.b0, v), as1 = cmul(a.a0, make_double2((double)s1.x, (double)s1.y));
+            aux_out[off_y + p * nx + x] = make_double2(f0.x + cB * (bv.x + as1.x), f0.y + cB * (bv.y + as1.y));
+          }
+        }
+      }
     }
-    if (it + PF < ITERS) fetch(zi + PF, q);
     // First order: the x-face sources of this iteration's two stages, read
     // from LDS by the lanes holding a face column ahead of the stencil work,
     // so that their latency overlaps it.  Indices are clamped in range; they
@@ -443,10 +446,12 @@ __device__ __forceinline__ void fused2_body(const typename cpx<T>::t* __restrict
         o[c] = czero<C>();
         if (!active) continue;
         const C cen = Yc[k - 1][c], bel = Yb[k - 1][c], abv = prev[c];
-        const C ym = plane[k - 1][r - 1][c][lane + 1];
-        const C yp = plane[k - 1][r + 1][c][lane + 1];
-        const C xm = c == 0 ? plane[k - 1][r][1][lane] : Yc[k - 1][0];
-        const C xp = c == 0 ? Yc[k - 1][1] : plane[k - 1][r][0][lane + 2];
+        // stage k reads rows r-1 .. r+1 of w (k = 1) or of s1 (k = 2)
+        auto row = [&](int rr) -> C(&)[2][66] { return k == 1 ? pw[rr] : ps[rr - 1]; };
+        const C ym = row(r - 1)[c][lane + 1];
+        const C yp = row(r + 1)[c][lane + 1];
+        const C xm = c == 0 ? row(r)[1][lane] : Yc[k - 1][0];
+        const C xp = c == 0 ? Yc[k - 1][1] : row(r)[0][lane + 2];
         C b0;
         if (SAME_BASE) b0 = k == 1 ? Yc[0][c] : wm2[c];
         else b0 = Bd[k - 1][c];
@@ -470,7 +475,7 @@ __device__ __forceinline__ void fused2_body(const typename cpx<T>::t* __restrict
         // with g = the auxiliary input (stage 1) or the auxiliary stage
         // v_f = fb_f + cA (b av_f + a w) (stage 2), added to the plain stage
         // output as -i cf g.
-        const int pl = zk - (z0 - 1), rr = r - 1;
+        const int pl = zk - (z0 - 1);
         const double cf2 = k == 1 ? cA : cB;
         // x faces: at most one column per lane, its source read above
         if (cxf >= 0) {
@@ -496,41 +501,35 @@ __device__ __forceinline__ void fused2_body(const typename cpx<T>::t* __restrict
             double sr = 0, si = 0;
             double2 as1 = make_double2(0, 0);
             if (k == 2 && own) as1 = cmul(ba, make_double2((double)Yc[1][c].x, (double)Yc[1][c].y));
-            if (fy) {
-              const double2 g = k == 1 ? fyg[pl * kCols + lx] : fyv[(zk - z0) * kCols + lx];
-              sr += g.x;
-              si += g.y;
-              if (own) {
-                const double2 q = fyq[(zk - z0) * kCols + lx];
-                aux_out[off_y + zk * nx + x] = make_double2(q.x + as1.x, q.y + as1.y);
-              }
-            }
-            if (fz && !ZREG) {
-              const double2 g = k == 1 ? fzg[rr * kCols + lx] : fzv[(r - H) * kCols + lx];
-              sr += g.x;
-              si += g.y;
-              if (own) {
-                const double2 q = fzq[(r - H) * kCols + lx];
-                aux_out[off_z + y * nx + x] = make_double2(q.x + as1.x, q.y + as1.y);
-              }
-            }
-            if (fz && ZREG) {
+            // stage 1 adds g; stage 2 adds v = f0 + cA (b g + a w), w at this
+            // plane, and at owned points writes f0 + cB b v + cB a s1
+            const double2 wv = make_double2((double)wm2[c].x, (double)wm2[c].y);
+            auto face = [&](const double2 g, const double2 f0, int oidx) {
               if (k == 1) {
-                sr += gz[c].x;
-                si += gz[c].y;
-              } else {
-                // v = f0 + cA (b g + a w) with w at this plane, Q = f0 + cB b v
-                const double2 f0 = SAME_BASE ? gz[c] : f0z[c];
-                const double2 bg = cmul(a.b0, gz[c]);
-                const double2 aw = cmul(a.a0, make_double2((double)wm2[c].x, (double)wm2[c].y));
-                const double2 v = make_double2(f0.x + cA * (bg.x + aw.x), f0.y + cA * (bg.y + aw.y));
-                sr += v.x;
-                si += v.y;
-                if (own) {
-                  const double2 bv = cmul(a.b0, v);
-                  aux_out[off_z + y * nx + x] = make_double2(f0.x + cB * bv.x + as1.x, f0.y + cB * bv.y + as1.y);
-                }
+                sr += g.x;
+                si += g.y;
+                return;
               }
+              const double2 bg = cmul(a.b0, g), aw = cmul(a.a0, wv);
+              const double2 v = make_double2(f0.x + cA * (bg.x + aw.x), f0.y + cA * (bg.y + aw.y));
+              sr += v.x;
+              si += v.y;
+              if (own) {
+                const double2 bv = cmul(a.b0, v);
+                aux_out[oidx] = make_double2(f0.x + cB * bv.x + as1.x, f0.y + cB * bv.y + as1.y);
+              }
+            };
+            const double2 zero = make_double2(0, 0);
+            if (fy) {
+              // stage 1: g; stage 2: v from the halo wave's ring (the
+              // auxiliary outputs are written there too)
+              const double2 g = k == 1 ? fyg[pl * kCols + lx] : vy[(zk & 1) * kCols + lx];
+              sr += g.x;
+              si += g.y;
+            }
+            if (fz) {
+              const double2 f0 = SAME_BASE ? gz[c] : (k == 2 ? fzf[(r - H) * kCols + lx] : zero);
+              face(gz[c], f0, off_z + y * nx + x);
             }
             o[c].x += T(cf2 * si);
             o[c].y += T(-cf2 * sr);
@@ -559,12 +558,12 @@ __device__ __forceinline__ void fused2_body(const typename cpx<T>::t* __restrict
     }
     // publish this plane's stage inputs; with a single buffer every wave
     // must first be done reading the previous ones
-    auto& pnext = planes[DBN == 2 ? ((it + 1) & 1) : 0];
     if (DBN == 1) sync_lds();
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
-#pragma unroll
-      for (int c = 0; c < 2; ++c) pnext[j][r][c][lane + 1] = Yc[j][c];
+    for (int c = 0; c < 2; ++c) {
+      pwn[r][c][lane + 1] = Yc[0][c];
+      if (r >= 1 && r < ROWS - 1) psn[r - 1][c][lane + 1] = Yc[1][c];
+    }
     sync_lds();
   }
 }

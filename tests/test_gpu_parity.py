@@ -147,7 +147,8 @@ def test_zero_steps_and_minimum_box():
 @pytest.mark.parametrize("steps", [5, 6])
 def test_fused_path_parity(order, shape, steps):
     # several 8x8 (y, z) tiles with ragged tails (10 = one plane/row past a
-    # tile and a face row/plane in the halo); odd and even step counts
+    # tile and a face row/plane in the halo); odd and even step counts; rows
+    # of one x chunk (odd and even nx) and of several
     r = _run_pair("fused", shape, 0.25, 0.004, 1, order, steps, s0=1.5, s1=1.5, window=0, path="fused")
     assert r["solver"].use_fused
     assert r["err"] < TOL64, r["err"]
@@ -156,8 +157,11 @@ def test_fused_path_parity(order, shape, steps):
 
 
 @pytest.mark.parametrize("order", ["dirichlet", "first"])
-def test_fused_path_parity_fp32(order):
-    r = _run_pair("fused-c64", (19, 21, 45), 0.25, 0.004, 1, order, 7, s1=1.0, window=0, dtype="c64",
+@pytest.mark.parametrize("shape", [(19, 21, 45), (18, 20, 44)])
+def test_fused_path_parity_fp32(order, shape):
+    # odd and even row lengths (the x-face columns in the second or the
+    # first column of a lane)
+    r = _run_pair("fused-c64", shape, 0.25, 0.004, 1, order, 7, s1=1.0, window=0, dtype="c64",
                   path="fused")
     assert r["solver"].use_fused
     assert r["err"] < TOL32, r["err"]
