@@ -477,8 +477,19 @@ __device__ __forceinline__ void fused2_body(const typename cpx<T>::t* __restrict
         // output as -i cf g.
         const int pl = zk - (z0 - 1);
         const double cf2 = k == 1 ? cA : cB;
-        // x faces: at most one column per lane, its source read above
-        if (cxf >= 0) {
+        // x faces: at most one column per lane, its source read above.  In
+        // FP64 a branch per column costs fewer vector instructions than
+        // selecting between zero and the source for both columns; in FP32
+        // the selects are the cheaper form.
+        if constexpr (std::is_same<T, double>::value) {
+          if (cxf == 0) {
+            o[0].x += cf2 * gx[k - 1].y;
+            o[0].y += -cf2 * gx[k - 1].x;
+          } else if (cxf == 1) {
+            o[1].x += cf2 * gx[k - 1].y;
+            o[1].y += -cf2 * gx[k - 1].x;
+          }
+        } else if (cxf >= 0) {
           const double2 g = gx[k - 1];
           const T dx = T(cf2 * g.y), dy = T(-cf2 * g.x);
           o[0].x += cxf ? T(0) : dx;
