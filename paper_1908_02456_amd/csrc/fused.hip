@@ -415,23 +415,24 @@ __device__ __forceinline__ void fused2_body(const typename cpx<T>::t* __restrict
       }
     }
     // First order: the x-face sources of this iteration's two stages, read
-    // from LDS by the lanes holding a face column ahead of the stencil work,
-    // so that their latency overlaps it.  Indices are clamped in range; they
-    // do not bind in the active stages that use the values.  Stage 1: av at
-    // plane zi-1; stage 2: v at plane zi-2 from the halo wave's ring.
+    // from LDS ahead of the stencil work so that their latency overlaps it.
+    // Stage 1: av at plane zi-1; stage 2: v at plane zi-2 from the halo
+    // wave's ring.  Every lane reads (the indices are clamped in range, and
+    // do not bind in the active stages that use the values); only the lanes
+    // holding a face column use them.  A branch here, or around the adds
+    // below, splits the stage code into blocks that the compiler schedules
+    // apart, which costs more than the extra reads and selects.
     double2 gx[2] = {make_double2(0, 0), make_double2(0, 0)};
     int cxf = -1;
     if (ORDER == 3) {
       const int x0 = xb + 2 * lane;
       cxf = (x0 == 0 || x0 == nx - 1) ? 0 : ((x0 + 1 == nx - 1) ? 1 : -1);
-      if (cxf >= 0) {
-        const int side = x0 + cxf == 0 ? 0 : 1;
-        const int rrc = min(max(r - 1, 0), FR - 1);
-        const int plc = min(max(zi - z0, 0), FP - 1);
-        const int jc = min(max(r - H, 0), TY - 1);
-        gx[0] = fxg[(side * FP + plc) * FR + rrc];
-        gx[1] = vx[(((zi - 2) & 1) * TY + jc) * 2 + side];
-      }
+      const int side = x0 == 0 ? 0 : 1;
+      const int rrc = min(max(r - 1, 0), FR - 1);
+      const int plc = min(max(zi - z0, 0), FP - 1);
+      const int jc = min(max(r - H, 0), TY - 1);
+      gx[0] = fxg[(side * FP + plc) * FR + rrc];
+      gx[1] = vx[(((zi - 2) & 1) * TY + jc) * 2 + side];
     }
 #pragma unroll
     for (int k = 1; k <= 2; ++k) {
@@ -477,25 +478,23 @@ __device__ __forceinline__ void fused2_body(const typename cpx<T>::t* __restrict
         // output as -i cf g.
         const int pl = zk - (z0 - 1);
         const double cf2 = k == 1 ? cA : cB;
-        // x faces: at most one column per lane, its source read above.  In
-        // FP64 a branch per column costs fewer vector instructions than
-        // selecting between zero and the source for both columns; in FP32
-        // the selects are the cheaper form.
-        if constexpr (std::is_same<T, double>::value) {
-          if (cxf == 0) {
-            o[0].x += cf2 * gx[k - 1].y;
-            o[0].y += -cf2 * gx[k - 1].x;
-          } else if (cxf == 1) {
-            o[1].x += cf2 * gx[k - 1].y;
-            o[1].y += -cf2 * gx[k - 1].x;
-          }
-        } else if (cxf >= 0) {
+        // x faces: at most one column per lane, its source read above,
+        // added without a branch (zero for the other columns)
+        {
           const double2 g = gx[k - 1];
-          const T dx = T(cf2 * g.y), dy = T(-cf2 * g.x);
-          o[0].x += cxf ? T(0) : dx;
-          o[0].y += cxf ? T(0) : dy;
-          o[1].x += cxf ? dx : T(0);
-          o[1].y += cxf ? dy : T(0);
+          const bool c0 = cxf == 0, c1 = cxf == 1;
+          if constexpr (std::is_same<T, double>::value) {
+            o[0].x += cf2 * (c0 ? g.y : 0.0);
+            o[0].y += -cf2 * (c0 ? g.x : 0.0);
+            o[1].x += cf2 * (c1 ? g.y : 0.0);
+            o[1].y += -cf2 * (c1 ? g.x : 0.0);
+          } else {
+            const T dx = T(cf2 * g.y), dy = T(-cf2 * g.x);
+            o[0].x += c0 ? dx : T(0);
+            o[0].y += c0 ? dy : T(0);
+            o[1].x += c1 ? dx : T(0);
+            o[1].y += c1 ? dy : T(0);
+          }
         }
         // y and z faces: whole rows (wave-uniform), both columns of each lane,
         // sources precomputed at staging; stage 2 also writes the auxiliary
