@@ -156,6 +156,19 @@ def test_fused_path_parity(order, shape, steps):
         assert r["aux_err"] < TOL64, r["aux_err"]
 
 
+@pytest.mark.parametrize("shape,dtype", [((17, 12, 20), "c128"), ((9, 10, 14), "c128"), ((17, 12, 20), "c64")])
+def test_fused_first_order_face_plane_in_tile_halo(shape, dtype):
+    # nz = 8k + 9 (8-plane tiles) and 4k + 5 (4-plane tiles): the last z-face
+    # plane is a stage-1-only halo plane of one tile and an own plane of the
+    # next; ny = 12 puts the last y-face row in the second tile's own rows
+    r = _run_pair("fused-zhalo", shape, 0.25, 0.004, 1, "first", 5, s1=1.5, window=0, dtype=dtype, path="fused")
+    assert r["solver"].use_fused
+    tol = TOL64 if dtype == "c128" else TOL32
+    assert r["err"] < tol, r["err"]
+    if dtype == "c128":
+        assert r["aux_err"] < TOL64, r["aux_err"]
+
+
 @pytest.mark.parametrize("order", ["dirichlet", "first"])
 @pytest.mark.parametrize("shape", [(19, 21, 45), (18, 20, 44)])
 def test_fused_path_parity_fp32(order, shape):
