@@ -460,12 +460,13 @@ __device__ __forceinline__ void fused2_body(const typename cpx<T>::t* __restrict
         T hr = diag * cen.x + off * (bel.x + abv.x + ym.x + yp.x + xm.x + xp.x) + v * cen.x;
         T hi = diag * cen.y + off * (bel.y + abv.y + ym.y + yp.y + xm.y + xp.y) + v * cen.y;
         if (ORDER == 2) {
-          const int nf = (x == 0) + (x == nx - 1) + (y == 0) + (y == ny - 1) + (zk == 0) + (zk == nz - 1);
-          if (nf) {
-            const double2 sv = cmul(a.m0, make_double2((double)cen.x, (double)cen.y));
-            hr += T(nf * sv.x);
-            hi += T(nf * sv.y);
-          }
+          // zeroth-order local term nf m0 y, nf = number of faces at the
+          // point (0 inside); computed for every lane without a branch, in
+          // the stencil's precision
+          const T nf = T((x == 0) + (x == nx - 1) + (y == 0) + (y == ny - 1) + (zk == 0) + (zk == nz - 1));
+          const T m0x = T(a.m0.x), m0y = T(a.m0.y);
+          hr += nf * (m0x * cen.x - m0y * cen.y);
+          hi += nf * (m0x * cen.y + m0y * cen.x);
         }
         // columns outside the box stay zero (they are x neighbours)
         o[c].x = in ? b0.x + cf * hi : T(0);

@@ -169,7 +169,7 @@ def test_fused_first_order_face_plane_in_tile_halo(shape, dtype):
         assert r["aux_err"] < TOL64, r["aux_err"]
 
 
-@pytest.mark.parametrize("order", ["dirichlet", "first"])
+@pytest.mark.parametrize("order", ["dirichlet", "zeroth", "first"])
 @pytest.mark.parametrize("shape", [(19, 21, 45), (18, 20, 44)])
 def test_fused_path_parity_fp32(order, shape):
     # odd and even row lengths (the x-face columns in the second or the
