@@ -19,12 +19,14 @@
 //     Horner stages rides along in a register delay line;
 //   * tiles are numbered so that consecutive tiles share an XCD and its L2.
 // fused2_kernel runs two of the four stages per launch (two launches per step,
-// two-deep halos) and also carries the zeroth- and first-order conditions: the
-// face sources and the auxiliary stages are evaluated at face points only
-// (whole rows on y and z faces, the two edge lanes on x faces), from the
-// auxiliary arrays in global memory and the field values already in
-// registers.  The state is read from one buffer and written to another,
-// since neighbouring tiles read halos that a tile overwrites.
+// two-deep halos) and also carries the zeroth- and first-order conditions.
+// The first-order auxiliary stages are formed at face points only: on the x
+// faces and the y-face row by the two halo waves (which do no stencil work),
+// through small LDS rings; on the z-face plane by the row waves from
+// registers.  The face sources enter the stage outputs of the face points
+// (whole rows on y and z faces, one column at each end of a row on x faces).
+// The state is read from one buffer and written to another, since
+// neighbouring tiles read halos that a tile overwrites.
 #include <hip/hip_runtime.h>
 
 #include <cstdlib>
