@@ -279,6 +279,11 @@ abc_status abc_setup(const abc_params* pp, abc_ctx** out) {
     S.facc = static_cast<double2*>(tmp);
     if ((st = dev_alloc(c, &tmp, naux * 16)) != ABC_OK) { abc_destroy(c); return st; }
     S.src = static_cast<double2*>(tmp);
+    if (p.form == ABC_FORM_BOX && p.batch == 1) {
+      // one orbital: E y gathered once per stage for the row-blocked product
+      if ((st = dev_alloc(c, &tmp, naux * 16)) != ABC_OK) { abc_destroy(c); return st; }
+      S.bwork[0] = static_cast<double2*>(tmp);
+    }
     if (p.form == ABC_FORM_BOX && p.batch > 1) {
       // the operator over the orbital batch is one complex GEMM per stage;
       // a first call here lets rocBLAS finish its lazy setup (no allocation

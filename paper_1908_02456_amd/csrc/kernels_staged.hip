@@ -455,6 +455,95 @@ hipError_t face_fft_apply(const abc_launch& L, const double2* gin, double2* gout
 }
 
 // ---------------------------------------------------------------------------
+// box form, one orbital: the same product with E y gathered once per stage
+// into a contiguous vector x2, and kBoxRows rows per workgroup, so that every
+// vector element a thread loads serves kBoxRows matrix rows.  Partial sums
+// reduce within each wave by shuffles, then across the waves in LDS; the
+// stage update is that of box_gemv_kernel.  Rows past nrow read the last row
+// and write nothing.
+// ---------------------------------------------------------------------------
+constexpr int kBoxRows = 4, kBoxRowsMin = 4096;
+
+__global__ void __launch_bounds__(kBlock) box_gemv_rows_kernel(
+    const double2* __restrict__ mat, int nrow, int naux, int ncol, int ident, const double2* __restrict__ gin,
+    const double2* __restrict__ x2, double2* __restrict__ gout, double2* __restrict__ facc,
+    double2* __restrict__ aux_out, double coef, int mode) {
+  constexpr int RB = kBoxRows, NW = kBlock / 64;
+  __shared__ double2 red[RB][NW];
+  const int row0 = blockIdx.x * RB;
+  const double2* mrow[RB];
+  double sr[RB], si[RB];
+#pragma unroll
+  for (int r = 0; r < RB; ++r) {
+    mrow[r] = mat + (long long)min(row0 + r, nrow - 1) * ncol;
+    sr[r] = si[r] = 0.0;
+  }
+  // boundary-variable columns; rows below ident skip them (their [0, I]
+  // block is added in the update)
+  for (int j = threadIdx.x; j < naux; j += kBlock) {
+    const double2 v = gin[j];
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+      if (row0 + r < ident) continue;
+      const double2 m = mrow[r][j];
+      sr[r] += m.x * v.x - m.y * v.y;
+      si[r] += m.x * v.y + m.y * v.x;
+    }
+  }
+  // field columns
+  for (int j = threadIdx.x; j < ncol - naux; j += kBlock) {
+    const double2 v = x2[j];
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+      const double2 m = mrow[r][naux + j];
+      sr[r] += m.x * v.x - m.y * v.y;
+      si[r] += m.x * v.y + m.y * v.x;
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < RB; ++r) {
+    for (int o = 32; o > 0; o >>= 1) {
+      sr[r] += __shfl_down(sr[r], o, 64);
+      si[r] += __shfl_down(si[r], o, 64);
+    }
+    if ((threadIdx.x & 63) == 0) red[r][threadIdx.x >> 6] = make_double2(sr[r], si[r]);
+  }
+  __syncthreads();
+  if (threadIdx.x >= RB) return;
+  const int r = threadIdx.x, row = row0 + r;
+  if (row >= nrow) return;
+  double2 t = red[r][0];
+  for (int w = 1; w < NW; ++w) {
+    t.x += red[r][w].x;
+    t.y += red[r][w].y;
+  }
+  if (naux == 0) {
+    gout[row] = t;
+    return;
+  }
+  if (row < ident) {
+    const double2 gv = gin[row + ident];
+    t.x += gv.x;
+    t.y += gv.y;
+  }
+  const double2 gn = make_double2(coef * t.x, coef * t.y);
+  if (mode == 0) {
+    const double2 g0 = gin[row];
+    facc[row] = make_double2(g0.x + gn.x, g0.y + gn.y);
+    gout[row] = gn;
+  } else if (mode == 1) {
+    double2 sacc = facc[row];
+    sacc.x += gn.x;
+    sacc.y += gn.y;
+    facc[row] = sacc;
+    gout[row] = gn;
+  } else {
+    const double2 sacc = facc[row];
+    aux_out[row] = make_double2(sacc.x + gn.x, sacc.y + gn.y);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // box form: dense operator on Gamma.  One workgroup per row; the row of the
 // rows x ncol matrix times [x1; x2] where x1 = the naux boundary variables of
 // the stage (first and second order) or absent (naux = 0, zeroth), x2 = E y.
@@ -815,6 +904,17 @@ hipError_t step_staged_t(const abc_launch& L, const abc_scratch& S, void* psi_v,
           if (rec)
             abc_launch_kernel(tm, "box_epilogue", box_epilogue_kernel, dim3(nblocks(cnt)), dim3(kBlock), st,
                               (const double2*)tout, gcur, gnext, S.facc, aux, cnt, coef, mode);
+        } else if (box && g.batch == 1 && S.bwork[0] && abc::box_rows(L.order, L.n_gamma) >= kBoxRowsMin) {
+          // one orbital, large operator: gather E y, then kBoxRows rows per
+          // workgroup (below kBoxRowsMin rows the extra launch and the fewer
+          // workgroups cost more than the shared vector loads save)
+          const int n = L.n_gamma, rows = abc::box_rows(L.order, n);
+          abc_launch_kernel(tm, kBoundLabel[k], box_gather_kernel<T>, dim3(nblocks(n)), dim3(kBlock), st,
+                            (const C*)ycur, L.gamma_lin, n, 1, S.bwork[0]);
+          abc_launch_kernel(tm, kBoundLabel[k], box_gemv_rows_kernel, dim3((rows + kBoxRows - 1) / kBoxRows),
+                            dim3(kBlock), st, (const double2*)L.box_mat, rows, abc::box_aux_rows(L.order, n),
+                            abc::box_cols(L.order, n), L.order == ABC_SECOND ? n : 0, gcur,
+                            (const double2*)S.bwork[0], rec ? gnext : S.src, S.facc, aux, coef, mode);
         } else if (box) {
           const int n = L.n_gamma;
           dim3 grid(abc::box_rows(L.order, n), g.batch);

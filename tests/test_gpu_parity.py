@@ -103,6 +103,19 @@ def test_box_form_parity(R, order, s2):
         assert r["aux_err"] < TOL64, r["aux_err"]
 
 
+@pytest.mark.parametrize("order", ["zeroth", "first"])
+def test_box_form_large_operator_parity(order):
+    # 28^3, R = 1: n_Gamma = 4376 rows, above the size where one orbital's
+    # operator is applied with E y gathered once per stage and several rows
+    # per workgroup (the small boxes above use one workgroup per row)
+    n = 28
+    print("case: box form large", order, flush=True)
+    r = _run_pair("box-large", (n, n, n), 0.25, 0.004, 1, order, 3, form="box", s0=1.0, s1=1.0)
+    assert r["err"] < TOL64, r["err"]
+    if order == "first":
+        assert r["aux_err"] < TOL64, r["aux_err"]
+
+
 def test_batch_meanfield_parity():
     r = _run_pair("batch-meanfield", (9, 10, 11), 0.3, 0.004, 1, "first", 5, s1=1.0, window=2, batch=3,
                   meanfield=(-1.0, 0.5))
