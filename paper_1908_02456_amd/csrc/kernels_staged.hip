@@ -95,13 +95,12 @@ __global__ void __launch_bounds__(kBlock) meanfield_kernel(const typename cpx<T>
 // mode 2: psi = acc + y_new                      (stage 4)
 // ---------------------------------------------------------------------------
 template <typename T, int R, bool PER>
-__global__ void __launch_bounds__(kBlock) stage_kernel(
-    const typename cpx<T>::t* __restrict__ yin, typename cpx<T>::t* __restrict__ yout,
+__device__ __forceinline__ void stage_body(
+    long long e, const typename cpx<T>::t* __restrict__ yin, typename cpx<T>::t* __restrict__ yout,
     typename cpx<T>::t* __restrict__ acc, typename cpx<T>::t* __restrict__ psi_out,
     const T* __restrict__ V, const double2* __restrict__ fsrc, const double2* __restrict__ bsrc,
-    const int* __restrict__ point_gamma, Geometry g, StencilCoef sc, double coef, int mode) {
+    const int* __restrict__ point_gamma, const Geometry& g, const StencilCoef& sc, double coef, int mode) {
   using C = typename cpx<T>::t;
-  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const int B = g.batch;
   if (e >= g.npts * B) return;
   const long long p = e / B;
@@ -181,6 +180,16 @@ __global__ void __launch_bounds__(kBlock) stage_kernel(
   }
 }
 
+template <typename T, int R, bool PER>
+__global__ void __launch_bounds__(kBlock) stage_kernel(
+    const typename cpx<T>::t* __restrict__ yin, typename cpx<T>::t* __restrict__ yout,
+    typename cpx<T>::t* __restrict__ acc, typename cpx<T>::t* __restrict__ psi_out,
+    const T* __restrict__ V, const double2* __restrict__ fsrc, const double2* __restrict__ bsrc,
+    const int* __restrict__ point_gamma, Geometry g, StencilCoef sc, double coef, int mode) {
+  stage_body<T, R, PER>((long long)blockIdx.x * blockDim.x + threadIdx.x, yin, yout, acc, psi_out, V, fsrc, bsrc,
+                        point_gamma, g, sc, coef, mode);
+}
+
 // ---------------------------------------------------------------------------
 // face-form boundary operator, one thread per face element (f, l, t1, t2, b)
 // first order: g_out = coef (B g_in + A E y);  mode as above for (facc, aux)
@@ -191,12 +200,11 @@ struct LocalBlock {
 };
 
 template <typename T, int R>
-__global__ void __launch_bounds__(kBlock) face_kernel(
-    const double2* __restrict__ gin, double2* __restrict__ gout, double2* __restrict__ facc,
+__device__ __forceinline__ void face_body(
+    long long e, const double2* __restrict__ gin, double2* __restrict__ gout, double2* __restrict__ facc,
     double2* __restrict__ aux_out, const typename cpx<T>::t* __restrict__ yin,
-    const double2* __restrict__ ker, LocalBlock a, Geometry g, int w, double coef, int mode,
+    const double2* __restrict__ ker, const LocalBlock& a, const Geometry& g, int w, double coef, int mode,
     int first) {
-  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const int B = g.batch;
   if (e >= g.face_off[6]) return;
   int f = 0;
@@ -256,6 +264,37 @@ __global__ void __launch_bounds__(kBlock) face_kernel(
     const double2 s = facc[e];
     aux_out[e] = make_double2(s.x + gn.x, s.y + gn.y);
   }
+}
+
+template <typename T, int R>
+__global__ void __launch_bounds__(kBlock) face_kernel(
+    const double2* __restrict__ gin, double2* __restrict__ gout, double2* __restrict__ facc,
+    double2* __restrict__ aux_out, const typename cpx<T>::t* __restrict__ yin,
+    const double2* __restrict__ ker, LocalBlock a, Geometry g, int w, double coef, int mode,
+    int first) {
+  face_body<T, R>((long long)blockIdx.x * blockDim.x + threadIdx.x, gin, gout, facc, aux_out, yin, ker, a, g, w,
+                  coef, mode, first);
+}
+
+// A stage and its boundary-variable stage in one launch, for the orders whose
+// stage reads the auxiliary input rather than the boundary kernel's output
+// (first and second) and a local face operator: the first nsb blocks run the
+// stage, the rest the face elements.  It saves a launch and the gap before
+// it per stage.
+template <typename T, int R, bool PER>
+__global__ void __launch_bounds__(kBlock) stage_face_kernel(
+    const typename cpx<T>::t* __restrict__ yin, typename cpx<T>::t* __restrict__ yout,
+    typename cpx<T>::t* __restrict__ acc, typename cpx<T>::t* __restrict__ psi_out,
+    const T* __restrict__ V, const double2* __restrict__ fsrc, const int* __restrict__ point_gamma,
+    StencilCoef sc, const double2* __restrict__ gin, double2* __restrict__ gout, double2* __restrict__ facc,
+    double2* __restrict__ aux_out, const double2* __restrict__ ker, LocalBlock a, Geometry g, int w, double coef,
+    int mode, unsigned nsb) {
+  if (blockIdx.x < nsb)
+    stage_body<T, R, PER>((long long)blockIdx.x * blockDim.x + threadIdx.x, yin, yout, acc, psi_out, V, fsrc, nullptr,
+                          point_gamma, g, sc, coef, mode);
+  else
+    face_body<T, R>((long long)(blockIdx.x - nsb) * blockDim.x + threadIdx.x, gin, gout, facc, aux_out, yin, ker, a,
+                    g, w, coef, mode, 1);
 }
 
 // ---------------------------------------------------------------------------
@@ -873,6 +912,9 @@ hipError_t step_staged_t(const abc_launch& L, const abc_scratch& S, void* psi_v,
       const int mode = k == 1 ? 0 : (k == 4 ? 2 : 1);
       const double2* fsrc = nullptr;
       const double2* bsrc = nullptr;
+      // the boundary-variable stage runs in the stage's launch (its output)
+      bool merged = false;
+      double2* merged_gnext = nullptr;
       if (rec || zeroth) {
         double2* gnext = (k == 4) ? nullptr : S.g[(k - 1) & 1];
         if (box && L.blas && g.batch > 1) {
@@ -926,6 +968,12 @@ hipError_t step_staged_t(const abc_launch& L, const abc_scratch& S, void* psi_v,
           const hipError_t e = face_fft_apply<T, R>(L, gcur, rec ? gnext : S.src, S.facc, aux, ycur, a, coef, mode,
                                                     rec ? 1 : 0, st, tm, kBoundLabel[k]);
           if (e != hipSuccess) return e;
+        } else if (rec && L.w == 0) {
+          // local operator: launched with the stage below (with a window the
+          // face work is heavy enough that the combined launch is slower
+          // than two: 128^3, w = 8, 409 against 333 us per step)
+          merged = true;
+          merged_gnext = gnext;
         } else {
           abc_launch_kernel(tm, kBoundLabel[k], face_kernel<T, R>, dim3(nblocks(nface)), dim3(kBlock), st, gcur,
                             rec ? gnext : S.src, S.facc, aux, ycur, L.face_ker, a, g, L.w, coef, mode,
@@ -936,8 +984,15 @@ hipError_t step_staged_t(const abc_launch& L, const abc_scratch& S, void* psi_v,
         if (rec) gcur = gnext;
       }
       C* yout = (k == 4) ? nullptr : (keep ? static_cast<C*>(keep[k - 1]) : y[(k - 1) & 1]);
-      abc_launch_kernel(tm, kStageLabel[k], stage_kernel<T, R, PER>, dim3(nblocks(nel)), dim3(kBlock), st, ycur,
-                        yout, acc, psi, Vuse, fsrc, bsrc, L.point_gamma, g, sc, coef, mode);
+      if (merged) {
+        const unsigned nsb = (unsigned)nblocks(nel);
+        abc_launch_kernel(tm, kStageLabel[k], stage_face_kernel<T, R, PER>, dim3(nsb + nblocks(nface)), dim3(kBlock),
+                          st, ycur, yout, acc, psi, Vuse, fsrc, L.point_gamma, sc, fsrc, merged_gnext, S.facc, aux,
+                          L.face_ker, a, g, L.w, coef, mode, nsb);
+      } else {
+        abc_launch_kernel(tm, kStageLabel[k], stage_kernel<T, R, PER>, dim3(nblocks(nel)), dim3(kBlock), st, ycur,
+                          yout, acc, psi, Vuse, fsrc, bsrc, L.point_gamma, g, sc, coef, mode);
+      }
       ycur = yout;
     }
     if (tm) tm->end_step();
