@@ -169,6 +169,27 @@ def test_fused_path_parity(order, shape, steps):
         assert r["aux_err"] < TOL64, r["aux_err"]
 
 
+def _random_shapes(seed, count):
+    # seeded box shapes for the fused path: ragged tiles in every direction,
+    # rows of one or several x chunks, 4- and 8-plane tiles
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(count):
+        out.append((int(rng.integers(6, 42)), int(rng.integers(10, 42)), int(rng.integers(4, 260))))
+    return out
+
+
+@pytest.mark.parametrize("order", ["dirichlet", "zeroth", "first"])
+@pytest.mark.parametrize("shape", _random_shapes(1908, 6))
+def test_fused_path_random_shapes(order, shape):
+    r = _run_pair("fused-random", shape, 0.25, 0.004, 1, order, 3, s0=1.5, s1=1.5, window=0, path="fused",
+                  seed=sum(shape))
+    assert r["solver"].use_fused
+    assert r["err"] < TOL64, r["err"]
+    if order == "first":
+        assert r["aux_err"] < TOL64, r["aux_err"]
+
+
 @pytest.mark.parametrize("shape,dtype", [((17, 12, 20), "c128"), ((9, 10, 14), "c128"), ((17, 12, 20), "c64")])
 def test_fused_first_order_face_plane_in_tile_halo(shape, dtype):
     # nz = 8k + 9 (8-plane tiles) and 4k + 5 (4-plane tiles): the last z-face
