@@ -276,6 +276,99 @@ __global__ void __launch_bounds__(kBlock) face_kernel(
                   coef, mode, first);
 }
 
+// Face-form boundary operator with a window (w >= 2), one orbital: the same
+// sum as face_kernel, tiled.  A workgroup computes a kFT x kFT tile of one
+// face layer l; the input it needs ((kFT + 2w)^2 points of each source layer,
+// zero outside the face) is staged in LDS once, and the kernel taps, the
+// same for every thread of the loop, are read from global memory where they
+// serve the whole wave.  Per output: R (2w+1)^2 complex multiply-adds from
+// LDS.  The first order's local A E y term and the stage update follow as
+// in face_kernel.
+constexpr int kFT = 16, kFaceTileMax = 4096;  // 16 x 16 = kBlock outputs; LDS in double2
+static_assert(kFT * kFT == kBlock, "one output per thread");
+
+inline int face_tile_side(int w) { return kFT + 2 * w; }
+inline bool face_tiled_ok(int R, int w, int batch) {
+  return batch == 1 && w >= 2 && R * face_tile_side(w) * face_tile_side(w) <= kFaceTileMax;
+}
+
+template <typename T, int R>
+__global__ void __launch_bounds__(kBlock) face_tiled_kernel(
+    const double2* __restrict__ gin, double2* __restrict__ gout, double2* __restrict__ facc,
+    double2* __restrict__ aux_out, const typename cpx<T>::t* __restrict__ yin,
+    const double2* __restrict__ ker, LocalBlock a, Geometry g, int w, double coef, int mode, int first) {
+  __shared__ double2 tin[kFaceTileMax];
+  const int f = blockIdx.y / R, l = blockIdx.y - f * R;
+  const int n1 = g.face_n1[f], n2 = g.face_n2[f];
+  const int nt2 = (n2 + kFT - 1) / kFT;
+  if ((int)blockIdx.x >= ((n1 + kFT - 1) / kFT) * nt2) return;  // past this face's tiles
+  const int t1b = ((int)blockIdx.x / nt2) * kFT, t2b = ((int)blockIdx.x % nt2) * kFT;
+  const int S = kFT + 2 * w, K = 2 * w + 1;
+  for (int lp = 0; lp < R; ++lp) {
+    for (int i = threadIdx.x; i < S * S; i += kBlock) {
+      const int a1 = i / S, a2 = i - a1 * S;
+      const int j1 = t1b - w + a1, j2 = t2b - w + a2;
+      double2 v = make_double2(0, 0);
+      if (j1 >= 0 && j1 < n1 && j2 >= 0 && j2 < n2) {
+        if (first) {
+          v = gin[g.face_off[f] + ((long long)lp * n1 + j1) * n2 + j2];
+        } else {
+          const auto yv = yin[face_point(g, f, lp, j1, j2)];
+          v = make_double2((double)yv.x, (double)yv.y);
+        }
+      }
+      tin[(lp * S + a1) * S + a2] = v;
+    }
+  }
+  __syncthreads();
+  const int o1 = threadIdx.x / kFT, o2 = threadIdx.x - o1 * kFT;
+  const int t1 = t1b + o1, t2 = t2b + o2;
+  double sr = 0, si = 0;
+  for (int lp = 0; lp < R; ++lp) {
+    const double2* kl = ker + (long long)(l * R + lp) * K * K;
+    const double2* base = tin + (lp * S + o1) * S + o2;
+    // input point j = t - w + d meets the tap t - j + w = 2w - d
+    for (int d1 = 0; d1 < K; ++d1) {
+      const double2* krow = kl + (long long)(2 * w - d1) * K + 2 * w;
+      const double2* irow = base + d1 * S;
+      for (int d2 = 0; d2 < K; ++d2) {
+        const double2 kv = krow[-d2];
+        const double2 v = irow[d2];
+        sr += kv.x * v.x - kv.y * v.y;
+        si += kv.x * v.y + kv.y * v.x;
+      }
+    }
+  }
+  if (t1 >= n1 || t2 >= n2) return;
+  const long long e = g.face_off[f] + ((long long)l * n1 + t1) * n2 + t2;
+  if (!first) {
+    gout[e] = make_double2(sr, si);
+    return;
+  }
+  for (int lp = 0; lp < R; ++lp) {
+    const double2 av = a.m[l * R + lp];
+    const auto yv = yin[face_point(g, f, lp, t1, t2)];
+    const double yr = (double)yv.x, yi = (double)yv.y;
+    sr += av.x * yr - av.y * yi;
+    si += av.x * yi + av.y * yr;
+  }
+  const double2 gn = make_double2(coef * sr, coef * si);
+  if (mode == 0) {
+    const double2 g0 = gin[e];
+    facc[e] = make_double2(g0.x + gn.x, g0.y + gn.y);
+    gout[e] = gn;
+  } else if (mode == 1) {
+    double2 sacc = facc[e];
+    sacc.x += gn.x;
+    sacc.y += gn.y;
+    facc[e] = sacc;
+    gout[e] = gn;
+  } else {
+    const double2 sacc = facc[e];
+    aux_out[e] = make_double2(sacc.x + gn.x, sacc.y + gn.y);
+  }
+}
+
 // A stage and its boundary-variable stage in one launch, for the orders whose
 // stage reads the auxiliary input rather than the boundary kernel's output
 // (first and second) and a local face operator: the first nsb blocks run the
@@ -974,6 +1067,13 @@ hipError_t step_staged_t(const abc_launch& L, const abc_scratch& S, void* psi_v,
           // than two: 128^3, w = 8, 409 against 333 us per step)
           merged = true;
           merged_gnext = gnext;
+        } else if (face_tiled_ok(R, L.w, g.batch)) {
+          int tiles = 0;
+          for (int f = 0; f < 6; ++f)
+            tiles = std::max(tiles, ((g.face_n1[f] + kFT - 1) / kFT) * ((g.face_n2[f] + kFT - 1) / kFT));
+          abc_launch_kernel(tm, kBoundLabel[k], face_tiled_kernel<T, R>, dim3(tiles, 6 * R), dim3(kBlock), st, gcur,
+                            rec ? gnext : S.src, S.facc, aux, ycur, L.face_ker, a, g, L.w, coef, mode,
+                            rec ? 1 : 0);
         } else {
           abc_launch_kernel(tm, kBoundLabel[k], face_kernel<T, R>, dim3(nblocks(nface)), dim3(kBlock), st, gcur,
                             rec ? gnext : S.src, S.facc, aux, ycur, L.face_ker, a, g, L.w, coef, mode,
