@@ -103,6 +103,17 @@ def test_box_form_parity(R, order, s2):
         assert r["aux_err"] < TOL64, r["aux_err"]
 
 
+@pytest.mark.parametrize("shape,R,order,window", [((18, 21, 35), 1, "first", 3), ((19, 34, 17), 1, "zeroth", 4),
+                                                  ((20, 19, 23), 2, "first", 2), ((17, 18, 33), 3, "zeroth", 2)])
+def test_windowed_faces_several_tiles_parity(shape, R, order, window):
+    # faces wider than one 16 x 16 tile of the LDS-tiled convolution, with
+    # ragged tiles at the far edges
+    r = _run_pair("faces-tiled", shape, 0.25, 0.004, R, order, 4, s0=1.5, s1=1.5, window=window)
+    assert r["err"] < TOL64, r["err"]
+    if order == "first":
+        assert r["aux_err"] < TOL64, r["aux_err"]
+
+
 @pytest.mark.parametrize("order", ["zeroth", "first"])
 def test_box_form_large_operator_parity(order):
     # 28^3, R = 1: n_Gamma = 4376 rows, above the size where one orbital's
