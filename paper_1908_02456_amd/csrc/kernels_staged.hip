@@ -278,26 +278,28 @@ __global__ void __launch_bounds__(kBlock) face_kernel(
 
 // Face-form boundary operator with a window (w >= 2), one orbital: the same
 // sum as face_kernel, tiled.  A workgroup computes a kFT x kFT tile of one
-// face layer l; the input it needs ((kFT + 2w)^2 points of each source layer,
-// zero outside the face) is staged in LDS once, and the kernel taps, the
-// same for every thread of the loop, are read from global memory where they
-// serve the whole wave.  Per output: R (2w+1)^2 complex multiply-adds from
-// LDS.  The first order's local A E y term and the stage update follow as
-// in face_kernel.
-constexpr int kFT = 16, kFaceTileMax = 4096;  // 16 x 16 = kBlock outputs; LDS in double2
-static_assert(kFT * kFT == kBlock, "one output per thread");
-
-inline int face_tile_side(int w) { return kFT + 2 * w; }
+// face layer l.  The input it needs ((kFT + 2w)^2 points of each source
+// layer, zero outside the face) and the taps are staged in LDS once; a tap
+// read is the same address for the whole wave.  Each output is summed by
+// kFSplit threads over interleaved tap rows and combined in LDS: the faces
+// are small (6 n^2 outputs), and one thread per output leaves too few waves
+// to hide the latency of the multiply-add chains.  The first order's local
+// A E y term and the stage update follow as in face_kernel.
+constexpr int kFT = 16, kFSplit = 4, kFBlock = kFT * kFT * kFSplit;  // 16 x 16 outputs, 4 threads each
+constexpr int kFaceInMax = 3072, kFaceTapMax = 1024;                  // LDS, in double2
 inline bool face_tiled_ok(int R, int w, int batch) {
-  return batch == 1 && w >= 2 && R * face_tile_side(w) * face_tile_side(w) <= kFaceTileMax;
+  const int K = 2 * w + 1, S = kFT + 2 * w;
+  return batch == 1 && w >= 2 && R * S * S <= kFaceInMax && R * K * K <= kFaceTapMax;
 }
 
 template <typename T, int R>
-__global__ void __launch_bounds__(kBlock) face_tiled_kernel(
+__global__ void __launch_bounds__(kFBlock) face_tiled_kernel(
     const double2* __restrict__ gin, double2* __restrict__ gout, double2* __restrict__ facc,
     double2* __restrict__ aux_out, const typename cpx<T>::t* __restrict__ yin,
     const double2* __restrict__ ker, LocalBlock a, Geometry g, int w, double coef, int mode, int first) {
-  __shared__ double2 tin[kFaceTileMax];
+  __shared__ double2 tin[kFaceInMax];
+  __shared__ double2 tap[kFaceTapMax];
+  __shared__ double2 part[kFSplit - 1][kFT * kFT];
   const int f = blockIdx.y / R, l = blockIdx.y - f * R;
   const int n1 = g.face_n1[f], n2 = g.face_n2[f];
   const int nt2 = (n2 + kFT - 1) / kFT;
@@ -305,7 +307,7 @@ __global__ void __launch_bounds__(kBlock) face_tiled_kernel(
   const int t1b = ((int)blockIdx.x / nt2) * kFT, t2b = ((int)blockIdx.x % nt2) * kFT;
   const int S = kFT + 2 * w, K = 2 * w + 1;
   for (int lp = 0; lp < R; ++lp) {
-    for (int i = threadIdx.x; i < S * S; i += kBlock) {
+    for (int i = threadIdx.x; i < S * S; i += kFBlock) {
       const int a1 = i / S, a2 = i - a1 * S;
       const int j1 = t1b - w + a1, j2 = t2b - w + a2;
       double2 v = make_double2(0, 0);
@@ -319,26 +321,37 @@ __global__ void __launch_bounds__(kBlock) face_tiled_kernel(
       }
       tin[(lp * S + a1) * S + a2] = v;
     }
+    // taps reversed, so that the input and the tap run the same direction
+    const double2* kl = ker + (long long)(l * R + lp) * K * K;
+    for (int i = threadIdx.x; i < K * K; i += kFBlock) tap[lp * K * K + i] = kl[K * K - 1 - i];
   }
   __syncthreads();
-  const int o1 = threadIdx.x / kFT, o2 = threadIdx.x - o1 * kFT;
-  const int t1 = t1b + o1, t2 = t2b + o2;
+  // thread (q, o): output o of the tile, tap rows d1 = q, q + kFSplit, ...
+  const int q = threadIdx.x / (kFT * kFT), o = threadIdx.x - q * (kFT * kFT);
+  const int o1 = o / kFT, o2 = o - o1 * kFT;
   double sr = 0, si = 0;
   for (int lp = 0; lp < R; ++lp) {
-    const double2* kl = ker + (long long)(l * R + lp) * K * K;
-    const double2* base = tin + (lp * S + o1) * S + o2;
-    // input point j = t - w + d meets the tap t - j + w = 2w - d
-    for (int d1 = 0; d1 < K; ++d1) {
-      const double2* krow = kl + (long long)(2 * w - d1) * K + 2 * w;
-      const double2* irow = base + d1 * S;
+    for (int d1 = q; d1 < K; d1 += kFSplit) {
+      const double2* irow = tin + (lp * S + o1 + d1) * S + o2;
+      const double2* krow = tap + lp * K * K + d1 * K;
+#pragma unroll 4
       for (int d2 = 0; d2 < K; ++d2) {
-        const double2 kv = krow[-d2];
+        const double2 kv = krow[d2];
         const double2 v = irow[d2];
         sr += kv.x * v.x - kv.y * v.y;
         si += kv.x * v.y + kv.y * v.x;
       }
     }
   }
+  if (q > 0) part[q - 1][o] = make_double2(sr, si);
+  __syncthreads();
+  if (q > 0) return;
+#pragma unroll
+  for (int p = 0; p < kFSplit - 1; ++p) {
+    sr += part[p][o].x;
+    si += part[p][o].y;
+  }
+  const int t1 = t1b + o1, t2 = t2b + o2;
   if (t1 >= n1 || t2 >= n2) return;
   const long long e = g.face_off[f] + ((long long)l * n1 + t1) * n2 + t2;
   if (!first) {
@@ -1071,7 +1084,7 @@ hipError_t step_staged_t(const abc_launch& L, const abc_scratch& S, void* psi_v,
           int tiles = 0;
           for (int f = 0; f < 6; ++f)
             tiles = std::max(tiles, ((g.face_n1[f] + kFT - 1) / kFT) * ((g.face_n2[f] + kFT - 1) / kFT));
-          abc_launch_kernel(tm, kBoundLabel[k], face_tiled_kernel<T, R>, dim3(tiles, 6 * R), dim3(kBlock), st, gcur,
+          abc_launch_kernel(tm, kBoundLabel[k], face_tiled_kernel<T, R>, dim3(tiles, 6 * R), dim3(kFBlock), st, gcur,
                             rec ? gnext : S.src, S.facc, aux, ycur, L.face_ker, a, g, L.w, coef, mode,
                             rec ? 1 : 0);
         } else {
