@@ -551,17 +551,26 @@ inline int ilog2(int v) {
   return k;
 }
 
+// Lines per workgroup for transforms of length L over n lines: enough for
+// every thread to own a butterfly (L TW / 2 >= kBlock), and no more, so that
+// the few hundred lines of a face pair spread over many workgroups; the
+// strided column pass takes at least `minTW` lines for wider segments.
+inline int fft_lines_per_group(int L, int n, int minTW) {
+  const int tw = std::max(std::max(1, 2 * kBlock / L), minTW);
+  return std::min(n, std::min(tw, std::max(1, 4096 / L)));
+}
+
 // 2D transform of S slabs of P1 x P2 points at base, with the twiddle
 // tables tw2 (length P2 lines) and tw1 (length P1 lines); at most 64 KB of
 // LDS per workgroup (P <= 4096)
 hipError_t fft2_slabs(double2* base, int P1, int P2, int S, const double2* tw2, const double2* tw1, hipStream_t st) {
   {
-    const int L = P2, TW = std::min(P1, std::max(1, 4096 / L));
+    const int L = P2, TW = fft_lines_per_group(L, P1, 1);
     fft_lines_kernel<<<S * P1 / TW, kBlock, (size_t)TW * L * sizeof(double2), st>>>(
         base, tw2, L, ilog2(L), TW, 1, (long long)TW * L, 0, L, 1);
   }
   {
-    const int L = P1, TW = std::min(P2, std::max(1, 4096 / L));
+    const int L = P1, TW = fft_lines_per_group(L, P2, 4);
     const int per = P2 / TW;
     fft_lines_kernel<<<S * per, kBlock, (size_t)TW * L * sizeof(double2), st>>>(
         base, tw1, L, ilog2(L), TW, per, (long long)P1 * P2, 1, 1, P2);
