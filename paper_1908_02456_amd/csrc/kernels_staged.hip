@@ -410,11 +410,13 @@ __global__ void __launch_bounds__(kBlock) stage_face_kernel(
 // Toeplitz section on the n1 x n2 face because P >= 2 n - 1.
 // ---------------------------------------------------------------------------
 
-// x (the aux stage, or E y for the zeroth order) into the padded slabs of pair q
+// x (the aux stage, or E y for the zeroth order) into the padded slabs of
+// pair q = blockIdx.y (blocks past the pair's slabs do nothing)
 template <typename T>
 __global__ void __launch_bounds__(kBlock) fft_pack_kernel(const double2* __restrict__ gin,
                                                           const typename cpx<T>::t* __restrict__ yin, int first,
-                                                          Geometry g, FaceFFT ff, int q) {
+                                                          Geometry g, FaceFFT ff) {
+  const int q = blockIdx.y;
   const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const int P1 = ff.P1[q], P2 = ff.P2[q], R = g.R, B = g.batch;
   const long long per = (long long)P1 * P2;
@@ -440,11 +442,10 @@ __global__ void __launch_bounds__(kBlock) fft_pack_kernel(const double2* __restr
 // radix-2 transforms of TW lines of length L = 2^logL per workgroup in LDS
 // ([t][k]); line t of group gi starts at (gi / per) A + (gi % per) TW C +
 // t tstride and steps kstride; tw[k] = exp(+-2 pi i k / L), k < L/2
-__global__ void __launch_bounds__(kBlock) fft_lines_kernel(double2* __restrict__ a, const double2* __restrict__ tw,
-                                                           int L, int logL, int TW, int per, long long A, long long C,
-                                                           long long tstride, long long kstride) {
+__device__ __forceinline__ void fft_lines_body(double2* __restrict__ a, const double2* __restrict__ tw, int L,
+                                               int logL, int TW, int per, long long A, long long C, long long tstride,
+                                               long long kstride, int gi) {
   extern __shared__ double2 buf[];
-  const int gi = blockIdx.x;
   const long long base = (long long)(gi / per) * A + (long long)(gi % per) * TW * C;
   const int tot = TW * L;
   const bool kfast = kstride == 1;
@@ -476,8 +477,31 @@ __global__ void __launch_bounds__(kBlock) fft_lines_kernel(double2* __restrict__
   }
 }
 
+__global__ void __launch_bounds__(kBlock) fft_lines_kernel(double2* __restrict__ a, const double2* __restrict__ tw,
+                                                           int L, int logL, int TW, int per, long long A, long long C,
+                                                           long long tstride, long long kstride) {
+  fft_lines_body(a, tw, L, logL, TW, per, A, C, tstride, kstride, blockIdx.x);
+}
+
+// one pass of line transforms over the three face pairs at once (pair
+// blockIdx.y), for the stepping: a launch per pass instead of one per pair
+struct LinePass {
+  long long base, A, C, tstride, kstride, tw_off;
+  int L, logL, TW, per, nblk;
+};
+struct LinePasses {
+  LinePass p[3];
+};
+__global__ void __launch_bounds__(kBlock) fft_pairs_kernel(double2* __restrict__ a, const double2* __restrict__ tw,
+                                                           LinePasses P) {
+  const LinePass& p = P.p[blockIdx.y];
+  if ((int)blockIdx.x >= p.nblk) return;
+  fft_lines_body(a + p.base, tw + p.tw_off, p.L, p.logL, p.TW, p.per, p.A, p.C, p.tstride, p.kstride, blockIdx.x);
+}
+
 // Z(l) = sum_l' spec(l, l') W(l') / (P1 P2) per point of the spectra, pair q
-__global__ void __launch_bounds__(kBlock) fft_mul_kernel(FaceFFT ff, int q, int R, int B) {
+__global__ void __launch_bounds__(kBlock) fft_mul_kernel(FaceFFT ff, int R, int B) {
+  const int q = blockIdx.y;
   const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const long long per = (long long)ff.P1[q] * ff.P2[q];
   if (e >= (long long)ff.S[q] * per) return;
@@ -578,10 +602,45 @@ hipError_t fft2_slabs(double2* base, int P1, int P2, int S, const double2* tw2, 
   return hipGetLastError();
 }
 
-// 2D transform of every slab of pair q in a (forward: fwd = 1)
-hipError_t fft2_pair(const FaceFFT& ff, double2* a, int q, bool fwd, hipStream_t st) {
-  return fft2_slabs(a + ff.woff[q], ff.P1[q], ff.P2[q], ff.S[q], ff.tw + ff.twoff[q][fwd ? 0 : 1],
-                    ff.tw + ff.twoff[q][fwd ? 2 : 3], st);
+// 2D transform of every slab of the three pairs in a (forward: fwd = 1):
+// the row pass of all pairs in one launch, then the column pass
+hipError_t fft2_pairs(const FaceFFT& ff, double2* a, bool fwd, hipStream_t st) {
+  for (int pass = 0; pass < 2; ++pass) {
+    LinePasses P{};
+    int nblk = 0;
+    size_t lds = 0;
+    for (int q = 0; q < 3; ++q) {
+      LinePass& p = P.p[q];
+      const int P1 = ff.P1[q], P2 = ff.P2[q], S = ff.S[q];
+      p.base = ff.woff[q];
+      if (pass == 0) {  // rows: lines along t2
+        p.L = P2;
+        p.TW = fft_lines_per_group(P2, P1, 1);
+        p.per = 1;
+        p.A = (long long)p.TW * P2;
+        p.C = 0;
+        p.tstride = P2;
+        p.kstride = 1;
+        p.nblk = S * P1 / p.TW;
+        p.tw_off = ff.twoff[q][fwd ? 0 : 1];
+      } else {  // columns: lines along t1
+        p.L = P1;
+        p.TW = fft_lines_per_group(P1, P2, 4);
+        p.per = P2 / p.TW;
+        p.A = (long long)P1 * P2;
+        p.C = 1;
+        p.tstride = 1;
+        p.kstride = P2;
+        p.nblk = S * p.per;
+        p.tw_off = ff.twoff[q][fwd ? 2 : 3];
+      }
+      p.logL = ilog2(p.L);
+      nblk = std::max(nblk, p.nblk);
+      lds = std::max(lds, (size_t)p.TW * p.L * sizeof(double2));
+    }
+    fft_pairs_kernel<<<dim3(nblk, 3), kBlock, lds, st>>>(a, ff.tw, P);
+  }
+  return hipGetLastError();
 }
 
 // the face operator of one stage by FFT: gout (first order: coef (B g + A E
@@ -592,16 +651,18 @@ hipError_t face_fft_apply(const abc_launch& L, const double2* gin, double2* gout
                           hipStream_t st, abc_timer* tm, const char* label) {
   const FaceFFT& ff = *L.face_fft;
   const Geometry& g = L.g;
+  // the three face pairs together in every phase (their slabs are disjoint)
+  unsigned nb = 0;
   for (int q = 0; q < 3; ++q) {
     const long long cnt = (long long)ff.S[q] * ff.P1[q] * ff.P2[q];
-    const unsigned nb = (unsigned)((cnt + kBlock - 1) / kBlock);
-    fft_pack_kernel<T><<<nb, kBlock, 0, st>>>(gin, yin, first, g, ff, q);
-    hipError_t e = fft2_pair(ff, ff.W, q, true, st);
-    if (e != hipSuccess) return e;
-    fft_mul_kernel<<<nb, kBlock, 0, st>>>(ff, q, g.R, g.batch);
-    e = fft2_pair(ff, ff.Z, q, false, st);
-    if (e != hipSuccess) return e;
+    nb = std::max(nb, (unsigned)((cnt + kBlock - 1) / kBlock));
   }
+  fft_pack_kernel<T><<<dim3(nb, 3), kBlock, 0, st>>>(gin, yin, first, g, ff);
+  hipError_t e = fft2_pairs(ff, ff.W, true, st);
+  if (e != hipSuccess) return e;
+  fft_mul_kernel<<<dim3(nb, 3), kBlock, 0, st>>>(ff, g.R, g.batch);
+  e = fft2_pairs(ff, ff.Z, false, st);
+  if (e != hipSuccess) return e;
   const long long nface = g.face_off[6];
   abc_launch_kernel(tm, label, fft_finish_kernel<T, R>, dim3((unsigned)((nface + kBlock - 1) / kBlock)), dim3(kBlock),
                     st, gin, gout, facc, aux_out, yin, a, g, ff, coef, mode, first);
