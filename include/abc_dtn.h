@@ -41,7 +41,10 @@
  *                   half-space DtN kernel, truncated to |p|_inf <= window and
  *                   (fejer = 1) tapered by the separable triangular window,
  *                   which keeps both stability theorems' sign conditions.
- *                   window >= max(n)-1 with fejer = 0 is the exact section.
+ *                   window >= max(n)-1 with fejer = 0 is the exact section,
+ *                   applied by zero-padded 2D FFTs (padded side P = the
+ *                   power of two >= 2n - 1; ABC_ENOTSUP unless R * P <= 4096
+ *                   on every face).
  *
  * Memory, layout and ownership
  * ----------------------------

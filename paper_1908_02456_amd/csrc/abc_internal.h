@@ -100,6 +100,8 @@ struct FaceFFT {
   long long woff[4];           // each pair's slabs in W and Z (complex elements)
   long long soff[4];           // each pair's R x R kernel spectra in spec
   long long twoff[3][4];       // twiddles per pair: forward / inverse along t2, forward / inverse along t1
+  int lg1[3], lg2[3];          // log2 P1, log2 P2
+  int twr[3], twc[3];          // lines per workgroup: row passes (along t2), column pass (along t1, R layers)
   double2 *W, *Z, *spec, *tw;
 };
 
@@ -187,6 +189,18 @@ void abc_launch_kernel(abc_timer* tm, const char* label, void (*k)(P...), dim3 g
   }
   hipEvent_t e0, e1;
   if (tm->pair(label, &e0, &e1)) hipExtLaunchKernelGGL(k, grid, block, 0, st, e0, e1, 0, args...);
+}
+
+// the same with `lds` bytes of dynamic LDS
+template <typename... P, typename... A>
+void abc_launch_kernel_lds(abc_timer* tm, const char* label, void (*k)(P...), dim3 grid, dim3 block, size_t lds,
+                           hipStream_t st, A... args) {
+  if (!tm) {
+    k<<<grid, block, lds, st>>>(args...);
+    return;
+  }
+  hipEvent_t e0, e1;
+  if (tm->pair(label, &e0, &e1)) hipExtLaunchKernelGGL(k, grid, block, lds, st, e0, e1, 0, args...);
 }
 
 // keep (optional): three psi-sized buffers that receive the stage vectors

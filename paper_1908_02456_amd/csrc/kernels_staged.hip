@@ -407,58 +407,27 @@ __global__ void __launch_bounds__(kBlock) stage_face_kernel(
 // exact face sections by FFT.  Per face pair q (faces 2q, 2q + 1) the slabs
 // s = (side R + l) B + b of P1 x P2 points ([t1][t2]) hold the zero-padded
 // face layers; the circular convolution with the padded kernel equals the
-// Toeplitz section on the n1 x n2 face because P >= 2 n - 1.
+// Toeplitz section on the n1 x n2 face because P >= 2 n - 1.  A stage takes
+// three launches, each over the three face pairs (pair = blockIdx.y):
+//   rows:    the face layers, zero-extended along t2, transformed along t2
+//            into W (only the n1 rows that hold data: the padded rows are
+//            zero and stay zero under a transform along t2);
+//   columns: per column of the R layers of one (side, batch) slab group, the
+//            forward transform along t1 (rows >= n1 taken as zero), the
+//            product with the R x R kernel spectra, and the inverse transform,
+//            written to Z for the rows t1 < n1 only;
+//   inverse rows + epilogue: the inverse transform along t2 of those rows,
+//            then the face_kernel epilogue on t2 < n2.
 // ---------------------------------------------------------------------------
 
-// x (the aux stage, or E y for the zeroth order) into the padded slabs of
-// pair q = blockIdx.y (blocks past the pair's slabs do nothing)
-template <typename T>
-__global__ void __launch_bounds__(kBlock) fft_pack_kernel(const double2* __restrict__ gin,
-                                                          const typename cpx<T>::t* __restrict__ yin, int first,
-                                                          Geometry g, FaceFFT ff) {
-  const int q = blockIdx.y;
-  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  const int P1 = ff.P1[q], P2 = ff.P2[q], R = g.R, B = g.batch;
-  const long long per = (long long)P1 * P2;
-  if (e >= (long long)ff.S[q] * per) return;
-  const int sl = (int)(e / per);
-  const int m = (int)(e - (long long)sl * per);
-  const int i1 = m / P2, i2 = m % P2;
-  const int b = sl % B, l = (sl / B) % R, side = sl / (B * R);
-  const int f = 2 * q + side;
-  const int n1 = g.face_n1[f], n2 = g.face_n2[f];
-  double2 v = make_double2(0.0, 0.0);
-  if (i1 < n1 && i2 < n2) {
-    if (first) {
-      v = gin[g.face_off[f] + (((long long)l * n1 + i1) * n2 + i2) * B + b];
-    } else {
-      const auto yv = yin[face_point(g, f, l, i1, i2) * B + b];
-      v = make_double2((double)yv.x, (double)yv.y);
-    }
-  }
-  ff.W[ff.woff[q] + e] = v;
-}
-
-// radix-2 transforms of TW lines of length L = 2^logL per workgroup in LDS
-// ([t][k]); line t of group gi starts at (gi / per) A + (gi % per) TW C +
-// t tstride and steps kstride; tw[k] = exp(+-2 pi i k / L), k < L/2
-__device__ __forceinline__ void fft_lines_body(double2* __restrict__ a, const double2* __restrict__ tw, int L,
-                                               int logL, int TW, int per, long long A, long long C, long long tstride,
-                                               long long kstride, int gi) {
-  extern __shared__ double2 buf[];
-  const long long base = (long long)(gi / per) * A + (long long)(gi % per) * TW * C;
-  const int tot = TW * L;
-  const bool kfast = kstride == 1;
-  for (int e = threadIdx.x; e < tot; e += blockDim.x) {
-    const int t = kfast ? e / L : e % TW;
-    const int k = kfast ? e % L : e / TW;
-    const unsigned rk = __brev((unsigned)k) >> (32 - logL);
-    buf[t * L + rk] = a[base + t * tstride + k * kstride];
-  }
-  __syncthreads();
+// decimation in time: TW lines of L points ([t][k]) held in bit-reversed
+// order in buf are transformed in place to natural order; tw[k] =
+// exp(+-2 pi i k / L), k < L/2.  Ends with a barrier.
+__device__ __forceinline__ void fft_dit(double2* buf, const double2* __restrict__ tw, int L, int TW) {
+  const int nb = TW * L / 2;
   for (int len = 2, sh = 1; len <= L; len <<= 1, ++sh) {
     const int half = len >> 1, step = L >> sh;
-    for (int bf = threadIdx.x; bf < tot / 2; bf += blockDim.x) {
+    for (int bf = threadIdx.x; bf < nb; bf += blockDim.x) {
       const int t = bf / (L / 2), r = bf % (L / 2);
       const int grp = r / half, pos = r % half;
       const int i0 = t * L + grp * len + pos, i1 = i0 + half;
@@ -470,6 +439,50 @@ __device__ __forceinline__ void fft_lines_body(double2* __restrict__ a, const do
     }
     __syncthreads();
   }
+}
+
+// decimation in frequency: natural order in, bit-reversed order out (the
+// same transform as fft_dit).  Ends with a barrier.
+__device__ __forceinline__ void fft_dif(double2* buf, const double2* __restrict__ tw, int L, int TW) {
+  const int nb = TW * L / 2;
+  for (int len = L; len >= 2; len >>= 1) {
+    const int half = len >> 1, step = L / len;
+    for (int bf = threadIdx.x; bf < nb; bf += blockDim.x) {
+      const int t = bf / (L / 2), r = bf % (L / 2);
+      const int grp = r / half, pos = r % half;
+      const int i0 = t * L + grp * len + pos, i1 = i0 + half;
+      const double2 w = tw[pos * step];
+      const double2 u = buf[i0], v = buf[i1];
+      const double2 d = make_double2(u.x - v.x, u.y - v.y);
+      buf[i0] = make_double2(u.x + v.x, u.y + v.y);
+      buf[i1] = make_double2(d.x * w.x - d.y * w.y, d.x * w.y + d.y * w.x);
+    }
+    __syncthreads();
+  }
+}
+
+__device__ __forceinline__ int bit_rev(int k, int logL) {
+  return logL == 0 ? 0 : (int)(__brev((unsigned)k) >> (32 - logL));
+}
+
+// TW lines of length L = 2^logL per workgroup; line t of group gi starts at
+// (gi / per) A + (gi % per) TW C + t tstride and steps kstride (the kernel
+// spectra at setup)
+__global__ void __launch_bounds__(kBlock) fft_lines_kernel(double2* __restrict__ a, const double2* __restrict__ tw,
+                                                           int L, int logL, int TW, int per, long long A, long long C,
+                                                           long long tstride, long long kstride) {
+  extern __shared__ double2 buf[];
+  const int gi = blockIdx.x;
+  const long long base = (long long)(gi / per) * A + (long long)(gi % per) * TW * C;
+  const int tot = TW * L;
+  const bool kfast = kstride == 1;
+  for (int e = threadIdx.x; e < tot; e += blockDim.x) {
+    const int t = kfast ? e / L : e % TW;
+    const int k = kfast ? e % L : e / TW;
+    buf[t * L + bit_rev(k, logL)] = a[base + t * tstride + k * kstride];
+  }
+  __syncthreads();
+  fft_dit(buf, tw, L, TW);
   for (int e = threadIdx.x; e < tot; e += blockDim.x) {
     const int t = kfast ? e / L : e % TW;
     const int k = kfast ? e % L : e / TW;
@@ -477,95 +490,157 @@ __device__ __forceinline__ void fft_lines_body(double2* __restrict__ a, const do
   }
 }
 
-__global__ void __launch_bounds__(kBlock) fft_lines_kernel(double2* __restrict__ a, const double2* __restrict__ tw,
-                                                           int L, int logL, int TW, int per, long long A, long long C,
-                                                           long long tstride, long long kstride) {
-  fft_lines_body(a, tw, L, logL, TW, per, A, C, tstride, kstride, blockIdx.x);
-}
-
-// one pass of line transforms over the three face pairs at once (pair
-// blockIdx.y), for the stepping: a launch per pass instead of one per pair
-struct LinePass {
-  long long base, A, C, tstride, kstride, tw_off;
-  int L, logL, TW, per, nblk;
-};
-struct LinePasses {
-  LinePass p[3];
-};
-__global__ void __launch_bounds__(kBlock) fft_pairs_kernel(double2* __restrict__ a, const double2* __restrict__ tw,
-                                                           LinePasses P) {
-  const LinePass& p = P.p[blockIdx.y];
-  if ((int)blockIdx.x >= p.nblk) return;
-  fft_lines_body(a + p.base, tw + p.tw_off, p.L, p.logL, p.TW, p.per, p.A, p.C, p.tstride, p.kstride, blockIdx.x);
-}
-
-// Z(l) = sum_l' spec(l, l') W(l') / (P1 P2) per point of the spectra, pair q
-__global__ void __launch_bounds__(kBlock) fft_mul_kernel(FaceFFT ff, int R, int B) {
-  const int q = blockIdx.y;
-  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  const long long per = (long long)ff.P1[q] * ff.P2[q];
-  if (e >= (long long)ff.S[q] * per) return;
-  const int sl = (int)(e / per);
-  const long long m = e - (long long)sl * per;
-  const int b = sl % B, l = (sl / B) % R, side = sl / (B * R);
-  const double inv = 1.0 / (double)per;
-  double zr = 0, zi = 0;
-  for (int lp = 0; lp < R; ++lp) {
-    const double2 k = ff.spec[ff.soff[q] + (long long)(l * R + lp) * per + m];
-    const double2 x = ff.W[ff.woff[q] + ((long long)((side * R + lp) * B + b)) * per + m];
-    zr += k.x * x.x - k.y * x.y;
-    zi += k.x * x.y + k.y * x.x;
+// rows: line ln = s n1 + t1 (ln < S n1) of pair q is row t1 of slab s
+template <typename T>
+__global__ void __launch_bounds__(kBlock) fft_rows_fwd_kernel(const double2* __restrict__ gin,
+                                                              const typename cpx<T>::t* __restrict__ yin, int first,
+                                                              Geometry g, FaceFFT ff) {
+  extern __shared__ double2 buf[];
+  const int q = blockIdx.y, f0 = 2 * q;
+  const int n1 = g.face_n1[f0], n2 = g.face_n2[f0], R = g.R, B = g.batch;
+  const int P1 = ff.P1[q], P2 = ff.P2[q], logL = ff.lg2[q], TW = ff.twr[q];
+  const int nline = ff.S[q] * n1, ln0 = blockIdx.x * TW;
+  if (ln0 >= nline) return;
+  const int tot = TW * P2;
+  for (int e = threadIdx.x; e < tot; e += blockDim.x) {
+    const int t = e >> logL, k = e & (P2 - 1), ln = ln0 + t;
+    double2 v = make_double2(0.0, 0.0);
+    if (ln < nline && k < n2) {
+      const int sl = ln / n1, t1 = ln - sl * n1;
+      const int b = sl % B, l = (sl / B) % R, f = f0 + sl / (B * R);
+      if (first) {
+        v = gin[g.face_off[f] + (((long long)l * n1 + t1) * n2 + k) * B + b];
+      } else {
+        const auto yv = yin[face_point(g, f, l, t1, k) * B + b];
+        v = make_double2((double)yv.x, (double)yv.y);
+      }
+    }
+    buf[t * P2 + bit_rev(k, logL)] = v;
   }
-  ff.Z[ff.woff[q] + e] = make_double2(zr * inv, zi * inv);
+  __syncthreads();
+  fft_dit(buf, ff.tw + ff.twoff[q][0], P2, TW);
+  double2* W = ff.W + ff.woff[q];
+  for (int e = threadIdx.x; e < tot; e += blockDim.x) {
+    const int t = e >> logL, k = e & (P2 - 1), ln = ln0 + t;
+    if (ln < nline) {
+      const int sl = ln / n1, t1 = ln - sl * n1;
+      W[((long long)sl * P1 + t1) * P2 + k] = buf[t * P2 + k];
+    }
+  }
 }
 
-// the face_kernel epilogue on the convolution read from Z
+// columns: workgroup = (slab group side B + b, TW columns from c0); the R
+// layers of the group sit in LDS one after the other ([l][t][k])
+__global__ void __launch_bounds__(kBlock) fft_cols_kernel(Geometry g, FaceFFT ff) {
+  extern __shared__ double2 buf[];
+  const int q = blockIdx.y;
+  const int n1 = g.face_n1[2 * q], R = g.R, B = g.batch;
+  const int P1 = ff.P1[q], P2 = ff.P2[q], logL = ff.lg1[q], TW = ff.twc[q];
+  const int per = P2 / TW;
+  if ((int)blockIdx.x >= 2 * B * per) return;
+  const int sg = blockIdx.x / per, c0 = (blockIdx.x % per) * TW;
+  const int side = sg / B, b = sg % B;
+  const int tot = TW * P1;
+  const long long slab = (long long)P1 * P2;
+  for (int l = 0; l < R; ++l) {
+    const double2* src = ff.W + ff.woff[q] + (long long)((side * R + l) * B + b) * slab + c0;
+    for (int e = threadIdx.x; e < tot; e += blockDim.x) {
+      const int t = e % TW, k = e / TW;
+      buf[l * tot + t * P1 + bit_rev(k, logL)] = k < n1 ? src[(long long)k * P2 + t] : make_double2(0.0, 0.0);
+    }
+  }
+  __syncthreads();
+  fft_dit(buf, ff.tw + ff.twoff[q][2], P1, R * TW);
+  // Z(l) = sum_l' spec(l, l') W(l') / (P1 P2), point by point
+  const double inv = 1.0 / (double)slab;
+  const double2* spec = ff.spec + ff.soff[q];
+  for (int e = threadIdx.x; e < tot; e += blockDim.x) {
+    const int t = e % TW, k = e / TW;
+    const long long m = (long long)k * P2 + c0 + t;
+    double2 x[abc::kMaxR];
+    for (int lp = 0; lp < R; ++lp) x[lp] = buf[lp * tot + t * P1 + k];
+    for (int l = 0; l < R; ++l) {
+      double zr = 0, zi = 0;
+      for (int lp = 0; lp < R; ++lp) {
+        const double2 kv = spec[(long long)(l * R + lp) * slab + m];
+        zr += kv.x * x[lp].x - kv.y * x[lp].y;
+        zi += kv.x * x[lp].y + kv.y * x[lp].x;
+      }
+      buf[l * tot + t * P1 + k] = make_double2(zr * inv, zi * inv);
+    }
+  }
+  __syncthreads();
+  fft_dif(buf, ff.tw + ff.twoff[q][3], P1, R * TW);
+  const int tout = TW * n1;
+  for (int l = 0; l < R; ++l) {
+    double2* dst = ff.Z + ff.woff[q] + (long long)((side * R + l) * B + b) * slab + c0;
+    for (int e = threadIdx.x; e < tout; e += blockDim.x) {
+      const int t = e % TW, k = e / TW;
+      dst[(long long)k * P2 + t] = buf[l * tot + t * P1 + bit_rev(k, logL)];
+    }
+  }
+}
+
+// inverse rows of Z (t1 < n1) and the face_kernel epilogue on t2 < n2
 template <typename T, int R>
-__global__ void __launch_bounds__(kBlock) fft_finish_kernel(
+__global__ void __launch_bounds__(kBlock) fft_rows_inv_kernel(
     const double2* __restrict__ gin, double2* __restrict__ gout, double2* __restrict__ facc,
     double2* __restrict__ aux_out, const typename cpx<T>::t* __restrict__ yin, LocalBlock a, Geometry g, FaceFFT ff,
     double coef, int mode, int first) {
-  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  const int B = g.batch;
-  if (e >= g.face_off[6]) return;
-  int f = 0;
-  while (e >= g.face_off[f + 1]) ++f;
-  const long long r = e - g.face_off[f];
-  const int n1 = g.face_n1[f], n2 = g.face_n2[f];
-  const int b = (int)(r % B);
-  const long long qq = r / B;
-  const int t2 = (int)(qq % n2);
-  const int t1 = (int)((qq / n2) % n1);
-  const int l = (int)(qq / ((long long)n1 * n2));
-  const int q = f >> 1, side = f & 1;
-  const long long per = (long long)ff.P1[q] * ff.P2[q];
-  const double2 cv = ff.Z[ff.woff[q] + ((long long)((side * R + l) * B + b)) * per + (long long)t1 * ff.P2[q] + t2];
-  double sr = cv.x, si = cv.y;
-  if (!first) {
-    gout[e] = make_double2(sr, si);
-    return;
+  extern __shared__ double2 buf[];
+  const int q = blockIdx.y, f0 = 2 * q;
+  const int n1 = g.face_n1[f0], n2 = g.face_n2[f0], B = g.batch;
+  const int P1 = ff.P1[q], P2 = ff.P2[q], logL = ff.lg2[q], TW = ff.twr[q];
+  const int nline = ff.S[q] * n1, ln0 = blockIdx.x * TW;
+  if (ln0 >= nline) return;
+  const double2* Z = ff.Z + ff.woff[q];
+  const int tot = TW * P2;
+  for (int e = threadIdx.x; e < tot; e += blockDim.x) {
+    const int t = e >> logL, k = e & (P2 - 1), ln = ln0 + t;
+    double2 v = make_double2(0.0, 0.0);
+    if (ln < nline) {
+      const int sl = ln / n1, t1 = ln - sl * n1;
+      v = Z[((long long)sl * P1 + t1) * P2 + k];
+    }
+    buf[t * P2 + bit_rev(k, logL)] = v;
   }
-  for (int lp = 0; lp < R; ++lp) {
-    const double2 av = a.m[l * R + lp];
-    const auto yv = yin[face_point(g, f, lp, t1, t2) * B + b];
-    const double yr = (double)yv.x, yi = (double)yv.y;
-    sr += av.x * yr - av.y * yi;
-    si += av.x * yi + av.y * yr;
-  }
-  const double2 gn = make_double2(coef * sr, coef * si);
-  if (mode == 0) {
-    const double2 g0 = gin[e];
-    facc[e] = make_double2(g0.x + gn.x, g0.y + gn.y);
-    gout[e] = gn;
-  } else if (mode == 1) {
-    double2 s2 = facc[e];
-    s2.x += gn.x;
-    s2.y += gn.y;
-    facc[e] = s2;
-    gout[e] = gn;
-  } else {
-    const double2 s2 = facc[e];
-    aux_out[e] = make_double2(s2.x + gn.x, s2.y + gn.y);
+  __syncthreads();
+  fft_dit(buf, ff.tw + ff.twoff[q][1], P2, TW);
+  const int tout = TW * n2;
+  for (int e = threadIdx.x; e < tout; e += blockDim.x) {
+    const int t = e / n2, t2 = e - t * n2, ln = ln0 + t;
+    if (ln >= nline) continue;
+    const int sl = ln / n1, t1 = ln - sl * n1;
+    const int b = sl % B, l = (sl / B) % R, f = f0 + sl / (B * R);
+    const long long fe = g.face_off[f] + (((long long)l * n1 + t1) * n2 + t2) * B + b;
+    const double2 cv = buf[t * P2 + t2];
+    double sr = cv.x, si = cv.y;
+    if (!first) {
+      gout[fe] = make_double2(sr, si);
+      continue;
+    }
+    for (int lp = 0; lp < R; ++lp) {
+      const double2 av = a.m[l * R + lp];
+      const auto yv = yin[face_point(g, f, lp, t1, t2) * B + b];
+      const double yr = (double)yv.x, yi = (double)yv.y;
+      sr += av.x * yr - av.y * yi;
+      si += av.x * yi + av.y * yr;
+    }
+    const double2 gn = make_double2(coef * sr, coef * si);
+    if (mode == 0) {
+      const double2 g0 = gin[fe];
+      facc[fe] = make_double2(g0.x + gn.x, g0.y + gn.y);
+      gout[fe] = gn;
+    } else if (mode == 1) {
+      double2 s2 = facc[fe];
+      s2.x += gn.x;
+      s2.y += gn.y;
+      facc[fe] = s2;
+      gout[fe] = gn;
+    } else {
+      const double2 s2 = facc[fe];
+      aux_out[fe] = make_double2(s2.x + gn.x, s2.y + gn.y);
+    }
   }
 }
 
@@ -602,47 +677,6 @@ hipError_t fft2_slabs(double2* base, int P1, int P2, int S, const double2* tw2, 
   return hipGetLastError();
 }
 
-// 2D transform of every slab of the three pairs in a (forward: fwd = 1):
-// the row pass of all pairs in one launch, then the column pass
-hipError_t fft2_pairs(const FaceFFT& ff, double2* a, bool fwd, hipStream_t st) {
-  for (int pass = 0; pass < 2; ++pass) {
-    LinePasses P{};
-    int nblk = 0;
-    size_t lds = 0;
-    for (int q = 0; q < 3; ++q) {
-      LinePass& p = P.p[q];
-      const int P1 = ff.P1[q], P2 = ff.P2[q], S = ff.S[q];
-      p.base = ff.woff[q];
-      if (pass == 0) {  // rows: lines along t2
-        p.L = P2;
-        p.TW = fft_lines_per_group(P2, P1, 1);
-        p.per = 1;
-        p.A = (long long)p.TW * P2;
-        p.C = 0;
-        p.tstride = P2;
-        p.kstride = 1;
-        p.nblk = S * P1 / p.TW;
-        p.tw_off = ff.twoff[q][fwd ? 0 : 1];
-      } else {  // columns: lines along t1
-        p.L = P1;
-        p.TW = fft_lines_per_group(P1, P2, 4);
-        p.per = P2 / p.TW;
-        p.A = (long long)P1 * P2;
-        p.C = 1;
-        p.tstride = 1;
-        p.kstride = P2;
-        p.nblk = S * p.per;
-        p.tw_off = ff.twoff[q][fwd ? 2 : 3];
-      }
-      p.logL = ilog2(p.L);
-      nblk = std::max(nblk, p.nblk);
-      lds = std::max(lds, (size_t)p.TW * p.L * sizeof(double2));
-    }
-    fft_pairs_kernel<<<dim3(nblk, 3), kBlock, lds, st>>>(a, ff.tw, P);
-  }
-  return hipGetLastError();
-}
-
 // the face operator of one stage by FFT: gout (first order: coef (B g + A E
 // y) with the Taylor modes of face_kernel; zeroth: M E y)
 template <typename T, int R>
@@ -651,21 +685,19 @@ hipError_t face_fft_apply(const abc_launch& L, const double2* gin, double2* gout
                           hipStream_t st, abc_timer* tm, const char* label) {
   const FaceFFT& ff = *L.face_fft;
   const Geometry& g = L.g;
-  // the three face pairs together in every phase (their slabs are disjoint)
-  unsigned nb = 0;
+  unsigned nr = 0, nc = 0;
+  size_t lr = 0, lc = 0;
   for (int q = 0; q < 3; ++q) {
-    const long long cnt = (long long)ff.S[q] * ff.P1[q] * ff.P2[q];
-    nb = std::max(nb, (unsigned)((cnt + kBlock - 1) / kBlock));
+    const int n1 = g.face_n1[2 * q];
+    nr = std::max(nr, (unsigned)((ff.S[q] * n1 + ff.twr[q] - 1) / ff.twr[q]));
+    nc = std::max(nc, (unsigned)(2 * g.batch * (ff.P2[q] / ff.twc[q])));
+    lr = std::max(lr, (size_t)ff.twr[q] * ff.P2[q] * sizeof(double2));
+    lc = std::max(lc, (size_t)g.R * ff.twc[q] * ff.P1[q] * sizeof(double2));
   }
-  fft_pack_kernel<T><<<dim3(nb, 3), kBlock, 0, st>>>(gin, yin, first, g, ff);
-  hipError_t e = fft2_pairs(ff, ff.W, true, st);
-  if (e != hipSuccess) return e;
-  fft_mul_kernel<<<dim3(nb, 3), kBlock, 0, st>>>(ff, g.R, g.batch);
-  e = fft2_pairs(ff, ff.Z, false, st);
-  if (e != hipSuccess) return e;
-  const long long nface = g.face_off[6];
-  abc_launch_kernel(tm, label, fft_finish_kernel<T, R>, dim3((unsigned)((nface + kBlock - 1) / kBlock)), dim3(kBlock),
-                    st, gin, gout, facc, aux_out, yin, a, g, ff, coef, mode, first);
+  fft_rows_fwd_kernel<T><<<dim3(nr, 3), kBlock, lr, st>>>(gin, yin, first, g, ff);
+  fft_cols_kernel<<<dim3(nc, 3), kBlock, lc, st>>>(g, ff);
+  abc_launch_kernel_lds(tm, label, fft_rows_inv_kernel<T, R>, dim3(nr, 3), dim3(kBlock), lr, st, gin, gout, facc,
+                        aux_out, yin, a, g, ff, coef, mode, first);
   return hipGetLastError();
 }
 
@@ -1263,6 +1295,13 @@ abc_status face_fft_setup(const Geometry& g, int R, int w, const std::vector<abc
     ff.P1[q] = P1;
     ff.P2[q] = P2;
     ff.S[q] = 2 * R * B;
+    ff.lg1[q] = ilog2(P1);
+    ff.lg2[q] = ilog2(P2);
+    ff.twr[q] = fft_lines_per_group(P2, ff.S[q] * n1, 1);
+    int twc = fft_lines_per_group(P1, P2, 4);
+    while (twc > 1 && R * twc * P1 > 4096) twc >>= 1;
+    if (R * twc * P1 > 4096) { err = "face too large for the FFT face path at this stencil radius"; return ABC_ENOTSUP; }
+    ff.twc[q] = twc;
     ff.woff[q] = woff;
     woff += (long long)ff.S[q] * P1 * P2;
     ff.soff[q] = soff;

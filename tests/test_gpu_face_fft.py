@@ -30,6 +30,8 @@ CASES = [
     ((12, 11, 10), 1, "first", 3, "c128", 3),
     ((10, 11, 12), 1, "first", 1, "c64", 4),
     ((24, 26, 25), 1, "first", 1, "c128", 3),
+    ((9, 10, 11), 3, "first", 1, "c128", 3),
+    ((10, 9, 11), 3, "zeroth", 2, "c128", 3),
 ]
 
 
