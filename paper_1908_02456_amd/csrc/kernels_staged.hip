@@ -94,6 +94,64 @@ __global__ void __launch_bounds__(kBlock) meanfield_kernel(const typename cpx<T>
 // mode 1: acc += y_new,       y_out = y_new      (stages 2, 3)
 // mode 2: psi = acc + y_new                      (stage 4)
 // ---------------------------------------------------------------------------
+// the rest of a stage at point p (orbital b, element e) once the stencil sum
+// (hr, hi) is formed: potential, boundary source, -i coef, and the mode's
+// accumulator update
+// (vv = V[p] when V is given, av = acc[e] in modes 1 and 2: loaded by the
+// caller, so that a sweep can issue them early)
+template <typename T, int R>
+__device__ __forceinline__ void stage_tail(long long e, long long p, int b, int x, int y, int z,
+                                           const typename cpx<T>::t c0, T hr, T hi, T vv, typename cpx<T>::t av,
+                                           typename cpx<T>::t* __restrict__ acc, typename cpx<T>::t* __restrict__ yout,
+                                           typename cpx<T>::t* __restrict__ psi_out, const T* __restrict__ V,
+                                           const double2* __restrict__ fsrc, const double2* __restrict__ bsrc,
+                                           const int* __restrict__ point_gamma, const Geometry& g, double coef,
+                                           int mode) {
+  using C = typename cpx<T>::t;
+  if (V) {
+    hr += vv * c0.x;
+    hi += vv * c0.y;
+  }
+  // boundary term (FP64 source, added in the stencil precision)
+  if (fsrc) {
+    if (x < R || x >= g.nx - R || y < R || y >= g.ny - R || z < R || z >= g.nz - R) {
+      const double2 s = face_gather(g, fsrc, x, y, z, b);
+      hr += T(s.x);
+      hi += T(s.y);
+    }
+  } else if (bsrc) {
+    const int gi = point_gamma[p];
+    if (gi >= 0) {
+      const double2 s = bsrc[(long long)gi * g.batch + b];
+      hr += T(s.x);
+      hi += T(s.y);
+    }
+  }
+  // y_new = coef * (-i) (H y + src)
+  const T cf = T(coef);
+  C yn;
+  yn.x = cf * hi;
+  yn.y = -cf * hr;
+  if (mode == 0) {
+    C a;
+    a.x = c0.x + yn.x;
+    a.y = c0.y + yn.y;
+    acc[e] = a;
+    yout[e] = yn;
+  } else if (mode == 1) {
+    C a = av;
+    a.x += yn.x;
+    a.y += yn.y;
+    acc[e] = a;
+    yout[e] = yn;
+  } else {
+    C a = av;
+    a.x += yn.x;
+    a.y += yn.y;
+    psi_out[e] = a;
+  }
+}
+
 template <typename T, int R, bool PER>
 __device__ __forceinline__ void stage_body(
     long long e, const typename cpx<T>::t* __restrict__ yin, typename cpx<T>::t* __restrict__ yout,
@@ -135,49 +193,12 @@ __device__ __forceinline__ void stage_body(
     hr += w * ar;
     hi += w * ai;
   }
-  if (V) {
-    const T v = V[p];
-    hr += v * c0.x;
-    hi += v * c0.y;
-  }
-  // boundary term (FP64 source, added in the stencil precision)
-  if (fsrc) {
-    if (x < R || x >= g.nx - R || y < R || y >= g.ny - R || z < R || z >= g.nz - R) {
-      const double2 s = face_gather(g, fsrc, x, y, z, b);
-      hr += T(s.x);
-      hi += T(s.y);
-    }
-  } else if (bsrc) {
-    const int gi = point_gamma[p];
-    if (gi >= 0) {
-      const double2 s = bsrc[(long long)gi * B + b];
-      hr += T(s.x);
-      hi += T(s.y);
-    }
-  }
-  // y_new = coef * (-i) (H y + src)
-  const T cf = T(coef);
-  C yn;
-  yn.x = cf * hi;
-  yn.y = -cf * hr;
-  if (mode == 0) {
-    C a;
-    a.x = c0.x + yn.x;
-    a.y = c0.y + yn.y;
-    acc[e] = a;
-    yout[e] = yn;
-  } else if (mode == 1) {
-    C a = acc[e];
-    a.x += yn.x;
-    a.y += yn.y;
-    acc[e] = a;
-    yout[e] = yn;
-  } else {
-    C a = acc[e];
-    a.x += yn.x;
-    a.y += yn.y;
-    psi_out[e] = a;
-  }
+  C av;
+  av.x = 0;
+  av.y = 0;
+  if (mode != 0) av = acc[e];
+  stage_tail<T, R>(e, p, b, x, y, z, c0, hr, hi, V ? V[p] : T(0), av, acc, yout, psi_out, V, fsrc, bsrc, point_gamma,
+                   g, coef, mode);
 }
 
 template <typename T, int R, bool PER>
@@ -188,6 +209,178 @@ __global__ void __launch_bounds__(kBlock) stage_kernel(
     const int* __restrict__ point_gamma, Geometry g, StencilCoef sc, double coef, int mode) {
   stage_body<T, R, PER>((long long)blockIdx.x * blockDim.x + threadIdx.x, yin, yout, acc, psi_out, V, fsrc, bsrc,
                         point_gamma, g, sc, coef, mode);
+}
+
+// ---------------------------------------------------------------------------
+// the same sweep tiled, for one orbital with zero outside the box: a
+// workgroup owns kTX x-columns, TY = kTW J rows (wave w takes rows w, w + kTW,
+// ...) and tz planes, and marches z.  Each thread keeps its J points' 2R + 1
+// z-neighbours in a register queue that advances one plane per step, so the
+// tile's interior is read from memory once; the centre plane goes to LDS with
+// R-wide x and y halos (double buffered: one barrier per plane) for the x
+// and y neighbours.  The next plane's loads are issued before the barrier.
+// ---------------------------------------------------------------------------
+constexpr int kTX = 64, kTW = kBlock / 64;
+// one row per thread; planes per tile by radius (measured at 128^3, us per
+// step: R = 3 136 with 16 planes against 142 with 8 and 193 with 32; R = 2
+// 117 with 8 against 122 with 16; two rows per thread 143 and 129).  R = 1
+// keeps the untiled sweep (174.6 tiled against 167.7 at w = 8).
+constexpr int kTileJ = 1;
+constexpr int kTiledMinR = 2;
+constexpr int tile_planes(int R) { return R >= 3 ? 16 : 8; }
+
+struct TileGrid {
+  int ntx, nty, ntz, tz;
+  int tiles_per_xcd;  // tiles / 8 when that divides, for the XCD-aware order; else 0
+};
+
+template <int R, int J>
+struct TileShape {
+  static constexpr int TY = kTW * J, LX = kTX + 2 * R, LY = TY + 2 * R;
+  static constexpr int NH = 2 * R * (kTX + TY);        // halo points per plane
+  static constexpr int HPT = (NH + kBlock - 1) / kBlock;  // per thread
+};
+
+template <typename T, int R, int J>
+__device__ __forceinline__ void stage_tiled_body(
+    int tile, const TileGrid& tg, const typename cpx<T>::t* __restrict__ yin, typename cpx<T>::t* __restrict__ yout,
+    typename cpx<T>::t* __restrict__ acc, typename cpx<T>::t* __restrict__ psi_out, const T* __restrict__ V,
+    const double2* __restrict__ fsrc, const double2* __restrict__ bsrc, const int* __restrict__ point_gamma,
+    const Geometry& g, const StencilCoef& sc, double coef, int mode) {
+  using C = typename cpx<T>::t;
+  using S = TileShape<R, J>;
+  __shared__ C pl[2][S::LY][S::LX];
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  const int bx = tile % tg.ntx, by = (tile / tg.ntx) % tg.nty, bz = tile / (tg.ntx * tg.nty);
+  const int x0 = bx * kTX, y0 = by * S::TY, z0 = bz * tg.tz;
+  const int z1 = min(z0 + tg.tz, g.nz);
+  const int nx = g.nx, ny = g.ny, nz = g.nz;
+  const long long sy = nx, sz = (long long)nx * ny;
+  const int x = x0 + tx;
+  auto load = [&](int xx, int yy, int zz) {
+    C v;
+    v.x = 0;
+    v.y = 0;
+    if (xx >= 0 && xx < nx && yy >= 0 && yy < ny && zz >= 0 && zz < nz) v = yin[zz * sz + yy * sy + xx];
+    return v;
+  };
+  // halo point h of a plane: LDS position and box coordinates
+  auto halo_pos = [&](int h, int& ly, int& lx) {
+    if (h < 2 * R * kTX) {
+      const int r = h / kTX, c = h % kTX;
+      ly = r < R ? r : S::TY + r;
+      lx = R + c;
+    } else {
+      const int k = h - 2 * R * kTX, r = k % S::TY, c = k / S::TY;
+      ly = R + r;
+      lx = c < R ? c : kTX + c;
+    }
+  };
+  C q[J][2 * R + 1];
+  C hv[S::HPT];
+#pragma unroll
+  for (int j = 0; j < J; ++j)
+#pragma unroll
+    for (int i = 0; i <= 2 * R; ++i) q[j][i] = load(x, y0 + ty + kTW * j, z0 - R + i);
+#pragma unroll
+  for (int hh = 0; hh < S::HPT; ++hh) {
+    const int h = threadIdx.x + hh * kBlock;
+    int ly = 0, lx = 0;
+    if (h < S::NH) halo_pos(h, ly, lx);
+    hv[hh] = load(x0 - R + lx, y0 - R + ly, h < S::NH ? z0 : -1);
+  }
+  const T diag = T(sc.diag);
+  T off[R + 1];
+#pragma unroll
+  for (int k = 1; k <= R; ++k) off[k] = T(sc.off[k]);
+  for (int z = z0; z < z1; ++z) {
+    const int buf = (z - z0) & 1;
+#pragma unroll
+    for (int j = 0; j < J; ++j) pl[buf][R + ty + kTW * j][R + tx] = q[j][R];
+#pragma unroll
+    for (int hh = 0; hh < S::HPT; ++hh) {
+      const int h = threadIdx.x + hh * kBlock;
+      if (h < S::NH) {
+        int ly, lx;
+        halo_pos(h, ly, lx);
+        pl[buf][ly][lx] = hv[hh];
+      }
+    }
+    T vv[J];
+    C av[J];
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      const int yy = y0 + ty + kTW * j;
+      const long long pnt = z * sz + yy * sy + x;
+      const bool in = x < nx && yy < ny;
+      vv[j] = (V && in) ? V[pnt] : T(0);
+      av[j].x = 0;
+      av[j].y = 0;
+      if (mode != 0 && in) av[j] = acc[pnt];
+    }
+    C nxt[J];
+    const bool more = z + 1 < z1;
+#pragma unroll
+    for (int j = 0; j < J; ++j) nxt[j] = load(x, y0 + ty + kTW * j, more ? z + R + 1 : -1);
+#pragma unroll
+    for (int hh = 0; hh < S::HPT; ++hh) {
+      const int h = threadIdx.x + hh * kBlock;
+      int ly = 0, lx = 0;
+      if (h < S::NH) halo_pos(h, ly, lx);
+      hv[hh] = load(x0 - R + lx, y0 - R + ly, (more && h < S::NH) ? z + 1 : -1);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      const int yy = y0 + ty + kTW * j, ly = R + ty + kTW * j, lx = R + tx;
+      const C c0 = q[j][R];
+      T hr = diag * c0.x, hi = diag * c0.y;
+#pragma unroll
+      for (int k = 1; k <= R; ++k) {
+        const C a0 = pl[buf][ly][lx + k], a1 = pl[buf][ly][lx - k];
+        const C a2 = pl[buf][ly + k][lx], a3 = pl[buf][ly - k][lx];
+        const C a4 = q[j][R + k], a5 = q[j][R - k];
+        hr += off[k] * (((a0.x + a1.x) + (a2.x + a3.x)) + (a4.x + a5.x));
+        hi += off[k] * (((a0.y + a1.y) + (a2.y + a3.y)) + (a4.y + a5.y));
+      }
+      if (x < nx && yy < ny) {
+        const long long pnt = z * sz + yy * sy + x;
+        stage_tail<T, R>(pnt, pnt, 0, x, yy, z, c0, hr, hi, vv[j], av[j], acc, yout, psi_out, V, fsrc, bsrc,
+                         point_gamma, g, coef, mode);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+#pragma unroll
+      for (int i = 0; i < 2 * R; ++i) q[j][i] = q[j][i + 1];
+      q[j][2 * R] = nxt[j];
+    }
+  }
+}
+
+inline TileGrid make_tile_grid(const Geometry& g, int TY, int tz) {
+  TileGrid tg;
+  tg.ntx = (g.nx + kTX - 1) / kTX;
+  tg.nty = (g.ny + TY - 1) / TY;
+  tg.tz = tz;
+  tg.ntz = (g.nz + tz - 1) / tz;
+  const int n = tg.ntx * tg.nty * tg.ntz;
+  tg.tiles_per_xcd = n % 8 == 0 ? n / 8 : 0;
+  return tg;
+}
+
+__device__ __forceinline__ int xcd_tile(int bid, const TileGrid& tg) {
+  return tg.tiles_per_xcd ? (bid & 7) * tg.tiles_per_xcd + (bid >> 3) : bid;
+}
+
+template <typename T, int R, int J>
+__global__ void __launch_bounds__(kBlock) stage_tiled_kernel(
+    TileGrid tg, const typename cpx<T>::t* __restrict__ yin, typename cpx<T>::t* __restrict__ yout,
+    typename cpx<T>::t* __restrict__ acc, typename cpx<T>::t* __restrict__ psi_out, const T* __restrict__ V,
+    const double2* __restrict__ fsrc, const double2* __restrict__ bsrc, const int* __restrict__ point_gamma,
+    Geometry g, StencilCoef sc, double coef, int mode) {
+  stage_tiled_body<T, R, J>(xcd_tile(blockIdx.x, tg), tg, yin, yout, acc, psi_out, V, fsrc, bsrc, point_gamma, g,
+                            sc, coef, mode);
 }
 
 // ---------------------------------------------------------------------------
@@ -398,6 +591,23 @@ __global__ void __launch_bounds__(kBlock) stage_face_kernel(
   if (blockIdx.x < nsb)
     stage_body<T, R, PER>((long long)blockIdx.x * blockDim.x + threadIdx.x, yin, yout, acc, psi_out, V, fsrc, nullptr,
                           point_gamma, g, sc, coef, mode);
+  else
+    face_body<T, R>((long long)(blockIdx.x - nsb) * blockDim.x + threadIdx.x, gin, gout, facc, aux_out, yin, ker, a,
+                    g, w, coef, mode, 1);
+}
+
+// the same with the tiled stage sweep in the first tg tiles
+template <typename T, int R, int J>
+__global__ void __launch_bounds__(kBlock) stage_face_tiled_kernel(
+    TileGrid tg, const typename cpx<T>::t* __restrict__ yin, typename cpx<T>::t* __restrict__ yout,
+    typename cpx<T>::t* __restrict__ acc, typename cpx<T>::t* __restrict__ psi_out, const T* __restrict__ V,
+    const double2* __restrict__ fsrc, const int* __restrict__ point_gamma, StencilCoef sc,
+    const double2* __restrict__ gin, double2* __restrict__ gout, double2* __restrict__ facc,
+    double2* __restrict__ aux_out, const double2* __restrict__ ker, LocalBlock a, Geometry g, int w, double coef,
+    int mode, unsigned nsb) {
+  if (blockIdx.x < nsb)
+    stage_tiled_body<T, R, J>(xcd_tile(blockIdx.x, tg), tg, yin, yout, acc, psi_out, V, fsrc, nullptr, point_gamma,
+                              g, sc, coef, mode);
   else
     face_body<T, R>((long long)(blockIdx.x - nsb) * blockDim.x + threadIdx.x, gin, gout, facc, aux_out, yin, ker, a,
                     g, w, coef, mode, 1);
@@ -1098,6 +1308,10 @@ hipError_t step_staged_t(const abc_launch& L, const abc_scratch& S, void* psi_v,
   const LocalBlock a = make_local(L.a_loc);
   const long long nel = g.npts * g.batch;
   const long long nface = g.face_off[6];
+  // one orbital, zero outside the box: the tiled sweep
+  const bool tiled = !PER && g.batch == 1 && R >= kTiledMinR;
+  const TileGrid tg = make_tile_grid(g, TileShape<R, kTileJ>::TY, tile_planes(R));
+  const unsigned ntile = (unsigned)(tg.ntx * tg.nty * tg.ntz);
   const bool zeroth = L.order == ABC_ZEROTH;
   // boundary variables with their own recurrence: f (first), f and g (second)
   const bool rec = L.order == ABC_FIRST || L.order == ABC_SECOND;
@@ -1199,11 +1413,18 @@ hipError_t step_staged_t(const abc_launch& L, const abc_scratch& S, void* psi_v,
         if (rec) gcur = gnext;
       }
       C* yout = (k == 4) ? nullptr : (keep ? static_cast<C*>(keep[k - 1]) : y[(k - 1) & 1]);
-      if (merged) {
+      if (merged && tiled) {
+        abc_launch_kernel(tm, kStageLabel[k], stage_face_tiled_kernel<T, R, kTileJ>, dim3(ntile + nblocks(nface)),
+                          dim3(kBlock), st, tg, ycur, yout, acc, psi, Vuse, fsrc, L.point_gamma, sc, fsrc,
+                          merged_gnext, S.facc, aux, L.face_ker, a, g, L.w, coef, mode, ntile);
+      } else if (merged) {
         const unsigned nsb = (unsigned)nblocks(nel);
         abc_launch_kernel(tm, kStageLabel[k], stage_face_kernel<T, R, PER>, dim3(nsb + nblocks(nface)), dim3(kBlock),
                           st, ycur, yout, acc, psi, Vuse, fsrc, L.point_gamma, sc, fsrc, merged_gnext, S.facc, aux,
                           L.face_ker, a, g, L.w, coef, mode, nsb);
+      } else if (tiled) {
+        abc_launch_kernel(tm, kStageLabel[k], stage_tiled_kernel<T, R, kTileJ>, dim3(ntile), dim3(kBlock), st, tg,
+                          ycur, yout, acc, psi, Vuse, fsrc, bsrc, L.point_gamma, g, sc, coef, mode);
       } else {
         abc_launch_kernel(tm, kStageLabel[k], stage_kernel<T, R, PER>, dim3(nblocks(nel)), dim3(kBlock), st, ycur,
                           yout, acc, psi, Vuse, fsrc, bsrc, L.point_gamma, g, sc, coef, mode);
