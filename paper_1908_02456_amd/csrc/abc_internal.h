@@ -102,6 +102,7 @@ struct FaceFFT {
   long long twoff[3][4];       // twiddles per pair: forward / inverse along t2, forward / inverse along t1
   int lg1[3], lg2[3];          // log2 P1, log2 P2
   int twr[3], twc[3];          // lines per workgroup: row passes (along t2), column pass (along t1, R layers)
+  int stwr[3], stwc[3];        // 1: those passes keep their twiddle table in LDS
   double2 *W, *Z, *spec, *tw;
 };
 

@@ -632,8 +632,9 @@ __global__ void __launch_bounds__(kBlock) stage_face_tiled_kernel(
 
 // decimation in time: TW lines of L points ([t][k]) held in bit-reversed
 // order in buf are transformed in place to natural order; tw[k] =
-// exp(+-2 pi i k / L), k < L/2.  Ends with a barrier.
-__device__ __forceinline__ void fft_dit(double2* buf, const double2* __restrict__ tw, int L, int TW) {
+// exp(+-2 pi i k / L), k < L/2 (cj: its conjugate, the opposite sign; tw may
+// sit in LDS or in global memory).  Ends with a barrier.
+__device__ __forceinline__ void fft_dit(double2* buf, const double2* tw, int L, int TW, bool cj = false) {
   const int nb = TW * L / 2;
   for (int len = 2, sh = 1; len <= L; len <<= 1, ++sh) {
     const int half = len >> 1, step = L >> sh;
@@ -641,7 +642,8 @@ __device__ __forceinline__ void fft_dit(double2* buf, const double2* __restrict_
       const int t = bf / (L / 2), r = bf % (L / 2);
       const int grp = r / half, pos = r % half;
       const int i0 = t * L + grp * len + pos, i1 = i0 + half;
-      const double2 w = tw[pos * step];
+      double2 w = tw[pos * step];
+      if (cj) w.y = -w.y;
       const double2 u = buf[i0], v0 = buf[i1];
       const double2 v = make_double2(v0.x * w.x - v0.y * w.y, v0.x * w.y + v0.y * w.x);
       buf[i0] = make_double2(u.x + v.x, u.y + v.y);
@@ -653,7 +655,7 @@ __device__ __forceinline__ void fft_dit(double2* buf, const double2* __restrict_
 
 // decimation in frequency: natural order in, bit-reversed order out (the
 // same transform as fft_dit).  Ends with a barrier.
-__device__ __forceinline__ void fft_dif(double2* buf, const double2* __restrict__ tw, int L, int TW) {
+__device__ __forceinline__ void fft_dif(double2* buf, const double2* tw, int L, int TW, bool cj = false) {
   const int nb = TW * L / 2;
   for (int len = L; len >= 2; len >>= 1) {
     const int half = len >> 1, step = L / len;
@@ -661,7 +663,8 @@ __device__ __forceinline__ void fft_dif(double2* buf, const double2* __restrict_
       const int t = bf / (L / 2), r = bf % (L / 2);
       const int grp = r / half, pos = r % half;
       const int i0 = t * L + grp * len + pos, i1 = i0 + half;
-      const double2 w = tw[pos * step];
+      double2 w = tw[pos * step];
+      if (cj) w.y = -w.y;
       const double2 u = buf[i0], v = buf[i1];
       const double2 d = make_double2(u.x - v.x, u.y - v.y);
       buf[i0] = make_double2(u.x + v.x, u.y + v.y);
@@ -669,6 +672,16 @@ __device__ __forceinline__ void fft_dif(double2* buf, const double2* __restrict_
     }
     __syncthreads();
   }
+}
+
+// the L/2 twiddles of a table copied behind the lines in LDS when the plan
+// left room for them (stw), else read where they are; the caller's barrier
+// after its loads covers the copy
+__device__ __forceinline__ const double2* stage_twiddles(double2* lds, const double2* __restrict__ tw, int L,
+                                                         int stw) {
+  if (!stw) return tw;
+  for (int i = threadIdx.x; i < L / 2; i += blockDim.x) lds[i] = tw[i];
+  return lds;
 }
 
 __device__ __forceinline__ int bit_rev(int k, int logL) {
@@ -712,6 +725,7 @@ __global__ void __launch_bounds__(kBlock) fft_rows_fwd_kernel(const double2* __r
   const int nline = ff.S[q] * n1, ln0 = blockIdx.x * TW;
   if (ln0 >= nline) return;
   const int tot = TW * P2;
+  const double2* tw = stage_twiddles(buf + tot, ff.tw + ff.twoff[q][0], P2, ff.stwr[q]);
   for (int e = threadIdx.x; e < tot; e += blockDim.x) {
     const int t = e >> logL, k = e & (P2 - 1), ln = ln0 + t;
     double2 v = make_double2(0.0, 0.0);
@@ -728,7 +742,7 @@ __global__ void __launch_bounds__(kBlock) fft_rows_fwd_kernel(const double2* __r
     buf[t * P2 + bit_rev(k, logL)] = v;
   }
   __syncthreads();
-  fft_dit(buf, ff.tw + ff.twoff[q][0], P2, TW);
+  fft_dit(buf, tw, P2, TW);
   double2* W = ff.W + ff.woff[q];
   for (int e = threadIdx.x; e < tot; e += blockDim.x) {
     const int t = e >> logL, k = e & (P2 - 1), ln = ln0 + t;
@@ -752,6 +766,8 @@ __global__ void __launch_bounds__(kBlock) fft_cols_kernel(Geometry g, FaceFFT ff
   const int side = sg / B, b = sg % B;
   const int tot = TW * P1;
   const long long slab = (long long)P1 * P2;
+  // forward twiddles along t1; the inverse ones are their conjugates
+  const double2* tw = stage_twiddles(buf + R * tot, ff.tw + ff.twoff[q][2], P1, ff.stwc[q]);
   for (int l = 0; l < R; ++l) {
     const double2* src = ff.W + ff.woff[q] + (long long)((side * R + l) * B + b) * slab + c0;
     for (int e = threadIdx.x; e < tot; e += blockDim.x) {
@@ -760,7 +776,7 @@ __global__ void __launch_bounds__(kBlock) fft_cols_kernel(Geometry g, FaceFFT ff
     }
   }
   __syncthreads();
-  fft_dit(buf, ff.tw + ff.twoff[q][2], P1, R * TW);
+  fft_dit(buf, tw, P1, R * TW);
   // Z(l) = sum_l' spec(l, l') W(l') / (P1 P2), point by point
   const double inv = 1.0 / (double)slab;
   const double2* spec = ff.spec + ff.soff[q];
@@ -780,7 +796,7 @@ __global__ void __launch_bounds__(kBlock) fft_cols_kernel(Geometry g, FaceFFT ff
     }
   }
   __syncthreads();
-  fft_dif(buf, ff.tw + ff.twoff[q][3], P1, R * TW);
+  fft_dif(buf, tw, P1, R * TW, true);
   const int tout = TW * n1;
   for (int l = 0; l < R; ++l) {
     double2* dst = ff.Z + ff.woff[q] + (long long)((side * R + l) * B + b) * slab + c0;
@@ -805,6 +821,7 @@ __global__ void __launch_bounds__(kBlock) fft_rows_inv_kernel(
   if (ln0 >= nline) return;
   const double2* Z = ff.Z + ff.woff[q];
   const int tot = TW * P2;
+  const double2* tw = stage_twiddles(buf + tot, ff.tw + ff.twoff[q][1], P2, ff.stwr[q]);
   for (int e = threadIdx.x; e < tot; e += blockDim.x) {
     const int t = e >> logL, k = e & (P2 - 1), ln = ln0 + t;
     double2 v = make_double2(0.0, 0.0);
@@ -815,7 +832,7 @@ __global__ void __launch_bounds__(kBlock) fft_rows_inv_kernel(
     buf[t * P2 + bit_rev(k, logL)] = v;
   }
   __syncthreads();
-  fft_dit(buf, ff.tw + ff.twoff[q][1], P2, TW);
+  fft_dit(buf, tw, P2, TW);
   const int tout = TW * n2;
   for (int e = threadIdx.x; e < tout; e += blockDim.x) {
     const int t = e / n2, t2 = e - t * n2, ln = ln0 + t;
@@ -897,16 +914,19 @@ hipError_t face_fft_apply(const abc_launch& L, const double2* gin, double2* gout
   const Geometry& g = L.g;
   unsigned nr = 0, nc = 0;
   size_t lr = 0, lc = 0;
+  int br = 64, bc = 64;  // threads: one per butterfly of the widest pair, whole waves, at most kBlock
   for (int q = 0; q < 3; ++q) {
     const int n1 = g.face_n1[2 * q];
+    br = std::max(br, std::min(kBlock, (ff.twr[q] * ff.P2[q] / 2 + 63) / 64 * 64));
+    bc = std::max(bc, std::min(kBlock, (g.R * ff.twc[q] * ff.P1[q] / 2 + 63) / 64 * 64));
     nr = std::max(nr, (unsigned)((ff.S[q] * n1 + ff.twr[q] - 1) / ff.twr[q]));
     nc = std::max(nc, (unsigned)(2 * g.batch * (ff.P2[q] / ff.twc[q])));
-    lr = std::max(lr, (size_t)ff.twr[q] * ff.P2[q] * sizeof(double2));
-    lc = std::max(lc, (size_t)g.R * ff.twc[q] * ff.P1[q] * sizeof(double2));
+    lr = std::max(lr, (size_t)(ff.twr[q] * ff.P2[q] + (ff.stwr[q] ? ff.P2[q] / 2 : 0)) * sizeof(double2));
+    lc = std::max(lc, (size_t)(g.R * ff.twc[q] * ff.P1[q] + (ff.stwc[q] ? ff.P1[q] / 2 : 0)) * sizeof(double2));
   }
-  fft_rows_fwd_kernel<T><<<dim3(nr, 3), kBlock, lr, st>>>(gin, yin, first, g, ff);
-  fft_cols_kernel<<<dim3(nc, 3), kBlock, lc, st>>>(g, ff);
-  abc_launch_kernel_lds(tm, label, fft_rows_inv_kernel<T, R>, dim3(nr, 3), dim3(kBlock), lr, st, gin, gout, facc,
+  fft_rows_fwd_kernel<T><<<dim3(nr, 3), br, lr, st>>>(gin, yin, first, g, ff);
+  fft_cols_kernel<<<dim3(nc, 3), bc, lc, st>>>(g, ff);
+  abc_launch_kernel_lds(tm, label, fft_rows_inv_kernel<T, R>, dim3(nr, 3), dim3(br), lr, st, gin, gout, facc,
                         aux_out, yin, a, g, ff, coef, mode, first);
   return hipGetLastError();
 }
@@ -1519,10 +1539,13 @@ abc_status face_fft_setup(const Geometry& g, int R, int w, const std::vector<abc
     ff.lg1[q] = ilog2(P1);
     ff.lg2[q] = ilog2(P2);
     ff.twr[q] = fft_lines_per_group(P2, ff.S[q] * n1, 1);
-    int twc = fft_lines_per_group(P1, P2, 4);
+    int twc = fft_lines_per_group(P1, P2, 2);
     while (twc > 1 && R * twc * P1 > 4096) twc >>= 1;
     if (R * twc * P1 > 4096) { err = "face too large for the FFT face path at this stencil radius"; return ABC_ENOTSUP; }
     ff.twc[q] = twc;
+    // twiddles in LDS behind the lines where the 64 KB allow
+    ff.stwr[q] = ff.twr[q] * P2 + P2 / 2 <= 4096;
+    ff.stwc[q] = R * twc * P1 + P1 / 2 <= 4096;
     ff.woff[q] = woff;
     woff += (long long)ff.S[q] * P1 * P2;
     ff.soff[q] = soff;
