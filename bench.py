@@ -50,12 +50,12 @@ def large_box_reference(Solver, torch, wl, dtype, path, steps_total):
     psi_b = torch.zeros((big, big, big), dtype=cdt, device="cuda")
     psi_b[off:off + n, off:off + n, off:off + n] = torch.from_numpy(wl.psi0).to(cdt)
     Vb = torch.from_numpy(W.gaussian_well((big,) * 3, wl.h, 5.0)).to(rdt).cuda()
-    sb = Solver((big,) * 3, wl.h, wl.dt, order="dirichlet", dtype=dtype, path=path)
+    sb = Solver((big,) * 3, wl.h, wl.dt, radius=wl.radius, order="dirichlet", dtype=dtype, path=path)
     sb.step(psi_b, None, Vb, steps_total)
     return psi_b[off:off + n, off:off + n, off:off + n].to(torch.complex128).clone()
 
 
-def physics_error(Solver, torch, wl, dtype, window, path, steps_total):
+def physics_error(Solver, torch, wl, dtype, window, path, steps_total, fejer=True):
     """Relative L2 error at T of the absorbing run vs the doubled Dirichlet box,
     both started from the same box-only data (zero outside the small box)."""
     n = wl.n
@@ -63,13 +63,14 @@ def physics_error(Solver, torch, wl, dtype, window, path, steps_total):
     cdt = torch.complex128 if dtype == "c128" else torch.complex64
     rdt = torch.float64 if dtype == "c128" else torch.float32
     ref = large_box_reference(Solver, torch, wl, dtype, path, steps_total)
-    s = Solver((n,) * 3, wl.h, wl.dt, order="first", s1=wl.s1, window=window, dtype=dtype, path=path)
+    s = Solver((n,) * 3, wl.h, wl.dt, radius=wl.radius, order="first", s1=wl.s1, window=window, fejer=fejer,
+               dtype=dtype, path=path)
     psi = torch.from_numpy(wl.psi0).to(cdt).cuda()
     aux = s.new_aux()
     V = torch.from_numpy(wl.V).to(rdt).cuda()
     s.step(psi, aux, V, steps_total)
     # the same box with zero boundary values (what the condition replaces)
-    sd = Solver((n,) * 3, wl.h, wl.dt, order="dirichlet", dtype=dtype, path=path)
+    sd = Solver((n,) * 3, wl.h, wl.dt, radius=wl.radius, order="dirichlet", dtype=dtype, path=path)
     psid = torch.from_numpy(wl.psi0).to(cdt).cuda()
     sd.step(psid, None, V, steps_total)
     torch.cuda.synchronize()
@@ -465,7 +466,7 @@ def bench_paper_replica(Solver, torch, W, steps=600, every=50, big=97):
     return out
 
 
-def cpu_baseline(wl, window, budget_s=15.0):
+def cpu_baseline(wl, window, budget_s=15.0, fejer=True):
     """FP64 oracle (NumPy, single-threaded elementwise) on the same workload,
     for as many whole steps as fit in about budget_s seconds."""
     try:
@@ -473,7 +474,8 @@ def cpu_baseline(wl, window, budget_s=15.0):
     except Exception:  # pragma: no cover
         threadpool_limits = None
     from oracle import integrate
-    st = integrate.make_setup((wl.n,) * 3, wl.h, wl.dt, wl.radius, "first", s1=wl.s1, window=window)
+    st = integrate.make_setup((wl.n,) * 3, wl.h, wl.dt, wl.radius, "first", s1=wl.s1, window=window,
+                              use_window=fejer)
     psi, aux = wl.psi0.copy(), integrate.zero_aux(st)
     ctx = threadpool_limits(1) if threadpool_limits else None
     if ctx:
@@ -510,6 +512,9 @@ def main():
     ap.add_argument("--dtype", default="c128", choices=["c128", "c64"])
     ap.add_argument("--n", type=int, default=128)
     ap.add_argument("--window", type=int, default=0)
+    ap.add_argument("--radius", type=int, default=1, choices=[1, 2, 3], help="stencil half-width R")
+    ap.add_argument("--no-fejer", action="store_true",
+                    help="face kernels truncated without the triangular taper (w >= n - 1: exact sections)")
     ap.add_argument("--path", default="auto", choices=["auto", "staged", "fused"])
     ap.add_argument("--no-physics", action="store_true")
     ap.add_argument("--replica", action="store_true",
@@ -528,12 +533,14 @@ def main():
     from paper_1908_02456_amd import workloads as W
     from paper_1908_02456_amd.solver import Solver
 
-    wl = W.well_packet(n=args.n, window=args.window)
+    wl = W.well_packet(n=args.n, window=args.window, radius=args.radius)
     cdt = torch.complex128 if args.dtype == "c128" else torch.complex64
     rdt = torch.float64 if args.dtype == "c128" else torch.float32
-    log("setup: %d^3 first-order faces w=%d %s path=%s" % (wl.n, args.window, args.dtype, args.path))
-    s = Solver((wl.n,) * 3, wl.h, wl.dt, order="first", s1=wl.s1, window=args.window, dtype=args.dtype,
-               path=args.path)
+    log("setup: %d^3 first-order faces R=%d w=%d%s %s path=%s" % (wl.n, wl.radius, args.window,
+                                                              " (no taper)" if args.no_fejer else "",
+                                                              args.dtype, args.path))
+    s = Solver((wl.n,) * 3, wl.h, wl.dt, radius=wl.radius, order="first", s1=wl.s1, window=args.window,
+               fejer=not args.no_fejer, dtype=args.dtype, path=args.path)
     psi = torch.from_numpy(wl.psi0).to(cdt).cuda().contiguous()
     V = torch.from_numpy(wl.V).to(rdt).cuda().contiguous()
     aux = s.new_aux()
@@ -586,7 +593,7 @@ def main():
            "config": {"workload": "single orbital %d^3, h=%.2g, dt=%.3g, first-order face-form DtN ABC "
                                   "(s1=%.3g, w=%d), Gaussian well + k=(3,1,0) packet, %s"
                                   % (wl.n, wl.h, wl.dt, wl.s1, args.window, args.dtype),
-                      "grid": [wl.n] * 3, "radius": wl.radius, "path": args.path},
+                      "grid": [wl.n] * 3, "radius": wl.radius, "fejer": not args.no_fejer, "path": args.path},
            "roofline": roof}
     if args.copy_gib > 0:
         nb = int(args.copy_gib * (1 << 30)) // 16 * 16
@@ -625,10 +632,11 @@ def main():
         out["paper_replica"] = bench_paper_replica(Solver, torch, W)
     if not args.no_physics:
         log("physics run: %d steps vs %d^3 zero-boundary box" % (wl.steps, 2 * wl.n))
-        out["physics"] = physics_error(Solver, torch, wl, args.dtype, args.window, args.path, wl.steps)
+        out["physics"] = physics_error(Solver, torch, wl, args.dtype, args.window, args.path, wl.steps,
+                                       fejer=not args.no_fejer)
     if not args.no_cpu:
         log("cpu baseline (oracle) ...")
-        out["cpu_baseline"] = cpu_baseline(wl, args.window)
+        out["cpu_baseline"] = cpu_baseline(wl, args.window, fejer=not args.no_fejer)
     print(json.dumps(out), flush=True)
 
 

@@ -634,13 +634,14 @@ __global__ void __launch_bounds__(kBlock) stage_face_tiled_kernel(
 // order in buf are transformed in place to natural order; tw[k] =
 // exp(+-2 pi i k / L), k < L/2 (cj: its conjugate, the opposite sign; tw may
 // sit in LDS or in global memory).  Ends with a barrier.
-__device__ __forceinline__ void fft_dit(double2* buf, const double2* tw, int L, int TW, bool cj = false) {
+__device__ __forceinline__ void fft_dit(double2* buf, const double2* tw, int L, int logL, int TW, bool cj = false) {
   const int nb = TW * L / 2;
   for (int len = 2, sh = 1; len <= L; len <<= 1, ++sh) {
     const int half = len >> 1, step = L >> sh;
     for (int bf = threadIdx.x; bf < nb; bf += blockDim.x) {
-      const int t = bf / (L / 2), r = bf % (L / 2);
-      const int grp = r / half, pos = r % half;
+      // L, len and half are powers of two: shifts and masks
+      const int t = bf >> (logL - 1), r = bf & ((L >> 1) - 1);
+      const int grp = r >> (sh - 1), pos = r & (half - 1);
       const int i0 = t * L + grp * len + pos, i1 = i0 + half;
       double2 w = tw[pos * step];
       if (cj) w.y = -w.y;
@@ -655,13 +656,13 @@ __device__ __forceinline__ void fft_dit(double2* buf, const double2* tw, int L, 
 
 // decimation in frequency: natural order in, bit-reversed order out (the
 // same transform as fft_dit).  Ends with a barrier.
-__device__ __forceinline__ void fft_dif(double2* buf, const double2* tw, int L, int TW, bool cj = false) {
+__device__ __forceinline__ void fft_dif(double2* buf, const double2* tw, int L, int logL, int TW, bool cj = false) {
   const int nb = TW * L / 2;
-  for (int len = L; len >= 2; len >>= 1) {
-    const int half = len >> 1, step = L / len;
+  for (int len = L, sh = logL; len >= 2; len >>= 1, --sh) {
+    const int half = len >> 1, step = L >> sh;
     for (int bf = threadIdx.x; bf < nb; bf += blockDim.x) {
-      const int t = bf / (L / 2), r = bf % (L / 2);
-      const int grp = r / half, pos = r % half;
+      const int t = bf >> (logL - 1), r = bf & ((L >> 1) - 1);
+      const int grp = r >> (sh - 1), pos = r & (half - 1);
       const int i0 = t * L + grp * len + pos, i1 = i0 + half;
       double2 w = tw[pos * step];
       if (cj) w.y = -w.y;
@@ -705,7 +706,7 @@ __global__ void __launch_bounds__(kBlock) fft_lines_kernel(double2* __restrict__
     buf[t * L + bit_rev(k, logL)] = a[base + t * tstride + k * kstride];
   }
   __syncthreads();
-  fft_dit(buf, tw, L, TW);
+  fft_dit(buf, tw, L, logL, TW);
   for (int e = threadIdx.x; e < tot; e += blockDim.x) {
     const int t = kfast ? e / L : e % TW;
     const int k = kfast ? e % L : e / TW;
@@ -742,7 +743,7 @@ __global__ void __launch_bounds__(kBlock) fft_rows_fwd_kernel(const double2* __r
     buf[t * P2 + bit_rev(k, logL)] = v;
   }
   __syncthreads();
-  fft_dit(buf, tw, P2, TW);
+  fft_dit(buf, tw, P2, logL, TW);
   double2* W = ff.W + ff.woff[q];
   for (int e = threadIdx.x; e < tot; e += blockDim.x) {
     const int t = e >> logL, k = e & (P2 - 1), ln = ln0 + t;
@@ -761,6 +762,7 @@ __global__ void __launch_bounds__(kBlock) fft_cols_kernel(Geometry g, FaceFFT ff
   const int n1 = g.face_n1[2 * q], R = g.R, B = g.batch;
   const int P1 = ff.P1[q], P2 = ff.P2[q], logL = ff.lg1[q], TW = ff.twc[q];
   const int per = P2 / TW;
+  const int lgTW = __ffs(TW) - 1;  // TW is a power of two
   if ((int)blockIdx.x >= 2 * B * per) return;
   const int sg = blockIdx.x / per, c0 = (blockIdx.x % per) * TW;
   const int side = sg / B, b = sg % B;
@@ -771,17 +773,17 @@ __global__ void __launch_bounds__(kBlock) fft_cols_kernel(Geometry g, FaceFFT ff
   for (int l = 0; l < R; ++l) {
     const double2* src = ff.W + ff.woff[q] + (long long)((side * R + l) * B + b) * slab + c0;
     for (int e = threadIdx.x; e < tot; e += blockDim.x) {
-      const int t = e % TW, k = e / TW;
+      const int t = e & (TW - 1), k = e >> lgTW;
       buf[l * tot + t * P1 + bit_rev(k, logL)] = k < n1 ? src[(long long)k * P2 + t] : make_double2(0.0, 0.0);
     }
   }
   __syncthreads();
-  fft_dit(buf, tw, P1, R * TW);
+  fft_dit(buf, tw, P1, logL, R * TW);
   // Z(l) = sum_l' spec(l, l') W(l') / (P1 P2), point by point
   const double inv = 1.0 / (double)slab;
   const double2* spec = ff.spec + ff.soff[q];
   for (int e = threadIdx.x; e < tot; e += blockDim.x) {
-    const int t = e % TW, k = e / TW;
+    const int t = e & (TW - 1), k = e >> lgTW;
     const long long m = (long long)k * P2 + c0 + t;
     double2 x[abc::kMaxR];
     for (int lp = 0; lp < R; ++lp) x[lp] = buf[lp * tot + t * P1 + k];
@@ -796,12 +798,12 @@ __global__ void __launch_bounds__(kBlock) fft_cols_kernel(Geometry g, FaceFFT ff
     }
   }
   __syncthreads();
-  fft_dif(buf, tw, P1, R * TW, true);
+  fft_dif(buf, tw, P1, logL, R * TW, true);
   const int tout = TW * n1;
   for (int l = 0; l < R; ++l) {
     double2* dst = ff.Z + ff.woff[q] + (long long)((side * R + l) * B + b) * slab + c0;
     for (int e = threadIdx.x; e < tout; e += blockDim.x) {
-      const int t = e % TW, k = e / TW;
+      const int t = e & (TW - 1), k = e >> lgTW;
       dst[(long long)k * P2 + t] = buf[l * tot + t * P1 + bit_rev(k, logL)];
     }
   }
@@ -832,7 +834,7 @@ __global__ void __launch_bounds__(kBlock) fft_rows_inv_kernel(
     buf[t * P2 + bit_rev(k, logL)] = v;
   }
   __syncthreads();
-  fft_dit(buf, tw, P2, TW);
+  fft_dit(buf, tw, P2, logL, TW);
   const int tout = TW * n2;
   for (int e = threadIdx.x; e < tout; e += blockDim.x) {
     const int t = e / n2, t2 = e - t * n2, ln = ln0 + t;
