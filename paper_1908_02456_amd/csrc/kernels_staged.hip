@@ -161,11 +161,22 @@ __device__ __forceinline__ void stage_body(
   using C = typename cpx<T>::t;
   const int B = g.batch;
   if (e >= g.npts * B) return;
-  const long long p = e / B;
-  const int b = (int)(e - p * B);
-  const int x = (int)(p % g.nx);
-  const int y = (int)((p / g.nx) % g.ny);
-  const int z = (int)(p / ((long long)g.nx * g.ny));
+  long long p;
+  int b, x, y, z;
+  if (g.npts * B <= 0x7fffffffLL) {  // 32-bit index arithmetic (64-bit division is a long software routine)
+    const unsigned ue = (unsigned)e, up = ue / (unsigned)B, r = up / (unsigned)g.nx;
+    p = up;
+    b = (int)(ue - up * (unsigned)B);
+    x = (int)(up - r * (unsigned)g.nx);
+    z = (int)(r / (unsigned)g.ny);
+    y = (int)(r - (unsigned)z * (unsigned)g.ny);
+  } else {
+    p = e / B;
+    b = (int)(e - p * B);
+    x = (int)(p % g.nx);
+    y = (int)((p / g.nx) % g.ny);
+    z = (int)(p / ((long long)g.nx * g.ny));
+  }
   const C c0 = yin[e];
   T hr = T(sc.diag) * c0.x, hi = T(sc.diag) * c0.y;
   const long long sx = B, sy = (long long)g.nx * B, sz = (long long)g.nx * g.ny * B;
