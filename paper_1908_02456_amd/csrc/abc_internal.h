@@ -206,9 +206,13 @@ void abc_launch_kernel_lds(abc_timer* tm, const char* label, void (*k)(P...), di
 
 // keep (optional): three psi-sized buffers that receive the stage vectors
 // z_1, z_2, z_3 of the (last) step instead of the scratch ping-pong.
+// psi_in, aux_in (optional): the first step reads its state from these
+// instead of psi and aux, which receive the result; the inputs are left as
+// they were (a step out of place, without a copy).
 hipError_t launch_step_staged(const abc_launch& L, const abc_scratch& S, void* psi, double2* aux,
                               const void* V, int n_steps, hipStream_t st, abc_timer* tm = nullptr,
-                              void* const* keep = nullptr);
+                              void* const* keep = nullptr, const void* psi_in = nullptr,
+                              const double2* aux_in = nullptr);
 // Discrete adjoint (adjoint.hip).  La is L with the adjoint operators
 // (dt -> -dt, conjugate-transposed boundary operators, rescaled aux).
 struct abc_adjoint_args {

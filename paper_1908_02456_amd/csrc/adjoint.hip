@@ -250,31 +250,34 @@ abc_status run_adjoint(const abc_launch& L, const abc_launch& La, const abc_scra
   if (nf) ABC_TRY(hipMemsetAsync(mu, 0, nf * sizeof(double2), st));
   const long long npl = (long long)np;
   const unsigned gb = (unsigned)((np + kBlock - 1) / kBlock);
-  // backward over segments
+  // backward over segments; lambda alternates between lam and y0, so the
+  // value before each adjoint step stays where the V gradient reads it
+  double2* lcur = lam;
+  double2* lnext = y0;
   for (int c = nck - 1; c >= 0; --c) {
     const int s0 = c * stride, len = std::min(stride, N - s0);
     // recompute the segment, keeping each step's state and stage vectors
     ABC_TRY(hipMemcpyAsync(seg[0], ckp[c], pb, hipMemcpyDeviceToDevice, st));
     if (nf) ABC_TRY(hipMemcpyAsync(segf[0], ckf[c], nf * sizeof(double2), hipMemcpyDeviceToDevice, st));
     for (int i = 0; i < len; ++i) {
+      // one step from seg[i] (and segf[i]) into the next slot, out of place
       double2* next = i + 1 < len ? seg[i + 1] : X;
       double2* nextf = i + 1 < len ? segf[i + 1] : fX;
-      ABC_TRY(hipMemcpyAsync(next, seg[i], pb, hipMemcpyDeviceToDevice, st));
-      if (nf) ABC_TRY(hipMemcpyAsync(nextf, segf[i], nf * sizeof(double2), hipMemcpyDeviceToDevice, st));
-      ABC_TRY(launch_step_staged(L, S, next, nf ? nextf : nullptr, V, 1, st, nullptr, &kz[3 * (size_t)i]));
+      ABC_TRY(launch_step_staged(L, S, next, nf ? nextf : nullptr, V, 1, st, nullptr, &kz[3 * (size_t)i], seg[i],
+                                 nf ? segf[i] : nullptr));
     }
     for (int i = len - 1; i >= 0; --i) {
-      // adjoint step, keeping its stage vectors
-      ABC_TRY(hipMemcpyAsync(y0, lam, pb, hipMemcpyDeviceToDevice, st));
-      ABC_TRY(launch_step_staged(La, S, lam, nf ? mu : nullptr, V, 1, st, nullptr, ky));
-      vgrad_kernel<<<gb, kBlock, 0, st>>>(a.grad_V, y0, static_cast<double2*>(ky[0]), static_cast<double2*>(ky[1]),
+      // adjoint step from lcur into lnext (mu in place), keeping its stage vectors
+      ABC_TRY(launch_step_staged(La, S, lnext, nf ? mu : nullptr, V, 1, st, nullptr, ky, lcur));
+      vgrad_kernel<<<gb, kBlock, 0, st>>>(a.grad_V, lcur, static_cast<double2*>(ky[0]), static_cast<double2*>(ky[1]),
                                           static_cast<double2*>(ky[2]), seg[i], static_cast<double2*>(kz[3 * i]),
                                           static_cast<double2*>(kz[3 * i + 1]), static_cast<double2*>(kz[3 * i + 2]),
                                           npl, L.dt);
       ABC_TRY(hipGetLastError());
+      std::swap(lcur, lnext);
     }
   }
-  ABC_TRY(hipMemcpyAsync(a.grad_psi0, lam, pb, hipMemcpyDeviceToDevice, st));
+  ABC_TRY(hipMemcpyAsync(a.grad_psi0, lcur, pb, hipMemcpyDeviceToDevice, st));
   ABC_TRY(hipMemcpyAsync(a.J_host, Jd, sizeof(double), hipMemcpyDeviceToHost, st));
   ABC_TRY(hipStreamSynchronize(st));
 #undef ABC_TRY

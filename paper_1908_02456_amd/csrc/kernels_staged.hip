@@ -1328,7 +1328,8 @@ inline unsigned nblocks(long long n) { return (unsigned)((n + kBlock - 1) / kBlo
 
 template <typename T, int R, bool PER>
 hipError_t step_staged_t(const abc_launch& L, const abc_scratch& S, void* psi_v, double2* aux,
-                         const void* V_v, int n_steps, hipStream_t st, abc_timer* tm, void* const* keep) {
+                         const void* V_v, int n_steps, hipStream_t st, abc_timer* tm, void* const* keep,
+                         const void* psi_in, const double2* aux_in) {
   static const char* kStageLabel[5] = {"", "stage_1", "stage_2", "stage_3", "stage_4"};
   static const char* kBoundLabel[5] = {"", "boundary_1", "boundary_2", "boundary_3", "boundary_4"};
   using C = typename cpx<T>::t;
@@ -1350,18 +1351,20 @@ hipError_t step_staged_t(const abc_launch& L, const abc_scratch& S, void* psi_v,
   const bool rec = L.order == ABC_FIRST || L.order == ABC_SECOND;
   const bool box = L.form == ABC_FORM_BOX;
   for (int s = 0; s < n_steps; ++s) {
+    // this step's input state (the first step may read it from elsewhere)
+    const C* pin = (s == 0 && psi_in) ? static_cast<const C*>(psi_in) : psi;
     const T* Vuse = V;
     if (L.meanfield == ABC_MF_SKYRME) {
-      const hipError_t e = skyrme_veff(*L.pot, psi, false, g.batch, sizeof(T) == 4, V, S.veff, L.t0, L.t3, st, tm);
+      const hipError_t e = skyrme_veff(*L.pot, pin, false, g.batch, sizeof(T) == 4, V, S.veff, L.t0, L.t3, st, tm);
       if (e != hipSuccess) return e;
       Vuse = static_cast<const T*>(S.veff);
     } else if (L.meanfield) {
-      abc_launch_kernel(tm, "meanfield", meanfield_kernel<T>, dim3(nblocks(g.npts)), dim3(kBlock), st,
-                        (const C*)psi, V, static_cast<T*>(S.veff), g.npts, g.batch, T(L.t0), T(L.t3));
+      abc_launch_kernel(tm, "meanfield", meanfield_kernel<T>, dim3(nblocks(g.npts)), dim3(kBlock), st, pin, V,
+                        static_cast<T*>(S.veff), g.npts, g.batch, T(L.t0), T(L.t3));
       Vuse = static_cast<const T*>(S.veff);
     }
-    const C* ycur = psi;
-    const double2* gcur = aux;  // g_0 = f
+    const C* ycur = pin;
+    const double2* gcur = (s == 0 && aux_in) ? aux_in : aux;  // g_0 = f
     for (int k = 1; k <= 4; ++k) {
       const double coef = L.dt / k;
       const int mode = k == 1 ? 0 : (k == 4 ? 2 : 1);
@@ -1495,12 +1498,13 @@ hipError_t diag_t(const abc_launch& L, const abc_scratch& S, const void* psi, co
 
 template <typename T>
 hipError_t dispatch_step(const abc_launch& L, const abc_scratch& S, void* psi, double2* aux, const void* V,
-                         int n, hipStream_t st, abc_timer* tm, void* const* keep) {
+                         int n, hipStream_t st, abc_timer* tm, void* const* keep, const void* pin,
+                         const double2* ain) {
   const bool per = L.periodic != 0;
   switch (L.g.R) {
-    case 1: return per ? step_staged_t<T, 1, true>(L, S, psi, aux, V, n, st, tm, keep) : step_staged_t<T, 1, false>(L, S, psi, aux, V, n, st, tm, keep);
-    case 2: return per ? step_staged_t<T, 2, true>(L, S, psi, aux, V, n, st, tm, keep) : step_staged_t<T, 2, false>(L, S, psi, aux, V, n, st, tm, keep);
-    case 3: return per ? step_staged_t<T, 3, true>(L, S, psi, aux, V, n, st, tm, keep) : step_staged_t<T, 3, false>(L, S, psi, aux, V, n, st, tm, keep);
+    case 1: return per ? step_staged_t<T, 1, true>(L, S, psi, aux, V, n, st, tm, keep, pin, ain) : step_staged_t<T, 1, false>(L, S, psi, aux, V, n, st, tm, keep, pin, ain);
+    case 2: return per ? step_staged_t<T, 2, true>(L, S, psi, aux, V, n, st, tm, keep, pin, ain) : step_staged_t<T, 2, false>(L, S, psi, aux, V, n, st, tm, keep, pin, ain);
+    case 3: return per ? step_staged_t<T, 3, true>(L, S, psi, aux, V, n, st, tm, keep, pin, ain) : step_staged_t<T, 3, false>(L, S, psi, aux, V, n, st, tm, keep, pin, ain);
   }
   return hipErrorInvalidValue;
 }
@@ -1520,9 +1524,10 @@ hipError_t dispatch_diag(const abc_launch& L, const abc_scratch& S, const void* 
 }  // namespace
 
 hipError_t launch_step_staged(const abc_launch& L, const abc_scratch& S, void* psi, double2* aux, const void* V,
-                              int n_steps, hipStream_t st, abc_timer* tm, void* const* keep) {
-  if (L.dtype == ABC_C64) return dispatch_step<float>(L, S, psi, aux, V, n_steps, st, tm, keep);
-  return dispatch_step<double>(L, S, psi, aux, V, n_steps, st, tm, keep);
+                              int n_steps, hipStream_t st, abc_timer* tm, void* const* keep, const void* psi_in,
+                              const double2* aux_in) {
+  if (L.dtype == ABC_C64) return dispatch_step<float>(L, S, psi, aux, V, n_steps, st, tm, keep, psi_in, aux_in);
+  return dispatch_step<double>(L, S, psi, aux, V, n_steps, st, tm, keep, psi_in, aux_in);
 }
 
 hipError_t launch_diagnostics(const abc_launch& L, const abc_scratch& S, const void* psi, const double2* aux,
