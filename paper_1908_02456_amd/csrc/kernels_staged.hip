@@ -90,18 +90,19 @@ __global__ void __launch_bounds__(kBlock) meanfield_kernel(const typename cpx<T>
 
 // ---------------------------------------------------------------------------
 // box sweep of one stage
-// mode 0: y_out = y_new                             (stage 1, y_in = psi)
-// mode 3: acc = psi + y_in + y_new, y_out = y_new   (stage 2; psi read from
-//         `state`: stage 1 leaves the running sum to it, saving a write)
-// mode 1: acc += y_new,             y_out = y_new   (stage 3)
-// mode 2: state = acc + y_new                       (stage 4: the new psi)
+// The running Taylor sum psi + z_1 + z_2 + z_3 + z_4 is formed by stages 2
+// and 4 from their own input (z_1, z_3) and the sum so far, in the order of
+// a running sum, so stages 1 and 3 only write their z:
+// mode 0: y_out = y_new                                (stages 1, 3)
+// mode 1: acc = (state + y_in) + y_new, y_out = y_new  (stage 2; state = psi)
+// mode 2: state = (acc + y_in) + y_new                 (stage 4: the new psi)
 // The face kernels keep their own modes 0 (stage 1), 1 (stages 2, 3) and 2.
 // ---------------------------------------------------------------------------
 // the rest of a stage at point p (orbital b, element e) once the stencil sum
 // (hr, hi) is formed: potential, boundary source, -i coef, and the mode's
 // accumulator update
-// (vv = V[p] when V is given, av = acc[e] in modes 1 and 2 and state[e] in
-// mode 3: loaded by the caller, so that a sweep can issue them early)
+// (vv = V[p] when V is given, av = state[e] in mode 1 and acc[e] in mode 2:
+// loaded by the caller, so that a sweep can issue them early)
 template <typename T, int R>
 __device__ __forceinline__ void stage_tail(long long e, long long p, int b, int x, int y, int z,
                                            const typename cpx<T>::t c0, T hr, T hi, T vv, typename cpx<T>::t av,
@@ -135,24 +136,15 @@ __device__ __forceinline__ void stage_tail(long long e, long long p, int b, int 
   C yn;
   yn.x = cf * hi;
   yn.y = -cf * hr;
+  C a;
+  a.x = (av.x + c0.x) + yn.x;
+  a.y = (av.y + c0.y) + yn.y;
   if (mode == 0) {
     yout[e] = yn;
-  } else if (mode == 3) {
-    C a;
-    a.x = (av.x + c0.x) + yn.x;  // (psi + y_1) + y_2, the order of a running sum
-    a.y = (av.y + c0.y) + yn.y;
-    acc[e] = a;
-    yout[e] = yn;
   } else if (mode == 1) {
-    C a = av;
-    a.x += yn.x;
-    a.y += yn.y;
     acc[e] = a;
     yout[e] = yn;
   } else {
-    C a = av;
-    a.x += yn.x;
-    a.y += yn.y;
     state[e] = a;
   }
 }
@@ -212,8 +204,8 @@ __device__ __forceinline__ void stage_body(
   C av;
   av.x = 0;
   av.y = 0;
-  if (mode == 3) av = state[e];
-  else if (mode != 0) av = acc[e];
+  if (mode == 1) av = state[e];
+  else if (mode == 2) av = acc[e];
   stage_tail<T, R>(e, p, b, x, y, z, c0, hr, hi, V ? V[p] : T(0), av, acc, yout, state, V, fsrc, bsrc, point_gamma,
                    g, coef, mode);
 }
@@ -333,7 +325,7 @@ __device__ __forceinline__ void stage_tiled_body(
       vv[j] = (V && in) ? V[pnt] : T(0);
       av[j].x = 0;
       av[j].y = 0;
-      if (mode != 0 && in) av[j] = mode == 3 ? state[pnt] : acc[pnt];
+      if (mode != 0 && in) av[j] = mode == 1 ? state[pnt] : acc[pnt];
     }
     C nxt[J];
     const bool more = z + 1 < z1;
@@ -604,13 +596,13 @@ __global__ void __launch_bounds__(kBlock) stage_face_kernel(
     const T* __restrict__ V, const double2* __restrict__ fsrc, const int* __restrict__ point_gamma,
     StencilCoef sc, const double2* __restrict__ gin, double2* __restrict__ gout, double2* __restrict__ facc,
     double2* __restrict__ aux_out, const double2* __restrict__ ker, LocalBlock a, Geometry g, int w, double coef,
-    int mode, unsigned nsb) {
+    int mode, int fmode, unsigned nsb) {
   if (blockIdx.x < nsb)
     stage_body<T, R, PER>((long long)blockIdx.x * blockDim.x + threadIdx.x, yin, yout, acc, state, V, fsrc, nullptr,
                           point_gamma, g, sc, coef, mode);
   else
     face_body<T, R>((long long)(blockIdx.x - nsb) * blockDim.x + threadIdx.x, gin, gout, facc, aux_out, yin, ker, a,
-                    g, w, coef, mode == 3 ? 1 : mode, 1);  // stage mode 3 is face mode 1
+                    g, w, coef, fmode, 1);
 }
 
 // the same with the tiled stage sweep in the first tg tiles
@@ -621,13 +613,13 @@ __global__ void __launch_bounds__(kBlock) stage_face_tiled_kernel(
     const double2* __restrict__ fsrc, const int* __restrict__ point_gamma, StencilCoef sc,
     const double2* __restrict__ gin, double2* __restrict__ gout, double2* __restrict__ facc,
     double2* __restrict__ aux_out, const double2* __restrict__ ker, LocalBlock a, Geometry g, int w, double coef,
-    int mode, unsigned nsb) {
+    int mode, int fmode, unsigned nsb) {
   if (blockIdx.x < nsb)
     stage_tiled_body<T, R, J>(xcd_tile(blockIdx.x, tg), tg, yin, yout, acc, state, V, fsrc, nullptr, point_gamma,
                               g, sc, coef, mode);
   else
     face_body<T, R>((long long)(blockIdx.x - nsb) * blockDim.x + threadIdx.x, gin, gout, facc, aux_out, yin, ker, a,
-                    g, w, coef, mode == 3 ? 1 : mode, 1);  // stage mode 3 is face mode 1
+                    g, w, coef, fmode, 1);
 }
 
 // ---------------------------------------------------------------------------
@@ -1455,19 +1447,20 @@ hipError_t step_staged_t(const abc_launch& L, const abc_scratch& S, void* psi_v,
         if (rec) gcur = gnext;
       }
       C* yout = (k == 4) ? nullptr : (keep ? static_cast<C*>(keep[k - 1]) : y[(k - 1) & 1]);
-      // the stage sweep's own mode: stage 2 forms the running sum from the
-      // step's input state (read through `state`), stage 4 writes the new one
-      const int smode = k == 2 ? 3 : mode;
+      // the stage sweep's own mode (the face work keeps `mode`): stage 2
+      // starts the running sum from the step's input state, read through
+      // `state`; stage 4 finishes it into the new state
+      const int smode = k == 2 ? 1 : (k == 4 ? 2 : 0);
       C* state = k == 2 ? const_cast<C*>(pin) : psi;
       if (merged && tiled) {
         abc_launch_kernel(tm, kStageLabel[k], stage_face_tiled_kernel<T, R, kTileJ>, dim3(ntile + nblocks(nface)),
                           dim3(kBlock), st, tg, ycur, yout, acc, state, Vuse, fsrc, L.point_gamma, sc, fsrc,
-                          merged_gnext, S.facc, aux, L.face_ker, a, g, L.w, coef, smode, ntile);
+                          merged_gnext, S.facc, aux, L.face_ker, a, g, L.w, coef, smode, mode, ntile);
       } else if (merged) {
         const unsigned nsb = (unsigned)nblocks(nel);
         abc_launch_kernel(tm, kStageLabel[k], stage_face_kernel<T, R, PER>, dim3(nsb + nblocks(nface)), dim3(kBlock),
                           st, ycur, yout, acc, state, Vuse, fsrc, L.point_gamma, sc, fsrc, merged_gnext, S.facc, aux,
-                          L.face_ker, a, g, L.w, coef, smode, nsb);
+                          L.face_ker, a, g, L.w, coef, smode, mode, nsb);
       } else if (tiled) {
         abc_launch_kernel(tm, kStageLabel[k], stage_tiled_kernel<T, R, kTileJ>, dim3(ntile), dim3(kBlock), st, tg,
                           ycur, yout, acc, state, Vuse, fsrc, bsrc, L.point_gamma, g, sc, coef, smode);
