@@ -100,8 +100,12 @@ def alg_bytes(label, n, R, csz, rsz, first=True):
         return npts * (2 * csz + rsz) + (faces * 32 if first else 0)
     if label == "fused2_half_b":                    # read u2, psi, V, both aux; write psi', f'
         return npts * (3 * csz + rsz) + (faces * 48 if first else 0)
-    if label.startswith("stage_"):                  # y in, acc, psi/base, V, y out
+    if label in ("stage_1", "stage_3"):             # y in, V; z out
+        return npts * (2 * csz + rsz)
+    if label == "stage_2":                          # y in, psi, V; running sum and z out
         return npts * (4 * csz + rsz)
+    if label == "stage_4":                          # y in, running sum, V; psi' out
+        return npts * (3 * csz + rsz)
     if label.startswith("boundary_"):
         return faces * (16 * 3 + csz)
     return None
