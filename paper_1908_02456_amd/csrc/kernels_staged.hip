@@ -639,23 +639,49 @@ __global__ void __launch_bounds__(kBlock) stage_face_tiled_kernel(
 //            then the face_kernel epilogue on t2 < n2.
 // ---------------------------------------------------------------------------
 
-// decimation in time: TW lines of L points ([t][k]) held in bit-reversed
-// order in buf are transformed in place to natural order; tw[k] =
-// exp(+-2 pi i k / L), k < L/2 (cj: its conjugate, the opposite sign; tw may
-// sit in LDS or in global memory).  Ends with a barrier.
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+__device__ __forceinline__ double2 twiddle(const double2* tw, int k, bool cj) {
+  double2 w = tw[k];
+  if (cj) w.y = -w.y;
+  return w;
+}
+
+// decimation in time: TW lines of L = 2^logL points ([t][k]) held in
+// bit-reversed order in buf are transformed in place to natural order; tw[k]
+// = exp(+-2 pi i k / L), k < L/2 (cj: its conjugate, the opposite sign; tw
+// may sit in LDS or in global memory).  Two radix-2 stages per pass: each
+// thread takes four points i + {0, 1, 2, 3} h of a 4h block through stage
+// sh (span 2h) and stage sh + 1 (span 4h), so a pass is one LDS round trip
+// and one barrier; an odd logL leaves one radix-2 stage.  L, the spans and h
+// are powers of two: shifts and masks.  Ends with a barrier.
 __device__ __forceinline__ void fft_dit(double2* buf, const double2* tw, int L, int logL, int TW, bool cj = false) {
-  const int nb = TW * L / 2;
-  for (int len = 2, sh = 1; len <= L; len <<= 1, ++sh) {
-    const int half = len >> 1, step = L >> sh;
+  int sh = 1;
+  for (; sh + 1 <= logL; sh += 2) {
+    const int h = 1 << (sh - 1), s1 = L >> sh, s2 = L >> (sh + 1), nq = TW * L / 4;
+    for (int q = threadIdx.x; q < nq; q += blockDim.x) {
+      const int t = q >> (logL - 2), r = q & ((L >> 2) - 1);
+      const int pos = r & (h - 1), i = t * L + ((r >> (sh - 1)) << (sh + 1)) + pos;
+      const double2 w1 = twiddle(tw, pos * s1, cj);
+      const double2 a = buf[i], b = cmul(buf[i + h], w1), c = buf[i + 2 * h], d = cmul(buf[i + 3 * h], w1);
+      const double2 a1 = make_double2(a.x + b.x, a.y + b.y), b1 = make_double2(a.x - b.x, a.y - b.y);
+      const double2 c1 = cmul(make_double2(c.x + d.x, c.y + d.y), twiddle(tw, pos * s2, cj));
+      const double2 d1 = cmul(make_double2(c.x - d.x, c.y - d.y), twiddle(tw, (pos + h) * s2, cj));
+      buf[i] = make_double2(a1.x + c1.x, a1.y + c1.y);
+      buf[i + 2 * h] = make_double2(a1.x - c1.x, a1.y - c1.y);
+      buf[i + h] = make_double2(b1.x + d1.x, b1.y + d1.y);
+      buf[i + 3 * h] = make_double2(b1.x - d1.x, b1.y - d1.y);
+    }
+    __syncthreads();
+  }
+  if (sh == logL) {  // the last stage, span L
+    const int half = L >> 1, nb = TW * L / 2;
     for (int bf = threadIdx.x; bf < nb; bf += blockDim.x) {
-      // L, len and half are powers of two: shifts and masks
-      const int t = bf >> (logL - 1), r = bf & ((L >> 1) - 1);
-      const int grp = r >> (sh - 1), pos = r & (half - 1);
-      const int i0 = t * L + grp * len + pos, i1 = i0 + half;
-      double2 w = tw[pos * step];
-      if (cj) w.y = -w.y;
-      const double2 u = buf[i0], v0 = buf[i1];
-      const double2 v = make_double2(v0.x * w.x - v0.y * w.y, v0.x * w.y + v0.y * w.x);
+      const int t = bf >> (logL - 1), pos = bf & (half - 1);
+      const int i0 = t * L + pos, i1 = i0 + half;
+      const double2 u = buf[i0], v = cmul(buf[i1], twiddle(tw, pos, cj));
       buf[i0] = make_double2(u.x + v.x, u.y + v.y);
       buf[i1] = make_double2(u.x - v.x, u.y - v.y);
     }
@@ -664,21 +690,35 @@ __device__ __forceinline__ void fft_dit(double2* buf, const double2* tw, int L, 
 }
 
 // decimation in frequency: natural order in, bit-reversed order out (the
-// same transform as fft_dit).  Ends with a barrier.
+// same transform as fft_dit).  Two stages per pass, spans 4h then 2h; an odd
+// logL leaves the span-2 stage, whose twiddle is 1.  Ends with a barrier.
 __device__ __forceinline__ void fft_dif(double2* buf, const double2* tw, int L, int logL, int TW, bool cj = false) {
-  const int nb = TW * L / 2;
-  for (int len = L, sh = logL; len >= 2; len >>= 1, --sh) {
-    const int half = len >> 1, step = L >> sh;
+  int sh = logL;
+  for (; sh - 1 >= 1; sh -= 2) {
+    const int h = 1 << (sh - 2), s1 = L >> sh, s2 = L >> (sh - 1), nq = TW * L / 4;
+    for (int q = threadIdx.x; q < nq; q += blockDim.x) {
+      const int t = q >> (logL - 2), r = q & ((L >> 2) - 1);
+      const int pos = r & (h - 1), i = t * L + ((r >> (sh - 2)) << sh) + pos;
+      const double2 a = buf[i], b = buf[i + h], c = buf[i + 2 * h], d = buf[i + 3 * h];
+      const double2 a1 = make_double2(a.x + c.x, a.y + c.y);
+      const double2 c1 = cmul(make_double2(a.x - c.x, a.y - c.y), twiddle(tw, pos * s1, cj));
+      const double2 b1 = make_double2(b.x + d.x, b.y + d.y);
+      const double2 d1 = cmul(make_double2(b.x - d.x, b.y - d.y), twiddle(tw, (pos + h) * s1, cj));
+      const double2 w2 = twiddle(tw, pos * s2, cj);
+      buf[i] = make_double2(a1.x + b1.x, a1.y + b1.y);
+      buf[i + h] = cmul(make_double2(a1.x - b1.x, a1.y - b1.y), w2);
+      buf[i + 2 * h] = make_double2(c1.x + d1.x, c1.y + d1.y);
+      buf[i + 3 * h] = cmul(make_double2(c1.x - d1.x, c1.y - d1.y), w2);
+    }
+    __syncthreads();
+  }
+  if (sh == 1) {  // span 2
+    const int nb = TW * L / 2;
     for (int bf = threadIdx.x; bf < nb; bf += blockDim.x) {
-      const int t = bf >> (logL - 1), r = bf & ((L >> 1) - 1);
-      const int grp = r >> (sh - 1), pos = r & (half - 1);
-      const int i0 = t * L + grp * len + pos, i1 = i0 + half;
-      double2 w = tw[pos * step];
-      if (cj) w.y = -w.y;
+      const int i0 = 2 * bf, i1 = i0 + 1;
       const double2 u = buf[i0], v = buf[i1];
-      const double2 d = make_double2(u.x - v.x, u.y - v.y);
       buf[i0] = make_double2(u.x + v.x, u.y + v.y);
-      buf[i1] = make_double2(d.x * w.x - d.y * w.y, d.x * w.y + d.y * w.x);
+      buf[i1] = make_double2(u.x - v.x, u.y - v.y);
     }
     __syncthreads();
   }
@@ -925,7 +965,11 @@ hipError_t face_fft_apply(const abc_launch& L, const double2* gin, double2* gout
   const Geometry& g = L.g;
   unsigned nr = 0, nc = 0;
   size_t lr = 0, lc = 0;
-  int br = 64, bc = 64;  // threads: one per butterfly of the widest pair, whole waves, at most kBlock
+  // threads: one per two points of the widest pair, whole waves, at most
+  // kBlock (the four-point passes leave half of them idle, but the extra
+  // waves hide more latency than the smaller blocks save: 204 against 215 us
+  // per step at 128^3)
+  int br = 64, bc = 64;
   for (int q = 0; q < 3; ++q) {
     const int n1 = g.face_n1[2 * q];
     br = std::max(br, std::min(kBlock, (ff.twr[q] * ff.P2[q] / 2 + 63) / 64 * 64));
