@@ -232,10 +232,10 @@ __global__ void __launch_bounds__(kBlock) stage_kernel(
 constexpr int kTX = 64, kTW = kBlock / 64;
 // one row per thread; planes per tile by radius (measured at 128^3, us per
 // step: R = 3 136 with 16 planes against 142 with 8 and 193 with 32; R = 2
-// 117 with 8 against 122 with 16; two rows per thread 143 and 129).  R = 1
-// keeps the untiled sweep (174.6 tiled against 167.7 at w = 8).
+// 117 with 8 against 122 with 16; two rows per thread 143 and 129; R = 1,
+// w = 8: 136 with 8 planes, 157 with 16, 159 untiled).
 constexpr int kTileJ = 1;
-constexpr int kTiledMinR = 2;
+constexpr int kTiledMinR = 1;
 constexpr int tile_planes(int R) { return R >= 3 ? 16 : 8; }
 
 struct TileGrid {

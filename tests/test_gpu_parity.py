@@ -114,14 +114,16 @@ def test_windowed_faces_several_tiles_parity(shape, R, order, window):
         assert r["aux_err"] < TOL64, r["aux_err"]
 
 
-@pytest.mark.parametrize("shape,R", [((35, 9, 70), 3), ((19, 7, 66), 2), ((17, 8, 64), 3)])
+@pytest.mark.parametrize("shape,R", [((35, 9, 70), 3), ((19, 7, 66), 2), ((17, 8, 64), 3), ((19, 9, 70), 1),
+                                     ((9, 5, 130), 1)])
 @pytest.mark.parametrize("order,window,dtype", [("dirichlet", 0, "c128"), ("zeroth", 0, "c128"),
                                                 ("first", 0, "c128"), ("first", 2, "c128"), ("first", 0, "c64")])
 def test_tiled_sweep_parity(shape, R, order, window, dtype):
-    # R >= 2, one orbital: the z-marching LDS-tiled stage sweep, with several
-    # 64-column tiles in x, ragged row tiles in y and ragged plane chunks in z
-    # (16 planes at R = 3, 8 at R = 2); first order at w = 0 runs it merged
-    # with the face work, the others as a launch of its own
+    # one orbital on the staged path: the z-marching LDS-tiled stage sweep,
+    # with several 64-column tiles in x, ragged row tiles in y and ragged
+    # plane chunks in z (16 planes at R = 3, 8 at R = 1, 2); first order at
+    # w = 0 runs it merged with the face work, the others as a launch of its
+    # own
     r = _run_pair("tiled-sweep", shape, 0.25, 0.004, R, order, 3, s0=1.5, s1=1.5, window=window, dtype=dtype)
     tol = TOL64 if dtype == "c128" else TOL32
     assert r["err"] < tol, r["err"]
