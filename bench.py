@@ -529,8 +529,8 @@ def main():
                     help="also run one plain device copy of this size (calibrates rocprofv3 byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path (see DESIGN.md for how the "
-              "stepper would shard); run with --gpus 1", file=sys.stderr)
+        print("bench.py runs on one GPU only: the stepper has no multi-GPU path; run with --gpus 1",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch
