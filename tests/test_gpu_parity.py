@@ -150,6 +150,18 @@ def test_batch_meanfield_parity():
     assert r["err"] < TOL64 and r["aux_err"] < TOL64, (r["err"], r["aux_err"])
 
 
+@pytest.mark.parametrize("R,window,dtype", [(2, 2, "c128"), (1, 3, "c128"), (3, 0, "c64")])
+def test_single_orbital_meanfield_tiled_sweep_parity(R, window, dtype):
+    # one orbital with the t0/t3 mean field on the staged path: the tiled
+    # sweep reads the potential rebuilt from the current state every step
+    r = _run_pair("meanfield-tiled", (13, 9, 70), 0.3, 0.004, R, "first", 4, s1=1.0, window=window,
+                  meanfield=(-1.0, 0.5), dtype=dtype, path="staged")
+    tol = TOL64 if dtype == "c128" else TOL32
+    assert r["err"] < tol, r["err"]
+    if dtype == "c128":
+        assert r["aux_err"] < TOL64, r["aux_err"]
+
+
 @pytest.mark.parametrize("order,window", [("first", 0), ("first", 2), ("zeroth", 1), ("dirichlet", 0)])
 def test_fp32_path_parity(order, window):
     r = _run_pair("c64", (12, 11, 10), 0.25, 0.004, 1, order, 8, s0=1.0, s1=1.0, window=window, dtype="c64")
