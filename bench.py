@@ -37,32 +37,32 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def large_box_reference(Solver, torch, wl, dtype, path, steps_total):
+def large_box_reference(Solver, torch, wl, path, steps_total):
     """The doubled zero-boundary box run from the zero-extended data, cut back
-    to the small box (complex128)."""
+    to the small box.  Always complex128 with a float64 potential, whatever
+    precision the run it is compared with uses."""
     n = wl.n
     big = 2 * n
     off = (big - n) // 2
-    cdt = torch.complex128 if dtype == "c128" else torch.complex64
-    rdt = torch.float64 if dtype == "c128" else torch.float32
     from paper_1908_02456_amd import workloads as W
     # zero-extended initial data; the well is evaluated on the big grid
-    psi_b = torch.zeros((big, big, big), dtype=cdt, device="cuda")
-    psi_b[off:off + n, off:off + n, off:off + n] = torch.from_numpy(wl.psi0).to(cdt)
-    Vb = torch.from_numpy(W.gaussian_well((big,) * 3, wl.h, 5.0)).to(rdt).cuda()
-    sb = Solver((big,) * 3, wl.h, wl.dt, radius=wl.radius, order="dirichlet", dtype=dtype, path=path)
+    psi_b = torch.zeros((big, big, big), dtype=torch.complex128, device="cuda")
+    psi_b[off:off + n, off:off + n, off:off + n] = torch.from_numpy(wl.psi0)
+    Vb = torch.from_numpy(W.gaussian_well((big,) * 3, wl.h, 5.0)).cuda()
+    sb = Solver((big,) * 3, wl.h, wl.dt, radius=wl.radius, order="dirichlet", dtype="c128", path=path)
     sb.step(psi_b, None, Vb, steps_total)
-    return psi_b[off:off + n, off:off + n, off:off + n].to(torch.complex128).clone()
+    return psi_b[off:off + n, off:off + n, off:off + n].clone()
 
 
 def physics_error(Solver, torch, wl, dtype, window, path, steps_total, fejer=True):
-    """Relative L2 error at T of the absorbing run vs the doubled Dirichlet box,
-    both started from the same box-only data (zero outside the small box)."""
+    """Relative L2 error at T of the absorbing run vs the doubled Dirichlet box
+    (complex128), both started from the same box-only data (zero outside the
+    small box)."""
     n = wl.n
     big = 2 * n
     cdt = torch.complex128 if dtype == "c128" else torch.complex64
     rdt = torch.float64 if dtype == "c128" else torch.float32
-    ref = large_box_reference(Solver, torch, wl, dtype, path, steps_total)
+    ref = large_box_reference(Solver, torch, wl, path, steps_total)
     s = Solver((n,) * 3, wl.h, wl.dt, radius=wl.radius, order="first", s1=wl.s1, window=window, fejer=fejer,
                dtype=dtype, path=path)
     psi = torch.from_numpy(wl.psi0).to(cdt).cuda()
@@ -79,7 +79,8 @@ def physics_error(Solver, torch, wl, dtype, window, path, steps_total, fejer=Tru
     e_dir = torch.linalg.vector_norm(psid.to(torch.complex128) - ref).item() / nr
     h3 = wl.h ** 3
     return {"err_vs_large_box": e_abc, "err_dirichlet_same_box": e_dir, "large_box_n": big,
-            "T": steps_total * wl.dt, "norm_abc": h3 * float(torch.sum(torch.abs(psi.to(torch.complex128)) ** 2)),
+            "large_box_dtype": "c128", "T": steps_total * wl.dt,
+            "norm_abc": h3 * float(torch.sum(torch.abs(psi.to(torch.complex128)) ** 2)),
             "norm_large_box_in_box": h3 * nr * nr, "norm_initial": h3 * float(np.sum(np.abs(wl.psi0) ** 2))}
 
 
@@ -89,13 +90,40 @@ def shell_counts(n, R):
     return n ** 3 - inner, 6 * R * n * n
 
 
-def alg_bytes(label, n, R, csz, rsz, first=True):
-    """Algorithmic bytes of one launch of the step at n^3 (what the launch must
-    read and write once: state csz, potential rsz, FP64 face aux 16 B)."""
-    npts = n ** 3
-    _, faces = shell_counts(n, R)
+def method_bytes_per_update(n, R, csz, rsz, first=True):
+    """Algorithmic bytes of one grid-point update (one point advanced one full
+    step, all four stages and the condition): the state read and written once
+    (2 csz), the potential read once (rsz) and, for the first order, the FP64
+    face aux read and written once (32 B per face entry, 6 R n^2 entries over
+    n^3 points)."""
+    b = 2 * csz + rsz
+    if first:
+        b += 32.0 * 6 * R / n
+    return b
+
+
+def launch_step_share(label):
+    """Fraction of one step's grid-point updates a launch performs: a launch
+    of the one-pass sweep carries the whole step, a two-stage half one half, a
+    stage of the staged sweep one quarter.  Face-only launches update no grid
+    points (None)."""
     if label == "fused_step":
-        return npts * (2 * csz + rsz)               # read psi, V; write psi'
+        return 1.0
+    if label.startswith("fused2_half"):
+        return 0.5
+    if label.startswith("stage_"):
+        return 0.25
+    return None
+
+
+def launch_io_bytes(label, n, R, csz, rsz, first=True):
+    """Bytes a launch itself reads and writes once at n^3 (state csz,
+    potential rsz, FP64 face aux 16 B): the implementation's own traffic,
+    which counts the intermediate stage arrays the method does not need."""
+    npts = n ** 3
+    faces = 6 * R * n * n
+    if label == "fused_step":
+        return npts * (2 * csz + rsz) + (faces * 32 if first else 0)
     if label == "fused2_half_a":                    # read psi, V, f; write u2 and its aux
         return npts * (2 * csz + rsz) + (faces * 32 if first else 0)
     if label == "fused2_half_b":                    # read u2, psi, V, both aux; write psi', f'
@@ -109,6 +137,32 @@ def alg_bytes(label, n, R, csz, rsz, first=True):
     if label.startswith("boundary_"):
         return faces * (16 * 3 + csz)
     return None
+
+
+def roofline(table, n, R, csz, rsz, ms_step, traffic, first=True):
+    """Roofline of the dominant grid sweep: its algorithmic bytes (the method's
+    bytes per update times the updates the launch performs) over its average
+    duration, against the 8 TB/s HBM peak.  impl_frac prices the same launch
+    at its own I/O instead; traffic_ratio is the counted HBM bytes over the
+    algorithmic bytes."""
+    b_upd = method_bytes_per_update(n, R, csz, rsz, first)
+    sweeps = [r for r in table if launch_step_share(r["launch"]) is not None and r["ms"] > 0]
+    dom = max(sweeps or table, key=lambda r: r["ms"])
+    share = launch_step_share(dom["launch"])
+    alg = b_upd * n ** 3 * share if share else None
+    achieved = alg / (dom["ms"] / 1e3) / 1e9 if alg else None
+    io = launch_io_bytes(dom["launch"], n, R, csz, rsz, first)
+    step_alg = b_upd * n ** 3
+    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS if achieved else None,
+            "traffic": traffic, "kernel": dom["launch"], "alg_bytes_per_update": b_upd,
+            "step_share_per_launch": share, "alg_bytes_per_launch": alg, "avg_launch_ms": dom["ms"],
+            "impl_bytes_per_launch": io,
+            "impl_frac": (io / (dom["ms"] / 1e3) / 1e9 / HBM_PEAK_GBS) if io else None,
+            "traffic_ratio": (traffic / alg) if (traffic and alg) else None,
+            "step_alg_bytes": step_alg,
+            "step_frac": step_alg / (ms_step / 1e3) / 1e9 / HBM_PEAK_GBS,
+            "launches": table}
 
 
 def measured_traffic(label, args):
@@ -147,21 +201,31 @@ def _time(torch, fn, stream=None):
     return e0.elapsed_time(e1)
 
 
-def bench_c64(Solver, torch, wl, steps, psi_ref):
-    """The same workload with the complex64 stencil (FP64 aux), and its
-    deviation from the complex128 run after the same steps."""
-    s = Solver((wl.n,) * 3, wl.h, wl.dt, order="first", s1=wl.s1, window=wl.window, dtype="c64")
+def bench_c64(Solver, torch, wl, args, steps):
+    """The headline workload with the complex64 stencil (FP64 aux), built from
+    the same arguments as the headline (radius, window, taper, path): time per
+    step, and its relative deviation from the complex128 run of the same
+    problem after the workload's full step count."""
+    kw = dict(radius=wl.radius, order="first", s1=wl.s1, window=args.window, fejer=not args.no_fejer,
+              path=args.path)
+    s = Solver((wl.n,) * 3, wl.h, wl.dt, dtype="c64", **kw)
+    V32 = torch.from_numpy(wl.V).to(torch.float32).cuda()
     psi = torch.from_numpy(wl.psi0).to(torch.complex64).cuda()
-    V = torch.from_numpy(wl.V).to(torch.float32).cuda()
     aux = s.new_aux()
-    s.step(psi, aux, V, 20)
-    ms = _time(torch, lambda: s.step(psi, aux, V, steps))
+    s.step(psi, aux, V32, 20)
+    ms = _time(torch, lambda: s.step(psi, aux, V32, steps))
     psi = torch.from_numpy(wl.psi0).to(torch.complex64).cuda()
     aux = s.new_aux()
-    s.step(psi, aux, V, 20 + steps)
-    d = (psi.to(torch.complex128) - psi_ref).abs().max().item() / psi_ref.abs().max().item()
+    s.step(psi, aux, V32, wl.steps)
+    s128 = Solver((wl.n,) * 3, wl.h, wl.dt, dtype="c128", **kw)
+    ref = torch.from_numpy(wl.psi0).cuda()
+    s128.step(ref, s128.new_aux(), torch.from_numpy(wl.V).cuda(), wl.steps)
+    torch.cuda.synchronize()
+    d = psi.to(torch.complex128) - ref
     return {"ms_per_step": ms / steps, "value": wl.n ** 3 * steps / (ms / 1e3), "unit": "grid-point-updates/s",
-            "rel_dev_from_c128_after_steps": d, "steps": 20 + steps}
+            "rel_err_vs_c128_max": d.abs().max().item() / ref.abs().max().item(),
+            "rel_err_vs_c128_l2": torch.linalg.vector_norm(d).item() / torch.linalg.vector_norm(ref).item(),
+            "compared_after_steps": wl.steps}
 
 
 def bench_batch(Batch, Solver, torch, W, steps=20):
@@ -215,20 +279,33 @@ def bench_adjoint(Solver, torch, W):
             "adjoint_over_forward": ms_adj / ms_fwd, "forward_path": "fused" if s.use_fused else "staged"}
 
 
-def bench_tdhf(Solver, torch, W, steps=10):
+def bench_tdhf(Solver, torch, W, steps=10, full_steps=1000):
     """32 oscillator orbitals on 96^3 with the mean field U = -rho + 0.5 rho^2,
-    first-order condition, complex64 stencil / FP64 aux (orbitals as boxes of
-    one fused launch, the mean field rebuilt every step)."""
+    first-order condition, complex64 stencil / FP64 aux: time per step, and
+    the relative deviation of the orbitals from the complex128 run of the same
+    batch after the workload's 1000 steps."""
     n, nb, h = 96, 32, 0.2
     orb = W.oscillator_orbitals((n,) * 3, h, nb, seed=3)
-    s = Solver((n,) * 3, h, 0.002, order="first", s1=1.0, window=0, dtype="c64", batch=nb, meanfield=(-1.0, 0.5))
+    kw = dict(order="first", s1=1.0, window=0, batch=nb, meanfield=(-1.0, 0.5))
+    s = Solver((n,) * 3, h, 0.002, dtype="c64", **kw)
     psi = torch.from_numpy(orb).to(torch.complex64).cuda().contiguous()
     aux = s.new_aux()
     s.step(psi, aux, None, 2)
     ms = _time(torch, lambda: s.step(psi, aux, None, steps))
-    return {"grid": n, "orbitals": nb, "steps": steps, "ms_per_step": ms / steps,
-            "value": n ** 3 * nb * steps / (ms / 1e3), "unit": "orbital-point-updates/s",
-            "path": "fused orbital batch" if s.use_fused else "staged"}
+    out = {"grid": n, "orbitals": nb, "steps": steps, "ms_per_step": ms / steps,
+           "value": n ** 3 * nb * steps / (ms / 1e3), "unit": "orbital-point-updates/s",
+           "path": "fused orbital batch" if s.use_fused else "staged"}
+    psi = torch.from_numpy(orb).to(torch.complex64).cuda().contiguous()
+    aux = s.new_aux()
+    s.step(psi, aux, None, full_steps)
+    s128 = Solver((n,) * 3, h, 0.002, dtype="c128", **kw)
+    ref = torch.from_numpy(orb).cuda().contiguous()
+    ms128 = _time(torch, lambda: s128.step(ref, s128.new_aux(), None, full_steps))
+    d = psi.to(torch.complex128) - ref
+    out.update({"rel_err_vs_c128_max": d.abs().max().item() / ref.abs().max().item(),
+                "rel_err_vs_c128_l2": torch.linalg.vector_norm(d).item() / torch.linalg.vector_norm(ref).item(),
+                "compared_after_steps": full_steps, "c128_ms_per_step": ms128 / full_steps})
+    return out
 
 
 def bench_tdhf_skyrme(Solver, torch, W, steps=10):
@@ -367,7 +444,7 @@ def bench_h2_point(Solver, torch, wl, modes=64, nodes=4096):
     gpu_s = (time.perf_counter() - t0) / len(pts)
     out = {"modes": modes, "nodes": nodes, "gpu_s_per_point": gpu_s,
            "gpu_integrand_evals_per_s": modes * modes * nodes / gpu_s}
-    ref = large_box_reference(Solver, torch, wl, "c128", "auto", wl.steps)
+    ref = large_box_reference(Solver, torch, wl, "auto", wl.steps)
     nr = torch.linalg.vector_norm(ref).item()
     V = torch.from_numpy(wl.V).cuda()
     for w in (0, 8):
@@ -390,7 +467,7 @@ def bench_face_windows(Solver, torch, wl, steps_timed=20):
     w = 8 with the Fejer window (staged, direct convolution) and the exact
     section w = n - 1 (staged, zero-padded 2D FFTs): time per step and the
     relative error against the large zero-boundary box after 2000 steps."""
-    ref = large_box_reference(Solver, torch, wl, "c128", "auto", wl.steps)
+    ref = large_box_reference(Solver, torch, wl, "auto", wl.steps)
     nr = torch.linalg.vector_norm(ref).item()
     V = torch.from_numpy(wl.V).cuda()
     out = {}
@@ -472,7 +549,8 @@ def bench_paper_replica(Solver, torch, W, steps=600, every=50, big=97):
 
 def cpu_baseline(wl, window, budget_s=15.0, fejer=True):
     """FP64 oracle (NumPy, single-threaded elementwise) on the same workload,
-    for as many whole steps as fit in about budget_s seconds."""
+    for as many whole steps as fit in about budget_s seconds.  Returns the
+    record and the oracle's state after those steps."""
     try:
         from threadpoolctl import threadpool_limits
     except Exception:  # pragma: no cover
@@ -501,11 +579,68 @@ def cpu_baseline(wl, window, budget_s=15.0, fejer=True):
     finally:
         if ctx:
             ctx.__exit__(None, None, None)
-    return {"value": wl.n ** 3 * steps / el, "unit": "grid-point-updates/s", "cores": 1, "kind": "oracle",
-            "sample": "%d Taylor steps of the same %d^3 first-order face-form workload (FP64 NumPy, %.1f s)"
-                      % (steps, wl.n, el),
-            "h2_objective": {"s_per_point": h2_s, "integrand_evals_per_s": 32 * 32 * 1024 / h2_s,
-                             "sample": "one candidate, 32 x 32 modes x 1024 nodes"}}
+    rec = {"value": wl.n ** 3 * steps / el, "unit": "grid-point-updates/s", "cores": 1, "kind": "oracle",
+           "sample": "%d Taylor steps of the same %d^3 first-order face-form workload (FP64 NumPy, %.1f s)"
+                     % (steps, wl.n, el),
+           "h2_objective": {"s_per_point": h2_s, "integrand_evals_per_s": 32 * 32 * 1024 / h2_s,
+                            "sample": "one candidate, 32 x 32 modes x 1024 nodes"}}
+    return rec, psi, steps
+
+
+def errors_vs_oracle(Solver, torch, wl, args, psi_oracle, steps):
+    """Relative error of the device runs in both precisions against the
+    oracle's state after the same steps of the headline problem (the oracle's
+    sample above)."""
+    kw = dict(radius=wl.radius, order="first", s1=wl.s1, window=args.window, fejer=not args.no_fejer,
+              path=args.path)
+    ref = torch.from_numpy(psi_oracle)
+    out = {"steps": steps}
+    for dt_name, cdt, rdt in (("c128", torch.complex128, torch.float64), ("c64", torch.complex64, torch.float32)):
+        s = Solver((wl.n,) * 3, wl.h, wl.dt, dtype=dt_name, **kw)
+        psi = torch.from_numpy(wl.psi0).to(cdt).cuda()
+        s.step(psi, s.new_aux(), torch.from_numpy(wl.V).to(rdt).cuda(), steps)
+        torch.cuda.synchronize()
+        d = psi.cpu().to(torch.complex128) - ref
+        out[dt_name] = {"rel_err_max": d.abs().max().item() / ref.abs().max().item(),
+                        "rel_err_l2": torch.linalg.vector_norm(d).item() / torch.linalg.vector_norm(ref).item()}
+    return out
+
+
+def tdhf_oracle_sample(Solver, torch, W, steps=1):
+    """The TDHF batch (96^3, 32 orbitals, t0/t3 mean field, first order) in the
+    oracle for one step (about 17 s on one core): its time per step, and the complex64
+    device run's relative error against it after the same steps."""
+    try:
+        from threadpoolctl import threadpool_limits
+    except Exception:  # pragma: no cover
+        threadpool_limits = None
+    from oracle import integrate
+    n, nb, h, dt = 96, 32, 0.2, 0.002
+    orb = W.oscillator_orbitals((n,) * 3, h, nb, seed=3)
+    st = integrate.make_setup((n,) * 3, h, dt, 1, "first", s1=1.0, window=0, t0=-1.0, t3=0.5)
+    V0 = np.zeros((n,) * 3)
+    ctx = threadpool_limits(1) if threadpool_limits else None
+    if ctx:
+        ctx.__enter__()
+    try:
+        t0 = time.perf_counter()
+        psi, aux = orb.copy(), integrate.zero_aux(st, nb)
+        for _ in range(steps):
+            psi, aux = integrate.taylor4_step(st, psi, aux, V0)
+        el = time.perf_counter() - t0
+    finally:
+        if ctx:
+            ctx.__exit__(None, None, None)
+    s = Solver((n,) * 3, h, dt, order="first", s1=1.0, window=0, dtype="c64", batch=nb, meanfield=(-1.0, 0.5))
+    g = torch.from_numpy(orb).to(torch.complex64).cuda().contiguous()
+    s.step(g, s.new_aux(), None, steps)
+    torch.cuda.synchronize()
+    ref = torch.from_numpy(psi)
+    d = g.cpu().to(torch.complex128) - ref
+    return {"steps": steps, "oracle_s_per_step": el / steps,
+            "oracle_orbital_point_updates_per_s": n ** 3 * nb * steps / el, "cores": 1,
+            "c64_rel_err_max": d.abs().max().item() / ref.abs().max().item(),
+            "c64_rel_err_l2": torch.linalg.vector_norm(d).item() / torch.linalg.vector_norm(ref).item()}
 
 
 def main():
@@ -573,21 +708,14 @@ def main():
     rsz = 8 if args.dtype == "c128" else 4
     table = []
     for label, lms in per_launch:
-        b = alg_bytes(label, wl.n, wl.radius, csz, rsz)
-        table.append({"launch": label, "ms": lms, "alg_bytes": b,
-                      "GB/s": (b / (lms / 1e3) / 1e9) if (b and lms > 0) else None})
-    dom = max(table, key=lambda r: r["ms"])
+        b = launch_io_bytes(label, wl.n, wl.radius, csz, rsz)
+        table.append({"launch": label, "ms": lms, "impl_bytes": b,
+                      "impl_GB/s": (b / (lms / 1e3) / 1e9) if (b and lms > 0) else None})
     log("launches per step: " + ", ".join("%s %.2f us" % (r["launch"], r["ms"] * 1e3) for r in table))
-    achieved = dom["GB/s"]
-    roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
-            "traffic": measured_traffic(dom["launch"], args), "kernel": dom["launch"],
-            "alg_bytes_per_launch": dom["alg_bytes"], "avg_launch_ms": dom["ms"],
-            "launches": table}
-    # the method's own bytes per update (state in/out, V, FP64 face aux in/out)
-    step_bytes = npts * (2 * csz + rsz) + 6 * wl.radius * wl.n * wl.n * 32
-    roof["step_alg_bytes"] = step_bytes
-    roof["step_frac"] = step_bytes / (ms_step / 1e3) / 1e9 / HBM_PEAK_GBS
+    sweeps = [r["launch"] for r in table if launch_step_share(r["launch"]) is not None]
+    dom_label = max((r for r in table if r["launch"] in sweeps), key=lambda r: r["ms"])["launch"] if sweeps else None
+    roof = roofline(table, wl.n, wl.radius, csz, rsz, ms_step,
+                    measured_traffic(dom_label, args) if dom_label else None)
 
     out = {"metric": "grid-point-updates/s incl. ABC (% HBM roofline); err vs FP64 large-box oracle",
            "value": value, "unit": "grid-point-updates/s", "n_gpus": 1, "steps": args.steps,
@@ -611,9 +739,7 @@ def main():
     if not args.no_extra:
         from paper_1908_02456_amd.solver import Batch
         extra = {}
-        psi_ref = torch.from_numpy(wl.psi0).cuda()
-        s.step(psi_ref, s.new_aux(), torch.from_numpy(wl.V).cuda(), 220) if args.dtype == "c128" else None
-        for name, fn in (("c64", lambda: bench_c64(Solver, torch, wl, 200, psi_ref)),
+        for name, fn in (("c64", lambda: bench_c64(Solver, torch, wl, args, 200)),
                          ("batch", lambda: bench_batch(Batch, Solver, torch, W)),
                          ("adjoint", lambda: bench_adjoint(Solver, torch, W)),
                          ("tdhf", lambda: bench_tdhf(Solver, torch, W)),
@@ -640,7 +766,12 @@ def main():
                                        fejer=not args.no_fejer)
     if not args.no_cpu:
         log("cpu baseline (oracle) ...")
-        out["cpu_baseline"] = cpu_baseline(wl, args.window, fejer=not args.no_fejer)
+        cb, psi_or, k = cpu_baseline(wl, args.window, fejer=not args.no_fejer)
+        cb["errors_vs_oracle"] = errors_vs_oracle(Solver, torch, wl, args, psi_or, k)
+        if not args.no_extra:
+            log("cpu baseline: TDHF oracle sample ...")
+            cb["tdhf_sample"] = tdhf_oracle_sample(Solver, torch, W)
+        out["cpu_baseline"] = cb
     print(json.dumps(out), flush=True)
 
 

@@ -1000,6 +1000,14 @@ abc_status abc_tune_batch(abc_batch* b, void* const* psi, void* const* aux, cons
     if (s == ABC_OK && aux) s = sv.save(aux[i], b->inst[i]->aux_elems * sizeof(double2), st);
     if (s != ABC_OK) return s;
   }
+  // On every exit, each instance's tile depth is its group's (the depth the
+  // group's kernels are instantiated at) and the callers' states are back.
+  auto finish = [&](abc_status r) {
+    for (auto& g : b->groups)
+      for (int i : g.idx) b->inst[i]->L.fused_tz = g.tz;
+    const abc_status rr = sv.restore(st);
+    return r != ABC_OK ? r : rr;
+  };
   for (auto& g : b->groups) {
     int max_tz = 16;
     for (int i : g.idx) max_tz = std::min(max_tz, fused_max_tz(g.order, b->inst[i]->p.nz));
@@ -1022,19 +1030,18 @@ abc_status abc_tune_batch(abc_batch* b, void* const* psi, void* const* aux, cons
             return e;
           },
           st, &ms);
-      if (s != ABC_OK) return s;
+      if (s != ABC_OK) return finish(s);
       if (ms < best_ms) {
         best_ms = ms;
         best = tz;
       }
     }
     g.tz = best;
-    for (int i : g.idx) b->inst[i]->L.fused_tz = best;
   }
   // a cached graph was captured with the old depths
   if (b->exec) hipGraphExecDestroy(b->exec);
   if (b->graph) hipGraphDestroy(b->graph);
   b->exec = nullptr;
   b->graph = nullptr;
-  return sv.restore(st);
+  return finish(ABC_OK);
 }

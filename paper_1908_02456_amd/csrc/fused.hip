@@ -851,6 +851,10 @@ hipError_t launch_batch_fused(const std::vector<FusedMember>& m, int tz, const v
   const int nb = (int)m.size();
   if (nb == 0 || n <= 0) return hipSuccess;
   const abc_launch& L0 = *m[0].L;
+  // the descriptors' tile counts come from each box's depth; the kernels are
+  // instantiated at tz, so every box must have been built at that depth
+  for (int i = 0; i < nb; ++i)
+    if (m[i].L->fused_tz != tz) return hipErrorInvalidValue;
   if (n & 1)
     for (int i = 0; i < nb; ++i) {
       const abc_launch& L = *m[i].L;
