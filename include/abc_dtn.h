@@ -285,6 +285,23 @@ abc_status abc_potential_iterations(const abc_ctx* ctx, long long* out);
 abc_status abc_diagnostics(abc_ctx* ctx, const void* psi, const void* aux,
                            const void* V, double* out, void* stream);
 
+/* abc_diagnostics without any device allocation, for callers that cannot
+ * allocate (code under HIP graph capture, serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, output and kernels as
+ * abc_diagnostics; the reduction partials live in a fixed array of the
+ * library, one copy per GPU, held until the process ends:
+ *   at most 64 orbitals (batch), 64 * 320 * 4 doubles = 640 KiB.
+ * A larger batch returns ABC_EINVAL before any work is queued.  The call
+ * queues its kernels on the stream and returns without synchronising; it
+ * calls no hipMalloc, hipFree or other allocating routine.  Every call on a
+ * GPU, from any context, shares that GPU's array: calls that overlap in time
+ * on one GPU (other streams, other threads) race and give wrong results;
+ * serialise them on one stream.  The array keeps the last call's partials;
+ * each call writes every partial it reads first, so nothing has to be
+ * cleared. */
+abc_status abc_diagnostics_noalloc(abc_ctx* ctx, const void* psi, const void* aux,
+                                   const void* V, double* out, void* stream);
+
 /* Number of complex128 elements of the auxiliary buffer (0 unless first or
  * second order; second order: 2 n_Gamma batch). */
 size_t abc_aux_elems(const abc_ctx* ctx);

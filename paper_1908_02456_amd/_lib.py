@@ -23,7 +23,8 @@ EXPORTED = ["abc_params_default", "abc_setup", "abc_step", "abc_diagnostics", "a
             "abc_step_timed", "abc_launch_label", "abc_adjoint", "abc_tune", "abc_setup_batch",
             "abc_step_batch", "abc_tune_batch", "abc_batch_aux_elems", "abc_batch_launch_groups",
             "abc_batch_tile_depth", "abc_destroy_batch", "abc_h2_objective",
-            "abc_effective_potential", "abc_potential_iterations", "abc_state_save", "abc_state_load"]
+            "abc_effective_potential", "abc_potential_iterations", "abc_state_save", "abc_state_load",
+            "abc_diagnostics_noalloc"]
 
 
 class AbcParams(ctypes.Structure):
@@ -103,6 +104,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.abc_state_load.restype = ctypes.c_int
     lib.abc_diagnostics.argtypes = [vp, vp, vp, vp, vp, vp]
     lib.abc_diagnostics.restype = ctypes.c_int
+    lib.abc_diagnostics_noalloc.argtypes = [vp, vp, vp, vp, vp, vp]
+    lib.abc_diagnostics_noalloc.restype = ctypes.c_int
     lib.abc_aux_elems.argtypes = [vp]
     lib.abc_aux_elems.restype = ctypes.c_size_t
     lib.abc_export.argtypes = [vp, ctypes.c_int, vp, ctypes.c_size_t]

@@ -243,5 +243,10 @@ abc_status run_h2_objective(const abc_params& p, const double* s1, int count, in
 abc_status run_adjoint(const abc_launch& L, const abc_launch& La, const abc_scratch& S, const abc_adjoint_args& a,
                        hipStream_t st, std::string& err);
 
+// Reduction partials go to red, or to the context's S.red when red is null.
 hipError_t launch_diagnostics(const abc_launch& L, const abc_scratch& S, const void* psi,
-                              const double2* aux, const void* V, double* out, hipStream_t st);
+                              const double2* aux, const void* V, double* out, hipStream_t st,
+                              double* red = nullptr);
+
+// Doubles of reduction partials one diagnostics call writes for a batch.
+size_t diag_partial_doubles(int batch);

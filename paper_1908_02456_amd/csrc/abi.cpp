@@ -6,6 +6,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -667,6 +668,62 @@ abc_status abc_diagnostics(abc_ctx* c, const void* psi, const void* aux, const v
   if (!c || !psi || !out) return fail(ABC_EINVAL, "null argument");
   hipError_t e = launch_diagnostics(c->L, c->S, psi, static_cast<const double2*>(aux), V, out,
                                     static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return fail(ABC_EDEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
+  return ABC_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Reduction partials of abc_diagnostics_noalloc: a fixed device array, one
+// copy per GPU, held until the process ends.  Host code never uses its name
+// as an address (that would be the host-side stand-in); the device address
+// is looked up once per device and kept.
+constexpr int kNoallocMaxBatch = 64;
+constexpr size_t kNoallocScratchDoubles = (size_t)kNoallocMaxBatch * (256 + 64) * 4;
+__device__ __align__(256) double scratch[kNoallocScratchDoubles];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// device address of this device's copy of the array (first call on a
+// device: hipGetSymbolAddress with that device current)
+abc_status noalloc_scratch(double** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices)
+    return fail(ABC_EDEVICE, "abc_diagnostics_noalloc: no current device (or device index >= 64)");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(ABC_EDEVICE, std::string("abc_diagnostics_noalloc: hipGetSymbolAddress: ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = static_cast<double*>(ptr);
+  }
+  *out = g_scratch_ptr[dev];
+  return ABC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+abc_status abc_diagnostics_noalloc(abc_ctx* c, const void* psi, const void* aux, const void* V, double* out,
+                                   void* stream) {
+  if (!c || !psi || !out) return fail(ABC_EINVAL, "null argument");
+  if (diag_partial_doubles(c->p.batch) > kNoallocScratchDoubles)
+    return fail(ABC_EINVAL, "abc_diagnostics_noalloc: batch " + std::to_string(c->p.batch) +
+                                " exceeds the fixed scratch, which holds the partials of at most " +
+                                std::to_string(kNoallocMaxBatch) + " orbitals");
+  double* red = nullptr;
+  abc_status s = noalloc_scratch(&red);
+  if (s != ABC_OK) return s;
+  // every partial the finishing pass reads is written by this call's own
+  // reduction blocks first, so nothing needs clearing between calls
+  hipError_t e = launch_diagnostics(c->L, c->S, psi, static_cast<const double2*>(aux), V, out,
+                                    static_cast<hipStream_t>(stream), red);
   if (e != hipSuccess) return fail(ABC_EDEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
   return ABC_OK;
 }

@@ -1520,26 +1520,26 @@ hipError_t step_staged_t(const abc_launch& L, const abc_scratch& S, void* psi_v,
 }
 
 template <typename T, int R, bool PER>
-hipError_t diag_t(const abc_launch& L, const abc_scratch& S, const void* psi, const double2* aux, const void* V,
+hipError_t diag_t(const abc_launch& L, double* red, const void* psi, const double2* aux, const void* V,
                   double* out, hipStream_t st) {
   using C = typename cpx<T>::t;
   const Geometry& g = L.g;
   const StencilCoef sc = make_coef(L);
   dim3 grid(kRedBlocks, g.batch);
   diag_points_kernel<T, R, PER><<<grid, kBlock, 0, st>>>(static_cast<const C*>(psi), static_cast<const T*>(V), g, sc,
-                                                         L.meanfield, L.t0, L.t3, S.red);
+                                                         L.meanfield, L.t0, L.t3, red);
   const int has_aux = (L.order == ABC_FIRST && aux) ? 1 : 0;
   if (has_aux) {
     dim3 ga(kAuxBlocks, g.batch);
     if (L.form == ABC_FORM_BOX) {
-      diag_box_aux_kernel<<<ga, kBlock, 0, st>>>(aux, L.box_q, L.n_gamma, g.batch, S.red);
+      diag_box_aux_kernel<<<ga, kBlock, 0, st>>>(aux, L.box_q, L.n_gamma, g.batch, red);
     } else {
       long long lines = 0;
       for (int f = 0; f < 6; ++f) lines += (long long)g.face_n1[f] * g.face_n2[f];
-      diag_aux_kernel<R><<<ga, kBlock, 0, st>>>(aux, g, make_local(L.q_loc), lines, S.red);
+      diag_aux_kernel<R><<<ga, kBlock, 0, st>>>(aux, g, make_local(L.q_loc), lines, red);
     }
   }
-  diag_finish_kernel<<<(g.batch + 63) / 64, 64, 0, st>>>(S.red, g.batch, L.h * L.h * L.h, has_aux, out);
+  diag_finish_kernel<<<(g.batch + 63) / 64, 64, 0, st>>>(red, g.batch, L.h * L.h * L.h, has_aux, out);
   return hipGetLastError();
 }
 
@@ -1557,13 +1557,13 @@ hipError_t dispatch_step(const abc_launch& L, const abc_scratch& S, void* psi, d
 }
 
 template <typename T>
-hipError_t dispatch_diag(const abc_launch& L, const abc_scratch& S, const void* psi, const double2* aux,
+hipError_t dispatch_diag(const abc_launch& L, double* red, const void* psi, const double2* aux,
                          const void* V, double* out, hipStream_t st) {
   const bool per = L.periodic != 0;
   switch (L.g.R) {
-    case 1: return per ? diag_t<T, 1, true>(L, S, psi, aux, V, out, st) : diag_t<T, 1, false>(L, S, psi, aux, V, out, st);
-    case 2: return per ? diag_t<T, 2, true>(L, S, psi, aux, V, out, st) : diag_t<T, 2, false>(L, S, psi, aux, V, out, st);
-    case 3: return per ? diag_t<T, 3, true>(L, S, psi, aux, V, out, st) : diag_t<T, 3, false>(L, S, psi, aux, V, out, st);
+    case 1: return per ? diag_t<T, 1, true>(L, red, psi, aux, V, out, st) : diag_t<T, 1, false>(L, red, psi, aux, V, out, st);
+    case 2: return per ? diag_t<T, 2, true>(L, red, psi, aux, V, out, st) : diag_t<T, 2, false>(L, red, psi, aux, V, out, st);
+    case 3: return per ? diag_t<T, 3, true>(L, red, psi, aux, V, out, st) : diag_t<T, 3, false>(L, red, psi, aux, V, out, st);
   }
   return hipErrorInvalidValue;
 }
@@ -1578,10 +1578,13 @@ hipError_t launch_step_staged(const abc_launch& L, const abc_scratch& S, void* p
 }
 
 hipError_t launch_diagnostics(const abc_launch& L, const abc_scratch& S, const void* psi, const double2* aux,
-                              const void* V, double* out, hipStream_t st) {
-  if (L.dtype == ABC_C64) return dispatch_diag<float>(L, S, psi, aux, V, out, st);
-  return dispatch_diag<double>(L, S, psi, aux, V, out, st);
+                              const void* V, double* out, hipStream_t st, double* red) {
+  if (!red) red = S.red;
+  if (L.dtype == ABC_C64) return dispatch_diag<float>(L, red, psi, aux, V, out, st);
+  return dispatch_diag<double>(L, red, psi, aux, V, out, st);
 }
+
+size_t diag_partial_doubles(int batch) { return (size_t)batch * (kRedBlocks + kAuxBlocks) * 4; }
 
 // FFT plan of the exact face sections: padded sizes per face pair, work
 // slabs, twiddle tables, and the kernel spectra (the padded R x R kernel

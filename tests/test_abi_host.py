@@ -182,6 +182,7 @@ def test_null_arguments_are_rejected_without_a_device(lib):
     J = ctypes.c_double(0)
     assert lib.abc_adjoint(None, None, None, 1, 0, 0, None, None, ctypes.byref(J), None) == _lib.ABC_EINVAL
     assert lib.abc_diagnostics(None, None, None, None, None, None) == _lib.ABC_EINVAL
+    assert lib.abc_diagnostics_noalloc(None, None, None, None, None, None) == _lib.ABC_EINVAL
     assert lib.abc_export(None, 0, None, 0) == _lib.ABC_EINVAL
     assert lib.abc_tune(None, None, None, None, None, None) == _lib.ABC_EINVAL
     b = vp()
