@@ -276,7 +276,7 @@ def bench_adjoint(Solver, torch, W):
     aux = s.new_aux()
     ms_fwd = _time(torch, lambda: s.step(psi, aux, V, prm["steps"]))
     return {"grid": n, "steps": prm["steps"], "J": out["r"][0], "ms_adjoint": ms_adj, "ms_forward": ms_fwd,
-            "adjoint_over_forward": ms_adj / ms_fwd, "forward_path": "fused" if s.use_fused else "staged"}
+            "adjoint_over_forward": ms_adj / ms_fwd, "forward_path": s.path}
 
 
 def bench_tdhf(Solver, torch, W, steps=10, full_steps=1000):
@@ -340,7 +340,7 @@ def bench_r3(Solver, torch, wl, steps=20):
     s.step(psi, aux, V, 2)
     ms = _time(torch, lambda: s.step(psi, aux, V, steps))
     return {"radius": 3, "ms_per_step": ms / steps, "value": wl.n ** 3 * steps / (ms / 1e3),
-            "unit": "grid-point-updates/s", "path": "fused" if s.use_fused else "staged"}
+            "unit": "grid-point-updates/s", "path": s.path}
 
 
 def bench_box_batch(Solver, torch, W, nb=32, steps=20):
@@ -482,7 +482,7 @@ def bench_face_windows(Solver, torch, wl, steps_timed=20):
         aux = s.new_aux()
         s.step(psi, aux, V, wl.steps)
         torch.cuda.synchronize()
-        out[name] = {"window": w, "fejer": fejer, "ms_per_step": ms, "path": "fused" if s.use_fused else "staged",
+        out[name] = {"window": w, "fejer": fejer, "ms_per_step": ms, "path": s.path,
                      "err_vs_large_box": torch.linalg.vector_norm(psi - ref).item() / nr}
         del s, psi, aux
         torch.cuda.empty_cache()
@@ -725,7 +725,8 @@ def main():
            "config": {"workload": "single orbital %d^3, h=%.2g, dt=%.3g, first-order face-form DtN ABC "
                                   "(s1=%.3g, w=%d), Gaussian well + k=(3,1,0) packet, %s"
                                   % (wl.n, wl.h, wl.dt, wl.s1, args.window, args.dtype),
-                      "grid": [wl.n] * 3, "radius": wl.radius, "fejer": not args.no_fejer, "path": args.path},
+                      "grid": [wl.n] * 3, "radius": wl.radius, "fejer": not args.no_fejer, "path": args.path,
+                      "path_chosen": s.path},
            "roofline": roof}
     if args.copy_gib > 0:
         nb = int(args.copy_gib * (1 << 30)) // 16 * 16

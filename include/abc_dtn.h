@@ -97,7 +97,7 @@ enum { ABC_FORM_BOX = 0, ABC_FORM_FACES = 1 };
 enum { ABC_C128 = 0, ABC_C64 = 1 };
 enum { ABC_MF_NONE = 0, ABC_MF_T0T3 = 1, ABC_MF_SKYRME = 2 };
 /* execution path of abc_step */
-enum { ABC_PATH_AUTO = 0, ABC_PATH_STAGED = 1, ABC_PATH_FUSED = 2 };
+enum { ABC_PATH_AUTO = 0, ABC_PATH_STAGED = 1, ABC_PATH_FUSED = 2, ABC_PATH_ONEPASS = 3 };
 
 typedef struct {
   int nx, ny, nz;     /* box points per axis (>= 2R + 1)                     */
@@ -116,7 +116,17 @@ typedef struct {
   int batch;          /* wavefunctions sharing grid, V and boundary (>= 1)  */
   int meanfield;      /* ABC_MF_NONE | ABC_MF_T0T3                          */
   double t0, t3;      /* mean-field coefficients                            */
-  int path;           /* ABC_PATH_*                                        */
+  int path;           /* ABC_PATH_AUTO: the one-pass sweep (all four stages
+                         in one launch per step) where it covers the
+                         parameters (for the first order only on rows of
+                         128 columns), else the two-stage fused kernels,
+                         else the staged path.  ABC_PATH_FUSED / ABC_PATH_ONEPASS
+                         force those kernels (ABC_ENOTSUP when they do not
+                         cover the parameters): R = 1, window 0, nx, ny >= 4,
+                         nz >= 5; the one-pass sweep also one orbital, no
+                         mean field, nx <= 128 and, for the first order,
+                         ny > 12 / 16 and nz > 20 / 12 (complex128 /
+                         complex64); ABC_PATH_STAGED the general path     */
   int reserved[3];    /* must be zero                                       */
   double s3, s4;      /* second order: the last two interpolation points;
                          s1..s4 positive and distinct                       */
@@ -315,7 +325,9 @@ size_t abc_aux_elems(const abc_ctx* ctx);
  * n = capacity in complex128 elements; returns EINVAL if too small. */
 abc_status abc_export(const abc_ctx* ctx, int which, void* host_out, size_t n);
 
-/* Execution path chosen at setup: ABC_PATH_STAGED or ABC_PATH_FUSED. */
+/* Execution path chosen at setup: ABC_PATH_STAGED, ABC_PATH_FUSED (two
+ * launches of two stages per step) or ABC_PATH_ONEPASS (one launch per
+ * step). */
 int abc_path(const abc_ctx* ctx);
 
 /* Bytes of device memory held by the context. */

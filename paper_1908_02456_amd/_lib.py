@@ -15,7 +15,7 @@ ABC_BATCH_GRAPH = 1
 ORDERS = {"dirichlet": 0, "periodic": 1, "zeroth": 2, "first": 3, "second": 4}
 FORMS = {"box": 0, "faces": 1}
 DTYPES = {"c128": 0, "c64": 1}
-PATHS = {"auto": 0, "staged": 1, "fused": 2}
+PATHS = {"auto": 0, "staged": 1, "fused": 2, "onepass": 3}
 OBJECTIVES = {"prob": 0, "energy": 1}
 
 EXPORTED = ["abc_params_default", "abc_setup", "abc_step", "abc_diagnostics", "abc_aux_elems",

@@ -120,6 +120,8 @@ struct abc_launch {
   double2 a_loc[abc::kMaxR * abc::kMaxR];
   double2 q_loc[abc::kMaxR * abc::kMaxR];
   double2 fused_m0, fused_b0;  // window-0 face operator value (host copy)
+  // one-pass sweep: the step polynomial as (1 + a1 x + b1 x^2)(1 + a2 x + b2 x^2)
+  double fused_a1, fused_b1, fused_a2, fused_b2;
   int fused_stages;            // 4: one launch per step; 2: two launches
   int fused_tz;                // planes per tile of the two-stage kernel (4, 8, 16)
   // box form

@@ -83,7 +83,7 @@ abc_status check_params(const abc_params& p) {
   }
   for (int i = 0; i < 3; ++i)
     if (p.reserved2[i] != 0) return fail(ABC_EINVAL, "reserved fields must be zero");
-  if (p.path < ABC_PATH_AUTO || p.path > ABC_PATH_FUSED) return fail(ABC_EINVAL, "unknown path");
+  if (p.path < ABC_PATH_AUTO || p.path > ABC_PATH_ONEPASS) return fail(ABC_EINVAL, "unknown path");
   if (p.window < 0) return fail(ABC_EINVAL, "window must be >= 0");
   if (p.order == ABC_PERIODIC && p.nx < 2 * p.radius + 1) return fail(ABC_EINVAL, "periodic box too small");
   if (p.order == ABC_ZEROTH && !(p.s0 > 0)) return fail(ABC_EUNSTABLE, "s0 must be positive (zeroth-order theorem)");
@@ -381,8 +381,8 @@ abc_status abc_setup(const abc_params* pp, abc_ctx** out) {
   c->use_fused = 0;
   if (p.path != ABC_PATH_STAGED) {
     std::string why;
-    const bool ok = fused_supported(p, &why);
-    if (p.path == ABC_PATH_FUSED && !ok) {
+    const bool ok = p.path == ABC_PATH_ONEPASS ? fused4_supported(p, &why) : fused_supported(p, &why);
+    if ((p.path == ABC_PATH_FUSED || p.path == ABC_PATH_ONEPASS) && !ok) {
       abc_destroy(c);
       return fail(ABC_ENOTSUP, "fused path: " + why);
     }
@@ -425,7 +425,10 @@ size_t abc_aux_elems(const abc_ctx* c) { return c ? c->aux_elems : 0; }
 
 size_t abc_device_bytes(const abc_ctx* c) { return c ? c->bytes : 0; }
 
-int abc_path(const abc_ctx* c) { return (c && c->use_fused) ? ABC_PATH_FUSED : ABC_PATH_STAGED; }
+int abc_path(const abc_ctx* c) {
+  if (!c || !c->use_fused) return ABC_PATH_STAGED;
+  return c->L.fused_stages == 4 ? ABC_PATH_ONEPASS : ABC_PATH_FUSED;
+}
 
 abc_status abc_step(abc_ctx* c, void* psi, void* aux, const void* V, int n_steps, void* stream) {
   if (!c || !psi) return fail(ABC_EINVAL, "null context or psi");
@@ -892,7 +895,11 @@ abc_status abc_setup_batch(const abc_params* ps, int n, abc_batch** out) {
       abc_destroy_batch(b);
       return fail(ABC_ENOTSUP, "instance " + std::to_string(i) + ": the Skyrme mean field is not batched");
     }
-    abc_status st = abc_setup(&ps[i], &c);
+    // the batch launch runs the two-stage kernels: an instance on the
+    // automatic path takes them when they cover it
+    abc_params pi = ps[i];
+    if (pi.path == ABC_PATH_AUTO && fused_supported(pi, nullptr)) pi.path = ABC_PATH_FUSED;
+    abc_status st = abc_setup(&pi, &c);
     if (st != ABC_OK) {
       const std::string msg = "instance " + std::to_string(i) + ": " + g_last_error;
       abc_destroy_batch(b);

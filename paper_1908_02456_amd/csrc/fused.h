@@ -9,6 +9,8 @@
 
 // true when the fused kernel covers the parameters; otherwise *why says why
 bool fused_supported(const abc_params& p, std::string* why);
+// the same for the one-pass sweep (all four stages in one launch)
+bool fused4_supported(const abc_params& p, std::string* why);
 
 // allocate/prepare whatever the fused path needs beyond the staged scratch
 abc_status fused_prepare(const abc_params& p, abc_launch& L, std::vector<void*>* allocs, size_t* bytes,

@@ -29,6 +29,7 @@
 // neighbouring tiles read halos that a tile overwrites.
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <cstdlib>
 #include <type_traits>
 #include <utility>
@@ -49,6 +50,7 @@ struct FusedArgs {
   int nty, ntiles, tiles_per_xcd;
   double diag, off;
   double coef[5];
+  double sa1, sa2;  // one-pass sweep: base scales of stages 1 and 3 (factored form)
   double2 m0, b0, a0;
   int face_off[7];
   int has_V;
@@ -99,6 +101,53 @@ __device__ __forceinline__ void bload(__amdgpu_buffer_rsrc_t r, unsigned off, do
 }
 __device__ __forceinline__ void bload(__amdgpu_buffer_rsrc_t r, unsigned off, float& v) {
   v = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+
+// Neighbouring lanes' values by DPP (no LDS traffic): lane i receives lane
+// i - 1 (shr) or i + 1 (shl); lanes past the wave's ends receive zero.
+__device__ __forceinline__ double dpp_shift(double v, bool right) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = (int)b, hi = (int)(b >> 32);
+  const int l2 = right ? __builtin_amdgcn_update_dpp(0, lo, 0x138, 0xF, 0xF, true)
+                       : __builtin_amdgcn_update_dpp(0, lo, 0x130, 0xF, 0xF, true);
+  const int h2 = right ? __builtin_amdgcn_update_dpp(0, hi, 0x138, 0xF, 0xF, true)
+                       : __builtin_amdgcn_update_dpp(0, hi, 0x130, 0xF, 0xF, true);
+  return __builtin_bit_cast(double, ((long long)h2 << 32) | (unsigned)l2);
+}
+__device__ __forceinline__ float dpp_shift(float v, bool right) {
+  const int b = __builtin_bit_cast(int, v);
+  return __builtin_bit_cast(float, right ? __builtin_amdgcn_update_dpp(0, b, 0x138, 0xF, 0xF, true)
+                                         : __builtin_amdgcn_update_dpp(0, b, 0x130, 0xF, 0xF, true));
+}
+template <typename C>
+__device__ __forceinline__ C dpp_shift_c(C v, bool right) {
+  C o;
+  o.x = dpp_shift(v.x, right);
+  o.y = dpp_shift(v.y, right);
+  return o;
+}
+// The same, with the lane past the wave's end (lane 0 for shr, 63 for shl)
+// receiving `edge` instead of zero (its destination is left as it was).
+__device__ __forceinline__ double dpp_shift_edge(double v, bool right, double edge) {
+  const long long b = __builtin_bit_cast(long long, v), e = __builtin_bit_cast(long long, edge);
+  const int lo = (int)b, hi = (int)(b >> 32), elo = (int)e, ehi = (int)(e >> 32);
+  const int l2 = right ? __builtin_amdgcn_update_dpp(elo, lo, 0x138, 0xF, 0xF, false)
+                       : __builtin_amdgcn_update_dpp(elo, lo, 0x130, 0xF, 0xF, false);
+  const int h2 = right ? __builtin_amdgcn_update_dpp(ehi, hi, 0x138, 0xF, 0xF, false)
+                       : __builtin_amdgcn_update_dpp(ehi, hi, 0x130, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, ((long long)h2 << 32) | (unsigned)l2);
+}
+__device__ __forceinline__ float dpp_shift_edge(float v, bool right, float edge) {
+  const int b = __builtin_bit_cast(int, v), e = __builtin_bit_cast(int, edge);
+  return __builtin_bit_cast(float, right ? __builtin_amdgcn_update_dpp(e, b, 0x138, 0xF, 0xF, false)
+                                         : __builtin_amdgcn_update_dpp(e, b, 0x130, 0xF, 0xF, false));
+}
+template <typename C, typename T>
+__device__ __forceinline__ C dpp_shift_edge_c(C v, bool right, T ex, T ey) {
+  C o;
+  o.x = dpp_shift_edge(v.x, right, ex);
+  o.y = dpp_shift_edge(v.y, right, ey);
+  return o;
 }
 
 // Half of the Horner step per launch:
@@ -616,6 +665,501 @@ __global__ void __launch_bounds__(64 * (kTY2 + 2 * kHalo2)) fused2_batch_kernel(
                                        b.aux_out, t - b.tile_begin);
 }
 
+// ---------------------------------------------------------------------------
+// One-pass step: all four Horner stages in one z-marching sweep, so the
+// state, the potential and the result cross HBM once per step (40 B per
+// point at complex128).  The tile is the whole row (nx <= 128) by TY rows by
+// TZ planes, with four-deep halos in y and z; stage k is computed on rows
+// k .. ROWS-1-k and planes z0-(4-k) .. z0+TZ+(3-k), so each stage is exact
+// where the next reads it.  Register state per lane (two columns): the
+// centre and below planes of each stage's input, the Horner base at the two
+// oldest planes and V at the four stage planes.  The stage inputs' centre
+// planes are published in LDS, level j (the output of stage j, level 0 =
+// psi) only on the rows stage j+1 reads, double-buffered (one barrier per
+// plane).  complex128: TY = 4, TZ = 16, 12 waves (about 160 VGPRs);
+// complex64: TY = 8, TZ = 8, 16 waves.
+// ---------------------------------------------------------------------------
+constexpr int kHalo4 = 4;
+template <typename T> struct Tile4;
+template <> struct Tile4<double> { static constexpr int TY = 4, TZ = 16; };
+template <> struct Tile4<float> { static constexpr int TY = 8, TZ = 8; };
+
+template <typename T>
+__host__ __device__ constexpr int rows4() { return Tile4<T>::TY + 2 * kHalo4; }
+// first LDS row of level j (level j holds the ROWS - 2j rows j .. ROWS-1-j)
+template <typename T>
+__host__ __device__ constexpr int level_base4(int j) { return j * rows4<T>() - j * (j - 1); }
+
+// The step polynomial is applied as the product of its two real quadratic
+// factors, P(x) = (1 + a1 x + b1 x^2)(1 + a2 x + b2 x^2), each in two stages
+// (u = state, L = generator, D = dt):
+//   stage 1: t = a1 u + b1 D L u      stage 2: v = u + D L t
+//   stage 3: s = a2 v + b2 D L v      stage 4: u' = v + D L s
+// The same polynomial as the Taylor sum, in another rounding order.  Every
+// stage's base is its own input (stages 1, 3) or the input of the stage
+// before it at the same plane (stages 2, 4), which the z queue already holds,
+// so no separate copy of the step's initial state rides along.
+// ORDER: 0 = zero outside the box, 2 = zeroth order (local face term),
+// 3 = first order (Theorem 3.2, local face operators): the psi stage adds
+// -i g_k sum_f A_f at face points (A_f the face's auxiliary stage input, g_k
+// the stage's coefficient) and the auxiliary stage is base + g_k (b A + a
+// psi_in), with the bases above.  A face point's auxiliary values pass
+// through the four stages in four consecutive planes of the march:
+//  * x faces and the tile's y-face row: the two halo waves (rows 0 and
+//    ROWS-1 take part in no stage) run the auxiliary stages one plane ahead
+//    of the row waves, from the stage inputs published in LDS, and hand the
+//    next plane's sources A over through LDS (double-buffered by plane
+//    parity); they keep the bases in LDS slots indexed by plane & 3.  Row 0
+//    takes the x faces (one lane per side and row; f0 staged for the whole
+//    march at the start), row ROWS-1 the y-face row (f0 fetched a plane
+//    ahead);
+//  * the z-face plane: one stage at a time is on it, so the row waves run
+//    its auxiliary stage themselves (slots per thread; f0 read at stage 1).
+// So the first-order tile needs ny > ROWS and nz > TZ + 4 (at most one face
+// row and plane per tile), and one plane buffer (two barriers per plane) to
+// fit the slots in LDS.
+// FULL: every lane's two columns lie in the box (nx == 128); otherwise the
+// stage outputs of columns x >= nx are forced to zero (they are read as the
+// x neighbours of the last column).
+template <typename T, int ORDER, bool FULL, bool DB>
+__global__ void __launch_bounds__(64 * rows4<T>()) fused4_kernel(const typename cpx<T>::t* __restrict__ pin,
+                                                                  typename cpx<T>::t* __restrict__ pout,
+                                                                  const T* __restrict__ V, FusedArgs a,
+                                                                  const double2* __restrict__ fin,
+                                                                  double2* __restrict__ fout) {
+  using C = typename cpx<T>::t;
+  constexpr int TY = Tile4<T>::TY, TZ = Tile4<T>::TZ, H = kHalo4;
+  constexpr int ROWS = rows4<T>();
+  constexpr int NT = 64 * ROWS;
+  constexpr int ITERS = TZ + 2 * H;
+  constexpr int NLR = level_base4<T>(4);  // published rows over the four levels
+  constexpr bool FO = ORDER == 3;
+  // rows as [column parity][lane] (x neighbours come by DPP, so no guard
+  // cells); two buffers (DB: one barrier per plane) or one (two barriers)
+  __shared__ C pl[DB ? 2 : 1][NLR][2][64];
+  // first-order face data (sizes in double2; 1 when unused)
+  constexpr int NXF = FO ? 2 * ROWS * ITERS : 1, NXS = FO ? 2 * 4 * 2 * ROWS : 1, NXB = FO ? 2 * ROWS * 4 : 1;
+  constexpr int NYS = FO ? 2 * 4 * 2 * 64 : 1, NYB = FO ? 4 * 2 * 64 : 1, NZC = FO ? ROWS * 2 * 64 * 2 : 1;
+  __shared__ double2 xf0[NXF];  // [side][row][march plane]        x-face f0
+  __shared__ double2 xsrc[NXS];  // [plane parity][stage][side][row] x-face stage inputs A
+  __shared__ double2 xb[NXB];   // [side][row][plane & 3]          x-face bases
+  __shared__ double2 ysrc[NYS];  // [plane parity][stage][c][lane]  y-face stage inputs A
+  __shared__ double2 yb[NYB];   // [plane & 3][c][lane]            y-face bases
+  __shared__ double2 zch[NZC];  // [row][c][lane][A, base]         z-face slots
+
+  const int lane = threadIdx.x & 63;
+  const int r = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform row
+  int tile = blockIdx.x;
+  if (a.tiles_per_xcd) tile = (blockIdx.x & 7) * a.tiles_per_xcd + (blockIdx.x >> 3);
+  const int ty = tile % a.nty, tz = tile / a.nty;
+  const int y0 = ty * TY, z0 = tz * TZ;
+  const int nx = a.nx, ny = a.ny, nz = a.nz;
+  const int sz = nx * ny;
+  const int y = y0 - H + r;
+  const bool row_in = y >= 0 && y < ny;
+  const int ybase = y * nx;
+  const bool own_row = r >= H && r < H + TY && row_in;
+  bool inx[2];
+#pragma unroll
+  for (int c = 0; c < 2; ++c) inx[c] = FULL || 2 * lane + c < nx;
+
+  for (int i = threadIdx.x; i < (DB ? 2 : 1) * NLR * 2 * 64; i += NT) (&pl[0][0][0][0])[i] = czero<C>();
+
+  // first order: the faces the tile meets
+  const int xh = nx - 1;  // high x-face column
+  int yrow = -1, yface = -1;  // the tile row on a y face, and the face
+  int zface_plane = -1, zface = -1;  // the z-face plane the march meets
+  if (FO) {
+    if (y0 - H <= 0) yrow = H - y0, yface = 2;
+    else if (y0 - H + ROWS - 1 >= ny - 1) yrow = ny - 1 - (y0 - H), yface = 3;
+    if (yrow < 1 || yrow > ROWS - 2) yrow = yface = -1;  // no stage runs on rows 0 and ROWS-1
+    if (z0 - H <= 0) zface_plane = 0, zface = 4;
+    else if (z0 + TZ + H - 1 >= nz - 1) zface_plane = nz - 1, zface = 5;
+    // the x-face f0 over the march
+    for (int i = threadIdx.x; i < NXF; i += NT) {
+      const int q = i % ITERS, rr = (i / ITERS) % ROWS, side = i / (ITERS * ROWS);
+      const int yy = y0 - H + rr, zz = z0 - H + q;
+      double2 v = make_double2(0, 0);
+      if (yy >= 0 && yy < ny && zz >= 0 && zz < nz) v = fin[a.face_off[side] + zz * ny + yy];
+      xf0[i] = v;
+    }
+  }
+  // Helper waves run in a loop of their own: the halo rows 0 and ROWS-1
+  // (which take part in no stage) publish their psi row, and with the first
+  // order every wave whose row lies outside the box (tiles at a y face) joins
+  // them for the face jobs, the auxiliary stages of the plane's four stages:
+  //  * without a y-face row (two helpers): helper 0 runs the x faces' stages
+  //    1-2, helper 1 stages 3-4, one (stage, side, row) item per lane;
+  //  * with one and at least five helpers: helpers 0-3 run the y-face row's
+  //    stages 1-4 (two columns per lane), helper 4 all x-face items;
+  //  * otherwise (a y-face row in a tile's halo, few helpers): helper 0 the
+  //    stages 1-2 of both, the last helper stages 3-4.
+  // Rows 0 and ROWS-1 also fetch the y face's f0 (even / odd columns).
+  const int nlo = FO ? min(max(H - y0, 1), ROWS) : 1;            // rows 0 .. nlo-1
+  const int hstart = FO ? min(max(ny - y0 + H, 0), ROWS - 1) : ROWS - 1;  // rows hstart ..
+  const bool helper = r < nlo || r >= hstart;
+  constexpr int NXI = FO ? 4 * 2 * ROWS : 0;           // x-face items
+  const int ycol = r == 0 ? 0 : 1;                     // f0 fetch of the y face
+  const bool yfetch = FO && yrow >= 0 && (r == 0 || r == ROWS - 1) && 2 * lane + ycol < nx;
+
+  C Yc[4][2], Yb[4][2];  // stage-k inputs (level k-1): centre / below plane
+  T Dd[4][2];            // diagonal of H (stencil centre + V) at planes zi-1 .. zi-4
+  C pf[2];               // psi and V of the next plane, fetched an iteration ahead
+  T pv[2];
+  double2 pfy;           // y-face job: the face's f0 at the next plane (the wave's column)
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      Yc[j][c] = Yb[j][c] = czero<C>();
+      Dd[j][c] = T(0);
+    }
+  }
+  pfy = make_double2(0, 0);
+  const T diag = T(a.diag), off = T(a.off);
+  const T sa1 = T(a.sa1), sa2 = T(a.sa2);
+  const unsigned cbytes = (unsigned)(nz * sz) * (unsigned)sizeof(C);
+  const __amdgpu_buffer_rsrc_t rp = make_rsrc(pin, cbytes);
+  const __amdgpu_buffer_rsrc_t rv = make_rsrc(V, a.has_V ? (unsigned)(nz * sz) * (unsigned)sizeof(T) : 0u);
+  const __amdgpu_buffer_rsrc_t rf = make_rsrc(fin, FO ? (unsigned)a.face_off[6] * 16u : 0u);
+  // plane zz (and, for the y-face job, the face's f0 there); cells outside
+  // the box read as zero (out-of-range offsets)
+  auto fetch = [&](int zz, bool face_f0) __attribute__((always_inline)) {
+    const bool ok = row_in && zz >= 0 && zz < nz;
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      const bool in = ok && inx[c];
+      const unsigned idx = (unsigned)(zz * sz + ybase + 2 * lane + c);
+      bload(rp, in ? idx * (unsigned)sizeof(C) : kOob, pf[c]);
+      bload(rv, in ? idx * (unsigned)sizeof(T) : kOob, pv[c]);
+    }
+    if (FO && face_f0 && yfetch) {
+      const bool okf = zz >= 0 && zz < nz;
+      const unsigned fi = (unsigned)(a.face_off[yface] + zz * nx + 2 * lane + ycol);
+      bload(rf, okf ? fi * 16u : kOob, pfy);
+    }
+  };
+  fetch(z0 - H, true);
+  __syncthreads();
+
+  // one face point's auxiliary stage k: A its input, B the carried base,
+  // ce the psi stage input there; returns the output and the next base
+  auto aux_stage = [&](int k, double2 A, double2 B, double2 ce, double2& nB) __attribute__((always_inline)) {
+    const double gk = a.coef[5 - k];
+    const double2 bA = cmul(a.b0, A), ac = cmul(a.a0, ce);
+    double2 base;
+    if (k == 1 || k == 3) {
+      const double sc = k == 1 ? a.sa1 : a.sa2;
+      base = make_double2(sc * A.x, sc * A.y);
+    } else {
+      base = B;
+    }
+    const double2 nA = make_double2(base.x + gk * (bA.x + ac.x), base.y + gk * (bA.y + ac.y));
+    nB = (k == 1 || k == 3) ? A : nA;  // f0 for stage 2, v for stage 4
+    return nA;
+  };
+
+  if (helper) {
+    const int nhelp = nlo + (ROWS - hstart);
+    const int hid = r < nlo ? r : nlo + (r - hstart);
+    // this helper's stages: x faces [xk0, xk1], the y-face row [yk0, yk1]
+    int xk0 = 1, xk1 = 0, yk0 = 1, yk1 = 0;
+    if (FO) {
+      const bool yf = yrow >= 0;
+      if (yf && nhelp >= 5) {
+        if (hid < 4) yk0 = yk1 = hid + 1;
+        else if (hid == 4) xk0 = 1, xk1 = 4;
+      } else if (hid == 0) {
+        xk0 = 1, xk1 = 2;
+        if (yf) yk0 = 1, yk1 = 2;
+      } else if (hid == nhelp - 1) {
+        xk0 = 3, xk1 = 4;
+        if (yf) yk0 = 3, yk1 = 4;
+      }
+    }
+    const int nxi = (xk1 - xk0 + 1) * 2 * ROWS;  // x items of this helper
+#pragma unroll
+    for (int it = 0; it < ITERS; ++it) {
+      const int zi = z0 - H + it;
+      const auto& rd = pl[DB ? (it & 1) : 0];
+      auto& wr = pl[DB ? ((it + 1) & 1) : 0];
+      const int par = it & 1, npar = (it + 1) & 1;
+      C cur[2];          // psi of this row at plane zi (published below)
+      const double2 fy = pfy;  // y-face f0 at plane zi (the next plane's stage 1)
+#pragma unroll
+      for (int c = 0; c < 2; ++c) cur[c] = pf[c];
+      if (it + 1 < ITERS) fetch(zi + 1, true);
+      if (FO) {
+        // one item: the auxiliary stage k of a face point; loads first for
+        // every item of a group, then the arithmetic and the stores (the
+        // items are independent: each stage is at its own plane and slot)
+        struct Item {
+          double2 A, B, ce;
+        };
+        // x faces: item j = (stage xk0 + j / (2 ROWS), side, row), two rounds
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          const int jj = lane + 64 * q;
+          if (jj < nxi) {
+            const int k = xk0 + jj / (2 * ROWS), ch = jj % (2 * ROWS), side = ch / ROWS, row = ch % ROWS;
+            const int zk = zi - k;
+            const int yy = y0 - H + row;
+            const int xcol = side ? xh : 0;
+            const int lb = level_base4<T>(k - 1) - (k - 1);
+            const int rr = min(max(row, k - 1), ROWS - k);  // a published row of level k-1
+            const int bi = (side * ROWS + row) * 4 + (zk & 3);
+            const C ce = rd[lb + rr][xcol & 1][xcol >> 1];
+            const Item in{xsrc[((par * 4 + (k - 1)) * 2 + side) * ROWS + row], xb[bi],
+                          make_double2((double)ce.x, (double)ce.y)};
+            const bool act = row >= k && row < ROWS - k && it >= 2 * k && yy >= 0 && yy < ny && zk >= 0 && zk < nz;
+            if (act) {
+              double2 nB;
+              const double2 nA = aux_stage(k, in.A, in.B, in.ce, nB);
+              if (k < 4) {
+                xsrc[((npar * 4 + k) * 2 + side) * ROWS + row] = nA;
+                xb[bi] = nB;
+              } else if (row >= H && row < H + TY && zk >= z0 && zk < z0 + TZ) {
+                fout[a.face_off[side] + zk * ny + yy] = nA;
+              }
+            }
+            // the stage-1 input of the next plane (zi): f0
+            if (k == 1) xsrc[((npar * 4 + 0) * 2 + side) * ROWS + row] = xf0[(side * ROWS + row) * ITERS + it];
+          }
+        }
+        // the y-face row: stages [yk0, yk1], both columns of the lane
+        for (int k = yk0; k <= yk1; ++k) {
+          const int zk = zi - k;
+          const int lb = level_base4<T>(k - 1) - (k - 1);
+          const int rr = min(max(yrow, k - 1), ROWS - k);
+          Item in[2];
+#pragma unroll
+          for (int c = 0; c < 2; ++c) {
+            const C ce = rd[lb + rr][c][lane];
+            in[c] = Item{ysrc[((par * 4 + (k - 1)) * 2 + c) * 64 + lane], yb[((zk & 3) * 2 + c) * 64 + lane],
+                         make_double2((double)ce.x, (double)ce.y)};
+          }
+          const bool act = yrow >= k && yrow < ROWS - k && it >= 2 * k && zk >= 0 && zk < nz;
+#pragma unroll
+          for (int c = 0; c < 2; ++c) {
+            if (!act || !inx[c]) continue;
+            double2 nB;
+            const double2 nA = aux_stage(k, in[c].A, in[c].B, in[c].ce, nB);
+            if (k < 4) {
+              ysrc[((npar * 4 + k) * 2 + c) * 64 + lane] = nA;
+              yb[((zk & 3) * 2 + c) * 64 + lane] = nB;
+            } else if (yrow >= H && yrow < H + TY && zk >= z0 && zk < z0 + TZ) {
+              fout[a.face_off[yface] + zk * nx + 2 * lane + c] = nA;
+            }
+          }
+        }
+        if (yfetch) ysrc[((npar * 4 + 0) * 2 + ycol) * 64 + lane] = fy;
+      }
+      if (!DB) sync_lds();
+      if (r == 0 || r == ROWS - 1) {
+#pragma unroll
+        for (int c = 0; c < 2; ++c) wr[r == 0 ? 0 : level_base4<T>(1) - 1][c][lane] = cur[c];
+      }
+      sync_lds();
+    }
+    return;
+  }
+
+#pragma unroll
+  for (int it = 0; it < ITERS; ++it) {
+    const int zi = z0 - H + it;
+    const auto& rd = pl[DB ? (it & 1) : 0];
+    auto& wr = pl[DB ? ((it + 1) & 1) : 0];
+    const int par = it & 1;
+    C prev[2];   // the previous stage's output at the plane above (stage 1: psi(zi))
+    T dcur[2];
+    C ub[2];     // stage-2 base: psi at plane zi - 2
+    C vb[2];     // stage-4 base: the stage-2 output at plane zi - 4
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      prev[c] = pf[c];
+      dcur[c] = diag + pv[c];
+      ub[c] = Yb[0][c];
+      vb[c] = Yb[2][c];
+    }
+    if (it + 1 < ITERS) fetch(zi + 1, false);
+#pragma unroll
+    for (int k = 1; k <= 4; ++k) {
+      const int zk = zi - k;
+      const T cf = T(a.coef[5 - k]);
+      const bool active = r >= k && r < ROWS - k && it >= 2 * k && row_in && zk >= 0 && zk < nz;
+      C o[2];
+      if (active) {
+        // level k-1 rows r-1, r, r+1 (published at the end of the previous plane)
+        const int lb = level_base4<T>(k - 1) - (k - 1);
+        // First order on full rows: the x-face sources -i g A enter as the
+        // x neighbours outside the box of columns 0 and 127, A / off (the
+        // lanes past the wave's ends of the DPP shifts), so that no select is
+        // needed.  Other rows add them below.
+        T e0x = T(0), e0y = T(0), e1x = T(0), e1y = T(0);
+        if (FO && FULL) {
+          const double2 s0 = xsrc[((par * 4 + (k - 1)) * 2 + 0) * ROWS + r];
+          const double2 s1 = xsrc[((par * 4 + (k - 1)) * 2 + 1) * ROWS + r];
+          const double io = 1.0 / a.off;
+          e0x = T(s0.x * io), e0y = T(s0.y * io), e1x = T(s1.x * io), e1y = T(s1.y * io);
+        }
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+          const int x = 2 * lane + c;
+          const C cen = Yc[k - 1][c], bel = Yb[k - 1][c], abv = prev[c];
+          const C ym = rd[lb + r - 1][c][lane];
+          const C yp = rd[lb + r + 1][c][lane];
+          // x neighbours: the lane's other column, or the neighbouring lane's
+          // (a row is one wave, so by DPP)
+          C xm, xp;
+          if (FO && FULL) {
+            xm = c == 0 ? dpp_shift_edge_c(Yc[k - 1][1], true, e0x, e0y) : Yc[k - 1][0];
+            xp = c == 0 ? Yc[k - 1][1] : dpp_shift_edge_c(Yc[k - 1][0], false, e1x, e1y);
+          } else {
+            xm = c == 0 ? dpp_shift_c(Yc[k - 1][1], true) : Yc[k - 1][0];
+            xp = c == 0 ? Yc[k - 1][1] : dpp_shift_c(Yc[k - 1][0], false);
+          }
+          const T d = Dd[k - 1][c];
+          T hr = d * cen.x + off * (((bel.x + abv.x) + (ym.x + yp.x)) + (xm.x + xp.x));
+          T hi = d * cen.y + off * (((bel.y + abv.y) + (ym.y + yp.y)) + (xm.y + xp.y));
+          if (ORDER == 2) {
+            const T nf = T((x == 0) + (x == nx - 1) + (y == 0) + (y == ny - 1) + (zk == 0) + (zk == nz - 1));
+            const T m0x = T(a.m0.x), m0y = T(a.m0.y);
+            hr += nf * (m0x * cen.x - m0y * cen.y);
+            hi += nf * (m0x * cen.y + m0y * cen.x);
+          }
+          if (k == 1 || k == 3) {
+            const T sa = k == 1 ? sa1 : sa2;
+            o[c].x = sa * cen.x + cf * hi;
+            o[c].y = sa * cen.y - cf * hr;
+          } else {
+            const C b = k == 2 ? ub[c] : vb[c];
+            o[c].x = b.x + cf * hi;
+            o[c].y = b.y - cf * hr;
+          }
+        }
+        if (FO) {
+          // face sources -i g_k A_f, in FP64
+          const double gk = a.coef[5 - k];
+          // x faces on rows that do not fill the wave: every lane reads both
+          // sides' inputs of its row (one address per wave) and adds them
+          // under selects at the face columns
+          if (!FULL) {
+            const double2 s0 = xsrc[((par * 4 + (k - 1)) * 2 + 0) * ROWS + r];
+            const double2 s1 = xsrc[((par * 4 + (k - 1)) * 2 + 1) * ROWS + r];
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+              const int x = 2 * lane + c;
+              const double sr = (x == 0 ? s0.x : 0.0) + (x == xh ? s1.x : 0.0);
+              const double si = (x == 0 ? s0.y : 0.0) + (x == xh ? s1.y : 0.0);
+              o[c].x += T(gk * si);
+              o[c].y -= T(gk * sr);
+            }
+          }
+          // the tile's y-face row (whole wave)
+          if (r == yrow) {
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+              const double2 A = ysrc[((par * 4 + (k - 1)) * 2 + c) * 64 + lane];
+              o[c].x += T(gk * A.y);
+              o[c].y -= T(gk * A.x);
+            }
+          }
+          // the z-face plane (wave-uniform: one stage at a time is on it)
+          if (zk == zface_plane) {
+            const bool own_pt = k == 4 && own_row && zk >= z0 && zk < z0 + TZ;
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+              if (!inx[c]) continue;
+              const C ce = Yc[k - 1][c];
+              const int si = ((r * 2 + c) * 64 + lane) * 2;
+              const double2 A = k == 1 ? fin[a.face_off[zface] + ybase + 2 * lane + c] : zch[si];
+              const double2 B = k == 1 ? A : zch[si + 1];
+              o[c].x += T(gk * A.y);
+              o[c].y -= T(gk * A.x);
+              double2 nB;
+              const double2 nA = aux_stage(k, A, B, make_double2((double)ce.x, (double)ce.y), nB);
+              if (k < 4) {
+                zch[si] = nA;
+                zch[si + 1] = nB;
+              } else if (own_pt) {
+                fout[a.face_off[zface] + ybase + 2 * lane + c] = nA;
+              }
+            }
+          }
+        }
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+          if (!FULL && !inx[c]) o[c] = czero<C>();
+      } else {
+        o[0] = o[1] = czero<C>();
+      }
+      // stage k is the last reader of its input window: slide it
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        Yb[k - 1][c] = Yc[k - 1][c];
+        Yc[k - 1][c] = prev[c];
+        prev[c] = o[c];
+      }
+      // keep the next stage's LDS reads below this stage's arithmetic (with
+      // all four stages' reads hoisted the registers run out)
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    // stage 4's output is the new state at plane zi - 4
+    const int z4 = zi - 4;
+    const bool own_out = own_row && it >= 2 * H && z4 < nz;
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      if (own_out && inx[c]) pout[z4 * sz + ybase + 2 * lane + c] = prev[c];
+      Dd[3][c] = Dd[2][c];
+      Dd[2][c] = Dd[1][c];
+      Dd[1][c] = Dd[0][c];
+      Dd[0][c] = dcur[c];
+    }
+    // publish the next plane's stage inputs: level j on rows j .. ROWS-1-j
+    // (with one buffer, after every wave is done reading it)
+    if (!DB) sync_lds();
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      if (r >= j && r < ROWS - j) {
+        const int lr = level_base4<T>(j) + r - j;
+#pragma unroll
+        for (int c = 0; c < 2; ++c) wr[lr][c][lane] = Yc[j][c];
+      }
+    }
+    sync_lds();
+  }
+}
+
+template <typename T>
+FusedArgs make_args4(const abc_launch& L) {
+  FusedArgs a{};
+  a.nx = L.g.nx;
+  a.ny = L.g.ny;
+  a.nz = L.g.nz;
+  a.ntx = 1;
+  a.xw = a.nx;
+  a.nty = (a.ny + Tile4<T>::TY - 1) / Tile4<T>::TY;
+  const int ntz = (a.nz + Tile4<T>::TZ - 1) / Tile4<T>::TZ;
+  a.ntiles = a.nty * ntz;
+  a.tiles_per_xcd = (a.ntiles % 8 == 0) ? a.ntiles / 8 : 0;
+  const double s = 1.0 / (2.0 * L.h * L.h);
+  a.diag = -3.0 * L.c[0] * s;
+  a.off = -L.c[1] * s;
+  // stage k reads coef[5 - k]: the factored form's coefficients
+  a.coef[4] = L.fused_b1 * L.dt;
+  a.coef[3] = L.dt;
+  a.coef[2] = L.fused_b2 * L.dt;
+  a.coef[1] = L.dt;
+  a.coef[0] = 0;
+  a.sa1 = L.fused_a1;
+  a.sa2 = L.fused_a2;
+  for (int f = 0; f < 7; ++f) a.face_off[f] = (int)L.g.face_off[f];
+  a.m0 = L.fused_m0;
+  a.b0 = L.fused_b0;
+  a.a0 = L.a_loc[0];
+  return a;
+}
+
 template <typename T>
 FusedArgs make_args(const abc_launch& L) {
   FusedArgs a{};
@@ -697,15 +1241,79 @@ bool fused_supported(const abc_params& p, std::string* why) {
   return true;
 }
 
+bool fused4_supported(const abc_params& p, std::string* why) {
+  auto no = [&](const char* m) {
+    if (why) *why = m;
+    return false;
+  };
+  if (!fused_supported(p, why)) return false;
+  if (p.batch != 1 || p.meanfield != ABC_MF_NONE) return no("one-pass sweep: one orbital, no mean field");
+  if (p.nx > kCols) return no("one-pass sweep: nx <= 128");
+  if (p.order == ABC_FIRST) {
+    // at most one y-face row and one z-face plane per tile
+    const bool c64 = p.dtype == ABC_C64;
+    const int rows = c64 ? rows4<float>() : rows4<double>();
+    const int tz = c64 ? Tile4<float>::TZ : Tile4<double>::TZ;
+    if (p.ny <= rows || p.nz <= tz + kHalo4)
+      return no("one-pass sweep, first order: ny > rows per tile and nz > planes per tile + 4");
+  }
+  return true;
+}
+
+// The Taylor-4 polynomial 1 + x + x^2/2 + x^3/6 + x^4/24 as the product of
+// two real quadratics (1 + a1 x + b1 x^2)(1 + a2 x + b2 x^2): 24 P(x) =
+// (x^2 + p x + q)(x^2 + (4 - p) x + 24/q) pairs its two conjugate root
+// pairs, with (p, q) solving q + 24/q + p (4 - p) = 12 and
+// 24 p / q + (4 - p) q = 24 (matching the x^2 and x coefficients; x^3 and
+// x^0 hold by construction).  Newton's method from (3.5, 3.8); a_i = p_i/q_i,
+// b_i = 1/q_i.  Returns false unless the product reproduces every
+// coefficient to 1e-14.
+bool taylor4_quadratic_factors(double* a1, double* b1, double* a2, double* b2) {
+  double p = 3.5, q = 3.8;
+  for (int it = 0; it < 50; ++it) {
+    const double f1 = q + 24.0 / q + p * (4.0 - p) - 12.0;
+    const double f2 = 24.0 * p / q + (4.0 - p) * q - 24.0;
+    const double j11 = 4.0 - 2.0 * p, j12 = 1.0 - 24.0 / (q * q);
+    const double j21 = 24.0 / q - q, j22 = -24.0 * p / (q * q) + (4.0 - p);
+    const double det = j11 * j22 - j12 * j21;
+    if (det == 0) return false;
+    const double dp = (f1 * j22 - f2 * j12) / det, dq = (j11 * f2 - j21 * f1) / det;
+    p -= dp;
+    q -= dq;
+    if (std::fabs(dp) + std::fabs(dq) < 1e-16 * (std::fabs(p) + std::fabs(q))) break;
+  }
+  const double p2 = 4.0 - p, q2 = 24.0 / q;
+  *a1 = p / q;
+  *b1 = 1.0 / q;
+  *a2 = p2 / q2;
+  *b2 = 1.0 / q2;
+  // (1 + a1 x + b1 x^2)(1 + a2 x + b2 x^2) against 1, 1, 1/2, 1/6, 1/24
+  const double c1 = *a1 + *a2, c2 = *b1 + *b2 + *a1 * *a2, c3 = *a1 * *b2 + *a2 * *b1, c4 = *b1 * *b2;
+  return std::fabs(c1 - 1.0) < 1e-14 && std::fabs(c2 - 0.5) < 1e-14 && std::fabs(c3 - 1.0 / 6) < 1e-14 &&
+         std::fabs(c4 - 1.0 / 24) < 1e-14;
+}
+
 abc_status fused_prepare(const abc_params& p, abc_launch& L, std::vector<void*>* allocs, size_t* bytes,
                          std::string& err) {
   (void)allocs;
   (void)bytes;
-  (void)err;
-  // two launches of two Horner stages per step (a four-stage pipeline is
-  // register bound in FP64 and measured slower in both precisions); the tile
-  // depth (4, 8 or 16 planes) starts at 8 and is set by the tuner
+  // the one-pass sweep where it covers the parameters (automatic path) or
+  // when asked for, else two launches of two Horner stages per step, whose
+  // tile depth (4, 8 or 16 planes) starts at 8 and is set by the tuner
   L.fused_stages = 2;
+  // Automatic choice: the one-pass sweep wherever it covers the parameters,
+  // except the first order on rows narrower than 128 columns, where its
+  // x-face sources need selects and it measured slower than the two-stage
+  // kernels (96^3: 48 against 39 us per step)
+  const bool auto4 = fused4_supported(p, nullptr) && (p.order != ABC_FIRST || p.nx == kCols);
+  if (p.path == ABC_PATH_ONEPASS || (p.path == ABC_PATH_AUTO && auto4)) {
+    if (!fused4_supported(p, &err)) return ABC_ENOTSUP;
+    if (!taylor4_quadratic_factors(&L.fused_a1, &L.fused_b1, &L.fused_a2, &L.fused_b2)) {
+      err = "one-pass sweep: factoring the Taylor polynomial failed";
+      return ABC_EDEVICE;
+    }
+    L.fused_stages = 4;
+  }
   L.fused_tz = std::min(8, fused_max_tz(p.order, p.nz));
   return ABC_OK;
 }
@@ -716,9 +1324,58 @@ bool fused_tz_valid(const abc_launch& L, int tz) {
 
 namespace {
 
+// One launch per step on the one-pass sweep; the ping-pong is arranged so
+// that the last step writes the caller's buffers.
+template <typename T, int ORDER>
+void launch4(abc_timer* tm, bool full, dim3 g, dim3 b, hipStream_t st, const typename cpx<T>::t* src,
+             typename cpx<T>::t* dst, const T* V, const FusedArgs& a, const double2* fin, double2* fout) {
+  // first order: one plane buffer, so the face slots fit in LDS
+  constexpr bool DB = ORDER != 3;
+  if (full) abc_launch_kernel(tm, "fused_step", fused4_kernel<T, ORDER, true, DB>, g, b, st, src, dst, V, a, fin, fout);
+  else abc_launch_kernel(tm, "fused_step", fused4_kernel<T, ORDER, false, DB>, g, b, st, src, dst, V, a, fin, fout);
+}
+
+template <typename T>
+hipError_t step4_t(const abc_launch& L, const abc_scratch& S, void* psi_v, double2* aux, const void* V_v, int n,
+                   hipStream_t st, abc_timer* tm) {
+  using C = typename cpx<T>::t;
+  FusedArgs a = make_args4<T>(L);
+  a.has_V = V_v != nullptr;
+  C* user = static_cast<C*>(psi_v);
+  C* scr = static_cast<C*>(S.y[0]);
+  C* src = user;
+  C* dst = scr;
+  const bool first = L.order == ABC_FIRST;
+  double2* fsrc = aux;
+  double2* fdst = S.facc;
+  if (n & 1) {
+    hipError_t e = hipMemcpyAsync(scr, user, (size_t)L.g.npts * sizeof(C), hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess && first)
+      e = hipMemcpyAsync(S.facc, aux, (size_t)L.g.face_off[6] * sizeof(double2), hipMemcpyDeviceToDevice, st);
+    if (e != hipSuccess) return e;
+    src = scr;
+    dst = user;
+    fsrc = S.facc;
+    fdst = aux;
+  }
+  const T* V = static_cast<const T*>(V_v);
+  const dim3 g(a.ntiles), b(64 * rows4<T>());
+  const bool full = a.nx == kCols;
+  for (int s = 0; s < n; ++s) {
+    if (L.order == ABC_FIRST) launch4<T, 3>(tm, full, g, b, st, src, dst, V, a, fsrc, fdst);
+    else if (L.order == ABC_ZEROTH) launch4<T, 2>(tm, full, g, b, st, src, dst, V, a, nullptr, nullptr);
+    else launch4<T, 0>(tm, full, g, b, st, src, dst, V, a, nullptr, nullptr);
+    if (tm) tm->end_step();
+    std::swap(src, dst);
+    std::swap(fsrc, fdst);
+  }
+  return hipGetLastError();
+}
+
 template <typename T>
 hipError_t step_t(const abc_launch& L, const abc_scratch& S, void* psi_v, double2* aux, const void* V_v, int n,
                   hipStream_t st, abc_timer* tm) {
+  if (L.fused_stages == 4) return step4_t<T>(L, S, psi_v, aux, V_v, n, st, tm);
   using C = typename cpx<T>::t;
   FusedArgs a = make_args<T>(L);
   a.has_V = V_v != nullptr;

@@ -75,7 +75,9 @@ class Solver:
     | "second" (box form; s_points = its four interpolation points).
     form: "faces" | "box".  dtype: "c128" | "c64".  meanfield: (t0, t3), a dict with
     t0, t3, v0, a, e2, tol, maxit (the Skyrme mean field with Yukawa and Coulomb
-    terms), or None.
+    terms), or None.  path: "auto" | "staged" | "fused" (two launches of two
+    stages per step) | "onepass" (one launch per step); after setup,
+    ``self.path`` names the one chosen.
     """
 
     def __init__(self, shape: Sequence[int], h: float, dt: float, *, radius: int = 1,
@@ -100,7 +102,9 @@ class Solver:
         self._ctx = ctx
         self._lib = lib
         self.aux_elems = int(lib.abc_aux_elems(ctx))
-        self.use_fused = int(lib.abc_path(ctx)) == _lib.PATHS["fused"]
+        code = int(lib.abc_path(ctx))
+        self.path = {v: k for k, v in _lib.PATHS.items()}[code]
+        self.use_fused = self.path in ("fused", "onepass")
 
     # ------------------------------------------------------------------
     def close(self):

@@ -1,0 +1,79 @@
+"""The one-pass sweep (all four stages of a Taylor-4 step in one z-marching
+launch, the step polynomial applied as the product of its two real
+quadratic factors) against the FP64 oracle, element by element: complex128
+at 1e-12 and complex64 at 1e-5 of the largest magnitude, the first order's
+auxiliary values at 1e-12 (they stay FP64) and 1e-5.  Boxes span several
+tiles in y and z with ragged tails (complex128 tiles are 4 rows by 16
+planes, complex64 tiles 8 by 8), including a last tile one row or one plane
+deep, whose face row or plane then lies in the previous tile's halo; narrow,
+odd and full 128-column rows; odd and even step counts (the ping-pong ends
+in the caller's buffers either way).  Also: the full 128^3 headline workload
+agrees with the two-pass fused path, every point compared."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from test_gpu_parity import TOL32, TOL64, _run_pair  # noqa: E402
+from paper_1908_02456_amd import workloads as W  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = [(21, 19, 37), (35, 9, 128), (7, 6, 5), (18, 33, 100)]
+
+
+@pytest.mark.parametrize("order", ["dirichlet", "zeroth"])
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("steps", [3, 4])
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_onepass_parity(order, shape, steps, dtype):
+    r = _run_pair("onepass %s %s" % (order, dtype), shape, 0.25, 0.004, 1, order, steps, dtype=dtype,
+                  path="onepass", seed=7)
+    tol = TOL64 if dtype == "c128" else TOL32
+    assert r["err"] <= tol, r["err"]
+
+
+# first order: ny > rows per tile (12 / 16) and nz > planes per tile + 4
+# (20 / 12), so that a tile meets at most one y-face row and one z-face plane
+FIRST_SHAPES = [(21, 19, 37), (33, 17, 128), (24, 33, 100), (22, 18, 9)]
+
+
+@pytest.mark.parametrize("shape", FIRST_SHAPES)
+@pytest.mark.parametrize("steps", [3, 4])
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_onepass_first_order_parity(shape, steps, dtype):
+    r = _run_pair("onepass first %s" % dtype, shape, 0.25, 0.004, 1, "first", steps, s1=1.5, dtype=dtype,
+                  path="onepass", seed=11)
+    tol = TOL64 if dtype == "c128" else TOL32
+    assert r["err"] <= tol, r["err"]
+    assert r["aux_err"] <= tol, r["aux_err"]
+
+
+@pytest.mark.parametrize("order", ["dirichlet", "first"])
+def test_onepass_headline_size_matches_two_pass(order):
+    from paper_1908_02456_amd.solver import Solver
+    wl = W.well_packet(n=128)
+    print("case: onepass 128^3 %s vs fused two-pass" % order, flush=True)
+    out, aux = [], []
+    for path in ("fused", "onepass"):
+        s = Solver((128,) * 3, wl.h, wl.dt, order=order, s1=wl.s1, path=path)
+        psi = torch.from_numpy(wl.psi0).cuda()
+        a = s.new_aux()
+        s.step(psi, a, torch.from_numpy(wl.V).cuda(), 7)
+        out.append(psi)
+        aux.append(a)
+    torch.cuda.synchronize()
+    d = (out[0] - out[1]).abs().max().item() / out[0].abs().max().item()
+    assert d <= TOL64, d
+    if order == "first":
+        da = (aux[0] - aux[1]).abs().max().item() / aux[0].abs().max().item()
+        assert da <= TOL64, da
+
+
+def test_onepass_refuses_what_it_does_not_cover():
+    from paper_1908_02456_amd.solver import Solver
+    from paper_1908_02456_amd._lib import AbcError
+    with pytest.raises(AbcError):
+        Solver((10, 10, 130), 0.25, 0.004, order="dirichlet", path="onepass")
+    with pytest.raises(AbcError):
+        Solver((10, 10, 10), 0.25, 0.004, order="dirichlet", radius=2, path="onepass")
