@@ -130,7 +130,6 @@ struct abc_launch {
   const int* gamma_lin;       // gamma index -> linear point index
   const int* point_gamma;     // linear point index -> gamma index or -1
   int n_gamma;
-  void* blas;                 // rocBLAS handle for the box form over orbital batches (or null)
 };
 
 struct abc_scratch {

@@ -39,7 +39,6 @@ struct abc_ctx {
   double2* box_mat = nullptr;
   double2* box_q = nullptr;
   std::vector<std::string> launch_labels;  // launches of a step, from the last abc_step_timed
-  rocblas_handle blas = nullptr;           // box form over an orbital batch
   OrbitalBatch* orb = nullptr;             // fused path over an orbital batch / mean field
   abc_launch La{};                         // adjoint operator set (built on first abc_adjoint)
   bool adjoint_ready = false;
@@ -140,7 +139,6 @@ const char* abc_last_error(void) { return g_last_error.c_str(); }
 
 void abc_destroy(abc_ctx* c) {
   if (!c) return;
-  if (c->blas) rocblas_destroy_handle(c->blas);
   if (c->pot.host) (void)hipHostFree(c->pot.host);
   if (c->pot.blas) rocblas_destroy_handle(static_cast<rocblas_handle>(c->pot.blas));
   if (c->orb) {
@@ -286,27 +284,16 @@ abc_status abc_setup(const abc_params* pp, abc_ctx** out) {
       S.bwork[0] = static_cast<double2*>(tmp);
     }
     if (p.form == ABC_FORM_BOX && p.batch > 1) {
-      // the operator over the orbital batch is one complex GEMM per stage;
-      // a first call here lets rocBLAS finish its lazy setup (no allocation
-      // in abc_step afterwards)
+      // the operator over the orbital batch is one complex GEMM per stage
+      // (the gathered E y and the GEMM result)
+      if (p.batch > 64) {
+        abc_destroy(c);
+        return fail(ABC_ENOTSUP, "box form over an orbital batch: at most 64 orbitals");
+      }
       if ((st = dev_alloc(c, &tmp, naux * 16)) != ABC_OK) { abc_destroy(c); return st; }
       S.bwork[0] = static_cast<double2*>(tmp);
       if ((st = dev_alloc(c, &tmp, naux * 16)) != ABC_OK) { abc_destroy(c); return st; }
       S.bwork[1] = static_cast<double2*>(tmp);
-      const int n = c->n_gamma, nb = p.batch;
-      const int ld = abc::box_cols(p.order, n);
-      const rocblas_double_complex one = {1.0, 0.0}, zero = {0.0, 0.0};
-      if (rocblas_create_handle(&c->blas) != rocblas_status_success ||
-          hipMemset(S.bwork[0], 0, naux * 16) != hipSuccess ||
-          rocblas_zgemm_64(c->blas, rocblas_operation_none, rocblas_operation_none, nb, n, n, &one,
-                        reinterpret_cast<const rocblas_double_complex*>(S.bwork[0]), nb,
-                        reinterpret_cast<const rocblas_double_complex*>(L.box_mat), ld, &zero,
-                        reinterpret_cast<rocblas_double_complex*>(S.bwork[1]), nb) != rocblas_status_success ||
-          hipDeviceSynchronize() != hipSuccess) {
-        abc_destroy(c);
-        return fail(ABC_EDEVICE, "rocBLAS setup for the batched box form failed");
-      }
-      L.blas = c->blas;
     }
   }
   if (p.meanfield) {

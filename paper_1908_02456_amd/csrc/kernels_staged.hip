@@ -1368,6 +1368,98 @@ __global__ void __launch_bounds__(kBlock) box_epilogue_kernel(const double2* __r
 
 inline unsigned nblocks(long long n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
+// Box form over an orbital batch: T = Op X, complex FP64, on the matrix cores.
+// Op is the row-major operator (rows x ld); X = [X1; X2] stacks the
+// auxiliary input (na rows, [row][orbital]) on the gathered E y (ld - na
+// rows); T is [row][orbital].  Complex products as four real products
+// (re re - im im, re im + im re) with v_mfma_f64_16x16x4f64, which computes
+// D (16 x 16) += A (16 x 4) B (4 x 16) over the wave: lane l holds A[l % 16][l / 16],
+// B[l / 16][l % 16] and, in its v-th result register, D[l / 16 + 4 v][l % 16].
+// A workgroup owns 16 operator rows and all orbitals (NT tiles of 16
+// columns); its kGemmSplit waves take every kGemmSplit-th chunk of 16 k
+// (split K, so that the launch has one workgroup per 16 rows and still
+// fills the chip), and their partial products are summed in LDS in wave
+// order (deterministic).  In a chunk each lane loads four consecutive
+// operator entries of its row (64 B): k quad kq = l / 16 takes entries
+// 4 kq .. 4 kq + 3, and MFMA j uses entry 4 kq + j (the sum over k is the
+// same in any order; A and B use the same one).  The operator is streamed
+// once per stage for all orbitals; X (K x nb) stays in L2.
+constexpr int kGemmSplit = 8;
+typedef double gemm_d4 __attribute__((ext_vector_type(4)));
+
+template <int NT>
+__global__ void __launch_bounds__(64 * kGemmSplit) box_gemm_kernel(const double2* __restrict__ op, int rows, int ld,
+                                                                  int na, const double2* __restrict__ x1,
+                                                                  const double2* __restrict__ x2, int nb,
+                                                                  double2* __restrict__ t) {
+  __shared__ double2 red[kGemmSplit][NT][4][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int row0 = blockIdx.x * 16;
+  const int ar = lane & 15, kq = lane >> 4;
+  const int arow = row0 + ar;
+  const bool arow_ok = arow < rows;
+  const double2* oprow = op + (long long)(arow_ok ? arow : 0) * ld;
+  gemm_d4 cre[NT], cim[NT];
+#pragma unroll
+  for (int u = 0; u < NT; ++u) cre[u] = cim[u] = gemm_d4{0, 0, 0, 0};
+  for (int k0 = 16 * w; k0 < ld; k0 += 16 * kGemmSplit) {
+    double2 a[4];
+    double2 b[NT][4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int k = k0 + 4 * kq + j;
+      a[j] = (arow_ok && k < ld) ? oprow[k] : make_double2(0, 0);
+      const double2* xr = k < na ? x1 + (long long)k * nb : x2 + (long long)(k - na) * nb;
+#pragma unroll
+      for (int u = 0; u < NT; ++u) {
+        const int col = u * 16 + ar;
+        b[u][j] = (k < ld && col < nb) ? xr[col] : make_double2(0, 0);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+#pragma unroll
+      for (int u = 0; u < NT; ++u) {
+        cre[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[j].x, b[u][j].x, cre[u], 0, 0, 0);
+        cre[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a[j].y, b[u][j].y, cre[u], 0, 0, 0);
+        cim[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[j].x, b[u][j].y, cim[u], 0, 0, 0);
+        cim[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[j].y, b[u][j].x, cim[u], 0, 0, 0);
+      }
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < NT; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) red[w][u][v][lane] = make_double2(cre[u][v], cim[u][v]);
+  __syncthreads();
+  // the waves' partial sums in a fixed order; element e = (u, v, lane)
+  for (int e = threadIdx.x; e < NT * 4 * 64; e += 64 * kGemmSplit) {
+    const int u = e >> 8, v = (e >> 6) & 3, l = e & 63;
+    double2 sum = red[0][u][v][l];
+#pragma unroll
+    for (int q = 1; q < kGemmSplit; ++q) {
+      const double2 p = red[q][u][v][l];
+      sum.x += p.x;
+      sum.y += p.y;
+    }
+    const int row = row0 + (l >> 4) + 4 * v, col = u * 16 + (l & 15);
+    if (row < rows && col < nb) t[(long long)row * nb + col] = sum;
+  }
+}
+
+// T = Op [X1; X2] for nb <= 64 orbitals (one to four column tiles)
+hipError_t box_gemm(abc_timer* tm, const double2* op, int rows, int ld, int na, const double2* x1,
+                    const double2* x2, int nb, double2* t, hipStream_t st) {
+  const dim3 g((unsigned)((rows + 15) / 16)), b(64 * kGemmSplit);
+  const int nt = (nb + 15) / 16;
+  if (nt == 1) abc_launch_kernel(tm, "box_gemm", box_gemm_kernel<1>, g, b, st, op, rows, ld, na, x1, x2, nb, t);
+  else if (nt == 2) abc_launch_kernel(tm, "box_gemm", box_gemm_kernel<2>, g, b, st, op, rows, ld, na, x1, x2, nb, t);
+  else if (nt == 3) abc_launch_kernel(tm, "box_gemm", box_gemm_kernel<3>, g, b, st, op, rows, ld, na, x1, x2, nb, t);
+  else if (nt == 4) abc_launch_kernel(tm, "box_gemm", box_gemm_kernel<4>, g, b, st, op, rows, ld, na, x1, x2, nb, t);
+  else return hipErrorInvalidValue;
+  return hipSuccess;
+}
+
 template <typename T, int R, bool PER>
 hipError_t step_staged_t(const abc_launch& L, const abc_scratch& S, void* psi_v, double2* aux,
                          const void* V_v, int n_steps, hipStream_t st, abc_timer* tm, void* const* keep,
@@ -1417,10 +1509,10 @@ hipError_t step_staged_t(const abc_launch& L, const abc_scratch& S, void* psi_v,
       double2* merged_gnext = nullptr;
       if (rec || zeroth) {
         double2* gnext = (k == 4) ? nullptr : S.g[(k - 1) & 1];
-        if (box && L.blas && g.batch > 1) {
-          // Y^T = X^T M^T in rocBLAS's column-major view of the row-major
-          // operator (rows x (na + n)): T = [B | A] [g; E y] (first),
-          // the 2n rows of the second order, or M E y (zeroth)
+        if (box && g.batch > 1) {
+          // one complex GEMM over the orbitals on the matrix cores: T =
+          // [B | A] [g; E y] (first), the 2n rows of the second order, or
+          // M E y (zeroth); the operator is read once for all orbitals
           const int n = L.n_gamma, nb = g.batch;
           const int na = abc::box_aux_rows(L.order, n), rows = abc::box_rows(L.order, n);
           const int ld = abc::box_cols(L.order, n);
@@ -1428,21 +1520,9 @@ hipError_t step_staged_t(const abc_launch& L, const abc_scratch& S, void* psi_v,
           abc_launch_kernel(tm, kBoundLabel[k], box_gather_kernel<T>, dim3(nblocks(ng)), dim3(kBlock), st,
                             (const C*)ycur, L.gamma_lin, n, nb, S.bwork[0]);
           double2* tout = rec ? S.bwork[1] : S.src;
-          if (tm) tm->mark_host(st, "box_gemm");
-          const rocblas_double_complex one = {1.0, 0.0}, zero = {0.0, 0.0};
-          rocblas_handle hb = static_cast<rocblas_handle>(L.blas);
-          rocblas_status rs = rocblas_set_stream(hb, st);
-          if (rs == rocblas_status_success && rec)
-            rs = rocblas_zgemm_64(hb, rocblas_operation_none, rocblas_operation_none, nb, rows, na, &one,
-                               reinterpret_cast<const rocblas_double_complex*>(gcur), nb,
-                               reinterpret_cast<const rocblas_double_complex*>(L.box_mat), ld, &zero,
-                               reinterpret_cast<rocblas_double_complex*>(tout), nb);
-          if (rs == rocblas_status_success)
-            rs = rocblas_zgemm_64(hb, rocblas_operation_none, rocblas_operation_none, nb, rows, n, &one,
-                               reinterpret_cast<const rocblas_double_complex*>(S.bwork[0]), nb,
-                               reinterpret_cast<const rocblas_double_complex*>(L.box_mat + na), ld,
-                               rec ? &one : &zero, reinterpret_cast<rocblas_double_complex*>(tout), nb);
-          if (rs != rocblas_status_success) return hipErrorLaunchFailure;
+          const hipError_t ge = box_gemm(tm, L.box_mat, rows, ld, na, rec ? gcur : nullptr,
+                                         (const double2*)S.bwork[0], nb, tout, st);
+          if (ge != hipSuccess) return ge;
           if (rec)
             abc_launch_kernel(tm, "box_epilogue", box_epilogue_kernel, dim3(nblocks(cnt)), dim3(kBlock), st,
                               (const double2*)tout, gcur, gnext, S.facc, aux, cnt, coef, mode);

@@ -333,12 +333,32 @@ def test_fused_first_order_small_box_falls_back():
                                         (1, "first", 2.0)])
 def test_box_form_orbital_batch_parity(R, order, s2):
     # box form over an orbital batch: the operator is applied as one complex
-    # GEMM per stage (rocBLAS) instead of one matrix pass per orbital
+    # GEMM per stage (FP64 matrix cores) instead of one matrix pass per orbital
     n = 6 if R == 1 else 7
     r = _run_pair("box-batch", (n, n, n), 0.3, 0.004, R, order, 5, form="box", s0=1.0, s1=1.0, s2=s2, batch=5)
     assert r["err"] < TOL64, r["err"]
     if order == "first":
         assert r["aux_err"] < TOL64, r["aux_err"]
+
+
+@pytest.mark.parametrize("order,batch", [("first", 17), ("zeroth", 33), ("first", 64), ("zeroth", 2)])
+def test_box_form_orbital_batch_gemm_tiles(order, batch):
+    # the GEMM's ragged edges: n_Gamma = 7^3 - 5^3 = 218 operator rows (not a
+    # multiple of the 16-row wave tile or the 64-row workgroup), K = 436 (first
+    # order, [B | A]) or 218 (zeroth), both off the 16-wide k chunk, and 2, 17,
+    # 33 or 64 orbitals (one to four 16-column tiles, ragged but the last)
+    r = _run_pair("box-batch-gemm", (7, 7, 7), 0.3, 0.004, 1, order, 3, form="box", s0=1.0, s1=1.0,
+                  batch=batch, seed=5)
+    assert r["err"] < TOL64, r["err"]
+    if order == "first":
+        assert r["aux_err"] < TOL64, r["aux_err"]
+
+
+def test_box_form_orbital_batch_over_64_is_refused():
+    Solver = _gpu()
+    from paper_1908_02456_amd._lib import AbcError
+    with pytest.raises(AbcError):
+        Solver((6, 6, 6), 0.3, 0.004, order="zeroth", form="box", batch=65)
 
 
 @pytest.mark.parametrize("batch,meanfield,dtype,order", [(3, None, "c128", "first"), (5, (-1.0, 0.5), "c128", "first"),
