@@ -127,7 +127,9 @@ typedef struct {
                          mean field, nx <= 128 and, for the first order,
                          ny > 12 / 16 and nz > 20 / 12 (complex128 /
                          complex64); ABC_PATH_STAGED the general path     */
-  int reserved[3];    /* must be zero                                       */
+  int diag_every;     /* abc_step_monitored: steps between diagnostic records
+                         (>= 1 to monitor; 0 = no monitoring)               */
+  int reserved[2];    /* must be zero                                       */
   double s3, s4;      /* second order: the last two interpolation points;
                          s1..s4 positive and distinct                       */
   /* ABC_MF_SKYRME (Sec. 4.3): U = t0 rho + t3 rho^2 + W_Y + W_C with
@@ -169,6 +171,33 @@ abc_status abc_setup(const abc_params* p, abc_ctx** out);
  * iterations. */
 abc_status abc_step(abc_ctx* ctx, void* psi, void* aux, const void* V,
                     int n_steps, void* stream);
+
+/* Flags of abc_step_monitored. */
+enum { ABC_FLAG_NONFINITE = 1, ABC_FLAG_W_INCREASE = 2 };
+
+/* abc_step with in-step monitoring (Sec. 3: the zeroth- and first-order
+ * stability proofs make the Lyapunov functional W non-increasing).  After
+ * every p.diag_every-th step counted over the context's monitored calls,
+ * the norm, W and the energy of the state (the abc_diagnostics output,
+ * 3*batch + 1 doubles) go to the device ring `ring` as one record of
+ * 3*batch + 2 doubles: the step count, then that output; the k-th record
+ * since setup goes to slot k mod ring_len.  The device word `flags`
+ * (caller-owned, zero it to start) collects, by atomic or:
+ *   ABC_FLAG_NONFINITE   a record holds a NaN or infinity (a blown-up or
+ *                        corrupted state);
+ *   ABC_FLAG_W_INCREASE  W of some orbital grew by more than 1e-12 of its
+ *                        value since the previous record (zeroth and first
+ *                        order, Dirichlet and periodic boxes; the second
+ *                        order has no such functional and is not checked).
+ * The host reads flags and the ring when it wishes (after synchronising the
+ * stream); nothing here synchronises.  The records are separate reduction
+ * launches on diagnostic steps only (the energy needs H of the new state,
+ * which the sweeps do not form), using the context's reduction scratch:
+ * one monitored call per context at a time.  ABC_EINVAL if p.diag_every
+ * < 1, ring_len < 1 or a pointer is null. */
+abc_status abc_step_monitored(abc_ctx* ctx, void* psi, void* aux, const void* V,
+                              int n_steps, void* stream, double* ring, int ring_len,
+                              unsigned* flags);
 
 /* Measurement run: advances the state by n_steps (>= 1) exactly as abc_step
  * does, but issues every kernel launch through hipExtLaunchKernel with a

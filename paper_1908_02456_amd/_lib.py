@@ -6,12 +6,14 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libabc_dtn.so")
+# ABC_DTN_LIBRARY names another build of the same ABI (the host-sanitizer one)
+LIB_PATH = os.environ.get("ABC_DTN_LIBRARY") or os.path.join(HERE, "libabc_dtn.so")
 
 ABC_OK, ABC_EINVAL, ABC_ENOMEM, ABC_EDEVICE, ABC_EUNSTABLE, ABC_ENOTSUP, ABC_EIO = 0, -1, -2, -3, -4, -5, -6
 STATUS_NAMES = {0: "ABC_OK", -1: "ABC_EINVAL", -2: "ABC_ENOMEM", -3: "ABC_EDEVICE",
                 -4: "ABC_EUNSTABLE", -5: "ABC_ENOTSUP", -6: "ABC_EIO"}
 ABC_BATCH_GRAPH = 1
+ABC_FLAG_NONFINITE, ABC_FLAG_W_INCREASE = 1, 2
 ORDERS = {"dirichlet": 0, "periodic": 1, "zeroth": 2, "first": 3, "second": 4}
 FORMS = {"box": 0, "faces": 1}
 DTYPES = {"c128": 0, "c64": 1}
@@ -24,7 +26,7 @@ EXPORTED = ["abc_params_default", "abc_setup", "abc_step", "abc_diagnostics", "a
             "abc_step_batch", "abc_tune_batch", "abc_batch_aux_elems", "abc_batch_launch_groups",
             "abc_batch_tile_depth", "abc_destroy_batch", "abc_h2_objective",
             "abc_effective_potential", "abc_potential_iterations", "abc_state_save", "abc_state_load",
-            "abc_diagnostics_noalloc"]
+            "abc_diagnostics_noalloc", "abc_step_monitored"]
 
 
 class AbcParams(ctypes.Structure):
@@ -36,7 +38,7 @@ class AbcParams(ctypes.Structure):
         ("window", ctypes.c_int), ("fejer", ctypes.c_int), ("dtype", ctypes.c_int),
         ("batch", ctypes.c_int), ("meanfield", ctypes.c_int),
         ("t0", ctypes.c_double), ("t3", ctypes.c_double),
-        ("path", ctypes.c_int), ("reserved", ctypes.c_int * 3),
+        ("path", ctypes.c_int), ("diag_every", ctypes.c_int), ("reserved", ctypes.c_int * 2),
         ("s3", ctypes.c_double), ("s4", ctypes.c_double),
         ("v0", ctypes.c_double), ("a_yukawa", ctypes.c_double), ("e2", ctypes.c_double),
         ("pcg_tol", ctypes.c_double), ("pcg_maxit", ctypes.c_int), ("reserved2", ctypes.c_int * 3),
@@ -106,6 +108,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.abc_diagnostics.restype = ctypes.c_int
     lib.abc_diagnostics_noalloc.argtypes = [vp, vp, vp, vp, vp, vp]
     lib.abc_diagnostics_noalloc.restype = ctypes.c_int
+    lib.abc_step_monitored.argtypes = [vp, vp, vp, vp, ctypes.c_int, vp, vp, ctypes.c_int, vp]
+    lib.abc_step_monitored.restype = ctypes.c_int
     lib.abc_aux_elems.argtypes = [vp]
     lib.abc_aux_elems.restype = ctypes.c_size_t
     lib.abc_export.argtypes = [vp, ctypes.c_int, vp, ctypes.c_size_t]

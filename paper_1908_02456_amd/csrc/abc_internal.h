@@ -251,3 +251,8 @@ hipError_t launch_diagnostics(const abc_launch& L, const abc_scratch& S, const v
 
 // Doubles of reduction partials one diagnostics call writes for a batch.
 size_t diag_partial_doubles(int batch);
+
+// One-block check of a monitor record (abc_step_monitored): writes the step
+// count to rec[0] and ors the ABC_FLAG_* conditions of rec[1..] into *flags.
+hipError_t launch_monitor_check(double* rec, int batch, long long step, double* prevW, bool have_prev, bool check_w,
+                                double tol, unsigned* flags, hipStream_t st);

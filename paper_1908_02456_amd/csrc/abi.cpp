@@ -44,6 +44,9 @@ struct abc_ctx {
   bool adjoint_ready = false;
   PotentialSolver pot;                     // ABC_MF_SKYRME solves
   FaceFFT fft{};                           // exact face sections by FFT
+  long long mon_steps = 0;                 // steps taken by abc_step_monitored
+  long long mon_records = 0;               // records it has written
+  double* mon_prevW = nullptr;             // W of the last record, per orbital
 };
 
 namespace {
@@ -101,7 +104,8 @@ abc_status check_params(const abc_params& p) {
     if (p.form != ABC_FORM_BOX)
       return fail(ABC_ENOTSUP, "second order: box form only (the face sections lose stability)");
   }
-  for (int i = 0; i < 3; ++i)
+  if (p.diag_every < 0) return fail(ABC_EINVAL, "diag_every must be >= 0");
+  for (int i = 0; i < 2; ++i)
     if (p.reserved[i] != 0) return fail(ABC_EINVAL, "reserved fields must be zero");
   return ABC_OK;
 }
@@ -431,6 +435,45 @@ abc_status abc_step(abc_ctx* c, void* psi, void* aux, const void* V, int n_steps
   else
     e = launch_step_staged(c->L, c->S, psi, static_cast<double2*>(aux), V, n_steps, st);
   if (e != hipSuccess) return fail(ABC_EDEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
+  return ABC_OK;
+}
+
+abc_status abc_step_monitored(abc_ctx* c, void* psi, void* aux, const void* V, int n_steps, void* stream,
+                              double* ring, int ring_len, unsigned* flags) {
+  if (!c || !psi || !ring || !flags) return fail(ABC_EINVAL, "null argument");
+  if (c->p.diag_every < 1) return fail(ABC_EINVAL, "abc_step_monitored: the context's diag_every must be >= 1");
+  if (ring_len < 1) return fail(ABC_EINVAL, "abc_step_monitored: ring_len must be >= 1");
+  if (n_steps < 0) return fail(ABC_EINVAL, "n_steps must be >= 0");
+  if (c->aux_elems && !aux) return fail(ABC_EINVAL, "first and second order need the aux buffer");
+  const int B = c->p.batch;
+  if (!c->mon_prevW) {
+    void* ptr = nullptr;
+    abc_status s = dev_alloc(c, &ptr, sizeof(double) * B);
+    if (s != ABC_OK) return s;
+    c->mon_prevW = static_cast<double*>(ptr);
+  }
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  // W is non-increasing for every order but the second (Sec. 3); an FP32
+  // state carries rounding noise of about 1e-7 in it
+  const bool check_w = c->p.order != ABC_SECOND;
+  const double tol = c->p.dtype == ABC_C64 ? 1e-6 : 1e-12;
+  const size_t rec_len = 3 * (size_t)B + 2;
+  const int every = c->p.diag_every;
+  int left = n_steps;
+  while (left > 0) {
+    const int k = std::min<long long>(left, every - c->mon_steps % every);
+    abc_status s = abc_step(c, psi, aux, V, k, stream);
+    if (s != ABC_OK) return s;
+    c->mon_steps += k;
+    left -= k;
+    if (c->mon_steps % every != 0) continue;
+    double* rec = ring + (size_t)(c->mon_records % ring_len) * rec_len;
+    hipError_t e = launch_diagnostics(c->L, c->S, psi, static_cast<const double2*>(aux), V, rec + 1, st);
+    if (e == hipSuccess)
+      e = launch_monitor_check(rec, B, c->mon_steps, c->mon_prevW, c->mon_records > 0, check_w, tol, flags, st);
+    if (e != hipSuccess) return fail(ABC_EDEVICE, std::string("monitor launch: ") + hipGetErrorString(e));
+    ++c->mon_records;
+  }
   return ABC_OK;
 }
 

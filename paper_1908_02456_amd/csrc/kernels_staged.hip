@@ -1666,6 +1666,36 @@ hipError_t launch_diagnostics(const abc_launch& L, const abc_scratch& S, const v
 
 size_t diag_partial_doubles(int batch) { return (size_t)batch * (kRedBlocks + kAuxBlocks) * 4; }
 
+// Monitor record check (one block).  rec = [step, the 3 B + 1 diagnostics]:
+// stores the step count, raises ABC_FLAG_NONFINITE if a diagnostic is NaN or
+// infinite and, with check_w, ABC_FLAG_W_INCREASE if an orbital's W exceeds
+// its previous record by more than tol of that value (the zeroth- and
+// first-order theorems of Sec. 3 make W non-increasing); the new W values
+// then become the previous ones.
+__global__ void __launch_bounds__(256) monitor_check_kernel(double* __restrict__ rec, int B, double step,
+                                                            double* __restrict__ prevW, int have_prev, int check_w,
+                                                            double tol, unsigned* __restrict__ flags) {
+  const int t = threadIdx.x;
+  if (t == 0) rec[0] = step;
+  const double* d = rec + 1;
+  unsigned f = 0;
+  for (int i = t; i < 3 * B + 1; i += blockDim.x)
+    if (!isfinite(d[i])) f |= ABC_FLAG_NONFINITE;
+  for (int j = t; j < B; j += blockDim.x) {
+    const double w = d[B + j];
+    if (check_w && have_prev && w - prevW[j] > tol * fabs(prevW[j])) f |= ABC_FLAG_W_INCREASE;
+    prevW[j] = w;
+  }
+  if (f) atomicOr(flags, f);
+}
+
+hipError_t launch_monitor_check(double* rec, int batch, long long step, double* prevW, bool have_prev, bool check_w,
+                                double tol, unsigned* flags, hipStream_t st) {
+  monitor_check_kernel<<<1, 256, 0, st>>>(rec, batch, (double)step, prevW, have_prev ? 1 : 0, check_w ? 1 : 0, tol,
+                                          flags);
+  return hipGetLastError();
+}
+
 // FFT plan of the exact face sections: padded sizes per face pair, work
 // slabs, twiddle tables, and the kernel spectra (the padded R x R kernel
 // layers transformed on the device)

@@ -27,7 +27,7 @@ SECOND_ORDER_POINTS = (1.0, 2.0, 3.0, 10.0)
 
 def make_params(shape, h, dt, *, radius=1, order="first", form="faces", s0=1.0, s1=1.0, s2=0.0, window=0,
                 fejer=True, dtype="c128", batch=1, meanfield=None, path="auto",
-                s_points=None) -> _lib.AbcParams:
+                s_points=None, diag_every=0) -> _lib.AbcParams:
     """abc_params for a box of shape (nz, ny, nx) (see include/abc_dtn.h).
     s_points: the four interpolation points of the second order (default
     SECOND_ORDER_POINTS); s1, s2 are the first order's."""
@@ -65,6 +65,7 @@ def make_params(shape, h, dt, *, radius=1, order="first", form="faces", s0=1.0, 
         p.meanfield = 1
         p.t0, p.t3 = float(meanfield[0]), float(meanfield[1])
     p.path = _lib.PATHS[path]
+    p.diag_every = int(diag_every)
     return p
 
 
@@ -77,17 +78,19 @@ class Solver:
     t0, t3, v0, a, e2, tol, maxit (the Skyrme mean field with Yukawa and Coulomb
     terms), or None.  path: "auto" | "staged" | "fused" (two launches of two
     stages per step) | "onepass" (one launch per step); after setup,
-    ``self.path`` names the one chosen.
+    ``self.path`` names the one chosen.  diag_every: steps between the
+    records of step_monitored (0: no monitoring).
     """
 
     def __init__(self, shape: Sequence[int], h: float, dt: float, *, radius: int = 1,
                  order: str = "first", form: str = "faces", s0: float = 1.0, s1: float = 1.0,
                  s2: float = 0.0, window: int = 0, fejer: bool = True, dtype: str = "c128",
-                 batch: int = 1, meanfield=None, path: str = "auto", device=None, s_points=None):
+                 batch: int = 1, meanfield=None, path: str = "auto", device=None, s_points=None,
+                 diag_every: int = 0):
         lib = _lib.load()
         p = make_params(shape, h, dt, radius=radius, order=order, form=form, s0=s0, s1=s1, s2=s2,
                         window=window, fejer=fejer, dtype=dtype, batch=batch, meanfield=meanfield, path=path,
-                        s_points=s_points)
+                        s_points=s_points, diag_every=diag_every)
         nz, ny, nx = (int(v) for v in shape)
         self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
         self.params = p
@@ -153,6 +156,29 @@ class Solver:
         vp = self._check_V(V)
         ap = self._check_aux(aux)
         _lib.check(self._lib.abc_step(self._ctx, psi.data_ptr(), ap, vp, int(n_steps), _stream_handle(stream)))
+        return psi
+
+    def new_monitor(self, ring_len: int = 16):
+        """(ring, flags) for step_monitored: ring_len records of 3*batch+2
+        float64 (step count, then the diagnostics), and a zeroed int32 flag word."""
+        ring = torch.zeros((int(ring_len), 3 * self.batch + 2), dtype=torch.float64, device=self.device)
+        return ring, torch.zeros(1, dtype=torch.int32, device=self.device)
+
+    def step_monitored(self, psi, ring, flags, aux=None, V=None, n_steps: int = 1, stream=None):
+        """step() with a diagnostics record every diag_every steps into ``ring``
+        and the _lib.ABC_FLAG_* failure flags or-ed into ``flags`` (both on the
+        device; read them after synchronising)."""
+        self._check_psi(psi)
+        vp = self._check_V(V)
+        ap = self._check_aux(aux)
+        if ring.dtype != torch.float64 or ring.dim() != 2 or ring.shape[1] != 3 * self.batch + 2 \
+                or not ring.is_contiguous() or ring.device.type != "cuda":
+            raise ValueError("ring must be a contiguous float64 CUDA tensor of shape (n, %d)" % (3 * self.batch + 2))
+        if flags.dtype != torch.int32 or flags.numel() < 1 or flags.device.type != "cuda":
+            raise ValueError("flags must be an int32 CUDA tensor")
+        _lib.check(self._lib.abc_step_monitored(self._ctx, psi.data_ptr(), ap, vp, int(n_steps),
+                                                _stream_handle(stream), ring.data_ptr(), int(ring.shape[0]),
+                                                flags.data_ptr()))
         return psi
 
     def step_timed(self, psi, aux=None, V=None, n_steps: int = 1, stream=None, cap: int = 64):

@@ -48,7 +48,7 @@ int main(void) {
   printf("%zu", sizeof(abc_params));
 #define F(x) printf(" %zu", offsetof(abc_params, x));
   F(nx) F(ny) F(nz) F(h) F(dt) F(radius) F(order) F(form) F(s0) F(s1) F(s2) F(window) F(fejer)
-  F(dtype) F(batch) F(meanfield) F(t0) F(t3) F(path) F(reserved) F(s3) F(s4) F(v0) F(a_yukawa) F(e2)
+  F(dtype) F(batch) F(meanfield) F(t0) F(t3) F(path) F(diag_every) F(reserved) F(s3) F(s4) F(v0) F(a_yukawa) F(e2)
   F(pcg_tol) F(pcg_maxit) F(reserved2)
   printf("\n");
   return 0;
@@ -62,7 +62,8 @@ int main(void) {
         vals = [int(v) for v in subprocess.run([exe], capture_output=True, text=True).stdout.split()]
     P = _lib.AbcParams
     names = ["nx", "ny", "nz", "h", "dt", "radius", "order", "form", "s0", "s1", "s2", "window", "fejer",
-             "dtype", "batch", "meanfield", "t0", "t3", "path", "reserved", "s3", "s4", "v0", "a_yukawa", "e2",
+             "dtype", "batch", "meanfield", "t0", "t3", "path", "diag_every", "reserved", "s3", "s4", "v0", "a_yukawa",
+             "e2",
              "pcg_tol", "pcg_maxit", "reserved2"]
     assert vals[0] == ctypes.sizeof(P)
     assert vals[1:] == [getattr(P, n).offset for n in names]
@@ -103,6 +104,7 @@ BAD_PARAMS = [
     (dict(meanfield=4), _lib.ABC_EINVAL, b"mean field"),
     (dict(path=7), _lib.ABC_EINVAL, b"path"),
     (dict(window=-1), _lib.ABC_EINVAL, b"window"),
+    (dict(diag_every=-1), _lib.ABC_EINVAL, b"diag_every"),
     (dict(order=2, s0=0.0), _lib.ABC_EUNSTABLE, b"s0"),
     (dict(order=3, s1=-1.0), _lib.ABC_EUNSTABLE, b"s1"),
     (dict(order=3, form=1, s2=2.0), _lib.ABC_ENOTSUP, b"face form"),
@@ -139,11 +141,11 @@ def test_reserved_fields_must_be_zero(lib):
     lib.abc_params_default(ctypes.byref(p))
     p.nx = p.ny = p.nz = 8
     p.h, p.dt = 0.25, 0.004
-    p.reserved[2] = 1
+    p.reserved[1] = 1
     ctx = ctypes.c_void_p()
     assert lib.abc_setup(ctypes.byref(p), ctypes.byref(ctx)) == _lib.ABC_EINVAL
     assert b"reserved" in lib.abc_last_error()
-    p.reserved[2] = 0
+    p.reserved[1] = 0
     p.reserved2[1] = 1
     assert lib.abc_setup(ctypes.byref(p), ctypes.byref(ctx)) == _lib.ABC_EINVAL
     assert b"reserved" in lib.abc_last_error()
@@ -183,6 +185,7 @@ def test_null_arguments_are_rejected_without_a_device(lib):
     assert lib.abc_adjoint(None, None, None, 1, 0, 0, None, None, ctypes.byref(J), None) == _lib.ABC_EINVAL
     assert lib.abc_diagnostics(None, None, None, None, None, None) == _lib.ABC_EINVAL
     assert lib.abc_diagnostics_noalloc(None, None, None, None, None, None) == _lib.ABC_EINVAL
+    assert lib.abc_step_monitored(None, None, None, None, 1, None, None, 1, None) == _lib.ABC_EINVAL
     assert lib.abc_export(None, 0, None, 0) == _lib.ABC_EINVAL
     assert lib.abc_tune(None, None, None, None, None, None) == _lib.ABC_EINVAL
     b = vp()
