@@ -660,6 +660,8 @@ def main():
                     help="also run the paper's 3D experiment at its own size (31^3, R = 3, dense box operators)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the batch / adjoint / c64 / TDHF figures")
+    ap.add_argument("--only-extra", default="",
+                    help="comma-separated names: run only these of the extra figures (e.g. tdhf,batch)")
     ap.add_argument("--copy-gib", type=float, default=0.0,
                     help="also run one plain device copy of this size (calibrates rocprofv3 byte counters)")
     args = ap.parse_args()
@@ -737,6 +739,7 @@ def main():
         torch.cuda.synchronize()
         out["copy_calibration_bytes"] = 2 * nb
         del src_t, dst_t
+    only = set(v for v in args.only_extra.split(",") if v)
     if not args.no_extra:
         from paper_1908_02456_amd.solver import Batch
         extra = {}
@@ -751,6 +754,8 @@ def main():
                          ("box64", lambda: bench_box64(Solver, torch, W)),
                          ("h2_point", lambda: bench_h2_point(Solver, torch, wl)),
                          ("face_windows", lambda: bench_face_windows(Solver, torch, wl))):
+            if only and name not in only:
+                continue
             log("extra: %s" % name)
             try:
                 extra[name] = fn()
