@@ -106,6 +106,14 @@ struct FaceFFT {
   double2 *W, *Z, *spec, *tw;
 };
 
+// Boundary-shell buffers of the one-pass sweep with a non-local face
+// operator: four psi-sized arrays (only their shell points are used) and two
+// face-aux arrays.
+struct ShellScratch {
+  void* vol[4];
+  double2* face[2];
+};
+
 struct abc_launch {
   abc::Geometry g;
   double h, dt;
@@ -123,6 +131,8 @@ struct abc_launch {
   // one-pass sweep: the step polynomial as (1 + a1 x + b1 x^2)(1 + a2 x + b2 x^2)
   double fused_a1, fused_b1, fused_a2, fused_b2;
   int fused_stages;            // 4: one launch per step; 2: two launches
+  int fused_shell;             // one-pass sweep plus boundary-shell rounds (first order, window > 0)
+  ShellScratch shell;
   int fused_tz;                // planes per tile of the two-stage kernel (4, 8, 16)
   // box form
   const double2* box_mat;
@@ -248,6 +258,13 @@ abc_status run_adjoint(const abc_launch& L, const abc_launch& La, const abc_scra
 hipError_t launch_diagnostics(const abc_launch& L, const abc_scratch& S, const void* psi,
                               const double2* aux, const void* V, double* out, hipStream_t st,
                               double* red = nullptr);
+
+// Boundary-shell rounds of the one-pass sweep (first order, face form with a
+// non-local operator, R = 1, one orbital): from the step's input (psi, f)
+// they write the new aux to fout and add the boundary's correction to
+// psi_out, the condition-free sweep of the same input.
+hipError_t launch_shell_rounds(const abc_launch& L, const ShellScratch& W, const void* psi, const void* V,
+                               const double2* f, double2* fout, void* psi_out, hipStream_t st, abc_timer* tm);
 
 // Doubles of reduction partials one diagnostics call writes for a batch.
 size_t diag_partial_doubles(int batch);

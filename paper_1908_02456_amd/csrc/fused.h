@@ -11,6 +11,9 @@
 bool fused_supported(const abc_params& p, std::string* why);
 // the same for the one-pass sweep (all four stages in one launch)
 bool fused4_supported(const abc_params& p, std::string* why);
+// first order in the face form with a non-local operator (window > 0): the
+// one-pass sweep runs without the condition plus the boundary-shell rounds
+bool fused_shell_case(const abc_params& p);
 
 // allocate/prepare whatever the fused path needs beyond the staged scratch
 abc_status fused_prepare(const abc_params& p, abc_launch& L, std::vector<void*>* allocs, size_t* bytes,

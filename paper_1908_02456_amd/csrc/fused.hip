@@ -1241,11 +1241,25 @@ bool fused_supported(const abc_params& p, std::string* why) {
   return true;
 }
 
+bool fused_shell_case(const abc_params& p) {
+  return p.order == ABC_FIRST && p.form == ABC_FORM_FACES && p.window > 0;
+}
+
 bool fused4_supported(const abc_params& p, std::string* why) {
   auto no = [&](const char* m) {
     if (why) *why = m;
     return false;
   };
+  if (fused_shell_case(p)) {
+    // the condition-free sweep plus the boundary-shell rounds: the sweep's
+    // own limits, R = 1 and one orbital
+    if (p.radius != 1) return no("one-pass sweep with a windowed face operator: radius 1 only");
+    if (p.batch != 1 || p.meanfield != ABC_MF_NONE) return no("one-pass sweep: one orbital, no mean field");
+    abc_params q = p;
+    q.order = ABC_DIRICHLET;
+    q.window = 0;
+    return fused4_supported(q, why);
+  }
   if (!fused_supported(p, why)) return false;
   if (p.batch != 1 || p.meanfield != ABC_MF_NONE) return no("one-pass sweep: one orbital, no mean field");
   if (p.nx > kCols) return no("one-pass sweep: nx <= 128");
@@ -1295,8 +1309,6 @@ bool taylor4_quadratic_factors(double* a1, double* b1, double* a2, double* b2) {
 
 abc_status fused_prepare(const abc_params& p, abc_launch& L, std::vector<void*>* allocs, size_t* bytes,
                          std::string& err) {
-  (void)allocs;
-  (void)bytes;
   // the one-pass sweep where it covers the parameters (automatic path) or
   // when asked for, else two launches of two Horner stages per step, whose
   // tile depth (4, 8 or 16 planes) starts at 8 and is set by the tuner
@@ -1305,7 +1317,9 @@ abc_status fused_prepare(const abc_params& p, abc_launch& L, std::vector<void*>*
   // except the first order on rows narrower than 128 columns, where its
   // x-face sources need selects and it measured slower than the two-stage
   // kernels (96^3: 48 against 39 us per step)
-  const bool auto4 = fused4_supported(p, nullptr) && (p.order != ABC_FIRST || p.nx == kCols);
+  const bool auto4 =
+      fused4_supported(p, nullptr) && (p.order != ABC_FIRST || p.nx == kCols || fused_shell_case(p));
+  L.fused_shell = 0;
   if (p.path == ABC_PATH_ONEPASS || (p.path == ABC_PATH_AUTO && auto4)) {
     if (!fused4_supported(p, &err)) return ABC_ENOTSUP;
     if (!taylor4_quadratic_factors(&L.fused_a1, &L.fused_b1, &L.fused_a2, &L.fused_b2)) {
@@ -1313,6 +1327,24 @@ abc_status fused_prepare(const abc_params& p, abc_launch& L, std::vector<void*>*
       return ABC_EDEVICE;
     }
     L.fused_stages = 4;
+    if (fused_shell_case(p)) {
+      // four psi-sized and two face-aux buffers for the boundary-shell rounds
+      L.fused_shell = 1;
+      const size_t vb = (size_t)L.g.npts * (p.dtype == ABC_C64 ? 8 : 16);
+      const size_t fb = (size_t)L.g.face_off[6] * sizeof(double2);
+      for (int i = 0; i < 6; ++i) {
+        void* ptr = nullptr;
+        const size_t nb = i < 4 ? vb : fb;
+        if (hipMalloc(&ptr, nb) != hipSuccess) {
+          err = "one-pass sweep: boundary-shell buffers";
+          return ABC_ENOMEM;
+        }
+        allocs->push_back(ptr);
+        *bytes += nb;
+        if (i < 4) L.shell.vol[i] = ptr;
+        else L.shell.face[i - 4] = static_cast<double2*>(ptr);
+      }
+    }
   }
   L.fused_tz = std::min(8, fused_max_tz(p.order, p.nz));
   return ABC_OK;
@@ -1362,7 +1394,13 @@ hipError_t step4_t(const abc_launch& L, const abc_scratch& S, void* psi_v, doubl
   const dim3 g(a.ntiles), b(64 * rows4<T>());
   const bool full = a.nx == kCols;
   for (int s = 0; s < n; ++s) {
-    if (L.order == ABC_FIRST) launch4<T, 3>(tm, full, g, b, st, src, dst, V, a, fsrc, fdst);
+    if (L.fused_shell) {
+      // the condition-free sweep, then the boundary-shell rounds (new aux,
+      // the boundary's correction added to the swept state)
+      launch4<T, 0>(tm, full, g, b, st, src, dst, V, a, nullptr, nullptr);
+      const hipError_t e = launch_shell_rounds(L, L.shell, src, V_v, fsrc, fdst, dst, st, tm);
+      if (e != hipSuccess) return e;
+    } else if (L.order == ABC_FIRST) launch4<T, 3>(tm, full, g, b, st, src, dst, V, a, fsrc, fdst);
     else if (L.order == ABC_ZEROTH) launch4<T, 2>(tm, full, g, b, st, src, dst, V, a, nullptr, nullptr);
     else launch4<T, 0>(tm, full, g, b, st, src, dst, V, a, nullptr, nullptr);
     if (tm) tm->end_step();

@@ -859,11 +859,19 @@ __global__ void __launch_bounds__(kBlock) fft_cols_kernel(Geometry g, FaceFFT ff
 }
 
 // inverse rows of Z (t1 < n1) and the face_kernel epilogue on t2 < n2
+// mode 3 (shell stages of the one-pass sweep, one orbital): gout = alpha base +
+// beta (B x + A E (yin + y2)), base and y2 optional
+struct FaceAffine {
+  const double2* base;
+  const void* y2;
+  double alpha, beta;
+};
+
 template <typename T, int R>
 __global__ void __launch_bounds__(kBlock) fft_rows_inv_kernel(
     const double2* __restrict__ gin, double2* __restrict__ gout, double2* __restrict__ facc,
     double2* __restrict__ aux_out, const typename cpx<T>::t* __restrict__ yin, LocalBlock a, Geometry g, FaceFFT ff,
-    double coef, int mode, int first) {
+    double coef, int mode, int first, FaceAffine af) {
   extern __shared__ double2 buf[];
   const int q = blockIdx.y, f0 = 2 * q;
   const int n1 = g.face_n1[f0], n2 = g.face_n2[f0], B = g.batch;
@@ -895,6 +903,31 @@ __global__ void __launch_bounds__(kBlock) fft_rows_inv_kernel(
     double sr = cv.x, si = cv.y;
     if (!first) {
       gout[fe] = make_double2(sr, si);
+      continue;
+    }
+    if (mode == 3) {
+      using C = typename cpx<T>::t;
+      const C* y2 = static_cast<const C*>(af.y2);
+      for (int lp = 0; lp < R; ++lp) {
+        const double2 av = a.m[l * R + lp];
+        const long long pp = face_point(g, f, lp, t1, t2);
+        const auto yv = yin[pp];
+        double yr = (double)yv.x, yi = (double)yv.y;
+        if (y2) {
+          const auto zv = y2[pp];
+          yr += (double)zv.x;
+          yi += (double)zv.y;
+        }
+        sr += av.x * yr - av.y * yi;
+        si += av.x * yi + av.y * yr;
+      }
+      double2 o = make_double2(af.beta * sr, af.beta * si);
+      if (af.base) {
+        const double2 bv = af.base[fe];
+        o.x += af.alpha * bv.x;
+        o.y += af.alpha * bv.y;
+      }
+      gout[fe] = o;
       continue;
     }
     for (int lp = 0; lp < R; ++lp) {
@@ -960,7 +993,7 @@ hipError_t fft2_slabs(double2* base, int P1, int P2, int S, const double2* tw2, 
 template <typename T, int R>
 hipError_t face_fft_apply(const abc_launch& L, const double2* gin, double2* gout, double2* facc, double2* aux_out,
                           const typename cpx<T>::t* yin, const LocalBlock& a, double coef, int mode, int first,
-                          hipStream_t st, abc_timer* tm, const char* label) {
+                          hipStream_t st, abc_timer* tm, const char* label, FaceAffine af = FaceAffine{}) {
   const FaceFFT& ff = *L.face_fft;
   const Geometry& g = L.g;
   unsigned nr = 0, nc = 0;
@@ -982,7 +1015,7 @@ hipError_t face_fft_apply(const abc_launch& L, const double2* gin, double2* gout
   fft_rows_fwd_kernel<T><<<dim3(nr, 3), br, lr, st>>>(gin, yin, first, g, ff);
   fft_cols_kernel<<<dim3(nc, 3), bc, lc, st>>>(g, ff);
   abc_launch_kernel_lds(tm, label, fft_rows_inv_kernel<T, R>, dim3(nr, 3), dim3(br), lr, st, gin, gout, facc,
-                        aux_out, yin, a, g, ff, coef, mode, first);
+                        aux_out, yin, a, g, ff, coef, mode, first, af);
   return hipGetLastError();
 }
 
@@ -1460,6 +1493,461 @@ hipError_t box_gemm(abc_timer* tm, const double2* op, int rows, int ld, int na, 
   return hipSuccess;
 }
 
+// ---------------------------------------------------------------------------
+// Boundary shell of the one-pass sweep with a non-local face operator (first
+// order, face form, window > 0 or exact sections; one orbital).
+//
+// The step is linear in (psi, f).  Split every stage quantity of the factored
+// step (t, v, s, u') into the box with zero boundary values (the "Dirichlet
+// chain", what the one-pass sweep without a condition computes) plus a
+// correction delta driven by the E^T f terms.  delta_t lives on the face
+// layers only and every later stage widens it by R layers, so delta_u'
+// vanishes deeper than 4R: the step is the plain sweep plus delta_u' on a
+// shell of depth 4R.  The auxiliary stages need the full stage values on the
+// face layers (Dirichlet chain + delta), and the Dirichlet chain there needs
+// psi only 4R deep.  So after the condition-free sweep, four small rounds
+// compute, on shells of shrinking (Dirichlet) and growing (delta) depth,
+// everything the boundary needs, with one application of the face operator
+// B per round; the last adds delta_u' to the swept state.  Stage formulas (D = dt, L_psi(y, g) =
+// -i (H y + E^T g), L_f(y, g) = B g + A E y):
+//   round 1: t_D = a1 psi + b1 D L_psi(psi)        depth < 3R
+//            dt  = b1 D L_psi(0, f)                 depth < R
+//            t_f = a1 f + b1 D L_f(psi, f)
+//   round 2: v_D = psi + D L_psi(t_D)               depth < 2R
+//            dv  = D L_psi(dt, t_f)                 depth < 2R
+//            v_f = f + D L_f(t_D + dt, t_f)
+//   round 3: s_D = a2 v_D + b2 D L_psi(v_D)         depth < R
+//            ds  = a2 dv + b2 D L_psi(dv, v_f)      depth < 3R
+//            s_f = a2 v_f + b2 D L_f(v_D + dv, v_f)
+//   round 4: du  = dv + D L_psi(ds, s_f)            depth < 4R
+//            f'  = v_f + D L_f(s_D + ds, s_f)
+// ---------------------------------------------------------------------------
+
+// points of depth < d (distance to the nearest face), as six disjoint
+// blocks: the x slabs whole, the y slabs between them, the z slabs inside
+// both
+struct ShellBox {
+  int d, xl, xh, yl, yh, zl, zh, mx, my;
+  long long off[7];
+};
+
+ShellBox make_shell_box(const Geometry& g, int d) {
+  ShellBox b{};
+  b.d = d;
+  b.xl = std::min(d, g.nx);
+  b.xh = std::min(d, g.nx - b.xl);
+  b.mx = g.nx - b.xl - b.xh;
+  b.yl = std::min(d, g.ny);
+  b.yh = std::min(d, g.ny - b.yl);
+  b.my = g.ny - b.yl - b.yh;
+  b.zl = std::min(d, g.nz);
+  b.zh = std::min(d, g.nz - b.zl);
+  const long long cnt[6] = {(long long)b.xl * g.ny * g.nz, (long long)b.xh * g.ny * g.nz,
+                            (long long)b.mx * b.yl * g.nz, (long long)b.mx * b.yh * g.nz,
+                            (long long)b.mx * b.my * b.zl, (long long)b.mx * b.my * b.zh};
+  b.off[0] = 0;
+  for (int i = 0; i < 6; ++i) b.off[i + 1] = b.off[i] + cnt[i];
+  return b;
+}
+
+// coordinates of shell point i < b.off[6] (32-bit arithmetic: the grids of
+// the one-pass sweep stay below 2^31 points)
+__device__ __forceinline__ void shell_point(const Geometry& g, const ShellBox& b, unsigned i, int& x, int& y, int& z) {
+  int r = 0;
+  while (i >= (unsigned)b.off[r + 1]) ++r;
+  const unsigned q = i - (unsigned)b.off[r];
+  if (r < 2) {
+    const unsigned w = r == 0 ? b.xl : b.xh;
+    const unsigned row = q / w;
+    x = (int)(q - row * w) + (r == 0 ? 0 : g.nx - b.xh);
+    const unsigned zz = row / (unsigned)g.ny;
+    y = (int)(row - zz * g.ny);
+    z = (int)zz;
+  } else if (r < 4) {
+    const unsigned w = r == 2 ? b.yl : b.yh;
+    const unsigned row = q / (unsigned)b.mx;
+    x = b.xl + (int)(q - row * b.mx);
+    const unsigned zz = row / w;
+    y = (int)(row - zz * w) + (r == 2 ? 0 : g.ny - b.yh);
+    z = (int)zz;
+  } else {
+    const unsigned row = q / (unsigned)b.mx;
+    x = b.xl + (int)(q - row * b.mx);
+    const unsigned zz = row / (unsigned)b.my;
+    y = b.yl + (int)(row - zz * b.my);
+    z = (int)zz + (r == 4 ? 0 : g.nz - b.zh);
+  }
+}
+
+__device__ __forceinline__ int point_depth(const Geometry& g, int x, int y, int z) {
+  return min(min(min(x, g.nx - 1 - x), min(y, g.ny - 1 - y)), min(z, g.nz - 1 - z));
+}
+
+// one shell stage: out = alpha base + beta (-i) (H in + E^T aux) on the
+// points of depth < box.d, or out += that with accumulate.  in and base read
+// as zero outside the box and at depth >= in_depth / base_depth (where they
+// are zero by construction and their buffers hold nothing); null pointers
+// are zero.  FP64 arithmetic.
+template <typename C>
+struct ShellStage {
+  ShellBox box;
+  const C* in;
+  const C* base;
+  const double2* aux;
+  C* out;
+  int in_depth, base_depth, accumulate;
+  double alpha, beta;
+  unsigned nblk;
+};
+
+template <typename T, int R>
+__device__ __forceinline__ void shell_stage_point(const ShellStage<typename cpx<T>::t>& sp, unsigned i,
+                                                  const Geometry& g, const T* __restrict__ V, StencilCoef sc) {
+  using C = typename cpx<T>::t;
+  if (i >= (unsigned)sp.box.off[6]) return;
+  int x, y, z;
+  shell_point(g, sp.box, i, x, y, z);
+  const int p = (z * g.ny + y) * g.nx + x;
+  // every load below reads a valid address (clamped coordinates) and is
+  // masked afterwards, so that all of them are in flight together
+  double hr = 0, hi = 0;
+  if (sp.in) {
+    // neighbours deeper than in_depth: possible only when in_depth <= d + R
+    const bool masked = sp.in_depth <= sp.box.d + R;
+    auto ld = [&](int xx, int yy, int zz) -> double2 {
+      const bool inb = (unsigned)xx < (unsigned)g.nx && (unsigned)yy < (unsigned)g.ny && (unsigned)zz < (unsigned)g.nz;
+      const int cx = min(max(xx, 0), g.nx - 1), cy = min(max(yy, 0), g.ny - 1), cz = min(max(zz, 0), g.nz - 1);
+      const C v = sp.in[(cz * g.ny + cy) * g.nx + cx];
+      const bool ok = inb && (!masked || point_depth(g, cx, cy, cz) < sp.in_depth);
+      return ok ? make_double2((double)v.x, (double)v.y) : make_double2(0.0, 0.0);
+    };
+    double2 nb[1 + 6 * R];
+    nb[0] = ld(x, y, z);
+#pragma unroll
+    for (int k = 1; k <= R; ++k) {
+      nb[6 * k - 5] = ld(x - k, y, z);
+      nb[6 * k - 4] = ld(x + k, y, z);
+      nb[6 * k - 3] = ld(x, y - k, z);
+      nb[6 * k - 2] = ld(x, y + k, z);
+      nb[6 * k - 1] = ld(x, y, z - k);
+      nb[6 * k] = ld(x, y, z + k);
+    }
+    const double dg = sc.diag + (V ? (double)V[p] : 0.0);
+    hr = dg * nb[0].x;
+    hi = dg * nb[0].y;
+#pragma unroll
+    for (int k = 1; k <= R; ++k) {
+      double sx = 0, sy = 0;
+#pragma unroll
+      for (int m = 6 * k - 5; m <= 6 * k; ++m) {
+        sx += nb[m].x;
+        sy += nb[m].y;
+      }
+      hr += sc.off[k] * sx;
+      hi += sc.off[k] * sy;
+    }
+  }
+  if (sp.aux) {
+    // E^T aux: the six faces, layer clamped to [0, R) and masked
+    const int lx0 = min(x, R - 1), lx1 = min(g.nx - 1 - x, R - 1);
+    const int ly0 = min(y, R - 1), ly1 = min(g.ny - 1 - y, R - 1);
+    const int lz0 = min(z, R - 1), lz1 = min(g.nz - 1 - z, R - 1);
+    auto fv = [&](int f, int l, int t1, int t2) {
+      return sp.aux[g.face_off[f] + ((long long)l * g.face_n1[f] + t1) * g.face_n2[f] + t2];
+    };
+    const double2 v0 = fv(0, lx0, z, y), v1 = fv(1, lx1, z, y), v2 = fv(2, ly0, z, x), v3 = fv(3, ly1, z, x);
+    const double2 v4 = fv(4, lz0, y, x), v5 = fv(5, lz1, y, x);
+    const bool m0 = x < R, m1 = x >= g.nx - R, m2 = y < R, m3 = y >= g.ny - R, m4 = z < R, m5 = z >= g.nz - R;
+    hr += (m0 ? v0.x : 0.0) + (m1 ? v1.x : 0.0) + (m2 ? v2.x : 0.0) + (m3 ? v3.x : 0.0) + (m4 ? v4.x : 0.0) +
+          (m5 ? v5.x : 0.0);
+    hi += (m0 ? v0.y : 0.0) + (m1 ? v1.y : 0.0) + (m2 ? v2.y : 0.0) + (m3 ? v3.y : 0.0) + (m4 ? v4.y : 0.0) +
+          (m5 ? v5.y : 0.0);
+  }
+  // -i (hr + i hi) = hi - i hr
+  double orr = sp.beta * hi, oi = -sp.beta * hr;
+  if (sp.base) {
+    const C bv = sp.base[p];
+    if (point_depth(g, x, y, z) < sp.base_depth) {
+      orr += sp.alpha * (double)bv.x;
+      oi += sp.alpha * (double)bv.y;
+    }
+  }
+  C o;
+  if (sp.accumulate) {
+    o = sp.out[p];
+    o.x = (T)((double)o.x + orr);
+    o.y = (T)((double)o.y + oi);
+  } else {
+    o.x = (T)orr;
+    o.y = (T)oi;
+  }
+  sp.out[p] = o;
+}
+
+// two independent shell stages in one launch (blocks [0, a.nblk) run a)
+template <typename T, int R>
+__global__ void __launch_bounds__(kBlock) shell_stage_kernel(ShellStage<typename cpx<T>::t> a,
+                                                             ShellStage<typename cpx<T>::t> b, Geometry g,
+                                                             const T* __restrict__ V, StencilCoef sc) {
+  if (blockIdx.x < a.nblk)
+    shell_stage_point<T, R>(a, blockIdx.x * kBlock + threadIdx.x, g, V, sc);
+  else
+    shell_stage_point<T, R>(b, (blockIdx.x - a.nblk) * kBlock + threadIdx.x, g, V, sc);
+}
+
+// face operator of a shell round (one orbital, any window):
+// out = alpha base + beta (sum_{|p| <= w} k(p) x + A E (y + y2))
+template <typename T, int R>
+__global__ void __launch_bounds__(kBlock) face_affine_kernel(const double2* __restrict__ xin,
+                                                             double2* __restrict__ out,
+                                                             const typename cpx<T>::t* __restrict__ yin,
+                                                             const double2* __restrict__ ker, LocalBlock a, Geometry g,
+                                                             int w, FaceAffine af) {
+  using C = typename cpx<T>::t;
+  const long long e = (long long)blockIdx.x * kBlock + threadIdx.x;
+  if (e >= g.face_off[6]) return;
+  int f = 0;
+  while (e >= g.face_off[f + 1]) ++f;
+  const long long r = e - g.face_off[f];
+  const int n1 = g.face_n1[f], n2 = g.face_n2[f];
+  const int t2 = (int)(r % n2);
+  const int t1 = (int)((r / n2) % n1);
+  const int l = (int)(r / ((long long)n1 * n2));
+  const int K = 2 * w + 1;
+  double sr = 0, si = 0;
+  const int j1lo = max(0, t1 - w), j1hi = min(n1 - 1, t1 + w);
+  const int j2lo = max(0, t2 - w), j2hi = min(n2 - 1, t2 + w);
+  for (int lp = 0; lp < R; ++lp) {
+    const double2* kl = ker + ((long long)(l * R + lp)) * K * K;
+    const double2* xl = xin + g.face_off[f] + (long long)lp * n1 * n2;
+    for (int j1 = j1lo; j1 <= j1hi; ++j1) {
+      const double2* krow = kl + (long long)(t1 - j1 + w) * K;
+      for (int j2 = j2lo; j2 <= j2hi; ++j2) {
+        const double2 kv = krow[t2 - j2 + w];
+        const double2 v = xl[(long long)j1 * n2 + j2];
+        sr += kv.x * v.x - kv.y * v.y;
+        si += kv.x * v.y + kv.y * v.x;
+      }
+    }
+  }
+  const C* y2 = static_cast<const C*>(af.y2);
+  for (int lp = 0; lp < R; ++lp) {
+    const double2 av = a.m[l * R + lp];
+    const long long pp = face_point(g, f, lp, t1, t2);
+    const C yv = yin[pp];
+    double yr = (double)yv.x, yi = (double)yv.y;
+    if (y2) {
+      const C zv = y2[pp];
+      yr += (double)zv.x;
+      yi += (double)zv.y;
+    }
+    sr += av.x * yr - av.y * yi;
+    si += av.x * yi + av.y * yr;
+  }
+  double2 o = make_double2(af.beta * sr, af.beta * si);
+  if (af.base) {
+    const double2 bv = af.base[e];
+    o.x += af.alpha * bv.x;
+    o.y += af.alpha * bv.y;
+  }
+  out[e] = o;
+}
+
+// The same, tiled: a workgroup computes kAT1 x kAT2 outputs of one face
+// layer; the inputs it needs ((kAT1 + 2w) x (kAT2 + 2w) per source layer,
+// zero outside the face) and the taps are staged in dynamic LDS once.  Each
+// thread owns four consecutive outputs of a row and a quarter of the tap
+// rows, and slides a four-wide input window along each tap row, so one tap
+// and one new input (two LDS reads) feed four complex multiply-adds; the
+// quarters are summed in LDS.
+constexpr int kAT1 = 16, kAT2 = 32, kASplit = 4, kABlock = kAT1 * (kAT2 / 4) * kASplit;  // 512 threads
+inline size_t face_affine_lds(int R, int w) {
+  const int K = 2 * w + 1;
+  return ((size_t)R * (kAT1 + 2 * w) * (kAT2 + 2 * w) + (size_t)R * K * K + (size_t)(kASplit - 1) * kAT1 * kAT2) *
+         sizeof(double2);
+}
+inline bool face_affine_tiled_ok(int R, int w) { return w >= 2 && face_affine_lds(R, w) <= 64 * 1024; }
+
+template <typename T, int R>
+__global__ void __launch_bounds__(kABlock) face_affine_tiled_kernel(const double2* __restrict__ xin,
+                                                                    double2* __restrict__ out,
+                                                                    const typename cpx<T>::t* __restrict__ yin,
+                                                                    const double2* __restrict__ ker, LocalBlock a,
+                                                                    Geometry g, int w, FaceAffine af) {
+  using C = typename cpx<T>::t;
+  extern __shared__ double2 lds[];
+  const int S1 = kAT1 + 2 * w, S2 = kAT2 + 2 * w, K = 2 * w + 1;
+  double2* tin = lds;                     // [lp][S1][S2]
+  double2* tap = tin + R * S1 * S2;       // [lp][K][K], reversed
+  double2* part = tap + R * K * K;        // [q - 1][kAT1 * kAT2]
+  const int f = blockIdx.y / R, l = blockIdx.y - f * R;
+  const int n1 = g.face_n1[f], n2 = g.face_n2[f];
+  const int nt2 = (n2 + kAT2 - 1) / kAT2;
+  if ((int)blockIdx.x >= ((n1 + kAT1 - 1) / kAT1) * nt2) return;  // past this face's tiles
+  const int t1b = ((int)blockIdx.x / nt2) * kAT1, t2b = ((int)blockIdx.x % nt2) * kAT2;
+  for (int lp = 0; lp < R; ++lp) {
+    const double2* xl = xin + g.face_off[f] + (long long)lp * n1 * n2;
+    for (int i = threadIdx.x; i < S1 * S2; i += kABlock) {
+      const int a1 = i / S2, a2 = i - a1 * S2;
+      const int j1 = t1b - w + a1, j2 = t2b - w + a2;
+      tin[(lp * S1 + a1) * S2 + a2] =
+          (j1 >= 0 && j1 < n1 && j2 >= 0 && j2 < n2) ? xl[(long long)j1 * n2 + j2] : make_double2(0, 0);
+    }
+    const double2* kl = ker + (long long)(l * R + lp) * K * K;
+    for (int i = threadIdx.x; i < K * K; i += kABlock) tap[lp * K * K + i] = kl[K * K - 1 - i];
+  }
+  __syncthreads();
+  // thread (q, o1, c): outputs (o1, 4c .. 4c + 3), tap rows d1 = q, q + kASplit, ...
+  constexpr int kGroups = kAT1 * (kAT2 / 4);
+  const int q = threadIdx.x / kGroups, og = threadIdx.x - q * kGroups;
+  const int o1 = og / (kAT2 / 4), o2 = 4 * (og - o1 * (kAT2 / 4));
+  double ar[4] = {0, 0, 0, 0}, ai[4] = {0, 0, 0, 0};
+  for (int lp = 0; lp < R; ++lp) {
+    for (int d1 = q; d1 < K; d1 += kASplit) {
+      const double2* irow = tin + (lp * S1 + o1 + d1) * S2 + o2;
+      const double2* krow = tap + (lp * K + d1) * K;
+      double2 x0 = irow[0], x1 = irow[1], x2 = irow[2];
+#pragma unroll 4
+      for (int d2 = 0; d2 < K; ++d2) {
+        const double2 x3 = irow[d2 + 3];
+        const double2 kv = krow[d2];
+        ar[0] += kv.x * x0.x - kv.y * x0.y;
+        ai[0] += kv.x * x0.y + kv.y * x0.x;
+        ar[1] += kv.x * x1.x - kv.y * x1.y;
+        ai[1] += kv.x * x1.y + kv.y * x1.x;
+        ar[2] += kv.x * x2.x - kv.y * x2.y;
+        ai[2] += kv.x * x2.y + kv.y * x2.x;
+        ar[3] += kv.x * x3.x - kv.y * x3.y;
+        ai[3] += kv.x * x3.y + kv.y * x3.x;
+        x0 = x1;
+        x1 = x2;
+        x2 = x3;
+      }
+    }
+  }
+  if (q > 0) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) part[(q - 1) * kAT1 * kAT2 + o1 * kAT2 + o2 + j] = make_double2(ar[j], ai[j]);
+  }
+  __syncthreads();
+  if (q > 0) return;
+  const C* y2 = static_cast<const C*>(af.y2);
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    double sr = ar[j], si = ai[j];
+    for (int pq = 0; pq < kASplit - 1; ++pq) {
+      const double2 pv = part[pq * kAT1 * kAT2 + o1 * kAT2 + o2 + j];
+      sr += pv.x;
+      si += pv.y;
+    }
+    const int t1 = t1b + o1, t2 = t2b + o2 + j;
+    if (t1 >= n1 || t2 >= n2) continue;
+    const long long e = g.face_off[f] + ((long long)l * n1 + t1) * n2 + t2;
+    for (int lp = 0; lp < R; ++lp) {
+      const double2 av = a.m[l * R + lp];
+      const long long pp = face_point(g, f, lp, t1, t2);
+      const C yv = yin[pp];
+      double yr = (double)yv.x, yi = (double)yv.y;
+      if (y2) {
+        const C zv = y2[pp];
+        yr += (double)zv.x;
+        yi += (double)zv.y;
+      }
+      sr += av.x * yr - av.y * yi;
+      si += av.x * yi + av.y * yr;
+    }
+    double2 ov = make_double2(af.beta * sr, af.beta * si);
+    if (af.base) {
+      const double2 bv = af.base[e];
+      ov.x += af.alpha * bv.x;
+      ov.y += af.alpha * bv.y;
+    }
+    out[e] = ov;
+  }
+}
+
+template <typename T, int R>
+hipError_t shell_face_op(const abc_launch& L, const double2* x, double2* out, const typename cpx<T>::t* y,
+                         const LocalBlock& a, FaceAffine af, hipStream_t st, abc_timer* tm, const char* label) {
+  const Geometry& g = L.g;
+  if (L.face_fft)
+    return face_fft_apply<T, R>(L, x, out, nullptr, nullptr, y, a, 0.0, 3, 1, st, tm, label, af);
+  if (face_affine_tiled_ok(R, L.w)) {
+    int tiles = 0;
+    for (int f = 0; f < 6; ++f)
+      tiles = std::max(tiles, ((g.face_n1[f] + kAT1 - 1) / kAT1) * ((g.face_n2[f] + kAT2 - 1) / kAT2));
+    abc_launch_kernel_lds(tm, label, face_affine_tiled_kernel<T, R>, dim3(tiles, 6 * R), dim3(kABlock),
+                          face_affine_lds(R, L.w), st, x, out, y, L.face_ker, a, g, L.w, af);
+  } else {
+    abc_launch_kernel(tm, label, face_affine_kernel<T, R>, dim3(nblocks(g.face_off[6])), dim3(kBlock), st, x, out,
+                      y, L.face_ker, a, g, L.w, af);
+  }
+  return hipGetLastError();
+}
+
+template <typename T, int R>
+hipError_t shell_rounds_t(const abc_launch& L, const ShellScratch& W, const void* psi_v, const void* V_v,
+                          const double2* f, double2* fout, void* psi_out_v, hipStream_t st, abc_timer* tm) {
+  using C = typename cpx<T>::t;
+  static const char* kShellLabel[4] = {"shell_1", "shell_2", "shell_3", "shell_4"};
+  static const char* kFaceLabel[4] = {"shell_face_1", "shell_face_2", "shell_face_3", "shell_face_4"};
+  const Geometry& g = L.g;
+  const C* psi = static_cast<const C*>(psi_v);
+  const T* V = static_cast<const T*>(V_v);
+  C* P0 = static_cast<C*>(W.vol[0]);  // t_D, then s_D
+  C* P1 = static_cast<C*>(W.vol[1]);  // v_D
+  C* Q0 = static_cast<C*>(W.vol[2]);  // delta_t, then delta_s
+  C* Q1 = static_cast<C*>(W.vol[3]);  // delta_v
+  C* out = static_cast<C*>(psi_out_v);  // the swept state, += delta_u
+  double2* F0 = W.face[0];            // t_f, then s_f
+  double2* F1 = W.face[1];            // v_f
+  const StencilCoef sc = make_coef(L);
+  const LocalBlock a = make_local(L.a_loc);
+  const double D = L.dt, a1 = L.fused_a1, b1 = L.fused_b1, a2 = L.fused_a2, b2 = L.fused_b2;
+  constexpr int kAll = 1 << 30;
+  auto stage = [&](int d, const C* in, int in_depth, const C* base, int base_depth, const double2* aux, C* out,
+                   double alpha, double beta) {
+    ShellStage<C> sp{};
+    sp.box = make_shell_box(g, d);
+    sp.in = in;
+    sp.in_depth = in_depth;
+    sp.base = base;
+    sp.base_depth = base_depth;
+    sp.aux = aux;
+    sp.out = out;
+    sp.alpha = alpha;
+    sp.beta = beta;
+    sp.nblk = nblocks(sp.box.off[6]);
+    return sp;
+  };
+  auto launch = [&](int k, const ShellStage<C>& sa, const ShellStage<C>& sb) {
+    abc_launch_kernel(tm, kShellLabel[k], shell_stage_kernel<T, R>, dim3(sa.nblk + sb.nblk), dim3(kBlock), st, sa, sb,
+                      g, V, sc);
+  };
+  ShellStage<C> none{};
+  // round 1
+  launch(0, stage(3 * R, psi, kAll, psi, kAll, nullptr, P0, a1, b1 * D),
+         stage(R, nullptr, 0, nullptr, 0, f, Q0, 0.0, b1 * D));
+  hipError_t e = shell_face_op<T, R>(L, f, F0, psi, a, FaceAffine{f, nullptr, a1, b1 * D}, st, tm, kFaceLabel[0]);
+  if (e != hipSuccess) return e;
+  // round 2
+  launch(1, stage(2 * R, P0, kAll, psi, kAll, nullptr, P1, 1.0, D), stage(2 * R, Q0, R, nullptr, 0, F0, Q1, 0.0, D));
+  e = shell_face_op<T, R>(L, F0, F1, P0, a, FaceAffine{f, Q0, 1.0, D}, st, tm, kFaceLabel[1]);
+  if (e != hipSuccess) return e;
+  // round 3
+  launch(2, stage(R, P1, kAll, P1, kAll, nullptr, P0, a2, b2 * D),
+         stage(3 * R, Q1, 2 * R, Q1, 2 * R, F1, Q0, a2, b2 * D));
+  e = shell_face_op<T, R>(L, F1, F0, P1, a, FaceAffine{F1, Q1, a2, b2 * D}, st, tm, kFaceLabel[2]);
+  if (e != hipSuccess) return e;
+  // round 4
+  ShellStage<C> last = stage(4 * R, Q0, 3 * R, Q1, 2 * R, F0, out, 1.0, D);
+  last.accumulate = 1;
+  launch(3, none, last);
+  e = shell_face_op<T, R>(L, F0, fout, P0, a, FaceAffine{F1, Q0, 1.0, D}, st, tm, kFaceLabel[3]);
+  if (e != hipSuccess) return e;
+  return hipGetLastError();
+}
+
 template <typename T, int R, bool PER>
 hipError_t step_staged_t(const abc_launch& L, const abc_scratch& S, void* psi_v, double2* aux,
                          const void* V_v, int n_steps, hipStream_t st, abc_timer* tm, void* const* keep,
@@ -1780,4 +2268,11 @@ abc_status face_fft_setup(const Geometry& g, int R, int w, const std::vector<abc
     }
   if (hipDeviceSynchronize() != hipSuccess) { err = "kernel spectra transform failed"; return ABC_EDEVICE; }
   return ABC_OK;
+}
+
+hipError_t launch_shell_rounds(const abc_launch& L, const ShellScratch& W, const void* psi, const void* V,
+                               const double2* f, double2* fout, void* psi_out, hipStream_t st, abc_timer* tm) {
+  if (L.g.R != 1 || L.g.batch != 1) return hipErrorInvalidValue;
+  if (L.dtype == ABC_C64) return shell_rounds_t<float, 1>(L, W, psi, V, f, fout, psi_out, st, tm);
+  return shell_rounds_t<double, 1>(L, W, psi, V, f, fout, psi_out, st, tm);
 }

@@ -77,3 +77,44 @@ def test_onepass_refuses_what_it_does_not_cover():
         Solver((10, 10, 130), 0.25, 0.004, order="dirichlet", path="onepass")
     with pytest.raises(AbcError):
         Solver((10, 10, 10), 0.25, 0.004, order="dirichlet", radius=2, path="onepass")
+
+
+# first order with a non-local face operator: the condition-free sweep plus
+# the boundary-shell rounds (window 1: per-element face kernel; 3: tiled;
+# exact sections: zero-padded FFTs)
+SHELL_CASES = [(1, True), (3, True), (None, False)]
+
+
+@pytest.mark.parametrize("window,fejer", SHELL_CASES, ids=["w1", "w3", "exact"])
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("steps", [3, 4])
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_onepass_windowed_first_order_parity(window, fejer, shape, steps, dtype):
+    w = max(shape) - 1 if window is None else window
+    r = _run_pair("onepass shell first w=%d %s" % (w, dtype), shape, 0.25, 0.004, 1, "first", steps, s1=1.5,
+                  window=w, fejer=fejer, dtype=dtype, path="onepass", seed=13)
+    assert r["solver"].path == "onepass"
+    tol = TOL64 if dtype == "c128" else TOL32
+    assert r["err"] <= tol, r["err"]
+    assert r["aux_err"] <= tol, r["aux_err"]
+
+
+@pytest.mark.parametrize("window,fejer", [(8, True), (127, False)], ids=["w8", "exact"])
+def test_onepass_windowed_headline_size_matches_staged(window, fejer):
+    from paper_1908_02456_amd.solver import Solver
+    wl = W.well_packet(n=128)
+    print("case: onepass shell 128^3 first w=%d vs staged" % window, flush=True)
+    out, aux = [], []
+    for path in ("staged", "auto"):
+        s = Solver((128,) * 3, wl.h, wl.dt, order="first", s1=wl.s1, window=window, fejer=fejer, path=path)
+        assert s.path == ("staged" if path == "staged" else "onepass")
+        psi = torch.from_numpy(wl.psi0).cuda()
+        a = s.new_aux()
+        s.step(psi, a, torch.from_numpy(wl.V).cuda(), 7)
+        out.append(psi)
+        aux.append(a)
+    torch.cuda.synchronize()
+    d = (out[0] - out[1]).abs().max().item() / out[0].abs().max().item()
+    assert d <= TOL64, d
+    da = (aux[0] - aux[1]).abs().max().item() / aux[0].abs().max().item()
+    assert da <= TOL64, da
