@@ -463,17 +463,21 @@ def bench_h2_point(Solver, torch, wl, modes=64, nodes=4096):
 
 
 def bench_face_windows(Solver, torch, wl, steps_timed=20):
-    """The headline workload with wider face operators: w = 0 (fused path),
-    w = 8 with the Fejer window (staged, direct convolution) and the exact
-    section w = n - 1 (staged, zero-padded 2D FFTs): time per step and the
-    relative error against the large zero-boundary box after 2000 steps."""
+    """The headline workload with wider face operators: w = 0 (one-pass
+    sweep), w = 8 with the Fejer window (direct convolution) and the exact
+    section w = n - 1 (zero-padded 2D FFTs), the wider two on the staged path
+    and on the one-pass sweep with boundary-shell rounds: time per step and
+    the relative error against the large zero-boundary box after 2000 steps."""
     ref = large_box_reference(Solver, torch, wl, "auto", wl.steps)
     nr = torch.linalg.vector_norm(ref).item()
     V = torch.from_numpy(wl.V).cuda()
     out = {}
-    for name, w, fejer in (("w0", 0, True), ("w8_fejer", 8, True), ("exact_fft", wl.n - 1, False)):
+    for name, w, fejer, path in (("w0", 0, True, "auto"), ("w8_fejer", 8, True, "auto"),
+                                 ("w8_fejer_onepass", 8, True, "onepass"),
+                                 ("exact_fft", wl.n - 1, False, "auto"),
+                                 ("exact_fft_onepass", wl.n - 1, False, "onepass")):
         log("  face windows: %s" % name)
-        s = Solver((wl.n,) * 3, wl.h, wl.dt, order="first", s1=wl.s1, window=w, fejer=fejer)
+        s = Solver((wl.n,) * 3, wl.h, wl.dt, order="first", s1=wl.s1, window=w, fejer=fejer, path=path)
         psi = torch.from_numpy(wl.psi0).cuda()
         aux = s.new_aux()
         s.step(psi, aux, V, 2)

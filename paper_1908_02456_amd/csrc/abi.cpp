@@ -372,10 +372,7 @@ abc_status abc_setup(const abc_params* pp, abc_ctx** out) {
   c->use_fused = 0;
   if (p.path != ABC_PATH_STAGED) {
     std::string why;
-    // a windowed first-order face operator runs on the one-pass sweep only
-    const bool ok = (p.path == ABC_PATH_ONEPASS || (p.path == ABC_PATH_AUTO && fused_shell_case(p)))
-                        ? fused4_supported(p, &why)
-                        : fused_supported(p, &why);
+    const bool ok = p.path == ABC_PATH_ONEPASS ? fused4_supported(p, &why) : fused_supported(p, &why);
     if ((p.path == ABC_PATH_FUSED || p.path == ABC_PATH_ONEPASS) && !ok) {
       abc_destroy(c);
       return fail(ABC_ENOTSUP, "fused path: " + why);

@@ -1317,8 +1317,11 @@ abc_status fused_prepare(const abc_params& p, abc_launch& L, std::vector<void*>*
   // except the first order on rows narrower than 128 columns, where its
   // x-face sources need selects and it measured slower than the two-stage
   // kernels (96^3: 48 against 39 us per step)
-  const bool auto4 =
-      fused4_supported(p, nullptr) && (p.order != ABC_FIRST || p.nx == kCols || fused_shell_case(p));
+  // (a windowed first-order operator takes the one-pass sweep with the
+  // boundary-shell rounds only when asked for: at 128^3 it measured level
+  // with the staged path, w = 8 145 against 141 us per step, exact sections
+  // 182 against 185)
+  const bool auto4 = fused4_supported(p, nullptr) && !fused_shell_case(p) && (p.order != ABC_FIRST || p.nx == kCols);
   L.fused_shell = 0;
   if (p.path == ABC_PATH_ONEPASS || (p.path == ABC_PATH_AUTO && auto4)) {
     if (!fused4_supported(p, &err)) return ABC_ENOTSUP;

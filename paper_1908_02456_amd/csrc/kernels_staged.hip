@@ -1551,32 +1551,25 @@ ShellBox make_shell_box(const Geometry& g, int d) {
 }
 
 // coordinates of shell point i < b.off[6] (32-bit arithmetic: the grids of
-// the one-pass sweep stay below 2^31 points)
+// the one-pass sweep stay below 2^31 points).  Branch-free: the block is
+// found by comparisons against the (uniform) block offsets, and each
+// coordinate by selects, so no per-lane indexing of the argument struct.
 __device__ __forceinline__ void shell_point(const Geometry& g, const ShellBox& b, unsigned i, int& x, int& y, int& z) {
-  int r = 0;
-  while (i >= (unsigned)b.off[r + 1]) ++r;
-  const unsigned q = i - (unsigned)b.off[r];
-  if (r < 2) {
-    const unsigned w = r == 0 ? b.xl : b.xh;
-    const unsigned row = q / w;
-    x = (int)(q - row * w) + (r == 0 ? 0 : g.nx - b.xh);
-    const unsigned zz = row / (unsigned)g.ny;
-    y = (int)(row - zz * g.ny);
-    z = (int)zz;
-  } else if (r < 4) {
-    const unsigned w = r == 2 ? b.yl : b.yh;
-    const unsigned row = q / (unsigned)b.mx;
-    x = b.xl + (int)(q - row * b.mx);
-    const unsigned zz = row / w;
-    y = (int)(row - zz * w) + (r == 2 ? 0 : g.ny - b.yh);
-    z = (int)zz;
-  } else {
-    const unsigned row = q / (unsigned)b.mx;
-    x = b.xl + (int)(q - row * b.mx);
-    const unsigned zz = row / (unsigned)b.my;
-    y = b.yl + (int)(row - zz * b.my);
-    z = (int)zz + (r == 4 ? 0 : g.nz - b.zh);
-  }
+  const unsigned o1 = (unsigned)b.off[1], o2 = (unsigned)b.off[2], o3 = (unsigned)b.off[3];
+  const unsigned o4 = (unsigned)b.off[4], o5 = (unsigned)b.off[5];
+  const int r = (i >= o1) + (i >= o2) + (i >= o3) + (i >= o4) + (i >= o5);
+  const unsigned base = r == 0 ? 0u : r == 1 ? o1 : r == 2 ? o2 : r == 3 ? o3 : r == 4 ? o4 : o5;
+  const unsigned q = i - base;
+  // inner width (fastest), middle extent, offsets of the three coordinates
+  const bool xs = r < 2, ys = r == 2 || r == 3;
+  const unsigned wi = xs ? (unsigned)(r == 0 ? b.xl : b.xh) : (unsigned)b.mx;
+  const unsigned wm = xs ? (unsigned)g.ny : ys ? (unsigned)(r == 2 ? b.yl : b.yh) : (unsigned)b.my;
+  const unsigned row = q / wi;
+  const unsigned zz = row / wm;
+  const int ci = (int)(q - row * wi), cm = (int)(row - zz * wm);
+  x = ci + (xs ? (r == 0 ? 0 : g.nx - b.xh) : b.xl);
+  y = cm + (xs ? 0 : ys ? (r == 2 ? 0 : g.ny - b.yh) : b.yl);
+  z = (int)zz + (r == 5 ? g.nz - b.zh : 0);
 }
 
 __device__ __forceinline__ int point_depth(const Geometry& g, int x, int y, int z) {
@@ -1608,55 +1601,65 @@ __device__ __forceinline__ void shell_stage_point(const ShellStage<typename cpx<
   int x, y, z;
   shell_point(g, sp.box, i, x, y, z);
   const int p = (z * g.ny + y) * g.nx + x;
-  // every load below reads a valid address (clamped coordinates) and is
-  // masked afterwards, so that all of them are in flight together
-  double hr = 0, hi = 0;
-  if (sp.in) {
-    // neighbours deeper than in_depth: possible only when in_depth <= d + R
-    const bool masked = sp.in_depth <= sp.box.d + R;
-    auto ld = [&](int xx, int yy, int zz) -> double2 {
-      const bool inb = (unsigned)xx < (unsigned)g.nx && (unsigned)yy < (unsigned)g.ny && (unsigned)zz < (unsigned)g.nz;
-      const int cx = min(max(xx, 0), g.nx - 1), cy = min(max(yy, 0), g.ny - 1), cz = min(max(zz, 0), g.nz - 1);
-      const C v = sp.in[(cz * g.ny + cy) * g.nx + cx];
-      const bool ok = inb && (!masked || point_depth(g, cx, cy, cz) < sp.in_depth);
-      return ok ? make_double2((double)v.x, (double)v.y) : make_double2(0.0, 0.0);
-    };
-    double2 nb[1 + 6 * R];
-    nb[0] = ld(x, y, z);
+  // Every load reads a valid address (clamped coordinates; absent operands
+  // read the output array) and is masked afterwards, and all of them are
+  // issued before the first use, so one memory latency covers the point.
+  const bool has_in = sp.in != nullptr, has_aux = sp.aux != nullptr, has_base = sp.base != nullptr;
+  const C* in = has_in ? sp.in : sp.out;
+  const bool masked = sp.in_depth <= sp.box.d + R;  // neighbours deeper than in_depth exist
+  int nidx[1 + 6 * R];
+  bool nok[1 + 6 * R];
+  auto nb_at = [&](int m, int xx, int yy, int zz) {
+    const bool inb = (unsigned)xx < (unsigned)g.nx && (unsigned)yy < (unsigned)g.ny && (unsigned)zz < (unsigned)g.nz;
+    const int cx = min(max(xx, 0), g.nx - 1), cy = min(max(yy, 0), g.ny - 1), cz = min(max(zz, 0), g.nz - 1);
+    nidx[m] = (cz * g.ny + cy) * g.nx + cx;
+    nok[m] = has_in && inb && (!masked || point_depth(g, cx, cy, cz) < sp.in_depth);
+  };
+  nb_at(0, x, y, z);
 #pragma unroll
-    for (int k = 1; k <= R; ++k) {
-      nb[6 * k - 5] = ld(x - k, y, z);
-      nb[6 * k - 4] = ld(x + k, y, z);
-      nb[6 * k - 3] = ld(x, y - k, z);
-      nb[6 * k - 2] = ld(x, y + k, z);
-      nb[6 * k - 1] = ld(x, y, z - k);
-      nb[6 * k] = ld(x, y, z + k);
-    }
-    const double dg = sc.diag + (V ? (double)V[p] : 0.0);
-    hr = dg * nb[0].x;
-    hi = dg * nb[0].y;
+  for (int k = 1; k <= R; ++k) {
+    nb_at(6 * k - 5, x - k, y, z);
+    nb_at(6 * k - 4, x + k, y, z);
+    nb_at(6 * k - 3, x, y - k, z);
+    nb_at(6 * k - 2, x, y + k, z);
+    nb_at(6 * k - 1, x, y, z - k);
+    nb_at(6 * k, x, y, z + k);
+  }
+  C nv[1 + 6 * R];
+#pragma unroll
+  for (int m = 0; m < 1 + 6 * R; ++m) nv[m] = in[nidx[m]];
+  const double vp = V ? (double)V[p] : 0.0;
+  const C bv = (has_base ? sp.base : in)[p];
+  const C ov = sp.out[p];
+  // E^T aux: the six faces, layer clamped to [0, R) and masked
+  const double2* fb = has_aux ? sp.aux : reinterpret_cast<const double2*>(sp.out);
+  const int lx0 = min(x, R - 1), lx1 = min(g.nx - 1 - x, R - 1);
+  const int ly0 = min(y, R - 1), ly1 = min(g.ny - 1 - y, R - 1);
+  const int lz0 = min(z, R - 1), lz1 = min(g.nz - 1 - z, R - 1);
+  auto fidx = [&](int f, int l, int t1, int t2) -> long long {
+    return has_aux ? g.face_off[f] + ((long long)l * g.face_n1[f] + t1) * g.face_n2[f] + t2 : 0;
+  };
+  const double2 v0 = fb[fidx(0, lx0, z, y)], v1 = fb[fidx(1, lx1, z, y)], v2 = fb[fidx(2, ly0, z, x)];
+  const double2 v3 = fb[fidx(3, ly1, z, x)], v4 = fb[fidx(4, lz0, y, x)], v5 = fb[fidx(5, lz1, y, x)];
+  // -- arithmetic
+  double hr = 0, hi = 0;
+  if (has_in) {
+    const double dg = sc.diag + vp;
+    hr = nok[0] ? dg * (double)nv[0].x : 0.0;
+    hi = nok[0] ? dg * (double)nv[0].y : 0.0;
 #pragma unroll
     for (int k = 1; k <= R; ++k) {
       double sx = 0, sy = 0;
 #pragma unroll
       for (int m = 6 * k - 5; m <= 6 * k; ++m) {
-        sx += nb[m].x;
-        sy += nb[m].y;
+        sx += nok[m] ? (double)nv[m].x : 0.0;
+        sy += nok[m] ? (double)nv[m].y : 0.0;
       }
       hr += sc.off[k] * sx;
       hi += sc.off[k] * sy;
     }
   }
-  if (sp.aux) {
-    // E^T aux: the six faces, layer clamped to [0, R) and masked
-    const int lx0 = min(x, R - 1), lx1 = min(g.nx - 1 - x, R - 1);
-    const int ly0 = min(y, R - 1), ly1 = min(g.ny - 1 - y, R - 1);
-    const int lz0 = min(z, R - 1), lz1 = min(g.nz - 1 - z, R - 1);
-    auto fv = [&](int f, int l, int t1, int t2) {
-      return sp.aux[g.face_off[f] + ((long long)l * g.face_n1[f] + t1) * g.face_n2[f] + t2];
-    };
-    const double2 v0 = fv(0, lx0, z, y), v1 = fv(1, lx1, z, y), v2 = fv(2, ly0, z, x), v3 = fv(3, ly1, z, x);
-    const double2 v4 = fv(4, lz0, y, x), v5 = fv(5, lz1, y, x);
+  if (has_aux) {
     const bool m0 = x < R, m1 = x >= g.nx - R, m2 = y < R, m3 = y >= g.ny - R, m4 = z < R, m5 = z >= g.nz - R;
     hr += (m0 ? v0.x : 0.0) + (m1 ? v1.x : 0.0) + (m2 ? v2.x : 0.0) + (m3 ? v3.x : 0.0) + (m4 ? v4.x : 0.0) +
           (m5 ? v5.x : 0.0);
@@ -1665,22 +1668,17 @@ __device__ __forceinline__ void shell_stage_point(const ShellStage<typename cpx<
   }
   // -i (hr + i hi) = hi - i hr
   double orr = sp.beta * hi, oi = -sp.beta * hr;
-  if (sp.base) {
-    const C bv = sp.base[p];
-    if (point_depth(g, x, y, z) < sp.base_depth) {
-      orr += sp.alpha * (double)bv.x;
-      oi += sp.alpha * (double)bv.y;
-    }
+  if (has_base && point_depth(g, x, y, z) < sp.base_depth) {
+    orr += sp.alpha * (double)bv.x;
+    oi += sp.alpha * (double)bv.y;
+  }
+  if (sp.accumulate) {
+    orr += (double)ov.x;
+    oi += (double)ov.y;
   }
   C o;
-  if (sp.accumulate) {
-    o = sp.out[p];
-    o.x = (T)((double)o.x + orr);
-    o.y = (T)((double)o.y + oi);
-  } else {
-    o.x = (T)orr;
-    o.y = (T)oi;
-  }
+  o.x = (T)orr;
+  o.y = (T)oi;
   sp.out[p] = o;
 }
 
@@ -1756,11 +1754,11 @@ __global__ void __launch_bounds__(kBlock) face_affine_kernel(const double2* __re
 // The same, tiled: a workgroup computes kAT1 x kAT2 outputs of one face
 // layer; the inputs it needs ((kAT1 + 2w) x (kAT2 + 2w) per source layer,
 // zero outside the face) and the taps are staged in dynamic LDS once.  Each
-// thread owns four consecutive outputs of a row and a quarter of the tap
-// rows, and slides a four-wide input window along each tap row, so one tap
+// thread owns four consecutive outputs of a row and every kASplit-th tap
+// row, and slides a four-wide input window along each tap row, so one tap
 // and one new input (two LDS reads) feed four complex multiply-adds; the
-// quarters are summed in LDS.
-constexpr int kAT1 = 16, kAT2 = 32, kASplit = 4, kABlock = kAT1 * (kAT2 / 4) * kASplit;  // 512 threads
+// kASplit partial sums are added in LDS.
+constexpr int kAT1 = 8, kAT2 = 32, kASplit = 8, kABlock = kAT1 * (kAT2 / 4) * kASplit;  // 512 threads
 inline size_t face_affine_lds(int R, int w) {
   const int K = 2 * w + 1;
   return ((size_t)R * (kAT1 + 2 * w) * (kAT2 + 2 * w) + (size_t)R * K * K + (size_t)(kASplit - 1) * kAT1 * kAT2) *

@@ -8,7 +8,10 @@ planes, complex64 tiles 8 by 8), including a last tile one row or one plane
 deep, whose face row or plane then lies in the previous tile's halo; narrow,
 odd and full 128-column rows; odd and even step counts (the ping-pong ends
 in the caller's buffers either way).  Also: the full 128^3 headline workload
-agrees with the two-pass fused path, every point compared."""
+agrees with the two-pass fused path, every point compared; and the first
+order with a windowed or exact face operator (the condition-free sweep plus
+the boundary-shell rounds) against the oracle on the same boxes and against
+the staged path at 128^3."""
 import numpy as np
 import pytest
 
@@ -105,9 +108,9 @@ def test_onepass_windowed_headline_size_matches_staged(window, fejer):
     wl = W.well_packet(n=128)
     print("case: onepass shell 128^3 first w=%d vs staged" % window, flush=True)
     out, aux = [], []
-    for path in ("staged", "auto"):
+    for path in ("auto", "onepass"):
         s = Solver((128,) * 3, wl.h, wl.dt, order="first", s1=wl.s1, window=window, fejer=fejer, path=path)
-        assert s.path == ("staged" if path == "staged" else "onepass")
+        assert s.path == ("staged" if path == "auto" else "onepass")
         psi = torch.from_numpy(wl.psi0).cuda()
         a = s.new_aux()
         s.step(psi, a, torch.from_numpy(wl.V).cuda(), 7)
