@@ -658,7 +658,7 @@ def main():
     ap.add_argument("--radius", type=int, default=1, choices=[1, 2, 3], help="stencil half-width R")
     ap.add_argument("--no-fejer", action="store_true",
                     help="face kernels truncated without the triangular taper (w >= n - 1: exact sections)")
-    ap.add_argument("--path", default="auto", choices=["auto", "staged", "fused"])
+    ap.add_argument("--path", default="auto", choices=["auto", "staged", "fused", "onepass"])
     ap.add_argument("--no-physics", action="store_true")
     ap.add_argument("--replica", action="store_true",
                     help="also run the paper's 3D experiment at its own size (31^3, R = 3, dense box operators)")

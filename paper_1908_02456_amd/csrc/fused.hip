@@ -705,14 +705,14 @@ __host__ __device__ constexpr int level_base4(int j) { return j * rows4<T>() - j
 // the stage's coefficient) and the auxiliary stage is base + g_k (b A + a
 // psi_in), with the bases above.  A face point's auxiliary values pass
 // through the four stages in four consecutive planes of the march:
-//  * x faces and the tile's y-face row: the two halo waves (rows 0 and
-//    ROWS-1 take part in no stage) run the auxiliary stages one plane ahead
-//    of the row waves, from the stage inputs published in LDS, and hand the
-//    next plane's sources A over through LDS (double-buffered by plane
-//    parity); they keep the bases in LDS slots indexed by plane & 3.  Row 0
-//    takes the x faces (one lane per side and row; f0 staged for the whole
-//    march at the start), row ROWS-1 the y-face row (f0 fetched a plane
-//    ahead);
+//  * x faces and the tile's y-face row: helper waves (the halo rows, which
+//    take part in no stage, and at a y face every row outside the box) run
+//    the auxiliary stages one plane ahead of the row waves, from the stage
+//    inputs published in LDS, and hand the next plane's sources A over
+//    through LDS (double-buffered by plane parity); they keep the bases in
+//    LDS slots indexed by plane & 3.  The jobs are split among the helpers
+//    as described at the helper loop; the x faces' f0 is staged for the
+//    whole march at the start, the y face's fetched a plane ahead;
 //  * the z-face plane: one stage at a time is on it, so the row waves run
 //    its auxiliary stage themselves (slots per thread; f0 read at stage 1).
 // So the first-order tile needs ny > ROWS and nz > TZ + 4 (at most one face
