@@ -6,7 +6,8 @@
 ordinary torch operations, to whatever parameters built them (well amplitude
 and centre, packet momentum).  The forward value comes from the same adjoint
 call's forward sweep, so one call serves both passes when gradients are
-needed.
+needed; when neither psi0 nor V requires a gradient, only the forward steps
+and the objective run.
 """
 from __future__ import annotations
 
@@ -18,6 +19,10 @@ class AbcObjective(torch.autograd.Function):
     def forward(ctx, psi0, V, solver, n_steps, objective, ckpt_stride):
         psi0c = psi0.detach().contiguous()
         Vc = None if V is None else V.detach().contiguous()
+        if not any(ctx.needs_input_grad[:2]):
+            # no gradient asked for: the forward steps and the objective only
+            return torch.tensor(solver.objective(psi0c, Vc, n_steps, objective), dtype=torch.float64,
+                                device=psi0.device)
         J, gpsi, gV = solver.adjoint(psi0c, Vc, n_steps, objective, ckpt_stride)
         ctx.save_for_backward(gpsi, gV)
         ctx.has_V = V is not None

@@ -210,6 +210,20 @@ class Solver:
                                          ctypes.byref(J), _stream_handle(stream)))
         return J.value, gpsi, gV
 
+    def objective(self, psi0, V=None, n_steps: int = 1, objective: str = "prob", stream=None) -> float:
+        """J(psi_N) after n_steps from (psi0, f = 0), forward only: h^3 sum
+        |psi_N|^2 ("prob") or h^3 Re <psi_N, H psi_N> ("energy"), from the
+        device diagnostics of a stepped copy of psi0 (one orbital)."""
+        if self.batch != 1:
+            raise ValueError("objective: one orbital")
+        if objective not in _lib.OBJECTIVES:
+            raise ValueError("objective must be one of %s" % sorted(_lib.OBJECTIVES))
+        psi = psi0.detach().clone().contiguous()
+        aux = self.new_aux()
+        self.step(psi, aux, V, n_steps, stream=stream)
+        d = self.diagnostics(psi, aux if self.aux_elems else None, V, stream=stream)
+        return float(d[0 if objective == "prob" else 2].item())
+
     def tune(self, psi, aux=None, V=None, stream=None) -> int:
         """Pick the fused path's tile depth by timing (state restored); returns it."""
         self._check_psi(psi)

@@ -145,3 +145,21 @@ def test_autograd_parameter_gradients_full_size():
     # 96^3, 500 steps, first order, FP64, sqrt(n) checkpointing
     print("case: autograd 96^3 x 500", flush=True)
     _check_parameter_gradients(W.adjoint_packet(), 1e-4, 1e-6)
+
+
+@pytest.mark.parametrize("objective", ["prob", "energy"])
+def test_objective_without_gradients_skips_the_reverse_sweep(objective, monkeypatch):
+    print("case: objective without gradients", objective, flush=True)
+    Solver = _solver_cls()
+    from paper_1908_02456_amd.autograd import abc_objective
+    shape, h, dt, steps = (12, 11, 10), 0.25, 0.004, 9
+    s = Solver(shape, h, dt, order="first", s1=1.5, window=1, path="staged")
+    psi0 = torch.from_numpy(W.random_complex(shape, seed=5)).cuda()
+    V = torch.from_numpy(W.random_potential(shape, seed=6, scale=2.0)).cuda()
+    J_adj, _, _ = s.adjoint(psi0, V, steps, objective)
+    calls = []
+    monkeypatch.setattr(s, "adjoint", lambda *a, **k: calls.append(1))
+    J = abc_objective(s, psi0, V, steps, objective)
+    assert not calls
+    assert not J.requires_grad
+    assert abs(J.item() - J_adj) <= 1e-12 * abs(J_adj)
