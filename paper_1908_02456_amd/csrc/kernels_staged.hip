@@ -1529,6 +1529,7 @@ hipError_t box_gemm(abc_timer* tm, const double2* op, int rows, int ld, int na, 
 struct ShellBox {
   int d, xl, xh, yl, yh, zl, zh, mx, my;
   long long off[7];
+  unsigned blk[7];  // first workgroup of each block: a workgroup stays in one block
 };
 
 ShellBox make_shell_box(const Geometry& g, int d) {
@@ -1546,30 +1547,53 @@ ShellBox make_shell_box(const Geometry& g, int d) {
                             (long long)b.mx * b.yl * g.nz, (long long)b.mx * b.yh * g.nz,
                             (long long)b.mx * b.my * b.zl, (long long)b.mx * b.my * b.zh};
   b.off[0] = 0;
-  for (int i = 0; i < 6; ++i) b.off[i + 1] = b.off[i] + cnt[i];
+  b.blk[0] = 0;
+  for (int i = 0; i < 6; ++i) {
+    b.off[i + 1] = b.off[i] + cnt[i];
+    b.blk[i + 1] = b.blk[i] + (unsigned)((cnt[i] + kBlock - 1) / kBlock);
+  }
   return b;
 }
 
-// coordinates of shell point i < b.off[6] (32-bit arithmetic: the grids of
-// the one-pass sweep stay below 2^31 points).  Branch-free: the block is
-// found by comparisons against the (uniform) block offsets, and each
-// coordinate by selects, so no per-lane indexing of the argument struct.
-__device__ __forceinline__ void shell_point(const Geometry& g, const ShellBox& b, unsigned i, int& x, int& y, int& z) {
-  const unsigned o1 = (unsigned)b.off[1], o2 = (unsigned)b.off[2], o3 = (unsigned)b.off[3];
-  const unsigned o4 = (unsigned)b.off[4], o5 = (unsigned)b.off[5];
-  const int r = (i >= o1) + (i >= o2) + (i >= o3) + (i >= o4) + (i >= o5);
-  const unsigned base = r == 0 ? 0u : r == 1 ? o1 : r == 2 ? o2 : r == 3 ? o3 : r == 4 ? o4 : o5;
-  const unsigned q = i - base;
+// Coordinates of the shell point of thread t in workgroup wg (relative to the
+// stage's first workgroup); false past the end of the workgroup's block.  The
+// block, its sizes and offsets are wave-uniform (scalar), so the decode costs
+// two 32-bit divisions and no per-lane access to the argument struct.
+__device__ __forceinline__ bool shell_point(const Geometry& g, const ShellBox& b, unsigned wg, unsigned t, int& x,
+                                           int& y, int& z) {
+  int r = 0;
+#pragma unroll
+  for (int k = 1; k < 6; ++k) r += wg >= b.blk[k] ? 1 : 0;
+  const unsigned q = (wg - b.blk[r]) * kBlock + t;
+  if (q >= (unsigned)(b.off[r + 1] - b.off[r])) return false;
   // inner width (fastest), middle extent, offsets of the three coordinates
-  const bool xs = r < 2, ys = r == 2 || r == 3;
-  const unsigned wi = xs ? (unsigned)(r == 0 ? b.xl : b.xh) : (unsigned)b.mx;
-  const unsigned wm = xs ? (unsigned)g.ny : ys ? (unsigned)(r == 2 ? b.yl : b.yh) : (unsigned)b.my;
+  unsigned wi, wm;
+  int ox, oy, oz;
+  if (r < 2) {
+    wi = r == 0 ? b.xl : b.xh;
+    wm = g.ny;
+    ox = r == 0 ? 0 : g.nx - b.xh;
+    oy = 0;
+    oz = 0;
+  } else if (r < 4) {
+    wi = b.mx;
+    wm = r == 2 ? b.yl : b.yh;
+    ox = b.xl;
+    oy = r == 2 ? 0 : g.ny - b.yh;
+    oz = 0;
+  } else {
+    wi = b.mx;
+    wm = b.my;
+    ox = b.xl;
+    oy = b.yl;
+    oz = r == 4 ? 0 : g.nz - b.zh;
+  }
   const unsigned row = q / wi;
   const unsigned zz = row / wm;
-  const int ci = (int)(q - row * wi), cm = (int)(row - zz * wm);
-  x = ci + (xs ? (r == 0 ? 0 : g.nx - b.xh) : b.xl);
-  y = cm + (xs ? 0 : ys ? (r == 2 ? 0 : g.ny - b.yh) : b.yl);
-  z = (int)zz + (r == 5 ? g.nz - b.zh : 0);
+  x = (int)(q - row * wi) + ox;
+  y = (int)(row - zz * wm) + oy;
+  z = (int)zz + oz;
+  return true;
 }
 
 __device__ __forceinline__ int point_depth(const Geometry& g, int x, int y, int z) {
@@ -1594,12 +1618,11 @@ struct ShellStage {
 };
 
 template <typename T, int R>
-__device__ __forceinline__ void shell_stage_point(const ShellStage<typename cpx<T>::t>& sp, unsigned i,
+__device__ __forceinline__ void shell_stage_point(const ShellStage<typename cpx<T>::t>& sp, unsigned wg,
                                                   const Geometry& g, const T* __restrict__ V, StencilCoef sc) {
   using C = typename cpx<T>::t;
-  if (i >= (unsigned)sp.box.off[6]) return;
   int x, y, z;
-  shell_point(g, sp.box, i, x, y, z);
+  if (!shell_point(g, sp.box, wg, threadIdx.x, x, y, z)) return;
   const int p = (z * g.ny + y) * g.nx + x;
   // Every load reads a valid address (clamped coordinates; absent operands
   // read the output array) and is masked afterwards, and all of them are
@@ -1688,9 +1711,9 @@ __global__ void __launch_bounds__(kBlock) shell_stage_kernel(ShellStage<typename
                                                              ShellStage<typename cpx<T>::t> b, Geometry g,
                                                              const T* __restrict__ V, StencilCoef sc) {
   if (blockIdx.x < a.nblk)
-    shell_stage_point<T, R>(a, blockIdx.x * kBlock + threadIdx.x, g, V, sc);
+    shell_stage_point<T, R>(a, blockIdx.x, g, V, sc);
   else
-    shell_stage_point<T, R>(b, (blockIdx.x - a.nblk) * kBlock + threadIdx.x, g, V, sc);
+    shell_stage_point<T, R>(b, blockIdx.x - a.nblk, g, V, sc);
 }
 
 // face operator of a shell round (one orbital, any window):
@@ -1915,7 +1938,7 @@ hipError_t shell_rounds_t(const abc_launch& L, const ShellScratch& W, const void
     sp.out = out;
     sp.alpha = alpha;
     sp.beta = beta;
-    sp.nblk = nblocks(sp.box.off[6]);
+    sp.nblk = sp.box.blk[6];
     return sp;
   };
   auto launch = [&](int k, const ShellStage<C>& sa, const ShellStage<C>& sb) {
