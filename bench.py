@@ -294,7 +294,7 @@ def bench_tdhf(Solver, torch, W, steps=10, full_steps=1000):
     ms = _time(torch, lambda: s.step(psi, aux, None, steps))
     out = {"grid": n, "orbitals": nb, "steps": steps, "ms_per_step": ms / steps,
            "value": n ** 3 * nb * steps / (ms / 1e3), "unit": "orbital-point-updates/s",
-           "path": "fused orbital batch" if s.use_fused else "staged"}
+           "path": ("orbital batch, " + s.path) if s.use_fused else "staged"}
     psi = torch.from_numpy(orb).to(torch.complex64).cuda().contiguous()
     aux = s.new_aux()
     s.step(psi, aux, None, full_steps)
@@ -327,7 +327,7 @@ def bench_tdhf_skyrme(Solver, torch, W, steps=10):
             "value": n ** 3 * nb * steps / (ms / 1e3), "unit": "orbital-point-updates/s",
             "cg_iterations_per_step": {"yukawa": (y1 - y0) / (e1 - e0), "coulomb": (c1 - c0) / (e1 - e0)},
             "cold_start_iterations": {"yukawa": y0 / max(e0, 1), "coulomb": c0 / max(e0, 1)},
-            "path": "fused orbital batch" if s.use_fused else "staged"}
+            "path": ("orbital batch, " + s.path) if s.use_fused else "staged"}
 
 
 def bench_r3(Solver, torch, wl, steps=20):

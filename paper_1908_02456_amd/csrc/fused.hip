@@ -54,6 +54,7 @@ struct FusedArgs {
   double2 m0, b0, a0;
   int face_off[7];
   int has_V;
+  long long bstride, fstride;  // one-pass sweep over orbitals: elements between orbitals' psi / aux arrays
 };
 
 template <typename C>
@@ -749,6 +750,13 @@ __global__ void __launch_bounds__(64 * rows4<T>()) fused4_kernel(const typename 
 
   const int lane = threadIdx.x & 63;
   const int r = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform row
+  // an orbital batch: blockIdx.y picks the orbital's arrays (V is shared)
+  pin += (long long)blockIdx.y * a.bstride;
+  pout += (long long)blockIdx.y * a.bstride;
+  if (FO) {
+    fin += (long long)blockIdx.y * a.fstride;
+    fout += (long long)blockIdx.y * a.fstride;
+  }
   int tile = blockIdx.x;
   if (a.tiles_per_xcd) tile = (blockIdx.x & 7) * a.tiles_per_xcd + (blockIdx.x >> 3);
   const int ty = tile % a.nty, tz = tile / a.nty;
@@ -1261,7 +1269,6 @@ bool fused4_supported(const abc_params& p, std::string* why) {
     return fused4_supported(q, why);
   }
   if (!fused_supported(p, why)) return false;
-  if (p.batch != 1 || p.meanfield != ABC_MF_NONE) return no("one-pass sweep: one orbital, no mean field");
   if (p.nx > kCols) return no("one-pass sweep: nx <= 128");
   if (p.order == ABC_FIRST) {
     // at most one y-face row and one z-face plane per tile
@@ -1321,7 +1328,13 @@ abc_status fused_prepare(const abc_params& p, abc_launch& L, std::vector<void*>*
   // boundary-shell rounds only when asked for: at 128^3 it measured level
   // with the staged path, w = 8 145 against 141 us per step, exact sections
   // 182 against 185)
-  const bool auto4 = fused4_supported(p, nullptr) && !fused_shell_case(p) && (p.order != ABC_FIRST || p.nx == kCols);
+  // Orbital batches and the mean field (orbitals as boxes of one launch):
+  // the one-pass sweep for complex64 (the 96^3 x 32-orbital TDHF batch: 0.61
+  // against 0.70 ms per step); complex128 measured level (0.95 against 0.94)
+  // and stays on the two-stage kernels.
+  const bool orbitals = p.batch > 1 || p.meanfield != ABC_MF_NONE;
+  const bool auto4 = fused4_supported(p, nullptr) && !fused_shell_case(p) &&
+                     (orbitals ? p.dtype == ABC_C64 : (p.order != ABC_FIRST || p.nx == kCols));
   L.fused_shell = 0;
   if (p.path == ABC_PATH_ONEPASS || (p.path == ABC_PATH_AUTO && auto4)) {
     if (!fused4_supported(p, &err)) return ABC_ENOTSUP;
@@ -1410,6 +1423,27 @@ hipError_t step4_t(const abc_launch& L, const abc_scratch& S, void* psi_v, doubl
     std::swap(src, dst);
     std::swap(fsrc, fdst);
   }
+  return hipGetLastError();
+}
+
+// one step of B orbitals (arrays [B][npts], aux [B][nface]) on the one-pass
+// sweep, one launch (blockIdx.y = orbital, V shared)
+template <typename T>
+hipError_t step4_orbitals(const abc_launch& L1, int B, const void* src, void* dst, const double2* fsrc, double2* fdst,
+                          const void* V_v, hipStream_t st, abc_timer* tm) {
+  using C = typename cpx<T>::t;
+  FusedArgs a = make_args4<T>(L1);
+  a.has_V = V_v != nullptr;
+  a.bstride = L1.g.npts;
+  a.fstride = L1.g.face_off[6];
+  const dim3 g(a.ntiles, B), b(64 * rows4<T>());
+  const bool full = a.nx == kCols;
+  const C* s = static_cast<const C*>(src);
+  C* d = static_cast<C*>(dst);
+  const T* V = static_cast<const T*>(V_v);
+  if (L1.order == ABC_FIRST) launch4<T, 3>(tm, full, g, b, st, s, d, V, a, fsrc, fdst);
+  else if (L1.order == ABC_ZEROTH) launch4<T, 2>(tm, full, g, b, st, s, d, V, a, nullptr, nullptr);
+  else launch4<T, 0>(tm, full, g, b, st, s, d, V, a, nullptr, nullptr);
   return hipGetLastError();
 }
 
@@ -1715,6 +1749,38 @@ hipError_t launch_step_orbitals(OrbitalBatch& ob, void* psi, double2* aux, const
     }
     m[b] = {&L1, &S, static_cast<char*>(ob.soa[0]) + (size_t)b * np * csz, first ? ob.soa_f[0] + (size_t)b * nf : nullptr,
             ob.veff ? ob.veff : V};
+  }
+  if (L1.fused_stages == 4) {
+    // one-pass sweep over all orbitals in one launch per step (blockIdx.y =
+    // orbital); the ping-pong between arrays A and B ends in A
+    for (int s = 0; s < n; ++s) {
+      const int cur = (s & 1) == 0 ? in : 1 - in;
+      if (ob.veff) {
+        const void* cs = ob.soa[cur];
+        const unsigned blocks = (unsigned)((np + 255) / 256);
+        if (L1.meanfield == ABC_MF_SKYRME)
+          e = skyrme_veff(*L1.pot, cs, true, B, c64, V, ob.veff, L1.t0, L1.t3, st, tm);
+        else if (c64)
+          abc_launch_kernel(tm, "meanfield", meanfield_soa_kernel<float>, dim3(blocks), dim3(256), st,
+                            static_cast<const float2*>(cs), static_cast<const float*>(V),
+                            static_cast<float*>(ob.veff), np, B, float(L1.t0), float(L1.t3));
+        else
+          abc_launch_kernel(tm, "meanfield", meanfield_soa_kernel<double>, dim3(blocks), dim3(256), st,
+                            static_cast<const double2*>(cs), static_cast<const double*>(V),
+                            static_cast<double*>(ob.veff), np, B, L1.t0, L1.t3);
+        if (e != hipSuccess) return e;
+      }
+      const void* Vs = ob.veff ? ob.veff : V;
+      e = c64 ? step4_orbitals<float>(L1, B, ob.soa[cur], ob.soa[1 - cur], first ? ob.soa_f[cur] : nullptr,
+                                      first ? ob.soa_f[1 - cur] : nullptr, Vs, st, tm)
+              : step4_orbitals<double>(L1, B, ob.soa[cur], ob.soa[1 - cur], first ? ob.soa_f[cur] : nullptr,
+                                       first ? ob.soa_f[1 - cur] : nullptr, Vs, st, tm);
+      if (e != hipSuccess) return e;
+      if (tm) tm->end_step();
+    }
+    e = c64 ? transpose<float2>(ob.soa[0], psi, np, B, false, st) : transpose<double2>(ob.soa[0], psi, np, B, false, st);
+    if (e == hipSuccess && first) e = transpose<double2>(ob.soa_f[0], aux, nf, B, false, st);
+    return e;
   }
   if (ob.pending && hipEventSynchronize(ob.copied) != hipSuccess) return hipErrorUnknown;
   const int total = fused_batch_build(m, ob.desc_host, n);

@@ -121,3 +121,43 @@ def test_onepass_windowed_headline_size_matches_staged(window, fejer):
     assert d <= TOL64, d
     da = (aux[0] - aux[1]).abs().max().item() / aux[0].abs().max().item()
     assert da <= TOL64, da
+
+
+# orbital batches (orbital-innermost state, transposed once per call) on the
+# one-pass sweep: one launch per step over all orbitals (blockIdx.y), the
+# mean field rebuilt from the current state before every step
+@pytest.mark.parametrize("order", ["first", "zeroth", "dirichlet"])
+@pytest.mark.parametrize("meanfield", [None, (-1.0, 0.5)], ids=["plain", "meanfield"])
+@pytest.mark.parametrize("steps", [3, 4])
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_onepass_orbital_batch_parity(order, meanfield, steps, dtype):
+    r = _run_pair("onepass orbitals %s %s" % (order, dtype), (21, 19, 37), 0.25, 0.004, 1, order, steps, s0=1.5,
+                  s1=1.5, batch=3, meanfield=meanfield, dtype=dtype, path="onepass", seed=17)
+    assert r["solver"].path == "onepass"
+    tol = TOL64 if dtype == "c128" else TOL32
+    assert r["err"] <= tol, r["err"]
+    if order == "first":
+        assert r["aux_err"] <= tol, r["aux_err"]
+
+
+def test_onepass_orbital_batch_long_range_meanfield_matches_two_pass():
+    from paper_1908_02456_amd.solver import Solver
+    print("case: onepass orbitals with the long-range mean field", flush=True)
+    shape, nb = (22, 18, 30), 4
+    mf = dict(t0=-1.0, t3=0.5, v0=-2.0, a=0.7, e2=1.44, tol=1e-13, maxit=500)
+    psi0 = torch.from_numpy(W.random_complex(shape + (nb,), seed=21)).cuda() * 0.3
+    V = torch.from_numpy(W.random_potential(shape, seed=22, scale=2.0)).cuda()
+    out, aux = [], []
+    for path in ("fused", "onepass"):
+        s = Solver(shape, 0.25, 0.004, order="first", s1=1.5, batch=nb, meanfield=mf, path=path)
+        assert s.path == path
+        psi = psi0.clone()
+        a = s.new_aux()
+        s.step(psi, a, V, 5)
+        out.append(psi)
+        aux.append(a)
+    torch.cuda.synchronize()
+    d = (out[0] - out[1]).abs().max().item() / out[0].abs().max().item()
+    assert d <= TOL64, d
+    da = (aux[0] - aux[1]).abs().max().item() / max(aux[0].abs().max().item(), 1e-300)
+    assert da <= TOL64, da
