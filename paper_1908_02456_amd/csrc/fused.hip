@@ -741,12 +741,12 @@ __global__ void __launch_bounds__(64 * rows4<T>()) fused4_kernel(const typename 
   // first-order face data (sizes in double2; 1 when unused)
   constexpr int NXF = FO ? 2 * ROWS * ITERS : 1, NXS = FO ? 2 * 4 * 2 * ROWS : 1, NXB = FO ? 2 * ROWS * 4 : 1;
   constexpr int NYS = FO ? 2 * 4 * 2 * 64 : 1, NYB = FO ? 4 * 2 * 64 : 1, NZC = FO ? ROWS * 2 * 64 * 2 : 1;
-  __shared__ double2 xf0[NXF];  // [side][row][march plane]        x-face f0
+  __shared__ double2 xf0[NXF];  // [march plane][side][row]        x-face f0
   __shared__ double2 xsrc[NXS];  // [plane parity][stage][side][row] x-face stage inputs A
-  __shared__ double2 xb[NXB];   // [side][row][plane & 3]          x-face bases
+  __shared__ double2 xb[NXB];   // [plane & 3][side][row]          x-face bases
   __shared__ double2 ysrc[NYS];  // [plane parity][stage][c][lane]  y-face stage inputs A
   __shared__ double2 yb[NYB];   // [plane & 3][c][lane]            y-face bases
-  __shared__ double2 zch[NZC];  // [row][c][lane][A, base]         z-face slots
+  __shared__ double2 zch[NZC];  // [row][c][A, base][lane]         z-face slots
 
   const int lane = threadIdx.x & 63;
   const int r = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform row
@@ -789,7 +789,7 @@ __global__ void __launch_bounds__(64 * rows4<T>()) fused4_kernel(const typename 
       const int yy = y0 - H + rr, zz = z0 - H + q;
       double2 v = make_double2(0, 0);
       if (yy >= 0 && yy < ny && zz >= 0 && zz < nz) v = fin[a.face_off[side] + zz * ny + yy];
-      xf0[i] = v;
+      xf0[(q * 2 + side) * ROWS + rr] = v;
     }
   }
   // Helper waves run in a loop of their own: the halo rows 0 and ROWS-1
@@ -915,7 +915,7 @@ __global__ void __launch_bounds__(64 * rows4<T>()) fused4_kernel(const typename 
             const int xcol = side ? xh : 0;
             const int lb = level_base4<T>(k - 1) - (k - 1);
             const int rr = min(max(row, k - 1), ROWS - k);  // a published row of level k-1
-            const int bi = (side * ROWS + row) * 4 + (zk & 3);
+            const int bi = ((zk & 3) * 2 + side) * ROWS + row;
             const C ce = rd[lb + rr][xcol & 1][xcol >> 1];
             const Item in{xsrc[((par * 4 + (k - 1)) * 2 + side) * ROWS + row], xb[bi],
                           make_double2((double)ce.x, (double)ce.y)};
@@ -931,7 +931,7 @@ __global__ void __launch_bounds__(64 * rows4<T>()) fused4_kernel(const typename 
               }
             }
             // the stage-1 input of the next plane (zi): f0
-            if (k == 1) xsrc[((npar * 4 + 0) * 2 + side) * ROWS + row] = xf0[(side * ROWS + row) * ITERS + it];
+            if (k == 1) xsrc[((npar * 4 + 0) * 2 + side) * ROWS + row] = xf0[(it * 2 + side) * ROWS + row];
           }
         }
         // the y-face row: stages [yk0, yk1], both columns of the lane
@@ -1079,16 +1079,16 @@ __global__ void __launch_bounds__(64 * rows4<T>()) fused4_kernel(const typename 
             for (int c = 0; c < 2; ++c) {
               if (!inx[c]) continue;
               const C ce = Yc[k - 1][c];
-              const int si = ((r * 2 + c) * 64 + lane) * 2;
+              const int si = (r * 2 + c) * 128 + lane;  // A at si, base at si + 64
               const double2 A = k == 1 ? fin[a.face_off[zface] + ybase + 2 * lane + c] : zch[si];
-              const double2 B = k == 1 ? A : zch[si + 1];
+              const double2 B = k == 1 ? A : zch[si + 64];
               o[c].x += T(gk * A.y);
               o[c].y -= T(gk * A.x);
               double2 nB;
               const double2 nA = aux_stage(k, A, B, make_double2((double)ce.x, (double)ce.y), nB);
               if (k < 4) {
                 zch[si] = nA;
-                zch[si + 1] = nB;
+                zch[si + 64] = nB;
               } else if (own_pt) {
                 fout[a.face_off[zface] + ybase + 2 * lane + c] = nA;
               }
