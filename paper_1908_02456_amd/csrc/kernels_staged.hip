@@ -1624,9 +1624,9 @@ __device__ __forceinline__ void shell_stage_point(const ShellStage<typename cpx<
   int x, y, z;
   if (!shell_point(g, sp.box, wg, threadIdx.x, x, y, z)) return;
   const int p = (z * g.ny + y) * g.nx + x;
-  // Every load reads a valid address (clamped coordinates; absent operands
-  // read the output array) and is masked afterwards, and all of them are
-  // issued before the first use, so one memory latency covers the point.
+  // The neighbour loads read valid addresses (clamped coordinates; an absent
+  // input reads the output array) and are masked afterwards, all issued
+  // before the first use.
   const bool has_in = sp.in != nullptr, has_aux = sp.aux != nullptr, has_base = sp.base != nullptr;
   const C* in = has_in ? sp.in : sp.out;
   const bool masked = sp.in_depth <= sp.box.d + R;  // neighbours deeper than in_depth exist
@@ -1652,18 +1652,30 @@ __device__ __forceinline__ void shell_stage_point(const ShellStage<typename cpx<
 #pragma unroll
   for (int m = 0; m < 1 + 6 * R; ++m) nv[m] = in[nidx[m]];
   const double vp = V ? (double)V[p] : 0.0;
-  const C bv = (has_base ? sp.base : in)[p];
-  const C ov = sp.out[p];
-  // E^T aux: the six faces, layer clamped to [0, R) and masked
-  const double2* fb = has_aux ? sp.aux : reinterpret_cast<const double2*>(sp.out);
-  const int lx0 = min(x, R - 1), lx1 = min(g.nx - 1 - x, R - 1);
-  const int ly0 = min(y, R - 1), ly1 = min(g.ny - 1 - y, R - 1);
-  const int lz0 = min(z, R - 1), lz1 = min(g.nz - 1 - z, R - 1);
-  auto fidx = [&](int f, int l, int t1, int t2) -> long long {
-    return has_aux ? g.face_off[f] + ((long long)l * g.face_n1[f] + t1) * g.face_n2[f] + t2 : 0;
-  };
-  const double2 v0 = fb[fidx(0, lx0, z, y)], v1 = fb[fidx(1, lx1, z, y)], v2 = fb[fidx(2, ly0, z, x)];
-  const double2 v3 = fb[fidx(3, ly1, z, x)], v4 = fb[fidx(4, lz0, y, x)], v5 = fb[fidx(5, lz1, y, x)];
+  // the rest only where it is used (the loads come from L2 with little
+  // reuse, so their number, not their latency, sets the time): the base and
+  // the accumulated output by the stage's (uniform) flags, the face values
+  // on the face layers only
+  C bv{}, ov{};
+  if (has_base) bv = sp.base[p];
+  if (sp.accumulate) ov = sp.out[p];
+  double2 v0{}, v1{}, v2{}, v3{}, v4{}, v5{};
+  const bool on_faces = has_aux && point_depth(g, x, y, z) < R;
+  if (on_faces) {
+    // E^T aux: the six faces, layer clamped to [0, R) and masked below
+    const int lx0 = min(x, R - 1), lx1 = min(g.nx - 1 - x, R - 1);
+    const int ly0 = min(y, R - 1), ly1 = min(g.ny - 1 - y, R - 1);
+    const int lz0 = min(z, R - 1), lz1 = min(g.nz - 1 - z, R - 1);
+    auto fv = [&](int f, int l, int t1, int t2) {
+      return sp.aux[g.face_off[f] + ((long long)l * g.face_n1[f] + t1) * g.face_n2[f] + t2];
+    };
+    v0 = fv(0, lx0, z, y);
+    v1 = fv(1, lx1, z, y);
+    v2 = fv(2, ly0, z, x);
+    v3 = fv(3, ly1, z, x);
+    v4 = fv(4, lz0, y, x);
+    v5 = fv(5, lz1, y, x);
+  }
   // -- arithmetic
   double hr = 0, hi = 0;
   if (has_in) {
@@ -1682,7 +1694,7 @@ __device__ __forceinline__ void shell_stage_point(const ShellStage<typename cpx<
       hi += sc.off[k] * sy;
     }
   }
-  if (has_aux) {
+  if (on_faces) {
     const bool m0 = x < R, m1 = x >= g.nx - R, m2 = y < R, m3 = y >= g.ny - R, m4 = z < R, m5 = z >= g.nz - R;
     hr += (m0 ? v0.x : 0.0) + (m1 ? v1.x : 0.0) + (m2 ? v2.x : 0.0) + (m3 ? v3.x : 0.0) + (m4 ? v4.x : 0.0) +
           (m5 ? v5.x : 0.0);
