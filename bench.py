@@ -264,7 +264,8 @@ def bench_batch(Batch, Solver, torch, W, steps=20):
 
 def bench_adjoint(Solver, torch, W):
     """Adjoint workload (96^3, 500 steps, first order, FP64): reverse-mode
-    gradient with sqrt(n) checkpoints, against the plain forward run."""
+    gradient with sqrt(n) checkpoints, and with the whole run kept as one
+    segment, against the plain forward run."""
     prm = W.adjoint_packet()
     n = prm["n"]
     s = Solver((n,) * 3, prm["h"], prm["dt"], order="first", s1=prm["s1"], window=prm["window"])
@@ -272,11 +273,18 @@ def bench_adjoint(Solver, torch, W):
     V = torch.from_numpy(W.gaussian_well((n,) * 3, prm["h"], prm["amplitude"])).cuda()
     out = {}
     ms_adj = _time(torch, lambda: out.setdefault("r", s.adjoint(psi0, V, prm["steps"], "prob")))
+    # one segment kept whole (every state and stage vector in HBM, about
+    # 28 GB here): no recompute and no separate forward sweep
+    ms_all = _time(torch, lambda: out.setdefault("a", s.adjoint(psi0, V, prm["steps"], "prob",
+                                                                ckpt_stride=prm["steps"])))
     psi = psi0.clone()
     aux = s.new_aux()
     ms_fwd = _time(torch, lambda: s.step(psi, aux, V, prm["steps"]))
+    dg = (out["r"][1] - out["a"][1]).abs().max().item() / out["r"][1].abs().max().item()
     return {"grid": n, "steps": prm["steps"], "J": out["r"][0], "ms_adjoint": ms_adj, "ms_forward": ms_fwd,
-            "adjoint_over_forward": ms_adj / ms_fwd, "forward_path": s.path}
+            "adjoint_over_forward": ms_adj / ms_fwd, "forward_path": s.path,
+            "ms_adjoint_one_segment": ms_all, "one_segment_over_forward": ms_all / ms_fwd,
+            "grad_psi0_rel_diff_between_the_two": dg}
 
 
 def bench_tdhf(Solver, torch, W, steps=10, full_steps=1000):

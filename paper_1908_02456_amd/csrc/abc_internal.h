@@ -224,6 +224,12 @@ hipError_t launch_step_staged(const abc_launch& L, const abc_scratch& S, void* p
                               const void* V, int n_steps, hipStream_t st, abc_timer* tm = nullptr,
                               void* const* keep = nullptr, const void* psi_in = nullptr,
                               const double2* aux_in = nullptr);
+// One fused step out of place (psi_in, aux_in) -> (psi_out, aux_out) on the
+// two-stage kernels (L must satisfy fused_supported), keeping the Horner
+// intermediates u1, u2, u3 of the step in keep[0..2] (psi-sized).
+hipError_t launch_step_fused_keep(const abc_launch& L, const abc_scratch& S, const void* psi_in,
+                                  const double2* aux_in, void* psi_out, double2* aux_out, const void* V,
+                                  void* const* keep, hipStream_t st);
 // Discrete adjoint (adjoint.hip).  La is L with the adjoint operators
 // (dt -> -dt, conjugate-transposed boundary operators, rescaled aux).
 struct abc_adjoint_args {

@@ -17,8 +17,11 @@
 //
 // Checkpoints every `stride` steps (default ceil(sqrt(n))), taken during a
 // forward sweep on the fastest available path; each segment is recomputed
-// once on the staged kernels, keeping every step's state and forward stage
-// vectors, then walked backwards with one adjoint step per step.
+// once, keeping every step's state and its intermediates (the two-stage fused
+// kernels' Horner intermediates where they apply, else the staged kernels'
+// stage vectors), then walked backwards with one adjoint step per step.  With
+// stride >= n there is one segment, kept whole: its recompute is the forward
+// run (4 + 3 psi-sized vectors per step in memory, no separate sweep).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -137,6 +140,27 @@ __global__ void __launch_bounds__(kBlock) vgrad_kernel(double* __restrict__ gV, 
   gV[p] += dt * acc;
 }
 
+// The same with the forward step in Horner form (u3 = z + (dt/4) L z,
+// u2 = z + (dt/3) L u3, u1 = z + (dt/2) L u2, z' = z + dt L u1): differentiating
+// the Horner recursion and moving each L to the adjoint side gives
+//   gV += dt Im(conj(y_0) u1) + dt/2 Im(conj(y_1) u2) + dt/3 Im(conj(y_2) u3)
+//         + dt/4 Im(conj(y_3) z),
+// with y_j the adjoint's sum-form stage vectors as above (y_0 = lambda).
+__global__ void __launch_bounds__(kBlock) vgrad_horner_kernel(
+    double* __restrict__ gV, const double2* __restrict__ y0, const double2* __restrict__ y1,
+    const double2* __restrict__ y2, const double2* __restrict__ y3, const double2* __restrict__ u1,
+    const double2* __restrict__ u2, const double2* __restrict__ u3, const double2* __restrict__ z0, long long n,
+    double dt) {
+  const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const double2 a[4] = {y0[p], y1[p], y2[p], y3[p]};
+  const double2 b[4] = {u1[p], u2[p], u3[p], z0[p]};
+  double acc = 0;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) acc += (a[j].x * b[j].y - a[j].y * b[j].x) / (double)(j + 1);
+  gV[p] += dt * acc;
+}
+
 template <int R, bool PER>
 hipError_t launch_objective(const abc_launch& L, const double2* psi, const double* V, int objective, double2* lam,
                             double* gV, double* partial, double* J, hipStream_t st) {
@@ -236,10 +260,33 @@ abc_status run_adjoint(const abc_launch& L, const abc_launch& La, const abc_scra
     }                                                    \
   } while (0)
 
-  // forward sweep with checkpoints
+  // a step that keeps its intermediates: the two-stage fused kernels (Horner
+  // form, u1 u2 u3 kept) wherever they cover the operators, else the staged
+  // kernels (sum form, z1 z2 z3 kept); the V gradient is formed to match
+  const bool horner = a.use_fused && !L.fused_shell && L.w == 0 && g.R == 1 && !L.periodic;
+  auto step_keeping = [&](int i, const double2* yin, const double2* fin, double2* yout, double2* fout) {
+    if (horner) return launch_step_fused_keep(L, S, yin, fin, yout, fout, V, &kz[3 * (size_t)i], st);
+    return launch_step_staged(L, S, yout, fout, V, 1, st, nullptr, &kz[3 * (size_t)i], yin, fin);
+  };
+
+  // forward sweep with checkpoints; with one segment (stride >= n: every
+  // state and stage vector kept) the segment's own recompute below is the
+  // forward run, and no separate sweep is made
   ABC_TRY(hipMemcpyAsync(X, a.psi0, pb, hipMemcpyDeviceToDevice, st));
   if (nf) ABC_TRY(hipMemsetAsync(fX, 0, nf * sizeof(double2), st));
-  for (int c = 0; c < nck; ++c) {
+  const bool single = nck == 1;
+  if (single) {
+    ABC_TRY(hipMemcpyAsync(ckp[0], X, pb, hipMemcpyDeviceToDevice, st));
+    if (nf) ABC_TRY(hipMemcpyAsync(ckf[0], fX, nf * sizeof(double2), hipMemcpyDeviceToDevice, st));
+    ABC_TRY(hipMemcpyAsync(seg[0], ckp[0], pb, hipMemcpyDeviceToDevice, st));
+    if (nf) ABC_TRY(hipMemcpyAsync(segf[0], ckf[0], nf * sizeof(double2), hipMemcpyDeviceToDevice, st));
+    for (int i = 0; i < N; ++i) {
+      double2* next = i + 1 < N ? seg[i + 1] : X;
+      double2* nextf = i + 1 < N ? segf[i + 1] : fX;
+      ABC_TRY(step_keeping(i, seg[i], nf ? segf[i] : nullptr, next, nf ? nextf : nullptr));
+    }
+  }
+  for (int c = 0; c < nck && !single; ++c) {
     ABC_TRY(hipMemcpyAsync(ckp[c], X, pb, hipMemcpyDeviceToDevice, st));
     if (nf) ABC_TRY(hipMemcpyAsync(ckf[c], fX, nf * sizeof(double2), hipMemcpyDeviceToDevice, st));
     const int k = std::min(stride, N - c * stride);
@@ -257,22 +304,28 @@ abc_status run_adjoint(const abc_launch& L, const abc_launch& La, const abc_scra
   for (int c = nck - 1; c >= 0; --c) {
     const int s0 = c * stride, len = std::min(stride, N - s0);
     // recompute the segment, keeping each step's state and stage vectors
-    ABC_TRY(hipMemcpyAsync(seg[0], ckp[c], pb, hipMemcpyDeviceToDevice, st));
-    if (nf) ABC_TRY(hipMemcpyAsync(segf[0], ckf[c], nf * sizeof(double2), hipMemcpyDeviceToDevice, st));
-    for (int i = 0; i < len; ++i) {
+    // (already there with one segment)
+    if (!single) ABC_TRY(hipMemcpyAsync(seg[0], ckp[c], pb, hipMemcpyDeviceToDevice, st));
+    if (nf && !single) ABC_TRY(hipMemcpyAsync(segf[0], ckf[c], nf * sizeof(double2), hipMemcpyDeviceToDevice, st));
+    for (int i = 0; i < len && !single; ++i) {
       // one step from seg[i] (and segf[i]) into the next slot, out of place
       double2* next = i + 1 < len ? seg[i + 1] : X;
       double2* nextf = i + 1 < len ? segf[i + 1] : fX;
-      ABC_TRY(launch_step_staged(L, S, next, nf ? nextf : nullptr, V, 1, st, nullptr, &kz[3 * (size_t)i], seg[i],
-                                 nf ? segf[i] : nullptr));
+      ABC_TRY(step_keeping(i, seg[i], nf ? segf[i] : nullptr, next, nf ? nextf : nullptr));
     }
     for (int i = len - 1; i >= 0; --i) {
       // adjoint step from lcur into lnext (mu in place), keeping its stage vectors
       ABC_TRY(launch_step_staged(La, S, lnext, nf ? mu : nullptr, V, 1, st, nullptr, ky, lcur));
-      vgrad_kernel<<<gb, kBlock, 0, st>>>(a.grad_V, lcur, static_cast<double2*>(ky[0]), static_cast<double2*>(ky[1]),
-                                          static_cast<double2*>(ky[2]), seg[i], static_cast<double2*>(kz[3 * i]),
-                                          static_cast<double2*>(kz[3 * i + 1]), static_cast<double2*>(kz[3 * i + 2]),
-                                          npl, L.dt);
+      if (horner)
+        vgrad_horner_kernel<<<gb, kBlock, 0, st>>>(
+            a.grad_V, lcur, static_cast<double2*>(ky[0]), static_cast<double2*>(ky[1]), static_cast<double2*>(ky[2]),
+            static_cast<double2*>(kz[3 * i]), static_cast<double2*>(kz[3 * i + 1]),
+            static_cast<double2*>(kz[3 * i + 2]), seg[i], npl, L.dt);
+      else
+        vgrad_kernel<<<gb, kBlock, 0, st>>>(a.grad_V, lcur, static_cast<double2*>(ky[0]),
+                                            static_cast<double2*>(ky[1]), static_cast<double2*>(ky[2]), seg[i],
+                                            static_cast<double2*>(kz[3 * i]), static_cast<double2*>(kz[3 * i + 1]),
+                                            static_cast<double2*>(kz[3 * i + 2]), npl, L.dt);
       ABC_TRY(hipGetLastError());
       std::swap(lcur, lnext);
     }

@@ -182,7 +182,8 @@ __device__ __forceinline__ void fused2_body(const typename cpx<T>::t* __restrict
                                             typename cpx<T>::t* __restrict__ out, const T* __restrict__ V,
                                             const FusedArgs& a, double cA, double cB,
                                             const double2* __restrict__ av, const double2* __restrict__ fb,
-                                            double2* __restrict__ aux_out, int tile) {
+                                            double2* __restrict__ aux_out, int tile,
+                                            typename cpx<T>::t* __restrict__ keep1 = nullptr) {
   using C = typename cpx<T>::t;
   constexpr int TY = kTY2, H = kHalo2;
   constexpr int ROWS = TY + 2 * H;
@@ -599,6 +600,14 @@ __device__ __forceinline__ void fused2_body(const typename cpx<T>::t* __restrict
           }
         }
       }
+      if (k == 1 && keep1 && own_row && zk >= z0 && zk < z0 + TZ && zk < nz) {
+        // the stage-1 output at the tile's own points (kept for the adjoint)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+          const int x = xb + 2 * lane + c;
+          if (x >= xo && x < xe) keep1[zk * sz + ybase + x] = o[c];
+        }
+      }
 #pragma unroll
       for (int c = 0; c < 2; ++c) {
         Yb[k - 1][c] = Yc[k - 1][c];
@@ -636,10 +645,11 @@ template <typename T, int ORDER, bool SAME_BASE, int TZ, int PF = 1>
 __global__ void __launch_bounds__(64 * (kTY2 + 2 * kHalo2)) fused2_kernel(
     const typename cpx<T>::t* __restrict__ w_in, const typename cpx<T>::t* __restrict__ base_in,
     typename cpx<T>::t* __restrict__ out, const T* __restrict__ V, FusedArgs a, double cA, double cB,
-    const double2* __restrict__ av, const double2* __restrict__ fb, double2* __restrict__ aux_out) {
+    const double2* __restrict__ av, const double2* __restrict__ fb, double2* __restrict__ aux_out,
+    typename cpx<T>::t* __restrict__ keep1) {
   int tile = blockIdx.x;
   if (a.tiles_per_xcd) tile = (blockIdx.x & 7) * a.tiles_per_xcd + (blockIdx.x >> 3);
-  fused2_body<T, ORDER, SAME_BASE, TZ, PF>(w_in, base_in, out, V, a, cA, cB, av, fb, aux_out, tile);
+  fused2_body<T, ORDER, SAME_BASE, TZ, PF>(w_in, base_in, out, V, a, cA, cB, av, fb, aux_out, tile, keep1);
 }
 
 // many boxes in one launch: the grid is the concatenation of the boxes' tiles
@@ -1491,19 +1501,19 @@ hipError_t step_t(const abc_launch& L, const abc_scratch& S, void* psi_v, double
     {
       if (L.order == ABC_ZEROTH) {
         launch2<T, 2, true>(tm, "fused2_half_a", tz, g1, b2, st, (const C*)src, (const C*)src, mid, V, a, dt / 4,
-                            dt / 3, none, none, none_w);
+                            dt / 3, none, none, none_w, (C*)nullptr);
         launch2<T, 2, false>(tm, "fused2_half_b", tz, g1, b2, st, (const C*)mid, (const C*)src, dst, V, a, dt / 2,
-                             dt, none, none, none_w);
+                             dt, none, none, none_w, (C*)nullptr);
       } else if (first) {
         launch2<T, 3, true>(tm, "fused2_half_a", tz, g1, b2, st, (const C*)src, (const C*)src, mid, V, a, dt / 4,
-                            dt / 3, (const double2*)fsrc, (const double2*)fsrc, vmid);
+                            dt / 3, (const double2*)fsrc, (const double2*)fsrc, vmid, (C*)nullptr);
         launch2<T, 3, false>(tm, "fused2_half_b", tz, g1, b2, st, (const C*)mid, (const C*)src, dst, V, a, dt / 2,
-                             dt, (const double2*)vmid, (const double2*)fsrc, fdst);
+                             dt, (const double2*)vmid, (const double2*)fsrc, fdst, (C*)nullptr);
       } else {
         launch2<T, 0, true>(tm, "fused2_half_a", tz, g1, b2, st, (const C*)src, (const C*)src, mid, V, a, dt / 4,
-                            dt / 3, none, none, none_w);
+                            dt / 3, none, none, none_w, (C*)nullptr);
         launch2<T, 0, false>(tm, "fused2_half_b", tz, g1, b2, st, (const C*)mid, (const C*)src, dst, V, a, dt / 2,
-                             dt, none, none, none_w);
+                             dt, none, none, none_w, (C*)nullptr);
       }
     }
     if (tm) tm->end_step();
@@ -1513,7 +1523,51 @@ hipError_t step_t(const abc_launch& L, const abc_scratch& S, void* psi_v, double
   return hipGetLastError();
 }
 
+// One step out of place on the two-stage kernels, keeping the Horner
+// intermediates u1, u2, u3 of the step (keep[0..2], psi-sized): half A writes
+// u2 and keeps its stage-1 output u3, half B keeps u1.
+template <typename T>
+hipError_t step_keep_t(const abc_launch& L, const abc_scratch& S, const void* psi_in, const double2* aux_in,
+                       void* psi_out, double2* aux_out, const void* V_v, void* const* keep, hipStream_t st) {
+  using C = typename cpx<T>::t;
+  FusedArgs a = make_args<T>(L);
+  a.has_V = V_v != nullptr;
+  const C* src = static_cast<const C*>(psi_in);
+  C* dst = static_cast<C*>(psi_out);
+  C* u1 = static_cast<C*>(keep[0]);
+  C* u2 = static_cast<C*>(keep[1]);
+  C* u3 = static_cast<C*>(keep[2]);
+  const T* V = static_cast<const T*>(V_v);
+  const double dt = L.dt;
+  const int tz = L.fused_tz;
+  const dim3 g1(a.ntiles), b2(64 * (kTY2 + 2 * kHalo2));
+  const double2* none = nullptr;
+  double2* none_w = nullptr;
+  double2* vmid = S.g[0];
+  if (L.order == ABC_ZEROTH) {
+    launch2<T, 2, true>(nullptr, "", tz, g1, b2, st, src, src, u2, V, a, dt / 4, dt / 3, none, none, none_w, u3);
+    launch2<T, 2, false>(nullptr, "", tz, g1, b2, st, (const C*)u2, src, dst, V, a, dt / 2, dt, none, none, none_w,
+                         u1);
+  } else if (L.order == ABC_FIRST) {
+    launch2<T, 3, true>(nullptr, "", tz, g1, b2, st, src, src, u2, V, a, dt / 4, dt / 3, aux_in, aux_in, vmid, u3);
+    launch2<T, 3, false>(nullptr, "", tz, g1, b2, st, (const C*)u2, src, dst, V, a, dt / 2, dt,
+                         (const double2*)vmid, aux_in, aux_out, u1);
+  } else {
+    launch2<T, 0, true>(nullptr, "", tz, g1, b2, st, src, src, u2, V, a, dt / 4, dt / 3, none, none, none_w, u3);
+    launch2<T, 0, false>(nullptr, "", tz, g1, b2, st, (const C*)u2, src, dst, V, a, dt / 2, dt, none, none, none_w,
+                         u1);
+  }
+  return hipGetLastError();
+}
+
 }  // namespace
+
+hipError_t launch_step_fused_keep(const abc_launch& L, const abc_scratch& S, const void* psi_in,
+                                  const double2* aux_in, void* psi_out, double2* aux_out, const void* V,
+                                  void* const* keep, hipStream_t st) {
+  if (L.dtype == ABC_C64) return step_keep_t<float>(L, S, psi_in, aux_in, psi_out, aux_out, V, keep, st);
+  return step_keep_t<double>(L, S, psi_in, aux_in, psi_out, aux_out, V, keep, st);
+}
 
 hipError_t launch_step_fused(const abc_launch& L, const abc_scratch& S, void* psi, double2* aux, const void* V,
                              int n_steps, hipStream_t st, abc_timer* tm) {

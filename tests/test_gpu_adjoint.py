@@ -52,6 +52,34 @@ def test_adjoint_matches_oracle(name, kw, R, kind, stride):
     assert np.abs(gV_g - gV).max() < TOL * np.abs(gV).max()
 
 
+FUSED_CASES = [c for c in CASES if c[0] in ("dirichlet-prob", "zeroth-R1-w0-energy", "first-w0-prob",
+                                             "first-w0-energy")]
+
+
+@pytest.mark.parametrize("name,kw,R,kind,stride0", FUSED_CASES)
+@pytest.mark.parametrize("stride", [0, 1, 3, 7])
+def test_adjoint_with_fused_recompute_matches_oracle(name, kw, R, kind, stride0, stride):
+    # the two-stage fused kernels recompute the segments, keeping the Horner
+    # intermediates u1, u2, u3 of every step, and the potential gradient is
+    # formed from them (stride 7 = the whole run as one segment: no separate
+    # forward sweep)
+    print("case: adjoint fused recompute", name, "stride", stride, flush=True)
+    Solver = _solver_cls()
+    shape, h, dt, steps = (9, 10, 11), 0.3, 0.01, 7
+    psi0 = W.random_complex(shape, seed=31) - (0.5 + 0.5j)
+    V = W.random_potential(shape, seed=32, scale=2.0)
+    okw = dict(kw)
+    st = integrate.make_setup(shape, h, dt, R, **okw)
+    J, gpsi, gV = oadj.adjoint_run(st, psi0, V, steps, kind)
+    s = Solver(shape, h, dt, radius=R, path="fused", **okw)
+    assert s.path == "fused"
+    Jg, gpsi_g, gV_g = s.adjoint(torch.from_numpy(psi0).cuda(), torch.from_numpy(V).cuda(), steps, kind, stride)
+    gpsi_g, gV_g = gpsi_g.cpu().numpy(), gV_g.cpu().numpy()
+    assert abs(Jg - J) < TOL * abs(J), (Jg, J)
+    assert np.abs(gpsi_g - gpsi).max() < TOL * np.abs(gpsi).max()
+    assert np.abs(gV_g - gV).max() < TOL * np.abs(gV).max()
+
+
 def test_adjoint_zero_steps_and_strides_agree():
     print("case: adjoint strides", flush=True)
     Solver = _solver_cls()
@@ -62,7 +90,7 @@ def test_adjoint_zero_steps_and_strides_agree():
     J0, g0, gV0 = s.adjoint(psi0, V, 0, "prob")
     assert torch.allclose(g0, 2 * 0.25 ** 3 * psi0, rtol=0, atol=0) and float(gV0.abs().max()) == 0.0
     # checkpoints come from the forward sweep (fused path) and segment states
-    # from the staged recompute, so strides agree to rounding, not bit for bit
+    # from the recompute, so strides agree to rounding, not bit for bit
     outs = [s.adjoint(psi0, V, 13, "prob", st) for st in (1, 4, 0, 13, 50)]
     for J, g, gV in outs[1:]:
         assert J == outs[0][0]
