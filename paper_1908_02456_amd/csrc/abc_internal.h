@@ -230,6 +230,12 @@ hipError_t launch_step_staged(const abc_launch& L, const abc_scratch& S, void* p
 hipError_t launch_step_fused_keep(const abc_launch& L, const abc_scratch& S, const void* psi_in,
                                   const double2* aux_in, void* psi_out, double2* aux_out, const void* V,
                                   void* const* keep, hipStream_t st);
+// The same (complex128) keeping the increments u1 - z, u2 - z, u3 - z of the
+// intermediates over the step's input z in keep[0..2] (differences without
+// cancellation); uses S.y[1] for u2.
+hipError_t launch_step_fused_keepd(const abc_launch& L, const abc_scratch& S, const void* psi_in,
+                                   const double2* aux_in, void* psi_out, double2* aux_out, const void* V,
+                                   void* const* keep, hipStream_t st);
 // Discrete adjoint (adjoint.hip).  La is L with the adjoint operators
 // (dt -> -dt, conjugate-transposed boundary operators, rescaled aux).
 struct abc_adjoint_args {

@@ -544,6 +544,8 @@ abc_status build_adjoint(abc_ctx* c) {
       return fail(ABC_EDEVICE, "hipMemcpy of adjoint kernel failed");
     La.face_ker = static_cast<const double2*>(kd);
     if (c->p.order == ABC_FIRST) La.a_loc[0] = make_double2(-c->L.a_loc[0].x, c->L.a_loc[0].y);
+    // the fused kernels' local face value (window 0)
+    if (K == 1) La.fused_m0 = La.fused_b0 = kh[0];
   }
   c->adjoint_ready = true;
   return ABC_OK;

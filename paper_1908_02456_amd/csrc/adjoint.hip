@@ -140,20 +140,29 @@ __global__ void __launch_bounds__(kBlock) vgrad_kernel(double* __restrict__ gV, 
   gV[p] += dt * acc;
 }
 
-// The same with the forward step in Horner form (u3 = z + (dt/4) L z,
-// u2 = z + (dt/3) L u3, u1 = z + (dt/2) L u2, z' = z + dt L u1): differentiating
-// the Horner recursion and moving each L to the adjoint side gives
+// The same with both steps in Horner form.  Forward: u3 = z + (dt/4) L z,
+// u2 = z + (dt/3) L u3, u1 = z + (dt/2) L u2, z' = z + dt L u1; differentiating
+// the recursion and moving each L to the adjoint side gives
 //   gV += dt Im(conj(y_0) u1) + dt/2 Im(conj(y_1) u2) + dt/3 Im(conj(y_2) u3)
 //         + dt/4 Im(conj(y_3) z),
-// with y_j the adjoint's sum-form stage vectors as above (y_0 = lambda).
-__global__ void __launch_bounds__(kBlock) vgrad_horner_kernel(
-    double* __restrict__ gV, const double2* __restrict__ y0, const double2* __restrict__ y1,
-    const double2* __restrict__ y2, const double2* __restrict__ y3, const double2* __restrict__ u1,
+// with y_j the adjoint's sum-form vectors as above (y_0 = lambda).  The
+// adjoint step's own Horner intermediates w3 = l + (dt/4) M l, w2 = l +
+// (dt/3) M w3, w1 = l + (dt/2) M w2 (M = L^H, l = lambda), kept as the
+// increments d_k = w_k - l, give those back:
+//   y1 = 4 d3,  y2 = 6 d2 - 8 d3,  y3 = 4 d1 - 8 d2 + 8/3 d3.
+__global__ void __launch_bounds__(kBlock) vgrad_horner2_kernel(
+    double* __restrict__ gV, const double2* __restrict__ lam, const double2* __restrict__ w1,
+    const double2* __restrict__ w2, const double2* __restrict__ w3, const double2* __restrict__ u1,
     const double2* __restrict__ u2, const double2* __restrict__ u3, const double2* __restrict__ z0, long long n,
     double dt) {
   const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= n) return;
-  const double2 a[4] = {y0[p], y1[p], y2[p], y3[p]};
+  const double2 d1 = w1[p], d2 = w2[p], d3 = w3[p];
+  double2 a[4];
+  a[0] = lam[p];
+  a[1] = make_double2(4.0 * d3.x, 4.0 * d3.y);
+  a[2] = make_double2(6.0 * d2.x - 8.0 * d3.x, 6.0 * d2.y - 8.0 * d3.y);
+  a[3] = make_double2(4.0 * d1.x - 8.0 * d2.x + (8.0 / 3.0) * d3.x, 4.0 * d1.y - 8.0 * d2.y + (8.0 / 3.0) * d3.y);
   const double2 b[4] = {u1[p], u2[p], u3[p], z0[p]};
   double acc = 0;
 #pragma unroll
@@ -222,7 +231,7 @@ abc_status run_adjoint(const abc_launch& L, const abc_launch& La, const abc_scra
   // psi-sized: X, lam, y0, 3 adjoint stage vectors, checkpoints, segment
   // states and 3 forward stage vectors per segment step
   const size_t npsi = 6 + (size_t)nck + nseg + 3 * (size_t)nseg;
-  const size_t total = npsi * (pb + round) + (2 + (size_t)nck + nseg) * (fb + round) +
+  const size_t total = npsi * (pb + round) + (3 + (size_t)nck + nseg) * (fb + round) +
                        ((size_t)nb + 1) * sizeof(double) + 2 * round;
   Arena ar;
   hipError_t e = hipMalloc(&ar.base, total);
@@ -243,6 +252,7 @@ abc_status run_adjoint(const abc_launch& L, const abc_launch& La, const abc_scra
   for (auto& q : kz) q = ar.take<double2>(pb);
   double2* fX = ar.take<double2>(fb);
   double2* mu = ar.take<double2>(fb);
+  double2* mu2 = ar.take<double2>(fb);  // the adjoint aux's second buffer (fused adjoint step, out of place)
   std::vector<double2*> ckf(nck), segf(nseg);
   for (auto& q : ckf) q = ar.take<double2>(fb);
   for (auto& q : segf) q = ar.take<double2>(fb);
@@ -314,15 +324,22 @@ abc_status run_adjoint(const abc_launch& L, const abc_launch& La, const abc_scra
       ABC_TRY(step_keeping(i, seg[i], nf ? segf[i] : nullptr, next, nf ? nextf : nullptr));
     }
     for (int i = len - 1; i >= 0; --i) {
-      // adjoint step from lcur into lnext (mu in place), keeping its stage vectors
-      ABC_TRY(launch_step_staged(La, S, lnext, nf ? mu : nullptr, V, 1, st, nullptr, ky, lcur));
-      if (horner)
-        vgrad_horner_kernel<<<gb, kBlock, 0, st>>>(
+      if (horner) {
+        // adjoint step from lcur into lnext on the fused kernels (the aux
+        // out of place: mu -> mu2), keeping its Horner increments
+        ABC_TRY(launch_step_fused_keepd(La, S, lcur, nf ? mu : nullptr, lnext, nf ? mu2 : nullptr, V, ky, st));
+        std::swap(mu, mu2);
+        vgrad_horner2_kernel<<<gb, kBlock, 0, st>>>(
             a.grad_V, lcur, static_cast<double2*>(ky[0]), static_cast<double2*>(ky[1]), static_cast<double2*>(ky[2]),
             static_cast<double2*>(kz[3 * i]), static_cast<double2*>(kz[3 * i + 1]),
             static_cast<double2*>(kz[3 * i + 2]), seg[i], npl, L.dt);
-      else
-        vgrad_kernel<<<gb, kBlock, 0, st>>>(a.grad_V, lcur, static_cast<double2*>(ky[0]),
+        ABC_TRY(hipGetLastError());
+        std::swap(lcur, lnext);
+        continue;
+      }
+      // adjoint step from lcur into lnext (mu in place), keeping its stage vectors
+      ABC_TRY(launch_step_staged(La, S, lnext, nf ? mu : nullptr, V, 1, st, nullptr, ky, lcur));
+      vgrad_kernel<<<gb, kBlock, 0, st>>>(a.grad_V, lcur, static_cast<double2*>(ky[0]),
                                             static_cast<double2*>(ky[1]), static_cast<double2*>(ky[2]), seg[i],
                                             static_cast<double2*>(kz[3 * i]), static_cast<double2*>(kz[3 * i + 1]),
                                             static_cast<double2*>(kz[3 * i + 2]), npl, L.dt);

@@ -176,14 +176,18 @@ struct Box2 {
   int pad;
 };
 
-template <typename T, int ORDER, bool SAME_BASE, int TZ, int PF>
+// KEEPD (the adjoint's Horner steps): keep1 receives the stage-1 increment
+// (output minus base) instead of the output, and keep2 the stage-2 increment,
+// so that differences of the intermediates carry no cancellation.
+template <typename T, int ORDER, bool SAME_BASE, int TZ, int PF, bool KEEPD = false>
 __device__ __forceinline__ void fused2_body(const typename cpx<T>::t* __restrict__ w_in,
                                             const typename cpx<T>::t* __restrict__ base_in,
                                             typename cpx<T>::t* __restrict__ out, const T* __restrict__ V,
                                             const FusedArgs& a, double cA, double cB,
                                             const double2* __restrict__ av, const double2* __restrict__ fb,
                                             double2* __restrict__ aux_out, int tile,
-                                            typename cpx<T>::t* __restrict__ keep1 = nullptr) {
+                                            typename cpx<T>::t* __restrict__ keep1 = nullptr,
+                                            typename cpx<T>::t* __restrict__ keep2 = nullptr) {
   using C = typename cpx<T>::t;
   constexpr int TY = kTY2, H = kHalo2;
   constexpr int ROWS = TY + 2 * H;
@@ -493,6 +497,8 @@ __device__ __forceinline__ void fused2_body(const typename cpx<T>::t* __restrict
       const T cf = T(k == 1 ? cA : cB);
       const bool active = r >= k && r < ROWS - k && it >= 2 * k && row_in && zk >= 0 && zk < nz;
       C o[2];
+      C dk[2];  // the stage's increment (KEEPD only)
+      if constexpr (KEEPD) dk[0] = dk[1] = czero<C>();
 #pragma unroll
       for (int c = 0; c < 2; ++c) {
         const int lx = 2 * lane + c, x = xb + lx;
@@ -524,6 +530,10 @@ __device__ __forceinline__ void fused2_body(const typename cpx<T>::t* __restrict
         // columns outside the box stay zero (they are x neighbours)
         o[c].x = in ? b0.x + cf * hi : T(0);
         o[c].y = in ? b0.y - cf * hr : T(0);
+        if constexpr (KEEPD) {
+          dk[c].x = in ? cf * hi : T(0);
+          dk[c].y = in ? -cf * hr : T(0);
+        }
       }
       if (ORDER == 3 && active) {
         // First order: the psi stage also sees -i sum_f g_f at face points,
@@ -542,6 +552,12 @@ __device__ __forceinline__ void fused2_body(const typename cpx<T>::t* __restrict
             o[0].y += -cf2 * (c0 ? g.x : 0.0);
             o[1].x += cf2 * (c1 ? g.y : 0.0);
             o[1].y += -cf2 * (c1 ? g.x : 0.0);
+            if constexpr (KEEPD) {
+              dk[0].x += cf2 * (c0 ? g.y : 0.0);
+              dk[0].y += -cf2 * (c0 ? g.x : 0.0);
+              dk[1].x += cf2 * (c1 ? g.y : 0.0);
+              dk[1].y += -cf2 * (c1 ? g.x : 0.0);
+            }
           } else {
             const T dx = T(cf2 * g.y), dy = T(-cf2 * g.x);
             o[0].x += c0 ? dx : T(0);
@@ -597,15 +613,23 @@ __device__ __forceinline__ void fused2_body(const typename cpx<T>::t* __restrict
             }
             o[c].x += T(cf2 * si);
             o[c].y += T(-cf2 * sr);
+            if constexpr (KEEPD) {
+              dk[c].x += T(cf2 * si);
+              dk[c].y += T(-cf2 * sr);
+            }
           }
         }
       }
-      if (k == 1 && keep1 && own_row && zk >= z0 && zk < z0 + TZ && zk < nz) {
-        // the stage-1 output at the tile's own points (kept for the adjoint)
+      C* kp = k == 1 ? keep1 : (KEEPD ? keep2 : nullptr);
+      if (kp && own_row && zk >= z0 && zk < z0 + TZ && zk < nz) {
+        // the stage-1 output (or with KEEPD the stage's increment) at the
+        // tile's own points, kept for the adjoint
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
           const int x = xb + 2 * lane + c;
-          if (x >= xo && x < xe) keep1[zk * sz + ybase + x] = o[c];
+          C v = o[c];
+          if constexpr (KEEPD) v = dk[c];
+          if (x >= xo && x < xe) kp[zk * sz + ybase + x] = v;
         }
       }
 #pragma unroll
@@ -650,6 +674,19 @@ __global__ void __launch_bounds__(64 * (kTY2 + 2 * kHalo2)) fused2_kernel(
   int tile = blockIdx.x;
   if (a.tiles_per_xcd) tile = (blockIdx.x & 7) * a.tiles_per_xcd + (blockIdx.x >> 3);
   fused2_body<T, ORDER, SAME_BASE, TZ, PF>(w_in, base_in, out, V, a, cA, cB, av, fb, aux_out, tile, keep1);
+}
+
+// the same keeping the stage increments (the adjoint's Horner steps)
+template <typename T, int ORDER, bool SAME_BASE, int TZ>
+__global__ void __launch_bounds__(64 * (kTY2 + 2 * kHalo2)) fused2_keepd_kernel(
+    const typename cpx<T>::t* __restrict__ w_in, const typename cpx<T>::t* __restrict__ base_in,
+    typename cpx<T>::t* __restrict__ out, const T* __restrict__ V, FusedArgs a, double cA, double cB,
+    const double2* __restrict__ av, const double2* __restrict__ fb, double2* __restrict__ aux_out,
+    typename cpx<T>::t* __restrict__ keep1, typename cpx<T>::t* __restrict__ keep2) {
+  int tile = blockIdx.x;
+  if (a.tiles_per_xcd) tile = (blockIdx.x & 7) * a.tiles_per_xcd + (blockIdx.x >> 3);
+  fused2_body<T, ORDER, SAME_BASE, TZ, 1, true>(w_in, base_in, out, V, a, cA, cB, av, fb, aux_out, tile, keep1,
+                                               keep2);
 }
 
 // many boxes in one launch: the grid is the concatenation of the boxes' tiles
@@ -1216,6 +1253,18 @@ void launch2(abc_timer* tm, const char* label, int tz, dim3 g, dim3 b, hipStream
   }
 }
 
+template <typename T, int ORDER, bool SB, typename... A>
+void launch2_keepd(int tz, dim3 g, dim3 b, hipStream_t st, A... args) {
+  if constexpr (ORDER == 3) {
+    if (tz == 4) return abc_launch_kernel(nullptr, "", fused2_keepd_kernel<T, ORDER, SB, 4>, g, b, st, args...);
+    return abc_launch_kernel(nullptr, "", fused2_keepd_kernel<T, ORDER, SB, 8>, g, b, st, args...);
+  } else {
+    if (tz == 4) return abc_launch_kernel(nullptr, "", fused2_keepd_kernel<T, ORDER, SB, 4>, g, b, st, args...);
+    if (tz == 16) return abc_launch_kernel(nullptr, "", fused2_keepd_kernel<T, ORDER, SB, 16>, g, b, st, args...);
+    return abc_launch_kernel(nullptr, "", fused2_keepd_kernel<T, ORDER, SB, 8>, g, b, st, args...);
+  }
+}
+
 template <typename T, int ORDER, bool SB>
 void launch2_batch(abc_timer* tm, const char* label, int tz, dim3 g, hipStream_t st, const Box2* boxes, int nbox,
                    int total, int half) {
@@ -1560,7 +1609,52 @@ hipError_t step_keep_t(const abc_launch& L, const abc_scratch& S, const void* ps
   return hipGetLastError();
 }
 
+// The same keeping the increments: keep[2] = u3 - z, keep[1] = u2 - z,
+// keep[0] = u1 - z (z the step's input); u2 itself goes to S.y[1].
+template <typename T>
+hipError_t step_keepd_t(const abc_launch& L, const abc_scratch& S, const void* psi_in, const double2* aux_in,
+                        void* psi_out, double2* aux_out, const void* V_v, void* const* keep, hipStream_t st) {
+  using C = typename cpx<T>::t;
+  FusedArgs a = make_args<T>(L);
+  a.has_V = V_v != nullptr;
+  const C* src = static_cast<const C*>(psi_in);
+  C* dst = static_cast<C*>(psi_out);
+  C* mid = static_cast<C*>(S.y[1]);
+  C* d1 = static_cast<C*>(keep[0]);
+  C* d2 = static_cast<C*>(keep[1]);
+  C* d3 = static_cast<C*>(keep[2]);
+  const T* V = static_cast<const T*>(V_v);
+  const double dt = L.dt;
+  const int tz = L.fused_tz;
+  const dim3 g1(a.ntiles), b2(64 * (kTY2 + 2 * kHalo2));
+  const double2* none = nullptr;
+  double2* none_w = nullptr;
+  double2* vmid = S.g[0];
+  C* nul = nullptr;
+  if (L.order == ABC_ZEROTH) {
+    launch2_keepd<T, 2, true>(tz, g1, b2, st, src, src, mid, V, a, dt / 4, dt / 3, none, none, none_w, d3, d2);
+    launch2_keepd<T, 2, false>(tz, g1, b2, st, (const C*)mid, src, dst, V, a, dt / 2, dt, none, none, none_w, d1,
+                               nul);
+  } else if (L.order == ABC_FIRST) {
+    launch2_keepd<T, 3, true>(tz, g1, b2, st, src, src, mid, V, a, dt / 4, dt / 3, aux_in, aux_in, vmid, d3, d2);
+    launch2_keepd<T, 3, false>(tz, g1, b2, st, (const C*)mid, src, dst, V, a, dt / 2, dt, (const double2*)vmid,
+                               aux_in, aux_out, d1, nul);
+  } else {
+    launch2_keepd<T, 0, true>(tz, g1, b2, st, src, src, mid, V, a, dt / 4, dt / 3, none, none, none_w, d3, d2);
+    launch2_keepd<T, 0, false>(tz, g1, b2, st, (const C*)mid, src, dst, V, a, dt / 2, dt, none, none, none_w, d1,
+                               nul);
+  }
+  return hipGetLastError();
+}
+
 }  // namespace
+
+hipError_t launch_step_fused_keepd(const abc_launch& L, const abc_scratch& S, const void* psi_in,
+                                   const double2* aux_in, void* psi_out, double2* aux_out, const void* V,
+                                   void* const* keep, hipStream_t st) {
+  if (L.dtype != ABC_C128) return hipErrorInvalidValue;
+  return step_keepd_t<double>(L, S, psi_in, aux_in, psi_out, aux_out, V, keep, st);
+}
 
 hipError_t launch_step_fused_keep(const abc_launch& L, const abc_scratch& S, const void* psi_in,
                                   const double2* aux_in, void* psi_out, double2* aux_out, const void* V,

@@ -77,7 +77,14 @@ def test_adjoint_with_fused_recompute_matches_oracle(name, kw, R, kind, stride0,
     gpsi_g, gV_g = gpsi_g.cpu().numpy(), gV_g.cpu().numpy()
     assert abs(Jg - J) < TOL * abs(J), (Jg, J)
     assert np.abs(gpsi_g - gpsi).max() < TOL * np.abs(gpsi).max()
-    assert np.abs(gV_g - gV).max() < TOL * np.abs(gV).max()
+    # dJ/dV sums per step terms dt Im(conj(y_j) u_j) of size about dt |lambda|
+    # |psi|; the device evaluates the adjoint step in Horner form, the oracle
+    # as the Taylor sum, so they differ by the terms' rounding.  Where J is
+    # conserved (the probability in a box with zero boundary values) the
+    # terms cancel to a gradient a hundred times smaller than they are, and
+    # the bar is set on the terms' size.
+    terms = dt * np.abs(gpsi).max() * np.abs(psi0).max()
+    assert np.abs(gV_g - gV).max() < TOL * max(np.abs(gV).max(), terms)
 
 
 def test_adjoint_zero_steps_and_strides_agree():
