@@ -186,13 +186,47 @@ def r22(B1, B0, A1, A0, s):
     return np.linalg.solve(s * s * np.eye(n) - s * B1 - B0, s * A1 + A0)
 
 
-def box_second(shape, h, R, s_pts, L=None) -> BoxOperators:
+# Relative singular-value level below which directions of the DtN maps are
+# left out of the second-order interpolation (see box_second).
+SECOND_ORDER_TAU = 1e-2
+
+
+def dominant_subspace(Ks, tau=SECOND_ORDER_TAU) -> np.ndarray:
+    """Real orthonormal basis U (n x r) of the directions in which the maps
+    K(s_j) act above tau times their largest singular value: the eigenvectors
+    of Re sum_j K_j K_j^H (= sum_j Re K_j Re K_j^T + Im K_j Im K_j^T) whose
+    eigenvalues exceed tau^2 times the largest.  The span holds the real and
+    imaginary parts of the columns, so it is closed under conjugation."""
+    G = sum((K @ K.conj().T).real for K in Ks)
+    w, V = np.linalg.eigh(G)
+    return V[:, w > tau * tau * w.max()]
+
+
+def box_second(shape, h, R, s_pts, L=None, tau=SECOND_ORDER_TAU) -> BoxOperators:
     """Second-order coefficients of the dense box form by four-point
     interpolation of the DtN map (Sec. 3.3; the paper gives no stability
-    theorem for this order)."""
+    theorem for this order and does not say how the coefficients are formed).
+
+    For R >= 2 the maps are numerically rank-deficient: the deeper boundary
+    layers reach the exterior only through the small outer stencil weights,
+    and the singular values fall into two groups with a wide gap between
+    them (the boundary's outermost layer above about 0.09 of the largest,
+    the rest below about 1e-3, for R = 2 and 3, h = 0.1 to 0.3).  The 4n
+    system is then singular to working precision.  The
+    interpolation runs in the dominant subspace U of the four maps: the
+    reduced maps U^T K_j U are interpolated, and each coefficient is lifted
+    as U X U^T.  The auxiliary variables then live in span(U): they start at
+    zero and every source and coupling maps into it, so the dropped
+    directions stay inert.  When no direction falls below tau (R = 1) this is
+    the plain 4n solve."""
     gamma = gamma_points(shape, R)
     Ks = [dtn_box(shape, h, R, s, L) for s in s_pts]
-    B1, B0, A1, A0 = interp_second(Ks, s_pts)
+    U = dominant_subspace(Ks, tau)
+    if U.shape[1] == len(gamma):
+        B1, B0, A1, A0 = interp_second(Ks, s_pts)
+    else:
+        red = interp_second([U.T @ K @ U for K in Ks], s_pts)
+        B1, B0, A1, A0 = (U @ X @ U.T for X in red)
     return BoxOperators("second", gamma, B1=B1, B0=B0, A1=A1, A0=A0, C=B1 @ A1 + A0)
 
 

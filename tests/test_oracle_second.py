@@ -74,3 +74,82 @@ def test_second_order_absorbs_better_than_first_order():
 
     e_dir, e1, e2 = err("dirichlet"), err("first", s1=1.0), err("second", s_second=S_PTS)
     assert e2 < 0.5 * e1 < 0.5 * e_dir, (e_dir, e1, e2)
+
+
+# R >= 2: the interpolation in the dominant subspace of the four maps
+REDUCED_CASES = [((7, 7, 7), 2, 0.3), ((7, 8, 7), 2, 0.3), ((9, 9, 9), 3, 0.3)]
+
+
+def _stack_singular_values(Ks):
+    G = sum((K @ K.conj().T).real for K in Ks)
+    w = np.sort(np.linalg.eigvalsh(G))[::-1]
+    return np.sqrt(np.maximum(w, 0.0) / w[0])
+
+
+@pytest.mark.parametrize("shape,R,h", REDUCED_CASES)
+def test_second_order_subspace_is_the_outer_layer_past_a_gap(shape, R, h):
+    # the kept dimension is the number of points of the outermost boundary
+    # layer, and the cut falls in a gap at least ten times wide on either
+    # side of tau (so that any eigen-solver keeps the same subspace)
+    Ks = [dtn.dtn_box(shape, h, R, s) for s in S_PTS]
+    U = dtn.dominant_subspace(Ks)
+    nz, ny, nx = shape
+    assert U.shape[1] == nx * ny * nz - (nx - 2) * (ny - 2) * (nz - 2)
+    sv = _stack_singular_values(Ks)
+    r = U.shape[1]
+    assert sv[r - 1] > 5 * dtn.SECOND_ORDER_TAU and sv[r] < dtn.SECOND_ORDER_TAU / 5, (sv[r - 1], sv[r])
+    assert np.abs(U.T @ U - np.eye(r)).max() < 1e-12
+    # nothing is dropped at R = 1
+    K1 = [dtn.dtn_box((6, 6, 7), 0.3, 1, s) for s in S_PTS]
+    assert dtn.dominant_subspace(K1).shape[1] == K1[0].shape[0]
+
+
+@pytest.mark.parametrize("shape,R,h", REDUCED_CASES[::2])
+def test_second_order_reduced_interpolation(shape, R, h):
+    Ks = [dtn.dtn_box(shape, h, R, s) for s in S_PTS]
+    bo = dtn.box_second(shape, h, R, S_PTS)
+    U = dtn.dominant_subspace(Ks)
+    n, r = U.shape
+    P = U @ U.T
+    for K, s in zip(Ks, S_PTS):
+        # R22 interpolates the map's part on the subspace at the four points
+        assert np.abs(dtn.r22(bo.B1, bo.B0, bo.A1, bo.A0, s) - P @ K @ P).max() < 1e-9 * np.abs(K).max()
+        # and what is left out is the small part, below tau of the map
+        assert np.linalg.norm(K - P @ K @ P, 2) < dtn.SECOND_ORDER_TAU * np.linalg.norm(K, 2)
+    # every coefficient maps span(U) into itself and is zero off it
+    Q = np.eye(n) - P
+    for X in (bo.B1, bo.B0, bo.A1, bo.A0):
+        assert np.abs(Q @ X).max() < 1e-11 * np.abs(X).max() and np.abs(X @ Q).max() < 1e-11 * np.abs(X).max()
+    # the result does not depend on the basis of the subspace
+    rot, _ = np.linalg.qr(np.random.default_rng(11).standard_normal((r, r)))
+    V = U @ rot
+    alt = dtn.interp_second([V.T @ K @ V for K in Ks], S_PTS)
+    for X, Y in zip((bo.B1, bo.B0, bo.A1, bo.A0), alt):
+        assert np.abs(V @ Y @ V.T - X).max() < 1e-7 * np.abs(X).max()
+    # the reduced auxiliary dynamics [[0, I], [B0, B1]] is stable
+    red = [U.T @ X @ U for X in (bo.B1, bo.B0)]
+    G = np.block([[np.zeros((r, r)), np.eye(r)], [red[1], red[0]]])
+    assert np.linalg.eigvals(G).real.max() < 0
+
+
+@pytest.mark.slow
+def test_second_order_absorbs_better_than_first_order_R2():
+    # the same ordering with the wider stencil, where the coefficients come
+    # from the dominant subspace
+    n, big, h, dt, steps, R = 10, 26, 0.25, 0.004, 160, 2
+    psi0 = W.gaussian_packet((n,) * 3, h, k=(2.0, 0.0, 0.0))
+    V = np.zeros((n,) * 3)
+    off = (big - n) // 2
+    pb = np.zeros((big,) * 3, complex)
+    pb[off:off + n, off:off + n, off:off + n] = psi0
+    ref, _, _ = integrate.run(integrate.make_setup((big,) * 3, h, dt, R, "dirichlet"), pb, np.zeros((big,) * 3),
+                              steps)
+    ref = ref[off:off + n, off:off + n, off:off + n]
+
+    def err(order, **kw):
+        st = integrate.make_setup((n,) * 3, h, dt, R, order, form="box", **kw)
+        psi, _, _ = integrate.run(st, psi0, V, steps)
+        return np.linalg.norm(psi - ref) / np.linalg.norm(ref)
+
+    e_dir, e1, e2 = err("dirichlet"), err("first", s1=1.0), err("second", s_second=S_PTS)
+    assert e2 < 0.5 * e1 < 0.5 * e_dir, (e_dir, e1, e2)
