@@ -554,6 +554,8 @@ def bench_paper_replica(Solver, torch, W, steps=600, every=50, big=97):
         torch.cuda.synchronize()
         out[name] = {"setup_s": setup_s, "ms_per_step": e0.elapsed_time(e1) / steps, "norm": norms,
                      "err_vs_reference": errs, "device_bytes": s.device_bytes()}
+        if kw.get("form") == "box":
+            out[name].update(s.box_info())
         del s, psi, aux
         torch.cuda.empty_cache()
     return out

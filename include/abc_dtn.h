@@ -155,7 +155,13 @@ void abc_params_default(abc_params* p);
  * half-line DtN symbols per transverse mode, kernel coefficients.
  * Second order: box form only (ABC_ENOTSUP for the face form), the four
  * points positive and pairwise distinct (ABC_EINVAL otherwise); its
- * coefficients come from one 4 n_Gamma square solve (Sec. 3.3).
+ * coefficients come from one square solve of the interpolation conditions
+ * (Sec. 3.3).  For R >= 2 the four maps are numerically rank-deficient and
+ * that system is singular in FP64, so the solve runs in the maps' dominant
+ * subspace U (singular values of the four maps together above 1e-2 of the
+ * largest; at R = 2 and 3 the boundary's outermost layer): the reduced maps
+ * U^T K U are interpolated and the coefficients lifted as U X U^T, a
+ * 4 r square solve (r = n_Gamma when nothing is dropped, as at R = 1).
  * Returns ABC_EUNSTABLE when a sign condition of the stability theorems
  * fails on the symbol, or when dt times the spectral-radius bound of the
  * kinetic and boundary operators exceeds the Taylor-4 stability limit
@@ -351,6 +357,9 @@ size_t abc_aux_elems(const abc_ctx* ctx);
  *            n x 2n) or [[0, I, A1], [B0, B1, B1 A1 + A0]] (second,
  *            2n x 3n, acting on [f; g; E psi]), n = n_Gamma.
  * which = 2: face-form normal-line blocks, a (R*R) then q (R*R) complex128.
+ * which = 3: box-form sizes, two complex128: (n_Gamma, r), r the dimension
+ *            the second order interpolates in (n_Gamma for the other
+ *            orders), then (spectral bound of the boundary block, 0).
  * n = capacity in complex128 elements; returns EINVAL if too small. */
 abc_status abc_export(const abc_ctx* ctx, int which, void* host_out, size_t n);
 

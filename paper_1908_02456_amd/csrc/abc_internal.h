@@ -64,9 +64,10 @@ abc_status build_face_ops(const abc_params& p, FaceOps& ops, std::string& err);
 
 // Box form: dense operators built on the device.  mat_dev receives the
 // row-major operator (box_rows x box_cols), q_dev the first order's
-// Lyapunov weight (n x n) or NULL.
+// Lyapunov weight (n x n) or NULL, subspace_dim the dimension of the
+// subspace the second order interpolates in (n_Gamma otherwise).
 abc_status build_box_ops(const abc_params& p, double2** mat_dev, double2** q_dev, int* n_gamma,
-                         std::vector<int>& gamma_lin, double* spectral_bound, std::string& err);
+                         std::vector<int>& gamma_lin, double* spectral_bound, int* subspace_dim, std::string& err);
 
 }  // namespace abc
 

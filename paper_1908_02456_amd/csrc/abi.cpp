@@ -35,6 +35,8 @@ struct abc_ctx {
   size_t bytes = 0;
   size_t aux_elems = 0;
   int n_gamma = 0;
+  int box_rank = 0;         // box form: dimension the second order interpolates in
+  double box_bound = 0;    // box form: spectral bound of the boundary block
   int use_fused = 0;
   double2* box_mat = nullptr;
   double2* box_q = nullptr;
@@ -223,7 +225,8 @@ abc_status abc_setup(const abc_params* pp, abc_ctx** out) {
   if (bc && p.form == ABC_FORM_BOX) {
     std::vector<int> glin;
     double bound = 0;
-    st = abc::build_box_ops(p, &c->box_mat, &c->box_q, &c->n_gamma, glin, &bound, err);
+    st = abc::build_box_ops(p, &c->box_mat, &c->box_q, &c->n_gamma, glin, &bound, &c->box_rank, err);
+    c->box_bound = bound;
     if (st != ABC_OK) { abc_destroy(c); return fail(st, err); }
     if (c->box_mat) { c->allocations.push_back(c->box_mat); c->bytes += abc::box_mat_elems(p.order, c->n_gamma) * 16; }
     if (c->box_q) { c->allocations.push_back(c->box_q); c->bytes += (size_t)c->n_gamma * c->n_gamma * 16; }
@@ -776,6 +779,14 @@ abc_status abc_export(const abc_ctx* c, int which, void* host_out, size_t n) {
     if (cnt > n) return fail(ABC_EINVAL, "buffer too small");
     if (hipMemcpy(host_out, c->box_mat, cnt * 16, hipMemcpyDeviceToHost) != hipSuccess)
       return fail(ABC_EDEVICE, "hipMemcpy failed");
+    return ABC_OK;
+  }
+  if (which == 3) {
+    if (!c->box_mat) return fail(ABC_EINVAL, "no box-form matrix");
+    if (n < 2) return fail(ABC_EINVAL, "buffer too small");
+    abc::cd* o = static_cast<abc::cd*>(host_out);
+    o[0] = abc::cd((double)c->n_gamma, (double)c->box_rank);
+    o[1] = abc::cd(c->box_bound, 0.0);
     return ABC_OK;
   }
   if (which == 2) {

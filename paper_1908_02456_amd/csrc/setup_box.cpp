@@ -228,6 +228,20 @@ __global__ void __launch_bounds__(kThreads) axpby_kernel(double2* __restrict__ z
   z[e] = make_double2(a * u.x + b * v.x, a * u.y + b * v.y);
 }
 
+// out[e] = Re in[e]
+__global__ void __launch_bounds__(kThreads) real_part_kernel(double* __restrict__ out, const double2* __restrict__ in,
+                                                             long long count) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < count) out[e] = in[e].x;
+}
+
+// out[e] = in[e] + 0 i
+__global__ void __launch_bounds__(kThreads) real_to_complex_kernel(double2* __restrict__ out,
+                                                                   const double* __restrict__ in, long long count) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < count) out[e] = make_double2(in[e], 0.0);
+}
+
 // column-major entries (i, j) = v from a host-built list of distinct entries
 __global__ void __launch_bounds__(kThreads) scatter_kernel(double2* __restrict__ m, long long ld,
                                                            const int* __restrict__ ij, const double2* __restrict__ v,
@@ -350,6 +364,78 @@ abc_status lu_solve(rocblas_handle hnd, DevBufs& db, int m, int nrhs, double2* A
     err = std::string("singular matrix: ") + what;
     return ABC_EUNSTABLE;
   }
+  return ABC_OK;
+}
+
+// Second order at R >= 2 (Sec. 3.3, which leaves open how the coefficients
+// are formed): the four maps are numerically rank-deficient, with singular
+// values in two groups far apart (the outermost boundary layer's and the
+// deeper layers', which reach the exterior only through the small outer
+// stencil weights), and the 4n interpolation system is singular to working
+// precision.  The interpolation then runs in the maps' dominant subspace:
+// directions whose singular value (of the four maps together) is below
+// kSecondTau of the largest are left out.
+constexpr double kSecondTau = 1e-2;
+
+// Real orthonormal basis of that subspace: the eigenvectors of
+// Re sum_j K_j K_j^H whose eigenvalues exceed kSecondTau^2 times the largest
+// (that span holds the real and imaginary parts of every column).  *U
+// receives it as complex n x r column-major, or nullptr when r == n.
+abc_status dominant_subspace(rocblas_handle hnd, DevBufs& db, int n, double2* const* K, double2** U, int* r,
+                             std::string& err) {
+  *U = nullptr;
+  *r = n;
+  const size_t nsq = (size_t)n * n;
+  double2* Gc = nullptr;
+  double *Gr = nullptr, *D = nullptr, *E = nullptr;
+  rocblas_int* info = nullptr;
+  if (!db.alloc(&Gc, nsq) || !db.alloc(&Gr, nsq) || !db.alloc(&D, (size_t)n) || !db.alloc(&E, (size_t)n) ||
+      !db.alloc(&info, 1)) {
+    err = "hipMalloc failed";
+    return ABC_ENOMEM;
+  }
+  const zc one(1.0, 0.0), zero(0.0, 0.0);
+  for (int j = 0; j < 4; ++j)
+    if (rocblas_zgemm_64(hnd, rocblas_operation_none, rocblas_operation_conjugate_transpose, n, n, n, &one,
+                         reinterpret_cast<const zc*>(K[j]), n, reinterpret_cast<const zc*>(K[j]), n,
+                         j ? &one : &zero, reinterpret_cast<zc*>(Gc), n) != rocblas_status_success) {
+      err = "device GEMM for the maps' Gram matrix failed";
+      return ABC_EDEVICE;
+    }
+  real_part_kernel<<<nblk((long long)nsq), kThreads>>>(Gr, Gc, (long long)nsq);
+  if (hipGetLastError() != hipSuccess) { err = "setup kernel launch failed"; return ABC_EDEVICE; }
+  db.release(Gc);
+  // eigenvalues ascending, eigenvectors in place of Gr (column j for D[j])
+  if (rocsolver_dsyevd(hnd, rocblas_evect_original, rocblas_fill_upper, n, Gr, n, D, E, info) !=
+      rocblas_status_success) {
+    err = "rocSOLVER eigen-decomposition failed";
+    return ABC_EDEVICE;
+  }
+  std::vector<double> w(n);
+  rocblas_int hinfo = 0;
+  if (hipMemcpy(w.data(), D, (size_t)n * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess ||
+      hipMemcpy(&hinfo, info, sizeof(hinfo), hipMemcpyDeviceToHost) != hipSuccess) {
+    err = "hipMemcpy failed";
+    return ABC_EDEVICE;
+  }
+  if (hinfo != 0) {
+    err = "eigen-decomposition of the maps' Gram matrix did not converge";
+    return ABC_EDEVICE;
+  }
+  const double cut = kSecondTau * kSecondTau * w[n - 1];
+  int keep = 0;
+  for (int i = 0; i < n; ++i) keep += w[i] > cut;
+  if (keep == 0) {
+    err = "second-order interpolation: the DtN maps vanish";
+    return ABC_EUNSTABLE;
+  }
+  *r = keep;
+  if (keep == n) return ABC_OK;
+  double2* Uc = nullptr;
+  if (!db.alloc(&Uc, (size_t)n * keep)) { err = "hipMalloc failed"; return ABC_ENOMEM; }
+  real_to_complex_kernel<<<nblk((long long)n * keep), kThreads>>>(Uc, Gr + (size_t)(n - keep) * n, (long long)n * keep);
+  if (hipGetLastError() != hipSuccess) { err = "setup kernel launch failed"; return ABC_EDEVICE; }
+  *U = Uc;
   return ABC_OK;
 }
 
@@ -508,12 +594,13 @@ abc_status power_bound(rocblas_handle hnd, DevBufs& db, const double2* mat, int 
 }  // namespace
 
 abc_status build_box_ops(const abc_params& p, double2** mat_dev, double2** q_dev, int* n_gamma,
-                         std::vector<int>& gamma_lin, double* spectral_bound, std::string& err) {
+                         std::vector<int>& gamma_lin, double* spectral_bound, int* subspace_dim, std::string& err) {
   *mat_dev = nullptr;
   *q_dev = nullptr;
   BoxGeom bg = box_geometry(p);
   const int n = (int)bg.glin.size();
   *n_gamma = n;
+  if (subspace_dim) *subspace_dim = n;
   gamma_lin = bg.glin;
   const double nn = (double)n * n * 16;
   const double need = p.order == ABC_SECOND ? 36 * nn : (p.order == ABC_FIRST ? 7 * nn : 3 * nn);
@@ -634,39 +721,85 @@ abc_status build_box_ops(const abc_params& p, double2** mat_dev, double2** q_dev
     db.release(Qcm);
     db.release(HH);
   } else if (st == ABC_OK && p.order == ABC_SECOND) {
-    // Sec. 3.3: [B1 B0 A1 A0] from one 4n x 4n solve of the transposed
-    // interpolation system; X^T(k n + b, a) = coefficient k at (a, b),
-    // k = B1, B0, A1, A0
+    // Sec. 3.3: [B1 B0 A1 A0] from one 4r x 4r solve of the transposed
+    // interpolation system, r the dimension of the maps' dominant subspace
+    // (r = n unless directions fall below kSecondTau; then the reduced maps
+    // U^T K_j U are interpolated and each coefficient lifted as U X U^T).
+    // X^T(k r + b, a) = coefficient k at (a, b), k = B1, B0, A1, A0
     const double sp[4] = {p.s1, p.s2, p.s3, p.s4};
     FourK fk{};
     double2* Kd[4] = {nullptr, nullptr, nullptr, nullptr};
     for (int j = 0; j < 4 && st == ABC_OK; ++j) st = dtn_matrix(p, gd, sp[j], hnd, db, &Kd[j], err);
-    const long long m = 4LL * n;
-    double2 *MT = nullptr, *XT = nullptr, *W = nullptr;
-    if (st == ABC_OK && (!db.alloc(&MT, (size_t)(m * m)) || !db.alloc(&XT, (size_t)(m * n)))) {
+    double2* U = nullptr;
+    int r = n;
+    if (st == ABC_OK) st = dominant_subspace(hnd, db, n, Kd, &U, &r, err);
+    const zc one(1.0, 0.0), zero(0.0, 0.0);
+    if (st == ABC_OK && U) {
+      // K_j <- U^T K_j U (r x r); U is real, so U^T is its adjoint
+      double2* T = nullptr;
+      if (!db.alloc(&T, (size_t)n * r)) { err = "hipMalloc failed"; st = ABC_ENOMEM; }
+      for (int j = 0; j < 4 && st == ABC_OK; ++j) {
+        double2* Kr = nullptr;
+        if (!db.alloc(&Kr, (size_t)r * r)) { err = "hipMalloc failed"; st = ABC_ENOMEM; break; }
+        if (rocblas_zgemm_64(hnd, rocblas_operation_none, rocblas_operation_none, n, r, n, &one,
+                             reinterpret_cast<const zc*>(Kd[j]), n, reinterpret_cast<const zc*>(U), n, &zero,
+                             reinterpret_cast<zc*>(T), n) != rocblas_status_success ||
+            rocblas_zgemm_64(hnd, rocblas_operation_transpose, rocblas_operation_none, r, r, n, &one,
+                             reinterpret_cast<const zc*>(U), n, reinterpret_cast<const zc*>(T), n, &zero,
+                             reinterpret_cast<zc*>(Kr), r) != rocblas_status_success) {
+          err = "device GEMM for the reduced maps failed";
+          st = ABC_EDEVICE;
+        }
+        db.release(Kd[j]);
+        Kd[j] = Kr;
+      }
+      db.release(T);
+    }
+    const long long m = 4LL * r, mf = 4LL * n;
+    double2 *MT = nullptr, *XR = nullptr, *XT = nullptr, *W = nullptr;
+    if (st == ABC_OK && (!db.alloc(&MT, (size_t)(m * m)) || !db.alloc(&XR, (size_t)(m * r)))) {
       err = "hipMalloc failed";
       st = ABC_ENOMEM;
     }
     if (st == ABC_OK) {
       for (int j = 0; j < 4; ++j) { fk.K[j] = Kd[j]; fk.s[j] = sp[j]; }
-      dim3 grid(nblk(m), (unsigned)std::min<long long>(m + n, 65535));
-      second_system_kernel<<<grid, kThreads>>>(MT, XT, n, fk);
+      dim3 grid(nblk(m), (unsigned)std::min<long long>(m + r, 65535));
+      second_system_kernel<<<grid, kThreads>>>(MT, XR, r, fk);
       st = launch_ok(err);
     }
     for (int j = 0; j < 4; ++j) db.release(Kd[j]);
-    if (st == ABC_OK) st = lu_solve(hnd, db, (int)m, n, MT, XT, err, "second-order interpolation system");
+    if (st == ABC_OK) st = lu_solve(hnd, db, (int)m, r, MT, XR, err, "second-order interpolation system");
     db.release(MT);
+    if (st == ABC_OK && U) {
+      // coefficient_k^T = U Y~_k U^T into the full 4n x n layout (ld 4n)
+      double2* T = nullptr;
+      if (!db.alloc(&XT, (size_t)(mf * n)) || !db.alloc(&T, (size_t)n * r)) { err = "hipMalloc failed"; st = ABC_ENOMEM; }
+      for (int k = 0; k < 4 && st == ABC_OK; ++k)
+        if (rocblas_zgemm_64(hnd, rocblas_operation_none, rocblas_operation_none, n, r, r, &one,
+                             reinterpret_cast<const zc*>(U), n, reinterpret_cast<const zc*>(XR + (long long)k * r), m,
+                             &zero, reinterpret_cast<zc*>(T), n) != rocblas_status_success ||
+            rocblas_zgemm_64(hnd, rocblas_operation_none, rocblas_operation_transpose, n, n, r, &one,
+                             reinterpret_cast<const zc*>(T), n, reinterpret_cast<const zc*>(U), n, &zero,
+                             reinterpret_cast<zc*>(XT + (long long)k * n), mf) != rocblas_status_success) {
+          err = "device GEMM lifting the second-order coefficients failed";
+          st = ABC_EDEVICE;
+        }
+      db.release(T);
+      db.release(XR);
+      db.release(U);
+    } else {
+      XT = XR;
+    }
     // C^T = A1^T B1^T + A0^T; the view Y_k = XT + k n (lda 4n) is coefficient_k^T
     if (st == ABC_OK && !db.alloc(&W, (size_t)n * n)) { err = "hipMalloc failed"; st = ABC_ENOMEM; }
     if (st == ABC_OK) {
-      copy2d(W, n, XT + 3LL * n, m, n, n, one2, 0.0);  // row a of W = column a of Y_3: W = Y_3 column-major
+      copy2d(W, n, XT + 3LL * n, mf, n, n, one2, 0.0);  // row a of W = column a of Y_3: W = Y_3 column-major
       st = launch_ok(err);
     }
     if (st == ABC_OK) {
-      const zc one(1.0, 0.0);
       // W (column-major, = Y_3 = A0^T) += Y_2 Y_0 = A1^T B1^T
       if (rocblas_zgemm_64(hnd, rocblas_operation_none, rocblas_operation_none, n, n, n, &one,
-                           reinterpret_cast<const zc*>(XT + 2LL * n), m, reinterpret_cast<const zc*>(XT), m, &one,
+                           reinterpret_cast<const zc*>(XT + 2LL * n), mf, reinterpret_cast<const zc*>(XT), mf, &one,
                            reinterpret_cast<zc*>(W), n) != rocblas_status_success) {
         err = "device GEMM for B1 A1 + A0 failed";
         st = ABC_EDEVICE;
@@ -679,14 +812,15 @@ abc_status build_box_ops(const abc_params& p, double2** mat_dev, double2** q_dev
       const long long ld = 3LL * n;
       if (hipMemset(out, 0, (size_t)2 * n * ld * 16) != hipSuccess) { err = "hipMemset failed"; st = ABC_EDEVICE; }
       copy2d(out + n, ld, out + n, ld, n, n, make_double2(0.0, 0.0), 1.0);  // identity block
-      copy2d(out + 2LL * n, ld, XT + 2LL * n, m, n, n, one2, 0.0);          // A1
-      copy2d(out + n * ld, ld, XT + 1LL * n, m, n, n, one2, 0.0);           // B0
-      copy2d(out + n * ld + n, ld, XT, m, n, n, one2, 0.0);                 // B1
+      copy2d(out + 2LL * n, ld, XT + 2LL * n, mf, n, n, one2, 0.0);         // A1
+      copy2d(out + n * ld, ld, XT + 1LL * n, mf, n, n, one2, 0.0);          // B0
+      copy2d(out + n * ld + n, ld, XT, mf, n, n, one2, 0.0);                // B1
       copy2d(out + n * ld + 2LL * n, ld, W, n, n, n, one2, 0.0);            // C
       if (st == ABC_OK) st = launch_ok(err);
     }
     db.release(W);
     db.release(XT);
+    if (subspace_dim) *subspace_dim = r;
   }
   // spectral radius of M (zeroth), B (first) or the (f, g) block
   // [[0, I], [B0, B1]] (second), with a safety factor; the row-sum norm of

@@ -281,6 +281,12 @@ class Solver:
         _lib.check(self._lib.abc_export(self._ctx, which, buf.ctypes.data, count))
         return buf
 
+    def box_info(self) -> dict:
+        """Box form: n_Gamma, the dimension the second order interpolates in,
+        and the spectral bound of the boundary block."""
+        v = self.export(3, 2)
+        return {"n_gamma": int(v[0].real), "subspace_dim": int(v[0].imag), "bound": float(v[1].real)}
+
     def face_kernel(self) -> np.ndarray:
         R, w = self.params.radius, self.params.window
         K = 2 * w + 1
