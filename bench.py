@@ -331,11 +331,32 @@ def bench_tdhf_skyrme(Solver, torch, W, steps=10):
     e0, y0, c0 = s.potential_iterations()
     ms = _time(torch, lambda: s.step(psi, aux, None, steps))
     e1, y1, c1 = s.potential_iterations()
-    return {"grid": n, "orbitals": nb, "steps": steps, "ms_per_step": ms / steps,
-            "value": n ** 3 * nb * steps / (ms / 1e3), "unit": "orbital-point-updates/s",
-            "cg_iterations_per_step": {"yukawa": (y1 - y0) / (e1 - e0), "coulomb": (c1 - c0) / (e1 - e0)},
-            "cold_start_iterations": {"yukawa": y0 / max(e0, 1), "coulomb": c0 / max(e0, 1)},
-            "path": ("orbital batch, " + s.path) if s.use_fused else "staged"}
+    out = {"grid": n, "orbitals": nb, "steps": steps, "ms_per_step": ms / steps,
+           "value": n ** 3 * nb * steps / (ms / 1e3), "unit": "orbital-point-updates/s",
+           "cg_iterations_per_step": {"yukawa": (y1 - y0) / (e1 - e0), "coulomb": (c1 - c0) / (e1 - e0)},
+           "cold_start_iterations": {"yukawa": y0 / max(e0, 1), "coulomb": c0 / max(e0, 1)},
+           "path": ("orbital batch, " + s.path) if s.use_fused else "staged"}
+    # one CG iteration per solve issued without host reads (the sine-transform
+    # preconditioner is exact at R = 1; the unconverged count checks it),
+    # eagerly and as a captured graph of the same steps replayed
+    del s
+    fixed = 1
+    sf = Solver((n,) * 3, h, 0.002, order="first", s1=1.0, window=0, dtype="c64", batch=nb,
+                meanfield=dict(mf, fixed_iters=fixed))
+    psi = torch.from_numpy(orb).to(torch.complex64).cuda().contiguous()
+    aux = sf.new_aux()
+    sf.step(psi, aux, None, 2)
+    ms_fixed = _time(torch, lambda: sf.step(psi, aux, None, steps))
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        sf.step(psi, aux, None, steps)
+    g.replay()
+    ms_graph = _time(torch, lambda: g.replay())
+    out["fixed_iterations"] = {"iterations_per_solve": fixed, "ms_per_step": ms_fixed / steps,
+                               "ms_per_step_graph_replay": ms_graph / steps,
+                               "value_graph_replay": n ** 3 * nb * steps / (ms_graph / 1e3),
+                               "unconverged_solves": sf.potential_unconverged()}
+    return out
 
 
 def bench_r3(Solver, torch, wl, steps=20):
@@ -349,6 +370,34 @@ def bench_r3(Solver, torch, wl, steps=20):
     ms = _time(torch, lambda: s.step(psi, aux, V, steps))
     return {"radius": 3, "ms_per_step": ms / steps, "value": wl.n ** 3 * steps / (ms / 1e3),
             "unit": "grid-point-updates/s", "path": s.path}
+
+
+def bench_free_packet(Solver, torch, W, big=128):
+    """The free-packet workload (32^3, h = 0.25, zeroth order s0 = 1, 200
+    steps of dt = 0.005, k = 2 along x, centred) against the same packet in a
+    big^3 zero-boundary box cut back to the small one: relative L2 error at
+    T and time per step, for the dense box form, the face form and zero
+    boundary values."""
+    wl = W.free_packet_small()
+    n = wl.n
+    off = (big - n) // 2
+    pb = torch.zeros((big,) * 3, dtype=torch.complex128, device="cuda")
+    pb[off:off + n, off:off + n, off:off + n] = torch.from_numpy(wl.psi0).cuda()
+    Solver((big,) * 3, wl.h, wl.dt, order="dirichlet").step(pb, None, None, wl.steps)
+    ref = pb[off:off + n, off:off + n, off:off + n].clone()
+    nr = torch.linalg.vector_norm(ref).item()
+    out = {"grid": n, "reference_grid": big, "h": wl.h, "dt": wl.dt, "steps": wl.steps, "T": wl.steps * wl.dt}
+    for name, kw in (("zeroth_box", dict(order="zeroth", form="box", s0=wl.s0)),
+                     ("zeroth_faces", dict(order="zeroth", form="faces", s0=wl.s0)),
+                     ("dirichlet", dict(order="dirichlet"))):
+        s = Solver((n,) * 3, wl.h, wl.dt, **kw)
+        psi = torch.from_numpy(wl.psi0).cuda().contiguous()
+        s.step(psi, None, None, wl.steps)
+        torch.cuda.synchronize()
+        e = torch.linalg.vector_norm(psi - ref).item() / nr
+        ms = _time(torch, lambda: s.step(psi, None, None, 50)) / 50
+        out[name] = {"err_vs_large_box": e, "ms_per_step": ms, "path": s.path}
+    return out
 
 
 def bench_box_batch(Solver, torch, W, nb=32, steps=20):
@@ -763,6 +812,7 @@ def main():
                          ("tdhf", lambda: bench_tdhf(Solver, torch, W)),
                          ("tdhf_skyrme", lambda: bench_tdhf_skyrme(Solver, torch, W)),
                          ("r3", lambda: bench_r3(Solver, torch, wl)),
+                         ("free_packet", lambda: bench_free_packet(Solver, torch, W)),
                          ("box_batch", lambda: bench_box_batch(Solver, torch, W)),
                          ("orders_box", lambda: bench_orders_box(Solver, torch, W)),
                          ("box64", lambda: bench_box64(Solver, torch, W)),

@@ -140,7 +140,16 @@ typedef struct {
   double e2;            /* Coulomb e^2 (0: no Coulomb term)                 */
   double pcg_tol;       /* relative residual of the solves (> 0)            */
   int pcg_maxit;        /* iteration cap per solve (>= 1)                   */
-  int reserved2[3];     /* must be zero                                     */
+  int pcg_fixed;        /* 0: each solve reads its convergence flag on the
+                           host after every iteration and stops there (the
+                           step synchronises its stream); k >= 1: each solve
+                           issues exactly k iterations and reads nothing on
+                           the host (iterations after convergence are
+                           skipped on the device), so that abc_step can be
+                           captured in a HIP graph; solves still unconverged
+                           after k iterations are counted on the device
+                           (abc_potential_unconverged)                     */
+  int reserved2[2];     /* must be zero                                     */
 } abc_params;
 
 /* Fill p with defaults (R = 1, first order, face form, w = 0, fejer = 1,
@@ -306,16 +315,25 @@ abc_status abc_h2_objective(const abc_params* p, const double* s1, int count,
  * t0 rho + t3 rho^2 plus the Yukawa and Coulomb fields of rho = sum over
  * orbitals of |psi_j|^2, solved as in abc_step (the solves start from the
  * context's previous potentials).  psi, V (may be NULL) and out ([z][y][x],
- * the state's real type) are device buffers.  The call synchronises the
- * stream (the solves read their convergence flag on the host).
+ * the state's real type) are device buffers.  With pcg_fixed = 0 the call
+ * synchronises the stream (the solves read their convergence flag on the
+ * host).
  * ABC_ENOTSUP for other mean fields. */
 abc_status abc_effective_potential(abc_ctx* ctx, const void* psi, const void* V,
                                    void* out, void* stream);
 
 /* Conjugate-gradient work of the ABC_MF_SKYRME solves so far: out[0] =
  * number of mean-field evaluations, out[1] = Yukawa iterations, out[2] =
- * Coulomb iterations (all zero for other mean fields). */
+ * Coulomb iterations (all zero for other mean fields).  With pcg_fixed >= 1
+ * the iteration counts are kept on the device and this call synchronises
+ * the device to read them. */
 abc_status abc_potential_iterations(const abc_ctx* ctx, long long* out);
+
+/* Number of ABC_MF_SKYRME solves so far that ended without reaching
+ * pcg_tol (at pcg_maxit, or after the pcg_fixed iterations), into *out;
+ * counted on the device, so the call synchronises the device.  0 for other
+ * mean fields. */
+abc_status abc_potential_unconverged(const abc_ctx* ctx, long long* out);
 
 /* FP64 diagnostics of a state, written to device memory out (3*batch + 1
  * doubles): [0, batch) norm h^3 sum |psi_j|^2; [batch, 2 batch) Lyapunov

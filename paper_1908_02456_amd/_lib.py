@@ -25,7 +25,8 @@ EXPORTED = ["abc_params_default", "abc_setup", "abc_step", "abc_diagnostics", "a
             "abc_step_timed", "abc_launch_label", "abc_adjoint", "abc_tune", "abc_setup_batch",
             "abc_step_batch", "abc_tune_batch", "abc_batch_aux_elems", "abc_batch_launch_groups",
             "abc_batch_tile_depth", "abc_destroy_batch", "abc_h2_objective",
-            "abc_effective_potential", "abc_potential_iterations", "abc_state_save", "abc_state_load",
+            "abc_effective_potential", "abc_potential_iterations", "abc_potential_unconverged", "abc_state_save",
+            "abc_state_load",
             "abc_diagnostics_noalloc", "abc_step_monitored"]
 
 
@@ -41,7 +42,8 @@ class AbcParams(ctypes.Structure):
         ("path", ctypes.c_int), ("diag_every", ctypes.c_int), ("reserved", ctypes.c_int * 2),
         ("s3", ctypes.c_double), ("s4", ctypes.c_double),
         ("v0", ctypes.c_double), ("a_yukawa", ctypes.c_double), ("e2", ctypes.c_double),
-        ("pcg_tol", ctypes.c_double), ("pcg_maxit", ctypes.c_int), ("reserved2", ctypes.c_int * 3),
+        ("pcg_tol", ctypes.c_double), ("pcg_maxit", ctypes.c_int), ("pcg_fixed", ctypes.c_int),
+        ("reserved2", ctypes.c_int * 2),
     ]
 
 
@@ -100,6 +102,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.abc_effective_potential.restype = ctypes.c_int
     lib.abc_potential_iterations.argtypes = [vp, ctypes.POINTER(ctypes.c_longlong)]
     lib.abc_potential_iterations.restype = ctypes.c_int
+    lib.abc_potential_unconverged.argtypes = [vp, ctypes.POINTER(ctypes.c_longlong)]
+    lib.abc_potential_unconverged.restype = ctypes.c_int
     lib.abc_state_save.argtypes = [vp, vp, vp, ctypes.c_longlong, ctypes.c_char_p, vp]
     lib.abc_state_save.restype = ctypes.c_int
     lib.abc_state_load.argtypes = [vp, vp, vp, ctypes.POINTER(ctypes.c_longlong), ctypes.c_char_p, vp]

@@ -84,6 +84,8 @@ struct PotentialSolver {
   double *r = nullptr, *p = nullptr, *q = nullptr;      // CG vectors
   double *part = nullptr, *scal = nullptr;              // 3 nblk partial sums, scalar slots
   double* host = nullptr;                               // pinned: convergence flag, iteration count
+  int fixed = 0;                                        // > 0: iterations per solve, no host reads
+  double* tally = nullptr;                              // device: Yukawa, Coulomb iterations, unconverged solves
   // sine-transform preconditioner: DST-I matrices and R = 1 eigenvalues per
   // axis, its work vectors, the preconditioned residual and a rocBLAS handle
   double *sx = nullptr, *sy = nullptr, *sz = nullptr, *ex = nullptr, *ey = nullptr, *ez = nullptr;

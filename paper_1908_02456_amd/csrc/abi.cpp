@@ -85,7 +85,8 @@ abc_status check_params(const abc_params& p) {
     if (!(p.pcg_tol > 0 && std::isfinite(p.pcg_tol)) || p.pcg_maxit < 1)
       return fail(ABC_EINVAL, "mean field: pcg_tol > 0 and pcg_maxit >= 1");
   }
-  for (int i = 0; i < 3; ++i)
+  if (p.pcg_fixed < 0) return fail(ABC_EINVAL, "pcg_fixed must be >= 0");
+  for (int i = 0; i < 2; ++i)
     if (p.reserved2[i] != 0) return fail(ABC_EINVAL, "reserved fields must be zero");
   if (p.path < ABC_PATH_AUTO || p.path > ABC_PATH_ONEPASS) return fail(ABC_EINVAL, "unknown path");
   if (p.window < 0) return fail(ABC_EINVAL, "window must be >= 0");
@@ -325,6 +326,7 @@ abc_status abc_setup(const abc_params* pp, abc_ctx** out) {
     ps.e2 = p.e2;
     ps.tol = p.pcg_tol;
     ps.maxit = p.pcg_maxit;
+    ps.fixed = p.pcg_fixed;
     const size_t np = (size_t)L.g.npts;
     ps.nblk = (int)std::min<size_t>(1024, (np + 255) / 256);
     double** vec[9] = {&ps.rho, &ps.wy, &ps.wc, &ps.r, &ps.p, &ps.q, &ps.t1, &ps.t2, &ps.z};
@@ -361,6 +363,10 @@ abc_status abc_setup(const abc_params* pp, abc_ctx** out) {
     ps.part = static_cast<double*>(tmp);
     if (st == ABC_OK) st = dev_alloc(c, &tmp, 8 * sizeof(double));
     ps.scal = static_cast<double*>(tmp);
+    if (st == ABC_OK) st = dev_alloc(c, &tmp, 3 * sizeof(double));
+    ps.tally = static_cast<double*>(tmp);
+    if (st == ABC_OK && hipMemset(ps.tally, 0, 3 * sizeof(double)) != hipSuccess)
+      st = fail(ABC_EDEVICE, "hipMemset failed");
     if (st == ABC_OK && hipHostMalloc(&tmp, 2 * sizeof(double)) != hipSuccess) st = fail(ABC_ENOMEM, "pinned memory");
     if (st == ABC_OK) ps.host = static_cast<double*>(tmp);
     // the potentials start at zero (the first solve starts from zero)
@@ -404,8 +410,8 @@ abc_status abc_setup(const abc_params* pp, abc_ctx** out) {
         }
       }
       if (st == ABC_OK && p.meanfield) st = dev_alloc(c, &ob.veff, np * rsz);
-      if (st == ABC_OK) st = dev_alloc(c, &ob.desc_dev, fused_batch_desc_bytes(p.batch));
-      if (st == ABC_OK && (hipHostMalloc(&ob.desc_host, fused_batch_desc_bytes(p.batch)) != hipSuccess ||
+      if (st == ABC_OK) st = dev_alloc(c, &ob.desc_dev, 2 * fused_batch_desc_bytes(p.batch));
+      if (st == ABC_OK && (hipHostMalloc(&ob.desc_host, 2 * fused_batch_desc_bytes(p.batch)) != hipSuccess ||
                            hipEventCreate(&ob.copied) != hipSuccess))
         st = fail(ABC_ENOMEM, "orbital batch descriptors");
       if (st != ABC_OK) { abc_destroy(c); return st; }
@@ -430,6 +436,21 @@ abc_status abc_step(abc_ctx* c, void* psi, void* aux, const void* V, int n_steps
   if (c->aux_elems && !aux) return fail(ABC_EINVAL, "first and second order need the aux buffer");
   if (n_steps == 0) return ABC_OK;
   hipStream_t st = static_cast<hipStream_t>(stream);
+  {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone) {
+      if (c->p.meanfield == ABC_MF_SKYRME && c->pot.fixed == 0)
+        return fail(ABC_EINVAL, "graph capture of an ABC_MF_SKYRME step needs pcg_fixed >= 1 (the adaptive solves "
+                                "read their convergence flag on the host)");
+      if (c->orb && c->L.fused_stages == 2) {
+        const OrbitalBatch& ob = *c->orb;
+        const int par = n_steps & 1;
+        if (!ob.desc_ok[par] || ob.desc_V[par] != (ob.veff ? ob.veff : V))
+          return fail(ABC_EINVAL, "graph capture of an orbital batch: step once outside the capture with the same V "
+                                  "and the same parity of n_steps first (the launch descriptors are built then)");
+      }
+    }
+  }
   hipError_t e;
   if (c->orb)
     e = launch_step_orbitals(*c->orb, psi, static_cast<double2*>(aux), V, n_steps, st, nullptr);
@@ -676,11 +697,40 @@ abc_status abc_state_load(abc_ctx* c, void* psi, void* aux, long long* step, con
   return ABC_OK;
 }
 
+namespace {
+
+// the device tallies of the solves: Yukawa, Coulomb iterations, unconverged
+abc_status read_tally(const abc_ctx* c, double* t) {
+  t[0] = t[1] = t[2] = 0;
+  if (!c->pot.tally) return ABC_OK;
+  if (hipDeviceSynchronize() != hipSuccess || hipMemcpy(t, c->pot.tally, 3 * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
+    return fail(ABC_EDEVICE, "reading the solves' tallies failed");
+  return ABC_OK;
+}
+
+}  // namespace
+
 abc_status abc_potential_iterations(const abc_ctx* c, long long* out) {
   if (!c || !out) return fail(ABC_EINVAL, "null argument");
   out[0] = c->pot.solves;
   out[1] = c->pot.iters_y;
   out[2] = c->pot.iters_c;
+  if (c->pot.fixed > 0) {
+    double t[3];
+    const abc_status s = read_tally(c, t);
+    if (s != ABC_OK) return s;
+    out[1] = (long long)t[0];
+    out[2] = (long long)t[1];
+  }
+  return ABC_OK;
+}
+
+abc_status abc_potential_unconverged(const abc_ctx* c, long long* out) {
+  if (!c || !out) return fail(ABC_EINVAL, "null argument");
+  double t[3];
+  const abc_status s = read_tally(c, t);
+  if (s != ABC_OK) return s;
+  *out = (long long)t[2];
   return ABC_OK;
 }
 

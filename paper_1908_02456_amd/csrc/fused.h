@@ -56,8 +56,14 @@ struct OrbitalBatch {
   void* soa[3] = {nullptr, nullptr, nullptr};  // psi arrays [B][npts]: state A, state B, u2
   double2* soa_f[3] = {nullptr, nullptr, nullptr};  // aux arrays [B][nface]: A, B, aux of u2
   void* veff = nullptr;            // V + mean field (psi's real type), or null
-  void* desc_host = nullptr;       // pinned staging of the descriptors
-  void* desc_dev = nullptr;
+  // descriptors of the two-stage launches, one set per step-count parity,
+  // built on first use for a given potential buffer and reused after that
+  // (so a warmed-up step issues no copy and can be captured in a graph)
+  void* desc_host = nullptr;       // pinned staging, two sets
+  void* desc_dev = nullptr;        // two sets
+  const void* desc_V[2] = {nullptr, nullptr};
+  bool desc_ok[2] = {false, false};
+  int desc_total = 0;
   hipEvent_t copied = nullptr;
   bool pending = false;
   std::vector<abc_scratch> S;      // per-orbital scratch views into soa / soa_f

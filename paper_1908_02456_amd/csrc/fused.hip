@@ -1867,7 +1867,7 @@ hipError_t launch_batch_step(const abc_launch& L0, int nb, int tz, const void* d
 size_t orbital_batch_bytes(const abc_launch& L1, int B, bool first, bool meanfield) {
   const size_t csz = L1.dtype == ABC_C64 ? 8 : 16, rsz = L1.dtype == ABC_C64 ? 4 : 8;
   return 3 * (size_t)B * L1.g.npts * csz + (first ? 3 * (size_t)B * L1.g.face_off[6] * 16 : 0) +
-         (meanfield ? (size_t)L1.g.npts * rsz : 0) + fused_batch_desc_bytes(B);
+         (meanfield ? (size_t)L1.g.npts * rsz : 0) + 2 * fused_batch_desc_bytes(B);
 }
 
 hipError_t launch_step_orbitals(OrbitalBatch& ob, void* psi, double2* aux, const void* V, int n, hipStream_t st,
@@ -1930,12 +1930,27 @@ hipError_t launch_step_orbitals(OrbitalBatch& ob, void* psi, double2* aux, const
     if (e == hipSuccess && first) e = transpose<double2>(ob.soa_f[0], aux, nf, B, false, st);
     return e;
   }
-  if (ob.pending && hipEventSynchronize(ob.copied) != hipSuccess) return hipErrorUnknown;
-  const int total = fused_batch_build(m, ob.desc_host, n);
-  e = hipMemcpyAsync(ob.desc_dev, ob.desc_host, fused_batch_desc_bytes(B), hipMemcpyHostToDevice, st);
-  if (e == hipSuccess) e = hipEventRecord(ob.copied, st);
-  if (e != hipSuccess) return e;
-  ob.pending = true;
+  const int par = n & 1;
+  const size_t dbytes = fused_batch_desc_bytes(B);
+  const void* vkey = ob.veff ? ob.veff : V;
+  const void* ddev = static_cast<char*>(ob.desc_dev) + par * dbytes;
+  if (!ob.desc_ok[par] || ob.desc_V[par] != vkey) {
+    // a new descriptor set: never inside a graph capture (the copy would
+    // read host memory that a later call may rewrite)
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone)
+      return hipErrorStreamCaptureUnsupported;
+    if (ob.pending && hipEventSynchronize(ob.copied) != hipSuccess) return hipErrorUnknown;
+    void* dhost = static_cast<char*>(ob.desc_host) + par * dbytes;
+    ob.desc_total = fused_batch_build(m, dhost, n);
+    e = hipMemcpyAsync(const_cast<void*>(ddev), dhost, dbytes, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipEventRecord(ob.copied, st);
+    if (e != hipSuccess) return e;
+    ob.pending = true;
+    ob.desc_V[par] = vkey;
+    ob.desc_ok[par] = true;
+  }
+  const int total = ob.desc_total;
   for (int s = 0; s < n; ++s) {
     const int q = s & 1;
     if (ob.veff) {
@@ -1954,7 +1969,7 @@ hipError_t launch_step_orbitals(OrbitalBatch& ob, void* psi, double2* aux, const
                           static_cast<double*>(ob.veff), np, B, L1.t0, L1.t3);
       if (e != hipSuccess) return e;
     }
-    e = launch_batch_step(L1, B, ob.tz, ob.desc_dev, total, q, st, tm);
+    e = launch_batch_step(L1, B, ob.tz, ddev, total, q, st, tm);
     if (e != hipSuccess) return e;
     if (tm) tm->end_step();
   }

@@ -19,7 +19,11 @@
 // the block partials in the same fixed order (alpha and beta are identical
 // everywhere), and the convergence flag is read once per workgroup.  Solves
 // start from the previous step's potential unless that start is worse than
-// zero; the host reads the flag after each iteration.
+// zero.  Either the host reads the flag after each iteration and stops at
+// convergence, or (fixed mode) every solve issues a fixed number of
+// iterations whose kernels return at once after convergence, with no host
+// read, so that a step can be captured in a graph.  Each solve's iteration
+// count and whether it converged are added up on the device.
 #include <hip/hip_runtime.h>
 #include <rocblas/rocblas.h>
 
@@ -223,6 +227,15 @@ __global__ void __launch_bounds__(kT) cg_p_kernel(long long n, double tol2, doub
     p[e] = z[e] + beta * p[e];
 }
 
+// end of a solve: its iterations into tally[field], an unconverged solve
+// into tally[2]
+__global__ void cg_tally_kernel(const double* __restrict__ scal, double* __restrict__ tally, int field) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    tally[field] += scal[kIter];
+    if (scal[kDone] == 0.0) tally[2] += 1.0;
+  }
+}
+
 // divide the sine coefficients by the eigenvalues of the R = 1 operator
 // (-Delta_h + mu^2, zero outside) times the transforms' normalisation
 __global__ void __launch_bounds__(kT) dst_scale_kernel(double* __restrict__ a, const double* __restrict__ ex,
@@ -268,7 +281,7 @@ hipError_t dst_precond(const PotentialSolver& ps, double mu2, const double* r, d
 
 template <int R>
 hipError_t cg_solve(const Op& op, double mu2, const double* rho, double scale, double* x, PotentialSolver& ps,
-                    hipStream_t st, long long* iters) {
+                    hipStream_t st, long long* iters, int field) {
   const int nb = ps.nblk;
   double* part_a = ps.part;
   double* part_b = ps.part + nb;
@@ -283,6 +296,27 @@ hipError_t cg_solve(const Op& op, double mu2, const double* rho, double scale, d
     cg_dot_kernel<<<nb, kT, 0, st>>>(op.n, ps.r, ps.z, part_c, ps.scal);
     cg_first_kernel<<<nb, kT, 0, st>>>(op.n, ps.p, ps.z, part_c, nb, ps.scal);
     e = hipGetLastError();
+  }
+  if (ps.fixed > 0) {
+    // a fixed number of iterations, no host read; after convergence every
+    // CG kernel returns at once (the preconditioner's transforms still run)
+    for (int it = 0; e == hipSuccess && it < ps.fixed; ++it) {
+      const int cur = it & 1;
+      cg_ap_kernel<R><<<nb, kT, 0, st>>>(op, ps.p, ps.q, part_a, ps.scal);
+      cg_x_kernel<<<nb, kT, 0, st>>>(op.n, x, ps.r, ps.p, ps.q, part_a, part_b, nb, ps.scal, cur);
+      e = hipGetLastError();
+      if (e == hipSuccess) e = dst_precond(ps, mu2, ps.r, ps.z, st);
+      if (e == hipSuccess) {
+        cg_dot_kernel<<<nb, kT, 0, st>>>(op.n, ps.r, ps.z, part_c, ps.scal);
+        cg_p_kernel<<<nb, kT, 0, st>>>(op.n, tol2, ps.p, ps.z, part_b, part_c, nb, ps.scal, cur);
+        e = hipGetLastError();
+      }
+    }
+    if (e == hipSuccess) {
+      cg_tally_kernel<<<1, 64, 0, st>>>(ps.scal, ps.tally, field);
+      e = hipGetLastError();
+    }
+    return e;
   }
   if (e == hipSuccess) e = hipMemcpyAsync(ps.host, ps.scal + kDone, 2 * sizeof(double), hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
@@ -302,6 +336,10 @@ hipError_t cg_solve(const Op& op, double mu2, const double* rho, double scale, d
     if (e == hipSuccess) e = hipStreamSynchronize(st);
   }
   if (e == hipSuccess) *iters += (long long)ps.host[1];
+  if (e == hipSuccess) {
+    cg_tally_kernel<<<1, 64, 0, st>>>(ps.scal, ps.tally, field);
+    e = hipGetLastError();
+  }
   return e;
 }
 
@@ -348,11 +386,11 @@ hipError_t solve_both(PotentialSolver& ps, hipStream_t st) {
   hipError_t e = hipSuccess;
   if (ps.v0 != 0.0) {
     const Op op = make_op(ps, 1.0 / (ps.a * ps.a));
-    e = cg_solve<R>(op, 1.0 / (ps.a * ps.a), ps.rho, 4.0 * M_PI * ps.v0 * ps.a, ps.wy, ps, st, &ps.iters_y);
+    e = cg_solve<R>(op, 1.0 / (ps.a * ps.a), ps.rho, 4.0 * M_PI * ps.v0 * ps.a, ps.wy, ps, st, &ps.iters_y, 0);
   }
   if (e == hipSuccess && ps.e2 != 0.0) {
     const Op op = make_op(ps, 0.0);
-    e = cg_solve<R>(op, 0.0, ps.rho, 2.0 * M_PI * ps.e2, ps.wc, ps, st, &ps.iters_c);
+    e = cg_solve<R>(op, 0.0, ps.rho, 2.0 * M_PI * ps.e2, ps.wc, ps, st, &ps.iters_c, 1);
   }
   if (e == hipSuccess) ++ps.solves;
   return e;

@@ -59,6 +59,7 @@ def make_params(shape, h, dt, *, radius=1, order="first", form="faces", s0=1.0, 
         p.t0, p.t3 = float(mf.pop("t0", 0.0)), float(mf.pop("t3", 0.0))
         p.v0, p.a_yukawa, p.e2 = float(mf.pop("v0", 0.0)), float(mf.pop("a", 1.0)), float(mf.pop("e2", 0.0))
         p.pcg_tol, p.pcg_maxit = float(mf.pop("tol", 1e-12)), int(mf.pop("maxit", 1000))
+        p.pcg_fixed = int(mf.pop("fixed_iters", 0))
         if mf:
             raise ValueError("unknown mean-field keys %s" % sorted(mf))
     elif meanfield is not None:
@@ -259,6 +260,13 @@ class Solver:
         buf = (ctypes.c_longlong * 3)()
         _lib.check(self._lib.abc_potential_iterations(self._ctx, buf))
         return tuple(int(v) for v in buf)
+
+    def potential_unconverged(self) -> int:
+        """Mean-field solves so far that ended without reaching their tolerance
+        (counted on the device; synchronises it)."""
+        v = ctypes.c_longlong()
+        _lib.check(self._lib.abc_potential_unconverged(self._ctx, ctypes.byref(v)))
+        return int(v.value)
 
     def save_state(self, path: str, psi, aux=None, step: int = 0, stream=None):
         """Checkpoint (psi, aux) and a step counter to a file (abc_state_save)."""

@@ -49,7 +49,7 @@ int main(void) {
 #define F(x) printf(" %zu", offsetof(abc_params, x));
   F(nx) F(ny) F(nz) F(h) F(dt) F(radius) F(order) F(form) F(s0) F(s1) F(s2) F(window) F(fejer)
   F(dtype) F(batch) F(meanfield) F(t0) F(t3) F(path) F(diag_every) F(reserved) F(s3) F(s4) F(v0) F(a_yukawa) F(e2)
-  F(pcg_tol) F(pcg_maxit) F(reserved2)
+  F(pcg_tol) F(pcg_maxit) F(pcg_fixed) F(reserved2)
   printf("\n");
   return 0;
 }
@@ -64,7 +64,7 @@ int main(void) {
     names = ["nx", "ny", "nz", "h", "dt", "radius", "order", "form", "s0", "s1", "s2", "window", "fejer",
              "dtype", "batch", "meanfield", "t0", "t3", "path", "diag_every", "reserved", "s3", "s4", "v0", "a_yukawa",
              "e2",
-             "pcg_tol", "pcg_maxit", "reserved2"]
+             "pcg_tol", "pcg_maxit", "pcg_fixed", "reserved2"]
     assert vals[0] == ctypes.sizeof(P)
     assert vals[1:] == [getattr(P, n).offset for n in names]
 
@@ -117,6 +117,7 @@ BAD_PARAMS = [
     (dict(meanfield=2, v0=1.0, a_yukawa=0.0), _lib.ABC_EINVAL, b"Yukawa range"),
     (dict(meanfield=2, pcg_tol=0.0), _lib.ABC_EINVAL, b"pcg_tol"),
     (dict(meanfield=2, pcg_maxit=0), _lib.ABC_EINVAL, b"pcg_maxit"),
+    (dict(meanfield=2, pcg_fixed=-1), _lib.ABC_EINVAL, b"pcg_fixed"),
     (dict(meanfield=2, e2=float("nan")), _lib.ABC_EINVAL, b"finite"),
 ]
 
