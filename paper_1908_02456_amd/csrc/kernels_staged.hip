@@ -222,21 +222,27 @@ __global__ void __launch_bounds__(kBlock) stage_kernel(
 
 // ---------------------------------------------------------------------------
 // the same sweep tiled, for one orbital with zero outside the box: a
-// workgroup owns kTX x-columns, TY = kTW J rows (wave w takes rows w, w + kTW,
+// workgroup owns kTX x-columns, TY = TW J rows (wave w takes rows w, w + TW,
 // ...) and tz planes, and marches z.  Each thread keeps its J points' 2R + 1
 // z-neighbours in a register queue that advances one plane per step, so the
 // tile's interior is read from memory once; the centre plane goes to LDS with
 // R-wide x and y halos (double buffered: one barrier per plane) for the x
 // and y neighbours.  The next plane's loads are issued before the barrier.
 // ---------------------------------------------------------------------------
-constexpr int kTX = 64, kTW = kBlock / 64;
-// one row per thread; planes per tile by radius (measured at 128^3, us per
-// step: R = 3 136 with 16 planes against 142 with 8 and 193 with 32; R = 2
-// 117 with 8 against 122 with 16; two rows per thread 143 and 129; R = 1,
-// w = 8: 136 with 8 planes, 157 with 16, 159 untiled).
+constexpr int kTX = 64;
+// one row per thread; planes per tile and rows per tile by radius (measured
+// at 128^3, us per step, first order w = 0: with 4 rows, R = 3 136 with 16
+// planes against 142 with 8 and 193 with 32, R = 2 117 with 8 against 122
+// with 16, two rows per thread 143 and 129; R = 1, w = 8: 136 with 8 planes,
+// 157 with 16, 159 untiled.  Same-box A/B of the row count: R = 3 129.7 with
+// 4 rows x 16 planes, 129.5 with 8 x 16, 122.9 with 8 x 8, 127.9 with 16 x 8;
+// R = 2 106.0 with 4 x 8, 101.5 with 8 x 8: the y halo's share of each
+// plane's loads halves at 8 rows).
 constexpr int kTileJ = 1;
 constexpr int kTiledMinR = 1;
-constexpr int tile_planes(int R) { return R >= 3 ? 16 : 8; }
+constexpr int tile_planes(int R) { return 8; }
+// threads per tile (one row each): kTiledBlock(R) / 64 rows
+constexpr int kTiledBlock(int R) { return R >= 2 ? 512 : 256; }
 
 struct TileGrid {
   int ntx, nty, ntz, tz;
@@ -245,9 +251,10 @@ struct TileGrid {
 
 template <int R, int J>
 struct TileShape {
-  static constexpr int TY = kTW * J, LX = kTX + 2 * R, LY = TY + 2 * R;
+  static constexpr int NTB = kTiledBlock(R), TW = NTB / 64;  // threads, waves (rows per pass)
+  static constexpr int TY = TW * J, LX = kTX + 2 * R, LY = TY + 2 * R;
   static constexpr int NH = 2 * R * (kTX + TY);        // halo points per plane
-  static constexpr int HPT = (NH + kBlock - 1) / kBlock;  // per thread
+  static constexpr int HPT = (NH + NTB - 1) / NTB;     // per thread
 };
 
 template <typename T, int R, int J>
@@ -290,10 +297,10 @@ __device__ __forceinline__ void stage_tiled_body(
 #pragma unroll
   for (int j = 0; j < J; ++j)
 #pragma unroll
-    for (int i = 0; i <= 2 * R; ++i) q[j][i] = load(x, y0 + ty + kTW * j, z0 - R + i);
+    for (int i = 0; i <= 2 * R; ++i) q[j][i] = load(x, y0 + ty + S::TW * j, z0 - R + i);
 #pragma unroll
   for (int hh = 0; hh < S::HPT; ++hh) {
-    const int h = threadIdx.x + hh * kBlock;
+    const int h = threadIdx.x + hh * S::NTB;
     int ly = 0, lx = 0;
     if (h < S::NH) halo_pos(h, ly, lx);
     hv[hh] = load(x0 - R + lx, y0 - R + ly, h < S::NH ? z0 : -1);
@@ -305,10 +312,10 @@ __device__ __forceinline__ void stage_tiled_body(
   for (int z = z0; z < z1; ++z) {
     const int buf = (z - z0) & 1;
 #pragma unroll
-    for (int j = 0; j < J; ++j) pl[buf][R + ty + kTW * j][R + tx] = q[j][R];
+    for (int j = 0; j < J; ++j) pl[buf][R + ty + S::TW * j][R + tx] = q[j][R];
 #pragma unroll
     for (int hh = 0; hh < S::HPT; ++hh) {
-      const int h = threadIdx.x + hh * kBlock;
+      const int h = threadIdx.x + hh * S::NTB;
       if (h < S::NH) {
         int ly, lx;
         halo_pos(h, ly, lx);
@@ -319,7 +326,7 @@ __device__ __forceinline__ void stage_tiled_body(
     C av[J];
 #pragma unroll
     for (int j = 0; j < J; ++j) {
-      const int yy = y0 + ty + kTW * j;
+      const int yy = y0 + ty + S::TW * j;
       const long long pnt = z * sz + yy * sy + x;
       const bool in = x < nx && yy < ny;
       vv[j] = (V && in) ? V[pnt] : T(0);
@@ -330,10 +337,10 @@ __device__ __forceinline__ void stage_tiled_body(
     C nxt[J];
     const bool more = z + 1 < z1;
 #pragma unroll
-    for (int j = 0; j < J; ++j) nxt[j] = load(x, y0 + ty + kTW * j, more ? z + R + 1 : -1);
+    for (int j = 0; j < J; ++j) nxt[j] = load(x, y0 + ty + S::TW * j, more ? z + R + 1 : -1);
 #pragma unroll
     for (int hh = 0; hh < S::HPT; ++hh) {
-      const int h = threadIdx.x + hh * kBlock;
+      const int h = threadIdx.x + hh * S::NTB;
       int ly = 0, lx = 0;
       if (h < S::NH) halo_pos(h, ly, lx);
       hv[hh] = load(x0 - R + lx, y0 - R + ly, (more && h < S::NH) ? z + 1 : -1);
@@ -341,7 +348,7 @@ __device__ __forceinline__ void stage_tiled_body(
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < J; ++j) {
-      const int yy = y0 + ty + kTW * j, ly = R + ty + kTW * j, lx = R + tx;
+      const int yy = y0 + ty + S::TW * j, ly = R + ty + S::TW * j, lx = R + tx;
       const C c0 = q[j][R];
       T hr = diag * c0.x, hi = diag * c0.y;
 #pragma unroll
@@ -383,7 +390,7 @@ __device__ __forceinline__ int xcd_tile(int bid, const TileGrid& tg) {
 }
 
 template <typename T, int R, int J>
-__global__ void __launch_bounds__(kBlock) stage_tiled_kernel(
+__global__ void __launch_bounds__(kTiledBlock(R)) stage_tiled_kernel(
     TileGrid tg, const typename cpx<T>::t* __restrict__ yin, typename cpx<T>::t* __restrict__ yout,
     typename cpx<T>::t* __restrict__ acc, typename cpx<T>::t* __restrict__ state, const T* __restrict__ V,
     const double2* __restrict__ fsrc, const double2* __restrict__ bsrc, const int* __restrict__ point_gamma,
@@ -607,7 +614,7 @@ __global__ void __launch_bounds__(kBlock) stage_face_kernel(
 
 // the same with the tiled stage sweep in the first tg tiles
 template <typename T, int R, int J>
-__global__ void __launch_bounds__(kBlock) stage_face_tiled_kernel(
+__global__ void __launch_bounds__(kTiledBlock(R)) stage_face_tiled_kernel(
     TileGrid tg, const typename cpx<T>::t* __restrict__ yin, typename cpx<T>::t* __restrict__ yout,
     typename cpx<T>::t* __restrict__ acc, typename cpx<T>::t* __restrict__ state, const T* __restrict__ V,
     const double2* __restrict__ fsrc, const int* __restrict__ point_gamma, StencilCoef sc,
@@ -2098,8 +2105,9 @@ hipError_t step_staged_t(const abc_launch& L, const abc_scratch& S, void* psi_v,
       const int smode = k == 2 ? 1 : (k == 4 ? 2 : 0);
       C* state = k == 2 ? const_cast<C*>(pin) : psi;
       if (merged && tiled) {
-        abc_launch_kernel(tm, kStageLabel[k], stage_face_tiled_kernel<T, R, kTileJ>, dim3(ntile + nblocks(nface)),
-                          dim3(kBlock), st, tg, ycur, yout, acc, state, Vuse, fsrc, L.point_gamma, sc, fsrc,
+        abc_launch_kernel(tm, kStageLabel[k], stage_face_tiled_kernel<T, R, kTileJ>,
+                          dim3(ntile + (unsigned)((nface + kTiledBlock(R) - 1) / kTiledBlock(R))),
+                          dim3(kTiledBlock(R)), st, tg, ycur, yout, acc, state, Vuse, fsrc, L.point_gamma, sc, fsrc,
                           merged_gnext, S.facc, aux, L.face_ker, a, g, L.w, coef, smode, mode, ntile);
       } else if (merged) {
         const unsigned nsb = (unsigned)nblocks(nel);
@@ -2107,7 +2115,7 @@ hipError_t step_staged_t(const abc_launch& L, const abc_scratch& S, void* psi_v,
                           st, ycur, yout, acc, state, Vuse, fsrc, L.point_gamma, sc, fsrc, merged_gnext, S.facc, aux,
                           L.face_ker, a, g, L.w, coef, smode, mode, nsb);
       } else if (tiled) {
-        abc_launch_kernel(tm, kStageLabel[k], stage_tiled_kernel<T, R, kTileJ>, dim3(ntile), dim3(kBlock), st, tg,
+        abc_launch_kernel(tm, kStageLabel[k], stage_tiled_kernel<T, R, kTileJ>, dim3(ntile), dim3(kTiledBlock(R)), st, tg,
                           ycur, yout, acc, state, Vuse, fsrc, bsrc, L.point_gamma, g, sc, coef, smode);
       } else {
         abc_launch_kernel(tm, kStageLabel[k], stage_kernel<T, R, PER>, dim3(nblocks(nel)), dim3(kBlock), st, ycur,
