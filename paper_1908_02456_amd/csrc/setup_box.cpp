@@ -385,6 +385,11 @@ abc_status dominant_subspace(rocblas_handle hnd, DevBufs& db, int n, double2* co
                              std::string& err) {
   *U = nullptr;
   *r = n;
+  // the eigen-solver's interface indexes the matrix with 32-bit integers
+  if ((long long)n * n >= (1LL << 31)) {
+    err = "second-order interpolation: n_Gamma too large for the eigen-decomposition";
+    return ABC_ENOTSUP;
+  }
   const size_t nsq = (size_t)n * n;
   double2* Gc = nullptr;
   double *Gr = nullptr, *D = nullptr, *E = nullptr;
