@@ -155,6 +155,7 @@ struct abc_scratch {
   double* red;         // reduction partials
   int red_blocks;
   double2* bwork[2];   // box form over a batch: gathered E y, GEMM result ([gamma][orbital])
+  double2* bpart;      // box form over a batch: partial GEMM results when K is split over workgroups
 };
 
 // Per-launch timing for measurement runs: every kernel launch of a step is
@@ -223,6 +224,10 @@ void abc_launch_kernel_lds(abc_timer* tm, const char* label, void (*k)(P...), di
 // psi_in, aux_in (optional): the first step reads its state from these
 // instead of psi and aux, which receive the result; the inputs are left as
 // they were (a step out of place, without a copy).
+// elements of abc_scratch::bpart for a box-form orbital batch whose GEMM
+// result has `result_elems` elements (rows x orbitals)
+size_t box_gemm_part_elems(size_t result_elems);
+
 hipError_t launch_step_staged(const abc_launch& L, const abc_scratch& S, void* psi, double2* aux,
                               const void* V, int n_steps, hipStream_t st, abc_timer* tm = nullptr,
                               void* const* keep = nullptr, const void* psi_in = nullptr,

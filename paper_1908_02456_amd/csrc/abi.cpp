@@ -302,6 +302,10 @@ abc_status abc_setup(const abc_params* pp, abc_ctx** out) {
       S.bwork[0] = static_cast<double2*>(tmp);
       if ((st = dev_alloc(c, &tmp, naux * 16)) != ABC_OK) { abc_destroy(c); return st; }
       S.bwork[1] = static_cast<double2*>(tmp);
+      // partial products of the GEMM when its K is split over workgroups
+      // (the result has rows x orbitals = naux elements for every order)
+      if ((st = dev_alloc(c, &tmp, box_gemm_part_elems(naux) * 16)) != ABC_OK) { abc_destroy(c); return st; }
+      S.bpart = static_cast<double2*>(tmp);
     }
   }
   if (p.meanfield) {

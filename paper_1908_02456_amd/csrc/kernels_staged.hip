@@ -1417,14 +1417,17 @@ inline unsigned nblocks(long long n) { return (unsigned)((n + kBlock - 1) / kBlo
 // B[l / 16][l % 16] and, in its v-th result register, D[l / 16 + 4 v][l % 16].
 // A workgroup owns 16 operator rows and all orbitals (NT tiles of 16
 // columns); its kGemmSplit waves take every kGemmSplit-th chunk of 16 k
-// (split K, so that the launch has one workgroup per 16 rows and still
-// fills the chip), and their partial products are summed in LDS in wave
-// order (deterministic).  In a chunk each lane loads four consecutive
+// and their partial products are summed in LDS in wave order
+// (deterministic).  When the row tiles alone would leave part of the chip
+// idle in the last round of workgroups, K is further split over ks
+// workgroups per row tile (blockIdx.y), each writing its partial product,
+// and a second kernel adds the ks partials in order.  In a chunk each lane loads four consecutive
 // operator entries of its row (64 B): k quad kq = l / 16 takes entries
 // 4 kq .. 4 kq + 3, and MFMA j uses entry 4 kq + j (the sum over k is the
 // same in any order; A and B use the same one).  The operator is streamed
 // once per stage for all orbitals; X (K x nb) stays in L2.
 constexpr int kGemmSplit = 8;
+constexpr int kGemmMaxKs = 4;  // workgroups per row tile at most
 typedef double gemm_d4 __attribute__((ext_vector_type(4)));
 
 template <int NT>
@@ -1439,10 +1442,12 @@ __global__ void __launch_bounds__(64 * kGemmSplit) box_gemm_kernel(const double2
   const int arow = row0 + ar;
   const bool arow_ok = arow < rows;
   const double2* oprow = op + (long long)(arow_ok ? arow : 0) * ld;
+  const int ks = gridDim.y, ksi = blockIdx.y;  // K split over workgroups
+  t += (long long)ksi * rows * nb;
   gemm_d4 cre[NT], cim[NT];
 #pragma unroll
   for (int u = 0; u < NT; ++u) cre[u] = cim[u] = gemm_d4{0, 0, 0, 0};
-  for (int k0 = 16 * w; k0 < ld; k0 += 16 * kGemmSplit) {
+  for (int k0 = 16 * (ksi * kGemmSplit + w); k0 < ld; k0 += 16 * kGemmSplit * ks) {
     double2 a[4];
     double2 b[NT][4];
 #pragma unroll
@@ -1487,16 +1492,66 @@ __global__ void __launch_bounds__(64 * kGemmSplit) box_gemm_kernel(const double2
   }
 }
 
-// T = Op [X1; X2] for nb <= 64 orbitals (one to four column tiles)
+// t[e] = sum over the ks partial products, in order
+__global__ void __launch_bounds__(kBlock) box_gemm_reduce_kernel(const double2* __restrict__ part, int ks,
+                                                                 long long cnt, double2* __restrict__ t) {
+  const long long e = (long long)blockIdx.x * kBlock + threadIdx.x;
+  if (e >= cnt) return;
+  double2 s = part[e];
+  for (int q = 1; q < ks; ++q) {
+    const double2 p = part[(long long)q * cnt + e];
+    s.x += p.x;
+    s.y += p.y;
+  }
+  t[e] = s;
+}
+
+// workgroups per row tile: the split (up to kGemmMaxKs, keeping at least two
+// chunks of 16 k per wave) whose last round of workgroups leaves the fewest
+// compute units idle; 1 unless that gains more than 2 %
+int gemm_k_split(int rows, int ld) {
+  static int cus = 0;
+  if (cus == 0) {
+    int dev = 0, n = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) !=
+                                                 hipSuccess || n < 1)
+      n = 256;
+    cus = n;
+  }
+  const long long tiles = (rows + 15) / 16, chunks = (ld + 15) / 16;
+  int best = 1;
+  double best_eff = (double)tiles / (double)(((tiles + cus - 1) / cus) * cus);
+  for (int ks = 2; ks <= kGemmMaxKs; ++ks) {
+    if (chunks < 2LL * kGemmSplit * ks) break;
+    const long long wg = tiles * ks;
+    const double eff = (double)wg / (double)(((wg + cus - 1) / cus) * cus);
+    if (eff > best_eff + 0.02) {
+      best_eff = eff;
+      best = ks;
+    }
+  }
+  return best;
+}
+
+// T = Op [X1; X2] for nb <= 64 orbitals (one to four column tiles); part
+// (box_gemm_part_elems(rows nb) elements, or null) holds the partial
+// products when K is split over workgroups
 hipError_t box_gemm(abc_timer* tm, const double2* op, int rows, int ld, int na, const double2* x1,
-                    const double2* x2, int nb, double2* t, hipStream_t st) {
-  const dim3 g((unsigned)((rows + 15) / 16)), b(64 * kGemmSplit);
+                    const double2* x2, int nb, double2* t, double2* part, hipStream_t st) {
+  const int ks = part ? gemm_k_split(rows, ld) : 1;
+  const dim3 g((unsigned)((rows + 15) / 16), (unsigned)ks), b(64 * kGemmSplit);
   const int nt = (nb + 15) / 16;
-  if (nt == 1) abc_launch_kernel(tm, "box_gemm", box_gemm_kernel<1>, g, b, st, op, rows, ld, na, x1, x2, nb, t);
-  else if (nt == 2) abc_launch_kernel(tm, "box_gemm", box_gemm_kernel<2>, g, b, st, op, rows, ld, na, x1, x2, nb, t);
-  else if (nt == 3) abc_launch_kernel(tm, "box_gemm", box_gemm_kernel<3>, g, b, st, op, rows, ld, na, x1, x2, nb, t);
-  else if (nt == 4) abc_launch_kernel(tm, "box_gemm", box_gemm_kernel<4>, g, b, st, op, rows, ld, na, x1, x2, nb, t);
+  double2* out = ks > 1 ? part : t;
+  if (nt == 1) abc_launch_kernel(tm, "box_gemm", box_gemm_kernel<1>, g, b, st, op, rows, ld, na, x1, x2, nb, out);
+  else if (nt == 2) abc_launch_kernel(tm, "box_gemm", box_gemm_kernel<2>, g, b, st, op, rows, ld, na, x1, x2, nb, out);
+  else if (nt == 3) abc_launch_kernel(tm, "box_gemm", box_gemm_kernel<3>, g, b, st, op, rows, ld, na, x1, x2, nb, out);
+  else if (nt == 4) abc_launch_kernel(tm, "box_gemm", box_gemm_kernel<4>, g, b, st, op, rows, ld, na, x1, x2, nb, out);
   else return hipErrorInvalidValue;
+  if (ks > 1) {
+    const long long cnt = (long long)rows * nb;
+    abc_launch_kernel(tm, "box_gemm_sum", box_gemm_reduce_kernel, dim3((unsigned)((cnt + kBlock - 1) / kBlock)),
+                      dim3(kBlock), st, (const double2*)part, ks, cnt, t);
+  }
   return hipSuccess;
 }
 
@@ -2049,7 +2104,7 @@ hipError_t step_staged_t(const abc_launch& L, const abc_scratch& S, void* psi_v,
                             (const C*)ycur, L.gamma_lin, n, nb, S.bwork[0]);
           double2* tout = rec ? S.bwork[1] : S.src;
           const hipError_t ge = box_gemm(tm, L.box_mat, rows, ld, na, rec ? gcur : nullptr,
-                                         (const double2*)S.bwork[0], nb, tout, st);
+                                         (const double2*)S.bwork[0], nb, tout, S.bpart, st);
           if (ge != hipSuccess) return ge;
           if (rec)
             abc_launch_kernel(tm, "box_epilogue", box_epilogue_kernel, dim3(nblocks(cnt)), dim3(kBlock), st,
@@ -2178,6 +2233,8 @@ hipError_t dispatch_diag(const abc_launch& L, double* red, const void* psi, cons
 }
 
 }  // namespace
+
+size_t box_gemm_part_elems(size_t result_elems) { return (size_t)kGemmMaxKs * result_elems; }
 
 hipError_t launch_step_staged(const abc_launch& L, const abc_scratch& S, void* psi, double2* aux, const void* V,
                               int n_steps, hipStream_t st, abc_timer* tm, void* const* keep, const void* psi_in,
