@@ -1411,8 +1411,8 @@ inline unsigned nblocks(long long n) { return (unsigned)((n + kBlock - 1) / kBlo
 // Box form over an orbital batch: T = Op X, complex FP64, on the matrix cores.
 // Op is the row-major operator (rows x ld); X = [X1; X2] stacks the
 // auxiliary input (na rows, [row][orbital]) on the gathered E y (ld - na
-// rows); T is [row][orbital].  Complex products as four real products
-// (re re - im im, re im + im re) with v_mfma_f64_16x16x4f64, which computes
+// rows); T is [row][orbital].  Complex products as three real products
+// (below) with v_mfma_f64_16x16x4f64, which computes
 // D (16 x 16) += A (16 x 4) B (4 x 16) over the wave: lane l holds A[l % 16][l / 16],
 // B[l / 16][l % 16] and, in its v-th result register, D[l / 16 + 4 v][l % 16].
 // A workgroup owns 16 operator rows and all orbitals (NT tiles of 16
@@ -1444,9 +1444,12 @@ __global__ void __launch_bounds__(64 * kGemmSplit) box_gemm_kernel(const double2
   const double2* oprow = op + (long long)(arow_ok ? arow : 0) * ld;
   const int ks = gridDim.y, ksi = blockIdx.y;  // K split over workgroups
   t += (long long)ksi * rows * nb;
-  gemm_d4 cre[NT], cim[NT];
+  // three real products per complex product (Karatsuba): with Op = a + ib
+  // and X = c + id, p1 = (a + b) c, p2 = a (d - c), p3 = b (c + d), and
+  // Re T = p1 - p3, Im T = p1 + p2
+  gemm_d4 p1[NT], p2[NT], p3[NT];
 #pragma unroll
-  for (int u = 0; u < NT; ++u) cre[u] = cim[u] = gemm_d4{0, 0, 0, 0};
+  for (int u = 0; u < NT; ++u) p1[u] = p2[u] = p3[u] = gemm_d4{0, 0, 0, 0};
   for (int k0 = 16 * (ksi * kGemmSplit + w); k0 < ld; k0 += 16 * kGemmSplit * ks) {
     double2 a[4];
     double2 b[NT][4];
@@ -1463,19 +1466,19 @@ __global__ void __launch_bounds__(64 * kGemmSplit) box_gemm_kernel(const double2
     }
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
+      const double apb = a[j].x + a[j].y;
 #pragma unroll
       for (int u = 0; u < NT; ++u) {
-        cre[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[j].x, b[u][j].x, cre[u], 0, 0, 0);
-        cre[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a[j].y, b[u][j].y, cre[u], 0, 0, 0);
-        cim[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[j].x, b[u][j].y, cim[u], 0, 0, 0);
-        cim[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[j].y, b[u][j].x, cim[u], 0, 0, 0);
+        p1[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(apb, b[u][j].x, p1[u], 0, 0, 0);
+        p2[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[j].x, b[u][j].y - b[u][j].x, p2[u], 0, 0, 0);
+        p3[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[j].y, b[u][j].x + b[u][j].y, p3[u], 0, 0, 0);
       }
     }
   }
 #pragma unroll
   for (int u = 0; u < NT; ++u)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) red[w][u][v][lane] = make_double2(cre[u][v], cim[u][v]);
+    for (int v = 0; v < 4; ++v) red[w][u][v][lane] = make_double2(p1[u][v] - p3[u][v], p1[u][v] + p2[u][v]);
   __syncthreads();
   // the waves' partial sums in a fixed order; element e = (u, v, lane)
   for (int e = threadIdx.x; e < NT * 4 * 64; e += 64 * kGemmSplit) {
