@@ -960,6 +960,11 @@ struct abc_batch {
   };
   std::vector<Group> groups;
   std::vector<int> fallback;  // instances stepped through abc_step one by one
+  // groups after the first run on a second stream (default priority),
+  // forked from and joined back to the caller's stream, so that the groups'
+  // launches overlap and fill each other's last rounds of workgroups
+  hipStream_t side = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   std::vector<const void*> key;
@@ -971,6 +976,9 @@ void abc_destroy_batch(abc_batch* b) {
   if (!b) return;
   if (b->exec) hipGraphExecDestroy(b->exec);
   if (b->graph) hipGraphDestroy(b->graph);
+  if (b->fork) hipEventDestroy(b->fork);
+  if (b->join) hipEventDestroy(b->join);
+  if (b->side) hipStreamDestroy(b->side);
   for (auto& g : b->groups) {
     if (g.copied) hipEventDestroy(g.copied);
     if (g.host) hipHostFree(g.host);
@@ -1017,6 +1025,13 @@ abc_status abc_setup_batch(const abc_params* ps, int n, abc_batch** out) {
       g->dtype = c->p.dtype;
     }
     g->idx.push_back(i);
+  }
+  if (b->groups.size() > 1 &&
+      (hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking) != hipSuccess ||
+       hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess ||
+       hipEventCreateWithFlags(&b->join, hipEventDisableTiming) != hipSuccess)) {
+    abc_destroy_batch(b);
+    return fail(ABC_EDEVICE, "batch stream or events");
   }
   for (auto& g : b->groups) {
     for (int i : g.idx) g.tz = std::min(g.tz, fused_max_tz(g.order, b->inst[i]->p.nz));
@@ -1069,12 +1084,17 @@ abc_status check_batch_args(abc_batch* b, void* const* psi, void* const* aux) {
 // `use_graph ? gdev : dev`
 abc_status enqueue_batch(abc_batch* b, void* const* psi, void* const* aux, const void* const* V, int n,
                          hipStream_t st, bool use_graph, const std::vector<int>& totals) {
+  const bool two = b->side && b->groups.size() > 1;
+  if (two && (hipEventRecord(b->fork, st) != hipSuccess || hipStreamWaitEvent(b->side, b->fork, 0) != hipSuccess))
+    return fail(ABC_EDEVICE, "batch stream fork failed");
   for (size_t k = 0; k < b->groups.size(); ++k) {
     auto& g = b->groups[k];
-    hipError_t e = launch_batch_fused(members(b, g, psi, aux, V), g.tz, use_graph ? g.gdev : g.dev, totals[k], n, st,
-                                      nullptr);
+    hipError_t e = launch_batch_fused(members(b, g, psi, aux, V), g.tz, use_graph ? g.gdev : g.dev, totals[k], n,
+                                      two && k > 0 ? b->side : st, nullptr);
     if (e != hipSuccess) return fail(ABC_EDEVICE, std::string("batch launch: ") + hipGetErrorString(e));
   }
+  if (two && (hipEventRecord(b->join, b->side) != hipSuccess || hipStreamWaitEvent(st, b->join, 0) != hipSuccess))
+    return fail(ABC_EDEVICE, "batch stream join failed");
   for (int i : b->fallback) {
     abc_status s = abc_step(b->inst[i], psi[i], aux ? aux[i] : nullptr, V ? V[i] : nullptr, n, st);
     if (s != ABC_OK) return s;
