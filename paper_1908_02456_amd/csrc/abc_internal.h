@@ -66,8 +66,18 @@ abc_status build_face_ops(const abc_params& p, FaceOps& ops, std::string& err);
 // row-major operator (box_rows x box_cols), q_dev the first order's
 // Lyapunov weight (n x n) or NULL, subspace_dim the dimension of the
 // subspace the second order interpolates in (n_Gamma otherwise).
+// Second order in a subspace of dimension r < n_Gamma: the orthonormal basis
+// U (real, n_Gamma x r, column-major) and the reduced operator
+// [[0, I, A1~], [B0~, B1~, C~]] (2r x 3r, row-major), device buffers owned by
+// the caller (null, r = 0, when the second order uses no subspace).
+struct BoxReduced {
+  double* U = nullptr;
+  double2* red = nullptr;
+  int r = 0;
+};
 abc_status build_box_ops(const abc_params& p, double2** mat_dev, double2** q_dev, int* n_gamma,
-                         std::vector<int>& gamma_lin, double* spectral_bound, int* subspace_dim, std::string& err);
+                         std::vector<int>& gamma_lin, double* spectral_bound, int* subspace_dim, BoxReduced* reduced,
+                         std::string& err);
 
 }  // namespace abc
 
@@ -140,6 +150,12 @@ struct abc_launch {
   // box form
   const double2* box_mat;
   const double2* box_q;       // Lyapunov weight (H_gs H_gs^T)^{-1}, n x n
+  // second order in a subspace (box_r > 0): U, the reduced operator and a
+  // rocBLAS handle; one orbital steps through them instead of box_mat
+  const double* box_U;
+  const double2* box_red;
+  int box_r;
+  void* box_blas;
   const int* gamma_lin;       // gamma index -> linear point index
   const int* point_gamma;     // linear point index -> gamma index or -1
   int n_gamma;
@@ -156,6 +172,8 @@ struct abc_scratch {
   int red_blocks;
   double2* bwork[2];   // box form over a batch: gathered E y, GEMM result ([gamma][orbital])
   double2* bpart;      // box form over a batch: partial GEMM results when K is split over workgroups
+  double* bpack;       // second order in a subspace: 6 x n_Gamma packed vectors
+  double* bred;        // second order in a subspace: 20 r doubles of reduced vectors
 };
 
 // Per-launch timing for measurement runs: every kernel launch of a step is

@@ -36,6 +36,7 @@ struct abc_ctx {
   size_t aux_elems = 0;
   int n_gamma = 0;
   int box_rank = 0;         // box form: dimension the second order interpolates in
+  void* box_blas = nullptr;  // box form, second order in a subspace: rocBLAS handle of the reduced stages
   double box_bound = 0;    // box form: spectral bound of the boundary block
   int use_fused = 0;
   double2* box_mat = nullptr;
@@ -148,6 +149,7 @@ void abc_destroy(abc_ctx* c) {
   if (!c) return;
   if (c->pot.host) (void)hipHostFree(c->pot.host);
   if (c->pot.blas) rocblas_destroy_handle(static_cast<rocblas_handle>(c->pot.blas));
+  if (c->box_blas) rocblas_destroy_handle(static_cast<rocblas_handle>(c->box_blas));
   if (c->orb) {
     if (c->orb->copied) hipEventDestroy(c->orb->copied);
     if (c->orb->desc_host) hipHostFree(c->orb->desc_host);
@@ -226,9 +228,28 @@ abc_status abc_setup(const abc_params* pp, abc_ctx** out) {
   if (bc && p.form == ABC_FORM_BOX) {
     std::vector<int> glin;
     double bound = 0;
-    st = abc::build_box_ops(p, &c->box_mat, &c->box_q, &c->n_gamma, glin, &bound, &c->box_rank, err);
+    abc::BoxReduced red;
+    st = abc::build_box_ops(p, &c->box_mat, &c->box_q, &c->n_gamma, glin, &bound, &c->box_rank,
+                            p.batch == 1 ? &red : nullptr, err);
     c->box_bound = bound;
     if (st != ABC_OK) { abc_destroy(c); return fail(st, err); }
+    if (red.red) {
+      // one orbital steps the second order in the subspace (the lifted
+      // operator stays for the export)
+      c->allocations.push_back(red.U);
+      c->allocations.push_back(red.red);
+      c->bytes += (size_t)c->n_gamma * red.r * 8 + (size_t)6 * red.r * red.r * 16;
+      rocblas_handle hb = nullptr;
+      if (rocblas_create_handle(&hb) != rocblas_status_success) {
+        abc_destroy(c);
+        return fail(ABC_EDEVICE, "rocblas_create_handle failed");
+      }
+      c->box_blas = hb;
+      L.box_U = red.U;
+      L.box_red = red.red;
+      L.box_r = red.r;
+      L.box_blas = hb;
+    }
     if (c->box_mat) { c->allocations.push_back(c->box_mat); c->bytes += abc::box_mat_elems(p.order, c->n_gamma) * 16; }
     if (c->box_q) { c->allocations.push_back(c->box_q); c->bytes += (size_t)c->n_gamma * c->n_gamma * 16; }
     L.box_mat = c->box_mat;
@@ -290,6 +311,14 @@ abc_status abc_setup(const abc_params* pp, abc_ctx** out) {
       // one orbital: E y gathered once per stage for the row-blocked product
       if ((st = dev_alloc(c, &tmp, naux * 16)) != ABC_OK) { abc_destroy(c); return st; }
       S.bwork[0] = static_cast<double2*>(tmp);
+      if (L.box_r > 0) {
+        // the second order's reduced stages: 6 x n_Gamma packed vectors and
+        // 20 r doubles of reduced ones
+        if ((st = dev_alloc(c, &tmp, (size_t)6 * c->n_gamma * sizeof(double))) != ABC_OK) { abc_destroy(c); return st; }
+        S.bpack = static_cast<double*>(tmp);
+        if ((st = dev_alloc(c, &tmp, (size_t)20 * L.box_r * sizeof(double))) != ABC_OK) { abc_destroy(c); return st; }
+        S.bred = static_cast<double*>(tmp);
+      }
     }
     if (p.form == ABC_FORM_BOX && p.batch > 1) {
       // the operator over the orbital batch is one complex GEMM per stage

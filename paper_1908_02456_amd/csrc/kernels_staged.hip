@@ -1408,6 +1408,206 @@ __global__ void __launch_bounds__(kBlock) box_epilogue_kernel(const double2* __r
 
 inline unsigned nblocks(long long n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
+// ---------------------------------------------------------------------------
+// Second order in the DtN maps' dominant subspace U (n x r, real), one
+// orbital: a stage projects f, g and E y onto the subspace (one pass over U
+// for the three vectors), applies the reduced operator [[0, I, A1~], [B0~,
+// B1~, C~]] (two GEMVs: the constant [0, I] block is added, not read), lifts
+// the two results back (one pass over U) and applies the stage update in the
+// full coordinates, where the auxiliary variables stay.  The complex vectors ride in the
+// products with U as rows of real matrices: column j of the packed 6 x n (or
+// 4 x r) matrix holds the real and imaginary parts of the vectors' j-th
+// entries.  The projection and the lift read U once each, in kernels of
+// their own (the library GEMM took 0.3-0.8 ms for these 6- and 4-row shapes).
+// ---------------------------------------------------------------------------
+
+// W (6 x n, ld 6) from f = aux[0 .. n), g = aux[n .. 2n) and y
+__global__ void __launch_bounds__(kBlock) pack3_kernel(double* __restrict__ W, const double2* __restrict__ aux,
+                                                       const double2* __restrict__ y, int n) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  const double2 f = aux[j], gg = aux[n + j], yy = y[j];
+  double* w = W + 6LL * j;
+  w[0] = f.x; w[1] = f.y; w[2] = gg.x; w[3] = gg.y; w[4] = yy.x; w[5] = yy.y;
+}
+
+// v = [f~; g~; y~] (3r complex) from Z (6 x r, ld 6)
+__global__ void __launch_bounds__(kBlock) unpack3_kernel(double2* __restrict__ v, const double* __restrict__ Z,
+                                                         int r) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= r) return;
+  const double* z = Z + 6LL * j;
+  v[j] = make_double2(z[0], z[1]);
+  v[r + j] = make_double2(z[2], z[3]);
+  v[2 * r + j] = make_double2(z[4], z[5]);
+}
+
+// Tp (4 x r, ld 4) from t = [t_f~; t_g~] (2r complex)
+__global__ void __launch_bounds__(kBlock) pack2_kernel(double* __restrict__ Tp, const double2* __restrict__ t, int r) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= r) return;
+  const double2 a = t[j], b = t[r + j];
+  double* q = Tp + 4LL * j;
+  q[0] = a.x; q[1] = a.y; q[2] = b.x; q[3] = b.y;
+}
+
+// Z (6 x r, ld 6) = W (6 x n, ld 6) U (n x r, column-major): a workgroup
+// takes kProjCols columns of U, its threads stride over the n rows (each U
+// column read once, coalesced); the partial sums are reduced within each
+// wave by shuffles and across the waves in LDS, in a fixed order
+constexpr int kProjCols = 8;
+__global__ void __launch_bounds__(kBlock) proj_kernel(const double* __restrict__ U, int n, int r,
+                                                      const double* __restrict__ W, double* __restrict__ Z) {
+  constexpr int NV = kProjCols * 6, NW = kBlock / 64;
+  __shared__ double red[NW][NV];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int j0 = blockIdx.x * kProjCols;
+  double acc[NV];
+#pragma unroll
+  for (int q = 0; q < NV; ++q) acc[q] = 0.0;
+  for (int i = threadIdx.x; i < n; i += kBlock) {
+    double w[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) w[c] = W[6LL * i + c];
+#pragma unroll
+    for (int q = 0; q < kProjCols; ++q) {
+      const double u = j0 + q < r ? U[(long long)(j0 + q) * n + i] : 0.0;
+#pragma unroll
+      for (int c = 0; c < 6; ++c) acc[q * 6 + c] += w[c] * u;
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < NV; ++q) {
+    double v = acc[q];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    if (lane == 0) red[wv][q] = v;
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < NV) {
+    const int q = threadIdx.x;
+    double sum = red[0][q];
+#pragma unroll
+    for (int k = 1; k < NW; ++k) sum += red[k][q];
+    const int j = j0 + q / 6;
+    if (j < r) Z[6LL * j + q % 6] = sum;
+  }
+}
+
+// Tl (4 x n, ld 4) = Tp (4 x r, ld 4) U^T: a workgroup takes 64 rows i of U
+// (one per lane, coalesced) and its kLiftWaves waves a slice of the r
+// columns each (enough waves in flight to stream U); the partial sums are
+// added in LDS in wave order
+constexpr int kLiftWaves = 16;
+__global__ void __launch_bounds__(64 * kLiftWaves) lift_kernel(const double* __restrict__ U, int n, int r,
+                                                               const double* __restrict__ Tp,
+                                                               double* __restrict__ Tl) {
+  __shared__ double red[kLiftWaves][4][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int i = blockIdx.x * 64 + lane;
+  const int jlo = (int)((long long)r * w / kLiftWaves), jhi = (int)((long long)r * (w + 1) / kLiftWaves);
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  if (i < n) {
+    int j = jlo;
+    for (; j + 4 <= jhi; j += 4) {
+      double u[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) u[q] = U[(long long)(j + q) * n + i];
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[c] += Tp[4LL * (j + q) + c] * u[q];
+    }
+    for (; j < jhi; ++j) {
+      const double u = U[(long long)j * n + i];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) acc[c] += Tp[4LL * j + c] * u;
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 4; ++c) red[w][c][lane] = acc[c];
+  __syncthreads();
+  if (w == 0 && i < n) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      double sum = red[0][c][lane];
+      for (int q = 1; q < kLiftWaves; ++q) sum += red[q][c][lane];
+      Tl[4LL * i + c] = sum;
+    }
+  }
+}
+
+// the stage update of box_epilogue_kernel on T = [T_f; T_g] read from the
+// lifted 4 x n matrix (element e: part e / n, entry e % n)
+__global__ void __launch_bounds__(kBlock) lifted_epilogue_kernel(const double* __restrict__ Tl,
+                                                                 const double2* __restrict__ gin,
+                                                                 double2* __restrict__ gout,
+                                                                 double2* __restrict__ facc,
+                                                                 double2* __restrict__ aux_out, int n, double coef,
+                                                                 int mode) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= 2LL * n) return;
+  const int part = (int)(e / n), j = (int)(e % n);
+  const double* q = Tl + 4LL * j + 2 * part;
+  const double2 gn = make_double2(coef * q[0], coef * q[1]);
+  if (mode == 0) {
+    const double2 g0 = gin[e];
+    facc[e] = make_double2(g0.x + gn.x, g0.y + gn.y);
+    gout[e] = gn;
+  } else if (mode == 1) {
+    double2 s2 = facc[e];
+    s2.x += gn.x;
+    s2.y += gn.y;
+    facc[e] = s2;
+    gout[e] = gn;
+  } else {
+    const double2 s2 = facc[e];
+    aux_out[e] = make_double2(s2.x + gn.x, s2.y + gn.y);
+  }
+}
+
+template <typename T>
+hipError_t second_reduced_stage(const abc_launch& L, const abc_scratch& S, const typename cpx<T>::t* ycur,
+                                const double2* gcur, double2* gnext, double2* aux, double coef, int mode,
+                                hipStream_t st, abc_timer* tm, const char* label) {
+  using zc = rocblas_double_complex;
+  const int n = L.n_gamma, r = L.box_r;
+  rocblas_handle hb = static_cast<rocblas_handle>(L.box_blas);
+  if (rocblas_set_stream(hb, st) != rocblas_status_success) return hipErrorUnknown;
+  double* W = S.bpack;  // 6 x n in, then the lifted 4 x n
+  double* Z = S.bred;   // 6 x r
+  double2* v = reinterpret_cast<double2*>(S.bred + 6LL * r);  // [f~; g~; y~]
+  double2* t = v + 3LL * r;                                      // [t_f~; t_g~]
+  double* Tp = reinterpret_cast<double*>(t + 2LL * r);           // 4 x r
+  abc_launch_kernel(tm, label, box_gather_kernel<T>, dim3(nblocks(n)), dim3(kBlock), st, ycur, L.gamma_lin, n, 1,
+                    S.bwork[0]);
+  abc_launch_kernel(tm, "reduced_pack", pack3_kernel, dim3(nblocks(n)), dim3(kBlock), st, W, gcur,
+                    (const double2*)S.bwork[0], n);
+  abc_launch_kernel(tm, "reduced_project", proj_kernel, dim3((unsigned)((r + kProjCols - 1) / kProjCols)),
+                    dim3(kBlock), st, L.box_U, n, r, (const double*)W, Z);
+  abc_launch_kernel(tm, "reduced_unpack", unpack3_kernel, dim3(nblocks(r)), dim3(kBlock), st, v, (const double*)Z, r);
+  // t_g~ = [B0~ B1~ C~] v (rows r .. 2r of the row-major operator);
+  // t_f~ = g~ + A1~ y~ (rows 0 .. r, columns 2r .. 3r)
+  const zc cone(1.0, 0.0), czero(0.0, 0.0);
+  const long long ld = 3LL * r;
+  if (rocblas_zgemv_64(hb, rocblas_operation_transpose, ld, r, &cone,
+                       reinterpret_cast<const zc*>(L.box_red + (long long)r * ld), ld, reinterpret_cast<const zc*>(v),
+                       1, &czero, reinterpret_cast<zc*>(t + r), 1) != rocblas_status_success)
+    return hipErrorUnknown;
+  hipError_t e = hipMemcpyAsync(t, v + r, (size_t)r * sizeof(double2), hipMemcpyDeviceToDevice, st);
+  if (e != hipSuccess) return e;
+  if (rocblas_zgemv_64(hb, rocblas_operation_transpose, r, r, &cone, reinterpret_cast<const zc*>(L.box_red + 2LL * r),
+                       ld, reinterpret_cast<const zc*>(v + 2LL * r), 1, &cone, reinterpret_cast<zc*>(t), 1) !=
+      rocblas_status_success)
+    return hipErrorUnknown;
+  abc_launch_kernel(tm, "reduced_pack", pack2_kernel, dim3(nblocks(r)), dim3(kBlock), st, Tp, (const double2*)t, r);
+  abc_launch_kernel(tm, "reduced_lift", lift_kernel, dim3((unsigned)((n + 63) / 64)), dim3(64 * kLiftWaves), st,
+                    L.box_U, n, r, (const double*)Tp, W);
+  abc_launch_kernel(tm, "box_epilogue", lifted_epilogue_kernel, dim3(nblocks(2LL * n)), dim3(kBlock), st,
+                    (const double*)W, gcur, gnext, S.facc, aux, n, coef, mode);
+  return hipGetLastError();
+}
+
 // Box form over an orbital batch: T = Op X, complex FP64, on the matrix cores.
 // Op is the row-major operator (rows x ld); X = [X1; X2] stacks the
 // auxiliary input (na rows, [row][orbital]) on the gathered E y (ld - na
@@ -2112,6 +2312,11 @@ hipError_t step_staged_t(const abc_launch& L, const abc_scratch& S, void* psi_v,
           if (rec)
             abc_launch_kernel(tm, "box_epilogue", box_epilogue_kernel, dim3(nblocks(cnt)), dim3(kBlock), st,
                               (const double2*)tout, gcur, gnext, S.facc, aux, cnt, coef, mode);
+        } else if (box && g.batch == 1 && L.box_r > 0 && L.order == ABC_SECOND && S.bpack) {
+          // second order in the DtN maps' dominant subspace
+          const hipError_t e = second_reduced_stage<T>(L, S, (const C*)ycur, gcur, gnext, aux, coef, mode, st, tm,
+                                                       kBoundLabel[k]);
+          if (e != hipSuccess) return e;
         } else if (box && g.batch == 1 && S.bwork[0] && abc::box_rows(L.order, L.n_gamma) >= kBoxRowsMin) {
           // one orbital, large operator: gather E y, then kBoxRows rows per
           // workgroup (below kBoxRowsMin rows the extra launch and the fewer

@@ -381,9 +381,10 @@ constexpr double kSecondTau = 1e-2;
 // Re sum_j K_j K_j^H whose eigenvalues exceed kSecondTau^2 times the largest
 // (that span holds the real and imaginary parts of every column).  *U
 // receives it as complex n x r column-major, or nullptr when r == n.
-abc_status dominant_subspace(rocblas_handle hnd, DevBufs& db, int n, double2* const* K, double2** U, int* r,
-                             std::string& err) {
+abc_status dominant_subspace(rocblas_handle hnd, DevBufs& db, int n, double2* const* K, double2** U, double** Ur,
+                             int* r, std::string& err) {
   *U = nullptr;
+  *Ur = nullptr;
   *r = n;
   // the eigen-solver's interface indexes the matrix with 32-bit integers
   if ((long long)n * n >= (1LL << 31)) {
@@ -437,10 +438,17 @@ abc_status dominant_subspace(rocblas_handle hnd, DevBufs& db, int n, double2* co
   *r = keep;
   if (keep == n) return ABC_OK;
   double2* Uc = nullptr;
-  if (!db.alloc(&Uc, (size_t)n * keep)) { err = "hipMalloc failed"; return ABC_ENOMEM; }
+  double* Ure = nullptr;
+  if (!db.alloc(&Uc, (size_t)n * keep) || !db.alloc(&Ure, (size_t)n * keep)) { err = "hipMalloc failed"; return ABC_ENOMEM; }
   real_to_complex_kernel<<<nblk((long long)n * keep), kThreads>>>(Uc, Gr + (size_t)(n - keep) * n, (long long)n * keep);
   if (hipGetLastError() != hipSuccess) { err = "setup kernel launch failed"; return ABC_EDEVICE; }
+  if (hipMemcpy(Ure, Gr + (size_t)(n - keep) * n, (size_t)n * keep * sizeof(double), hipMemcpyDeviceToDevice) !=
+      hipSuccess) {
+    err = "hipMemcpy failed";
+    return ABC_EDEVICE;
+  }
   *U = Uc;
+  *Ur = Ure;
   return ABC_OK;
 }
 
@@ -596,10 +604,46 @@ abc_status power_bound(rocblas_handle hnd, DevBufs& db, const double2* mat, int 
   return ABC_OK;
 }
 
+// [[0, I, A1], [B0, B1, C]] (row-major, ld 3n) from the transposed
+// coefficient blocks Y_k = XT + k n (column-major n x n, ld m; k = B1, B0,
+// A1, A0), with C = B1 A1 + A0
+abc_status assemble_second(rocblas_handle hnd, DevBufs& db, double2* out, const double2* XT, long long m, int n,
+                           std::string& err) {
+  const double2 one2 = make_double2(1.0, 0.0);
+  const zc one(1.0, 0.0);
+  double2* W = nullptr;
+  if (!db.alloc(&W, (size_t)n * n)) { err = "hipMalloc failed"; return ABC_ENOMEM; }
+  // C^T = A1^T B1^T + A0^T: W (column-major, = Y_3 = A0^T) += Y_2 Y_0
+  copy2d(W, n, XT + 3LL * n, m, n, n, one2, 0.0);  // row a of W = column a of Y_3: W = Y_3 column-major
+  abc_status st = launch_ok(err);
+  if (st == ABC_OK &&
+      rocblas_zgemm_64(hnd, rocblas_operation_none, rocblas_operation_none, n, n, n, &one,
+                       reinterpret_cast<const zc*>(XT + 2LL * n), m, reinterpret_cast<const zc*>(XT), m, &one,
+                       reinterpret_cast<zc*>(W), n) != rocblas_status_success) {
+    err = "device GEMM for B1 A1 + A0 failed";
+    st = ABC_EDEVICE;
+  }
+  if (st == ABC_OK) {
+    // coefficient k at (i, j) is XT[i * m + k n + j]: row i of coefficient
+    // k is contiguous; W is C^T column-major, so C(i, j) = W[i * n + j]
+    const long long ld = 3LL * n;
+    if (hipMemset(out, 0, (size_t)2 * n * ld * 16) != hipSuccess) { err = "hipMemset failed"; st = ABC_EDEVICE; }
+    copy2d(out + n, ld, out + n, ld, n, n, make_double2(0.0, 0.0), 1.0);  // identity block
+    copy2d(out + 2LL * n, ld, XT + 2LL * n, m, n, n, one2, 0.0);          // A1
+    copy2d(out + n * ld, ld, XT + 1LL * n, m, n, n, one2, 0.0);           // B0
+    copy2d(out + n * ld + n, ld, XT, m, n, n, one2, 0.0);                 // B1
+    copy2d(out + n * ld + 2LL * n, ld, W, n, n, n, one2, 0.0);            // C
+    if (st == ABC_OK) st = launch_ok(err);
+  }
+  db.release(W);
+  return st;
+}
+
 }  // namespace
 
 abc_status build_box_ops(const abc_params& p, double2** mat_dev, double2** q_dev, int* n_gamma,
-                         std::vector<int>& gamma_lin, double* spectral_bound, int* subspace_dim, std::string& err) {
+                         std::vector<int>& gamma_lin, double* spectral_bound, int* subspace_dim, BoxReduced* reduced,
+                         std::string& err) {
   *mat_dev = nullptr;
   *q_dev = nullptr;
   BoxGeom bg = box_geometry(p);
@@ -736,8 +780,9 @@ abc_status build_box_ops(const abc_params& p, double2** mat_dev, double2** q_dev
     double2* Kd[4] = {nullptr, nullptr, nullptr, nullptr};
     for (int j = 0; j < 4 && st == ABC_OK; ++j) st = dtn_matrix(p, gd, sp[j], hnd, db, &Kd[j], err);
     double2* U = nullptr;
+    double* Ur = nullptr;
     int r = n;
-    if (st == ABC_OK) st = dominant_subspace(hnd, db, n, Kd, &U, &r, err);
+    if (st == ABC_OK) st = dominant_subspace(hnd, db, n, Kd, &U, &Ur, &r, err);
     const zc one(1.0, 0.0), zero(0.0, 0.0);
     if (st == ABC_OK && U) {
       // K_j <- U^T K_j U (r x r); U is real, so U^T is its adjoint
@@ -761,7 +806,7 @@ abc_status build_box_ops(const abc_params& p, double2** mat_dev, double2** q_dev
       db.release(T);
     }
     const long long m = 4LL * r, mf = 4LL * n;
-    double2 *MT = nullptr, *XR = nullptr, *XT = nullptr, *W = nullptr;
+    double2 *MT = nullptr, *XR = nullptr, *XT = nullptr;
     if (st == ABC_OK && (!db.alloc(&MT, (size_t)(m * m)) || !db.alloc(&XR, (size_t)(m * r)))) {
       err = "hipMalloc failed";
       st = ABC_ENOMEM;
@@ -775,6 +820,14 @@ abc_status build_box_ops(const abc_params& p, double2** mat_dev, double2** q_dev
     for (int j = 0; j < 4; ++j) db.release(Kd[j]);
     if (st == ABC_OK) st = lu_solve(hnd, db, (int)m, r, MT, XR, err, "second-order interpolation system");
     db.release(MT);
+    // the reduced operator and the basis, for stepping one orbital in the
+    // subspace (the lifted operator below serves the orbital batches and
+    // the export)
+    double2* red = nullptr;
+    if (st == ABC_OK && U && reduced) {
+      if (!db.alloc(&red, (size_t)2 * r * 3 * r)) { err = "hipMalloc failed"; st = ABC_ENOMEM; }
+      if (st == ABC_OK) st = assemble_second(hnd, db, red, XR, m, r, err);
+    }
     if (st == ABC_OK && U) {
       // coefficient_k^T = U Y~_k U^T into the full 4n x n layout (ld 4n)
       double2* T = nullptr;
@@ -795,37 +848,14 @@ abc_status build_box_ops(const abc_params& p, double2** mat_dev, double2** q_dev
     } else {
       XT = XR;
     }
-    // C^T = A1^T B1^T + A0^T; the view Y_k = XT + k n (lda 4n) is coefficient_k^T
-    if (st == ABC_OK && !db.alloc(&W, (size_t)n * n)) { err = "hipMalloc failed"; st = ABC_ENOMEM; }
-    if (st == ABC_OK) {
-      copy2d(W, n, XT + 3LL * n, mf, n, n, one2, 0.0);  // row a of W = column a of Y_3: W = Y_3 column-major
-      st = launch_ok(err);
-    }
-    if (st == ABC_OK) {
-      // W (column-major, = Y_3 = A0^T) += Y_2 Y_0 = A1^T B1^T
-      if (rocblas_zgemm_64(hnd, rocblas_operation_none, rocblas_operation_none, n, n, n, &one,
-                           reinterpret_cast<const zc*>(XT + 2LL * n), mf, reinterpret_cast<const zc*>(XT), mf, &one,
-                           reinterpret_cast<zc*>(W), n) != rocblas_status_success) {
-        err = "device GEMM for B1 A1 + A0 failed";
-        st = ABC_EDEVICE;
-      }
-    }
-    if (st == ABC_OK) {
-      // [[0, I, A1], [B0, B1, C]] row-major (ld 3n).  Coefficient k at (i, j)
-      // is XT[i * 4n + k n + j]: row i of coefficient k is contiguous.  W is
-      // C^T column-major, so C(i, j) = W[i * n + j].
-      const long long ld = 3LL * n;
-      if (hipMemset(out, 0, (size_t)2 * n * ld * 16) != hipSuccess) { err = "hipMemset failed"; st = ABC_EDEVICE; }
-      copy2d(out + n, ld, out + n, ld, n, n, make_double2(0.0, 0.0), 1.0);  // identity block
-      copy2d(out + 2LL * n, ld, XT + 2LL * n, mf, n, n, one2, 0.0);         // A1
-      copy2d(out + n * ld, ld, XT + 1LL * n, mf, n, n, one2, 0.0);          // B0
-      copy2d(out + n * ld + n, ld, XT, mf, n, n, one2, 0.0);                // B1
-      copy2d(out + n * ld + 2LL * n, ld, W, n, n, n, one2, 0.0);            // C
-      if (st == ABC_OK) st = launch_ok(err);
-    }
-    db.release(W);
+    if (st == ABC_OK) st = assemble_second(hnd, db, out, XT, mf, n, err);
     db.release(XT);
     if (subspace_dim) *subspace_dim = r;
+    if (st == ABC_OK && red && reduced) {
+      reduced->U = Ur;
+      reduced->red = red;
+      reduced->r = r;
+    }
   }
   // spectral radius of M (zeroth), B (first) or the (f, g) block
   // [[0, I], [B0, B1]] (second), with a safety factor; the row-sum norm of
@@ -835,10 +865,17 @@ abc_status build_box_ops(const abc_params& p, double2** mat_dev, double2** q_dev
                                      &bound, err);
   if (st == ABC_OK && hipDeviceSynchronize() != hipSuccess) { err = "box-form setup failed on the device"; st = ABC_EDEVICE; }
   rocblas_destroy_handle(hnd);
-  if (st != ABC_OK) return st;
+  if (st != ABC_OK) {
+    if (reduced) *reduced = BoxReduced{};  // freed with the other setup buffers
+    return st;
+  }
   *spectral_bound = bound;
   db.keep(out);
   *mat_dev = out;
+  if (reduced && reduced->red) {
+    db.keep(reduced->red);
+    db.keep(reduced->U);
+  }
   if (Q) {
     db.keep(Q);
     *q_dev = Q;
