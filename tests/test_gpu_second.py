@@ -150,15 +150,20 @@ def test_second_order_box_parity_other_points():
     assert r["err"] < tp and r["aux_err"] < ta, (r["err"], tp, r["aux_err"], ta)
 
 
-def test_second_order_orbital_batch_gemm_parity():
-    # the operator over five orbitals as two complex GEMMs per stage
-    r = _run("second-box-batch", (6, 6, 6), 0.3, 0.004, 1, 5, batch=5)
+@pytest.mark.parametrize("shape,R,batch", [((6, 6, 6), 1, 5), ((7, 7, 7), 2, 3)])
+def test_second_order_orbital_batch_gemm_parity(shape, R, batch):
+    # the operator over the orbitals as matrix-core GEMMs per stage (at R = 2
+    # the lifted coefficients of the dominant subspace)
+    r = _run("second-box-batch", shape, 0.3, 0.004, R, 5, batch=batch)
     tp, ta = _tolerances(r["st"], r["psi0"], r["V"], 5, r["ref_psi"], r["ref_flat"], S_PTS)
     assert r["err"] < tp and r["aux_err"] < ta, (r["err"], tp, r["aux_err"], ta)
 
 
-def test_second_order_fp32_stencil_parity():
-    r = _run("second-box-c64", (7, 6, 6), 0.3, 0.004, 1, 5, dtype="c64")
+@pytest.mark.parametrize("shape,R", [((7, 6, 6), 1), ((7, 7, 7), 2)])
+def test_second_order_fp32_stencil_parity(shape, R):
+    # at R = 2 one orbital steps in the dominant subspace (FP64 projection,
+    # reduced operator and lift around the FP32 stencil)
+    r = _run("second-box-c64", shape, 0.3, 0.004, R, 5, dtype="c64")
     assert r["err"] < TOL32, r["err"]
 
 
