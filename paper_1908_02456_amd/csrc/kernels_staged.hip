@@ -2510,7 +2510,10 @@ abc_status face_fft_setup(const Geometry& g, int R, int w, const std::vector<abc
     ff.S[q] = 2 * R * B;
     ff.lg1[q] = ilog2(P1);
     ff.lg2[q] = ilog2(P2);
-    ff.twr[q] = fft_lines_per_group(P2, ff.S[q] * n1, 1);
+    // row passes: kBlock points per workgroup (one 256-point line: 180.5
+    // against 184 us per step at 128^3 with two); column passes: two lines
+    // (one, four, eight or sixteen were slower: 196, 188, 203, 251 us)
+    ff.twr[q] = std::min(ff.S[q] * n1, std::max(1, kBlock / P2));
     int twc = fft_lines_per_group(P1, P2, 2);
     while (twc > 1 && R * twc * P1 > 4096) twc >>= 1;
     if (R * twc * P1 > 4096) { err = "face too large for the FFT face path at this stencil radius"; return ABC_ENOTSUP; }

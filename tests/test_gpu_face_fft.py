@@ -32,6 +32,7 @@ CASES = [
     ((24, 26, 25), 1, "first", 1, "c128", 3),
     ((9, 10, 11), 3, "first", 1, "c128", 3),
     ((10, 9, 11), 3, "zeroth", 2, "c128", 3),
+    ((6, 70, 68), 1, "first", 1, "c128", 2),  # 256-point transforms on the z faces
 ]
 
 
