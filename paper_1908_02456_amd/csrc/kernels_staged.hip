@@ -1032,9 +1032,11 @@ hipError_t face_fft_apply(const abc_launch& L, const double2* gin, double2* gout
 // vector element a thread loads serves kBoxRows matrix rows.  Partial sums
 // reduce within each wave by shuffles, then across the waves in LDS; the
 // stage update is that of box_gemv_kernel.  Rows past nrow read the last row
-// and write nothing.
+// and write nothing.  Mode kGemvPlain writes the product itself (after the
+// identity block's g for rows below ident).
 // ---------------------------------------------------------------------------
 constexpr int kBoxRows = 4, kBoxRowsMin = 4096;
+constexpr int kGemvPlain = 3;
 
 __global__ void __launch_bounds__(kBlock) box_gemv_rows_kernel(
     const double2* __restrict__ mat, int nrow, int naux, int ncol, int ident, const double2* __restrict__ gin,
@@ -1051,8 +1053,8 @@ __global__ void __launch_bounds__(kBlock) box_gemv_rows_kernel(
     sr[r] = si[r] = 0.0;
   }
   // boundary-variable columns; rows below ident skip them (their [0, I]
-  // block is added in the update)
-  for (int j = threadIdx.x; j < naux; j += kBlock) {
+  // block is added in the update), and so does a workgroup of such rows
+  for (int j = threadIdx.x; j < (row0 + RB > ident ? naux : 0); j += kBlock) {
     const double2 v = gin[j];
 #pragma unroll
     for (int r = 0; r < RB; ++r) {
@@ -1097,6 +1099,10 @@ __global__ void __launch_bounds__(kBlock) box_gemv_rows_kernel(
     const double2 gv = gin[row + ident];
     t.x += gv.x;
     t.y += gv.y;
+  }
+  if (mode == kGemvPlain) {
+    gout[row] = t;
+    return;
   }
   const double2 gn = make_double2(coef * t.x, coef * t.y);
   if (mode == 0) {
@@ -1494,31 +1500,32 @@ __global__ void __launch_bounds__(kBlock) proj_kernel(const double* __restrict__
   }
 }
 
-// Tl (4 x n, ld 4) = Tp (4 x r, ld 4) U^T: a workgroup takes 64 rows i of U
-// (one per lane, coalesced) and its kLiftWaves waves a slice of the r
-// columns each (enough waves in flight to stream U); the partial sums are
-// added in LDS in wave order
-constexpr int kLiftWaves = 16;
+// Tl (4 x n, ld 4) = Tp (4 x r, ld 4) U^T: a workgroup takes 32 rows i of U
+// (one per lane of each half-wave, coalesced), its kLiftWaves waves a slice
+// of the r columns each and the two halves of a wave alternate columns
+// (n / 32 workgroups fill the chip at the paper's n = 14166, enough waves in
+// flight to stream U); the partial sums are added in LDS in a fixed order
+constexpr int kLiftWaves = 16, kLiftRows = 32;
 __global__ void __launch_bounds__(64 * kLiftWaves) lift_kernel(const double* __restrict__ U, int n, int r,
                                                                const double* __restrict__ Tp,
                                                                double* __restrict__ Tl) {
   __shared__ double red[kLiftWaves][4][64];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int i = blockIdx.x * 64 + lane;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, half = lane >> 5;
+  const int i = blockIdx.x * kLiftRows + (lane & 31);
   const int jlo = (int)((long long)r * w / kLiftWaves), jhi = (int)((long long)r * (w + 1) / kLiftWaves);
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
   if (i < n) {
-    int j = jlo;
-    for (; j + 4 <= jhi; j += 4) {
+    int j = jlo + half;
+    for (; j + 6 < jhi; j += 8) {
       double u[4];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) u[q] = U[(long long)(j + q) * n + i];
+      for (int q = 0; q < 4; ++q) u[q] = U[(long long)(j + 2 * q) * n + i];
 #pragma unroll
       for (int q = 0; q < 4; ++q)
 #pragma unroll
-        for (int c = 0; c < 4; ++c) acc[c] += Tp[4LL * (j + q) + c] * u[q];
+        for (int c = 0; c < 4; ++c) acc[c] += Tp[4LL * (j + 2 * q) + c] * u[q];
     }
-    for (; j < jhi; ++j) {
+    for (; j < jhi; j += 2) {
       const double u = U[(long long)j * n + i];
 #pragma unroll
       for (int c = 0; c < 4; ++c) acc[c] += Tp[4LL * j + c] * u;
@@ -1527,11 +1534,11 @@ __global__ void __launch_bounds__(64 * kLiftWaves) lift_kernel(const double* __r
 #pragma unroll
   for (int c = 0; c < 4; ++c) red[w][c][lane] = acc[c];
   __syncthreads();
-  if (w == 0 && i < n) {
+  if (w == 0 && half == 0 && i < n) {
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
-      double sum = red[0][c][lane];
-      for (int q = 1; q < kLiftWaves; ++q) sum += red[q][c][lane];
+      double sum = red[0][c][lane] + red[0][c][lane + 32];
+      for (int q = 1; q < kLiftWaves; ++q) sum += red[q][c][lane] + red[q][c][lane + 32];
       Tl[4LL * i + c] = sum;
     }
   }
@@ -1570,10 +1577,7 @@ template <typename T>
 hipError_t second_reduced_stage(const abc_launch& L, const abc_scratch& S, const typename cpx<T>::t* ycur,
                                 const double2* gcur, double2* gnext, double2* aux, double coef, int mode,
                                 hipStream_t st, abc_timer* tm, const char* label) {
-  using zc = rocblas_double_complex;
   const int n = L.n_gamma, r = L.box_r;
-  rocblas_handle hb = static_cast<rocblas_handle>(L.box_blas);
-  if (rocblas_set_stream(hb, st) != rocblas_status_success) return hipErrorUnknown;
   double* W = S.bpack;  // 6 x n in, then the lifted 4 x n
   double* Z = S.bred;   // 6 x r
   double2* v = reinterpret_cast<double2*>(S.bred + 6LL * r);  // [f~; g~; y~]
@@ -1587,21 +1591,19 @@ hipError_t second_reduced_stage(const abc_launch& L, const abc_scratch& S, const
                     dim3(kBlock), st, L.box_U, n, r, (const double*)W, Z);
   abc_launch_kernel(tm, "reduced_unpack", unpack3_kernel, dim3(nblocks(r)), dim3(kBlock), st, v, (const double*)Z, r);
   // t_g~ = [B0~ B1~ C~] v (rows r .. 2r of the row-major operator);
-  // t_f~ = g~ + A1~ y~ (rows 0 .. r, columns 2r .. 3r)
-  const zc cone(1.0, 0.0), czero(0.0, 0.0);
-  const long long ld = 3LL * r;
-  if (rocblas_zgemv_64(hb, rocblas_operation_transpose, ld, r, &cone,
-                       reinterpret_cast<const zc*>(L.box_red + (long long)r * ld), ld, reinterpret_cast<const zc*>(v),
-                       1, &czero, reinterpret_cast<zc*>(t + r), 1) != rocblas_status_success)
-    return hipErrorUnknown;
-  hipError_t e = hipMemcpyAsync(t, v + r, (size_t)r * sizeof(double2), hipMemcpyDeviceToDevice, st);
-  if (e != hipSuccess) return e;
-  if (rocblas_zgemv_64(hb, rocblas_operation_transpose, r, r, &cone, reinterpret_cast<const zc*>(L.box_red + 2LL * r),
-                       ld, reinterpret_cast<const zc*>(v + 2LL * r), 1, &cone, reinterpret_cast<zc*>(t), 1) !=
-      rocblas_status_success)
-    return hipErrorUnknown;
+  // t_f~ = g~ + A1~ y~ (rows 0 .. r: their [0, I] block on the columns
+  // 0 .. 2r is not read, g~ is added)
+  const int ld = 3 * r;
+  const unsigned rb = (unsigned)((r + kBoxRows - 1) / kBoxRows);
+  abc_launch_kernel(tm, "reduced_operator", box_gemv_rows_kernel, dim3(rb), dim3(kBlock), st,
+                    (const double2*)(L.box_red + (long long)r * ld), r, 0, ld, 0, (const double2*)nullptr,
+                    (const double2*)v, t + r, (double2*)nullptr, (double2*)nullptr, 0.0, kGemvPlain);
+  abc_launch_kernel(tm, "reduced_operator", box_gemv_rows_kernel, dim3(rb), dim3(kBlock), st,
+                    (const double2*)L.box_red, r, 2 * r, ld, r, (const double2*)v, (const double2*)(v + 2LL * r), t,
+                    (double2*)nullptr, (double2*)nullptr, 0.0, kGemvPlain);
   abc_launch_kernel(tm, "reduced_pack", pack2_kernel, dim3(nblocks(r)), dim3(kBlock), st, Tp, (const double2*)t, r);
-  abc_launch_kernel(tm, "reduced_lift", lift_kernel, dim3((unsigned)((n + 63) / 64)), dim3(64 * kLiftWaves), st,
+  abc_launch_kernel(tm, "reduced_lift", lift_kernel, dim3((unsigned)((n + kLiftRows - 1) / kLiftRows)),
+                    dim3(64 * kLiftWaves), st,
                     L.box_U, n, r, (const double*)Tp, W);
   abc_launch_kernel(tm, "box_epilogue", lifted_epilogue_kernel, dim3(nblocks(2LL * n)), dim3(kBlock), st,
                     (const double*)W, gcur, gnext, S.facc, aux, n, coef, mode);
