@@ -67,11 +67,13 @@ abc_status build_face_ops(const abc_params& p, FaceOps& ops, std::string& err);
 // Lyapunov weight (n x n) or NULL, subspace_dim the dimension of the
 // subspace the second order interpolates in (n_Gamma otherwise).
 // Second order in a subspace of dimension r < n_Gamma: the orthonormal basis
-// U (real, n_Gamma x r, column-major) and the reduced operator
-// [[0, I, A1~], [B0~, B1~, C~]] (2r x 3r, row-major), device buffers owned by
-// the caller (null, r = 0, when the second order uses no subspace).
+// U (real, n_Gamma x r, column-major; Ut the same matrix row-major) and the
+// reduced operator [[0, I, A1~], [B0~, B1~, C~]] (2r x 3r, row-major), device
+// buffers owned by the caller (null, r = 0, when the second order uses no
+// subspace).
 struct BoxReduced {
   double* U = nullptr;
+  double* Ut = nullptr;
   double2* red = nullptr;
   int r = 0;
 };
@@ -150,12 +152,13 @@ struct abc_launch {
   // box form
   const double2* box_mat;
   const double2* box_q;       // Lyapunov weight (H_gs H_gs^T)^{-1}, n x n
-  // second order in a subspace (box_r > 0): U, the reduced operator and a
-  // rocBLAS handle; one orbital steps through them instead of box_mat
+  // second order in a subspace (box_r > 0): U (column-major, the
+  // projection; Ut row-major, the lift) and the reduced operator; one
+  // orbital steps through them instead of box_mat
   const double* box_U;
+  const double* box_Ut;
   const double2* box_red;
   int box_r;
-  void* box_blas;
   const int* gamma_lin;       // gamma index -> linear point index
   const int* point_gamma;     // linear point index -> gamma index or -1
   int n_gamma;

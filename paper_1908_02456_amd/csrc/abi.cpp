@@ -36,7 +36,6 @@ struct abc_ctx {
   size_t aux_elems = 0;
   int n_gamma = 0;
   int box_rank = 0;         // box form: dimension the second order interpolates in
-  void* box_blas = nullptr;  // box form, second order in a subspace: rocBLAS handle of the reduced stages
   double box_bound = 0;    // box form: spectral bound of the boundary block
   int use_fused = 0;
   double2* box_mat = nullptr;
@@ -149,7 +148,6 @@ void abc_destroy(abc_ctx* c) {
   if (!c) return;
   if (c->pot.host) (void)hipHostFree(c->pot.host);
   if (c->pot.blas) rocblas_destroy_handle(static_cast<rocblas_handle>(c->pot.blas));
-  if (c->box_blas) rocblas_destroy_handle(static_cast<rocblas_handle>(c->box_blas));
   if (c->orb) {
     if (c->orb->copied) hipEventDestroy(c->orb->copied);
     if (c->orb->desc_host) hipHostFree(c->orb->desc_host);
@@ -237,18 +235,13 @@ abc_status abc_setup(const abc_params* pp, abc_ctx** out) {
       // one orbital steps the second order in the subspace (the lifted
       // operator stays for the export)
       c->allocations.push_back(red.U);
+      c->allocations.push_back(red.Ut);
       c->allocations.push_back(red.red);
-      c->bytes += (size_t)c->n_gamma * red.r * 8 + (size_t)6 * red.r * red.r * 16;
-      rocblas_handle hb = nullptr;
-      if (rocblas_create_handle(&hb) != rocblas_status_success) {
-        abc_destroy(c);
-        return fail(ABC_EDEVICE, "rocblas_create_handle failed");
-      }
-      c->box_blas = hb;
+      c->bytes += (size_t)2 * c->n_gamma * red.r * 8 + (size_t)6 * red.r * red.r * 16;
       L.box_U = red.U;
+      L.box_Ut = red.Ut;
       L.box_red = red.red;
       L.box_r = red.r;
-      L.box_blas = hb;
     }
     if (c->box_mat) { c->allocations.push_back(c->box_mat); c->bytes += abc::box_mat_elems(p.order, c->n_gamma) * 16; }
     if (c->box_q) { c->allocations.push_back(c->box_q); c->bytes += (size_t)c->n_gamma * c->n_gamma * 16; }

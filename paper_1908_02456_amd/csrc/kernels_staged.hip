@@ -1500,47 +1500,49 @@ __global__ void __launch_bounds__(kBlock) proj_kernel(const double* __restrict__
   }
 }
 
-// Tl (4 x n, ld 4) = Tp (4 x r, ld 4) U^T: a workgroup takes 32 rows i of U
-// (one per lane of each half-wave, coalesced), its kLiftWaves waves a slice
-// of the r columns each and the two halves of a wave alternate columns
-// (n / 32 workgroups fill the chip at the paper's n = 14166, enough waves in
-// flight to stream U); the partial sums are added in LDS in a fixed order
-constexpr int kLiftWaves = 16, kLiftRows = 32;
-__global__ void __launch_bounds__(64 * kLiftWaves) lift_kernel(const double* __restrict__ U, int n, int r,
-                                                               const double* __restrict__ Tp,
-                                                               double* __restrict__ Tl) {
-  __shared__ double red[kLiftWaves][4][64];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, half = lane >> 5;
-  const int i = blockIdx.x * kLiftRows + (lane & 31);
-  const int jlo = (int)((long long)r * w / kLiftWaves), jhi = (int)((long long)r * (w + 1) / kLiftWaves);
-  double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  if (i < n) {
-    int j = jlo + half;
-    for (; j + 6 < jhi; j += 8) {
-      double u[4];
+// Tl (4 x n, ld 4) = Tp (4 x r, ld 4) U^T from the row-major copy Ut of U:
+// a wave takes kLiftRows rows i of Ut and its lanes stride the r columns
+// (coalesced rows, streamed once; each Tp entry serves the wave's rows); the
+// four sums of each row reduce over the wave by shuffles in a fixed order
+constexpr int kLiftRows = 4;
+__global__ void __launch_bounds__(kBlock) lift_kernel(const double* __restrict__ Ut, int n, int r,
+                                                      const double* __restrict__ Tp, double* __restrict__ Tl) {
+  const int lane = threadIdx.x & 63;
+  const long long wave = ((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const long long i0 = wave * kLiftRows;
+  if (i0 >= n) return;  // whole waves
+  const double* row[kLiftRows];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) u[q] = U[(long long)(j + 2 * q) * n + i];
+  for (int k = 0; k < kLiftRows; ++k) row[k] = Ut + min(i0 + k, (long long)n - 1) * r;
+  double acc[kLiftRows][4];
 #pragma unroll
-      for (int q = 0; q < 4; ++q)
+  for (int k = 0; k < kLiftRows; ++k)
 #pragma unroll
-        for (int c = 0; c < 4; ++c) acc[c] += Tp[4LL * (j + 2 * q) + c] * u[q];
-    }
-    for (; j < jhi; j += 2) {
-      const double u = U[(long long)j * n + i];
+    for (int c = 0; c < 4; ++c) acc[k][c] = 0.0;
+  for (int j = lane; j < r; j += 64) {
+    const double2 t01 = *reinterpret_cast<const double2*>(Tp + 4LL * j);
+    const double2 t23 = *reinterpret_cast<const double2*>(Tp + 4LL * j + 2);
 #pragma unroll
-      for (int c = 0; c < 4; ++c) acc[c] += Tp[4LL * j + c] * u;
+    for (int k = 0; k < kLiftRows; ++k) {
+      const double u = row[k][j];
+      acc[k][0] += t01.x * u;
+      acc[k][1] += t01.y * u;
+      acc[k][2] += t23.x * u;
+      acc[k][3] += t23.y * u;
     }
   }
 #pragma unroll
-  for (int c = 0; c < 4; ++c) red[w][c][lane] = acc[c];
-  __syncthreads();
-  if (w == 0 && half == 0 && i < n) {
+  for (int k = 0; k < kLiftRows; ++k)
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      double sum = red[0][c][lane] + red[0][c][lane + 32];
-      for (int q = 1; q < kLiftWaves; ++q) sum += red[q][c][lane] + red[q][c][lane + 32];
-      Tl[4LL * i + c] = sum;
-    }
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) acc[k][c] += __shfl_down(acc[k][c], off, 64);
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < kLiftRows; ++k)
+      if (i0 + k < n)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) Tl[4 * (i0 + k) + c] = acc[k][c];
   }
 }
 
@@ -1602,9 +1604,9 @@ hipError_t second_reduced_stage(const abc_launch& L, const abc_scratch& S, const
                     (const double2*)L.box_red, r, 2 * r, ld, r, (const double2*)v, (const double2*)(v + 2LL * r), t,
                     (double2*)nullptr, (double2*)nullptr, 0.0, kGemvPlain);
   abc_launch_kernel(tm, "reduced_pack", pack2_kernel, dim3(nblocks(r)), dim3(kBlock), st, Tp, (const double2*)t, r);
-  abc_launch_kernel(tm, "reduced_lift", lift_kernel, dim3((unsigned)((n + kLiftRows - 1) / kLiftRows)),
-                    dim3(64 * kLiftWaves), st,
-                    L.box_U, n, r, (const double*)Tp, W);
+  const long long lift_threads = (long long)(n + kLiftRows - 1) / kLiftRows * 64;
+  abc_launch_kernel(tm, "reduced_lift", lift_kernel, dim3((unsigned)((lift_threads + kBlock - 1) / kBlock)),
+                    dim3(kBlock), st, L.box_Ut, n, r, (const double*)Tp, W);
   abc_launch_kernel(tm, "box_epilogue", lifted_epilogue_kernel, dim3(nblocks(2LL * n)), dim3(kBlock), st,
                     (const double*)W, gcur, gnext, S.facc, aux, n, coef, mode);
   return hipGetLastError();

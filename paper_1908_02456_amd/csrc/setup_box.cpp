@@ -242,6 +242,15 @@ __global__ void __launch_bounds__(kThreads) real_to_complex_kernel(double2* __re
   if (e < count) out[e] = make_double2(in[e], 0.0);
 }
 
+// out (rows x cols, row-major) = in (rows x cols, column-major)
+__global__ void __launch_bounds__(kThreads) transpose_real_kernel(double* __restrict__ out,
+                                                                  const double* __restrict__ in, int rows, int cols) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long long)rows * cols) return;
+  const long long i = e / cols, j = e % cols;
+  out[e] = in[j * rows + i];
+}
+
 // column-major entries (i, j) = v from a host-built list of distinct entries
 __global__ void __launch_bounds__(kThreads) scatter_kernel(double2* __restrict__ m, long long ld,
                                                            const int* __restrict__ ij, const double2* __restrict__ v,
@@ -852,9 +861,21 @@ abc_status build_box_ops(const abc_params& p, double2** mat_dev, double2** q_dev
     db.release(XT);
     if (subspace_dim) *subspace_dim = r;
     if (st == ABC_OK && red && reduced) {
-      reduced->U = Ur;
-      reduced->red = red;
-      reduced->r = r;
+      // the stepping reads U by columns (projection) and by rows (lift)
+      double* Ut = nullptr;
+      if (!db.alloc(&Ut, (size_t)n * r)) {
+        err = "hipMalloc failed";
+        st = ABC_ENOMEM;
+      } else {
+        transpose_real_kernel<<<nblk((long long)n * r), kThreads>>>(Ut, Ur, n, r);
+        if (hipGetLastError() != hipSuccess) { err = "setup kernel launch failed"; st = ABC_EDEVICE; }
+      }
+      if (st == ABC_OK) {
+        reduced->U = Ur;
+        reduced->Ut = Ut;
+        reduced->red = red;
+        reduced->r = r;
+      }
     }
   }
   // spectral radius of M (zeroth), B (first) or the (f, g) block
@@ -875,6 +896,7 @@ abc_status build_box_ops(const abc_params& p, double2** mat_dev, double2** q_dev
   if (reduced && reduced->red) {
     db.keep(reduced->red);
     db.keep(reduced->U);
+    db.keep(reduced->Ut);
   }
   if (Q) {
     db.keep(Q);
